@@ -1,0 +1,80 @@
+"""The pins must catch plausible mistakes: each case plants one in the oracle
+(on the CPU, through monkeypatch) and checks that a pin then fails."""
+import numpy as np
+import pytest
+
+import oracle.contract as C
+import oracle.mpo as MPO
+from tests import test_oracle_pins as pins
+
+
+def _swap_phys(W):
+    return np.ascontiguousarray(W.transpose(0, 1, 3, 2))
+
+
+def test_transposed_mpo_in_heff_is_caught(monkeypatch):
+    good = C.apply_heff
+    monkeypatch.setattr(C, "apply_heff", lambda L, W, R, psi: good(L, _swap_phys(W), R, psi))
+    with pytest.raises(AssertionError):
+        pins.test_apply_heff_equals_kronecker_matrix(3, 2, 4, 5, 5)
+
+
+def test_swapped_environment_legs_are_caught(monkeypatch):
+    good = C.apply_heff
+    monkeypatch.setattr(C, "apply_heff",
+                        lambda L, W, R, psi: good(L, W, np.ascontiguousarray(R.transpose(2, 1, 0)), psi))
+    with pytest.raises(AssertionError):
+        pins.test_apply_heff_equals_kronecker_matrix(3, 2, 4, 5, 5)
+
+
+def test_bra_ket_mixup_in_env_update_is_caught(monkeypatch):
+    good = C.update_left
+    monkeypatch.setattr(C, "update_left",
+                        lambda L, W, A: good(np.ascontiguousarray(L.transpose(2, 1, 0)), W, A))
+    with pytest.raises(AssertionError):
+        pins.test_env_updates_equal_bruteforce()
+
+
+def test_wrong_expansion_term_is_caught(monkeypatch):
+    good = C.expansion_term_l2r
+    monkeypatch.setattr(C, "expansion_term_l2r",
+                        lambda L, W, psi, alpha: good(L, _swap_phys(W), psi, alpha))
+    with pytest.raises(AssertionError):
+        pins.test_worked_example_sec4_3(0.6, 0.8)
+
+
+def test_missing_jordan_wigner_string_is_caught(monkeypatch):
+    ops = MPO.fermion_site()
+    good = MPO._finite_state_mpo
+
+    def no_string(l, d, starts, strings, finishers, coupling, onsite, R):
+        if d == 4:
+            strings = [ops["I"]] * len(strings)
+        return good(l, d, starts, strings, finishers, coupling, onsite, R)
+    monkeypatch.setattr(MPO, "_finite_state_mpo", no_string)
+    with pytest.raises(AssertionError):
+        pins.test_long_range_hopping_mpo_equals_fock_ed()
+
+
+def test_wrong_hopping_sign_is_caught(monkeypatch):
+    ops = MPO.fermion_site()
+    good = MPO._finite_state_mpo
+
+    def bad_start(l, d, starts, strings, finishers, coupling, onsite, R):
+        if d == 4:
+            starts = [ops["cd_up"], ops["cd_dn"], ops["c_up"], ops["c_dn"]]   # F dropped
+        return good(l, d, starts, strings, finishers, coupling, onsite, R)
+    monkeypatch.setattr(MPO, "_finite_state_mpo", bad_start)
+    with pytest.raises(AssertionError):
+        pins.test_hubbard_mpo_equals_fock_ed(3, 4.0)
+
+
+def test_wrong_neighbour_update_is_caught(monkeypatch):
+    good = C.truncate_l2r
+
+    def bad(Mt, psi, nbr, kmax, eps):
+        A, B, s, disc = good(Mt, psi, nbr, kmax, eps)
+        return A, B[::-1].copy(), s, disc        # rows of S V^T applied in the wrong order
+    monkeypatch.setattr(C, "truncate_l2r", bad)
+    with pytest.raises(AssertionError):
+        pins.test_truncation_without_cut_keeps_state_and_discarded_weight("l2r")
