@@ -1,0 +1,229 @@
+"""H_eff * psi microbenchmark of the DMRG3S hot path on one MI355X.
+
+Workload (the isolated H_eff microbenchmark): Fermi-Hubbard chain MPO
+(t = 1, U = 8, d = 4, w = 6, Jordan-Wigner strings); environments L and R
+built on the GPU by contracting a seeded Gaussian MPS of ceil(log_4 m) sites,
+left- (right-) canonicalised through the library's truncation, with the MPO
+from the chain ends; psi[m, 4, m] Gaussian and normalised.  One step = one
+application of H_eff (GEMM over the left MPS bond, W-map, GEMM over the right
+MPO and MPS bonds).  Inputs are resident in HBM when timing starts.
+
+Prints one JSON line.  `value` is FP64 GFLOP/s at the default m = 2048 with
+the flop count F = 2 wl d ml^2 mr + 2 d^2 wl wr ml mr + 2 wr d ml mr^2.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"f64": 78.6e12, "f32": 157.3e12, "bf16": 2516.6e12}
+HBM_PEAK = 8.0e12
+
+
+def heff_flops(ml, d, mr, wl, wr):
+    return 2.0 * wl * d * ml * ml * mr + 2.0 * d * d * wl * wr * ml * mr + 2.0 * wr * d * ml * mr * mr
+
+
+def gemm_flops(ml, d, mr, wl, wr):
+    return {"gemm1": 2.0 * (ml * wl) * (d * mr) * ml, "wmap": 2.0 * d * d * wl * wr * ml * mr,
+            "gemm2": 2.0 * (ml * d) * mr * (wr * mr)}
+
+
+def build_inputs(ctx, abi, synth, torch, m, dev):
+    """L, W, R (FP64, device) of the microbenchmark, built by the library."""
+    d = 4
+    ns = synth.env_sites_for(m, d)
+    mpo = abi.hubbard_chain_mpo(2 * ns + 1, t=1.0, U=8.0)
+    W = torch.tensor(mpo[ns], dtype=torch.float64, device=dev)
+
+    def canonical(tensors, direction):
+        out = []
+        for t in tensors:
+            x = torch.tensor(t, dtype=torch.float64, device=dev)
+            ml_, d_, mr_ = x.shape
+            if direction == abi.L2R:
+                k = mr_
+                site = torch.empty(ml_ * d_ * k, dtype=torch.float64, device=dev)
+                dummy = torch.zeros(mr_, dtype=torch.float64, device=dev)
+                nb = torch.empty(k, dtype=torch.float64, device=dev)
+                kk, _, _ = ctx.truncate(abi.L2R, x.reshape(ml_ * d_, mr_), x, k, 0.0, dummy, site, nb,
+                                        renormalize=False)
+                out.append(site[: ml_ * d_ * kk].reshape(ml_, d_, kk))
+            else:
+                k = ml_
+                site = torch.empty(k * d_ * mr_, dtype=torch.float64, device=dev)
+                dummy = torch.zeros(ml_, dtype=torch.float64, device=dev)
+                nb = torch.empty(k, dtype=torch.float64, device=dev)
+                kk, _, _ = ctx.truncate(abi.R2L, x.reshape(ml_, d_ * mr_), x, k, 0.0, dummy, site, nb,
+                                        renormalize=False)
+                out.append(site[: kk * d_ * mr_].reshape(kk, d_, mr_))
+        return out
+
+    left = canonical(synth.growing_mps(ns, d, m, synth.SEED_LEFT), abi.L2R)
+    L = torch.ones(1, dtype=torch.float64, device=dev).reshape(1, 1, 1)
+    for i, A in enumerate(left):
+        wl, wr = mpo[i].shape[0], mpo[i].shape[1]
+        out = torch.empty((A.shape[2], wr, A.shape[2]), dtype=torch.float64, device=dev)
+        ctx.update_env(abi.L2R, L, torch.tensor(mpo[i], dtype=torch.float64, device=dev), A, out)
+        L = out
+    # right environment: mirror image of a growing MPS, attached to the right end
+    right_src = [t.transpose(2, 1, 0).copy() for t in reversed(synth.growing_mps(ns, d, m, synth.SEED_RIGHT))]
+    right = canonical(right_src, abi.R2L)
+    R = torch.ones(1, dtype=torch.float64, device=dev).reshape(1, 1, 1)
+    for j in range(ns - 1, -1, -1):
+        site_idx = ns + 1 + j
+        B = right[j]
+        wl = mpo[site_idx].shape[0]
+        out = torch.empty((B.shape[0], wl, B.shape[0]), dtype=torch.float64, device=dev)
+        ctx.update_env(abi.R2L, R, torch.tensor(mpo[site_idx], dtype=torch.float64, device=dev), B, out)
+        R = out
+    torch.cuda.synchronize()
+    return L.contiguous(), W.contiguous(), R.contiguous()
+
+
+def time_heff(ctx, torch, L, W, R, psi, out, steps, warmup):
+    for _ in range(warmup):
+        ctx.apply_heff(L, W, R, psi, out)
+    torch.cuda.synchronize()
+    ctx.profile_begin(steps)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for _ in range(steps):
+        ctx.apply_heff(L, W, R, psi, out)
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms, n = ctx.profile_end()
+    ms = start.elapsed_time(stop) / steps
+    return ms, wall, [k / max(n, 1) for k in kern_ms]
+
+
+def cpu_baseline(L, W, R, psi, budget_s):
+    """The oracle's H_eff (NumPy FP64, tensordot in the paper's order) on the
+    same arrays, repeated until `budget_s` seconds are used (at least once)."""
+    import numpy as np
+    from oracle import contract as C
+    try:
+        import threadpoolctl
+        threads = max([p.get("num_threads", 1) for p in threadpoolctl.threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    Ln, Wn, Rn, pn = [np.ascontiguousarray(x) for x in (L, W, R, psi)]
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        C.apply_heff(Ln, Wn, Rn, pn)
+        reps += 1
+        if time.perf_counter() - t0 >= budget_s or reps >= 100:
+            break
+    dt = (time.perf_counter() - t0) / reps
+    return dt, reps, threads
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--m", type=int, default=2048)
+    ap.add_argument("--extra-m", type=str, default="256,1024",
+                    help="other bond dimensions reported beside the headline (comma list, '' = none)")
+    ap.add_argument("--no-f32", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the H_eff hot path of one GPU's share); "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1501_05504_amd import abi, synth
+
+    dev = torch.device("cuda:0")
+    ctx = abi.Context(0)
+    d, w = 4, 6
+    results = {}
+    heads = None
+    for m in [args.m] + [int(x) for x in args.extra_m.split(",") if x.strip()]:
+        print("bench: building inputs m=%d" % m, file=sys.stderr, flush=True)
+        L, W, R = build_inputs(ctx, abi, synth, torch, m, dev)
+        psi = torch.tensor(synth.gaussian((m, d, m), synth.SEED_PSI), dtype=torch.float64, device=dev)
+        psi /= torch.linalg.vector_norm(psi)
+        out = torch.empty_like(psi)
+        F = heff_flops(m, d, m, w, w)
+        steps = args.steps if m == args.m else max(10, args.steps // 2)
+        ms, wall, kern = time_heff(ctx, torch, L, W, R, psi, out, steps, args.warmup)
+        entry = {"ms": ms, "gflops": F / ms * 1e-6, "kernel_ms": dict(zip(["gemm1", "wmap", "gemm2"], kern)),
+                 "steps": steps, "wall_s": wall}
+        print("bench: m=%d f64 %.3f ms  %.1f GFLOP/s  kernels %s" % (m, ms, F / ms * 1e-6, kern),
+              file=sys.stderr, flush=True)
+        if not args.no_f32:
+            Lf, Wf, Rf, pf = L.float(), W.float(), R.float(), psi.float()
+            of = torch.empty_like(pf)
+            ms32, _, kern32 = time_heff(ctx, torch, Lf, Wf, Rf, pf, of, steps, args.warmup)
+            entry["f32"] = {"ms": ms32, "gflops": F / ms32 * 1e-6,
+                            "kernel_ms": dict(zip(["gemm1", "wmap", "gemm2"], kern32))}
+            print("bench: m=%d f32 %.3f ms  %.1f GFLOP/s" % (m, ms32, F / ms32 * 1e-6), file=sys.stderr, flush=True)
+        results[m] = entry
+        if m == args.m:
+            heads = (L, W, R, psi, out, ms, kern, steps)
+        else:
+            del L, R, psi, out
+            torch.cuda.empty_cache()
+
+    L, W, R, psi, out, ms, kern, steps = heads
+    m = args.m
+    F = heff_flops(m, d, m, w, w)
+    gf = gemm_flops(m, d, m, w, w)
+    names = ["gemm1", "wmap", "gemm2"]
+    dom = max([0, 2], key=lambda i: kern[i])           # dominant MFMA kernel
+    achieved = gf[names[dom]] / (kern[dom] * 1e-3)
+    line = {
+        "metric": "H_eff*psi GFLOP/s (FP64, Hubbard MPO d=4 w=6, m=%d)" % m,
+        "value": round(F / ms * 1e-6, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded Gaussian MPS environments, Gaussian psi)",
+        "config": {"workload": "heff_microbench_hubbard", "m": m, "d": d, "w": w,
+                   "flop_per_step": F, "seeds": {"left": synth.SEED_LEFT, "right": synth.SEED_RIGHT,
+                                                 "psi": synth.SEED_PSI}},
+        "pct_fp64_mfma_peak": round(100 * F / (ms * 1e-3) / PEAK["f64"], 2),
+        "roofline": {"bound": "mfma", "kernel": names[dom], "achieved": round(achieved / 1e12, 3),
+                     "peak": PEAK["f64"] / 1e12, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK["f64"], 4), "traffic": None},
+        "per_m": {str(k): {"f64_gflops": round(v["gflops"], 1),
+                           "f64_pct_peak": round(100 * v["gflops"] * 1e9 / PEAK["f64"], 2),
+                           "f32_gflops": round(v["f32"]["gflops"], 1) if "f32" in v else None,
+                           "f32_pct_peak": round(100 * v["f32"]["gflops"] * 1e9 / PEAK["f32"], 2) if "f32" in v else None,
+                           "kernel_ms_f64": {a: round(b, 4) for a, b in v["kernel_ms"].items()}}
+                  for k, v in results.items()},
+    }
+    if not args.no_cpu:
+        print("bench: cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        Ln, Wn, Rn, pn = [x.cpu().numpy() for x in (L, W, R, psi)]
+        dt, reps, threads = cpu_baseline(Ln, Wn, Rn, pn, args.cpu_budget)
+        line["cpu_baseline"] = {"value": round(F / dt * 1e-9, 2), "unit": "GFLOP/s", "cores": threads,
+                                "kind": "oracle",
+                                "sample": "%d H_eff application(s) at m=%d (same arrays), %.2f s each" % (reps, m, dt)}
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

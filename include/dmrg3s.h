@@ -1,0 +1,277 @@
+/*
+ * dmrg3s.h -- C-ABI of the MI355X hot path of strictly single-site DMRG with
+ * subspace expansion (DMRG3S; Hubig, McCulloch, Schollwoeck, Wolf).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - All tensors are real, dense and row-major.  Tensor pointers are DEVICE
+ *    pointers owned by the caller unless a comment says "host".  The library
+ *    never frees caller memory; it owns only its workspace (Sec. "Ownership").
+ *  - Index names follow the paper's notation:
+ *      L[a, w, x]    (m_l, w_l, m_l)   left environment L_{i-1}; a bra, x ket
+ *      W[w, v, s, t] (w_l, w_r, d, d)  MPO tensor W_i; s out (bra), t in (ket)
+ *                                      (the paper's (d, d, w, w), permuted)
+ *      psi[x, t, y]  (m_l, d, m_r)     site tensor M_i (paper: (d, m, m), permuted)
+ *      R[b, v, y]    (m_r, w_r, m_r)   right environment R_{i+1}; b bra, y ket
+ *  - Dimensions are ints >= 1.  Every call checks shapes, nulls and enums
+ *    before any launch and returns D3S_EINVAL with a message (d3s_last_error)
+ *    when they are wrong.  HIP / rocSOLVER failures return D3S_EDEVICE.
+ *  - Calls are stream-ordered on the context's stream and asynchronous unless
+ *    they return host values (truncate, energy, lanczos, sweep, prepare),
+ *    which synchronise the stream.
+ *  - No exception and no abort crosses this boundary.
+ *
+ * Ownership
+ * ---------
+ *  The context owns a grow-only workspace (intermediates T1/T2, Krylov basis,
+ *  Gram matrix, eigen-workspace).  It is allocated with the optional
+ *  allocator callbacks (stream-ordered) or with hipMalloc, and released by
+ *  d3s_destroy.  rocSOLVER, used for the FP64 symmetric eigensolve of the
+ *  truncation, allocates its own internal workspace.
+ */
+#ifndef DMRG3S_H
+#define DMRG3S_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  D3S_OK = 0,
+  D3S_ENOCONV = 1,   /* warning: the eigensolver hit its limit; the output is the best Ritz pair */
+  D3S_EINVAL = -1,   /* bad argument (shape, null pointer, enum) -- nothing was launched */
+  D3S_ENOMEM = -2,   /* workspace allocation failed */
+  D3S_EDEVICE = -3,  /* HIP or rocSOLVER error */
+  D3S_ENUMERIC = -4  /* non-finite energy or norm */
+} d3s_status;
+
+/* Arithmetic of the contractions.  Element types of the tensor pointers:
+ *  D3S_F64 : every tensor double.
+ *  D3S_F32 : every tensor float (FP32 MFMA, FP32 accumulation).
+ *  D3S_BF16: L, R, psi bfloat16 (uint16 bits), W float, out float
+ *            (BF16 MFMA with FP32 accumulation). */
+typedef enum { D3S_F64 = 0, D3S_F32 = 1, D3S_BF16 = 2 } d3s_prec;
+
+/* Sweep direction of a site update: left-to-right expands the right bond
+ * of the site, right-to-left its left bond (Sec. 4.1). */
+typedef enum { D3S_L2R = 0, D3S_R2L = 1 } d3s_dir;
+
+typedef struct d3s_ctx_s* d3s_ctx;
+
+/* Optional stream-ordered allocator for the workspace; NULL = hipMalloc. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* stream, void* user);
+  void (*free)(void* ptr, void* stream, void* user);
+  void* user;
+} d3s_allocator;
+
+/* Create a context on `device` issuing work on `stream` (a hipStream_t;
+ * NULL = the null stream).  `alloc` may be NULL.  *ctx is set on success. */
+d3s_status d3s_create(d3s_ctx* ctx, int device, void* stream, const d3s_allocator* alloc);
+/* Release the workspace and the context.  NULL is ignored. */
+void d3s_destroy(d3s_ctx ctx);
+/* Message of the last non-OK status on this context ("" if none).  Owned by
+ * the context, valid until the next call on it. */
+const char* d3s_last_error(d3s_ctx ctx);
+/* Change the stream of a context. */
+d3s_status d3s_set_stream(d3s_ctx ctx, void* stream);
+/* Wait for all work issued on the context's stream. */
+d3s_status d3s_synchronize(d3s_ctx ctx);
+/* Library version string (host, static). */
+const char* d3s_version(void);
+/* GEMM tile configuration: -1 = size heuristic (default), 0 = 128x128
+ * block tiles (4 waves of 64x64), 1 = 64x64 block tiles (4 waves of 32x32). */
+d3s_status d3s_set_tile_config(d3s_ctx ctx, int cfg);
+
+/*
+ * H_eff * psi  (eq. es-iter, Sec. 5):
+ *   out[a,s,b] = sum_{w,v,x,t,y} L[a,w,x] W[w,v,s,t] psi[x,t,y] R[b,v,y]
+ * contracted in the order (((L psi) W) R) of Sec. 5: a GEMM over the left
+ * MPS bond (M = m_l w_l, K = m_l, N = d m_r), the W-map over (w, t), and a
+ * GEMM over (v, y) (M = m_l d, K = w_r m_r, N = m_r).
+ * Element types follow `prec` (see d3s_prec).  `out` must not alias an input.
+ * Asynchronous.
+ */
+d3s_status d3s_apply_heff(d3s_ctx ctx, d3s_prec prec, int ml, int d, int mr, int wl, int wr,
+                          const void* L, const void* W, const void* R, const void* psi, void* out);
+
+/* Per-kernel timing of d3s_apply_heff: while enabled, HIP events are
+ * recorded on the context's stream around each of its three launches (GEMM
+ * over the left bond, W-map, GEMM over (v, y)) for up to `capacity` calls.
+ * d3s_profile_end synchronises, writes the summed milliseconds of the three
+ * kernels to total_ms[0..2] (host) and the number of timed calls to *count,
+ * and disables the recording. */
+d3s_status d3s_profile_begin(d3s_ctx ctx, int capacity);
+d3s_status d3s_profile_end(d3s_ctx ctx, double* total_ms, int* count);
+
+/*
+ * Subspace expansion (Sec. 4.1) with the expansion term of eq. subexp-ourt
+ * (Sec. 4.2), FP64:
+ *   L2R: P[a,s,v,y] = alpha sum L[a,w,x] W[w,v,s,t] psi[x,t,y]
+ *        Mtilde = [psi | P], an (m_l d) x (m_r + w_r m_r) row-major matrix:
+ *        row (a,s), columns y (psi) then (v,y) (P).  `env` is L (m_l, w_l, m_l).
+ *   R2L: P[w,a,s,b] = alpha sum W[w,v,s,t] psi[a,t,y] R[b,v,y]
+ *        Mtilde = [psi ; P], an (m_l + w_l m_l) x (d m_r) row-major matrix:
+ *        rows a (psi) then (w,a) (P), column (s,b).  `env` is R (m_r, w_r, m_r).
+ * The zero block of the neighbour (Sec. 4.1) is never materialised.
+ * Asynchronous.
+ */
+d3s_status d3s_expand_subspace(d3s_ctx ctx, d3s_dir dir, int ml, int d, int mr, int wl, int wr,
+                               const double* env, const double* W, const double* psi,
+                               double alpha, double* Mtilde);
+
+/*
+ * Truncation of the expanded bond and absorption into the neighbour
+ * (steps 4-5 of the site update, Sec. 5; cost discussion in Sec. 4.2), FP64.
+ *   L2R: Mtilde is (m_l d) x width.  Its top-k left singular vectors U_k give
+ *        site_out = U_k as (m_l, d, k).  The neighbour B (m_r x nbr_other,
+ *        i.e. (m_r, d', m') flattened) becomes nbr_out = (U_k^T psi_mat) B,
+ *        k x nbr_other: only the first m_r columns of S V^T meet the nonzero
+ *        rows of the zero-padded neighbour.
+ *   R2L: Mtilde is width x (d m_r).  Its top-k right singular vectors give
+ *        site_out = V_k^T as (k, d, m_r).  The neighbour A (nbr_other x m_l)
+ *        becomes nbr_out = A (psi_mat V_k), nbr_other x k.
+ * k = min(kmax, #{ j : s_j > rel_cutoff * s_0 }).  Singular values come from
+ * the FP64 Gram matrix of Mtilde on its smaller side and rocSOLVER's dsyevd.
+ * `renormalize` != 0 scales nbr_out to unit Frobenius norm.
+ * s_host (host, may be NULL) receives the min(m_l d, width) (L2R) or
+ * min(width, d m_r) (R2L) singular values, descending.  *k_out (host) and
+ * *discarded (host, sum of the dropped s_j^2) are set.  Synchronises.
+ */
+d3s_status d3s_truncate(d3s_ctx ctx, d3s_dir dir, int ml, int d, int mr, long width,
+                        const double* Mtilde, const double* psi, int kmax, double rel_cutoff,
+                        const double* nbr_in, long nbr_other, double* site_out, double* nbr_out,
+                        int renormalize, double* s_host, int* k_out, double* discarded);
+
+/*
+ * Environment update (Sec. 2: L_i = L_{i-1} A_i^+ W_i A_i, R_i = R_{i+1} B_i^+ W_i B_i;
+ * step 6 of Sec. 5), FP64.
+ *   L2R: env_in = L (m_l, w_l, m_l), site = A (m_l, d, m_r)
+ *        -> env_out[b,v,y] = sum L[a,w,x] A[a,s,b] W[w,v,s,t] A[x,t,y], (m_r, w_r, m_r)
+ *   R2L: env_in = R (m_r, w_r, m_r), site = B (m_l, d, m_r)
+ *        -> env_out[a,w,x] = sum B[a,s,b] W[w,v,s,t] B[x,t,y] R[b,v,y], (m_l, w_l, m_l)
+ * Asynchronous.
+ */
+d3s_status d3s_update_env(d3s_ctx ctx, d3s_dir dir, int ml, int d, int mr, int wl, int wr,
+                          const double* env_in, const double* W, const double* site,
+                          double* env_out);
+
+/*
+ * Smallest eigenpair of H_eff (step 1 of Sec. 5: "an eigensolver targeting
+ * the smallest eigenvalue"): Lanczos with full FP64 re-orthogonalisation,
+ * warm-started from psi, at most kmax Krylov vectors per restart, stopping at
+ * residual <= tol * max(1, |theta|) or after max_matvecs products.  psi (FP64,
+ * in/out) receives the normalised Ritz vector, *theta (host) the Ritz value,
+ * *matvecs (host, may be NULL) the number of H_eff products.
+ * `prec` selects the arithmetic of the products: D3S_F64 is the plain path;
+ * D3S_F32 / D3S_BF16 run the products on FP32 / BF16 MFMA from cast copies of
+ * L, R and recover FP64 accuracy by FP64 residual refinement of the Ritz
+ * vector (the Krylov vectors, re-orthogonalisation and tridiagonal problem
+ * stay FP64).  Returns D3S_ENOCONV (a warning) when the limit was hit.
+ * Synchronises.
+ */
+d3s_status d3s_lanczos(d3s_ctx ctx, d3s_prec prec, int ml, int d, int mr, int wl, int wr,
+                       const double* L, const double* W, const double* R, double* psi,
+                       double tol, int kmax, int max_matvecs, double* theta, int* matvecs);
+
+/* <psi|H_eff|psi> / <psi|psi> in FP64 (host result).  Synchronises. */
+d3s_status d3s_energy(d3s_ctx ctx, int ml, int d, int mr, int wl, int wr, const double* L,
+                      const double* W, const double* R, const double* psi, double* energy);
+
+/*
+ * Adjoint of H_eff with respect to W (FP64): for y = H_eff(W) psi and a
+ * cotangent ybar (m_l, d, m_r),
+ *   Wbar[w,v,s,t] = sum_{a,b,x,y} ybar[a,s,b] L[a,w,x] psi[x,t,y] R[b,v,y],
+ * shape (w_l, w_r, d, d).  With ybar = psi this is dE/dW of <psi|H_eff|psi>.
+ * (The paper is silent on derivatives; this is the exact vector-Jacobian
+ * product of the linear map W -> H_eff(W) psi.)  Asynchronous.
+ */
+d3s_status d3s_heff_grad_W(d3s_ctx ctx, int ml, int d, int mr, int wl, int wr, const double* L,
+                           const double* R, const double* psi, const double* ybar, double* Wbar);
+
+/* ---------------------------------------------------------------- sweeps */
+
+/* A finite MPS with its MPO and environments, all FP64 device buffers owned
+ * by the caller (Sec. 2 notation, sites numbered 0..l-1 here):
+ *   site[i]  M_i, (m[i], d, m[i+1]), capacity >= mmax*d*mmax doubles
+ *   mpo[i]   W_i, (w[i], w[i+1], d, d)
+ *   lenv[i]  environment of sites 0..i-1, (m[i], w[i], m[i]),   capacity >= mmax*wmax*mmax
+ *   renv[i]  environment of sites i+1..l-1, (m[i+1], w[i+1], m[i+1]), same capacity
+ * m (host, l+1 entries, m[0] = m[l] = 1) holds the current bond dimensions and
+ * is updated in place; w (host, l+1 entries, w[0] = w[l] = 1).  The
+ * orthogonality centre is tracked in `center`. */
+typedef struct {
+  int l;
+  int d;
+  int mmax;
+  int* m;
+  const int* w;
+  double** site;
+  double* const* mpo;
+  double** lenv;
+  double** renv;
+  int center;
+} d3s_state;
+
+typedef struct {
+  double alpha;          /* in/out: mixing factor of the expansion term (Sec. 6) */
+  int adaptive_alpha;    /* 1: adapt alpha after every site update (Sec. 6); 0: keep it */
+  double eps;            /* singular values s_j <= eps * s_0 are dropped (1e-14) */
+  double lanczos_tol;    /* residual tolerance of the eigensolver (1e-12) */
+  int lanczos_kmax;      /* Krylov vectors per restart (40) */
+  int lanczos_max_matvecs; /* products per site update (2000) */
+  d3s_prec prec;         /* arithmetic of the eigensolver's H_eff products */
+  double e_before;       /* in/out: energy of the state entering the next site update */
+} d3s_sweep_params;
+
+/* One record per site update (steps 1-8 of Sec. 5). */
+typedef struct {
+  int site, dir, k, matvecs;
+  double e_before, lambda, e_f, alpha, discarded;
+  double t_eig, t_expand, t_trunc, t_env, t_energy;  /* seconds */
+} d3s_site_record;
+
+typedef struct {
+  int capacity;              /* entries available in `records` (>= 2 (l-1)) */
+  int count;                 /* out */
+  d3s_site_record* records;  /* host array */
+  double energy;             /* out: last lambda* of the sweep */
+  double seconds;            /* out: wall time of the sweep */
+  int nonconverged;          /* out: eigensolves that hit their limit */
+} d3s_sweep_stats;
+
+/* Bring a state with Gaussian (or any) site tensors into left-canonical form
+ * with its centre on the last site (QR-like gauge through the truncation
+ * machinery without expansion), normalise it, set lenv[0] = renv[l-1] = 1,
+ * build lenv[1..l-1] and return <Psi|H|Psi> in *energy (host).  Bond
+ * dimensions in m are capped at min(mmax, d^b, d^(l-b)).  Synchronises. */
+d3s_status d3s_prepare(d3s_ctx ctx, d3s_state* state, double* energy);
+
+/* One full sweep: right-to-left over sites l-1..1, then left-to-right over
+ * sites 0..l-2, every site update being steps 1-8 of Sec. 5 with the
+ * alpha rule of Sec. 6 (see DESIGN notes in the source for the readings).
+ * Requires the centre on site l-1 (as left by d3s_prepare or a previous
+ * sweep).  Synchronises. */
+d3s_status d3s_sweep(d3s_ctx ctx, d3s_state* state, d3s_sweep_params* params,
+                     d3s_sweep_stats* stats);
+
+/* ---------------------------------------------------------------- models */
+/* MPO builders (host arrays, FP64, layout W[w,v,s,t], one block per site,
+ * concatenated; offsets[i] = start of site i, dims[i] = w_i for i = 0..l).
+ * `out` may be NULL to query the total number of doubles in *total. */
+/* Spin-1/2 exchange: H = sum_{i<j<=i+range} J_ij S_i.S_j; J given as an
+ * l x range table, J[i*range + r-1] = J_{i,i+r}. */
+d3s_status d3s_mpo_spin_exchange(int l, int range, const double* J, double* out, long* offsets,
+                                 int* dims, long* total);
+/* Spinful fermions: H = -sum t_ij (c+_is c_js + h.c.) + U sum n_up n_dn - sum mu_i n_i,
+ * t given as an l x range table like J; Jordan-Wigner strings between partners;
+ * site basis (|0>, |up>, |dn>, |updn>). */
+d3s_status d3s_mpo_fermion_hopping(int l, int range, const double* t, double U, const double* mu,
+                                   double* out, long* offsets, int* dims, long* total);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DMRG3S_H */

@@ -1,0 +1,372 @@
+"""Thin ctypes binding of libdmrg3s (include/dmrg3s.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+library.  Tensors are torch tensors on the GPU (device memory and streams are
+all torch is used for); their data pointers and the current HIP stream are
+handed to the C-ABI.  Importing this module loads the library and raises
+ImportError when it has not been built.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libdmrg3s.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libdmrg3s.so is not built (run __graft_entry__.build() or "
+                      "python paper_1501_05504_amd/build_lib.py): " + LIB_PATH)
+_lib = ctypes.CDLL(LIB_PATH)
+
+F64, F32, BF16 = 0, 1, 2
+L2R, R2L = 0, 1
+OK, ENOCONV, EINVAL, ENOMEM, EDEVICE, ENUMERIC = 0, 1, -1, -2, -3, -4
+_PREC = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}
+
+c_int, c_long, c_double, c_void_p = ctypes.c_int, ctypes.c_long, ctypes.c_double, ctypes.c_void_p
+c_int_p, c_double_p = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
+
+
+class d3s_allocator(ctypes.Structure):
+    _fields_ = [("alloc", c_void_p), ("free", c_void_p), ("user", c_void_p)]
+
+
+class d3s_state(ctypes.Structure):
+    _fields_ = [("l", c_int), ("d", c_int), ("mmax", c_int), ("m", c_int_p), ("w", c_int_p),
+                ("site", ctypes.POINTER(c_void_p)), ("mpo", ctypes.POINTER(c_void_p)),
+                ("lenv", ctypes.POINTER(c_void_p)), ("renv", ctypes.POINTER(c_void_p)),
+                ("center", c_int)]
+
+
+class d3s_sweep_params(ctypes.Structure):
+    _fields_ = [("alpha", c_double), ("adaptive_alpha", c_int), ("eps", c_double),
+                ("lanczos_tol", c_double), ("lanczos_kmax", c_int), ("lanczos_max_matvecs", c_int),
+                ("prec", c_int), ("e_before", c_double)]
+
+
+class d3s_site_record(ctypes.Structure):
+    _fields_ = [("site", c_int), ("dir", c_int), ("k", c_int), ("matvecs", c_int),
+                ("e_before", c_double), ("lam", c_double), ("e_f", c_double), ("alpha", c_double),
+                ("discarded", c_double), ("t_eig", c_double), ("t_expand", c_double),
+                ("t_trunc", c_double), ("t_env", c_double), ("t_energy", c_double)]
+
+
+class d3s_sweep_stats(ctypes.Structure):
+    _fields_ = [("capacity", c_int), ("count", c_int), ("records", ctypes.POINTER(d3s_site_record)),
+                ("energy", c_double), ("seconds", c_double), ("nonconverged", c_int)]
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_create = _sig("d3s_create", c_int, [ctypes.POINTER(c_void_p), c_int, c_void_p, ctypes.POINTER(d3s_allocator)])
+_destroy = _sig("d3s_destroy", None, [c_void_p])
+_last_error = _sig("d3s_last_error", ctypes.c_char_p, [c_void_p])
+_set_stream = _sig("d3s_set_stream", c_int, [c_void_p, c_void_p])
+_synchronize = _sig("d3s_synchronize", c_int, [c_void_p])
+_version = _sig("d3s_version", ctypes.c_char_p, [])
+_set_tile_config = _sig("d3s_set_tile_config", c_int, [c_void_p, c_int])
+_profile_begin = _sig("d3s_profile_begin", c_int, [c_void_p, c_int])
+_profile_end = _sig("d3s_profile_end", c_int, [c_void_p, c_double_p, c_int_p])
+_apply_heff = _sig("d3s_apply_heff", c_int, [c_void_p, c_int] + [c_int] * 5 + [c_void_p] * 5)
+_expand = _sig("d3s_expand_subspace", c_int, [c_void_p, c_int] + [c_int] * 5 + [c_void_p] * 3 +
+               [c_double, c_void_p])
+_truncate = _sig("d3s_truncate", c_int, [c_void_p, c_int, c_int, c_int, c_int, c_long, c_void_p, c_void_p,
+                                         c_int, c_double, c_void_p, c_long, c_void_p, c_void_p, c_int,
+                                         c_double_p, c_int_p, c_double_p])
+_update_env = _sig("d3s_update_env", c_int, [c_void_p, c_int] + [c_int] * 5 + [c_void_p] * 4)
+_lanczos = _sig("d3s_lanczos", c_int, [c_void_p, c_int] + [c_int] * 5 + [c_void_p] * 4 +
+                [c_double, c_int, c_int, c_double_p, c_int_p])
+_energy = _sig("d3s_energy", c_int, [c_void_p] + [c_int] * 5 + [c_void_p] * 4 + [c_double_p])
+_grad_w = _sig("d3s_heff_grad_W", c_int, [c_void_p] + [c_int] * 5 + [c_void_p] * 5)
+_prepare = _sig("d3s_prepare", c_int, [c_void_p, ctypes.POINTER(d3s_state), c_double_p])
+_sweep = _sig("d3s_sweep", c_int, [c_void_p, ctypes.POINTER(d3s_state), ctypes.POINTER(d3s_sweep_params),
+                                   ctypes.POINTER(d3s_sweep_stats)])
+_mpo_spin = _sig("d3s_mpo_spin_exchange", c_int, [c_int, c_int, c_double_p, c_double_p,
+                                                  ctypes.POINTER(c_long), c_int_p, ctypes.POINTER(c_long)])
+_mpo_fermion = _sig("d3s_mpo_fermion_hopping", c_int, [c_int, c_int, c_double_p, c_double, c_double_p,
+                                                       c_double_p, ctypes.POINTER(c_long), c_int_p,
+                                                       ctypes.POINTER(c_long)])
+
+
+class D3SError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("dmrg3s status %d: %s" % (status, msg))
+        self.status = status
+
+
+def version():
+    return _version().decode()
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A library context bound to a device and to torch's current stream."""
+
+    def __init__(self, device=0):
+        self.device = device
+        h = c_void_p()
+        stream = torch.cuda.current_stream(device).cuda_stream
+        st = _create(ctypes.byref(h), device, c_void_p(stream), None)
+        if st != OK:
+            raise D3SError(st, "d3s_create failed")
+        self.h = h
+
+    def close(self):
+        if self.h:
+            _destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, warn_ok=False):
+        if st == OK or (warn_ok and st == ENOCONV):
+            return st
+        raise D3SError(st, _last_error(self.h).decode())
+
+    def _sync_stream(self):
+        self._check(_set_stream(self.h, c_void_p(torch.cuda.current_stream(self.device).cuda_stream)))
+
+    def synchronize(self):
+        self._check(_synchronize(self.h))
+
+    def set_tile_config(self, cfg):
+        self._check(_set_tile_config(self.h, cfg))
+
+    def profile_begin(self, capacity):
+        self._check(_profile_begin(self.h, capacity))
+
+    def profile_end(self):
+        """Returns ([ms GEMM-1, ms W-map, ms GEMM-2] summed, number of calls)."""
+        ms = (ctypes.c_double * 3)()
+        n = c_int()
+        self._check(_profile_end(self.h, ms, ctypes.byref(n)))
+        return list(ms), n.value
+
+    # --- the hot path ---------------------------------------------------
+    def apply_heff(self, L, W, R, psi, out):
+        self._sync_stream()
+        ml, d, mr = psi.shape
+        wl, wr = W.shape[0], W.shape[1]
+        prec = _PREC[psi.dtype]
+        return self._check(_apply_heff(self.h, prec, ml, d, mr, wl, wr, _ptr(L), _ptr(W), _ptr(R),
+                                       _ptr(psi), _ptr(out)))
+
+    def expand_subspace(self, direction, env, W, psi, alpha, Mtilde):
+        self._sync_stream()
+        ml, d, mr = psi.shape
+        wl, wr = W.shape[0], W.shape[1]
+        return self._check(_expand(self.h, direction, ml, d, mr, wl, wr, _ptr(env), _ptr(W), _ptr(psi),
+                                   float(alpha), _ptr(Mtilde)))
+
+    def truncate(self, direction, Mtilde, psi, kmax, rel_cutoff, nbr, site_out, nbr_out, renormalize=True):
+        """Returns (k, discarded, singular values)."""
+        self._sync_stream()
+        ml, d, mr = psi.shape
+        if direction == L2R:
+            width = Mtilde.shape[1]
+            other = nbr.numel() // mr
+            n = ml * d
+        else:
+            width = Mtilde.shape[0]
+            other = nbr.numel() // ml
+            n = d * mr
+        s = (ctypes.c_double * n)()
+        k = c_int()
+        disc = c_double()
+        self._check(_truncate(self.h, direction, ml, d, mr, width, _ptr(Mtilde), _ptr(psi), kmax,
+                              float(rel_cutoff), _ptr(nbr), other, _ptr(site_out), _ptr(nbr_out),
+                              1 if renormalize else 0, s, ctypes.byref(k), ctypes.byref(disc)))
+        return k.value, disc.value, list(s)
+
+    def update_env(self, direction, env_in, W, site, env_out):
+        self._sync_stream()
+        ml, d, mr = site.shape
+        wl, wr = W.shape[0], W.shape[1]
+        return self._check(_update_env(self.h, direction, ml, d, mr, wl, wr, _ptr(env_in), _ptr(W),
+                                       _ptr(site), _ptr(env_out)))
+
+    def lanczos(self, L, W, R, psi, tol=1e-12, kmax=40, max_matvecs=2000, prec=F64):
+        """Returns (theta, matvecs, converged); psi is overwritten by the Ritz vector."""
+        self._sync_stream()
+        ml, d, mr = psi.shape
+        wl, wr = W.shape[0], W.shape[1]
+        th = c_double()
+        nmv = c_int()
+        st = self._check(_lanczos(self.h, prec, ml, d, mr, wl, wr, _ptr(L), _ptr(W), _ptr(R), _ptr(psi),
+                                  float(tol), kmax, max_matvecs, ctypes.byref(th), ctypes.byref(nmv)),
+                         warn_ok=True)
+        return th.value, nmv.value, st == OK
+
+    def energy(self, L, W, R, psi):
+        self._sync_stream()
+        ml, d, mr = psi.shape
+        wl, wr = W.shape[0], W.shape[1]
+        e = c_double()
+        self._check(_energy(self.h, ml, d, mr, wl, wr, _ptr(L), _ptr(W), _ptr(R), _ptr(psi),
+                            ctypes.byref(e)))
+        return e.value
+
+    def heff_grad_W(self, L, R, psi, ybar, Wbar):
+        self._sync_stream()
+        ml, d, mr = psi.shape
+        wl, wr = Wbar.shape[0], Wbar.shape[1]
+        return self._check(_grad_w(self.h, ml, d, mr, wl, wr, _ptr(L), _ptr(R), _ptr(psi), _ptr(ybar),
+                                   _ptr(Wbar)))
+
+    def prepare(self, state):
+        self._sync_stream()
+        e = c_double()
+        self._check(_prepare(self.h, ctypes.byref(state.c), ctypes.byref(e)))
+        state.pull_dims()
+        return e.value
+
+    def sweep(self, state, params):
+        """One full sweep; returns (status, stats, records)."""
+        self._sync_stream()
+        cap = 2 * state.l
+        recs = (d3s_site_record * cap)()
+        stats = d3s_sweep_stats(cap, 0, recs, 0.0, 0.0, 0)
+        st = self._check(_sweep(self.h, ctypes.byref(state.c), ctypes.byref(params), ctypes.byref(stats)),
+                         warn_ok=True)
+        state.pull_dims()
+        return st, stats, [recs[i] for i in range(min(stats.count, cap))]
+
+
+class State:
+    """Device buffers of an MPS, its MPO and its environments (torch-owned),
+    described to the library by a d3s_state."""
+
+    def __init__(self, mpo_blocks, site_tensors, mmax, device="cuda"):
+        self.l = len(site_tensors)
+        self.d = site_tensors[0].shape[1]
+        self.mmax = mmax
+        w = [1] + [int(b.shape[1]) for b in mpo_blocks]
+        self.wmax = max(w)
+        cap_site = mmax * self.d * mmax
+        cap_env = mmax * self.wmax * mmax
+        self.site = [torch.zeros(cap_site, dtype=torch.float64, device=device) for _ in range(self.l)]
+        self.lenv = [torch.zeros(cap_env, dtype=torch.float64, device=device) for _ in range(self.l)]
+        self.renv = [torch.zeros(cap_env, dtype=torch.float64, device=device) for _ in range(self.l)]
+        self.mpo = [torch.as_tensor(b, dtype=torch.float64).contiguous().to(device) for b in mpo_blocks]
+        m = [1] + [int(t.shape[2]) for t in site_tensors]
+        for i, t in enumerate(site_tensors):
+            tt = torch.as_tensor(t, dtype=torch.float64).reshape(-1)
+            self.site[i][: tt.numel()].copy_(tt.to(device))
+        self._m = (c_int * (self.l + 1))(*m)
+        self._w = (c_int * (self.l + 1))(*w)
+        self._site = (c_void_p * self.l)(*[t.data_ptr() for t in self.site])
+        self._mpo = (c_void_p * self.l)(*[t.data_ptr() for t in self.mpo])
+        self._lenv = (c_void_p * self.l)(*[t.data_ptr() for t in self.lenv])
+        self._renv = (c_void_p * self.l)(*[t.data_ptr() for t in self.renv])
+        self.c = d3s_state(self.l, self.d, mmax, self._m, self._w, self._site, self._mpo, self._lenv,
+                           self._renv, self.l - 1)
+        self.m = list(m)
+        self.w = list(w)
+
+    def pull_dims(self):
+        self.m = [self._m[i] for i in range(self.l + 1)]
+
+    def site_tensor(self, i):
+        n = self.m[i] * self.d * self.m[i + 1]
+        return self.site[i][:n].reshape(self.m[i], self.d, self.m[i + 1])
+
+    def tensors(self):
+        return [self.site_tensor(i) for i in range(self.l)]
+
+
+def sweep_params(alpha=1e-3, adaptive=True, eps=1e-14, tol=1e-12, kmax=40, max_matvecs=2000, prec=F64,
+                 e_before=0.0):
+    return d3s_sweep_params(alpha, 1 if adaptive else 0, eps, tol, kmax, max_matvecs, prec, e_before)
+
+
+# --- model builders (host) -------------------------------------------------
+def _blocks(flat, offsets, dims, l, d):
+    out = []
+    for i in range(l):
+        n = dims[i] * dims[i + 1] * d * d
+        out.append(flat[offsets[i]: offsets[i] + n].reshape(dims[i], dims[i + 1], d, d).copy())
+    return out
+
+
+def mpo_spin_exchange(l, J_table):
+    """J_table: (l, range) array, J_table[i, r-1] = J_{i, i+r}."""
+    import numpy as np
+    J = np.ascontiguousarray(J_table, dtype=np.float64)
+    rng = J.shape[1]
+    total = c_long()
+    dims = (c_int * (l + 1))()
+    offs = (c_long * l)()
+    Jp = J.ctypes.data_as(c_double_p)
+    st = _mpo_spin(l, rng, Jp, None, offs, dims, ctypes.byref(total))
+    if st != OK:
+        raise D3SError(st, "d3s_mpo_spin_exchange")
+    flat = np.zeros(total.value)
+    _mpo_spin(l, rng, Jp, flat.ctypes.data_as(c_double_p), offs, dims, ctypes.byref(total))
+    return _blocks(flat, list(offs), list(dims), l, 2)
+
+
+def mpo_fermion_hopping(l, t_table, U=0.0, mu=None):
+    import numpy as np
+    t = np.ascontiguousarray(t_table, dtype=np.float64)
+    rng = t.shape[1]
+    mu_arr = None if mu is None else np.ascontiguousarray(mu, dtype=np.float64)
+    mup = None if mu_arr is None else mu_arr.ctypes.data_as(c_double_p)
+    total = c_long()
+    dims = (c_int * (l + 1))()
+    offs = (c_long * l)()
+    tp = t.ctypes.data_as(c_double_p)
+    st = _mpo_fermion(l, rng, tp, float(U), mup, None, offs, dims, ctypes.byref(total))
+    if st != OK:
+        raise D3SError(st, "d3s_mpo_fermion_hopping")
+    flat = np.zeros(total.value)
+    _mpo_fermion(l, rng, tp, float(U), mup, flat.ctypes.data_as(c_double_p), offs, dims, ctypes.byref(total))
+    return _blocks(flat, list(offs), list(dims), l, 4)
+
+
+def heisenberg_mpo(l, J=1.0):
+    import numpy as np
+    return mpo_spin_exchange(l, np.full((l, 1), J))
+
+
+def j1j2_mpo(l, J1=1.0, J2=0.0):
+    import numpy as np
+    tab = np.zeros((l, 2))
+    tab[:, 0] = J1
+    tab[:, 1] = J2
+    return mpo_spin_exchange(l, tab)
+
+
+def hubbard_chain_mpo(l, t=1.0, U=0.0, mu=None):
+    import numpy as np
+    return mpo_fermion_hopping(l, np.full((l, 1), t), U=U, mu=mu)
+
+
+def hubbard_cylinder_mpo(width, length, t=1.0, U=0.0):
+    """Sites numbered column by column (s = x*width + y), periodic across the
+    width; every column traversed in the same direction (hopping range = width)."""
+    import numpy as np
+    l = width * length
+    tab = np.zeros((l, width))
+    for x in range(length):
+        for y in range(width):
+            s = x * width + y
+            if width > 1 and (y + 1 < width or width > 2):
+                s2 = x * width + (y + 1) % width
+                i, j = min(s, s2), max(s, s2)
+                tab[i, j - i - 1] = t
+            if x + 1 < length:
+                tab[s, width - 1] = t
+    return mpo_fermion_hopping(l, tab, U=U)

@@ -1,0 +1,293 @@
+// The C-ABI of libdmrg3s: argument checks before any launch, then the
+// operations of ops.hip / sweep.hip.  No exception crosses this boundary.
+#include <rocblas/rocblas.h>
+
+#include <cmath>
+#include <new>
+
+#include "d3s_internal.h"
+
+struct d3s_ctx_s {
+  d3s::Ctx c;
+};
+
+namespace {
+
+using d3s::Error;
+
+template <typename F>
+d3s_status guarded(d3s_ctx ctx, F&& body) {
+  if (!ctx) return D3S_EINVAL;
+  try {
+    ctx->c.last_error.clear();
+    if (hipSetDevice(ctx->c.device) != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error{D3S_EDEVICE, "hipSetDevice failed"};
+    }
+    return body();
+  } catch (const Error& e) {
+    ctx->c.last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    ctx->c.last_error = "host allocation failed";
+    return D3S_ENOMEM;
+  } catch (...) {
+    ctx->c.last_error = "unexpected exception";
+    return D3S_EDEVICE;
+  }
+}
+
+void check_dims(int ml, int d, int mr, int wl, int wr) {
+  D3S_REQUIRE(ml >= 1 && d >= 1 && mr >= 1 && wl >= 1 && wr >= 1, "dimensions must be >= 1");
+  D3S_REQUIRE((long)wl * d <= 80 && (long)wr * d <= 80, "w * d must be <= 80");
+  D3S_REQUIRE((long)ml * wl * d * mr < (1L << 40), "tensor too large");
+  D3S_REQUIRE((long)ml * wl <= 0x7fffffffL && (long)wr * mr <= 0x7fffffffL && (long)d * mr <= 0x7fffffffL,
+              "GEMM extent exceeds 2^31");
+}
+
+void check_prec(d3s_prec p) {
+  D3S_REQUIRE(p == D3S_F64 || p == D3S_F32 || p == D3S_BF16, "invalid precision");
+}
+
+void check_dir(d3s_dir dir) { D3S_REQUIRE(dir == D3S_L2R || dir == D3S_R2L, "invalid direction"); }
+
+}  // namespace
+
+extern "C" {
+
+const char* d3s_version(void) { return "dmrg3s-mi355x 0.1 (gfx950)"; }
+
+d3s_status d3s_create(d3s_ctx* out, int device, void* stream, const d3s_allocator* alloc) {
+  if (!out) return D3S_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    (void)hipGetLastError();
+    return D3S_EINVAL;
+  }
+  if (alloc && (!alloc->alloc || !alloc->free)) return D3S_EINVAL;
+  d3s_ctx ctx = new (std::nothrow) d3s_ctx_s();
+  if (!ctx) return D3S_ENOMEM;
+  ctx->c.device = device;
+  ctx->c.stream = (hipStream_t)stream;
+  if (alloc) {
+    ctx->c.alloc = *alloc;
+    ctx->c.has_alloc = true;
+  }
+  if (hipSetDevice(device) != hipSuccess ||
+      hipHostMalloc((void**)&ctx->c.host_red, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    delete ctx;
+    return D3S_EDEVICE;
+  }
+  *out = ctx;
+  return D3S_OK;
+}
+
+void d3s_destroy(d3s_ctx ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->c.device);
+  (void)hipStreamSynchronize(ctx->c.stream);
+  for (hipEvent_t e : ctx->c.prof_ev) (void)hipEventDestroy(e);
+  d3s::ws_release_all(&ctx->c);
+  if (ctx->c.solver) rocblas_destroy_handle((rocblas_handle)ctx->c.solver);
+  if (ctx->c.host_red) (void)hipHostFree(ctx->c.host_red);
+  delete ctx;
+}
+
+const char* d3s_last_error(d3s_ctx ctx) { return ctx ? ctx->c.last_error.c_str() : "null context"; }
+
+d3s_status d3s_set_stream(d3s_ctx ctx, void* stream) {
+  return guarded(ctx, [&] {
+    ctx->c.stream = (hipStream_t)stream;
+    return D3S_OK;
+  });
+}
+
+d3s_status d3s_synchronize(d3s_ctx ctx) {
+  return guarded(ctx, [&] {
+    D3S_HIP(hipStreamSynchronize(ctx->c.stream));
+    return D3S_OK;
+  });
+}
+
+d3s_status d3s_set_tile_config(d3s_ctx ctx, int cfg) {
+  return guarded(ctx, [&] {
+    D3S_REQUIRE(cfg >= -1 && cfg <= 1, "tile config must be -1, 0 or 1");
+    ctx->c.tile_config = cfg;
+    return D3S_OK;
+  });
+}
+
+d3s_status d3s_profile_begin(d3s_ctx ctx, int capacity) {
+  return guarded(ctx, [&] {
+    D3S_REQUIRE(capacity >= 1 && capacity <= 100000, "capacity must be in [1, 100000]");
+    while ((int)ctx->c.prof_ev.size() < 4 * capacity) {
+      hipEvent_t e;
+      D3S_HIP(hipEventCreate(&e));
+      ctx->c.prof_ev.push_back(e);
+    }
+    ctx->c.prof_cap = capacity;
+    ctx->c.prof_n = 0;
+    ctx->c.prof = true;
+    return D3S_OK;
+  });
+}
+
+d3s_status d3s_profile_end(d3s_ctx ctx, double* total_ms, int* count) {
+  return guarded(ctx, [&] {
+    D3S_REQUIRE(total_ms && count, "null output");
+    D3S_HIP(hipStreamSynchronize(ctx->c.stream));
+    total_ms[0] = total_ms[1] = total_ms[2] = 0.0;
+    for (int i = 0; i < ctx->c.prof_n; ++i) {
+      for (int k = 0; k < 3; ++k) {
+        float ms = 0.f;
+        D3S_HIP(hipEventElapsedTime(&ms, ctx->c.prof_ev[4 * i + k], ctx->c.prof_ev[4 * i + k + 1]));
+        total_ms[k] += ms;
+      }
+    }
+    *count = ctx->c.prof_n;
+    ctx->c.prof = false;
+    ctx->c.prof_n = 0;
+    return D3S_OK;
+  });
+}
+
+d3s_status d3s_apply_heff(d3s_ctx ctx, d3s_prec prec, int ml, int d, int mr, int wl, int wr, const void* L,
+                          const void* W, const void* R, const void* psi, void* out) {
+  return guarded(ctx, [&] {
+    check_prec(prec);
+    check_dims(ml, d, mr, wl, wr);
+    D3S_REQUIRE(L && W && R && psi && out, "null tensor pointer");
+    D3S_REQUIRE(out != psi && out != L && out != R, "out must not alias an input");
+    d3s::op_apply_heff(&ctx->c, prec, ml, d, mr, wl, wr, L, W, R, psi, out);
+    return D3S_OK;
+  });
+}
+
+d3s_status d3s_expand_subspace(d3s_ctx ctx, d3s_dir dir, int ml, int d, int mr, int wl, int wr,
+                               const double* env, const double* W, const double* psi, double alpha,
+                               double* Mtilde) {
+  return guarded(ctx, [&] {
+    check_dir(dir);
+    check_dims(ml, d, mr, wl, wr);
+    D3S_REQUIRE(env && W && psi && Mtilde, "null tensor pointer");
+    D3S_REQUIRE(std::isfinite(alpha), "alpha must be finite");
+    d3s::op_expand(&ctx->c, dir, ml, d, mr, wl, wr, env, W, psi, alpha, Mtilde);
+    return D3S_OK;
+  });
+}
+
+d3s_status d3s_truncate(d3s_ctx ctx, d3s_dir dir, int ml, int d, int mr, long width, const double* Mtilde,
+                        const double* psi, int kmax, double rel_cutoff, const double* nbr_in, long nbr_other,
+                        double* site_out, double* nbr_out, int renormalize, double* s_host, int* k_out,
+                        double* discarded) {
+  return guarded(ctx, [&] {
+    check_dir(dir);
+    D3S_REQUIRE(ml >= 1 && d >= 1 && mr >= 1 && width >= 1 && nbr_other >= 1 && kmax >= 1,
+                "dimensions must be >= 1");
+    D3S_REQUIRE(Mtilde && psi && nbr_in && site_out && nbr_out && k_out && discarded, "null pointer");
+    D3S_REQUIRE(rel_cutoff >= 0.0, "rel_cutoff must be >= 0");
+    const long n = (dir == D3S_L2R) ? (long)ml * d : (long)d * mr;
+    D3S_REQUIRE(n <= 46340, "Gram dimension too large (n^2 must fit in int)");
+    if (dir == D3S_L2R) D3S_REQUIRE(width >= mr, "L2R: width must be >= m_r (psi occupies the first m_r columns)");
+    else D3S_REQUIRE(width >= ml, "R2L: width must be >= m_l (psi occupies the first m_l rows)");
+    D3S_REQUIRE(width <= 0x7fffffffL, "width too large");
+    d3s::TruncResult t = d3s::op_truncate(&ctx->c, dir, ml, d, mr, width, Mtilde, psi, kmax, rel_cutoff, nbr_in,
+                                          nbr_other, site_out, nbr_out, s_host, renormalize != 0);
+    D3S_HIP(hipStreamSynchronize(ctx->c.stream));
+    *k_out = t.k;
+    *discarded = t.discarded;
+    return D3S_OK;
+  });
+}
+
+d3s_status d3s_update_env(d3s_ctx ctx, d3s_dir dir, int ml, int d, int mr, int wl, int wr, const double* env_in,
+                          const double* W, const double* site, double* env_out) {
+  return guarded(ctx, [&] {
+    check_dir(dir);
+    check_dims(ml, d, mr, wl, wr);
+    D3S_REQUIRE(env_in && W && site && env_out, "null tensor pointer");
+    D3S_REQUIRE(env_out != env_in && env_out != site, "env_out must not alias an input");
+    d3s::op_update_env(&ctx->c, dir, ml, d, mr, wl, wr, env_in, W, site, env_out);
+    return D3S_OK;
+  });
+}
+
+d3s_status d3s_lanczos(d3s_ctx ctx, d3s_prec prec, int ml, int d, int mr, int wl, int wr, const double* L,
+                       const double* W, const double* R, double* psi, double tol, int kmax, int max_matvecs,
+                       double* theta, int* matvecs) {
+  return guarded(ctx, [&] {
+    check_prec(prec);
+    check_dims(ml, d, mr, wl, wr);
+    D3S_REQUIRE(L && W && R && psi && theta, "null pointer");
+    D3S_REQUIRE(kmax >= 2 && kmax <= 120, "kmax must be in [2, 120]");
+    D3S_REQUIRE(max_matvecs >= 1, "max_matvecs must be >= 1");
+    D3S_REQUIRE(tol > 0.0, "tol must be > 0");
+    d3s::LanczosResult r = d3s::op_lanczos(&ctx->c, prec, ml, d, mr, wl, wr, L, W, R, psi, tol, kmax, max_matvecs);
+    *theta = r.theta;
+    if (matvecs) *matvecs = r.matvecs;
+    return r.converged ? D3S_OK : D3S_ENOCONV;
+  });
+}
+
+d3s_status d3s_energy(d3s_ctx ctx, int ml, int d, int mr, int wl, int wr, const double* L, const double* W,
+                      const double* R, const double* psi, double* energy) {
+  return guarded(ctx, [&] {
+    check_dims(ml, d, mr, wl, wr);
+    D3S_REQUIRE(L && W && R && psi && energy, "null pointer");
+    *energy = d3s::op_energy(&ctx->c, ml, d, mr, wl, wr, L, W, R, psi);
+    return D3S_OK;
+  });
+}
+
+d3s_status d3s_heff_grad_W(d3s_ctx ctx, int ml, int d, int mr, int wl, int wr, const double* L, const double* R,
+                           const double* psi, const double* ybar, double* Wbar) {
+  return guarded(ctx, [&] {
+    check_dims(ml, d, mr, wl, wr);
+    D3S_REQUIRE(L && R && psi && ybar && Wbar, "null pointer");
+    d3s::op_heff_grad_W(&ctx->c, ml, d, mr, wl, wr, L, R, psi, ybar, Wbar);
+    return D3S_OK;
+  });
+}
+
+static void check_state(const d3s_state* s) {
+  D3S_REQUIRE(s, "null state");
+  D3S_REQUIRE(s->l >= 2 && s->d >= 1 && s->mmax >= 1, "state: need l >= 2, d >= 1, mmax >= 1");
+  D3S_REQUIRE(s->m && s->w && s->site && s->mpo && s->lenv && s->renv, "state: null array");
+  D3S_REQUIRE(s->m[0] == 1 && s->m[s->l] == 1 && s->w[0] == 1 && s->w[s->l] == 1,
+              "state: boundary bonds must be 1");
+  for (int i = 0; i < s->l; ++i) {
+    D3S_REQUIRE(s->site[i] && s->mpo[i] && s->lenv[i] && s->renv[i], "state: null tensor pointer");
+    D3S_REQUIRE(s->m[i] >= 1 && s->m[i] <= s->mmax, "state: bond dimension out of range");
+    D3S_REQUIRE(s->w[i] >= 1 && (long)s->w[i] * s->d <= 80, "state: MPO bond out of range");
+  }
+}
+
+d3s_status d3s_prepare(d3s_ctx ctx, d3s_state* state, double* energy) {
+  return guarded(ctx, [&] {
+    check_state(state);
+    D3S_REQUIRE(energy, "null energy pointer");
+    D3S_REQUIRE((long)state->d * state->mmax <= 46340, "d * mmax too large for the Gram route");
+    *energy = d3s::op_prepare(&ctx->c, state, 1e-14);
+    return D3S_OK;
+  });
+}
+
+d3s_status d3s_sweep(d3s_ctx ctx, d3s_state* state, d3s_sweep_params* params, d3s_sweep_stats* stats) {
+  return guarded(ctx, [&] {
+    check_state(state);
+    D3S_REQUIRE(params && stats, "null params or stats");
+    D3S_REQUIRE(stats->records || stats->capacity == 0, "stats: null records with capacity > 0");
+    check_prec(params->prec);
+    D3S_REQUIRE(params->lanczos_kmax >= 2 && params->lanczos_kmax <= 120, "lanczos_kmax must be in [2, 120]");
+    D3S_REQUIRE(params->lanczos_tol > 0.0 && params->lanczos_max_matvecs >= 1, "bad eigensolver limits");
+    D3S_REQUIRE(params->alpha >= 0.0 && std::isfinite(params->alpha), "alpha must be finite and >= 0");
+    D3S_REQUIRE((long)state->d * state->mmax <= 46340, "d * mmax too large for the Gram route");
+    d3s::op_sweep(&ctx->c, state, params, stats);
+    if (!std::isfinite(stats->energy)) throw Error{D3S_ENUMERIC, "sweep: non-finite energy"};
+    return stats->nonconverged ? D3S_ENOCONV : D3S_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,149 @@
+// Internal declarations of libdmrg3s (not part of the public C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dmrg3s.h"
+
+namespace d3s {
+
+typedef uint16_t bf16_t;   // raw bfloat16 bits (round-to-nearest-even on conversion)
+
+// ---------------------------------------------------------------- errors
+struct Error {
+  d3s_status code;
+  std::string msg;
+};
+
+#define D3S_HIP(call)                                                          \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess)                                                      \
+      throw ::d3s::Error{D3S_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define D3S_REQUIRE(cond, text)                                                \
+  do {                                                                         \
+    if (!(cond)) throw ::d3s::Error{D3S_EINVAL, std::string(text)};           \
+  } while (0)
+
+// ---------------------------------------------------------------- context
+enum WsSlot {
+  WS_T1 = 0, WS_T2, WS_LZ_V, WS_LZ_W, WS_LZ_COEF, WS_RED, WS_GRAM, WS_EIGVAL,
+  WS_EIGTMP, WS_UKT, WS_X, WS_MT, WS_CAST_L, WS_CAST_R, WS_CAST_X, WS_CAST_Y,
+  WS_CAST_W, WS_REF, WS_PSI, WS_INFO, WS_NBR, WS_MISC, WS_NSLOTS
+};
+
+struct Ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  d3s_allocator alloc{};
+  bool has_alloc = false;
+  void* ws_ptr[WS_NSLOTS] = {};
+  size_t ws_cap[WS_NSLOTS] = {};
+  void* solver = nullptr;            // rocblas_handle, created lazily
+  double* host_red = nullptr;        // pinned host staging for scalars
+  std::string last_error;
+  int tile_config = -1;              // GEMM tile configuration (-1 = heuristic)
+  // per-kernel profiling of H_eff: events around GEMM-1, W-map, GEMM-2
+  bool prof = false;
+  int prof_cap = 0, prof_n = 0;
+  std::vector<hipEvent_t> prof_ev;   // 4 per recorded application
+};
+
+void* ws_get(Ctx* c, int slot, size_t bytes);
+void ws_release_all(Ctx* c);
+
+// ---------------------------------------------------------------- GEMM
+// C[M x N] = alpha * A[M x K] * B[K x N] + beta * C, row-major C with ldc.
+// A is "K-contiguous" (A[m*lda + k]) when a_kc, else "M-contiguous" (A[k*lda + m]).
+// B is "K-contiguous" (B[n*ldb + k]) when b_kc, else "N-contiguous" (B[k*ldb + n]).
+// Batched over `batch` with element strides sA, sB, sC.
+struct GemmArgs {
+  int M, N, K;
+  const void* A; long lda; bool a_kc; long sA;
+  const void* B; long ldb; bool b_kc; long sB;
+  void* C; long ldc; long sC;
+  double alpha, beta;
+  int batch;
+};
+void gemm_f64(Ctx* c, const GemmArgs& g);
+void gemm_f32(Ctx* c, const GemmArgs& g);
+void gemm_bf16(Ctx* c, const GemmArgs& g);   // bf16 operands, fp32 C
+void gemm(Ctx* c, d3s_prec p, const GemmArgs& g);
+
+// ---------------------------------------------------------------- kernels
+// W-map of a left-to-right contraction:
+//   T2[a, s, v, y] = alpha * sum_{w,t} W[w, v, s, t] * T1[a, w, t, y]
+// T1 contiguous (ml, wl, d, mr); output row (a, s) at out + (a*d + s)*ld_out, inner (v, y).
+void wmap_l2r(Ctx* c, d3s_prec p, const void* T1, const void* W, void* out, long ld_out,
+              int ml, int d, int mr, int wl, int wr, double alpha);
+// W-map of a right-to-left contraction:
+//   Z[w, x, s, b] = alpha * sum_{v,t} W[w, v, s, t] * Y[x, t, b, v]
+// Y contiguous (ml, d, mr, wr); Z contiguous (wl, ml, d, mr).
+void wmap_r2l(Ctx* c, d3s_prec p, const void* Y, const void* W, void* Z,
+              int ml, int d, int mr, int wl, int wr, double alpha);
+
+// deterministic reductions (FP64)
+void dot_f64(Ctx* c, const double* x, const double* y, long n, double* out_dev);
+// coef[j] = <V_j, w> for j < k, V rows of length n with stride ldv
+void mdot_f64(Ctx* c, const double* V, long ldv, int k, const double* w, long n, double* coef_dev);
+// w += sign * sum_j coef[j] V_j  (coef on device)
+void maxpy_f64(Ctx* c, const double* V, long ldv, int k, const double* coef_dev, double sign,
+               double* w, long n);
+void scale_f64(Ctx* c, double* x, long n, double s_host);
+void scale_by_dev_f64(Ctx* c, double* x, long n, const double* s_dev, bool reciprocal);
+void axpby_f64(Ctx* c, double a, const double* x, double b, double* y, long n);
+void copy_f64(Ctx* c, const double* x, double* y, long n);
+void fill_f64(Ctx* c, double* x, long n, double v);
+// out[r][col] = in[col][r] for an R x C input (row-major), i.e. out is C x R
+void transpose_f64(Ctx* c, const double* in, long R, long C, double* out);
+// copy a rows x cols block with leading dimensions
+void copy2d_f64(Ctx* c, const double* src, long lds, double* dst, long ldd, long rows, long cols);
+// casts for the mixed-precision path
+void cast_f64_to_f32(Ctx* c, const double* x, float* y, long n);
+void cast_f64_to_bf16(Ctx* c, const double* x, bf16_t* y, long n);
+void cast_f32_to_f64(Ctx* c, const float* x, double* y, long n);
+// Wbar reduction of the adjoint: G[(w,t),(s,v)] = sum_{a,y} T1[a,w,t,y] * U[a,s,v,y]
+void adjoint_reduce_f64(Ctx* c, const double* T1, const double* U, double* G,
+                        int ml, int d, int mr, int wl, int wr);
+
+// ---------------------------------------------------------------- host-side ops
+void op_apply_heff(Ctx* c, d3s_prec p, int ml, int d, int mr, int wl, int wr,
+                   const void* L, const void* W, const void* R, const void* psi, void* out);
+void op_expand(Ctx* c, d3s_dir dir, int ml, int d, int mr, int wl, int wr,
+               const double* env, const double* W, const double* psi, double alpha, double* Mt);
+void op_update_env(Ctx* c, d3s_dir dir, int ml, int d, int mr, int wl, int wr,
+                   const double* env_in, const double* W, const double* site, double* env_out);
+struct TruncResult { int k; double discarded; double total; };
+TruncResult op_truncate(Ctx* c, d3s_dir dir, int ml, int d, int mr, long width,
+                        const double* Mt, const double* psi, int kmax, double eps,
+                        const double* nbr, long nbr_other, double* site_out, double* nbr_out,
+                        double* s_host, bool renormalize);
+struct LanczosResult { double theta; int matvecs; bool converged; int restarts; };
+LanczosResult op_lanczos(Ctx* c, d3s_prec p, int ml, int d, int mr, int wl, int wr,
+                         const double* L, const double* W, const double* R, double* psi,
+                         double tol, int kmax, int max_matvecs);
+double op_energy(Ctx* c, int ml, int d, int mr, int wl, int wr, const double* L,
+                 const double* W, const double* R, const double* psi);
+void op_heff_grad_W(Ctx* c, int ml, int d, int mr, int wl, int wr, const double* L,
+                    const double* R, const double* psi, const double* ybar, double* Wbar);
+
+double op_prepare(Ctx* c, d3s_state* s, double eps);
+void op_sweep(Ctx* c, d3s_state* s, d3s_sweep_params* p, d3s_sweep_stats* st);
+
+// host symmetric eigensolver (cyclic Jacobi) for small tridiagonal projections
+void jacobi_eigh(int n, std::vector<double>& A, std::vector<double>& evals,
+                 std::vector<double>& evecs);
+
+// rocSOLVER symmetric eigensolver (FP64, column-major, ascending eigenvalues)
+void syevd_f64(Ctx* c, int n, double* A, double* evals_dev);
+
+double read_scalar(Ctx* c, const double* dev);
+
+}  // namespace d3s

@@ -1,0 +1,401 @@
+// Bandwidth-bound kernels of the hot path: the W-maps (step 2 of the H_eff
+// ordering of Sec. 5), deterministic FP64 reductions and vector updates of
+// the Lanczos solver, layout helpers of the truncation, casts of the
+// mixed-precision path and the reduction of the W-adjoint.
+#include "d3s_internal.h"
+
+namespace d3s {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kRedBlocks = 1024;   // fixed partial count: reductions are order-deterministic
+
+__device__ __forceinline__ float bf16_to_f32(bf16_t h) {
+  return __uint_as_float(((uint32_t)h) << 16);
+}
+__device__ __forceinline__ bf16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (bf16_t)((u >> 16) | 0x40);   // quiet NaN
+  u += 0x7fffu + ((u >> 16) & 1u);                                           // round to nearest even
+  return (bf16_t)(u >> 16);
+}
+
+template <typename T> struct Cvt;
+template <> struct Cvt<double> {
+  __device__ static double ld(double x) { return x; }
+  __device__ static double st(double x) { return x; }
+};
+template <> struct Cvt<float> {
+  __device__ static float ld(float x) { return x; }
+  __device__ static float st(float x) { return x; }
+};
+template <> struct Cvt<bf16_t> {
+  __device__ static float ld(bf16_t x) { return bf16_to_f32(x); }
+  __device__ static bf16_t st(float x) { return f32_to_bf16(x); }
+};
+
+// ---------------------------------------------------------------- W-maps
+// One thread per (a, y): it holds the K = wl*d values T1[a, :, :, y] in
+// registers and produces the d*wr outputs; W (pre-scaled by alpha and laid
+// out as [(s,v)][(w,t)]) sits in LDS and is read by broadcast.
+template <typename Tin, typename Tout, typename Tc, int MAXK>
+__global__ __launch_bounds__(kThreads)
+void wmap_l2r_kernel(const Tin* __restrict__ T1, const Tc* __restrict__ Wg, Tout* __restrict__ out,
+                     long ld_out, int ml, int d, int mr, int wl, int wr, Tc alpha) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  Tc* sW = reinterpret_cast<Tc*>(smem_raw);
+  const int K = wl * d;
+  const int nOut = d * wr;
+  for (int i = threadIdx.x; i < K * nOut; i += blockDim.x) {
+    const int o = i / K, k = i - o * K;        // o = s*wr + v, k = w*d + t
+    const int s = o / wr, v = o - s * wr;
+    const int w = k / d, t = k - w * d;
+    sW[i] = alpha * Wg[((w * wr + v) * d + s) * d + t];
+  }
+  __syncthreads();
+  const int a = blockIdx.y;
+  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  if (y >= mr) return;
+  Tc in[MAXK];
+  const Tin* src = T1 + (long)a * K * mr + y;
+#pragma unroll
+  for (int k = 0; k < MAXK; ++k) in[k] = (k < K) ? (Tc)Cvt<Tin>::ld(src[(long)k * mr]) : Tc(0);
+  for (int o = 0; o < nOut; ++o) {
+    const Tc* wrow = sW + o * K;
+    Tc acc = 0;
+#pragma unroll
+    for (int k = 0; k < MAXK; ++k)
+      if (k < K) acc += wrow[k] * in[k];
+    const int s = o / wr, v = o - s * wr;
+    out[(long)(a * d + s) * ld_out + (long)v * mr + y] = Cvt<Tout>::st(acc);
+  }
+}
+
+// One thread per (x, b): inputs Y[x, t, b, :] for all t (K = d*wr values),
+// outputs Z[w, x, s, b] for all (w, s).
+template <typename Tin, typename Tout, typename Tc, int MAXK>
+__global__ __launch_bounds__(kThreads)
+void wmap_r2l_kernel(const Tin* __restrict__ Y, const Tc* __restrict__ Wg, Tout* __restrict__ Z,
+                     int ml, int d, int mr, int wl, int wr, Tc alpha) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  Tc* sW = reinterpret_cast<Tc*>(smem_raw);
+  const int K = d * wr;
+  const int nOut = wl * d;
+  for (int i = threadIdx.x; i < K * nOut; i += blockDim.x) {
+    const int o = i / K, k = i - o * K;        // o = w*d + s, k = t*wr + v
+    const int w = o / d, s = o - w * d;
+    const int t = k / wr, v = k - t * wr;
+    sW[i] = alpha * Wg[((w * wr + v) * d + s) * d + t];
+  }
+  __syncthreads();
+  const int x = blockIdx.y;
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= mr) return;
+  Tc in[MAXK];
+#pragma unroll
+  for (int k = 0; k < MAXK; ++k) {
+    if (k < K) {
+      const int t = k / wr, v = k - t * wr;
+      in[k] = (Tc)Cvt<Tin>::ld(Y[((long)(x * d + t) * mr + b) * wr + v]);
+    } else {
+      in[k] = Tc(0);
+    }
+  }
+  for (int o = 0; o < nOut; ++o) {
+    const Tc* wrow = sW + o * K;
+    Tc acc = 0;
+#pragma unroll
+    for (int k = 0; k < MAXK; ++k)
+      if (k < K) acc += wrow[k] * in[k];
+    const int w = o / d, s = o - w * d;
+    Z[((long)(w * ml + x) * d + s) * mr + b] = Cvt<Tout>::st(acc);
+  }
+}
+
+template <typename Tin, typename Tout, typename Tc>
+void wmap_l2r_t(Ctx* c, const void* T1, const void* W, void* out, long ld_out, int ml, int d,
+                int mr, int wl, int wr, double alpha) {
+  const int K = wl * d;
+  dim3 grid((mr + kThreads - 1) / kThreads, ml);
+  size_t sh = sizeof(Tc) * (size_t)K * d * wr;
+  auto args = [&](auto kern) {
+    hipLaunchKernelGGL(kern, grid, dim3(kThreads), sh, c->stream, (const Tin*)T1, (const Tc*)W,
+                       (Tout*)out, ld_out, ml, d, mr, wl, wr, (Tc)alpha);
+  };
+  if (K <= 8) args(wmap_l2r_kernel<Tin, Tout, Tc, 8>);
+  else if (K <= 16) args(wmap_l2r_kernel<Tin, Tout, Tc, 16>);
+  else if (K <= 32) args(wmap_l2r_kernel<Tin, Tout, Tc, 32>);
+  else if (K <= 80) args(wmap_l2r_kernel<Tin, Tout, Tc, 80>);
+  else throw Error{D3S_EINVAL, "W-map: w_l * d > 80 is not supported"};
+  D3S_HIP(hipGetLastError());
+}
+
+template <typename Tin, typename Tout, typename Tc>
+void wmap_r2l_t(Ctx* c, const void* Y, const void* W, void* Z, int ml, int d, int mr, int wl,
+                int wr, double alpha) {
+  const int K = d * wr;
+  dim3 grid((mr + kThreads - 1) / kThreads, ml);
+  size_t sh = sizeof(Tc) * (size_t)K * d * wl;
+  auto args = [&](auto kern) {
+    hipLaunchKernelGGL(kern, grid, dim3(kThreads), sh, c->stream, (const Tin*)Y, (const Tc*)W,
+                       (Tout*)Z, ml, d, mr, wl, wr, (Tc)alpha);
+  };
+  if (K <= 8) args(wmap_r2l_kernel<Tin, Tout, Tc, 8>);
+  else if (K <= 16) args(wmap_r2l_kernel<Tin, Tout, Tc, 16>);
+  else if (K <= 32) args(wmap_r2l_kernel<Tin, Tout, Tc, 32>);
+  else if (K <= 80) args(wmap_r2l_kernel<Tin, Tout, Tc, 80>);
+  else throw Error{D3S_EINVAL, "W-map: w_r * d > 80 is not supported"};
+  D3S_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += sh[w];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kThreads)
+void dot_partial_kernel(const double* __restrict__ x, const double* __restrict__ y, long n,
+                        double* __restrict__ part) {
+  __shared__ double sh[kThreads / 64];
+  double acc = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    acc += x[i] * y[i];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// coef-partials for k rows: part[j * gridDim.x + block]
+__global__ __launch_bounds__(kThreads)
+void mdot_partial_kernel(const double* __restrict__ V, long ldv, int k, const double* __restrict__ w,
+                         long n, double* __restrict__ part) {
+  __shared__ double sh[kThreads / 64];
+  for (int j = 0; j < k; ++j) {
+    const double* vj = V + (long)j * ldv;
+    double acc = 0.0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+      acc += vj[i] * w[i];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[(long)j * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+// out[j] = sum_b part[j * nb + b] in a fixed order; one block per j
+__global__ __launch_bounds__(kThreads)
+void reduce_rows_kernel(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  __shared__ double sh[kThreads / 64];
+  const int j = blockIdx.x;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += part[(long)j * nb + b];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[j] = s;
+}
+
+__global__ __launch_bounds__(kThreads)
+void maxpy_kernel(const double* __restrict__ V, long ldv, int k, const double* __restrict__ coef,
+                  double sign, double* __restrict__ w, long n) {
+  __shared__ double sc[128];
+  for (int j = threadIdx.x; j < k; j += blockDim.x) sc[j] = sign * coef[j];
+  __syncthreads();
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    double acc = w[i];
+    for (int j = 0; j < k; ++j) acc += sc[j] * V[(long)j * ldv + i];
+    w[i] = acc;
+  }
+}
+
+__global__ void scale_kernel(double* __restrict__ x, long n, double s) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    x[i] *= s;
+}
+
+__global__ void scale_dev_kernel(double* __restrict__ x, long n, const double* __restrict__ s, int recip_sqrt) {
+  const double f = recip_sqrt ? 1.0 / sqrt(*s) : *s;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    x[i] *= f;
+}
+
+__global__ void axpby_kernel(double a, const double* __restrict__ x, double b, double* __restrict__ y, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    y[i] = a * x[i] + b * y[i];
+}
+
+__global__ void fill_kernel(double* __restrict__ x, long n, double v) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+
+__global__ void transpose_kernel(const double* __restrict__ in, long R, long C, double* __restrict__ out) {
+  __shared__ double tile[32][33];
+  const long r0 = (long)blockIdx.y * 32, c0 = (long)blockIdx.x * 32;
+  for (int i = threadIdx.y; i < 32; i += blockDim.y) {
+    const long r = r0 + i, cc = c0 + threadIdx.x;
+    if (r < R && cc < C) tile[i][threadIdx.x] = in[r * C + cc];
+  }
+  __syncthreads();
+  for (int i = threadIdx.y; i < 32; i += blockDim.y) {
+    const long cc = c0 + i, r = r0 + threadIdx.x;
+    if (r < R && cc < C) out[cc * R + r] = tile[threadIdx.x][i];
+  }
+}
+
+__global__ void copy2d_kernel(const double* __restrict__ src, long lds, double* __restrict__ dst, long ldd,
+                              long rows, long cols) {
+  const long total = rows * cols;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+    const long r = i / cols, cc = i - r * cols;
+    dst[r * ldd + cc] = src[r * lds + cc];
+  }
+}
+
+template <typename Tout>
+__global__ void cast_kernel(const double* __restrict__ x, Tout* __restrict__ y, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    if constexpr (sizeof(Tout) == 2) y[i] = f32_to_bf16((float)x[i]);
+    else y[i] = (Tout)x[i];
+  }
+}
+
+__global__ void cast_f32_f64_kernel(const float* __restrict__ x, double* __restrict__ y, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    y[i] = (double)x[i];
+}
+
+// Wbar[w, v, s, t] = sum_a part[a][(w,t)][(s,v)], fixed order over a
+__global__ void adjoint_sum_kernel(const double* __restrict__ part, int ml, int d, int wl, int wr,
+                                   double* __restrict__ Wbar) {
+  const int n1 = wl * d, n2 = d * wr;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n1 * n2) return;
+  const int r = idx / n2, cc = idx - r * n2;     // r = (w,t), cc = (s,v)
+  double acc = 0.0;
+  for (int a = 0; a < ml; ++a) acc += part[(long)a * n1 * n2 + idx];
+  const int w = r / d, t = r - w * d;
+  const int s = cc / wr, v = cc - s * wr;
+  Wbar[((w * wr + v) * d + s) * d + t] = acc;
+}
+
+inline int grid_for(long n) {
+  long g = (n + kThreads - 1) / kThreads;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+}  // namespace
+
+void wmap_l2r(Ctx* c, d3s_prec p, const void* T1, const void* W, void* out, long ld_out, int ml,
+              int d, int mr, int wl, int wr, double alpha) {
+  if (p == D3S_F64) wmap_l2r_t<double, double, double>(c, T1, W, out, ld_out, ml, d, mr, wl, wr, alpha);
+  else if (p == D3S_F32) wmap_l2r_t<float, float, float>(c, T1, W, out, ld_out, ml, d, mr, wl, wr, alpha);
+  else wmap_l2r_t<float, bf16_t, float>(c, T1, W, out, ld_out, ml, d, mr, wl, wr, alpha);
+}
+
+void wmap_r2l(Ctx* c, d3s_prec p, const void* Y, const void* W, void* Z, int ml, int d, int mr,
+              int wl, int wr, double alpha) {
+  if (p == D3S_F64) wmap_r2l_t<double, double, double>(c, Y, W, Z, ml, d, mr, wl, wr, alpha);
+  else if (p == D3S_F32) wmap_r2l_t<float, float, float>(c, Y, W, Z, ml, d, mr, wl, wr, alpha);
+  else wmap_r2l_t<float, bf16_t, float>(c, Y, W, Z, ml, d, mr, wl, wr, alpha);
+}
+
+void dot_f64(Ctx* c, const double* x, const double* y, long n, double* out_dev) {
+  double* part = (double*)ws_get(c, WS_RED, sizeof(double) * kRedBlocks);
+  hipLaunchKernelGGL(dot_partial_kernel, dim3(kRedBlocks), dim3(kThreads), 0, c->stream, x, y, n, part);
+  hipLaunchKernelGGL(reduce_rows_kernel, dim3(1), dim3(kThreads), 0, c->stream, part, kRedBlocks, out_dev);
+  D3S_HIP(hipGetLastError());
+}
+
+void mdot_f64(Ctx* c, const double* V, long ldv, int k, const double* w, long n, double* coef_dev) {
+  if (k <= 0) return;
+  const int nb = 256;
+  double* part = (double*)ws_get(c, WS_RED, sizeof(double) * (size_t)nb * k);
+  hipLaunchKernelGGL(mdot_partial_kernel, dim3(nb), dim3(kThreads), 0, c->stream, V, ldv, k, w, n, part);
+  hipLaunchKernelGGL(reduce_rows_kernel, dim3(k), dim3(kThreads), 0, c->stream, part, nb, coef_dev);
+  D3S_HIP(hipGetLastError());
+}
+
+void maxpy_f64(Ctx* c, const double* V, long ldv, int k, const double* coef_dev, double sign, double* w,
+               long n) {
+  if (k <= 0) return;
+  if (k > 128) throw Error{D3S_EINVAL, "maxpy: more than 128 vectors"};
+  hipLaunchKernelGGL(maxpy_kernel, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, V, ldv, k, coef_dev,
+                     sign, w, n);
+  D3S_HIP(hipGetLastError());
+}
+
+void scale_f64(Ctx* c, double* x, long n, double s) {
+  hipLaunchKernelGGL(scale_kernel, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, x, n, s);
+  D3S_HIP(hipGetLastError());
+}
+
+void scale_by_dev_f64(Ctx* c, double* x, long n, const double* s_dev, bool reciprocal_sqrt) {
+  hipLaunchKernelGGL(scale_dev_kernel, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, x, n, s_dev,
+                     reciprocal_sqrt ? 1 : 0);
+  D3S_HIP(hipGetLastError());
+}
+
+void axpby_f64(Ctx* c, double a, const double* x, double b, double* y, long n) {
+  hipLaunchKernelGGL(axpby_kernel, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, a, x, b, y, n);
+  D3S_HIP(hipGetLastError());
+}
+
+void copy_f64(Ctx* c, const double* x, double* y, long n) {
+  if (n <= 0) return;
+  D3S_HIP(hipMemcpyAsync(y, x, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+}
+
+void fill_f64(Ctx* c, double* x, long n, double v) {
+  hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, x, n, v);
+  D3S_HIP(hipGetLastError());
+}
+
+void transpose_f64(Ctx* c, const double* in, long R, long C, double* out) {
+  dim3 grid((unsigned)((C + 31) / 32), (unsigned)((R + 31) / 32));
+  hipLaunchKernelGGL(transpose_kernel, grid, dim3(32, 8), 0, c->stream, in, R, C, out);
+  D3S_HIP(hipGetLastError());
+}
+
+void copy2d_f64(Ctx* c, const double* src, long lds, double* dst, long ldd, long rows, long cols) {
+  if (rows <= 0 || cols <= 0) return;
+  hipLaunchKernelGGL(copy2d_kernel, dim3(grid_for(rows * cols)), dim3(kThreads), 0, c->stream, src, lds,
+                     dst, ldd, rows, cols);
+  D3S_HIP(hipGetLastError());
+}
+
+void cast_f64_to_f32(Ctx* c, const double* x, float* y, long n) {
+  hipLaunchKernelGGL(cast_kernel<float>, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, x, y, n);
+  D3S_HIP(hipGetLastError());
+}
+
+void cast_f64_to_bf16(Ctx* c, const double* x, bf16_t* y, long n) {
+  hipLaunchKernelGGL(cast_kernel<bf16_t>, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, x, y, n);
+  D3S_HIP(hipGetLastError());
+}
+
+void cast_f32_to_f64(Ctx* c, const float* x, double* y, long n) {
+  hipLaunchKernelGGL(cast_f32_f64_kernel, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, x, y, n);
+  D3S_HIP(hipGetLastError());
+}
+
+void adjoint_reduce_f64(Ctx* c, const double* T1, const double* U, double* Wbar, int ml, int d, int mr,
+                        int wl, int wr) {
+  const int n1 = wl * d, n2 = d * wr;
+  double* part = (double*)ws_get(c, WS_MISC, sizeof(double) * (size_t)ml * n1 * n2);
+  // part[a] = T1[a] (n1 x mr) * U[a]^T (mr x n2), batched over a
+  GemmArgs g{n1, n2, mr, T1, mr, true, (long)n1 * mr, U, mr, true, (long)n2 * mr, part, n2,
+             (long)n1 * n2, 1.0, 0.0, ml};
+  gemm_f64(c, g);
+  const int tot = n1 * n2;
+  hipLaunchKernelGGL(adjoint_sum_kernel, dim3((tot + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                     c->stream, part, ml, d, wl, wr, Wbar);
+  D3S_HIP(hipGetLastError());
+}
+
+}  // namespace d3s

@@ -1,0 +1,471 @@
+// Host-side composition of the kernels into the operations of the site
+// update (Sec. 5): H_eff*psi, expansion, truncation, environment update,
+// the Lanczos eigensolver and the energy.  Everything here is stream-ordered
+// on the context's stream; host values are read back only where the
+// algorithm needs them (Ritz values, singular values, norms).
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+
+#include "d3s_internal.h"
+
+namespace d3s {
+
+// ---------------------------------------------------------------- workspace
+void* ws_get(Ctx* c, int slot, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  if (c->ws_cap[slot] >= bytes) return c->ws_ptr[slot];
+  size_t cap = std::max(bytes, c->ws_cap[slot] + c->ws_cap[slot] / 4);
+  cap = (cap + 255) & ~(size_t)255;
+  if (c->ws_ptr[slot]) {
+    if (c->has_alloc) c->alloc.free(c->ws_ptr[slot], c->stream, c->alloc.user);
+    else {
+      D3S_HIP(hipStreamSynchronize(c->stream));
+      D3S_HIP(hipFree(c->ws_ptr[slot]));
+    }
+    c->ws_ptr[slot] = nullptr;
+    c->ws_cap[slot] = 0;
+  }
+  void* p = nullptr;
+  if (c->has_alloc) {
+    p = c->alloc.alloc(cap, c->stream, c->alloc.user);
+  } else if (hipMalloc(&p, cap) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+  }
+  if (!p) throw Error{D3S_ENOMEM, "workspace allocation of " + std::to_string(cap) + " bytes failed"};
+  c->ws_ptr[slot] = p;
+  c->ws_cap[slot] = cap;
+  return p;
+}
+
+void ws_release_all(Ctx* c) {
+  for (int s = 0; s < WS_NSLOTS; ++s) {
+    if (!c->ws_ptr[s]) continue;
+    if (c->has_alloc) c->alloc.free(c->ws_ptr[s], c->stream, c->alloc.user);
+    else (void)hipFree(c->ws_ptr[s]);
+    c->ws_ptr[s] = nullptr;
+    c->ws_cap[s] = 0;
+  }
+}
+
+double read_scalar(Ctx* c, const double* dev) {
+  D3S_HIP(hipMemcpyAsync(c->host_red, dev, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  D3S_HIP(hipStreamSynchronize(c->stream));
+  return c->host_red[0];
+}
+
+static void read_many(Ctx* c, double* host, const double* dev, size_t n) {
+  D3S_HIP(hipMemcpyAsync(host, dev, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+  D3S_HIP(hipStreamSynchronize(c->stream));
+}
+
+static void write_many(Ctx* c, double* dev, const double* host, size_t n) {
+  D3S_HIP(hipMemcpyAsync(dev, host, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+  D3S_HIP(hipStreamSynchronize(c->stream));
+}
+
+// ---------------------------------------------------------------- H_eff psi
+// (((L psi) W) R), Sec. 5: GEMM over the left MPS bond, W-map, GEMM over (v, y).
+void op_apply_heff(Ctx* c, d3s_prec p, int ml, int d, int mr, int wl, int wr, const void* L,
+                   const void* W, const void* R, const void* psi, void* out) {
+  const size_t tsz = (p == D3S_F64) ? 8 : 4;       // T1 element size (fp32 for BF16 too)
+  const size_t t2sz = (p == D3S_F64) ? 8 : (p == D3S_F32 ? 4 : 2);
+  void* T1 = ws_get(c, WS_T1, tsz * (size_t)ml * wl * d * mr);
+  void* T2 = ws_get(c, WS_T2, t2sz * (size_t)ml * d * wr * mr);
+  hipEvent_t* ev = nullptr;
+  if (c->prof && c->prof_n < c->prof_cap) ev = &c->prof_ev[4 * (size_t)c->prof_n++];
+  if (ev) D3S_HIP(hipEventRecord(ev[0], c->stream));
+  GemmArgs g1{ml * wl, d * mr, ml, L, ml, true, 0, psi, (long)d * mr, false, 0, T1, (long)d * mr, 0,
+              1.0, 0.0, 1};
+  gemm(c, p, g1);
+  if (ev) D3S_HIP(hipEventRecord(ev[1], c->stream));
+  wmap_l2r(c, p, T1, W, T2, (long)wr * mr, ml, d, mr, wl, wr, 1.0);
+  if (ev) D3S_HIP(hipEventRecord(ev[2], c->stream));
+  GemmArgs g2{ml * d, mr, wr * mr, T2, (long)wr * mr, true, 0, R, (long)wr * mr, true, 0, out, mr, 0,
+              1.0, 0.0, 1};
+  gemm(c, p, g2);
+  if (ev) D3S_HIP(hipEventRecord(ev[3], c->stream));
+}
+
+// ---------------------------------------------------------------- expansion
+void op_expand(Ctx* c, d3s_dir dir, int ml, int d, int mr, int wl, int wr, const double* env,
+               const double* W, const double* psi, double alpha, double* Mt) {
+  if (dir == D3S_L2R) {
+    // Mt = [psi | alpha L psi W]  ((ml d) x (mr + wr mr))
+    const long ldm = (long)(1 + wr) * mr;
+    double* T1 = (double*)ws_get(c, WS_T1, sizeof(double) * (size_t)ml * wl * d * mr);
+    GemmArgs g1{ml * wl, d * mr, ml, env, ml, true, 0, psi, (long)d * mr, false, 0, T1, (long)d * mr, 0,
+                1.0, 0.0, 1};
+    gemm_f64(c, g1);
+    wmap_l2r(c, D3S_F64, T1, W, Mt + mr, ldm, ml, d, mr, wl, wr, alpha);
+    copy2d_f64(c, psi, mr, Mt, ldm, (long)ml * d, mr);
+  } else {
+    // Mt = [psi ; alpha W psi R]  ((ml + wl ml) x (d mr)); Y[(x,t),(b,v)] = psi R^T over y
+    double* Y = (double*)ws_get(c, WS_T1, sizeof(double) * (size_t)ml * d * mr * wr);
+    GemmArgs g1{ml * d, mr * wr, mr, psi, mr, true, 0, env, mr, true, 0, Y, (long)mr * wr, 0, 1.0, 0.0, 1};
+    gemm_f64(c, g1);
+    wmap_r2l(c, D3S_F64, Y, W, Mt + (long)ml * d * mr, ml, d, mr, wl, wr, alpha);
+    copy_f64(c, psi, Mt, (long)ml * d * mr);
+  }
+}
+
+// ---------------------------------------------------------------- environments
+void op_update_env(Ctx* c, d3s_dir dir, int ml, int d, int mr, int wl, int wr, const double* env_in,
+                   const double* W, const double* site, double* env_out) {
+  if (dir == D3S_L2R) {
+    double* T1 = (double*)ws_get(c, WS_T1, sizeof(double) * (size_t)ml * wl * d * mr);
+    double* T2 = (double*)ws_get(c, WS_T2, sizeof(double) * (size_t)ml * d * wr * mr);
+    GemmArgs g1{ml * wl, d * mr, ml, env_in, ml, true, 0, site, (long)d * mr, false, 0, T1, (long)d * mr, 0,
+                1.0, 0.0, 1};
+    gemm_f64(c, g1);
+    wmap_l2r(c, D3S_F64, T1, W, T2, (long)wr * mr, ml, d, mr, wl, wr, 1.0);
+    // env_out[b][(v,y)] = sum_{(a,s)} A[(a,s)][b] T2[(a,s)][(v,y)]
+    GemmArgs g2{mr, wr * mr, ml * d, site, mr, false, 0, T2, (long)wr * mr, false, 0, env_out,
+                (long)wr * mr, 0, 1.0, 0.0, 1};
+    gemm_f64(c, g2);
+  } else {
+    double* Y = (double*)ws_get(c, WS_T1, sizeof(double) * (size_t)ml * d * mr * wr);
+    double* Z = (double*)ws_get(c, WS_T2, sizeof(double) * (size_t)wl * ml * d * mr);
+    GemmArgs g1{ml * d, mr * wr, mr, site, mr, true, 0, env_in, mr, true, 0, Y, (long)mr * wr, 0, 1.0, 0.0, 1};
+    gemm_f64(c, g1);
+    wmap_r2l(c, D3S_F64, Y, W, Z, ml, d, mr, wl, wr, 1.0);
+    // env_out[a][(w,x)] = sum_{(s,b)} B[a][(s,b)] Z[(w,x)][(s,b)]
+    GemmArgs g2{ml, wl * ml, d * mr, site, (long)d * mr, true, 0, Z, (long)d * mr, true, 0, env_out,
+                (long)wl * ml, 0, 1.0, 0.0, 1};
+    gemm_f64(c, g2);
+  }
+}
+
+// ---------------------------------------------------------------- eigensolvers
+void syevd_f64(Ctx* c, int n, double* A, double* evals_dev) {
+  if (!c->solver) {
+    rocblas_handle h = nullptr;
+    if (rocblas_create_handle(&h) != rocblas_status_success)
+      throw Error{D3S_EDEVICE, "rocblas_create_handle failed"};
+    c->solver = h;
+  }
+  rocblas_handle h = (rocblas_handle)c->solver;
+  if (rocblas_set_stream(h, c->stream) != rocblas_status_success)
+    throw Error{D3S_EDEVICE, "rocblas_set_stream failed"};
+  double* E = (double*)ws_get(c, WS_EIGTMP, sizeof(double) * (size_t)n);
+  rocblas_int* info = (rocblas_int*)ws_get(c, WS_INFO, 64);
+  rocblas_status st = rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper, n, A, n,
+                                       evals_dev, E, info);
+  if (st != rocblas_status_success)
+    throw Error{D3S_EDEVICE, "rocsolver_dsyevd failed (status " + std::to_string((int)st) + ")"};
+  rocblas_int hinfo = 0;
+  D3S_HIP(hipMemcpyAsync(&hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, c->stream));
+  D3S_HIP(hipStreamSynchronize(c->stream));
+  if (hinfo != 0)
+    throw Error{D3S_EDEVICE, "rocsolver_dsyevd did not converge (info " + std::to_string(hinfo) + ")"};
+}
+
+// Cyclic Jacobi eigensolver for a small dense symmetric matrix (row-major A,
+// destroyed).  Eigenvalues ascending; evecs[j*n + i] = component i of vector j.
+void jacobi_eigh(int n, std::vector<double>& A, std::vector<double>& evals, std::vector<double>& evecs) {
+  std::vector<double> V((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, diag = 0.0;
+    for (int p = 0; p < n; ++p) {
+      diag += A[(size_t)p * n + p] * A[(size_t)p * n + p];
+      for (int q = p + 1; q < n; ++q) off += A[(size_t)p * n + q] * A[(size_t)p * n + q];
+    }
+    if (off <= 1e-34 * (diag + 1e-300)) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A[(size_t)p * n + q];
+        if (apq == 0.0) continue;
+        const double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
+        const double theta = (aqq - app) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+        for (int k = 0; k < n; ++k) {   // columns p, q
+          const double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
+          A[(size_t)k * n + p] = cs * akp - sn * akq;
+          A[(size_t)k * n + q] = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < n; ++k) {   // rows p, q
+          const double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
+          A[(size_t)p * n + k] = cs * apk - sn * aqk;
+          A[(size_t)q * n + k] = sn * apk + cs * aqk;
+        }
+        for (int k = 0; k < n; ++k) {   // eigenvector columns
+          const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+          V[(size_t)k * n + p] = cs * vkp - sn * vkq;
+          V[(size_t)k * n + q] = sn * vkp + cs * vkq;
+        }
+      }
+  }
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return A[(size_t)x * n + x] < A[(size_t)y * n + y]; });
+  evals.assign(n, 0.0);
+  evecs.assign((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    evals[j] = A[(size_t)order[j] * n + order[j]];
+    for (int i = 0; i < n; ++i) evecs[(size_t)j * n + i] = V[(size_t)i * n + order[j]];
+  }
+}
+
+// ---------------------------------------------------------------- truncation
+TruncResult op_truncate(Ctx* c, d3s_dir dir, int ml, int d, int mr, long width, const double* Mt,
+                        const double* psi, int kmax, double eps, const double* nbr, long nbr_other,
+                        double* site_out, double* nbr_out, double* s_host, bool renormalize) {
+  const int n = (dir == D3S_L2R) ? ml * d : d * mr;
+  double* G = (double*)ws_get(c, WS_GRAM, sizeof(double) * (size_t)n * n);
+  if (dir == D3S_L2R) {
+    GemmArgs g{n, n, (int)width, Mt, width, true, 0, Mt, width, true, 0, G, n, 0, 1.0, 0.0, 1};
+    gemm_f64(c, g);
+  } else {
+    GemmArgs g{n, n, (int)width, Mt, n, false, 0, Mt, n, false, 0, G, n, 0, 1.0, 0.0, 1};
+    gemm_f64(c, g);
+  }
+  double* ev = (double*)ws_get(c, WS_EIGVAL, sizeof(double) * (size_t)n);
+  syevd_f64(c, n, G, ev);
+  std::vector<double> lam(n);
+  read_many(c, lam.data(), ev, n);
+  std::vector<double> s2(n);
+  double total = 0.0;
+  for (int j = 0; j < n; ++j) {
+    s2[j] = std::max(lam[n - 1 - j], 0.0);
+    total += s2[j];
+  }
+  if (!(s2[0] > 0.0) || !std::isfinite(total))
+    throw Error{D3S_ENUMERIC, "truncate: the expanded tensor is zero or not finite"};
+  // The Gram route resolves s_j^2 only down to ~n u s_0^2; below that floor a
+  // singular value is indistinguishable from zero.
+  const double floor2 = std::max(eps * eps, (double)n * DBL_EPSILON) * s2[0];
+  int k = 0;
+  while (k < n && k < kmax && s2[k] > floor2) ++k;
+  double disc = 0.0;
+  for (int j = k; j < n; ++j) disc += s2[j];
+  if (s_host)
+    for (int j = 0; j < n; ++j) s_host[j] = std::sqrt(s2[j]);
+  // U_k^T (k x n): eigenvector n-1-j is column n-1-j of the column-major G
+  double* Ukt = (double*)ws_get(c, WS_UKT, sizeof(double) * (size_t)k * n);
+  copy2d_f64(c, G + (long)(n - 1) * n, -(long)n, Ukt, n, k, n);
+  if (dir == D3S_L2R) {
+    transpose_f64(c, Ukt, k, n, site_out);                      // A = U_k, (ml d) x k
+    double* X = (double*)ws_get(c, WS_X, sizeof(double) * (size_t)k * mr);
+    GemmArgs g1{k, mr, n, Ukt, n, true, 0, psi, mr, false, 0, X, mr, 0, 1.0, 0.0, 1};
+    gemm_f64(c, g1);                                            // X = U_k^T psi_mat
+    GemmArgs g2{k, (int)nbr_other, mr, X, mr, true, 0, nbr, nbr_other, false, 0, nbr_out, nbr_other, 0,
+                1.0, 0.0, 1};
+    gemm_f64(c, g2);                                            // B~ = X B
+  } else {
+    copy_f64(c, Ukt, site_out, (long)k * n);                    // B = V_k^T, k x (d mr)
+    double* X = (double*)ws_get(c, WS_X, sizeof(double) * (size_t)ml * k);
+    GemmArgs g1{ml, k, n, psi, n, true, 0, Ukt, n, true, 0, X, k, 0, 1.0, 0.0, 1};
+    gemm_f64(c, g1);                                            // X = psi_mat V_k
+    GemmArgs g2{(int)nbr_other, k, ml, nbr, ml, true, 0, X, k, false, 0, nbr_out, k, 0, 1.0, 0.0, 1};
+    gemm_f64(c, g2);                                            // A~ = A X
+  }
+  if (renormalize) {
+    const long nn = (long)k * nbr_other;
+    double* r = (double*)ws_get(c, WS_LZ_COEF, sizeof(double) * 512);
+    dot_f64(c, nbr_out, nbr_out, nn, r);
+    const double nrm2 = read_scalar(c, r);
+    if (!(nrm2 > 0.0) || !std::isfinite(nrm2))
+      throw Error{D3S_ENUMERIC, "truncate: neighbour norm is zero or not finite"};
+    scale_f64(c, nbr_out, nn, 1.0 / std::sqrt(nrm2));
+  }
+  return TruncResult{k, disc, total};
+}
+
+// ---------------------------------------------------------------- energy
+double op_energy(Ctx* c, int ml, int d, int mr, int wl, int wr, const double* L, const double* W,
+                 const double* R, const double* psi) {
+  const long n = (long)ml * d * mr;
+  double* hp = (double*)ws_get(c, WS_REF, sizeof(double) * n);
+  op_apply_heff(c, D3S_F64, ml, d, mr, wl, wr, L, W, R, psi, hp);
+  double* r = (double*)ws_get(c, WS_LZ_COEF, sizeof(double) * 512);
+  dot_f64(c, psi, hp, n, r);
+  dot_f64(c, psi, psi, n, r + 1);
+  double h[2];
+  read_many(c, h, r, 2);
+  if (!(h[1] > 0.0)) throw Error{D3S_ENUMERIC, "energy: zero state"};
+  const double e = h[0] / h[1];
+  if (!std::isfinite(e)) throw Error{D3S_ENUMERIC, "energy: not finite"};
+  return e;
+}
+
+// ---------------------------------------------------------------- adjoint
+void op_heff_grad_W(Ctx* c, int ml, int d, int mr, int wl, int wr, const double* L, const double* R,
+                    const double* psi, const double* ybar, double* Wbar) {
+  double* T1 = (double*)ws_get(c, WS_T1, sizeof(double) * (size_t)ml * wl * d * mr);
+  double* U = (double*)ws_get(c, WS_T2, sizeof(double) * (size_t)ml * d * wr * mr);
+  // T1[(a,w),(t,y)] = L psi (GEMM over the left MPS bond, as in H_eff)
+  GemmArgs g1{ml * wl, d * mr, ml, L, ml, true, 0, psi, (long)d * mr, false, 0, T1, (long)d * mr, 0,
+              1.0, 0.0, 1};
+  gemm_f64(c, g1);
+  // U[(a,s),(v,y)] = sum_b ybar[(a,s), b] R[b, (v,y)]
+  GemmArgs g2{ml * d, wr * mr, mr, ybar, mr, true, 0, R, (long)wr * mr, false, 0, U, (long)wr * mr, 0,
+              1.0, 0.0, 1};
+  gemm_f64(c, g2);
+  adjoint_reduce_f64(c, T1, U, Wbar, ml, d, mr, wl, wr);
+}
+
+// ---------------------------------------------------------------- Lanczos
+namespace {
+struct Matvec {
+  Ctx* c;
+  d3s_prec p;
+  int ml, d, mr, wl, wr;
+  const double *L, *W, *R;
+  const void *Lc = nullptr, *Wc = nullptr, *Rc = nullptr;   // low-precision copies
+  void* xin = nullptr;
+  float* yout = nullptr;
+  long n;
+  void prepare() {
+    if (p == D3S_F64) return;
+    const long nl = (long)ml * wl * ml, nr = (long)mr * wr * mr, nw = (long)wl * wr * d * d;
+    float* Wf = (float*)ws_get(c, WS_CAST_W, 4 * nw);
+    cast_f64_to_f32(c, W, Wf, nw);
+    Wc = Wf;
+    if (p == D3S_F32) {
+      float* Lf = (float*)ws_get(c, WS_CAST_L, 4 * nl);
+      float* Rf = (float*)ws_get(c, WS_CAST_R, 4 * nr);
+      cast_f64_to_f32(c, L, Lf, nl);
+      cast_f64_to_f32(c, R, Rf, nr);
+      Lc = Lf;
+      Rc = Rf;
+      xin = ws_get(c, WS_CAST_X, 4 * n);
+    } else {
+      bf16_t* Lb = (bf16_t*)ws_get(c, WS_CAST_L, 2 * nl);
+      bf16_t* Rb = (bf16_t*)ws_get(c, WS_CAST_R, 2 * nr);
+      cast_f64_to_bf16(c, L, Lb, nl);
+      cast_f64_to_bf16(c, R, Rb, nr);
+      Lc = Lb;
+      Rc = Rb;
+      xin = ws_get(c, WS_CAST_X, 2 * n);
+    }
+    yout = (float*)ws_get(c, WS_CAST_Y, 4 * n);
+  }
+  // low-precision (or FP64) product
+  void apply(const double* x, double* y) {
+    if (p == D3S_F64) {
+      op_apply_heff(c, D3S_F64, ml, d, mr, wl, wr, L, W, R, x, y);
+      return;
+    }
+    if (p == D3S_F32) cast_f64_to_f32(c, x, (float*)xin, n);
+    else cast_f64_to_bf16(c, x, (bf16_t*)xin, n);
+    op_apply_heff(c, p, ml, d, mr, wl, wr, Lc, Wc, Rc, xin, yout);
+    cast_f32_to_f64(c, yout, y, n);
+  }
+  void apply_f64(const double* x, double* y) {
+    op_apply_heff(c, D3S_F64, ml, d, mr, wl, wr, L, W, R, x, y);
+  }
+};
+
+// One Lanczos run (with restarts) on the operator `mv`, starting from x
+// (normalised in place, overwritten by the Ritz vector).
+LanczosResult lanczos_core(Ctx* c, Matvec& mv, double* x, long n, double tol, int kmax, int max_mv,
+                           bool use_f64) {
+  const int kk = (int)std::min<long>(kmax, n);
+  double* V = (double*)ws_get(c, WS_LZ_V, sizeof(double) * (size_t)(kk + 1) * n);
+  double* w = (double*)ws_get(c, WS_LZ_W, sizeof(double) * n);
+  double* cf = (double*)ws_get(c, WS_LZ_COEF, sizeof(double) * 512);
+  double* cf1 = cf;          // first Gram-Schmidt coefficients
+  double* cf2 = cf + 128;    // second pass
+  double* sc = cf + 256;     // scalars
+  double* ydev = cf + 384;   // Ritz coefficients
+  LanczosResult res{0.0, 0, false, 0};
+  // normalise the start vector
+  dot_f64(c, x, x, n, sc);
+  double nrm2 = read_scalar(c, sc);
+  if (!(nrm2 > 0.0) || !std::isfinite(nrm2)) {
+    fill_f64(c, x, n, 1.0);
+    nrm2 = (double)n;
+  }
+  scale_f64(c, x, n, 1.0 / std::sqrt(nrm2));
+  copy_f64(c, x, V, n);
+  std::vector<double> alphas, betas, T, ev, evec;
+  double h[4];
+  for (;;) {
+    alphas.clear();
+    betas.clear();
+    int k = 0;
+    bool stop = false;
+    std::vector<double> y;
+    for (k = 0; k < kk; ++k) {
+      double* vk = V + (long)k * n;
+      if (use_f64) mv.apply_f64(vk, w);
+      else mv.apply(vk, w);
+      res.matvecs++;
+      mdot_f64(c, V, n, k + 1, w, n, cf1);
+      maxpy_f64(c, V, n, k + 1, cf1, -1.0, w, n);
+      mdot_f64(c, V, n, k + 1, w, n, cf2);
+      maxpy_f64(c, V, n, k + 1, cf2, -1.0, w, n);
+      dot_f64(c, w, w, n, sc + 1);
+      D3S_HIP(hipMemcpyAsync(h, cf1 + k, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      D3S_HIP(hipMemcpyAsync(h + 1, cf2 + k, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      D3S_HIP(hipMemcpyAsync(h + 2, sc + 1, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      D3S_HIP(hipStreamSynchronize(c->stream));
+      const double a = h[0] + h[1];
+      const double b = std::sqrt(std::max(h[2], 0.0));
+      if (!std::isfinite(a) || !std::isfinite(b)) throw Error{D3S_ENUMERIC, "lanczos: non-finite value"};
+      alphas.push_back(a);
+      const int m = k + 1;
+      T.assign((size_t)m * m, 0.0);
+      for (int i = 0; i < m; ++i) T[(size_t)i * m + i] = alphas[i];
+      for (int i = 0; i + 1 < m; ++i) T[(size_t)i * m + i + 1] = T[(size_t)(i + 1) * m + i] = betas[i];
+      jacobi_eigh(m, T, ev, evec);
+      res.theta = ev[0];
+      y.assign(evec.begin(), evec.begin() + m);
+      const double scale = std::max(1.0, std::fabs(res.theta));
+      const double resid = std::fabs(b * y[m - 1]);
+      if (resid <= tol * scale || b <= 1e-15 * scale || m == n) {
+        res.converged = true;
+        stop = true;
+        break;
+      }
+      if (res.matvecs >= max_mv) {
+        stop = true;
+        break;
+      }
+      betas.push_back(b);
+      if (k + 1 < kk) axpby_f64(c, 1.0 / b, w, 0.0, V + (long)(k + 1) * n, n);
+    }
+    const int m = (int)y.size();
+    // Ritz vector x = sum_j y_j V_j
+    write_many(c, ydev, y.data(), m);
+    fill_f64(c, x, n, 0.0);
+    maxpy_f64(c, V, n, m, ydev, 1.0, x, n);
+    dot_f64(c, x, x, n, sc);
+    const double xn = read_scalar(c, sc);
+    scale_f64(c, x, n, 1.0 / std::sqrt(xn));
+    if (stop) break;
+    res.restarts++;
+    copy_f64(c, x, V, n);
+  }
+  return res;
+}
+}  // namespace
+
+LanczosResult op_lanczos(Ctx* c, d3s_prec p, int ml, int d, int mr, int wl, int wr, const double* L,
+                         const double* W, const double* R, double* psi, double tol, int kmax,
+                         int max_matvecs) {
+  const long n = (long)ml * d * mr;
+  Matvec mv{c, p, ml, d, mr, wl, wr, L, W, R};
+  mv.n = n;
+  mv.prepare();
+  if (p == D3S_F64) return lanczos_core(c, mv, psi, n, tol, kmax, max_matvecs, true);
+  // Mixed precision: converge on the low-precision operator to its own
+  // accuracy, then refine with FP64 products: Lanczos on the exact operator
+  // warm-started from that Ritz vector needs only a few FP64 products because
+  // the start vector is already close to the eigenvector.
+  const double low_tol = (p == D3S_F32) ? 1e-5 : 3e-3;
+  LanczosResult r1 = lanczos_core(c, mv, psi, n, low_tol, kmax, max_matvecs, false);
+  LanczosResult r2 = lanczos_core(c, mv, psi, n, tol, kmax, std::max(1, max_matvecs - r1.matvecs), true);
+  r2.matvecs += r1.matvecs;
+  r2.restarts += r1.restarts;
+  return r2;
+}
+
+}  // namespace d3s

@@ -1,0 +1,210 @@
+// Sweep driver (Sec. 5, steps 1-8; alpha rule of Sec. 6), host C++.
+//
+// Readings of points the paper leaves open (the same readings the test
+// oracle uses, kept here as constants):
+//  - eigensolver: Lanczos with full re-orthogonalisation, warm start from
+//    the current site tensor;
+//  - truncation target of bond b: min(mmax, d^b, d^(l-b)); singular values
+//    s_j <= eps s_0 are dropped;
+//  - the neighbour is renormalised after absorbing S V^T, so E_f is a
+//    Rayleigh quotient, and E_f becomes E_before of the next site update;
+//  - alpha: no change when the truncation discarded no weight (the
+//    enrichment had no effect), otherwise shrink by 0.8 when |dE_O| <
+//    1e-13 |E|, grow by 1.25 when dE_T < 0.3 |dE_O|, else shrink by 0.8;
+//    clamped to [1e-16, 1];
+//  - a sweep is right-to-left over sites l-1..1 followed by left-to-right
+//    over sites 0..l-2.
+#include <chrono>
+#include <cmath>
+
+#include "d3s_internal.h"
+
+namespace d3s {
+namespace {
+
+constexpr double kAlphaTarget = 0.3;
+constexpr double kAlphaGrow = 1.25;
+constexpr double kAlphaShrink = 0.8;
+constexpr double kAlphaStall = 1e-13;
+constexpr double kAlphaNoCut = 1e-12;
+constexpr double kAlphaMin = 1e-16;
+constexpr double kAlphaMax = 1.0;
+
+long bond_budget(int l, int d, int mmax, int b) {
+  long cap = mmax;
+  long left = 1, right = 1;
+  for (int i = 0; i < b && left < cap; ++i) left *= d;
+  for (int i = 0; i < l - b && right < cap; ++i) right *= d;
+  return std::min(cap, std::min(left, right));
+}
+
+double now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+void update_alpha(d3s_sweep_params* p, double lam, double ef, double disc, double total) {
+  if (!p->adaptive_alpha) return;
+  const double dEO = lam - p->e_before;
+  const double dET = ef - lam;
+  if (disc <= kAlphaNoCut * total) {
+    // the expansion did not change the state: no information on alpha
+  } else if (std::fabs(dEO) < kAlphaStall * std::fabs(lam)) {
+    p->alpha *= kAlphaShrink;
+  } else if (dET < kAlphaTarget * std::fabs(dEO)) {
+    p->alpha *= kAlphaGrow;
+  } else {
+    p->alpha *= kAlphaShrink;
+  }
+  p->alpha = std::min(kAlphaMax, std::max(kAlphaMin, p->alpha));
+}
+
+int wmax_of(const d3s_state* s) {
+  int w = 1;
+  for (int i = 0; i <= s->l; ++i) w = std::max(w, s->w[i]);
+  return w;
+}
+
+}  // namespace
+
+double op_prepare(Ctx* c, d3s_state* s, double eps) {
+  const int l = s->l, d = s->d;
+  for (int b = 0; b <= l; ++b) {
+    const long bb = bond_budget(l, d, s->mmax, b);
+    if (s->m[b] > bb) throw Error{D3S_EINVAL, "prepare: bond " + std::to_string(b) + " exceeds its budget"};
+  }
+  const size_t cap = (size_t)s->mmax * d * s->mmax;
+  double* tmpS = (double*)ws_get(c, WS_PSI, sizeof(double) * cap);
+  double* tmpN = (double*)ws_get(c, WS_NBR, sizeof(double) * cap);
+  for (int i = 0; i + 1 < l; ++i) {
+    const int ml = s->m[i], mr = s->m[i + 1];
+    const long other = (long)d * s->m[i + 2];
+    TruncResult t = op_truncate(c, D3S_L2R, ml, d, mr, mr, s->site[i], s->site[i], (int)bond_budget(l, d, s->mmax, i + 1),
+                                eps, s->site[i + 1], other, tmpS, tmpN, nullptr, false);
+    copy_f64(c, tmpS, s->site[i], (long)ml * d * t.k);
+    copy_f64(c, tmpN, s->site[i + 1], (long)t.k * other);
+    s->m[i + 1] = t.k;
+  }
+  // normalise the last site
+  {
+    const long n = (long)s->m[l - 1] * d * s->m[l];
+    double* r = (double*)ws_get(c, WS_LZ_COEF, sizeof(double) * 512);
+    dot_f64(c, s->site[l - 1], s->site[l - 1], n, r);
+    const double nrm2 = read_scalar(c, r);
+    if (!(nrm2 > 0.0) || !std::isfinite(nrm2)) throw Error{D3S_ENUMERIC, "prepare: zero state"};
+    scale_f64(c, s->site[l - 1], n, 1.0 / std::sqrt(nrm2));
+  }
+  fill_f64(c, s->lenv[0], 1, 1.0);
+  fill_f64(c, s->renv[l - 1], 1, 1.0);
+  for (int i = 0; i + 1 < l; ++i)
+    op_update_env(c, D3S_L2R, s->m[i], d, s->m[i + 1], s->w[i], s->w[i + 1], s->lenv[i], s->mpo[i],
+                  s->site[i], s->lenv[i + 1]);
+  s->center = l - 1;
+  return op_energy(c, s->m[l - 1], d, s->m[l], s->w[l - 1], s->w[l], s->lenv[l - 1], s->mpo[l - 1],
+                   s->renv[l - 1], s->site[l - 1]);
+}
+
+void op_sweep(Ctx* c, d3s_state* s, d3s_sweep_params* p, d3s_sweep_stats* st) {
+  const int l = s->l, d = s->d;
+  if (s->center != l - 1) throw Error{D3S_EINVAL, "sweep: the orthogonality centre must be on site l-1"};
+  const int wmax = wmax_of(s);
+  const size_t cap = (size_t)s->mmax * d * s->mmax;
+  double* tmpS = (double*)ws_get(c, WS_PSI, sizeof(double) * cap);
+  double* tmpN = (double*)ws_get(c, WS_NBR, sizeof(double) * cap);
+  double* Mt = (double*)ws_get(c, WS_MT, sizeof(double) * (size_t)(1 + wmax) * cap);
+  const double t_start = now();
+  st->count = 0;
+  st->nonconverged = 0;
+  auto record = [&](const d3s_site_record& r) {
+    if (st->count < st->capacity) st->records[st->count] = r;
+    st->count++;
+  };
+  double lam = p->e_before;
+  // right to left
+  for (int i = l - 1; i >= 1; --i) {
+    d3s_site_record r{};
+    r.site = i;
+    r.dir = D3S_R2L;
+    r.e_before = p->e_before;
+    const int ml = s->m[i], mr = s->m[i + 1], wl = s->w[i], wr = s->w[i + 1];
+    double t0 = now();
+    LanczosResult lz = op_lanczos(c, p->prec, ml, d, mr, wl, wr, s->lenv[i], s->mpo[i], s->renv[i], s->site[i],
+                                  p->lanczos_tol, p->lanczos_kmax, p->lanczos_max_matvecs);
+    lam = lz.theta;
+    if (!lz.converged) st->nonconverged++;
+    double t1 = now();
+    op_expand(c, D3S_R2L, ml, d, mr, wl, wr, s->renv[i], s->mpo[i], s->site[i], p->alpha, Mt);
+    D3S_HIP(hipStreamSynchronize(c->stream));
+    double t2 = now();
+    const int mll = s->m[i - 1];
+    TruncResult t = op_truncate(c, D3S_R2L, ml, d, mr, (long)(1 + wl) * ml, Mt, s->site[i],
+                                (int)bond_budget(l, d, s->mmax, i), p->eps, s->site[i - 1], (long)mll * d,
+                                tmpS, tmpN, nullptr, true);
+    copy_f64(c, tmpS, s->site[i], (long)t.k * d * mr);
+    copy_f64(c, tmpN, s->site[i - 1], (long)mll * d * t.k);
+    s->m[i] = t.k;
+    double t3 = now();
+    op_update_env(c, D3S_R2L, t.k, d, mr, wl, wr, s->renv[i], s->mpo[i], s->site[i], s->renv[i - 1]);
+    D3S_HIP(hipStreamSynchronize(c->stream));
+    double t4 = now();
+    const double ef = op_energy(c, mll, d, t.k, s->w[i - 1], wl, s->lenv[i - 1], s->mpo[i - 1], s->renv[i - 1],
+                                s->site[i - 1]);
+    double t5 = now();
+    r.k = t.k;
+    r.matvecs = lz.matvecs;
+    r.lambda = lam;
+    r.e_f = ef;
+    r.alpha = p->alpha;
+    r.discarded = t.discarded;
+    r.t_eig = t1 - t0; r.t_expand = t2 - t1; r.t_trunc = t3 - t2; r.t_env = t4 - t3; r.t_energy = t5 - t4;
+    record(r);
+    update_alpha(p, lam, ef, t.discarded, t.total);
+    p->e_before = ef;
+    s->center = i - 1;
+  }
+  // left to right
+  for (int i = 0; i + 1 < l; ++i) {
+    d3s_site_record r{};
+    r.site = i;
+    r.dir = D3S_L2R;
+    r.e_before = p->e_before;
+    const int ml = s->m[i], mr = s->m[i + 1], wl = s->w[i], wr = s->w[i + 1];
+    double t0 = now();
+    LanczosResult lz = op_lanczos(c, p->prec, ml, d, mr, wl, wr, s->lenv[i], s->mpo[i], s->renv[i], s->site[i],
+                                  p->lanczos_tol, p->lanczos_kmax, p->lanczos_max_matvecs);
+    lam = lz.theta;
+    if (!lz.converged) st->nonconverged++;
+    double t1 = now();
+    op_expand(c, D3S_L2R, ml, d, mr, wl, wr, s->lenv[i], s->mpo[i], s->site[i], p->alpha, Mt);
+    D3S_HIP(hipStreamSynchronize(c->stream));
+    double t2 = now();
+    const int mrr = s->m[i + 2];
+    TruncResult t = op_truncate(c, D3S_L2R, ml, d, mr, (long)(1 + wr) * mr, Mt, s->site[i],
+                                (int)bond_budget(l, d, s->mmax, i + 1), p->eps, s->site[i + 1], (long)d * mrr,
+                                tmpS, tmpN, nullptr, true);
+    copy_f64(c, tmpS, s->site[i], (long)ml * d * t.k);
+    copy_f64(c, tmpN, s->site[i + 1], (long)t.k * d * mrr);
+    s->m[i + 1] = t.k;
+    double t3 = now();
+    op_update_env(c, D3S_L2R, ml, d, t.k, wl, wr, s->lenv[i], s->mpo[i], s->site[i], s->lenv[i + 1]);
+    D3S_HIP(hipStreamSynchronize(c->stream));
+    double t4 = now();
+    const double ef = op_energy(c, t.k, d, mrr, wr, s->w[i + 2], s->lenv[i + 1], s->mpo[i + 1], s->renv[i + 1],
+                                s->site[i + 1]);
+    double t5 = now();
+    r.k = t.k;
+    r.matvecs = lz.matvecs;
+    r.lambda = lam;
+    r.e_f = ef;
+    r.alpha = p->alpha;
+    r.discarded = t.discarded;
+    r.t_eig = t1 - t0; r.t_expand = t2 - t1; r.t_trunc = t3 - t2; r.t_env = t4 - t3; r.t_energy = t5 - t4;
+    record(r);
+    update_alpha(p, lam, ef, t.discarded, t.total);
+    p->e_before = ef;
+    s->center = i + 1;
+  }
+  st->energy = lam;
+  st->seconds = now() - t_start;
+}
+
+}  // namespace d3s

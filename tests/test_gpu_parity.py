@@ -1,0 +1,305 @@
+"""GPU parity: every C-ABI call against the CPU FP64 oracle on the same
+seeded inputs.  Tolerances:
+  FP64: max |gpu - oracle| <= 1e-12 * max |oracle| (sums of <= 10^5 products
+        with unit-scale Gaussian entries round to ~1e-15 relative each);
+  FP32: 3e-5 relative (K <= 2e4 terms at 6e-8 unit roundoff, random signs);
+  BF16: 2e-2 relative (operands and the intermediate T2 rounded to 8 bits).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import contract as C
+from oracle import ed, mpo as MPO
+from oracle.adjoint import heff_grad_W
+from oracle.dmrg3s import DMRG3S
+from paper_1501_05504_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+abi = pytest.importorskip("paper_1501_05504_amd.abi")
+
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = abi.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a, dtype=torch.float64):
+    return torch.tensor(np.asarray(a), dtype=torch.float64, device=DEV).to(dtype).contiguous()
+
+
+def rel_err(got, ref):
+    return float(np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+SHAPES = [  # (ml, d, mr, wl, wr): tiny, boundary w=1, ragged tails, several tiles
+    (1, 2, 1, 1, 5),
+    (2, 2, 4, 5, 5),
+    (16, 2, 16, 5, 5),
+    (37, 4, 53, 6, 6),
+    (130, 4, 70, 6, 1),
+    (70, 4, 130, 1, 6),
+    (200, 4, 257, 6, 6),
+    (64, 2, 64, 8, 8),
+    (96, 4, 96, 18, 18),
+    (300, 4, 300, 6, 6),
+]
+
+
+def _inputs(ml, d, mr, wl, wr, seed=0):
+    L = synth.gaussian((ml, wl, ml), 100 + seed)
+    W = synth.gaussian((wl, wr, d, d), 200 + seed)
+    R = synth.gaussian((mr, wr, mr), 300 + seed)
+    psi = synth.gaussian((ml, d, mr), 400 + seed)
+    return L, W, R, psi
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=[str(s) for s in SHAPES])
+def test_apply_heff_f64(ctx, shape):
+    ml, d, mr, wl, wr = shape
+    L, W, R, psi = _inputs(*shape)
+    ref = C.apply_heff(L, W, R, psi)
+    out = torch.full((ml, d, mr), float("nan"), dtype=torch.float64, device=DEV)
+    ctx.apply_heff(dev(L), dev(W), dev(R), dev(psi), out)
+    torch.cuda.synchronize()
+    assert rel_err(out.cpu().numpy(), ref) < 1e-12
+
+
+@pytest.mark.parametrize("cfg", [0, 1])
+def test_apply_heff_both_tile_configs(ctx, cfg):
+    ml, d, mr, wl, wr = 150, 4, 133, 6, 6
+    L, W, R, psi = _inputs(ml, d, mr, wl, wr, seed=7)
+    ref = C.apply_heff(L, W, R, psi)
+    out = torch.empty((ml, d, mr), dtype=torch.float64, device=DEV)
+    ctx.set_tile_config(cfg)
+    try:
+        ctx.apply_heff(dev(L), dev(W), dev(R), dev(psi), out)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_tile_config(-1)
+    assert rel_err(out.cpu().numpy(), ref) < 1e-12
+
+
+@pytest.mark.parametrize("shape", SHAPES[2:], ids=[str(s) for s in SHAPES[2:]])
+def test_apply_heff_f32(ctx, shape):
+    ml, d, mr, wl, wr = shape
+    L, W, R, psi = [np.asarray(x, dtype=np.float32).astype(np.float64) for x in _inputs(*shape)]
+    ref = C.apply_heff(L, W, R, psi)
+    out = torch.empty((ml, d, mr), dtype=torch.float32, device=DEV)
+    f = torch.float32
+    ctx.apply_heff(dev(L, f), dev(W, f), dev(R, f), dev(psi, f), out)
+    torch.cuda.synchronize()
+    assert rel_err(out.double().cpu().numpy(), ref) < 3e-5
+
+
+@pytest.mark.parametrize("shape", SHAPES[2:], ids=[str(s) for s in SHAPES[2:]])
+def test_apply_heff_bf16(ctx, shape):
+    ml, d, mr, wl, wr = shape
+    L, W, R, psi = _inputs(*shape)
+    b = torch.bfloat16
+    Lb, Rb, pb = dev(L, b), dev(R, b), dev(psi, b)
+    Wf = dev(W, torch.float32)
+    # oracle on the rounded operands
+    ref = C.apply_heff(Lb.double().cpu().numpy(), Wf.double().cpu().numpy(), Rb.double().cpu().numpy(),
+                       pb.double().cpu().numpy())
+    out = torch.empty((ml, d, mr), dtype=torch.float32, device=DEV)
+    ctx.apply_heff(Lb, Wf, Rb, pb, out)
+    torch.cuda.synchronize()
+    assert rel_err(out.double().cpu().numpy(), ref) < 2e-2
+
+
+def test_apply_heff_rejects_bad_arguments(ctx):
+    L, W, R, psi = _inputs(4, 2, 4, 5, 5)
+    x = dev(psi)
+    with pytest.raises(abi.D3SError) as e:
+        ctx.apply_heff(dev(L), dev(W), dev(R), x, x)
+    assert e.value.status == abi.EINVAL
+    assert "alias" in str(e.value)
+
+
+@pytest.mark.parametrize("shape", [(3, 2, 5, 5, 5), (37, 4, 53, 6, 6), (130, 4, 70, 6, 6)])
+def test_expand_subspace(ctx, shape):
+    ml, d, mr, wl, wr = shape
+    L, W, R, psi = _inputs(*shape, seed=3)
+    alpha = 0.37
+    Mt = torch.empty((ml * d, (1 + wr) * mr), dtype=torch.float64, device=DEV)
+    ctx.expand_subspace(abi.L2R, dev(L), dev(W), dev(psi), alpha, Mt)
+    ref = C.expanded_tensor_l2r(psi, C.expansion_term_l2r(L, W, psi, alpha))
+    torch.cuda.synchronize()
+    assert rel_err(Mt.cpu().numpy(), ref) < 1e-12
+    Mt2 = torch.empty(((1 + wl) * ml, d * mr), dtype=torch.float64, device=DEV)
+    ctx.expand_subspace(abi.R2L, dev(R), dev(W), dev(psi), alpha, Mt2)
+    ref2 = C.expanded_tensor_r2l(psi, C.expansion_term_r2l(R, W, psi, alpha))
+    torch.cuda.synchronize()
+    assert rel_err(Mt2.cpu().numpy(), ref2) < 1e-12
+
+
+@pytest.mark.parametrize("shape", [(3, 2, 5, 5, 5), (37, 4, 53, 6, 6), (130, 4, 70, 6, 6)])
+def test_update_env(ctx, shape):
+    ml, d, mr, wl, wr = shape
+    L, W, R, psi = _inputs(*shape, seed=5)
+    out = torch.empty((mr, wr, mr), dtype=torch.float64, device=DEV)
+    ctx.update_env(abi.L2R, dev(L), dev(W), dev(psi), out)
+    torch.cuda.synchronize()
+    assert rel_err(out.cpu().numpy(), C.update_left(L, W, psi)) < 1e-12
+    out2 = torch.empty((ml, wl, ml), dtype=torch.float64, device=DEV)
+    ctx.update_env(abi.R2L, dev(R), dev(W), dev(psi), out2)
+    torch.cuda.synchronize()
+    assert rel_err(out2.cpu().numpy(), C.update_right(R, W, psi)) < 1e-12
+
+
+def _mixed(tensors, mpo, center):
+    from tests.test_oracle_pins import _mixed_canonical, _envs
+    M = _mixed_canonical(tensors, center)
+    Lenv, Renv = _envs(mpo, M, center)
+    return M, Lenv, Renv
+
+
+@pytest.mark.parametrize("direction", ["l2r", "r2l"])
+@pytest.mark.parametrize("kmax", [3, 64])
+def test_truncate(ctx, direction, kmax):
+    """Singular values equal LAPACK's; the kept projector and the contracted
+    two-site block are gauge invariant and must match the oracle.  The Gram
+    route cannot resolve s_j below ~1e-7 s_0, so the GPU may keep fewer
+    (numerically null) states than LAPACK; the oracle is then re-run with the
+    GPU's k, which must only have dropped such states."""
+    l, center = 8, 4
+    mpo = MPO.heisenberg_mpo(l)
+    M, Lenv, Renv = _mixed(synth.random_mps(l, 2, 16, seed=31), mpo, center)
+    psi = M[center]
+    ml, d, mr = psi.shape
+    alpha = 0.2
+    if direction == "l2r":
+        Mt = C.expanded_tensor_l2r(psi, C.expansion_term_l2r(Lenv, mpo[center], psi, alpha))
+        nbr = M[center + 1]
+        n = ml * d
+        site = torch.empty(n * min(kmax, n), dtype=torch.float64, device=DEV)
+        nout = torch.empty(n * nbr.shape[1] * nbr.shape[2], dtype=torch.float64, device=DEV)
+        kk, dd, sv = ctx.truncate(abi.L2R, dev(Mt), dev(psi), kmax, 1e-14, dev(nbr), site, nout,
+                                  renormalize=False)
+        _, _, s, _ = C.truncate_l2r(Mt, psi, nbr, kmax, 1e-14)
+        A, B, _, disc = C.truncate_l2r(Mt, psi, nbr, kk, 1e-14)
+        Ag = site[: n * kk].cpu().numpy().reshape(n, kk)
+        Bg = nout[: kk * nbr.shape[1] * nbr.shape[2]].cpu().numpy().reshape(kk, -1)
+        Ao = A.reshape(n, kk)
+        assert np.abs(Ag @ Ag.T - Ao @ Ao.T).max() < 1e-10
+        two, ref_two = Ag @ Bg, Ao @ B.reshape(kk, -1)
+    else:
+        Mt = C.expanded_tensor_r2l(psi, C.expansion_term_r2l(Renv, mpo[center], psi, alpha))
+        nbr = M[center - 1]
+        n = d * mr
+        site = torch.empty(n * min(kmax, n), dtype=torch.float64, device=DEV)
+        nout = torch.empty(nbr.shape[0] * nbr.shape[1] * n, dtype=torch.float64, device=DEV)
+        kk, dd, sv = ctx.truncate(abi.R2L, dev(Mt), dev(psi), kmax, 1e-14, dev(nbr), site, nout,
+                                  renormalize=False)
+        _, _, s, _ = C.truncate_r2l(Mt, psi, nbr, kmax, 1e-14)
+        Bs, A, _, disc = C.truncate_r2l(Mt, psi, nbr, kk, 1e-14)
+        Bg = site[: kk * n].cpu().numpy().reshape(kk, n)
+        Ag = nout[: nbr.shape[0] * nbr.shape[1] * kk].cpu().numpy().reshape(-1, kk)
+        Bo = Bs.reshape(kk, n)
+        assert np.abs(Bg.T @ Bg - Bo.T @ Bo).max() < 1e-10
+        two, ref_two = Ag @ Bg, A.reshape(-1, kk) @ Bo
+    k_lapack = C.truncation_size(s, kmax, 1e-14)
+    assert kk <= k_lapack
+    assert kk == k_lapack or s[kk] < 1e-6 * s[0]
+    m = min(len(sv), len(s))
+    assert np.allclose(sv[:m], s[:m], atol=1e-7 * s[0])
+    assert abs(dd - disc) < 1e-10
+    assert rel_err(two, ref_two) < 1e-9
+
+
+def test_lanczos_matches_oracle_eigenvalue(ctx):
+    l, center = 10, 5
+    mpo = MPO.heisenberg_mpo(l)
+    M, Lenv, Renv = _mixed(synth.random_mps(l, 2, 16, seed=41), mpo, center)
+    H = C.heff_matrix(Lenv, mpo[center], Renv)
+    e0 = np.linalg.eigvalsh(H)[0]
+    x = dev(M[center])
+    th, nmv, ok = ctx.lanczos(dev(Lenv), dev(mpo[center]), dev(Renv), x, tol=1e-12, kmax=40)
+    assert ok
+    assert abs(th - e0) < 1e-11
+    xv = x.cpu().numpy().ravel()
+    assert np.linalg.norm(H @ xv - th * xv) < 1e-9
+    assert abs(ctx.energy(dev(Lenv), dev(mpo[center]), dev(Renv), x) - e0) < 1e-11
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_lanczos_mixed_precision_refines_to_f64(ctx, prec):
+    """Products in FP32 / BF16, FP64 refinement: the Ritz value matches the
+    FP64 eigenvalue to 1e-10."""
+    l, center = 10, 5
+    mpo = MPO.heisenberg_mpo(l)
+    M, Lenv, Renv = _mixed(synth.random_mps(l, 2, 32, seed=43), mpo, center)
+    H = C.heff_matrix(Lenv, mpo[center], Renv)
+    e0 = np.linalg.eigvalsh(H)[0]
+    x = dev(M[center])
+    p = abi.F32 if prec == "f32" else abi.BF16
+    th, nmv, ok = ctx.lanczos(dev(Lenv), dev(mpo[center]), dev(Renv), x, tol=1e-12, kmax=40, prec=p)
+    assert ok
+    assert abs(th - e0) < 1e-10
+
+
+def test_heff_grad_W(ctx):
+    ml, d, mr, wl, wr = 37, 4, 53, 6, 6
+    L, W, R, psi = _inputs(ml, d, mr, wl, wr, seed=9)
+    ybar = synth.gaussian((ml, d, mr), 999)
+    ref = heff_grad_W(L, R, psi, ybar)
+    out = torch.empty((wl, wr, d, d), dtype=torch.float64, device=DEV)
+    ctx.heff_grad_W(dev(L), dev(R), dev(psi), dev(ybar), out)
+    torch.cuda.synchronize()
+    assert rel_err(out.cpu().numpy(), ref) < 1e-12
+
+
+def test_sweep_heisenberg12_exact_bond(ctx):
+    """BASELINE configuration 1 with m = 64 (exact): the GPU DMRG3S energy
+    equals ED to 1e-10."""
+    l, m = 12, 64
+    e_ed = ed.ground_energy(ed.spin_chain_hamiltonian(l, {(i, i + 1): 1.0 for i in range(l - 1)}))
+    st = abi.State(abi.heisenberg_mpo(l), synth.random_mps(l, 2, m), m, device=DEV)
+    e0 = ctx.prepare(st)
+    params = abi.sweep_params(alpha=1e-3, e_before=e0)
+    prev = None
+    for s in range(12):
+        _, stats, recs = ctx.sweep(st, params)
+        for r in recs:
+            assert r.lam >= e_ed - 1e-10 and r.e_f >= e_ed - 1e-10
+        if prev is not None and abs(stats.energy - prev) / abs(stats.energy) < 1e-12:
+            break
+        prev = stats.energy
+    assert abs(stats.energy - e_ed) < 1e-10
+
+
+def test_sweep_heisenberg12_m16_matches_oracle(ctx):
+    """BASELINE configuration 1 (m = 16): GPU and oracle DMRG3S from the same
+    seeded state converge to the same energy (plain FP64 path: 1e-10)."""
+    l, m = 12, 16
+    tensors = synth.random_mps(l, 2, m)
+    st = abi.State(abi.heisenberg_mpo(l), tensors, m, device=DEV)
+    e0 = ctx.prepare(st)
+    params = abi.sweep_params(alpha=1e-3, e_before=e0)
+    prev = None
+    for s in range(30):
+        _, stats, _ = ctx.sweep(st, params)
+        if prev is not None and abs(stats.energy - prev) / abs(stats.energy) < 1e-12:
+            break
+        prev = stats.energy
+    run = DMRG3S(MPO.heisenberg_mpo(l), tensors, mmax=m, alpha0=1e-3)
+    E, _ = run.run(tol=1e-12, max_sweeps=30)
+    assert abs(stats.energy - E) < 1e-10
+    assert max(st.m) <= m
+
+
+def test_prepare_energy_equals_oracle(ctx):
+    l, m = 10, 12
+    tensors = synth.random_mps(l, 2, m, seed=77)
+    st = abi.State(abi.heisenberg_mpo(l), tensors, m, device=DEV)
+    e0 = ctx.prepare(st)
+    from oracle.adjoint import mpo_expectation
+    assert abs(e0 - mpo_expectation(MPO.heisenberg_mpo(l), tensors)) < 1e-12
