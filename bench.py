@@ -52,6 +52,8 @@ def build_inputs(ctx, abi, synth, torch, m, dev):
                 nb = torch.empty(k, dtype=torch.float64, device=dev)
                 kk, _, _ = ctx.truncate(abi.L2R, x.reshape(ml_ * d_, mr_), x, k, 0.0, dummy, site, nb,
                                         renormalize=False)
+                if kk != min(ml_ * d_, mr_):
+                    raise RuntimeError("left-canonicalisation lost rank: %d of %d" % (kk, min(ml_ * d_, mr_)))
                 out.append(site[: ml_ * d_ * kk].reshape(ml_, d_, kk))
             else:
                 k = ml_
@@ -60,6 +62,8 @@ def build_inputs(ctx, abi, synth, torch, m, dev):
                 nb = torch.empty(k, dtype=torch.float64, device=dev)
                 kk, _, _ = ctx.truncate(abi.R2L, x.reshape(ml_, d_ * mr_), x, k, 0.0, dummy, site, nb,
                                         renormalize=False)
+                if kk != min(ml_, d_ * mr_):
+                    raise RuntimeError("right-canonicalisation lost rank: %d of %d" % (kk, min(ml_, d_ * mr_)))
                 out.append(site[: kk * d_ * mr_].reshape(kk, d_, mr_))
         return out
 

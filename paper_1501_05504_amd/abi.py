@@ -108,6 +108,24 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _need(t, n, dtype, name):
+    """A kernel reads or writes n elements of t: refuse anything smaller, on
+    the host, before the call."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("%s must be a CUDA tensor" % name)
+    if t.dtype != dtype:
+        raise ValueError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.numel() < n:
+        raise ValueError("%s holds %d elements, the call needs %d" % (name, t.numel(), n))
+
+
+_ELT = {F64: (torch.float64, torch.float64, torch.float64),     # (L/R/psi, W, out)
+        F32: (torch.float32, torch.float32, torch.float32),
+        BF16: (torch.bfloat16, torch.float32, torch.float32)}
+
+
 class Context:
     """A library context bound to a device and to torch's current stream."""
 
@@ -161,6 +179,12 @@ class Context:
         ml, d, mr = psi.shape
         wl, wr = W.shape[0], W.shape[1]
         prec = _PREC[psi.dtype]
+        te, tw, to = _ELT[prec]
+        _need(L, ml * wl * ml, te, "L")
+        _need(W, wl * wr * d * d, tw, "W")
+        _need(R, mr * wr * mr, te, "R")
+        _need(psi, ml * d * mr, te, "psi")
+        _need(out, ml * d * mr, to, "out")
         return self._check(_apply_heff(self.h, prec, ml, d, mr, wl, wr, _ptr(L), _ptr(W), _ptr(R),
                                        _ptr(psi), _ptr(out)))
 
@@ -168,6 +192,15 @@ class Context:
         self._sync_stream()
         ml, d, mr = psi.shape
         wl, wr = W.shape[0], W.shape[1]
+        f = torch.float64
+        _need(W, wl * wr * d * d, f, "W")
+        _need(psi, ml * d * mr, f, "psi")
+        if direction == L2R:
+            _need(env, ml * wl * ml, f, "L")
+            _need(Mtilde, ml * d * (1 + wr) * mr, f, "Mtilde")
+        else:
+            _need(env, mr * wr * mr, f, "R")
+            _need(Mtilde, (1 + wl) * ml * d * mr, f, "Mtilde")
         return self._check(_expand(self.h, direction, ml, d, mr, wl, wr, _ptr(env), _ptr(W), _ptr(psi),
                                    float(alpha), _ptr(Mtilde)))
 
@@ -175,14 +208,27 @@ class Context:
         """Returns (k, discarded, singular values)."""
         self._sync_stream()
         ml, d, mr = psi.shape
+        f = torch.float64
         if direction == L2R:
             width = Mtilde.shape[1]
             other = nbr.numel() // mr
             n = ml * d
+            if Mtilde.shape[0] != n:
+                raise ValueError("L2R: Mtilde must have m_l*d rows")
+            _need(nbr, mr * other, f, "nbr")
+            _need(site_out, n * min(kmax, n), f, "site_out")
+            _need(nbr_out, min(kmax, n) * other, f, "nbr_out")
         else:
             width = Mtilde.shape[0]
             other = nbr.numel() // ml
             n = d * mr
+            if Mtilde.shape[1] != n:
+                raise ValueError("R2L: Mtilde must have d*m_r columns")
+            _need(nbr, ml * other, f, "nbr")
+            _need(site_out, n * min(kmax, n), f, "site_out")
+            _need(nbr_out, min(kmax, n) * other, f, "nbr_out")
+        _need(Mtilde, Mtilde.shape[0] * Mtilde.shape[1], f, "Mtilde")
+        _need(psi, ml * d * mr, f, "psi")
         s = (ctypes.c_double * n)()
         k = c_int()
         disc = c_double()
@@ -195,6 +241,15 @@ class Context:
         self._sync_stream()
         ml, d, mr = site.shape
         wl, wr = W.shape[0], W.shape[1]
+        f = torch.float64
+        _need(W, wl * wr * d * d, f, "W")
+        _need(site, ml * d * mr, f, "site")
+        if direction == L2R:
+            _need(env_in, ml * wl * ml, f, "L")
+            _need(env_out, mr * wr * mr, f, "env_out")
+        else:
+            _need(env_in, mr * wr * mr, f, "R")
+            _need(env_out, ml * wl * ml, f, "env_out")
         return self._check(_update_env(self.h, direction, ml, d, mr, wl, wr, _ptr(env_in), _ptr(W),
                                        _ptr(site), _ptr(env_out)))
 
@@ -203,6 +258,7 @@ class Context:
         self._sync_stream()
         ml, d, mr = psi.shape
         wl, wr = W.shape[0], W.shape[1]
+        self._check_heff_f64(L, W, R, psi, ml, d, mr, wl, wr)
         th = c_double()
         nmv = c_int()
         st = self._check(_lanczos(self.h, prec, ml, d, mr, wl, wr, _ptr(L), _ptr(W), _ptr(R), _ptr(psi),
@@ -210,10 +266,18 @@ class Context:
                          warn_ok=True)
         return th.value, nmv.value, st == OK
 
+    def _check_heff_f64(self, L, W, R, psi, ml, d, mr, wl, wr):
+        f = torch.float64
+        _need(L, ml * wl * ml, f, "L")
+        _need(W, wl * wr * d * d, f, "W")
+        _need(R, mr * wr * mr, f, "R")
+        _need(psi, ml * d * mr, f, "psi")
+
     def energy(self, L, W, R, psi):
         self._sync_stream()
         ml, d, mr = psi.shape
         wl, wr = W.shape[0], W.shape[1]
+        self._check_heff_f64(L, W, R, psi, ml, d, mr, wl, wr)
         e = c_double()
         self._check(_energy(self.h, ml, d, mr, wl, wr, _ptr(L), _ptr(W), _ptr(R), _ptr(psi),
                             ctypes.byref(e)))
@@ -223,6 +287,8 @@ class Context:
         self._sync_stream()
         ml, d, mr = psi.shape
         wl, wr = Wbar.shape[0], Wbar.shape[1]
+        self._check_heff_f64(L, Wbar, R, psi, ml, d, mr, wl, wr)
+        _need(ybar, ml * d * mr, torch.float64, "ybar")
         return self._check(_grad_w(self.h, ml, d, mr, wl, wr, _ptr(L), _ptr(R), _ptr(psi), _ptr(ybar),
                                    _ptr(Wbar)))
 
@@ -262,6 +328,16 @@ class State:
         self.renv = [torch.zeros(cap_env, dtype=torch.float64, device=device) for _ in range(self.l)]
         self.mpo = [torch.as_tensor(b, dtype=torch.float64).contiguous().to(device) for b in mpo_blocks]
         m = [1] + [int(t.shape[2]) for t in site_tensors]
+        if len(mpo_blocks) != self.l:
+            raise ValueError("one MPO tensor per site is required")
+        for i, t in enumerate(site_tensors):
+            if tuple(t.shape) != (m[i], self.d, m[i + 1]) or m[i + 1] > mmax or m[i] > mmax:
+                raise ValueError("site %d has shape %s, expected (%d, %d, %d) with bonds <= %d"
+                                 % (i, tuple(t.shape), m[i], self.d, m[i + 1], mmax))
+            if tuple(mpo_blocks[i].shape) != (w[i], w[i + 1], self.d, self.d):
+                raise ValueError("MPO tensor %d has shape %s" % (i, tuple(mpo_blocks[i].shape)))
+        if m[-1] != 1 or w[-1] != 1 or mpo_blocks[0].shape[0] != 1:
+            raise ValueError("open boundaries need m_l = w_l = 1 at both ends")
         for i, t in enumerate(site_tensors):
             tt = torch.as_tensor(t, dtype=torch.float64).reshape(-1)
             self.site[i][: tt.numel()].copy_(tt.to(device))

@@ -15,8 +15,10 @@
 // LDS row for the whole BK tile and feeds them to consecutive MFMA steps.
 // Each lane therefore issues two 16-byte LDS reads per operand tile per BK.
 //
-// Output layout of the 16x16 MFMA blocks: lane l, accumulator r holds
-// D[4*(l/16) + r][l % 16] (checked on the device by the layout probe test).
+// Output layout of the 16x16 MFMA blocks, lane l, accumulator r:
+//   FP32 / BF16 variants: D[4*(l/16) + r][l % 16]
+//   FP64 variant:         D[4*r + l/16][l % 16]   (one row per accumulator
+//                          group, the four lane groups interleaved)
 //
 // Block-tile to workgroup mapping: consecutive workgroup ids are dispatched
 // round-robin across the 8 XCDs, so the linear id is first remapped to give
@@ -223,7 +225,8 @@ void gemm_kernel(KParams p) {
       const int col = n0 + wn * WN + j * 16 + lrow;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * WM + i * 16 + lgrp * 4 + r;
+        const int rr = (sizeof(S) == 8) ? (r * 4 + lgrp) : (lgrp * 4 + r);
+        const int row = m0 + wm * WM + i * 16 + rr;
         if (row < p.M && col < p.N) {
           AT* dst = C + (long)row * p.ldc + col;
           AT v = alpha * acc[i][j][r];
