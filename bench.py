@@ -142,6 +142,9 @@ def main():
     ap.add_argument("--no-f32", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one plain 1 GiB read + 1 GiB write elementwise kernel (torch.neg) first, "
+                         "as the reference for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the H_eff hot path of one GPU's share); "
@@ -154,6 +157,13 @@ def main():
 
     dev = torch.device("cuda:0")
     ctx = abi.Context(0)
+    if args.copy_probe:
+        x = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        torch.neg(x, out=y)
+        torch.cuda.synchronize()
+        del x, y
+        print("bench: copy probe done (1 GiB read, 1 GiB written)", file=sys.stderr, flush=True)
     d, w = 4, 6
     results = {}
     heads = None
