@@ -142,6 +142,10 @@ def main():
     ap.add_argument("--no-f32", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tile", type=int, default=-1, help="GEMM tile configuration (-1 = library heuristic)")
+    ap.add_argument("--gaussian-env", action="store_true",
+                    help="Gaussian L and R instead of MPS-built environments (same kernels and shapes; "
+                         "no eigensolver calls, for counter runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 1 GiB read + 1 GiB write elementwise kernel (torch.neg) first, "
                          "as the reference for HBM byte counters")
@@ -169,7 +173,14 @@ def main():
     heads = None
     for m in [args.m] + [int(x) for x in args.extra_m.split(",") if x.strip()]:
         print("bench: building inputs m=%d" % m, file=sys.stderr, flush=True)
-        L, W, R = build_inputs(ctx, abi, synth, torch, m, dev)
+        if args.gaussian_env:
+            mpo = abi.hubbard_chain_mpo(3, t=1.0, U=8.0)
+            W = torch.tensor(mpo[1], dtype=torch.float64, device=dev)
+            L = torch.tensor(synth.gaussian((m, w, m), synth.SEED_LEFT), dtype=torch.float64, device=dev) / m
+            R = torch.tensor(synth.gaussian((m, w, m), synth.SEED_RIGHT), dtype=torch.float64, device=dev) / m
+        else:
+            L, W, R = build_inputs(ctx, abi, synth, torch, m, dev)
+        ctx.set_tile_config(args.tile)
         psi = torch.tensor(synth.gaussian((m, d, m), synth.SEED_PSI), dtype=torch.float64, device=dev)
         psi /= torch.linalg.vector_norm(psi)
         out = torch.empty_like(psi)
@@ -214,7 +225,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded Gaussian MPS environments, Gaussian psi)",
-        "config": {"workload": "heff_microbench_hubbard", "m": m, "d": d, "w": w,
+        "config": {"workload": "heff_microbench_hubbard", "m": m, "d": d, "w": w, "tile": args.tile,
+                   "environments": "gaussian" if args.gaussian_env else "mps",
                    "flop_per_step": F, "seeds": {"left": synth.SEED_LEFT, "right": synth.SEED_RIGHT,
                                                  "psi": synth.SEED_PSI}},
         "pct_fp64_mfma_peak": round(100 * F / (ms * 1e-3) / PEAK["f64"], 2),

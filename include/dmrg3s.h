@@ -82,8 +82,13 @@ d3s_status d3s_synchronize(d3s_ctx ctx);
 /* Library version string (host, static). */
 const char* d3s_version(void);
 /* GEMM tile configuration: -1 = size heuristic (default), 0 = 128x128
- * block tiles (4 waves of 64x64), 1 = 64x64 block tiles (4 waves of 32x32). */
+ * block tiles (4 waves of 64x64), 1 = 64x64 (4 waves of 32x32), 2 = 256x128
+ * (8 waves of 64x64), 3 = 128x128 (8 waves of 64x32). */
 d3s_status d3s_set_tile_config(d3s_ctx ctx, int cfg);
+/* Split-K of GEMMs whose tiles cannot fill the device (default on; the
+ * partial products are summed in a fixed order, so results stay
+ * deterministic).  enable = 0 turns it off. */
+d3s_status d3s_set_splitk(d3s_ctx ctx, int enable);
 
 /*
  * H_eff * psi  (eq. es-iter, Sec. 5):

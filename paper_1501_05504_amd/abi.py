@@ -71,6 +71,7 @@ _set_stream = _sig("d3s_set_stream", c_int, [c_void_p, c_void_p])
 _synchronize = _sig("d3s_synchronize", c_int, [c_void_p])
 _version = _sig("d3s_version", ctypes.c_char_p, [])
 _set_tile_config = _sig("d3s_set_tile_config", c_int, [c_void_p, c_int])
+_set_splitk = _sig("d3s_set_splitk", c_int, [c_void_p, c_int])
 _profile_begin = _sig("d3s_profile_begin", c_int, [c_void_p, c_int])
 _profile_end = _sig("d3s_profile_end", c_int, [c_void_p, c_double_p, c_int_p])
 _apply_heff = _sig("d3s_apply_heff", c_int, [c_void_p, c_int] + [c_int] * 5 + [c_void_p] * 5)
@@ -162,6 +163,9 @@ class Context:
 
     def set_tile_config(self, cfg):
         self._check(_set_tile_config(self.h, cfg))
+
+    def set_splitk(self, enable):
+        self._check(_set_splitk(self.h, 1 if enable else 0))
 
     def profile_begin(self, capacity):
         self._check(_profile_begin(self.h, capacity))

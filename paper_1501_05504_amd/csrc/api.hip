@@ -113,8 +113,15 @@ d3s_status d3s_synchronize(d3s_ctx ctx) {
 
 d3s_status d3s_set_tile_config(d3s_ctx ctx, int cfg) {
   return guarded(ctx, [&] {
-    D3S_REQUIRE(cfg >= -1 && cfg <= 1, "tile config must be -1, 0 or 1");
+    D3S_REQUIRE(cfg >= -1 && cfg <= 3, "tile config must be in [-1, 3]");
     ctx->c.tile_config = cfg;
+    return D3S_OK;
+  });
+}
+
+d3s_status d3s_set_splitk(d3s_ctx ctx, int enable) {
+  return guarded(ctx, [&] {
+    ctx->c.splitk_off = (enable == 0);
     return D3S_OK;
   });
 }

@@ -36,7 +36,7 @@ struct Error {
 enum WsSlot {
   WS_T1 = 0, WS_T2, WS_LZ_V, WS_LZ_W, WS_LZ_COEF, WS_RED, WS_GRAM, WS_EIGVAL,
   WS_EIGTMP, WS_UKT, WS_X, WS_MT, WS_CAST_L, WS_CAST_R, WS_CAST_X, WS_CAST_Y,
-  WS_CAST_W, WS_REF, WS_PSI, WS_INFO, WS_NBR, WS_MISC, WS_NSLOTS
+  WS_CAST_W, WS_REF, WS_PSI, WS_INFO, WS_NBR, WS_MISC, WS_SPLITK, WS_NSLOTS
 };
 
 struct Ctx {
@@ -50,6 +50,7 @@ struct Ctx {
   double* host_red = nullptr;        // pinned host staging for scalars
   std::string last_error;
   int tile_config = -1;              // GEMM tile configuration (-1 = heuristic)
+  bool splitk_off = false;           // disable split-K (tests compare both paths)
   // per-kernel profiling of H_eff: events around GEMM-1, W-map, GEMM-2
   bool prof = false;
   int prof_cap = 0, prof_n = 0;

@@ -25,6 +25,8 @@
 // every XCD a contiguous range of tiles, then tiles are grouped 8 row-tiles
 // at a time so that concurrently resident tiles share A rows and B columns
 // in that XCD's L2.
+#include <algorithm>
+
 #include "d3s_internal.h"
 
 namespace d3s {
@@ -47,18 +49,14 @@ template <> struct Acc<float> { typedef float T; typedef f4v V; };
 template <> struct Acc<bf16_t> { typedef float T; typedef f4v V; };
 
 template <typename S>
-__device__ __forceinline__ void mma_tile(typename Acc<S>::V& c, const Frag& a, const Frag& b) {
-  if constexpr (sizeof(S) == 8) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a.d[s], b.d[s], c, 0, 0, 0);
-  } else if constexpr (sizeof(S) == 4) {
-#pragma unroll
-    for (int s = 0; s < 8; ++s) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.f[s], b.f[s], c, 0, 0, 0);
-  } else {
-#pragma unroll
-    for (int s = 0; s < 2; ++s) c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h[s], b.h[s], c, 0, 0, 0);
-  }
+__device__ __forceinline__ void mma_step(typename Acc<S>::V& c, const Frag& a, const Frag& b, int s) {
+  if constexpr (sizeof(S) == 8) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a.d[s], b.d[s], c, 0, 0, 0);
+  else if constexpr (sizeof(S) == 4) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.f[s], b.f[s], c, 0, 0, 0);
+  else c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h[s], b.h[s], c, 0, 0, 0);
 }
+
+// MFMA steps per 32-byte fragment: 4 (FP64), 8 (FP32), 2 (BF16)
+template <typename S> constexpr int kSteps() { return sizeof(S) == 8 ? 4 : (sizeof(S) == 4 ? 8 : 2); }
 
 struct KParams {
   int M, N, K;
@@ -66,6 +64,8 @@ struct KParams {
   const void* B; long ldb; long sB;
   void* C; long ldc; long sC;
   double alpha, beta;
+  int kchunk;        // K range of one split (multiple of BK); == K when not split
+  long sSplit;       // element stride between the partial products of two splits
 };
 
 __device__ __forceinline__ void tile_coords(int nTm, int nTn, int& tm, int& tn) {
@@ -160,9 +160,11 @@ void gemm_kernel(KParams p) {
   tile_coords(nTm, nTn, tm, tn);
   const int m0 = tm * BM, n0 = tn * BN;
   const long bz = blockIdx.y;
+  const int kbeg = blockIdx.z * p.kchunk;
+  const int kend = min(p.K, kbeg + p.kchunk);
   const S* __restrict__ A = reinterpret_cast<const S*>(p.A) + bz * p.sA;
   const S* __restrict__ B = reinterpret_cast<const S*>(p.B) + bz * p.sB;
-  AT* __restrict__ C = reinterpret_cast<AT*>(p.C) + bz * p.sC;
+  AT* __restrict__ C = reinterpret_cast<AT*>(p.C) + bz * p.sC + (long)blockIdx.z * p.sSplit;
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -177,10 +179,10 @@ void gemm_kernel(KParams p) {
 
   Stager<S, BM, NT, AKC> ga;
   Stager<S, BN, NT, BKC> gb;
-  const int nk = (p.K + BK - 1) / BK;
+  const int nk = (kend - kbeg + BK - 1) / BK;
   if (nk > 0) {
-    ga.load(A, p.lda, m0, p.M, 0, p.K);
-    gb.load(B, p.ldb, n0, p.N, 0, p.K);
+    ga.load(A, p.lda, m0, p.M, kbeg, kend);
+    gb.load(B, p.ldb, n0, p.N, kbeg, kend);
     ga.store(sA[0]);
     gb.store(sB[0]);
   }
@@ -189,8 +191,8 @@ void gemm_kernel(KParams p) {
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
     if (kt + 1 < nk) {
-      ga.load(A, p.lda, m0, p.M, (kt + 1) * BK, p.K);
-      gb.load(B, p.ldb, n0, p.N, (kt + 1) * BK, p.K);
+      ga.load(A, p.lda, m0, p.M, kbeg + (kt + 1) * BK, kend);
+      gb.load(B, p.ldb, n0, p.N, kbeg + (kt + 1) * BK, kend);
     }
     Frag fa[TM], fb[TN];
     const int koff = lgrp * (32 / (int)sizeof(S));
@@ -206,10 +208,13 @@ void gemm_kernel(KParams p) {
       fb[j].q[0] = *reinterpret_cast<const uint4*>(src);
       fb[j].q[1] = *reinterpret_cast<const uint4*>(src + 16 / sizeof(S));
     }
+    // step outermost: TM*TN independent accumulators between two dependent MFMAs
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+    for (int st = 0; st < kSteps<S>(); ++st)
 #pragma unroll
-      for (int j = 0; j < TN; ++j) mma_tile<S>(acc[i][j], fa[i], fb[j]);
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) mma_step<S>(acc[i][j], fa[i], fb[j], st);
     if (kt + 1 < nk) {
       ga.store(sA[cur ^ 1]);
       gb.store(sB[cur ^ 1]);
@@ -237,11 +242,44 @@ void gemm_kernel(KParams p) {
     }
 }
 
+// C = alpha * sum_z P[z] + beta * C, in a fixed order over the splits
+template <typename AT>
+__global__ void splitk_reduce_kernel(const AT* __restrict__ P, int S, long sSplit, int M, int N, AT* __restrict__ C,
+                                     long ldc, double alpha, double beta) {
+  const long total = (long)M * N;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+    const long r = i / N, c = i - r * N;
+    AT acc = 0;
+    for (int z = 0; z < S; ++z) acc += P[z * sSplit + i];
+    AT v = (AT)alpha * acc;
+    AT* dst = C + r * ldc + c;
+    if (beta != 0.0) v += (AT)beta * *dst;
+    *dst = v;
+  }
+}
+
 template <typename S, int BM, int BN, int WM, int WN>
-void launch_cfg(Ctx* c, const GemmArgs& g) {
-  KParams p{g.M, g.N, g.K, g.A, g.lda, g.sA, g.B, g.ldb, g.sB, g.C, g.ldc, g.sC, g.alpha, g.beta};
+void launch_cfg(Ctx* c, const GemmArgs& g, int splits) {
+  typedef typename Acc<S>::T AT;
+  constexpr int BK = 128 / (int)sizeof(S);
   const int nTm = (g.M + BM - 1) / BM, nTn = (g.N + BN - 1) / BN;
-  dim3 grid((unsigned)(nTm * nTn), (unsigned)g.batch, 1);
+  KParams p{g.M, g.N, g.K, g.A, g.lda, g.sA, g.B, g.ldb, g.sB, g.C, g.ldc, g.sC, g.alpha, g.beta, g.K, 0};
+  AT* part = nullptr;
+  if (splits > 1) {
+    // chunk = ceil(K / splits) rounded up to BK; recompute the number of splits
+    int chunk = (g.K + splits - 1) / splits;
+    chunk = (chunk + BK - 1) / BK * BK;
+    splits = (g.K + chunk - 1) / chunk;
+    part = (AT*)ws_get(c, WS_SPLITK, sizeof(AT) * (size_t)splits * g.M * g.N);
+    p.C = part;
+    p.ldc = g.N;
+    p.sC = 0;
+    p.alpha = 1.0;
+    p.beta = 0.0;
+    p.kchunk = chunk;
+    p.sSplit = (long)g.M * g.N;
+  }
+  dim3 grid((unsigned)(nTm * nTn), (unsigned)g.batch, (unsigned)splits);
   dim3 block((BM / WM) * (BN / WN) * 64, 1, 1);
   if (g.a_kc && g.b_kc)
     hipLaunchKernelGGL((gemm_kernel<S, BM, BN, WM, WN, true, true>), grid, block, 0, c->stream, p);
@@ -252,20 +290,45 @@ void launch_cfg(Ctx* c, const GemmArgs& g) {
   else
     hipLaunchKernelGGL((gemm_kernel<S, BM, BN, WM, WN, false, false>), grid, block, 0, c->stream, p);
   D3S_HIP(hipGetLastError());
+  if (splits > 1) {
+    long total = (long)g.M * g.N;
+    long nb = std::min<long>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL((splitk_reduce_kernel<AT>), dim3((unsigned)nb), dim3(256), 0, c->stream, part, splits,
+                       (long)g.M * g.N, g.M, g.N, (AT*)g.C, g.ldc, g.alpha, g.beta);
+    D3S_HIP(hipGetLastError());
+  }
 }
 
+// Tile configurations (block tile / wave tile / waves):
+//   0: 128x128 / 64x64 / 4      1: 64x64 / 32x32 / 4
+//   2: 256x128 / 64x64 / 8      3: 128x128 / 64x32 / 8
 template <typename S>
 void gemm_dispatch(Ctx* c, const GemmArgs& g) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
-  // The 128x128 tile needs at least ~1 tile per CU to fill the chip; smaller
-  // problems use 64x64 tiles.
-  const long big = (long)((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch;
+  constexpr int BK = 128 / (int)sizeof(S);
   int cfg = c->tile_config;
-  if (cfg < 0) cfg = (big >= 256) ? 0 : 1;
-  if (cfg == 0)
-    launch_cfg<S, 128, 128, 64, 64>(c, g);
-  else
-    launch_cfg<S, 64, 64, 32, 32>(c, g);
+  const long t128 = (long)((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch;
+  if (cfg < 0) cfg = (t128 >= 256) ? 0 : 1;
+  long tiles;
+  switch (cfg) {
+    case 0: case 3: tiles = t128; break;
+    case 2: tiles = (long)((g.M + 255) / 256) * ((g.N + 127) / 128) * g.batch; break;
+    default: tiles = (long)((g.M + 63) / 64) * ((g.N + 63) / 64) * g.batch; break;
+  }
+  // split K when the tiles cannot fill the 256 CUs and K is long enough for
+  // every split to run several BK steps; only for unbatched products
+  int splits = 1;
+  if (g.batch == 1 && tiles < 256 && g.K >= 8 * BK) {
+    splits = (int)std::min<long>((512 + tiles - 1) / tiles, g.K / (4 * BK));
+    if (splits < 2) splits = 1;
+  }
+  if (c->splitk_off) splits = 1;
+  switch (cfg) {
+    case 0: launch_cfg<S, 128, 128, 64, 64>(c, g, splits); break;
+    case 2: launch_cfg<S, 256, 128, 64, 64>(c, g, splits); break;
+    case 3: launch_cfg<S, 128, 128, 64, 32>(c, g, splits); break;
+    default: launch_cfg<S, 64, 64, 32, 32>(c, g, splits); break;
+  }
 }
 
 }  // namespace

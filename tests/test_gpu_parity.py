@@ -72,8 +72,8 @@ def test_apply_heff_f64(ctx, shape):
     assert rel_err(out.cpu().numpy(), ref) < 1e-12
 
 
-@pytest.mark.parametrize("cfg", [0, 1])
-def test_apply_heff_both_tile_configs(ctx, cfg):
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+def test_apply_heff_every_tile_config(ctx, cfg):
     ml, d, mr, wl, wr = 150, 4, 133, 6, 6
     L, W, R, psi = _inputs(ml, d, mr, wl, wr, seed=7)
     ref = C.apply_heff(L, W, R, psi)
@@ -85,6 +85,31 @@ def test_apply_heff_both_tile_configs(ctx, cfg):
     finally:
         ctx.set_tile_config(-1)
     assert rel_err(out.cpu().numpy(), ref) < 1e-12
+
+
+@pytest.mark.parametrize("shape", [(256, 4, 256, 6, 6), (100, 4, 300, 6, 6), (40, 2, 900, 5, 5)],
+                         ids=["m256", "rect", "longK"])
+def test_apply_heff_split_k_equals_unsplit(ctx, shape):
+    """Small launches take the split-K path; it must agree with the oracle and,
+    within rounding, with the unsplit product."""
+    ml, d, mr, wl, wr = shape
+    L, W, R, psi = _inputs(ml, d, mr, wl, wr, seed=11)
+    ref = C.apply_heff(L, W, R, psi)
+    outs = []
+    for on in (True, False):
+        ctx.set_splitk(on)
+        out = torch.empty((ml, d, mr), dtype=torch.float64, device=DEV)
+        ctx.apply_heff(dev(L), dev(W), dev(R), dev(psi), out)
+        torch.cuda.synchronize()
+        outs.append(out.cpu().numpy())
+    ctx.set_splitk(True)
+    assert rel_err(outs[0], ref) < 1e-12
+    assert rel_err(outs[1], ref) < 1e-12
+    # deterministic: a second split run is bitwise identical
+    out = torch.empty((ml, d, mr), dtype=torch.float64, device=DEV)
+    ctx.apply_heff(dev(L), dev(W), dev(R), dev(psi), out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), outs[0])
 
 
 @pytest.mark.parametrize("shape", SHAPES[2:], ids=[str(s) for s in SHAPES[2:]])
