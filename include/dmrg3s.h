@@ -262,6 +262,16 @@ d3s_status d3s_prepare(d3s_ctx ctx, d3s_state* state, double* energy);
 d3s_status d3s_sweep(d3s_ctx ctx, d3s_state* state, d3s_sweep_params* params,
                      d3s_sweep_stats* stats);
 
+/* dE/dW_i of E = <Psi|H|Psi> for every site (FP64): grads[i] (device, host
+ * array of l pointers) receives a (w[i], w[i+1], d, d) tensor, the adjoint
+ * d3s_heff_grad_W with ybar = psi in the gauge centred on site i.  Summing
+ * <grads[i], dW_i/dJ> over sites gives dE/dJ for any MPO parameter J
+ * (product rule; equal to <Psi|dH/dJ|Psi>).  Requires the centre on site
+ * l-1 (as after d3s_prepare or a sweep); walks the centre to site 0 by uncut
+ * truncations, which leave the state unchanged, and rebuilds renv on the way.
+ * Synchronises. */
+d3s_status d3s_energy_gradients(d3s_ctx ctx, d3s_state* state, double** grads);
+
 /* ---------------------------------------------------------------- models */
 /* MPO builders (host arrays, FP64, layout W[w,v,s,t], one block per site,
  * concatenated; offsets[i] = start of site i, dims[i] = w_i for i = 0..l).

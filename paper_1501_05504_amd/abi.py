@@ -88,6 +88,7 @@ _grad_w = _sig("d3s_heff_grad_W", c_int, [c_void_p] + [c_int] * 5 + [c_void_p] *
 _prepare = _sig("d3s_prepare", c_int, [c_void_p, ctypes.POINTER(d3s_state), c_double_p])
 _sweep = _sig("d3s_sweep", c_int, [c_void_p, ctypes.POINTER(d3s_state), ctypes.POINTER(d3s_sweep_params),
                                    ctypes.POINTER(d3s_sweep_stats)])
+_grads = _sig("d3s_energy_gradients", c_int, [c_void_p, ctypes.POINTER(d3s_state), ctypes.POINTER(c_void_p)])
 _mpo_spin = _sig("d3s_mpo_spin_exchange", c_int, [c_int, c_int, c_double_p, c_double_p,
                                                   ctypes.POINTER(c_long), c_int_p, ctypes.POINTER(c_long)])
 _mpo_fermion = _sig("d3s_mpo_fermion_hopping", c_int, [c_int, c_int, c_double_p, c_double, c_double_p,
@@ -302,6 +303,15 @@ class Context:
         self._check(_prepare(self.h, ctypes.byref(state.c), ctypes.byref(e)))
         state.pull_dims()
         return e.value
+
+    def energy_gradients(self, state):
+        """dE/dW_i for every site (list of device tensors shaped like the MPO)."""
+        self._sync_stream()
+        grads = [torch.empty_like(w) for w in state.mpo]
+        arr = (c_void_p * state.l)(*[g.data_ptr() for g in grads])
+        self._check(_grads(self.h, ctypes.byref(state.c), arr))
+        state.pull_dims()
+        return grads
 
     def sweep(self, state, params):
         """One full sweep; returns (status, stats, records)."""

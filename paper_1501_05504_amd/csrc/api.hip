@@ -297,4 +297,15 @@ d3s_status d3s_sweep(d3s_ctx ctx, d3s_state* state, d3s_sweep_params* params, d3
   });
 }
 
+d3s_status d3s_energy_gradients(d3s_ctx ctx, d3s_state* state, double** grads) {
+  return guarded(ctx, [&] {
+    check_state(state);
+    D3S_REQUIRE(grads, "null gradient array");
+    for (int i = 0; i < state->l; ++i) D3S_REQUIRE(grads[i], "null gradient pointer");
+    D3S_REQUIRE((long)state->d * state->mmax <= 46340, "d * mmax too large for the Gram route");
+    d3s::op_gradients(&ctx->c, state, grads);
+    return D3S_OK;
+  });
+}
+
 }  // extern "C"

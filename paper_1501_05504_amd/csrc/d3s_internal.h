@@ -137,6 +137,7 @@ void op_heff_grad_W(Ctx* c, int ml, int d, int mr, int wl, int wr, const double*
 
 double op_prepare(Ctx* c, d3s_state* s, double eps);
 void op_sweep(Ctx* c, d3s_state* s, d3s_sweep_params* p, d3s_sweep_stats* st);
+void op_gradients(Ctx* c, d3s_state* s, double** grads);
 
 // host symmetric eigensolver (cyclic Jacobi) for small tridiagonal projections
 void jacobi_eigh(int n, std::vector<double>& A, std::vector<double>& evals,

@@ -207,4 +207,32 @@ void op_sweep(Ctx* c, d3s_state* s, d3s_sweep_params* p, d3s_sweep_stats* st) {
   st->seconds = now() - t_start;
 }
 
+// dE/dW_i of <Psi|H|Psi> for every site i, each taken with the environments
+// of the gauge centred on i (product rule over the MPO tensors).  Starts from
+// the centre on site l-1 with lenv[0..l-1] valid, walks right to left moving
+// the centre by an uncut truncation (alpha = 0: the state is unchanged up to
+// the resolution of the Gram route), and leaves the centre on site 0 with
+// renv[0..l-1] valid.
+void op_gradients(Ctx* c, d3s_state* s, double** grads) {
+  const int l = s->l, d = s->d;
+  if (s->center != l - 1) throw Error{D3S_EINVAL, "gradients: the orthogonality centre must be on site l-1"};
+  const size_t cap = (size_t)s->mmax * d * s->mmax;
+  double* tmpS = (double*)ws_get(c, WS_PSI, sizeof(double) * cap);
+  double* tmpN = (double*)ws_get(c, WS_NBR, sizeof(double) * cap);
+  for (int i = l - 1; i >= 0; --i) {
+    const int ml = s->m[i], mr = s->m[i + 1], wl = s->w[i], wr = s->w[i + 1];
+    op_heff_grad_W(c, ml, d, mr, wl, wr, s->lenv[i], s->renv[i], s->site[i], s->site[i], grads[i]);
+    if (i == 0) break;
+    const int mll = s->m[i - 1];
+    TruncResult t = op_truncate(c, D3S_R2L, ml, d, mr, ml, s->site[i], s->site[i], ml, 0.0, s->site[i - 1],
+                                (long)mll * d, tmpS, tmpN, nullptr, false);
+    copy_f64(c, tmpS, s->site[i], (long)t.k * d * mr);
+    copy_f64(c, tmpN, s->site[i - 1], (long)mll * d * t.k);
+    s->m[i] = t.k;
+    op_update_env(c, D3S_R2L, t.k, d, mr, wl, wr, s->renv[i], s->mpo[i], s->site[i], s->renv[i - 1]);
+    s->center = i - 1;
+  }
+  D3S_HIP(hipStreamSynchronize(c->stream));
+}
+
 }  // namespace d3s

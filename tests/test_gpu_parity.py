@@ -328,3 +328,58 @@ def test_prepare_energy_equals_oracle(ctx):
     e0 = ctx.prepare(st)
     from oracle.adjoint import mpo_expectation
     assert abs(e0 - mpo_expectation(MPO.heisenberg_mpo(l), tensors)) < 1e-12
+
+
+def test_autograd_heff_adjoints(ctx):
+    """The autograd Function's W and psi gradients equal the oracle's
+    definitions (vector-Jacobian products of the linear map)."""
+    from paper_1501_05504_amd.autograd import heff_apply
+    ml, d, mr, wl, wr = 21, 4, 33, 6, 6
+    L, W, R, psi = _inputs(ml, d, mr, wl, wr, seed=13)
+    ybar = synth.gaussian((ml, d, mr), 1313)
+    Wt = dev(W).requires_grad_(True)
+    pt = dev(psi).requires_grad_(True)
+    y = heff_apply(ctx, dev(L), Wt, dev(R), pt)
+    y.backward(dev(ybar))
+    torch.cuda.synchronize()
+    assert rel_err(y.detach().cpu().numpy(), C.apply_heff(L, W, R, psi)) < 1e-12
+    assert rel_err(Wt.grad.cpu().numpy(), heff_grad_W(L, R, psi, ybar)) < 1e-12
+    H = C.heff_matrix(L, W, R)
+    assert rel_err(pt.grad.cpu().numpy().ravel(), H.T @ ybar.ravel()) < 1e-12
+
+
+def test_dE_dJ2_hellmann_feynman_and_finite_difference(ctx):
+    """J1-J2 chain l = 12, J2 = 0.24, m = 64 (exact): dE/dJ2 from the
+    hand-written adjoint through autograd equals <Psi| sum S_i.S_{i+2} |Psi>
+    (oracle MPO expectation on the GPU's state, 1e-10) and the central finite
+    difference of ED ground energies (delta = 1e-4, 1e-6)."""
+    from oracle.adjoint import mpo_expectation
+    from paper_1501_05504_amd.autograd import mpo_energy
+    l, m, J2, dJ = 12, 64, 0.24, 1e-4
+    st = abi.State(abi.j1j2_mpo(l, 1.0, J2), synth.random_mps(l, 2, m, seed=12), m, device=DEV)
+    e0 = ctx.prepare(st)
+    params = abi.sweep_params(alpha=1e-3, e_before=e0, tol=1e-13)
+    prev = None
+    for s in range(20):
+        _, stats, _ = ctx.sweep(st, params)
+        if prev is not None and abs(stats.energy - prev) < 1e-13:
+            break
+        prev = stats.energy
+    W0 = [torch.tensor(w, dtype=torch.float64, device=DEV) for w in abi.j1j2_mpo(l, 1.0, 0.0)]
+    W1 = [torch.tensor(w, dtype=torch.float64, device=DEV) for w in abi.j1j2_mpo(l, 1.0, 1.0)]
+    j = torch.tensor(J2, dtype=torch.float64, device=DEV, requires_grad=True)
+    Ws = [a + j * (b - a) for a, b in zip(W0, W1)]
+    E = mpo_energy(ctx, st, Ws)
+    E.backward()
+    dEdJ = float(j.grad)
+    tensors = [t.cpu().numpy() for t in st.tensors()]
+    hf = mpo_expectation(MPO.spin_exchange_mpo(l, {(i, i + 2): 1.0 for i in range(l - 2)}), tensors)
+    assert abs(dEdJ - hf) < 1e-10
+
+    def e_ed(j2):
+        c = {(i, i + 1): 1.0 for i in range(l - 1)}
+        c.update({(i, i + 2): j2 for i in range(l - 2)})
+        return ed.ground_energy(ed.spin_chain_hamiltonian(l, c))
+    assert abs(float(E) - e_ed(J2)) < 1e-10
+    fd = (e_ed(J2 + dJ) - e_ed(J2 - dJ)) / (2 * dJ)
+    assert abs(dEdJ - fd) < 1e-6
