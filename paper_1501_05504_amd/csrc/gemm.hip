@@ -308,7 +308,11 @@ void gemm_dispatch(Ctx* c, const GemmArgs& g) {
   constexpr int BK = 128 / (int)sizeof(S);
   int cfg = c->tile_config;
   const long t128 = (long)((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch;
-  if (cfg < 0) cfg = (t128 >= 256) ? 0 : 1;
+  const long t256 = (long)((g.M + 255) / 256) * ((g.N + 127) / 128) * g.batch;
+  // measured on MI355X (H_eff at m = 256..4096): the 8-wave 256x128 tile is
+  // fastest once there are enough of them (split-K fills the rest); small
+  // products use 64x64 tiles
+  if (cfg < 0) cfg = (t256 >= 64 && g.M >= 512) ? 2 : 1;
   long tiles;
   switch (cfg) {
     case 0: case 3: tiles = t128; break;
