@@ -23,6 +23,19 @@ sys.path.insert(0, ROOT)
 PEAK = {"f64": 78.6e12, "f32": 157.3e12, "bf16": 2516.6e12}
 HBM_PEAK = 8.0e12
 
+# HBM bytes per launch of the FP64 H_eff GEMMs at m = 2048 from the rocprofv3
+# FETCH_SIZE / WRITE_SIZE passes (scaled by a 1 GiB copy reference), valid
+# only for the GEMM source they were taken on (first 16 hex digits of its
+# SHA-256); any other source reports null.
+TRAFFIC = {"src_sha": "d8b39c43b8adaae6", "m": 2048,
+           "gemm1": 4.029e9 + 0.805e9, "gemm2": 4.161e9 + 0.134e9}
+
+
+def gemm_source_sha():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_1501_05504_amd", "csrc", "gemm.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
 
 def heff_flops(ml, d, mr, wl, wr):
     return 2.0 * wl * d * ml * ml * mr + 2.0 * d * d * wl * wr * ml * mr + 2.0 * wr * d * ml * mr * mr
@@ -232,7 +245,9 @@ def main():
         "pct_fp64_mfma_peak": round(100 * F / (ms * 1e-3) / PEAK["f64"], 2),
         "roofline": {"bound": "mfma", "kernel": names[dom], "achieved": round(achieved / 1e12, 3),
                      "peak": PEAK["f64"] / 1e12, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK["f64"], 4), "traffic": None},
+                     "frac": round(achieved / PEAK["f64"], 4),
+                     "traffic": (TRAFFIC[names[dom]] if (gemm_source_sha() == TRAFFIC["src_sha"]
+                                                         and m == TRAFFIC["m"]) else None)},
         "per_m": {str(k): {"f64_gflops": round(v["gflops"], 1),
                            "f64_pct_peak": round(100 * v["gflops"] * 1e9 / PEAK["f64"], 2),
                            "f32_gflops": round(v["f32"]["gflops"], 1) if "f32" in v else None,
