@@ -196,6 +196,42 @@ d3s_status d3s_energy(d3s_ctx ctx, int ml, int d, int mr, int wl, int wr, const 
 d3s_status d3s_heff_grad_W(d3s_ctx ctx, int ml, int d, int mr, int wl, int wr, const double* L,
                            const double* R, const double* psi, const double* ybar, double* Wbar);
 
+/* ---------------------------------------------------------------- symmetry blocks */
+
+/* Charge sectors of one bond (host arrays): sector i holds dim[i] consecutive
+ * basis states of charge q[i*nq .. i*nq+nq-1]; the bond dimension is the sum
+ * of the dims.  nq = 1 for U(1) (2Sz), 2 for U(1)xU(1) (N, 2Sz). */
+typedef struct {
+  int nsec;
+  const int* q;
+  const int* dim;
+} d3s_sectors;
+
+typedef struct d3s_block_plan_s* d3s_block_plan;
+
+/* Plan the block-sparse H_eff of one site (the paper uses U(1) symmetries
+ * throughout Sec. 7 without describing the blocks; see DESIGN notes in the
+ * source for the rules).  Tensors keep the dense layouts above with bond
+ * states ordered by sector; psi must vanish outside q_a + q_s = q_b, L outside
+ * q_a - q_x = Delta_w and R outside q_b - q_y = Delta_v, where phys_q (d*nq)
+ * are the physical charges and wq_left (w_l*nq) / wq_right (w_r*nq) the MPO
+ * channel charges Delta.  The plan holds the task tables of two grouped MFMA
+ * launches (one per GEMM of the Sec. 5 ordering; the W-map stays dense).
+ * *flops (host, may be NULL) receives the flop count of the allowed block
+ * products, *ntasks (may be NULL) the number of block tasks.  Synchronises. */
+d3s_status d3s_block_plan_create(d3s_ctx ctx, int nq, int d, int wl, int wr, const d3s_sectors* left,
+                                 const d3s_sectors* right, const int* phys_q, const int* wq_left,
+                                 const int* wq_right, d3s_block_plan* plan, double* flops, int* ntasks);
+void d3s_block_plan_destroy(d3s_ctx ctx, d3s_block_plan plan);
+
+/* Block-sparse H_eff * psi with a plan: the same result as d3s_apply_heff on
+ * symmetric inputs, computing only the allowed blocks; `out` is zero outside
+ * the allowed blocks.  use_graph != 0 captures the launches into a hipGraph
+ * on first use with these buffers and replays it afterwards (ordered after /
+ * before the context's stream by events).  Asynchronous. */
+d3s_status d3s_apply_heff_blocks(d3s_ctx ctx, d3s_block_plan plan, d3s_prec prec, const void* L,
+                                 const void* W, const void* R, const void* psi, void* out, int use_graph);
+
 /* ---------------------------------------------------------------- sweeps */
 
 /* A finite MPS with its MPO and environments, all FP64 device buffers owned
@@ -285,6 +321,14 @@ d3s_status d3s_mpo_spin_exchange(int l, int range, const double* J, double* out,
  * site basis (|0>, |up>, |dn>, |updn>). */
 d3s_status d3s_mpo_fermion_hopping(int l, int range, const double* t, double U, const double* mu,
                                    double* out, long* offsets, int* dims, long* total);
+
+/* Charges Delta of the MPO channels of the builders above, in their channel
+ * order: spins 2 + 3*range channels of 2Sz (nq = 1; S+ / S- / Sz kinds carry
+ * +2 / -2 / 0), fermions 2 + 4*range channels of (N, 2Sz) (nq = 2; c+_up F,
+ * c+_dn F, F c_up, F c_dn carry (1,1), (1,-1), (-1,-1), (-1,1)); identity
+ * and completion channels carry 0.  out: host array of w*nq ints. */
+d3s_status d3s_mpo_spin_charges(int range, int* out);
+d3s_status d3s_mpo_fermion_charges(int range, int* out);
 
 #ifdef __cplusplus
 }

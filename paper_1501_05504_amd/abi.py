@@ -96,6 +96,20 @@ _mpo_fermion = _sig("d3s_mpo_fermion_hopping", c_int, [c_int, c_int, c_double_p,
                                                        ctypes.POINTER(c_long)])
 
 
+class d3s_sectors(ctypes.Structure):
+    _fields_ = [("nsec", c_int), ("q", c_int_p), ("dim", c_int_p)]
+
+
+_plan_create = _sig("d3s_block_plan_create", c_int, [c_void_p, c_int, c_int, c_int, c_int,
+                                                     ctypes.POINTER(d3s_sectors), ctypes.POINTER(d3s_sectors),
+                                                     c_int_p, c_int_p, c_int_p, ctypes.POINTER(c_void_p),
+                                                     c_double_p, c_int_p])
+_plan_destroy = _sig("d3s_block_plan_destroy", None, [c_void_p, c_void_p])
+_apply_blocks = _sig("d3s_apply_heff_blocks", c_int, [c_void_p, c_void_p, c_int] + [c_void_p] * 5 + [c_int])
+_spin_charges = _sig("d3s_mpo_spin_charges", c_int, [c_int, c_int_p])
+_fermion_charges = _sig("d3s_mpo_fermion_charges", c_int, [c_int, c_int_p])
+
+
 class D3SError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__("dmrg3s status %d: %s" % (status, msg))
@@ -380,6 +394,88 @@ class State:
 def sweep_params(alpha=1e-3, adaptive=True, eps=1e-14, tol=1e-12, kmax=40, max_matvecs=2000, prec=F64,
                  e_before=0.0):
     return d3s_sweep_params(alpha, 1 if adaptive else 0, eps, tol, kmax, max_matvecs, prec, e_before)
+
+
+# --- symmetry blocks -------------------------------------------------------
+def _ints(a):
+    import numpy as np
+    arr = np.ascontiguousarray(np.asarray(a, dtype=np.int32).ravel())
+    return arr, arr.ctypes.data_as(c_int_p)
+
+
+class BlockPlan:
+    """Task tables of one block-sparse H_eff (d3s_block_plan)."""
+
+    def __init__(self, ctx, nq, d, wl, wr, left_q, left_dim, right_q, right_dim, phys_q, wq_left, wq_right):
+        self.ctx = ctx
+        self._keep = []
+
+        def sec(q, dim):
+            qa, qp = _ints(q)
+            da, dp = _ints(dim)
+            self._keep += [qa, da]
+            return d3s_sectors(len(da), qp, dp)
+        self.left, self.right = sec(left_q, left_dim), sec(right_q, right_dim)
+        pa, pp = _ints(phys_q)
+        la, lp = _ints(wq_left)
+        ra, rp = _ints(wq_right)
+        self._keep += [pa, la, ra]
+        self.ml, self.mr = int(sum(left_dim)), int(sum(right_dim))
+        self.d, self.wl, self.wr = d, wl, wr
+        h = c_void_p()
+        fl = c_double()
+        nt = c_int()
+        ctx._sync_stream()
+        ctx._check(_plan_create(ctx.h, nq, d, wl, wr, ctypes.byref(self.left), ctypes.byref(self.right), pp, lp,
+                                rp, ctypes.byref(h), ctypes.byref(fl), ctypes.byref(nt)))
+        self.h = h
+        self.flops = fl.value
+        self.ntasks = nt.value
+
+    def apply(self, L, W, R, psi, out, use_graph=False):
+        ctx = self.ctx
+        ctx._sync_stream()
+        ml, d, mr, wl, wr = self.ml, self.d, self.mr, self.wl, self.wr
+        prec = _PREC[psi.dtype]
+        te, tw, to = _ELT[prec]
+        _need(L, ml * wl * ml, te, "L")
+        _need(W, wl * wr * d * d, tw, "W")
+        _need(R, mr * wr * mr, te, "R")
+        _need(psi, ml * d * mr, te, "psi")
+        _need(out, ml * d * mr, to, "out")
+        return ctx._check(_apply_blocks(ctx.h, self.h, prec, _ptr(L), _ptr(W), _ptr(R), _ptr(psi), _ptr(out),
+                                        1 if use_graph else 0))
+
+    def close(self):
+        if self.h:
+            _plan_destroy(self.ctx.h, self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mpo_spin_charges(rng):
+    import numpy as np
+    out = np.zeros(2 + 3 * rng, dtype=np.int32)
+    if _spin_charges(rng, out.ctypes.data_as(c_int_p)) != OK:
+        raise D3SError(EINVAL, "d3s_mpo_spin_charges")
+    return out.reshape(-1, 1)
+
+
+def mpo_fermion_charges(rng):
+    import numpy as np
+    out = np.zeros((2 + 4 * rng) * 2, dtype=np.int32)
+    if _fermion_charges(rng, out.ctypes.data_as(c_int_p)) != OK:
+        raise D3SError(EINVAL, "d3s_mpo_fermion_charges")
+    return out.reshape(-1, 2)
+
+
+SPIN_HALF_CHARGES = [[1], [-1]]                          # 2Sz of |up>, |down>
+HUBBARD_CHARGES = [[0, 0], [1, 1], [1, -1], [2, 0]]      # (N, 2Sz) of |0>, |up>, |dn>, |updn>
 
 
 # --- model builders (host) -------------------------------------------------

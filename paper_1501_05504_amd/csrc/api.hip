@@ -11,6 +11,11 @@ struct d3s_ctx_s {
   d3s::Ctx c;
 };
 
+struct d3s_block_plan_s {
+  d3s::BlockHeff h;
+  d3s::Sectors left, right;
+};
+
 namespace {
 
 using d3s::Error;
@@ -304,6 +309,65 @@ d3s_status d3s_energy_gradients(d3s_ctx ctx, d3s_state* state, double** grads) {
     for (int i = 0; i < state->l; ++i) D3S_REQUIRE(grads[i], "null gradient pointer");
     D3S_REQUIRE((long)state->d * state->mmax <= 46340, "d * mmax too large for the Gram route");
     d3s::op_gradients(&ctx->c, state, grads);
+    return D3S_OK;
+  });
+}
+
+static void check_sectors(const d3s_sectors* s, int nq, const char* name) {
+  D3S_REQUIRE(s && s->nsec >= 1 && s->q && s->dim, std::string(name) + ": null or empty sector list");
+  long tot = 0;
+  for (int i = 0; i < s->nsec; ++i) {
+    D3S_REQUIRE(s->dim[i] >= 1, std::string(name) + ": sector dimensions must be >= 1");
+    tot += s->dim[i];
+  }
+  D3S_REQUIRE(tot <= 1 << 20, std::string(name) + ": bond too large");
+  d3s::Sectors tmp(nq, s->nsec, s->q, s->dim);
+  D3S_REQUIRE((int)tmp.index.size() == s->nsec, std::string(name) + ": repeated charge");
+}
+
+d3s_status d3s_block_plan_create(d3s_ctx ctx, int nq, int d, int wl, int wr, const d3s_sectors* left,
+                                 const d3s_sectors* right, const int* phys_q, const int* wq_left,
+                                 const int* wq_right, d3s_block_plan* plan, double* flops, int* ntasks) {
+  return guarded(ctx, [&] {
+    D3S_REQUIRE(plan, "null plan pointer");
+    *plan = nullptr;
+    D3S_REQUIRE(nq == 1 || nq == 2, "nq must be 1 or 2");
+    D3S_REQUIRE(phys_q && wq_left && wq_right, "null charge array");
+    check_sectors(left, nq, "left");
+    check_sectors(right, nq, "right");
+    d3s_block_plan p = new d3s_block_plan_s();
+    p->left = d3s::Sectors(nq, left->nsec, left->q, left->dim);
+    p->right = d3s::Sectors(nq, right->nsec, right->q, right->dim);
+    try {
+      check_dims(p->left.total, d, p->right.total, wl, wr);
+      d3s::build_block_heff(&ctx->c, p->h, p->left, p->right, d, wl, wr, phys_q, wq_left, wq_right);
+    } catch (...) {
+      d3s::release_block_heff(p->h);
+      delete p;
+      throw;
+    }
+    if (flops) *flops = p->h.flops;
+    if (ntasks) *ntasks = p->h.g1.ntasks + p->h.g2.ntasks;
+    *plan = p;
+    return D3S_OK;
+  });
+}
+
+void d3s_block_plan_destroy(d3s_ctx ctx, d3s_block_plan plan) {
+  if (!plan) return;
+  if (ctx) (void)hipSetDevice(ctx->c.device);
+  d3s::release_block_heff(plan->h);
+  delete plan;
+}
+
+d3s_status d3s_apply_heff_blocks(d3s_ctx ctx, d3s_block_plan plan, d3s_prec prec, const void* L, const void* W,
+                                 const void* R, const void* psi, void* out, int use_graph) {
+  return guarded(ctx, [&] {
+    D3S_REQUIRE(plan, "null plan");
+    check_prec(prec);
+    D3S_REQUIRE(L && W && R && psi && out, "null tensor pointer");
+    D3S_REQUIRE(out != psi && out != L && out != R, "out must not alias an input");
+    d3s::op_apply_heff_blocks(&ctx->c, plan->h, prec, L, W, R, psi, out, use_graph != 0);
     return D3S_OK;
   });
 }

@@ -6,6 +6,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/dmrg3s.h"
@@ -78,6 +79,28 @@ void gemm_f32(Ctx* c, const GemmArgs& g);
 void gemm_bf16(Ctx* c, const GemmArgs& g);   // bf16 operands, fp32 C
 void gemm(Ctx* c, d3s_prec p, const GemmArgs& g);
 
+// ---------------------------------------------------------------- grouped GEMM
+// One output block per task, sum over the task's K-segments (see grouped.hip).
+struct GTask { int M, N, seg0, nseg, tile0; long c_off, ldc; };
+struct GSeg { int K; long a_off, lda, b_off, ldb; };
+struct GroupedPlan {
+  std::vector<GTask> tasks;
+  std::vector<GSeg> segs;
+  GTask* d_tasks = nullptr;     // device copies (owned by the plan)
+  GSeg* d_segs = nullptr;
+  int ntasks = 0, total_tiles = 0;
+  bool a_kc = true, b_kc = true;
+  int cfg = 1;                  // 0: 128x128 tiles, 1: 64x64 tiles
+  double flops = 0.0;
+};
+int grouped_tile(int cfg);
+// sort tasks largest-first, pick the tile size, compute tile prefix sums and
+// upload the tables (synchronises the stream)
+void grouped_finalize(Ctx* c, GroupedPlan& g);
+void grouped_release(GroupedPlan& g);
+void grouped_gemm(Ctx* c, d3s_prec p, const GroupedPlan& g, const void* A, const void* B, void* C,
+                  double alpha);
+
 // ---------------------------------------------------------------- kernels
 // W-map of a left-to-right contraction:
 //   T2[a, s, v, y] = alpha * sum_{w,t} W[w, v, s, t] * T1[a, w, t, y]
@@ -102,6 +125,7 @@ void scale_by_dev_f64(Ctx* c, double* x, long n, const double* s_dev, bool recip
 void axpby_f64(Ctx* c, double a, const double* x, double b, double* y, long n);
 void copy_f64(Ctx* c, const double* x, double* y, long n);
 void fill_f64(Ctx* c, double* x, long n, double v);
+void zero_bytes(Ctx* c, void* x, size_t bytes);   // kernel fill (safe inside graph capture)
 // out[r][col] = in[col][r] for an R x C input (row-major), i.e. out is C x R
 void transpose_f64(Ctx* c, const double* in, long R, long C, double* out);
 // copy a rows x cols block with leading dimensions
@@ -138,6 +162,36 @@ void op_heff_grad_W(Ctx* c, int ml, int d, int mr, int wl, int wr, const double*
 double op_prepare(Ctx* c, d3s_state* s, double eps);
 void op_sweep(Ctx* c, d3s_state* s, d3s_sweep_params* p, d3s_sweep_stats* st);
 void op_gradients(Ctx* c, d3s_state* s, double** grads);
+
+// ---------------------------------------------------------------- symmetry blocks
+// Charge sectors of one bond, states ordered by sector.
+struct Sectors {
+  int nq = 1, n = 0, total = 0;
+  std::vector<int> q, dim, off;
+  std::unordered_map<long, int> index;
+  Sectors() = default;
+  Sectors(int nq, int n, const int* q, const int* dim);
+  int find(const int* charge) const;   // -1 if the charge has no sector
+};
+
+// Grouped-GEMM plans of one block-sparse H_eff (and its captured graph).
+struct BlockHeff {
+  int ml = 0, mr = 0, d = 0, wl = 0, wr = 0;
+  GroupedPlan g1, g2;
+  double flops = 0.0;
+  void* graph = nullptr;
+  void* graph_exec = nullptr;
+  void* cap_stream = nullptr;
+  void* ev_in = nullptr;
+  void* ev_out = nullptr;
+  const void* graph_key[7] = {};
+  int graph_prec = -1;
+};
+void build_block_heff(Ctx* c, BlockHeff& h, const Sectors& left, const Sectors& right, int d, int wl, int wr,
+                      const int* phys_q, const int* wq_left, const int* wq_right);
+void release_block_heff(BlockHeff& h);
+void op_apply_heff_blocks(Ctx* c, BlockHeff& h, d3s_prec p, const void* L, const void* W, const void* R,
+                          const void* psi, void* out, bool use_graph);
 
 // host symmetric eigensolver (cyclic Jacobi) for small tridiagonal projections
 void jacobi_eigh(int n, std::vector<double>& A, std::vector<double>& evals,

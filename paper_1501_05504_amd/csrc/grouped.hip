@@ -1,0 +1,180 @@
+// Grouped MFMA GEMM over a task table: one launch computes every
+// symmetry-allowed block product of a block-sparse contraction.
+//
+// Each task owns an output block C[M x N] (at c_off, row stride ldc) and a
+// list of K-segments; a segment is one product A_s[M x K_s] * B_s[K_s x N]
+// (at a_off / b_off with its own leading dimensions).  The task's output is
+// alpha * sum over its segments, so contributions that land on the same
+// output block (the sum over the right MPO bond of the last H_eff
+// contraction, whose right-bond sectors differ from term to term) are
+// accumulated in registers, without atomics and in a fixed order.
+//
+// Workgroup b takes tile (b - tile0) of the task with the largest tile0 <= b
+// (binary search over the prefix sums).  Tasks are sorted largest-first by
+// the host so that long tiles start early.
+#include "mfma_tile.h"
+
+namespace d3s {
+namespace {
+
+using namespace tile;
+
+struct GParams {
+  const GTask* tasks;
+  const GSeg* segs;
+  int ntasks;
+  const void* A;
+  const void* B;
+  void* C;
+  double alpha;
+};
+
+template <typename S, int BM, int BN, int WM, int WN, bool AKC, bool BKC>
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64)
+void grouped_kernel(GParams p) {
+  typedef typename Acc<S>::T AT;
+  typedef typename Acc<S>::V AV;
+  constexpr int NT = (BM / WM) * (BN / WN) * 64;
+  constexpr int BK = 128 / (int)sizeof(S);
+  constexpr int LDK = BK + 16 / (int)sizeof(S);
+  constexpr int TM = WM / 16, TN = WN / 16;
+  constexpr int WGN = BN / WN;
+  __shared__ __align__(16) S sA[2][BM * LDK];
+  __shared__ __align__(16) S sB[2][BN * LDK];
+
+  const int bid = blockIdx.x;
+  int lo = 0, hi = p.ntasks - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (p.tasks[mid].tile0 <= bid) lo = mid;
+    else hi = mid - 1;
+  }
+  const GTask t = p.tasks[lo];
+  const int local = bid - t.tile0;
+  const int nTn = (t.N + BN - 1) / BN;
+  const int m0 = (local / nTn) * BM, n0 = (local % nTn) * BN;
+
+  const S* __restrict__ Ab = reinterpret_cast<const S*>(p.A);
+  const S* __restrict__ Bb = reinterpret_cast<const S*>(p.B);
+  AT* __restrict__ C = reinterpret_cast<AT*>(p.C) + t.c_off;
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wm = wave / WGN, wn = wave % WGN;
+  const int lrow = lane & 15, lgrp = lane >> 4;
+
+  AV acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = AV{0, 0, 0, 0};
+
+  Stager<S, BM, NT, AKC> ga;
+  Stager<S, BN, NT, BKC> gb;
+  const int send = t.seg0 + t.nseg;
+  // first non-empty segment
+  int cs = t.seg0, ck = 0;
+  while (cs < send && p.segs[cs].K <= 0) ++cs;
+  if (cs < send) {
+    const GSeg sg = p.segs[cs];
+    ga.load(Ab + sg.a_off, sg.lda, m0, t.M, 0, sg.K);
+    gb.load(Bb + sg.b_off, sg.ldb, n0, t.N, 0, sg.K);
+    ga.store(sA[0]);
+    gb.store(sB[0]);
+  }
+  __syncthreads();
+  int cur = 0;
+  while (cs < send) {
+    // the (segment, k-tile) after the current one
+    int ns = cs, nk = ck + 1;
+    if (nk * BK >= p.segs[cs].K) {
+      ns = cs + 1;
+      nk = 0;
+      while (ns < send && p.segs[ns].K <= 0) ++ns;
+    }
+    const bool more = ns < send;
+    if (more) {
+      const GSeg sg = p.segs[ns];
+      ga.load(Ab + sg.a_off, sg.lda, m0, t.M, nk * BK, sg.K);
+      gb.load(Bb + sg.b_off, sg.ldb, n0, t.N, nk * BK, sg.K);
+    }
+    Frag fa[TM], fb[TN];
+    const int koff = lgrp * (32 / (int)sizeof(S));
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const S* src = sA[cur] + (wm * WM + i * 16 + lrow) * LDK + koff;
+      fa[i].q[0] = *reinterpret_cast<const uint4*>(src);
+      fa[i].q[1] = *reinterpret_cast<const uint4*>(src + 16 / sizeof(S));
+    }
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const S* src = sB[cur] + (wn * WN + j * 16 + lrow) * LDK + koff;
+      fb[j].q[0] = *reinterpret_cast<const uint4*>(src);
+      fb[j].q[1] = *reinterpret_cast<const uint4*>(src + 16 / sizeof(S));
+    }
+#pragma unroll
+    for (int st = 0; st < kSteps<S>(); ++st)
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) mma_step<S>(acc[i][j], fa[i], fb[j], st);
+    if (more) {
+      ga.store(sA[cur ^ 1]);
+      gb.store(sB[cur ^ 1]);
+    }
+    __syncthreads();
+    cur ^= 1;
+    cs = ns;
+    ck = nk;
+  }
+
+  const AT alpha = (AT)p.alpha;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int col = n0 + wn * WN + j * 16 + lrow;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rr = (sizeof(S) == 8) ? (r * 4 + lgrp) : (lgrp * 4 + r);
+        const int row = m0 + wm * WM + i * 16 + rr;
+        if (row < t.M && col < t.N) C[(long)row * t.ldc + col] = alpha * acc[i][j][r];
+      }
+    }
+}
+
+template <typename S, int BM, int BN, int WM, int WN>
+void launch_grouped(Ctx* c, const GroupedPlan& g, const void* A, const void* B, void* C, double alpha) {
+  GParams p{g.d_tasks, g.d_segs, g.ntasks, A, B, C, alpha};
+  dim3 grid((unsigned)g.total_tiles), block((BM / WM) * (BN / WN) * 64);
+  if (g.a_kc && g.b_kc)
+    hipLaunchKernelGGL((grouped_kernel<S, BM, BN, WM, WN, true, true>), grid, block, 0, c->stream, p);
+  else if (g.a_kc && !g.b_kc)
+    hipLaunchKernelGGL((grouped_kernel<S, BM, BN, WM, WN, true, false>), grid, block, 0, c->stream, p);
+  else if (!g.a_kc && g.b_kc)
+    hipLaunchKernelGGL((grouped_kernel<S, BM, BN, WM, WN, false, true>), grid, block, 0, c->stream, p);
+  else
+    hipLaunchKernelGGL((grouped_kernel<S, BM, BN, WM, WN, false, false>), grid, block, 0, c->stream, p);
+  D3S_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+int grouped_tile(int cfg) { return cfg == 0 ? 128 : 64; }
+
+void grouped_gemm(Ctx* c, d3s_prec prec, const GroupedPlan& g, const void* A, const void* B, void* C,
+                  double alpha) {
+  if (g.ntasks <= 0 || g.total_tiles <= 0) return;
+  if (prec == D3S_F64) {
+    if (g.cfg == 0) launch_grouped<double, 128, 128, 64, 64>(c, g, A, B, C, alpha);
+    else launch_grouped<double, 64, 64, 32, 32>(c, g, A, B, C, alpha);
+  } else if (prec == D3S_F32) {
+    if (g.cfg == 0) launch_grouped<float, 128, 128, 64, 64>(c, g, A, B, C, alpha);
+    else launch_grouped<float, 64, 64, 32, 32>(c, g, A, B, C, alpha);
+  } else {
+    if (g.cfg == 0) launch_grouped<bf16_t, 128, 128, 64, 64>(c, g, A, B, C, alpha);
+    else launch_grouped<bf16_t, 64, 64, 32, 32>(c, g, A, B, C, alpha);
+  }
+}
+
+}  // namespace d3s

@@ -2,6 +2,8 @@
 // ordering of Sec. 5), deterministic FP64 reductions and vector updates of
 // the Lanczos solver, layout helpers of the truncation, casts of the
 // mixed-precision path and the reduction of the W-adjoint.
+#include <algorithm>
+
 #include "d3s_internal.h"
 
 namespace d3s {
@@ -232,6 +234,12 @@ __global__ void fill_kernel(double* __restrict__ x, long n, double v) {
     x[i] = v;
 }
 
+__global__ void zero_kernel(uint4* __restrict__ x, long n16, unsigned char* __restrict__ tail, int ntail) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (long)gridDim.x * blockDim.x)
+    x[i] = uint4{0, 0, 0, 0};
+  if (blockIdx.x == 0 && (int)threadIdx.x < ntail) tail[threadIdx.x] = 0;
+}
+
 __global__ void transpose_kernel(const double* __restrict__ in, long R, long C, double* __restrict__ out) {
   __shared__ double tile[32][33];
   const long r0 = (long)blockIdx.y * 32, c0 = (long)blockIdx.x * 32;
@@ -353,6 +361,16 @@ void copy_f64(Ctx* c, const double* x, double* y, long n) {
 
 void fill_f64(Ctx* c, double* x, long n, double v) {
   hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, x, n, v);
+  D3S_HIP(hipGetLastError());
+}
+
+void zero_bytes(Ctx* c, void* x, size_t bytes) {
+  if (bytes == 0) return;
+  if ((reinterpret_cast<uintptr_t>(x) & 15) != 0) throw Error{D3S_EINVAL, "zero_bytes: buffer not 16-byte aligned"};
+  const long n16 = (long)(bytes / 16);
+  const int ntail = (int)(bytes - (size_t)n16 * 16);
+  hipLaunchKernelGGL(zero_kernel, dim3(grid_for(std::max(n16, 1L))), dim3(kThreads), 0, c->stream, (uint4*)x, n16,
+                     (unsigned char*)x + n16 * 16, ntail);
   D3S_HIP(hipGetLastError());
 }
 

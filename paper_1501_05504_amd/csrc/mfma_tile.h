@@ -1,0 +1,113 @@
+// Building blocks shared by the MFMA GEMM kernels (plain and grouped):
+// fragment type, MFMA step per precision, LDS staging of operand tiles and
+// the XCD-aware tile order.  See gemm.hip for the design notes.
+#pragma once
+
+#include "d3s_internal.h"
+
+namespace d3s {
+namespace tile {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
+union Frag {
+  uint4 q[2];
+  double d[4];
+  float f[8];
+  bf8v h[2];
+};
+
+template <typename S> struct Acc;
+template <> struct Acc<double> { typedef double T; typedef d4v V; };
+template <> struct Acc<float> { typedef float T; typedef f4v V; };
+template <> struct Acc<bf16_t> { typedef float T; typedef f4v V; };
+
+template <typename S>
+__device__ __forceinline__ void mma_step(typename Acc<S>::V& c, const Frag& a, const Frag& b, int s) {
+  if constexpr (sizeof(S) == 8) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a.d[s], b.d[s], c, 0, 0, 0);
+  else if constexpr (sizeof(S) == 4) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.f[s], b.f[s], c, 0, 0, 0);
+  else c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h[s], b.h[s], c, 0, 0, 0);
+}
+
+// MFMA steps per 32-byte fragment: 4 (FP64), 8 (FP32), 2 (BF16)
+template <typename S> constexpr int kSteps() { return sizeof(S) == 8 ? 4 : (sizeof(S) == 4 ? 8 : 2); }
+
+
+__device__ __forceinline__ void tile_coords(int nTm, int nTn, int& tm, int& tn) {
+  const int nt = nTm * nTn;
+  int bid = blockIdx.x;
+  if ((nt & 7) == 0) bid = (bid & 7) * (nt >> 3) + (bid >> 3);
+  constexpr int G = 8;
+  const int per_group = G * nTn;
+  const int group = bid / per_group;
+  const int first = group * G;
+  const int gs = min(nTm - first, G);
+  const int in = bid - group * per_group;
+  tm = first + in % gs;
+  tn = in / gs;
+}
+
+// Stage one operand tile (O outer rows x BK k) from global into registers.
+// KC: X[o*ld + k];  !KC: X[k*ld + o].
+template <typename S, int O, int NT, bool KC>
+struct Stager {
+  static constexpr int BK = 128 / (int)sizeof(S);
+  static constexpr int VE = 16 / (int)sizeof(S);
+  static constexpr int LDK = BK + VE;              // LDS row: BK elements + 16-byte pad
+  static constexpr int CHUNKS = O * BK / VE;       // 16-byte chunks per tile
+  static constexpr int LPT = CHUNKS / NT;          // chunks per thread
+  static_assert(CHUNKS % NT == 0, "tile not divisible among threads");
+  uint4 r[LPT];
+
+  __device__ __forceinline__ void load(const S* __restrict__ X, long ld, int o0, int Odim, int k0, int K) {
+#pragma unroll
+    for (int p = 0; p < LPT; ++p) {
+      const int c = threadIdx.x + p * NT;
+      int o, k;
+      if constexpr (KC) { o = c / (BK / VE); k = (c % (BK / VE)) * VE; }
+      else { k = c / (O / VE); o = (c % (O / VE)) * VE; }
+      const int go = o0 + o, gk = k0 + k;
+      union { uint4 q; S e[VE]; } u;
+      if constexpr (KC) {
+        const S* src = X + (long)go * ld + gk;
+        if (go < Odim && gk + VE <= K && ((reinterpret_cast<uintptr_t>(src) & 15) == 0)) {
+          u.q = *reinterpret_cast<const uint4*>(src);
+        } else {
+#pragma unroll
+          for (int v = 0; v < VE; ++v) u.e[v] = (go < Odim && gk + v < K) ? src[v] : S(0);
+        }
+      } else {
+        const S* src = X + (long)gk * ld + go;
+        if (gk < K && go + VE <= Odim && ((reinterpret_cast<uintptr_t>(src) & 15) == 0)) {
+          u.q = *reinterpret_cast<const uint4*>(src);
+        } else {
+#pragma unroll
+          for (int v = 0; v < VE; ++v) u.e[v] = (gk < K && go + v < Odim) ? src[v] : S(0);
+        }
+      }
+      r[p] = u.q;
+    }
+  }
+
+  __device__ __forceinline__ void store(S* __restrict__ s) const {
+#pragma unroll
+    for (int p = 0; p < LPT; ++p) {
+      const int c = threadIdx.x + p * NT;
+      if constexpr (KC) {
+        const int o = c / (BK / VE), k = (c % (BK / VE)) * VE;
+        *reinterpret_cast<uint4*>(s + o * LDK + k) = r[p];
+      } else {
+        const int k = c / (O / VE), o = (c % (O / VE)) * VE;
+        union { uint4 q; S e[VE]; } u;
+        u.q = r[p];
+#pragma unroll
+        for (int v = 0; v < VE; ++v) s[(o + v) * LDK + k] = u.e[v];
+      }
+    }
+  }
+};
+
+}  // namespace tile
+}  // namespace d3s

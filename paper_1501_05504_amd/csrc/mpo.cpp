@@ -161,4 +161,32 @@ d3s_status d3s_mpo_fermion_hopping(int l, int range, const double* t, double U, 
                out, offsets, dims, total);
 }
 
+/* Channel charges Delta of the MPO bond channels in the builders' channel
+ * order (0 = identity before, 1 + k*range + r - 1 = kind k placed r sites
+ * before, last = complete).  Spin kinds S+, S-, Sz carry 2Sz = +2, -2, 0
+ * (nq = 1); fermion kinds c+_up F, c+_dn F, F c_up, F c_dn carry
+ * (N, 2Sz) = (1, 1), (1, -1), (-1, -1), (-1, 1) (nq = 2). */
+d3s_status d3s_mpo_spin_charges(int range, int* out) {
+  if (range < 1 || !out) return D3S_EINVAL;
+  const int kinds[3] = {2, -2, 0};
+  const int w = 2 + 3 * range;
+  for (int c = 0; c < w; ++c) out[c] = 0;
+  for (int k = 0; k < 3; ++k)
+    for (int r = 1; r <= range; ++r) out[1 + k * range + r - 1] = kinds[k];
+  return D3S_OK;
+}
+
+d3s_status d3s_mpo_fermion_charges(int range, int* out) {
+  if (range < 1 || !out) return D3S_EINVAL;
+  const int kinds[4][2] = {{1, 1}, {1, -1}, {-1, -1}, {-1, 1}};
+  const int w = 2 + 4 * range;
+  for (int c = 0; c < 2 * w; ++c) out[c] = 0;
+  for (int k = 0; k < 4; ++k)
+    for (int r = 1; r <= range; ++r) {
+      out[2 * (1 + k * range + r - 1)] = kinds[k][0];
+      out[2 * (1 + k * range + r - 1) + 1] = kinds[k][1];
+    }
+  return D3S_OK;
+}
+
 }  // extern "C"

@@ -47,3 +47,45 @@ def env_sites_for(m, d):
     while d ** k < m:
         k += 1
     return k
+
+
+# --- block structure of symmetric workloads ---------------------------------
+# Index bookkeeping only: which entries a charge-conserving tensor may hold.
+
+def gaussian_sectors(center, sigma, m, span, parity=True):
+    """(N, 2Sz) sectors around `center` with dimensions proportional to
+    exp(-(N-N0)^2 / 2 sN^2 - (2Sz-S0)^2 / 2 sS^2), normalised to m (largest
+    remainder rounding, empty sectors dropped).  parity: 2Sz = N mod 2."""
+    N0, S0 = center
+    sN, sS = sigma
+    qs, ws = [], []
+    for N in range(N0 - span[0], N0 + span[0] + 1):
+        for S in range(S0 - span[1], S0 + span[1] + 1):
+            if parity and (N - S) % 2:
+                continue
+            qs.append((N, S))
+            ws.append(np.exp(-(N - N0) ** 2 / (2 * sN ** 2) - (S - S0) ** 2 / (2 * sS ** 2)))
+    ws = np.array(ws) / np.sum(ws) * m
+    dims = np.floor(ws).astype(int)
+    rem = m - dims.sum()
+    for i in np.argsort(-(ws - dims))[:rem]:
+        dims[i] += 1
+    keep = dims > 0
+    return np.array(qs)[keep], dims[keep]
+
+
+def expand_charges(q, dims):
+    """Charge of every basis state of a bond (states ordered by sector)."""
+    return np.repeat(np.asarray(q), np.asarray(dims), axis=0)
+
+
+def mask_site(ql, qphys, qr):
+    """psi[a,s,b] may be nonzero iff q_a + q_s = q_b."""
+    ql, qphys, qr = (np.asarray(x) for x in (ql, qphys, qr))
+    return np.all(ql[:, None, None, :] + qphys[None, :, None, :] == qr[None, None, :, :], axis=-1)
+
+
+def mask_env(q, wq):
+    """L[a,w,x] may be nonzero iff q_a - q_x = Delta_w."""
+    q, wq = np.asarray(q), np.asarray(wq)
+    return np.all(q[:, None, None, :] - q[None, None, :, :] == wq[None, :, None, :], axis=-1)
