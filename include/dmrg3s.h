@@ -232,6 +232,25 @@ void d3s_block_plan_destroy(d3s_ctx ctx, d3s_block_plan plan);
 d3s_status d3s_apply_heff_blocks(d3s_ctx ctx, d3s_block_plan plan, d3s_prec prec, const void* L,
                                  const void* W, const void* R, const void* psi, void* out, int use_graph);
 
+/* Charges of a symmetric chain for the block-sparse sweep (host arrays,
+ * owned by the caller).  Bond b (0..l) currently has nsec[b] sectors with
+ * charges sec_q[b][0..nsec[b]*nq) and dimensions sec_dim[b][0..nsec[b]),
+ * states ordered by sector; the arrays hold up to maxsec sectors and are
+ * updated in place by d3s_prepare_blocks / d3s_sweep_blocks.  The sum of the
+ * dims of bond b must equal the state's m[b].  mpo_q[b] holds the w[b]*nq
+ * channel charges of MPO bond b (e.g. from d3s_mpo_fermion_charges; the
+ * boundary bonds have one channel of charge 0).  Bond l carries the target
+ * charge (the total quantum number of the state). */
+typedef struct {
+  int nq;
+  const int* phys_q;
+  const int* const* mpo_q;
+  int maxsec;
+  int* nsec;
+  int* const* sec_q;
+  int* const* sec_dim;
+} d3s_symmetry;
+
 /* ---------------------------------------------------------------- sweeps */
 
 /* A finite MPS with its MPO and environments, all FP64 device buffers owned
@@ -307,6 +326,20 @@ d3s_status d3s_sweep(d3s_ctx ctx, d3s_state* state, d3s_sweep_params* params,
  * truncations, which leave the state unchanged, and rebuilds renv on the way.
  * Synchronises. */
 d3s_status d3s_energy_gradients(d3s_ctx ctx, d3s_state* state, double** grads);
+
+/* Block-sparse (U(1) / U(1)xU(1)) twins of d3s_prepare / d3s_sweep.  The
+ * site tensors are first projected onto the symmetric subspace defined by
+ * the bond sectors in `sym` (entries violating q_a + q_s = q_b are zeroed),
+ * then treated exactly as by the dense calls, except that (i) the Lanczos
+ * products are block-sparse grouped launches (d3s_apply_heff_blocks),
+ * replayed from a hipGraph per site when use_graph != 0, and (ii) the
+ * truncation is block-diagonal: one FP64 Gram matrix and one batched
+ * rocSOLVER eigensolve per charge sector of the truncated bond, the kept
+ * states chosen globally by singular value.  The bond sectors are updated
+ * in `sym` after every truncation.  Synchronise. */
+d3s_status d3s_prepare_blocks(d3s_ctx ctx, d3s_state* state, d3s_symmetry* sym, double* energy);
+d3s_status d3s_sweep_blocks(d3s_ctx ctx, d3s_state* state, d3s_symmetry* sym, d3s_sweep_params* params,
+                            d3s_sweep_stats* stats, int use_graph);
 
 /* ---------------------------------------------------------------- models */
 /* MPO builders (host arrays, FP64, layout W[w,v,s,t], one block per site,

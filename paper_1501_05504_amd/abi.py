@@ -110,6 +110,18 @@ _spin_charges = _sig("d3s_mpo_spin_charges", c_int, [c_int, c_int_p])
 _fermion_charges = _sig("d3s_mpo_fermion_charges", c_int, [c_int, c_int_p])
 
 
+class d3s_symmetry(ctypes.Structure):
+    _fields_ = [("nq", c_int), ("phys_q", c_int_p), ("mpo_q", ctypes.POINTER(c_int_p)), ("maxsec", c_int),
+                ("nsec", c_int_p), ("sec_q", ctypes.POINTER(c_int_p)), ("sec_dim", ctypes.POINTER(c_int_p))]
+
+
+_prepare_blocks = _sig("d3s_prepare_blocks", c_int, [c_void_p, ctypes.POINTER(d3s_state),
+                                                     ctypes.POINTER(d3s_symmetry), c_double_p])
+_sweep_blocks = _sig("d3s_sweep_blocks", c_int, [c_void_p, ctypes.POINTER(d3s_state), ctypes.POINTER(d3s_symmetry),
+                                                 ctypes.POINTER(d3s_sweep_params), ctypes.POINTER(d3s_sweep_stats),
+                                                 c_int])
+
+
 class D3SError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__("dmrg3s status %d: %s" % (status, msg))
@@ -327,6 +339,23 @@ class Context:
         state.pull_dims()
         return grads
 
+    def prepare_blocks(self, state, sym):
+        self._sync_stream()
+        e = c_double()
+        self._check(_prepare_blocks(self.h, ctypes.byref(state.c), ctypes.byref(sym.c), ctypes.byref(e)))
+        state.pull_dims()
+        return e.value
+
+    def sweep_blocks(self, state, sym, params, use_graph=True):
+        self._sync_stream()
+        cap = 2 * state.l
+        recs = (d3s_site_record * cap)()
+        stats = d3s_sweep_stats(cap, 0, recs, 0.0, 0.0, 0)
+        st = self._check(_sweep_blocks(self.h, ctypes.byref(state.c), ctypes.byref(sym.c), ctypes.byref(params),
+                                       ctypes.byref(stats), 1 if use_graph else 0), warn_ok=True)
+        state.pull_dims()
+        return st, stats, [recs[i] for i in range(min(stats.count, cap))]
+
     def sweep(self, state, params):
         """One full sweep; returns (status, stats, records)."""
         self._sync_stream()
@@ -389,6 +418,55 @@ class State:
 
     def tensors(self):
         return [self.site_tensor(i) for i in range(self.l)]
+
+
+class Symmetry:
+    """Charges of a symmetric chain (d3s_symmetry): physical charges, MPO
+    channel charges per MPO bond and the current sectors of every MPS bond."""
+
+    def __init__(self, phys_q, mpo_channel_q, sectors, maxsec=4096):
+        import numpy as np
+        phys = np.ascontiguousarray(np.asarray(phys_q, dtype=np.int32))
+        self.nq = phys.shape[1]
+        self.l = len(sectors) - 1
+        self.maxsec = maxsec
+        self._phys = phys
+        self._mpo = [np.ascontiguousarray(np.asarray(q, dtype=np.int32).reshape(-1, self.nq))
+                     for q in mpo_channel_q]
+        self._secq = [np.zeros(maxsec * self.nq, dtype=np.int32) for _ in sectors]
+        self._secd = [np.zeros(maxsec, dtype=np.int32) for _ in sectors]
+        self._nsec = (c_int * (self.l + 1))()
+        for b, (q, dm) in enumerate(sectors):
+            q = np.asarray(q, dtype=np.int32).reshape(-1, self.nq)
+            n = len(dm)
+            if n > maxsec:
+                raise ValueError("more sectors than maxsec")
+            self._secq[b][: n * self.nq] = q.ravel()
+            self._secd[b][:n] = dm
+            self._nsec[b] = n
+        self._mpo_p = (c_int_p * (self.l + 1))(*[a.ctypes.data_as(c_int_p) for a in self._mpo])
+        self._secq_p = (c_int_p * (self.l + 1))(*[a.ctypes.data_as(c_int_p) for a in self._secq])
+        self._secd_p = (c_int_p * (self.l + 1))(*[a.ctypes.data_as(c_int_p) for a in self._secd])
+        self.c = d3s_symmetry(self.nq, self._phys.ctypes.data_as(c_int_p), self._mpo_p, maxsec, self._nsec,
+                              self._secq_p, self._secd_p)
+
+    def sectors(self, b):
+        n = self._nsec[b]
+        return self._secq[b][: n * self.nq].reshape(n, self.nq).copy(), self._secd[b][:n].copy()
+
+
+def mpo_bond_charges(mpo_blocks, channel_q):
+    """Channel charges of every MPO bond of a chain built by the builders
+    above: the bulk bonds carry `channel_q`; the boundary bonds have one
+    channel of charge 0."""
+    import numpy as np
+    nq = np.asarray(channel_q).shape[1]
+    l = len(mpo_blocks)
+    out = [np.zeros((1, nq), dtype=np.int32)]
+    for i in range(1, l):
+        out.append(np.asarray(channel_q, dtype=np.int32))
+    out.append(np.zeros((1, nq), dtype=np.int32))
+    return out
 
 
 def sweep_params(alpha=1e-3, adaptive=True, eps=1e-14, tol=1e-12, kmax=40, max_matvecs=2000, prec=F64,

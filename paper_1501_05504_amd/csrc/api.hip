@@ -2,6 +2,7 @@
 // operations of ops.hip / sweep.hip.  No exception crosses this boundary.
 #include <rocblas/rocblas.h>
 
+#include <algorithm>
 #include <cmath>
 #include <new>
 
@@ -369,6 +370,82 @@ d3s_status d3s_apply_heff_blocks(d3s_ctx ctx, d3s_block_plan plan, d3s_prec prec
     D3S_REQUIRE(out != psi && out != L && out != R, "out must not alias an input");
     d3s::op_apply_heff_blocks(&ctx->c, plan->h, prec, L, W, R, psi, out, use_graph != 0);
     return D3S_OK;
+  });
+}
+
+static d3s::SymChain read_sym(const d3s_state* s, const d3s_symmetry* y) {
+  D3S_REQUIRE(y && (y->nq == 1 || y->nq == 2), "symmetry: nq must be 1 or 2");
+  D3S_REQUIRE(y->phys_q && y->mpo_q && y->nsec && y->sec_q && y->sec_dim && y->maxsec >= 1,
+              "symmetry: null array");
+  d3s::SymChain c;
+  c.nq = y->nq;
+  c.phys.assign(y->phys_q, y->phys_q + (size_t)s->d * y->nq);
+  for (int b = 0; b <= s->l; ++b) {
+    D3S_REQUIRE(y->mpo_q[b] && y->sec_q[b] && y->sec_dim[b], "symmetry: null per-bond array");
+    c.wq.emplace_back(y->mpo_q[b], y->mpo_q[b] + (size_t)s->w[b] * y->nq);
+    D3S_REQUIRE(y->nsec[b] >= 1 && y->nsec[b] <= y->maxsec, "symmetry: sector count out of range");
+    long tot = 0;
+    for (int i = 0; i < y->nsec[b]; ++i) {
+      D3S_REQUIRE(y->sec_dim[b][i] >= 1, "symmetry: sector dimension must be >= 1");
+      tot += y->sec_dim[b][i];
+    }
+    D3S_REQUIRE(tot == s->m[b], "symmetry: sector dimensions of bond " + std::to_string(b) + " do not add up to m");
+    c.bonds.emplace_back(y->nq, y->nsec[b], y->sec_q[b], y->sec_dim[b]);
+    D3S_REQUIRE((int)c.bonds.back().index.size() == y->nsec[b], "symmetry: repeated charge on a bond");
+  }
+  return c;
+}
+
+static void write_sym(const d3s::SymChain& c, d3s_symmetry* y) {
+  for (size_t b = 0; b < c.bonds.size(); ++b) {
+    const d3s::Sectors& s = c.bonds[b];
+    const int n = std::min(s.n, y->maxsec);
+    y->nsec[b] = n;
+    for (int i = 0; i < n; ++i) {
+      y->sec_dim[b][i] = s.dim[i];
+      for (int k = 0; k < c.nq; ++k) y->sec_q[b][i * c.nq + k] = s.q[(size_t)i * c.nq + k];
+    }
+  }
+}
+
+static void check_sym_capacity(const d3s::SymChain& c, const d3s_symmetry* y) {
+  for (const d3s::Sectors& s : c.bonds)
+    D3S_REQUIRE(s.n <= y->maxsec, "symmetry: more sectors than maxsec");
+}
+
+d3s_status d3s_prepare_blocks(d3s_ctx ctx, d3s_state* state, d3s_symmetry* sym, double* energy) {
+  return guarded(ctx, [&] {
+    check_state(state);
+    D3S_REQUIRE(energy, "null energy pointer");
+    d3s::SymChain c = read_sym(state, sym);
+    *energy = d3s::op_prepare_blocks(&ctx->c, state, c, 1e-14);
+    check_sym_capacity(c, sym);
+    write_sym(c, sym);
+    return D3S_OK;
+  });
+}
+
+d3s_status d3s_sweep_blocks(d3s_ctx ctx, d3s_state* state, d3s_symmetry* sym, d3s_sweep_params* params,
+                            d3s_sweep_stats* stats, int use_graph) {
+  return guarded(ctx, [&] {
+    check_state(state);
+    D3S_REQUIRE(params && stats, "null params or stats");
+    D3S_REQUIRE(stats->records || stats->capacity == 0, "stats: null records with capacity > 0");
+    check_prec(params->prec);
+    D3S_REQUIRE(params->lanczos_kmax >= 2 && params->lanczos_kmax <= 120, "lanczos_kmax must be in [2, 120]");
+    D3S_REQUIRE(params->lanczos_tol > 0.0 && params->lanczos_max_matvecs >= 1, "bad eigensolver limits");
+    D3S_REQUIRE(params->alpha >= 0.0 && std::isfinite(params->alpha), "alpha must be finite and >= 0");
+    d3s::SymChain c = read_sym(state, sym);
+    try {
+      d3s::op_sweep_blocks(&ctx->c, state, c, params, stats, use_graph != 0);
+    } catch (...) {
+      if ([&] { for (auto& s : c.bonds) if (s.n > sym->maxsec) return false; return true; }()) write_sym(c, sym);
+      throw;
+    }
+    check_sym_capacity(c, sym);
+    write_sym(c, sym);
+    if (!std::isfinite(stats->energy)) throw Error{D3S_ENUMERIC, "sweep: non-finite energy"};
+    return stats->nonconverged ? D3S_ENOCONV : D3S_OK;
   });
 }
 

@@ -20,6 +20,9 @@
 // Tasks are the "uneven blocks" of a symmetric DMRG; all of them go into one
 // grouped launch per contraction.
 #include <algorithm>
+#include <cfloat>
+#include <chrono>
+#include <cmath>
 #include <unordered_map>
 
 #include "d3s_internal.h"
@@ -179,7 +182,7 @@ void build_block_heff(Ctx* c, BlockHeff& h, const Sectors& left, const Sectors& 
     }
   grouped_finalize(c, h.g1);
   grouped_finalize(c, h.g2);
-  // the dense W-map is part of the work; count its flops over the allowed T1 rows only
+  // flops of the allowed block products of the two GEMMs (the W-map, dense, is not counted)
   h.flops = h.g1.flops + h.g2.flops;
 }
 
@@ -263,6 +266,449 @@ void op_apply_heff_blocks(Ctx* c, BlockHeff& h, d3s_prec p, const void* L, const
   D3S_HIP(hipGraphLaunch((hipGraphExec_t)h.graph_exec, cs));
   D3S_HIP(hipEventRecord((hipEvent_t)h.ev_out, cs));
   D3S_HIP(hipStreamWaitEvent(c->stream, (hipEvent_t)h.ev_out, 0));
+}
+
+}  // namespace d3s
+
+// ============================================================ block sweeps
+namespace d3s {
+
+int charge_lkey(const int* q, int nq) { return nq == 1 ? q[0] : q[0] * 32768 + q[1]; }
+
+namespace {
+
+struct RowGroup { long start, stride; int count, local; };
+struct ColGroup { long start; int count, local; };
+struct SecGroup {
+  std::vector<int> q;
+  std::vector<RowGroup> rows;
+  std::vector<ColGroup> cols;
+  int nrows = 0, ncols = 0;
+  long xoff = 0;          // offset of the packed X_Q
+  int npad = 0, bucket = -1, idx = 0;
+  long goff = 0;          // offset of G_Q in the packed Gram buffer
+  int keep = 0, new_off = 0;
+};
+
+int next_pow2(int n) {
+  int p = 8;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+long budget_of(int l, int d, int mmax, int b) {
+  long cap = mmax, left = 1, right = 1;
+  for (int i = 0; i < b && left < cap; ++i) left *= d;
+  for (int i = 0; i < l - b && right < cap; ++i) right *= d;
+  return std::min(cap, std::min(left, right));
+}
+
+}  // namespace
+
+TruncBlocksResult op_truncate_blocks(Ctx* c, d3s_dir dir, const Sectors& left, const Sectors& right, int d,
+                                     const int* pq, const int* wq_exp, int wexp, long width, const double* Mt,
+                                     const double* psi, int kmax, double eps, const double* nbr, long nbr_other,
+                                     double* site_out, double* nbr_out, bool renormalize) {
+  const int nq = left.nq;
+  const int ml = left.total, mr = right.total;
+  const long n = (dir == D3S_L2R) ? (long)ml * d : (long)d * mr;     // Gram side
+  const long rowlen = (dir == D3S_L2R) ? width : (long)d * mr;
+  // ---- sector groups of the truncated bond
+  std::vector<SecGroup> groups;
+  std::unordered_map<long, int> gidx;
+  std::vector<int> qq(nq);
+  auto group_of = [&](const int* q) -> SecGroup& {
+    long key = 0;
+    for (int k = 0; k < nq; ++k) key = key * 2097152L + (q[k] + 1048576);
+    auto it = gidx.find(key);
+    if (it != gidx.end()) return groups[it->second];
+    gidx[key] = (int)groups.size();
+    groups.emplace_back();
+    groups.back().q.assign(q, q + nq);
+    return groups.back();
+  };
+  if (dir == D3S_L2R) {
+    for (int i = 0; i < left.n; ++i)
+      for (int s = 0; s < d; ++s) {
+        for (int k = 0; k < nq; ++k) qq[k] = left.q[(size_t)i * nq + k] + pq[s * nq + k];
+        SecGroup& g = group_of(qq.data());
+        g.rows.push_back({(long)left.off[i] * d + s, (long)d, left.dim[i], g.nrows});
+        g.nrows += left.dim[i];
+      }
+    for (SecGroup& g : groups) {
+      const int j = right.find(g.q.data());
+      if (j >= 0) {
+        g.cols.push_back({(long)right.off[j], right.dim[j], g.ncols});
+        g.ncols += right.dim[j];
+      }
+      for (int v = 0; v < wexp; ++v) {
+        for (int k = 0; k < nq; ++k) qq[k] = g.q[k] - wq_exp[v * nq + k];
+        const int jv = right.find(qq.data());
+        if (jv < 0) continue;
+        g.cols.push_back({(long)mr + (long)v * mr + right.off[jv], right.dim[jv], g.ncols});
+        g.ncols += right.dim[jv];
+      }
+    }
+  } else {
+    for (int j = 0; j < right.n; ++j)
+      for (int s = 0; s < d; ++s) {
+        for (int k = 0; k < nq; ++k) qq[k] = right.q[(size_t)j * nq + k] - pq[s * nq + k];
+        SecGroup& g = group_of(qq.data());
+        g.cols.push_back({(long)s * mr + right.off[j], right.dim[j], g.ncols});
+        g.ncols += right.dim[j];
+      }
+    for (SecGroup& g : groups) {
+      const int i = left.find(g.q.data());
+      if (i >= 0) {
+        g.rows.push_back({(long)left.off[i], 1L, left.dim[i], g.nrows});
+        g.nrows += left.dim[i];
+      }
+      for (int w = 0; w < wexp; ++w) {
+        for (int k = 0; k < nq; ++k) qq[k] = g.q[k] - wq_exp[w * nq + k];
+        const int iw = left.find(qq.data());
+        if (iw < 0) continue;
+        g.rows.push_back({(long)ml + (long)w * ml + left.off[iw], 1L, left.dim[iw], g.nrows});
+        g.nrows += left.dim[iw];
+      }
+    }
+  }
+  // drop groups without entries; Gram dimension per group
+  std::vector<SecGroup> gs;
+  for (SecGroup& g : groups)
+    if (g.nrows > 0 && g.ncols > 0) gs.push_back(std::move(g));
+  if (gs.empty()) throw Error{D3S_ENUMERIC, "truncate: the expanded tensor has no symmetry-allowed block"};
+  // ---- pack X_Q and plan the Gram products
+  long xtot = 0;
+  std::vector<CopyDesc> gather;
+  for (SecGroup& g : gs) {
+    g.xoff = xtot;
+    xtot += (long)g.nrows * g.ncols;
+    for (const RowGroup& rg : g.rows)
+      for (const ColGroup& cg : g.cols)
+        gather.push_back(CopyDesc{rg.start * rowlen + cg.start, rg.stride * rowlen, 1, g.xoff + (long)rg.local * g.ncols + cg.local,
+                                  (long)g.ncols, 1, rg.count, cg.count});
+  }
+  double* X = (double*)ws_get(c, WS_XPACK, sizeof(double) * (size_t)xtot);
+  copy_blocks(c, Mt, X, gather);
+  // buckets of equal padded size
+  std::vector<int> bucket_n;
+  std::vector<std::vector<int>> bucket_members;
+  for (int gi = 0; gi < (int)gs.size(); ++gi) {
+    SecGroup& g = gs[gi];
+    const int ng = (dir == D3S_L2R) ? g.nrows : g.ncols;
+    g.npad = next_pow2(ng);
+    int b = -1;
+    for (int k = 0; k < (int)bucket_n.size(); ++k)
+      if (bucket_n[k] == g.npad) b = k;
+    if (b < 0) {
+      b = (int)bucket_n.size();
+      bucket_n.push_back(g.npad);
+      bucket_members.emplace_back();
+    }
+    g.bucket = b;
+    g.idx = (int)bucket_members[b].size();
+    bucket_members[b].push_back(gi);
+  }
+  std::vector<long> bucket_goff(bucket_n.size()), bucket_voff(bucket_n.size());
+  long gtot = 0, vtot = 0;
+  for (size_t b = 0; b < bucket_n.size(); ++b) {
+    bucket_goff[b] = gtot;
+    bucket_voff[b] = vtot;
+    gtot += (long)bucket_members[b].size() * bucket_n[b] * bucket_n[b];
+    vtot += (long)bucket_members[b].size() * bucket_n[b];
+  }
+  double* G = (double*)ws_get(c, WS_GPACK, sizeof(double) * (size_t)gtot);
+  zero_bytes(c, G, sizeof(double) * (size_t)gtot);
+  GroupedPlan gp;
+  gp.a_kc = (dir == D3S_L2R);
+  gp.b_kc = (dir == D3S_L2R);
+  for (SecGroup& g : gs) {
+    g.goff = bucket_goff[g.bucket] + (long)g.idx * g.npad * g.npad;
+    GTask t;
+    GSeg sg;
+    if (dir == D3S_L2R) {    // X X^T over rows
+      t.M = t.N = g.nrows;
+      sg.K = g.ncols;
+      sg.a_off = g.xoff; sg.lda = g.ncols;
+      sg.b_off = g.xoff; sg.ldb = g.ncols;
+    } else {                 // X^T X over columns
+      t.M = t.N = g.ncols;
+      sg.K = g.nrows;
+      sg.a_off = g.xoff; sg.lda = g.ncols;
+      sg.b_off = g.xoff; sg.ldb = g.ncols;
+    }
+    t.seg0 = (int)gp.segs.size();
+    t.nseg = 1;
+    t.tile0 = 0;
+    t.c_off = g.goff;
+    t.ldc = g.npad;
+    gp.segs.push_back(sg);
+    gp.tasks.push_back(t);
+  }
+  grouped_finalize(c, gp);
+  grouped_gemm(c, D3S_F64, gp, X, X, G, 1.0);
+  grouped_release(gp);
+  double* V = (double*)ws_get(c, WS_GVAL, sizeof(double) * (size_t)vtot);
+  for (size_t b = 0; b < bucket_n.size(); ++b)
+    syevd_batched_f64(c, bucket_n[b], (int)bucket_members[b].size(), G + bucket_goff[b], V + bucket_voff[b]);
+  std::vector<double> ev(vtot);
+  D3S_HIP(hipMemcpyAsync(ev.data(), V, sizeof(double) * (size_t)vtot, hipMemcpyDeviceToHost, c->stream));
+  D3S_HIP(hipStreamSynchronize(c->stream));
+  // ---- global selection of the kept states
+  struct Cand { double lam; int g, rank; };
+  std::vector<Cand> cand;
+  double total = 0.0, s0 = 0.0;
+  long nsum = 0;
+  for (int gi = 0; gi < (int)gs.size(); ++gi) {
+    const SecGroup& g = gs[gi];
+    const int ng = (dir == D3S_L2R) ? g.nrows : g.ncols;
+    nsum += ng;
+    const double* e = ev.data() + bucket_voff[g.bucket] + (long)g.idx * g.npad;
+    for (int r = 0; r < ng; ++r) {
+      const double lam = std::max(e[g.npad - 1 - r], 0.0);
+      total += lam;
+      s0 = std::max(s0, lam);
+      cand.push_back({lam, gi, r});
+    }
+  }
+  if (!(s0 > 0.0) || !std::isfinite(total))
+    throw Error{D3S_ENUMERIC, "truncate: the expanded tensor is zero or not finite"};
+  const double floor2 = std::max(eps * eps, (double)nsum * DBL_EPSILON) * s0;
+  std::stable_sort(cand.begin(), cand.end(), [](const Cand& a, const Cand& b) { return a.lam > b.lam; });
+  int k = 0;
+  double kept = 0.0;
+  for (const Cand& cd : cand) {
+    if (k >= kmax || !(cd.lam > floor2)) break;
+    gs[cd.g].keep++;
+    kept += cd.lam;
+    ++k;
+  }
+  // ---- new bond sectors (ordered by charge key)
+  std::vector<int> order;
+  for (int gi = 0; gi < (int)gs.size(); ++gi)
+    if (gs[gi].keep > 0) order.push_back(gi);
+  std::sort(order.begin(), order.end(), [&](int a, int b) {
+    return charge_lkey(gs[a].q.data(), nq) < charge_lkey(gs[b].q.data(), nq);
+  });
+  TruncBlocksResult res;
+  res.k = k;
+  res.total = total;
+  res.discarded = std::max(0.0, total - kept);
+  int off = 0;
+  for (int gi : order) {
+    gs[gi].new_off = off;
+    off += gs[gi].keep;
+    res.q.insert(res.q.end(), gs[gi].q.begin(), gs[gi].q.end());
+    res.dim.push_back(gs[gi].keep);
+  }
+  // ---- the new site tensor from the kept eigenvectors (rank r <-> column npad-1-r)
+  std::vector<CopyDesc> scatter;
+  if (dir == D3S_L2R) {
+    zero_bytes(c, site_out, sizeof(double) * (size_t)n * k);
+    for (int gi : order) {
+      const SecGroup& g = gs[gi];
+      for (const RowGroup& rg : g.rows)
+        scatter.push_back(CopyDesc{g.goff + (long)(g.npad - 1) * g.npad + rg.local, 1, -(long)g.npad,
+                                   rg.start * k + g.new_off, rg.stride * k, 1, rg.count, g.keep});
+    }
+  } else {
+    zero_bytes(c, site_out, sizeof(double) * (size_t)k * n);
+    for (int gi : order) {
+      const SecGroup& g = gs[gi];
+      for (const ColGroup& cg : g.cols)
+        scatter.push_back(CopyDesc{g.goff + (long)(g.npad - 1) * g.npad + cg.local, -(long)g.npad, 1,
+                                   (long)g.new_off * n + cg.start, n, 1, g.keep, cg.count});
+    }
+  }
+  copy_blocks(c, G, site_out, scatter);
+  // ---- neighbour: the dense products on the structured layout
+  if (dir == D3S_L2R) {
+    double* Xn = (double*)ws_get(c, WS_X, sizeof(double) * (size_t)k * mr);
+    GemmArgs g1{k, mr, (int)n, site_out, k, false, 0, psi, mr, false, 0, Xn, mr, 0, 1.0, 0.0, 1};
+    gemm_f64(c, g1);
+    GemmArgs g2{k, (int)nbr_other, mr, Xn, mr, true, 0, nbr, nbr_other, false, 0, nbr_out, nbr_other, 0, 1.0, 0.0, 1};
+    gemm_f64(c, g2);
+  } else {
+    double* Xn = (double*)ws_get(c, WS_X, sizeof(double) * (size_t)ml * k);
+    GemmArgs g1{ml, k, (int)n, psi, n, true, 0, site_out, n, true, 0, Xn, k, 0, 1.0, 0.0, 1};
+    gemm_f64(c, g1);
+    GemmArgs g2{(int)nbr_other, k, ml, nbr, ml, true, 0, Xn, k, false, 0, nbr_out, k, 0, 1.0, 0.0, 1};
+    gemm_f64(c, g2);
+  }
+  if (renormalize) {
+    const long nn = (long)k * nbr_other;
+    double* r = (double*)ws_get(c, WS_LZ_COEF, sizeof(double) * 512);
+    dot_f64(c, nbr_out, nbr_out, nn, r);
+    const double nrm2 = read_scalar(c, r);
+    if (!(nrm2 > 0.0) || !std::isfinite(nrm2))
+      throw Error{D3S_ENUMERIC, "truncate: neighbour norm is zero or not finite"};
+    scale_f64(c, nbr_out, nn, 1.0 / std::sqrt(nrm2));
+  }
+  return res;
+}
+
+namespace {
+
+std::vector<int> state_keys(const Sectors& s) {
+  std::vector<int> k;
+  k.reserve(s.total);
+  for (int i = 0; i < s.n; ++i)
+    for (int r = 0; r < s.dim[i]; ++r) k.push_back(charge_lkey(&s.q[(size_t)i * s.nq], s.nq));
+  return k;
+}
+
+void mask_to_bonds(Ctx* c, d3s_state* s, SymChain& sym, int i) {
+  std::vector<int> ks(s->d);
+  for (int t = 0; t < s->d; ++t) ks[t] = charge_lkey(&sym.phys[(size_t)t * sym.nq], sym.nq);
+  mask_site(c, s->site[i], s->m[i], s->d, s->m[i + 1], state_keys(sym.bonds[i]), ks, state_keys(sym.bonds[i + 1]));
+}
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+void alpha_rule(d3s_sweep_params* p, double lam, double ef, double disc, double total) {
+  if (!p->adaptive_alpha) return;
+  const double dEO = lam - p->e_before, dET = ef - lam;
+  if (disc <= 1e-12 * total) {
+  } else if (std::fabs(dEO) < 1e-13 * std::fabs(lam)) {
+    p->alpha *= 0.8;
+  } else if (dET < 0.3 * std::fabs(dEO)) {
+    p->alpha *= 1.25;
+  } else {
+    p->alpha *= 0.8;
+  }
+  p->alpha = std::min(1.0, std::max(1e-16, p->alpha));
+}
+
+}  // namespace
+
+double op_prepare_blocks(Ctx* c, d3s_state* s, SymChain& sym, double eps) {
+  const int l = s->l, d = s->d;
+  for (int i = 0; i < l; ++i) mask_to_bonds(c, s, sym, i);
+  const size_t cap = (size_t)s->mmax * d * s->mmax;
+  double* tmpS = (double*)ws_get(c, WS_PSI, sizeof(double) * cap);
+  double* tmpN = (double*)ws_get(c, WS_NBR, sizeof(double) * cap);
+  for (int i = 0; i + 1 < l; ++i) {
+    const int ml = s->m[i], mr = s->m[i + 1];
+    const long other = (long)d * s->m[i + 2];
+    TruncBlocksResult t = op_truncate_blocks(c, D3S_L2R, sym.bonds[i], sym.bonds[i + 1], d, sym.phys.data(), nullptr,
+                                             0, mr, s->site[i], s->site[i], (int)budget_of(l, d, s->mmax, i + 1), eps,
+                                             s->site[i + 1], other, tmpS, tmpN, false);
+    copy_f64(c, tmpS, s->site[i], (long)ml * d * t.k);
+    copy_f64(c, tmpN, s->site[i + 1], (long)t.k * other);
+    s->m[i + 1] = t.k;
+    sym.bonds[i + 1] = Sectors(sym.nq, (int)t.dim.size(), t.q.data(), t.dim.data());
+  }
+  const long n = (long)s->m[l - 1] * d * s->m[l];
+  double* r = (double*)ws_get(c, WS_LZ_COEF, sizeof(double) * 512);
+  dot_f64(c, s->site[l - 1], s->site[l - 1], n, r);
+  const double nrm2 = read_scalar(c, r);
+  if (!(nrm2 > 0.0) || !std::isfinite(nrm2)) throw Error{D3S_ENUMERIC, "prepare: zero state in the target sector"};
+  scale_f64(c, s->site[l - 1], n, 1.0 / std::sqrt(nrm2));
+  fill_f64(c, s->lenv[0], 1, 1.0);
+  fill_f64(c, s->renv[l - 1], 1, 1.0);
+  for (int i = 0; i + 1 < l; ++i)
+    op_update_env(c, D3S_L2R, s->m[i], d, s->m[i + 1], s->w[i], s->w[i + 1], s->lenv[i], s->mpo[i], s->site[i],
+                  s->lenv[i + 1]);
+  s->center = l - 1;
+  return op_energy(c, s->m[l - 1], d, s->m[l], s->w[l - 1], s->w[l], s->lenv[l - 1], s->mpo[l - 1], s->renv[l - 1],
+                   s->site[l - 1]);
+}
+
+void op_sweep_blocks(Ctx* c, d3s_state* s, SymChain& sym, d3s_sweep_params* p, d3s_sweep_stats* st, bool use_graph) {
+  const int l = s->l, d = s->d;
+  if (s->center != l - 1) throw Error{D3S_EINVAL, "sweep: the orthogonality centre must be on site l-1"};
+  int wmax = 1;
+  for (int i = 0; i <= l; ++i) wmax = std::max(wmax, s->w[i]);
+  const size_t cap = (size_t)s->mmax * d * s->mmax;
+  double* tmpS = (double*)ws_get(c, WS_PSI, sizeof(double) * cap);
+  double* tmpN = (double*)ws_get(c, WS_NBR, sizeof(double) * cap);
+  double* Mt = (double*)ws_get(c, WS_MT, sizeof(double) * (size_t)(1 + wmax) * cap);
+  const double t_start = now_s();
+  st->count = 0;
+  st->nonconverged = 0;
+  double lam = p->e_before;
+  for (int pass = 0; pass < 2; ++pass) {
+    const bool r2l = (pass == 0);
+    const int i_first = r2l ? l - 1 : 0, i_last = r2l ? 1 : l - 2, step = r2l ? -1 : 1;
+    for (int i = i_first; r2l ? (i >= i_last) : (i <= i_last); i += step) {
+      d3s_site_record r{};
+      r.site = i;
+      r.dir = r2l ? D3S_R2L : D3S_L2R;
+      r.e_before = p->e_before;
+      const int ml = s->m[i], mr = s->m[i + 1], wl = s->w[i], wr = s->w[i + 1];
+      const double t0 = now_s();
+      BlockHeff plan;
+      LanczosResult lz;
+      try {
+        build_block_heff(c, plan, sym.bonds[i], sym.bonds[i + 1], d, wl, wr, sym.phys.data(), sym.wq[i].data(),
+                         sym.wq[i + 1].data());
+        lz = op_lanczos_blocks(c, p->prec, plan, s->lenv[i], s->mpo[i], s->renv[i], s->site[i], p->lanczos_tol,
+                               p->lanczos_kmax, p->lanczos_max_matvecs, use_graph);
+      } catch (...) {
+        release_block_heff(plan);
+        throw;
+      }
+      release_block_heff(plan);
+      lam = lz.theta;
+      if (!lz.converged) st->nonconverged++;
+      const double t1 = now_s();
+      TruncBlocksResult t;
+      double t2, t3, t4, ef;
+      if (r2l) {
+        op_expand(c, D3S_R2L, ml, d, mr, wl, wr, s->renv[i], s->mpo[i], s->site[i], p->alpha, Mt);
+        D3S_HIP(hipStreamSynchronize(c->stream));
+        t2 = now_s();
+        const int mll = s->m[i - 1];
+        t = op_truncate_blocks(c, D3S_R2L, sym.bonds[i], sym.bonds[i + 1], d, sym.phys.data(), sym.wq[i].data(), wl,
+                               (long)(1 + wl) * ml, Mt, s->site[i], (int)budget_of(l, d, s->mmax, i), p->eps,
+                               s->site[i - 1], (long)mll * d, tmpS, tmpN, true);
+        copy_f64(c, tmpS, s->site[i], (long)t.k * d * mr);
+        copy_f64(c, tmpN, s->site[i - 1], (long)mll * d * t.k);
+        s->m[i] = t.k;
+        sym.bonds[i] = Sectors(sym.nq, (int)t.dim.size(), t.q.data(), t.dim.data());
+        t3 = now_s();
+        op_update_env(c, D3S_R2L, t.k, d, mr, wl, wr, s->renv[i], s->mpo[i], s->site[i], s->renv[i - 1]);
+        D3S_HIP(hipStreamSynchronize(c->stream));
+        t4 = now_s();
+        ef = op_energy(c, mll, d, t.k, s->w[i - 1], wl, s->lenv[i - 1], s->mpo[i - 1], s->renv[i - 1], s->site[i - 1]);
+        s->center = i - 1;
+      } else {
+        op_expand(c, D3S_L2R, ml, d, mr, wl, wr, s->lenv[i], s->mpo[i], s->site[i], p->alpha, Mt);
+        D3S_HIP(hipStreamSynchronize(c->stream));
+        t2 = now_s();
+        const int mrr = s->m[i + 2];
+        t = op_truncate_blocks(c, D3S_L2R, sym.bonds[i], sym.bonds[i + 1], d, sym.phys.data(), sym.wq[i + 1].data(),
+                               wr, (long)(1 + wr) * mr, Mt, s->site[i], (int)budget_of(l, d, s->mmax, i + 1), p->eps,
+                               s->site[i + 1], (long)d * mrr, tmpS, tmpN, true);
+        copy_f64(c, tmpS, s->site[i], (long)ml * d * t.k);
+        copy_f64(c, tmpN, s->site[i + 1], (long)t.k * d * mrr);
+        s->m[i + 1] = t.k;
+        sym.bonds[i + 1] = Sectors(sym.nq, (int)t.dim.size(), t.q.data(), t.dim.data());
+        t3 = now_s();
+        op_update_env(c, D3S_L2R, ml, d, t.k, wl, wr, s->lenv[i], s->mpo[i], s->site[i], s->lenv[i + 1]);
+        D3S_HIP(hipStreamSynchronize(c->stream));
+        t4 = now_s();
+        ef = op_energy(c, t.k, d, mrr, wr, s->w[i + 2], s->lenv[i + 1], s->mpo[i + 1], s->renv[i + 1], s->site[i + 1]);
+        s->center = i + 1;
+      }
+      const double t5 = now_s();
+      r.k = t.k;
+      r.matvecs = lz.matvecs;
+      r.lambda = lam;
+      r.e_f = ef;
+      r.alpha = p->alpha;
+      r.discarded = t.discarded;
+      r.t_eig = t1 - t0; r.t_expand = t2 - t1; r.t_trunc = t3 - t2; r.t_env = t4 - t3; r.t_energy = t5 - t4;
+      if (st->count < st->capacity) st->records[st->count] = r;
+      st->count++;
+      alpha_rule(p, lam, ef, t.discarded, t.total);
+      p->e_before = ef;
+    }
+  }
+  st->energy = lam;
+  st->seconds = now_s() - t_start;
 }
 
 }  // namespace d3s

@@ -37,7 +37,7 @@ struct Error {
 enum WsSlot {
   WS_T1 = 0, WS_T2, WS_LZ_V, WS_LZ_W, WS_LZ_COEF, WS_RED, WS_GRAM, WS_EIGVAL,
   WS_EIGTMP, WS_UKT, WS_X, WS_MT, WS_CAST_L, WS_CAST_R, WS_CAST_X, WS_CAST_Y,
-  WS_CAST_W, WS_REF, WS_PSI, WS_INFO, WS_NBR, WS_MISC, WS_SPLITK, WS_NSLOTS
+  WS_CAST_W, WS_REF, WS_PSI, WS_INFO, WS_NBR, WS_MISC, WS_SPLITK, WS_DESC, WS_BLK_X, WS_XPACK, WS_GPACK, WS_GVAL, WS_NSLOTS
 };
 
 struct Ctx {
@@ -126,6 +126,12 @@ void axpby_f64(Ctx* c, double a, const double* x, double b, double* y, long n);
 void copy_f64(Ctx* c, const double* x, double* y, long n);
 void fill_f64(Ctx* c, double* x, long n, double v);
 void zero_bytes(Ctx* c, void* x, size_t bytes);   // kernel fill (safe inside graph capture)
+// strided 2D block copies: dst[dst_off + r*dst_rs + c*dst_cs] = src[src_off + r*src_rs + c*src_cs]
+struct CopyDesc { long src_off, src_rs, src_cs, dst_off, dst_rs, dst_cs; int rows, cols; };
+void copy_blocks(Ctx* c, const double* src, double* dst, const std::vector<CopyDesc>& desc);
+// zero the entries of a site tensor that violate q_a + q_s = q_b (linear charge keys per state)
+void mask_site(Ctx* c, double* M, int ml, int d, int mr, const std::vector<int>& ka, const std::vector<int>& ks,
+               const std::vector<int>& kb);
 // out[r][col] = in[col][r] for an R x C input (row-major), i.e. out is C x R
 void transpose_f64(Ctx* c, const double* in, long R, long C, double* out);
 // copy a rows x cols block with leading dimensions
@@ -192,6 +198,36 @@ void build_block_heff(Ctx* c, BlockHeff& h, const Sectors& left, const Sectors& 
 void release_block_heff(BlockHeff& h);
 void op_apply_heff_blocks(Ctx* c, BlockHeff& h, d3s_prec p, const void* L, const void* W, const void* R,
                           const void* psi, void* out, bool use_graph);
+
+// Charges of one symmetric chain (host copies of the caller's d3s_symmetry).
+struct SymChain {
+  int nq = 1;
+  std::vector<int> phys;                 // d*nq
+  std::vector<std::vector<int>> wq;      // per MPO bond b: w[b]*nq
+  std::vector<Sectors> bonds;            // per MPS bond b = 0..l
+};
+int charge_lkey(const int* q, int nq);   // linear key: key(q1 + q2) = key(q1) + key(q2)
+
+struct TruncBlocksResult {
+  int k = 0;
+  double discarded = 0.0, total = 0.0;
+  std::vector<int> q, dim;               // sectors of the new bond
+};
+// Block-diagonal truncation (per charge sector of the truncated bond) of the
+// expanded tensor; the neighbour update is the dense product on the
+// structured layout.  `wq_exp`: channel charges of the expanded MPO bond
+// (nullptr / wexp = 0 when Mt holds psi only).
+TruncBlocksResult op_truncate_blocks(Ctx* c, d3s_dir dir, const Sectors& left, const Sectors& right, int d,
+                                     const int* pq, const int* wq_exp, int wexp, long width, const double* Mt,
+                                     const double* psi, int kmax, double eps, const double* nbr, long nbr_other,
+                                     double* site_out, double* nbr_out, bool renormalize);
+double op_prepare_blocks(Ctx* c, d3s_state* s, SymChain& sym, double eps);
+void op_sweep_blocks(Ctx* c, d3s_state* s, SymChain& sym, d3s_sweep_params* p, d3s_sweep_stats* st,
+                     bool use_graph);
+LanczosResult op_lanczos_blocks(Ctx* c, d3s_prec p, BlockHeff& plan, const double* L, const double* W,
+                                const double* R, double* psi, double tol, int kmax, int max_matvecs,
+                                bool use_graph);
+void syevd_batched_f64(Ctx* c, int n, int batch, double* A, double* evals);
 
 // host symmetric eigensolver (cyclic Jacobi) for small tridiagonal projections
 void jacobi_eigh(int n, std::vector<double>& A, std::vector<double>& evals,

@@ -240,6 +240,29 @@ __global__ void zero_kernel(uint4* __restrict__ x, long n16, unsigned char* __re
   if (blockIdx.x == 0 && (int)threadIdx.x < ntail) tail[threadIdx.x] = 0;
 }
 
+// one workgroup per descriptor: a strided rows x cols block copy
+__global__ void copy_desc_kernel(const double* __restrict__ src, double* __restrict__ dst,
+                                 const CopyDesc* __restrict__ desc) {
+  const CopyDesc dd = desc[blockIdx.x];
+  const long total = (long)dd.rows * dd.cols;
+  for (long i = threadIdx.x; i < total; i += blockDim.x) {
+    const long r = i / dd.cols, c = i - r * dd.cols;
+    dst[dd.dst_off + r * dd.dst_rs + c * dd.dst_cs] = src[dd.src_off + r * dd.src_rs + c * dd.src_cs];
+  }
+}
+
+// M[a,s,b] = 0 unless key(q_a) + key(q_s) = key(q_b) (linear charge keys)
+__global__ void mask_site_kernel(double* __restrict__ M, int ml, int d, int mr, const int* __restrict__ ka,
+                                 const int* __restrict__ ks, const int* __restrict__ kb) {
+  const long total = (long)ml * d * mr;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+    const long b = i % mr;
+    const long as = i / mr;
+    const int s = (int)(as % d), a = (int)(as / d);
+    if (ka[a] + ks[s] != kb[b]) M[i] = 0.0;
+  }
+}
+
 __global__ void transpose_kernel(const double* __restrict__ in, long R, long C, double* __restrict__ out) {
   __shared__ double tile[32][33];
   const long r0 = (long)blockIdx.y * 32, c0 = (long)blockIdx.x * 32;
@@ -372,6 +395,30 @@ void zero_bytes(Ctx* c, void* x, size_t bytes) {
   hipLaunchKernelGGL(zero_kernel, dim3(grid_for(std::max(n16, 1L))), dim3(kThreads), 0, c->stream, (uint4*)x, n16,
                      (unsigned char*)x + n16 * 16, ntail);
   D3S_HIP(hipGetLastError());
+}
+
+void copy_blocks(Ctx* c, const double* src, double* dst, const std::vector<CopyDesc>& desc) {
+  if (desc.empty()) return;
+  CopyDesc* d = (CopyDesc*)ws_get(c, WS_DESC, sizeof(CopyDesc) * desc.size());
+  D3S_HIP(hipMemcpyAsync(d, desc.data(), sizeof(CopyDesc) * desc.size(), hipMemcpyHostToDevice, c->stream));
+  hipLaunchKernelGGL(copy_desc_kernel, dim3((unsigned)desc.size()), dim3(kThreads), 0, c->stream, src, dst, d);
+  D3S_HIP(hipGetLastError());
+  // the descriptor upload reads pageable host memory: wait before it goes away
+  D3S_HIP(hipStreamSynchronize(c->stream));
+}
+
+void mask_site(Ctx* c, double* M, int ml, int d, int mr, const std::vector<int>& ka, const std::vector<int>& ks,
+               const std::vector<int>& kb) {
+  std::vector<int> all(ka);
+  all.insert(all.end(), ks.begin(), ks.end());
+  all.insert(all.end(), kb.begin(), kb.end());
+  int* dk = (int*)ws_get(c, WS_DESC, sizeof(int) * all.size());
+  D3S_HIP(hipMemcpyAsync(dk, all.data(), sizeof(int) * all.size(), hipMemcpyHostToDevice, c->stream));
+  const long n = (long)ml * d * mr;
+  hipLaunchKernelGGL(mask_site_kernel, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, M, ml, d, mr, dk, dk + ml,
+                     dk + ml + d);
+  D3S_HIP(hipGetLastError());
+  D3S_HIP(hipStreamSynchronize(c->stream));
 }
 
 void transpose_f64(Ctx* c, const double* in, long R, long C, double* out) {

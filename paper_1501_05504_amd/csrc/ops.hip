@@ -164,6 +164,34 @@ void syevd_f64(Ctx* c, int n, double* A, double* evals_dev) {
     throw Error{D3S_EDEVICE, "rocsolver_dsyevd did not converge (info " + std::to_string(hinfo) + ")"};
 }
 
+// `batch` symmetric n x n matrices stored one after the other (column-major);
+// eigenvalues ascending into evals[b*n + i], eigenvectors overwrite A.
+void syevd_batched_f64(Ctx* c, int n, int batch, double* A, double* evals) {
+  if (batch <= 0) return;
+  if (!c->solver) {
+    rocblas_handle h = nullptr;
+    if (rocblas_create_handle(&h) != rocblas_status_success)
+      throw Error{D3S_EDEVICE, "rocblas_create_handle failed"};
+    c->solver = h;
+  }
+  rocblas_handle h = (rocblas_handle)c->solver;
+  if (rocblas_set_stream(h, c->stream) != rocblas_status_success)
+    throw Error{D3S_EDEVICE, "rocblas_set_stream failed"};
+  double* E = (double*)ws_get(c, WS_EIGTMP, sizeof(double) * (size_t)n * batch);
+  rocblas_int* info = (rocblas_int*)ws_get(c, WS_INFO, sizeof(rocblas_int) * (size_t)std::max(batch, 16));
+  rocblas_status st = rocsolver_dsyevd_strided_batched(h, rocblas_evect_original, rocblas_fill_upper, n, A, n,
+                                                       (rocblas_stride)n * n, evals, n, E, n, info, batch);
+  if (st != rocblas_status_success)
+    throw Error{D3S_EDEVICE, "rocsolver_dsyevd_strided_batched failed (status " + std::to_string((int)st) + ")"};
+  std::vector<rocblas_int> hinfo(batch);
+  D3S_HIP(hipMemcpyAsync(hinfo.data(), info, sizeof(rocblas_int) * batch, hipMemcpyDeviceToHost, c->stream));
+  D3S_HIP(hipStreamSynchronize(c->stream));
+  for (int b = 0; b < batch; ++b)
+    if (hinfo[b] != 0)
+      throw Error{D3S_EDEVICE, "rocsolver_dsyevd_strided_batched did not converge (info " +
+                                   std::to_string(hinfo[b]) + ")"};
+}
+
 // Cyclic Jacobi eigensolver for a small dense symmetric matrix (row-major A,
 // destroyed).  Eigenvalues ascending; evecs[j*n + i] = component i of vector j.
 void jacobi_eigh(int n, std::vector<double>& A, std::vector<double>& evals, std::vector<double>& evecs) {
@@ -322,6 +350,9 @@ struct Matvec {
   void* xin = nullptr;
   float* yout = nullptr;
   long n;
+  BlockHeff* plan = nullptr;     // block-sparse products when set
+  bool use_graph = false;
+  double* xblk = nullptr;        // fixed FP64 input buffer of the captured block graph
   void prepare() {
     if (p == D3S_F64) return;
     const long nl = (long)ml * wl * ml, nr = (long)mr * wr * mr, nw = (long)wl * wr * d * d;
@@ -350,15 +381,23 @@ struct Matvec {
   // low-precision (or FP64) product
   void apply(const double* x, double* y) {
     if (p == D3S_F64) {
-      op_apply_heff(c, D3S_F64, ml, d, mr, wl, wr, L, W, R, x, y);
+      apply_f64(x, y);
       return;
     }
     if (p == D3S_F32) cast_f64_to_f32(c, x, (float*)xin, n);
     else cast_f64_to_bf16(c, x, (bf16_t*)xin, n);
-    op_apply_heff(c, p, ml, d, mr, wl, wr, Lc, Wc, Rc, xin, yout);
+    if (plan) op_apply_heff_blocks(c, *plan, p, Lc, Wc, Rc, xin, yout, use_graph);
+    else op_apply_heff(c, p, ml, d, mr, wl, wr, Lc, Wc, Rc, xin, yout);
     cast_f32_to_f64(c, yout, y, n);
   }
   void apply_f64(const double* x, double* y) {
+    if (plan) {
+      // the captured graph reads a fixed input buffer
+      if (!xblk) xblk = (double*)ws_get(c, WS_BLK_X, sizeof(double) * n);
+      copy_f64(c, x, xblk, n);
+      op_apply_heff_blocks(c, *plan, D3S_F64, L, W, R, xblk, y, use_graph);
+      return;
+    }
     op_apply_heff(c, D3S_F64, ml, d, mr, wl, wr, L, W, R, x, y);
   }
 };
@@ -448,6 +487,21 @@ LanczosResult lanczos_core(Ctx* c, Matvec& mv, double* x, long n, double tol, in
 }
 }  // namespace
 
+static LanczosResult lanczos_with(Ctx* c, Matvec& mv, d3s_prec p, double* psi, long n, double tol, int kmax,
+                                  int max_matvecs);
+
+LanczosResult op_lanczos_blocks(Ctx* c, d3s_prec p, BlockHeff& plan, const double* L, const double* W,
+                                const double* R, double* psi, double tol, int kmax, int max_matvecs,
+                                bool use_graph) {
+  const long n = (long)plan.ml * plan.d * plan.mr;
+  Matvec mv{c, p, plan.ml, plan.d, plan.mr, plan.wl, plan.wr, L, W, R};
+  mv.n = n;
+  mv.plan = &plan;
+  mv.use_graph = use_graph;
+  mv.prepare();
+  return lanczos_with(c, mv, p, psi, n, tol, kmax, max_matvecs);
+}
+
 LanczosResult op_lanczos(Ctx* c, d3s_prec p, int ml, int d, int mr, int wl, int wr, const double* L,
                          const double* W, const double* R, double* psi, double tol, int kmax,
                          int max_matvecs) {
@@ -455,6 +509,11 @@ LanczosResult op_lanczos(Ctx* c, d3s_prec p, int ml, int d, int mr, int wl, int 
   Matvec mv{c, p, ml, d, mr, wl, wr, L, W, R};
   mv.n = n;
   mv.prepare();
+  return lanczos_with(c, mv, p, psi, n, tol, kmax, max_matvecs);
+}
+
+static LanczosResult lanczos_with(Ctx* c, Matvec& mv, d3s_prec p, double* psi, long n, double tol, int kmax,
+                                  int max_matvecs) {
   if (p == D3S_F64) return lanczos_core(c, mv, psi, n, tol, kmax, max_matvecs, true);
   // Mixed precision: converge on the low-precision operator to its own
   // accuracy, then refine with FP64 products: Lanczos on the exact operator

@@ -89,3 +89,73 @@ def mask_env(q, wq):
     """L[a,w,x] may be nonzero iff q_a - q_x = Delta_w."""
     q, wq = np.asarray(q), np.asarray(wq)
     return np.all(q[:, None, None, :] - q[None, None, :, :] == wq[None, :, None, :], axis=-1)
+
+
+def initial_sectors(l, phys_q, target, mmax):
+    """Sectors of the initial symmetric MPS: on bond b every charge Q that can
+    be reached from the left edge with b sites and completed to `target` with
+    the remaining l - b sites, with dimension min(#left states of charge Q,
+    #right states completing it); when these exceed the bond budget
+    min(mmax, d^b, d^(l-b)) the budget is shared in proportion (largest
+    remainder, at least one state for the heaviest sectors).  Sectors are
+    ordered by charge (lexicographically).  Returns a list of (q, dims)."""
+    phys = [tuple(int(x) for x in np.atleast_1d(q)) for q in phys_q]
+    nq = len(phys[0])
+    d = len(phys)
+    zero = tuple([0] * nq)
+    tgt = tuple(int(x) for x in np.atleast_1d(target))
+
+    def add(a, b, sign=1):
+        return tuple(x + sign * y for x, y in zip(a, b))
+    cap = 10 ** 15
+    left = [{zero: 1}]
+    for _ in range(l):
+        nxt = {}
+        for q, n in left[-1].items():
+            for ps in phys:
+                k = add(q, ps)
+                nxt[k] = min(cap, nxt.get(k, 0) + n)
+        left.append(nxt)
+    right = [None] * (l + 1)
+    right[l] = {tgt: 1}
+    for b in range(l - 1, -1, -1):
+        nxt = {}
+        for q, n in right[b + 1].items():
+            for ps in phys:
+                k = add(q, ps, -1)
+                nxt[k] = min(cap, nxt.get(k, 0) + n)
+        right[b] = nxt
+    out = []
+    for b in range(l + 1):
+        qs = sorted(q for q in left[b] if q in right[b])
+        w = np.array([min(left[b][q], right[b][q]) for q in qs], dtype=float)
+        budget = int(min(mmax, d ** b, d ** (l - b)))
+        if w.sum() <= budget:
+            dims = w.astype(int)
+        else:
+            share = w / w.sum() * budget
+            dims = np.floor(share).astype(int)
+            if dims.sum() == 0:
+                dims[np.argsort(-w)[:budget]] = 1
+            rem = budget - dims.sum()
+            for i in np.argsort(-(share - dims))[:max(rem, 0)]:
+                dims[i] += 1
+            dims = np.minimum(dims, w.astype(int))
+        keep = dims > 0
+        out.append((np.array(qs, dtype=int).reshape(-1, nq)[keep], dims[keep]))
+    return out
+
+
+def random_symmetric_mps(l, phys_q, target, mmax, seed=SEED_MPS):
+    """Gaussian site tensors on the initial sectors, zero outside the
+    symmetry-allowed blocks.  Returns (tensors, sectors)."""
+    secs = initial_sectors(l, phys_q, target, mmax)
+    rng = np.random.default_rng(seed)
+    d = len(phys_q)
+    tensors = []
+    for i in range(l):
+        ql = expand_charges(*secs[i])
+        qr = expand_charges(*secs[i + 1])
+        t = rng.standard_normal((len(ql), d, len(qr)))
+        tensors.append(t * mask_site(ql, np.asarray(phys_q).reshape(d, -1), qr))
+    return tensors, secs

@@ -1,0 +1,110 @@
+"""Block-sparse DMRG3S sweeps on the GPU (U(1) spins, U(1)xU(1) fermions):
+converged energies against exact diagonalisation in the target sector and
+against the dense CPU oracle started from the same symmetric state."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ed, mpo as MPO
+from oracle.dmrg3s import DMRG3S
+from paper_1501_05504_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+abi = pytest.importorskip("paper_1501_05504_amd.abi")
+
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = abi.Context(0)
+    yield c
+    c.close()
+
+
+def run_blocks(ctx, mpo, chan_q, phys, target, m, sweeps, seed, use_graph=True, prec=None, tol=1e-12):
+    tensors, secs = synth.random_symmetric_mps(len(mpo), phys, target, m, seed=seed)
+    st = abi.State(mpo, tensors, m, device=DEV)
+    sym = abi.Symmetry(phys, abi.mpo_bond_charges(mpo, chan_q), secs)
+    e0 = ctx.prepare_blocks(st, sym)
+    params = abi.sweep_params(alpha=1e-3, e_before=e0, prec=abi.F64 if prec is None else prec)
+    prev, hist = None, []
+    for s in range(sweeps):
+        _, stats, recs = ctx.sweep_blocks(st, sym, params, use_graph=use_graph)
+        hist.append(stats.energy)
+        if prev is not None and abs(stats.energy - prev) / abs(stats.energy) < tol:
+            break
+        prev = stats.energy
+    return stats.energy, st, sym, tensors, hist, recs
+
+
+def test_block_sweep_heisenberg12_sz0_equals_ed(ctx):
+    l, m = 12, 64
+    mpo = abi.heisenberg_mpo(l)
+    E, st, sym, _, _, recs = run_blocks(ctx, mpo, abi.mpo_spin_charges(1), abi.SPIN_HALF_CHARGES, [0], m, 12, 21)
+    H = ed.spin_chain_hamiltonian(l, {(i, i + 1): 1.0 for i in range(l - 1)})
+    e_ed = ed.ground_energy(H, mask=ed.spin_sz(l) == 0)
+    assert abs(E - e_ed) < 1e-10
+    for r in recs:
+        assert r.lam >= e_ed - 1e-10
+    # every bond keeps its sectors consistent with the state's bond dimensions
+    for b in range(l + 1):
+        q, d = sym.sectors(b)
+        assert d.sum() == st.m[b]
+
+
+def test_block_sweep_hubbard6_equals_ed_and_oracle(ctx):
+    """Hubbard l = 6, U = 8, N = 6, 2Sz = 0, m = 64 (exact): block sweeps on the
+    GPU, the dense oracle from the same symmetric initial state, and Fock ED
+    in the sector agree."""
+    l, m, U = 6, 64, 8.0
+    mpo = abi.hubbard_chain_mpo(l, t=1.0, U=U)
+    E, st, sym, tensors, _, _ = run_blocks(ctx, mpo, abi.mpo_fermion_charges(1), abi.HUBBARD_CHARGES, [l, 0], m,
+                                           12, 31)
+    H = ed.hubbard_hamiltonian(l, {(i, i + 1): 1.0 for i in range(l - 1)}, U=U)
+    N, S = ed.particle_numbers(l)
+    e_ed = ed.ground_energy(H, mask=(N == l) & (S == 0))
+    assert abs(E - e_ed) < 1e-10
+    run = DMRG3S(MPO.hubbard_chain_mpo(l, 1.0, U), tensors, mmax=m, alpha0=1e-3)
+    Eo, _ = run.run(tol=1e-12, max_sweeps=12)
+    assert abs(Eo - e_ed) < 1e-10
+
+
+def test_block_sweep_matches_dense_gpu_sweep(ctx):
+    """Same symmetric start, m below exact: block-sparse and dense GPU sweeps
+    (both FP64) converge to the same energy."""
+    l, m = 14, 24
+    mpo = abi.heisenberg_mpo(l)
+    E_b, _, _, tensors, _, _ = run_blocks(ctx, mpo, abi.mpo_spin_charges(1), abi.SPIN_HALF_CHARGES, [0], m, 30, 41)
+    st = abi.State(mpo, tensors, m, device=DEV)
+    e0 = ctx.prepare(st)
+    params = abi.sweep_params(alpha=1e-3, e_before=e0)
+    prev = None
+    for s in range(30):
+        _, stats, _ = ctx.sweep(st, params)
+        if prev is not None and abs(stats.energy - prev) / abs(stats.energy) < 1e-12:
+            break
+        prev = stats.energy
+    H = ed.spin_chain_hamiltonian(l, {(i, i + 1): 1.0 for i in range(l - 1)})
+    e_ed = ed.ground_energy(H, mask=ed.spin_sz(l) == 0)
+    assert E_b >= e_ed - 1e-10 and stats.energy >= e_ed - 1e-10
+    assert abs(E_b - stats.energy) < 1e-9
+
+
+def test_block_sweep_without_graph_equals_with_graph(ctx):
+    l, m = 10, 16
+    mpo = abi.heisenberg_mpo(l)
+    Eg, *_ = run_blocks(ctx, mpo, abi.mpo_spin_charges(1), abi.SPIN_HALF_CHARGES, [0], m, 6, 51, use_graph=True)
+    Ee, *_ = run_blocks(ctx, mpo, abi.mpo_spin_charges(1), abi.SPIN_HALF_CHARGES, [0], m, 6, 51, use_graph=False)
+    assert abs(Eg - Ee) < 1e-11
+
+
+def test_block_sweep_mixed_precision(ctx):
+    """FP32 block products with FP64 refinement reach the FP64 energy."""
+    l, m = 12, 64
+    mpo = abi.heisenberg_mpo(l)
+    E, *_ = run_blocks(ctx, mpo, abi.mpo_spin_charges(1), abi.SPIN_HALF_CHARGES, [0], m, 12, 21, prec=abi.F32)
+    H = ed.spin_chain_hamiltonian(l, {(i, i + 1): 1.0 for i in range(l - 1)})
+    e_ed = ed.ground_energy(H, mask=ed.spin_sz(l) == 0)
+    assert abs(E - e_ed) < 1e-8
