@@ -122,6 +122,82 @@ def time_heff(ctx, torch, L, W, R, psi, out, steps, warmup):
     return ms, wall, [k / max(n, 1) for k in kern_ms]
 
 
+def block_heff_bench(ctx, abi, synth, torch, np, m, dev, steps):
+    """Block-sparse H_eff (U(1)xU(1) Hubbard MPO): sectors with dimensions
+    ~ exp(-(N-N0)^2/18 - (2Sz)^2/18) normalised to m on both bonds (uneven
+    blocks, 100+ sectors), charge-conserving Gaussian L, R, psi; graph replay."""
+    qL, dL = synth.gaussian_sectors((32, 0), (3.0, 3.0), m, (10, 10))
+    qR, dR = synth.gaussian_sectors((33, 1), (3.0, 3.0), m, (10, 10))
+    W = abi.hubbard_chain_mpo(3, t=1.0, U=8.0)[1]
+    wq = abi.mpo_fermion_charges(1)
+    phys = np.array(abi.HUBBARD_CHARGES)
+    sl, sr = synth.expand_charges(qL, dL), synth.expand_charges(qR, dR)
+    L = torch.tensor(synth.gaussian((m, 6, m), synth.SEED_LEFT) * synth.mask_env(sl, wq) / m, device=dev)
+    R = torch.tensor(synth.gaussian((m, 6, m), synth.SEED_RIGHT) * synth.mask_env(sr, wq) / m, device=dev)
+    psi = torch.tensor(synth.gaussian((m, 4, m), synth.SEED_PSI) * synth.mask_site(sl, phys, sr), device=dev)
+    Wd = torch.tensor(W, device=dev)
+    out = torch.empty_like(psi)
+    plan = abi.BlockPlan(ctx, 2, 4, 6, 6, qL, dL, qR, dR, phys, wq, wq)
+    res = {}
+    for graph in (True, False):
+        for _ in range(3):
+            plan.apply(L, Wd, R, psi, out, use_graph=graph)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            plan.apply(L, Wd, R, psi, out, use_graph=graph)
+        b.record()
+        torch.cuda.synchronize()
+        res["graph" if graph else "eager"] = a.elapsed_time(b) / steps
+    dense = torch.empty_like(psi)
+    ctx.apply_heff(L, Wd, R, psi, dense)
+    torch.cuda.synchronize()
+    err = float((dense - out).abs().max() / dense.abs().max())
+    ms = res["graph"]
+    info = {"m": m, "sectors_left": len(dL), "sectors_right": len(dR), "tasks": plan.ntasks,
+            "block_gflop": round(plan.flops / 1e9, 2), "ms_graph": round(ms, 4), "ms_eager": round(res["eager"], 4),
+            "gflops": round(plan.flops / ms * 1e-6, 1),
+            "dense_flop_ratio": round(heff_flops(m, 4, m, 6, 6) / plan.flops, 1),
+            "max_rel_diff_vs_dense": err}
+    plan.close()
+    return info
+
+
+def block_sweep_bench(ctx, abi, synth, torch, np, dev, l, m, U, max_sweeps, tol):
+    """DMRG3S block sweeps on the Hubbard chain (half filling, 2Sz = 0) from
+    one seeded symmetric state, plain FP64 products vs FP32 products with FP64
+    refinement: wall time until the normalised sweep energy change < tol."""
+    out = {"workload": "hubbard_chain_blocks", "l": l, "m": m, "U": U, "tol": tol}
+    phys = abi.HUBBARD_CHARGES
+    mpo = abi.hubbard_chain_mpo(l, t=1.0, U=U)
+    for name, prec in (("f64", abi.F64), ("mixed_f32", abi.F32)):
+        tensors, secs = synth.random_symmetric_mps(l, phys, [l, 0], m, seed=synth.SEED_MPS)
+        st = abi.State(mpo, tensors, m, device=dev)
+        sym = abi.Symmetry(phys, abi.mpo_bond_charges(mpo, abi.mpo_fermion_charges(1)), secs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0 = ctx.prepare_blocks(st, sym)
+        params = abi.sweep_params(alpha=1e-3, e_before=e0, prec=prec)
+        prev, energies, t_conv = None, [], None
+        for sweep in range(max_sweeps):
+            _, stats, recs = ctx.sweep_blocks(st, sym, params, use_graph=True)
+            energies.append(stats.energy)
+            if prev is not None and abs(stats.energy - prev) / abs(stats.energy) < tol:
+                t_conv = time.perf_counter() - t0
+                break
+            prev = stats.energy
+        wall = time.perf_counter() - t0
+        split = {k: round(sum(getattr(r, k) for r in recs), 3) for k in ("t_eig", "t_expand", "t_trunc", "t_env", "t_energy")}
+        out[name] = {"seconds_to_tol": None if t_conv is None else round(t_conv, 3), "seconds": round(wall, 3),
+                     "sweeps": len(energies), "energy": energies[-1], "last_sweep_split_s": split,
+                     "max_bond": max(st.m)}
+        print("bench: block sweep %s: %d sweeps %.2f s  E=%.12f" % (name, len(energies), wall, energies[-1]),
+              file=sys.stderr, flush=True)
+    out["energy_diff"] = abs(out["f64"]["energy"] - out["mixed_f32"]["energy"])
+    return out
+
+
 def cpu_baseline(L, W, R, psi, budget_s):
     """The oracle's H_eff (NumPy FP64, tensordot in the paper's order) on the
     same arrays, repeated until `budget_s` seconds are used (at least once)."""
@@ -159,6 +235,10 @@ def main():
     ap.add_argument("--gaussian-env", action="store_true",
                     help="Gaussian L and R instead of MPS-built environments (same kernels and shapes; "
                          "no eigensolver calls, for counter runs)")
+    ap.add_argument("--no-blocks", action="store_true", help="skip the block-sparse H_eff and sweep measurements")
+    ap.add_argument("--sweep-l", type=int, default=32)
+    ap.add_argument("--sweep-m", type=int, default=256)
+    ap.add_argument("--sweep-max", type=int, default=10)
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 1 GiB read + 1 GiB write elementwise kernel (torch.neg) first, "
                          "as the reference for HBM byte counters")
@@ -255,6 +335,12 @@ def main():
                            "kernel_ms_f64": {a: round(b, 4) for a, b in v["kernel_ms"].items()}}
                   for k, v in results.items()},
     }
+    if not args.no_blocks:
+        print("bench: block-sparse H_eff ...", file=sys.stderr, flush=True)
+        line["blocks"] = block_heff_bench(ctx, abi, synth, torch, np, m, dev, max(10, steps // 2))
+        print("bench: blocks %s" % line["blocks"], file=sys.stderr, flush=True)
+        line["sweep"] = block_sweep_bench(ctx, abi, synth, torch, np, dev, args.sweep_l, args.sweep_m, 8.0,
+                                          args.sweep_max, 1e-8)
     if not args.no_cpu:
         print("bench: cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         Ln, Wn, Rn, pn = [x.cpu().numpy() for x in (L, W, R, psi)]

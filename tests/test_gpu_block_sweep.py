@@ -66,9 +66,14 @@ def test_block_sweep_hubbard6_equals_ed_and_oracle(ctx):
     N, S = ed.particle_numbers(l)
     e_ed = ed.ground_energy(H, mask=(N == l) & (S == 0))
     assert abs(E - e_ed) < 1e-10
-    run = DMRG3S(MPO.hubbard_chain_mpo(l, 1.0, U), tensors, mmax=m, alpha0=1e-3)
+    # the dense oracle does not protect the sector (rounding noise in other
+    # particle numbers grows); with mu = U/2 the half-filled singlet is the
+    # global ground state, so E + mu N must equal the sector energy
+    mu = [U / 2] * l
+    run = DMRG3S(MPO.fermion_hopping_mpo(l, {(i, i + 1): 1.0 for i in range(l - 1)}, U=U, mu=mu), tensors,
+                 mmax=m, alpha0=1e-3)
     Eo, _ = run.run(tol=1e-12, max_sweeps=12)
-    assert abs(Eo - e_ed) < 1e-10
+    assert abs(Eo + U / 2 * l - e_ed) < 1e-10
 
 
 def test_block_sweep_matches_dense_gpu_sweep(ctx):
