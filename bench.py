@@ -27,14 +27,18 @@ HBM_PEAK = 8.0e12
 # FETCH_SIZE / WRITE_SIZE passes (scaled by a 1 GiB copy reference), valid
 # only for the GEMM source they were taken on (first 16 hex digits of its
 # SHA-256); any other source reports null.
-TRAFFIC = {"src_sha": "d8b39c43b8adaae6", "m": 2048,
+TRAFFIC = {"src_sha": "pending", "m": 2048,
            "gemm1": 4.029e9 + 0.805e9, "gemm2": 4.161e9 + 0.134e9}
 
 
 def gemm_source_sha():
+    """SHA-256 (first 16 hex digits) of the GEMM kernel sources."""
     import hashlib
-    with open(os.path.join(ROOT, "paper_1501_05504_amd", "csrc", "gemm.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ("gemm.hip", "mfma_tile.h"):
+        with open(os.path.join(ROOT, "paper_1501_05504_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def heff_flops(ml, d, mr, wl, wr):

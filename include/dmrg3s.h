@@ -85,6 +85,14 @@ const char* d3s_version(void);
  * block tiles (4 waves of 64x64), 1 = 64x64 (4 waves of 32x32), 2 = 256x128
  * (8 waves of 64x64), 3 = 128x128 (8 waves of 64x32). */
 d3s_status d3s_set_tile_config(d3s_ctx ctx, int cfg);
+/* Autotuning of tile configurations (default off: a size heuristic picks
+ * them).  When on, the first dense GEMM of every shape class (precision,
+ * layouts, M, N, K) is timed in all tile configurations with HIP events and
+ * the fastest is kept, and block plans time both tile sizes of their grouped
+ * launches when they are created.  cache_path (may be NULL) names a text file
+ * of "key config" lines read now and appended to on every new decision.
+ * Tuning never happens during graph capture or for accumulating products. */
+d3s_status d3s_set_autotune(d3s_ctx ctx, int enable, const char* cache_path);
 /* Split-K of GEMMs whose tiles cannot fill the device (default on; the
  * partial products are summed in a fixed order, so results stay
  * deterministic).  enable = 0 turns it off. */
@@ -215,8 +223,9 @@ typedef struct d3s_block_plan_s* d3s_block_plan;
  * states ordered by sector; psi must vanish outside q_a + q_s = q_b, L outside
  * q_a - q_x = Delta_w and R outside q_b - q_y = Delta_v, where phys_q (d*nq)
  * are the physical charges and wq_left (w_l*nq) / wq_right (w_r*nq) the MPO
- * channel charges Delta.  The plan holds the task tables of two grouped MFMA
- * launches (one per GEMM of the Sec. 5 ordering; the W-map stays dense).
+ * channel charges Delta.  The plan holds the task tables of the grouped
+ * MFMA launches of the two GEMMs of the Sec. 5 ordering and of the block
+ * W-map between them.
  * *flops (host, may be NULL) receives the flop count of the allowed block
  * products, *ntasks (may be NULL) the number of block tasks.  Synchronises. */
 d3s_status d3s_block_plan_create(d3s_ctx ctx, int nq, int d, int wl, int wr, const d3s_sectors* left,
@@ -231,6 +240,26 @@ void d3s_block_plan_destroy(d3s_ctx ctx, d3s_block_plan plan);
  * before the context's stream by events).  Asynchronous. */
 d3s_status d3s_apply_heff_blocks(d3s_ctx ctx, d3s_block_plan plan, d3s_prec prec, const void* L,
                                  const void* W, const void* R, const void* psi, void* out, int use_graph);
+
+/* Block-sparse expansion of a site on the plan's bonds (Sec. 4.1-4.2, the
+ * expansion term of eq. subexp-ourt): the same FP64 result as
+ * d3s_expand_subspace on symmetric inputs.  L2R: env = L, Mt = [psi | alpha P]
+ * of shape (ml*d) x ((1+wr)*mr); R2L: env = R, Mt = [psi ; alpha P] of shape
+ * ((1+wl)*ml) x (d*mr).  Only the allowed blocks are computed (the first GEMM
+ * of the Sec. 5 ordering as a grouped launch, then a block W-map writing P
+ * straight into Mt); every other entry of Mt is written as zero.  Device
+ * pointers, caller-owned.  Asynchronous. */
+d3s_status d3s_expand_subspace_blocks(d3s_ctx ctx, d3s_block_plan plan, d3s_dir dir, const double* env,
+                                      const double* W, const double* psi, double alpha, double* Mt);
+/* Block-sparse environment update with the site tensor on the plan's bonds
+ * (Sec. 2 definitions of L_i and R_i): the same FP64 result as
+ * d3s_update_env on symmetric inputs.  L2R: env_in = L (ml, wl, ml),
+ * env_out (mr, wr, mr); R2L: env_in = R (mr, wr, mr), env_out (ml, wl, ml).
+ * Three grouped launches (first GEMM, block W-map, closing GEMM over the
+ * allowed (sector, channel) pairs); env_out is zero outside its allowed
+ * blocks.  Asynchronous. */
+d3s_status d3s_update_env_blocks(d3s_ctx ctx, d3s_block_plan plan, d3s_dir dir, const double* env_in,
+                                 const double* W, const double* site, double* env_out);
 
 /* Charges of a symmetric chain for the block-sparse sweep (host arrays,
  * owned by the caller).  Bond b (0..l) currently has nsec[b] sectors with
@@ -288,7 +317,7 @@ typedef struct {
 
 /* One record per site update (steps 1-8 of Sec. 5). */
 typedef struct {
-  int site, dir, k, matvecs;
+  int site, dir, k, matvecs, f64_matvecs;   /* matvecs: all H_eff products; f64_matvecs: the FP64 ones */
   double e_before, lambda, e_f, alpha, discarded;
   double t_eig, t_expand, t_trunc, t_env, t_energy;  /* seconds */
 } d3s_site_record;

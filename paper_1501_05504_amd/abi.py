@@ -46,7 +46,7 @@ class d3s_sweep_params(ctypes.Structure):
 
 
 class d3s_site_record(ctypes.Structure):
-    _fields_ = [("site", c_int), ("dir", c_int), ("k", c_int), ("matvecs", c_int),
+    _fields_ = [("site", c_int), ("dir", c_int), ("k", c_int), ("matvecs", c_int), ("f64_matvecs", c_int),
                 ("e_before", c_double), ("lam", c_double), ("e_f", c_double), ("alpha", c_double),
                 ("discarded", c_double), ("t_eig", c_double), ("t_expand", c_double),
                 ("t_trunc", c_double), ("t_env", c_double), ("t_energy", c_double)]
@@ -72,6 +72,7 @@ _synchronize = _sig("d3s_synchronize", c_int, [c_void_p])
 _version = _sig("d3s_version", ctypes.c_char_p, [])
 _set_tile_config = _sig("d3s_set_tile_config", c_int, [c_void_p, c_int])
 _set_splitk = _sig("d3s_set_splitk", c_int, [c_void_p, c_int])
+_set_autotune = _sig("d3s_set_autotune", c_int, [c_void_p, c_int, ctypes.c_char_p])
 _profile_begin = _sig("d3s_profile_begin", c_int, [c_void_p, c_int])
 _profile_end = _sig("d3s_profile_end", c_int, [c_void_p, c_double_p, c_int_p])
 _apply_heff = _sig("d3s_apply_heff", c_int, [c_void_p, c_int] + [c_int] * 5 + [c_void_p] * 5)
@@ -106,6 +107,9 @@ _plan_create = _sig("d3s_block_plan_create", c_int, [c_void_p, c_int, c_int, c_i
                                                      c_double_p, c_int_p])
 _plan_destroy = _sig("d3s_block_plan_destroy", None, [c_void_p, c_void_p])
 _apply_blocks = _sig("d3s_apply_heff_blocks", c_int, [c_void_p, c_void_p, c_int] + [c_void_p] * 5 + [c_int])
+_expand_blocks = _sig("d3s_expand_subspace_blocks", c_int,
+                      [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_double, c_void_p])
+_env_blocks = _sig("d3s_update_env_blocks", c_int, [c_void_p, c_void_p, c_int] + [c_void_p] * 4)
 _spin_charges = _sig("d3s_mpo_spin_charges", c_int, [c_int, c_int_p])
 _fermion_charges = _sig("d3s_mpo_fermion_charges", c_int, [c_int, c_int_p])
 
@@ -190,6 +194,10 @@ class Context:
 
     def set_tile_config(self, cfg):
         self._check(_set_tile_config(self.h, cfg))
+
+    def set_autotune(self, enable, cache_path=None):
+        self._check(_set_autotune(self.h, 1 if enable else 0,
+                                  None if cache_path is None else str(cache_path).encode()))
 
     def set_splitk(self, enable):
         self._check(_set_splitk(self.h, 1 if enable else 0))
@@ -523,6 +531,39 @@ class BlockPlan:
         _need(out, ml * d * mr, to, "out")
         return ctx._check(_apply_blocks(ctx.h, self.h, prec, _ptr(L), _ptr(W), _ptr(R), _ptr(psi), _ptr(out),
                                         1 if use_graph else 0))
+
+    def expand_subspace(self, direction, env, W, psi, alpha, Mtilde):
+        """Block-sparse d3s_expand_subspace (FP64) on the plan's bonds."""
+        ctx = self.ctx
+        ctx._sync_stream()
+        ml, d, mr, wl, wr = self.ml, self.d, self.mr, self.wl, self.wr
+        f = torch.float64
+        _need(W, wl * wr * d * d, f, "W")
+        _need(psi, ml * d * mr, f, "psi")
+        if direction == L2R:
+            _need(env, ml * wl * ml, f, "L")
+            _need(Mtilde, ml * d * (1 + wr) * mr, f, "Mtilde")
+        else:
+            _need(env, mr * wr * mr, f, "R")
+            _need(Mtilde, (1 + wl) * ml * d * mr, f, "Mtilde")
+        return ctx._check(_expand_blocks(ctx.h, self.h, direction, _ptr(env), _ptr(W), _ptr(psi), float(alpha),
+                                         _ptr(Mtilde)))
+
+    def update_env(self, direction, env_in, W, site, env_out):
+        """Block-sparse d3s_update_env (FP64) for a site tensor on the plan's bonds."""
+        ctx = self.ctx
+        ctx._sync_stream()
+        ml, d, mr, wl, wr = self.ml, self.d, self.mr, self.wl, self.wr
+        f = torch.float64
+        _need(W, wl * wr * d * d, f, "W")
+        _need(site, ml * d * mr, f, "site")
+        if direction == L2R:
+            _need(env_in, ml * wl * ml, f, "L")
+            _need(env_out, mr * wr * mr, f, "env_out")
+        else:
+            _need(env_in, mr * wr * mr, f, "R")
+            _need(env_out, ml * wl * ml, f, "env_out")
+        return ctx._check(_env_blocks(ctx.h, self.h, direction, _ptr(env_in), _ptr(W), _ptr(site), _ptr(env_out)))
 
     def close(self):
         if self.h:

@@ -125,6 +125,15 @@ d3s_status d3s_set_tile_config(d3s_ctx ctx, int cfg) {
   });
 }
 
+d3s_status d3s_set_autotune(d3s_ctx ctx, int enable, const char* cache_path) {
+  return guarded(ctx, [&] {
+    ctx->c.autotune = (enable != 0);
+    ctx->c.tune_path = cache_path ? std::string(cache_path) : std::string();
+    d3s::autotune_load(&ctx->c);
+    return D3S_OK;
+  });
+}
+
 d3s_status d3s_set_splitk(d3s_ctx ctx, int enable) {
   return guarded(ctx, [&] {
     ctx->c.splitk_off = (enable == 0);
@@ -369,6 +378,31 @@ d3s_status d3s_apply_heff_blocks(d3s_ctx ctx, d3s_block_plan plan, d3s_prec prec
     D3S_REQUIRE(L && W && R && psi && out, "null tensor pointer");
     D3S_REQUIRE(out != psi && out != L && out != R, "out must not alias an input");
     d3s::op_apply_heff_blocks(&ctx->c, plan->h, prec, L, W, R, psi, out, use_graph != 0);
+    return D3S_OK;
+  });
+}
+
+d3s_status d3s_expand_subspace_blocks(d3s_ctx ctx, d3s_block_plan plan, d3s_dir dir, const double* env,
+                                      const double* W, const double* psi, double alpha, double* Mt) {
+  return guarded(ctx, [&] {
+    D3S_REQUIRE(plan, "null plan");
+    D3S_REQUIRE(dir == D3S_L2R || dir == D3S_R2L, "dir must be D3S_L2R or D3S_R2L");
+    D3S_REQUIRE(env && W && psi && Mt, "null tensor pointer");
+    D3S_REQUIRE(Mt != psi && Mt != env, "Mt must not alias an input");
+    D3S_REQUIRE(std::isfinite(alpha), "alpha must be finite");
+    d3s::op_expand_blocks(&ctx->c, plan->h, dir, env, W, psi, alpha, Mt);
+    return D3S_OK;
+  });
+}
+
+d3s_status d3s_update_env_blocks(d3s_ctx ctx, d3s_block_plan plan, d3s_dir dir, const double* env_in,
+                                 const double* W, const double* site, double* env_out) {
+  return guarded(ctx, [&] {
+    D3S_REQUIRE(plan, "null plan");
+    D3S_REQUIRE(dir == D3S_L2R || dir == D3S_R2L, "dir must be D3S_L2R or D3S_R2L");
+    D3S_REQUIRE(env_in && W && site && env_out, "null tensor pointer");
+    D3S_REQUIRE(env_out != env_in && env_out != site, "env_out must not alias an input");
+    d3s::op_update_env_blocks(&ctx->c, plan->h, dir, env_in, W, site, env_out);
     return D3S_OK;
   });
 }

@@ -80,6 +80,18 @@ void grouped_finalize(Ctx* c, GroupedPlan& g) {
     t128 += (long)((t.M + 127) / 128) * ((t.N + 127) / 128);
   }
   g.cfg = (t128 >= 512 && 4 * t128 <= t64 + t64 / 4) ? 0 : 1;
+  g.ntasks = (int)g.tasks.size();
+  grouped_release(g);
+  if (g.ntasks == 0) return;
+  D3S_HIP(hipMalloc((void**)&g.d_tasks, sizeof(GTask) * g.tasks.size()));
+  D3S_HIP(hipMalloc((void**)&g.d_segs, sizeof(GSeg) * std::max<size_t>(1, g.segs.size())));
+  if (!g.segs.empty())
+    D3S_HIP(hipMemcpyAsync(g.d_segs, g.segs.data(), sizeof(GSeg) * g.segs.size(), hipMemcpyHostToDevice,
+                           c->stream));
+  grouped_retile(c, g);
+}
+
+void grouped_retile(Ctx* c, GroupedPlan& g) {
   const int tile = grouped_tile(g.cfg);
   int acc = 0;
   for (GTask& t : g.tasks) {
@@ -87,16 +99,9 @@ void grouped_finalize(Ctx* c, GroupedPlan& g) {
     acc += ((t.M + tile - 1) / tile) * ((t.N + tile - 1) / tile);
   }
   g.total_tiles = acc;
-  g.ntasks = (int)g.tasks.size();
-  grouped_release(g);
-  if (g.ntasks == 0) return;
-  D3S_HIP(hipMalloc((void**)&g.d_tasks, sizeof(GTask) * g.tasks.size()));
-  D3S_HIP(hipMalloc((void**)&g.d_segs, sizeof(GSeg) * std::max<size_t>(1, g.segs.size())));
+  if (g.ntasks == 0 || !g.d_tasks) return;
   D3S_HIP(hipMemcpyAsync(g.d_tasks, g.tasks.data(), sizeof(GTask) * g.tasks.size(), hipMemcpyHostToDevice,
                          c->stream));
-  if (!g.segs.empty())
-    D3S_HIP(hipMemcpyAsync(g.d_segs, g.segs.data(), sizeof(GSeg) * g.segs.size(), hipMemcpyHostToDevice,
-                           c->stream));
   D3S_HIP(hipStreamSynchronize(c->stream));
 }
 
@@ -107,36 +112,190 @@ void grouped_release(GroupedPlan& g) {
   g.d_segs = nullptr;
 }
 
+namespace {
+
+// offset and row stride of the psi block (i, t) whose right sector is j
+long psi_off(const BlockHeff& h, int i, int t, int j) {
+  return h.packed ? h.poff[(size_t)i * h.d + t] : ((long)h.left.off[i] * h.d + t) * h.mr + h.right.off[j];
+}
+long psi_ld(const BlockHeff& h, int j) { return h.packed ? (long)h.right.dim[j] : (long)h.d * h.mr; }
+
+const int* qv(const std::vector<int>& q, int i, int nq) { return q.data() + (size_t)i * nq; }
+
+// right sector of q_i + q_t (or -1)
+int right_of(const BlockHeff& h, int i, int t) {
+  const int nq = h.left.nq;
+  int qq[4];
+  for (int k = 0; k < nq; ++k) qq[k] = h.left.q[(size_t)i * nq + k] + h.pq[t * nq + k];
+  return h.right.find(qq);
+}
+
+// W-map tasks of a left-to-right contraction: input T1[a,w,t,y] (rows a of
+// length wl*d*mr), outputs the pairs (s,v) at out_base + s*out_ss + v*mr in
+// rows of length out_rs.
+void build_wmap_l2r(const BlockHeff& h, WmapPlan& wm, long out_base, long out_ss, long out_rs) {
+  const Sectors &L = h.left, &R = h.right;
+  const int nq = L.nq, d = h.d, wl = h.wl, wr = h.wr, mr = h.mr;
+  wm = WmapPlan();
+  wm.in_rs = (long)wl * d * mr;
+  wm.out_rs = out_rs;
+  std::vector<WmapEnt> ins, outs;
+  int qq[4];
+  for (int i = 0; i < L.n; ++i)
+    for (int j = 0; j < R.n; ++j) {
+      ins.clear();
+      outs.clear();
+      for (int w = 0; w < wl; ++w) {
+        for (int k = 0; k < nq; ++k) qq[k] = L.q[(size_t)i * nq + k] - h.wql[w * nq + k];
+        if (L.find(qq) < 0) continue;     // the first GEMM writes no T1 block for this w
+        for (int t = 0; t < d; ++t) {
+          bool ok = true;
+          for (int k = 0; k < nq; ++k) ok = ok && (qq[k] + h.pq[t * nq + k] == R.q[(size_t)j * nq + k]);
+          if (ok) ins.push_back(WmapEnt{(long)(w * d + t) * mr, w * wr * d * d + t, 0});
+        }
+      }
+      for (int sg = 0; sg < d; ++sg)
+        for (int v = 0; v < wr; ++v) {
+          bool ok = true;
+          for (int k = 0; k < nq; ++k)
+            ok = ok && (L.q[(size_t)i * nq + k] + h.pq[sg * nq + k] == R.q[(size_t)j * nq + k] + h.wqr[v * nq + k]);
+          if (ok) outs.push_back(WmapEnt{out_base + (long)sg * out_ss + (long)v * mr, v * d * d + sg * d, 0});
+        }
+      wmap_add(wm, L.off[i], L.dim[i], R.off[j], R.dim[j], ins, outs);
+    }
+}
+
+// W-map tasks of a right-to-left contraction: input Y[x,t,v,b] (rows x of
+// length d*wr*mr), outputs the pairs (w,s) at out_base + w*out_ws + s*mr in
+// rows of length d*mr.
+void build_wmap_r2l(const BlockHeff& h, WmapPlan& wm, long out_base, long out_ws) {
+  const Sectors &L = h.left, &R = h.right;
+  const int nq = L.nq, d = h.d, wl = h.wl, wr = h.wr, mr = h.mr;
+  wm = WmapPlan();
+  wm.in_rs = (long)d * wr * mr;
+  wm.out_rs = (long)d * mr;
+  std::vector<WmapEnt> ins, outs;
+  for (int i = 0; i < L.n; ++i)
+    for (int j = 0; j < R.n; ++j) {
+      ins.clear();
+      outs.clear();
+      for (int t = 0; t < d; ++t) {
+        const int jp = right_of(h, i, t);      // sector of y
+        if (jp < 0) continue;
+        for (int v = 0; v < wr; ++v) {
+          bool ok = true;
+          for (int k = 0; k < nq; ++k)
+            ok = ok && (R.q[(size_t)jp * nq + k] + h.wqr[v * nq + k] == R.q[(size_t)j * nq + k]);
+          if (ok) ins.push_back(WmapEnt{(long)(t * wr + v) * mr, v * d * d + t, 0});
+        }
+      }
+      for (int w = 0; w < wl; ++w)
+        for (int sg = 0; sg < d; ++sg) {
+          bool ok = true;
+          for (int k = 0; k < nq; ++k)
+            ok = ok && (L.q[(size_t)i * nq + k] + h.wql[w * nq + k] + h.pq[sg * nq + k] == R.q[(size_t)j * nq + k]);
+          if (ok) outs.push_back(WmapEnt{out_base + (long)w * out_ws + (long)sg * mr, w * wr * d * d + sg * d, 0});
+        }
+      wmap_add(wm, L.off[i], L.dim[i], R.off[j], R.dim[j], ins, outs);
+    }
+}
+
+void finalize_and_tune(Ctx* c, GroupedPlan& g, size_t na, size_t nb, size_t nc) {
+  grouped_finalize(c, g);
+  if (!c->autotune || g.ntasks == 0) return;
+  // time both tile sizes on zeroed operands of the right extents
+  double* s = (double*)ws_get(c, WS_TUNE, sizeof(double) * (na + nb + nc));
+  zero_bytes(c, s, sizeof(double) * (na + nb + nc));
+  tune_grouped(c, g, s, s + na, s + na + nb);
+}
+
+}  // namespace
+
+void wmap_add(WmapPlan& w, int i_off, int di, int j_off, int dj, const std::vector<WmapEnt>& ins,
+              const std::vector<WmapEnt>& outs) {
+  if (outs.empty() || di <= 0 || dj <= 0) return;
+  WmapTask t;
+  t.i_off = i_off;
+  t.di = di;
+  t.j_off = j_off;
+  t.dj = dj;
+  t.nin = (int)ins.size();
+  t.nout = (int)outs.size();
+  t.idx0 = (int)w.ents.size();
+  t.chunk0 = w.chunks;
+  w.chunks += (int)(((long)di * dj + 255) / 256);
+  w.ents.insert(w.ents.end(), ins.begin(), ins.end());
+  w.ents.insert(w.ents.end(), outs.begin(), outs.end());
+  w.maxk = std::max(w.maxk, std::max(t.nin, t.nout));
+  w.tasks.push_back(t);
+}
+
+void wmap_upload(Ctx* c, WmapPlan& w) {
+  wmap_release(w);
+  if (w.maxk > 80) throw Error{D3S_EINVAL, "block W-map: more than 80 channel pairs per block"};
+  if (w.tasks.empty()) return;
+  D3S_HIP(hipMalloc((void**)&w.d_tasks, sizeof(WmapTask) * w.tasks.size()));
+  D3S_HIP(hipMalloc((void**)&w.d_ents, sizeof(WmapEnt) * std::max<size_t>(1, w.ents.size())));
+  D3S_HIP(hipMemcpyAsync(w.d_tasks, w.tasks.data(), sizeof(WmapTask) * w.tasks.size(), hipMemcpyHostToDevice,
+                         c->stream));
+  if (!w.ents.empty())
+    D3S_HIP(hipMemcpyAsync(w.d_ents, w.ents.data(), sizeof(WmapEnt) * w.ents.size(), hipMemcpyHostToDevice,
+                           c->stream));
+  D3S_HIP(hipStreamSynchronize(c->stream));
+}
+
+void wmap_release(WmapPlan& w) {
+  if (w.d_tasks) (void)hipFree(w.d_tasks);
+  if (w.d_ents) (void)hipFree(w.d_ents);
+  w.d_tasks = nullptr;
+  w.d_ents = nullptr;
+}
+
 void build_block_heff(Ctx* c, BlockHeff& h, const Sectors& left, const Sectors& right, int d, int wl, int wr,
-                      const int* pq, const int* wql, const int* wqr) {
+                      const int* pq, const int* wql, const int* wqr, bool packed, bool with_g2) {
   const int nq = left.nq;
+  if (nq < 1 || nq > 4) throw Error{D3S_EINVAL, "blocks: 1 to 4 charges per state"};
   const int ml = left.total, mr = right.total;
+  h.left = left;
+  h.right = right;
   h.ml = ml;
   h.mr = mr;
   h.d = d;
   h.wl = wl;
   h.wr = wr;
+  h.pq.assign(pq, pq + (size_t)d * nq);
+  h.wql.assign(wql, wql + (size_t)wl * nq);
+  h.wqr.assign(wqr, wqr + (size_t)wr * nq);
+  h.packed = packed;
+  h.poff.assign((size_t)left.n * d, -1);
+  h.npacked = 0;
+  for (int i = 0; i < left.n; ++i)
+    for (int t = 0; t < d; ++t) {
+      const int j = right_of(h, i, t);
+      if (j < 0) continue;
+      h.poff[(size_t)i * d + t] = h.npacked;
+      h.npacked += (long)left.dim[i] * right.dim[j];
+    }
   h.g1 = GroupedPlan();
   h.g2 = GroupedPlan();
-  std::vector<int> qq(nq);
+  int qq[4];
   // GEMM-1: T1[(a,w),(t,y)] = sum_x L[(a,w),x] psi[x,(t,y)]
   h.g1.a_kc = true;
   h.g1.b_kc = false;
   for (int i = 0; i < left.n; ++i)
     for (int w = 0; w < wl; ++w) {
       for (int k = 0; k < nq; ++k) qq[k] = left.q[(size_t)i * nq + k] - wql[w * nq + k];
-      const int ip = left.find(qq.data());
+      const int ip = left.find(qq);
       if (ip < 0) continue;
       for (int t = 0; t < d; ++t) {
-        for (int k = 0; k < nq; ++k) qq[k] = left.q[(size_t)ip * nq + k] + pq[t * nq + k];
-        const int jp = right.find(qq.data());
+        const int jp = right_of(h, ip, t);
         if (jp < 0) continue;
         GSeg sg;
         sg.K = left.dim[ip];
         sg.a_off = ((long)left.off[i] * wl + w) * ml + left.off[ip];
         sg.lda = (long)wl * ml;
-        sg.b_off = ((long)left.off[ip] * d + t) * mr + right.off[jp];
-        sg.ldb = (long)d * mr;
+        sg.b_off = psi_off(h, ip, t, jp);
+        sg.ldb = psi_ld(h, jp);
         GTask tk;
         tk.M = left.dim[i];
         tk.N = right.dim[jp];
@@ -152,43 +311,60 @@ void build_block_heff(Ctx* c, BlockHeff& h, const Sectors& left, const Sectors& 
   // GEMM-2: out[(a,s), b] = sum_{v,y} T2[(a,s),(v,y)] R[b,(v,y)]
   h.g2.a_kc = true;
   h.g2.b_kc = true;
-  for (int i = 0; i < left.n; ++i)
-    for (int s = 0; s < d; ++s) {
-      for (int k = 0; k < nq; ++k) qq[k] = left.q[(size_t)i * nq + k] + pq[s * nq + k];
-      const int j = right.find(qq.data());
-      if (j < 0) continue;
-      GTask tk;
-      tk.M = left.dim[i];
-      tk.N = right.dim[j];
-      tk.seg0 = (int)h.g2.segs.size();
-      tk.nseg = 0;
-      tk.tile0 = 0;
-      tk.c_off = ((long)left.off[i] * d + s) * mr + right.off[j];
-      tk.ldc = (long)d * mr;
-      for (int v = 0; v < wr; ++v) {
-        for (int k = 0; k < nq; ++k) qq[k] = right.q[(size_t)j * nq + k] - wqr[v * nq + k];
-        const int jpp = right.find(qq.data());
-        if (jpp < 0) continue;
-        GSeg sg;
-        sg.K = right.dim[jpp];
-        sg.a_off = (((long)left.off[i] * d + s) * wr + v) * mr + right.off[jpp];
-        sg.lda = (long)d * wr * mr;
-        sg.b_off = ((long)right.off[j] * wr + v) * mr + right.off[jpp];
-        sg.ldb = (long)wr * mr;
-        h.g2.segs.push_back(sg);
-        tk.nseg++;
+  if (with_g2)
+    for (int i = 0; i < left.n; ++i)
+      for (int s = 0; s < d; ++s) {
+        const int j = right_of(h, i, s);
+        if (j < 0) continue;
+        GTask tk;
+        tk.M = left.dim[i];
+        tk.N = right.dim[j];
+        tk.seg0 = (int)h.g2.segs.size();
+        tk.nseg = 0;
+        tk.tile0 = 0;
+        tk.c_off = psi_off(h, i, s, j);
+        tk.ldc = psi_ld(h, j);
+        for (int v = 0; v < wr; ++v) {
+          for (int k = 0; k < nq; ++k) qq[k] = right.q[(size_t)j * nq + k] - wqr[v * nq + k];
+          const int jpp = right.find(qq);
+          if (jpp < 0) continue;
+          GSeg sg;
+          sg.K = right.dim[jpp];
+          sg.a_off = (((long)left.off[i] * d + s) * wr + v) * mr + right.off[jpp];
+          sg.lda = (long)d * wr * mr;
+          sg.b_off = ((long)right.off[j] * wr + v) * mr + right.off[jpp];
+          sg.ldb = (long)wr * mr;
+          h.g2.segs.push_back(sg);
+          tk.nseg++;
+        }
+        h.g2.tasks.push_back(tk);
       }
-      h.g2.tasks.push_back(tk);
-    }
-  grouped_finalize(c, h.g1);
-  grouped_finalize(c, h.g2);
-  // flops of the allowed block products of the two GEMMs (the W-map, dense, is not counted)
+  build_wmap_l2r(h, h.wm, 0, (long)wr * mr, (long)d * wr * mr);
+  wmap_upload(c, h.wm);
+  const size_t nL = (size_t)ml * wl * ml, nP = (size_t)ml * d * mr, nR = (size_t)mr * wr * mr;
+  const size_t nT = (size_t)ml * std::max(wl, wr) * d * mr;
+  finalize_and_tune(c, h.g1, nL, nP, nT);
+  finalize_and_tune(c, h.g2, nT, nR, nP);
+  // flops of the allowed block products of the two GEMMs (the W-map is not counted)
   h.flops = h.g1.flops + h.g2.flops;
 }
 
 void release_block_heff(BlockHeff& h) {
   grouped_release(h.g1);
   grouped_release(h.g2);
+  grouped_release(h.g_el);
+  grouped_release(h.g_y);
+  grouped_release(h.g_er);
+  wmap_release(h.wm);
+  wmap_release(h.wm_x);
+  wmap_release(h.wm_yx);
+  wmap_release(h.wm_yz);
+  h.g_el = GroupedPlan();
+  h.g_y = GroupedPlan();
+  h.g_er = GroupedPlan();
+  h.wm_x = WmapPlan();
+  h.wm_yx = WmapPlan();
+  h.wm_yz = WmapPlan();
   if (h.graph_exec) (void)hipGraphExecDestroy((hipGraphExec_t)h.graph_exec);
   if (h.graph) (void)hipGraphDestroy((hipGraph_t)h.graph);
   if (h.cap_stream) (void)hipStreamDestroy((hipStream_t)h.cap_stream);
@@ -197,17 +373,236 @@ void release_block_heff(BlockHeff& h) {
   h.graph_exec = h.graph = h.cap_stream = h.ev_in = h.ev_out = nullptr;
 }
 
+namespace {
+
+std::vector<CopyDesc> psi_blocks(const BlockHeff& h, bool to_packed, long rowlen) {
+  std::vector<CopyDesc> v;
+  const int d = h.d;
+  for (int i = 0; i < h.left.n; ++i)
+    for (int t = 0; t < d; ++t) {
+      const long po = h.poff[(size_t)i * d + t];
+      if (po < 0) continue;
+      const int j = right_of(h, i, t);
+      const long doff = ((long)h.left.off[i] * d + t) * rowlen + h.right.off[j];
+      const long drs = (long)d * rowlen, prs = h.right.dim[j];
+      if (to_packed) v.push_back(CopyDesc{doff, drs, 1, po, prs, 1, h.left.dim[i], h.right.dim[j]});
+      else v.push_back(CopyDesc{po, prs, 1, doff, drs, 1, h.left.dim[i], h.right.dim[j]});
+    }
+  return v;
+}
+
+// Y = psi * R^T over the allowed blocks: Y[(x,t),(v,b)] = sum_y psi[(x,t),y] R[(b,v),y]
+void ensure_y(Ctx* c, BlockHeff& h) {
+  if (h.g_y.ntasks != 0 || !h.g_y.tasks.empty()) return;
+  const Sectors &L = h.left, &R = h.right;
+  const int nq = L.nq, d = h.d, wr = h.wr, mr = h.mr;
+  GroupedPlan& g = h.g_y;
+  g.a_kc = true;
+  g.b_kc = true;
+  int qq[4];
+  for (int i = 0; i < L.n; ++i)
+    for (int t = 0; t < d; ++t) {
+      const int jp = right_of(h, i, t);
+      if (jp < 0) continue;
+      for (int v = 0; v < wr; ++v) {
+        for (int k = 0; k < nq; ++k) qq[k] = R.q[(size_t)jp * nq + k] + h.wqr[v * nq + k];
+        const int j = R.find(qq);
+        if (j < 0) continue;
+        GSeg sg;
+        sg.K = R.dim[jp];
+        sg.a_off = psi_off(h, i, t, jp);
+        sg.lda = psi_ld(h, jp);
+        sg.b_off = ((long)R.off[j] * wr + v) * mr + R.off[jp];
+        sg.ldb = (long)wr * mr;
+        GTask tk;
+        tk.M = L.dim[i];
+        tk.N = R.dim[j];
+        tk.seg0 = (int)g.segs.size();
+        tk.nseg = 1;
+        tk.tile0 = 0;
+        tk.c_off = (((long)L.off[i] * d + t) * wr + v) * mr + R.off[j];
+        tk.ldc = (long)d * wr * mr;
+        g.segs.push_back(sg);
+        g.tasks.push_back(tk);
+      }
+    }
+  const size_t nP = (size_t)h.ml * d * mr, nR = (size_t)mr * wr * mr, nY = (size_t)h.ml * d * wr * mr;
+  finalize_and_tune(c, g, nP, nR, nY);
+  if (g.tasks.empty()) g.ntasks = -1;   // built, nothing to do
+}
+
+// L2R environment: Lnew[(b),(v,y)] = sum_{(a,s)} site[(a,s),b] T2[(a,s),(v,y)]
+void ensure_env_l2r(Ctx* c, BlockHeff& h) {
+  if (h.g_el.ntasks != 0 || !h.g_el.tasks.empty()) return;
+  if (h.packed) throw Error{D3S_EINVAL, "blocks: environment updates need a dense-layout plan"};
+  const Sectors &L = h.left, &R = h.right;
+  const int nq = L.nq, d = h.d, wr = h.wr, mr = h.mr;
+  GroupedPlan& g = h.g_el;
+  g.a_kc = false;
+  g.b_kc = false;
+  int qq[4];
+  for (int j = 0; j < R.n; ++j)
+    for (int v = 0; v < wr; ++v) {
+      for (int k = 0; k < nq; ++k) qq[k] = R.q[(size_t)j * nq + k] - h.wqr[v * nq + k];
+      const int jpp = R.find(qq);
+      if (jpp < 0) continue;
+      GTask tk;
+      tk.M = R.dim[j];
+      tk.N = R.dim[jpp];
+      tk.seg0 = (int)g.segs.size();
+      tk.nseg = 0;
+      tk.tile0 = 0;
+      tk.c_off = ((long)R.off[j] * wr + v) * mr + R.off[jpp];
+      tk.ldc = (long)wr * mr;
+      for (int i = 0; i < L.n; ++i)
+        for (int s = 0; s < d; ++s) {
+          if (right_of(h, i, s) != j) continue;
+          GSeg sg;
+          sg.K = L.dim[i];
+          sg.a_off = ((long)L.off[i] * d + s) * mr + R.off[j];
+          sg.lda = (long)d * mr;
+          sg.b_off = (((long)L.off[i] * d + s) * wr + v) * mr + R.off[jpp];
+          sg.ldb = (long)d * wr * mr;
+          g.segs.push_back(sg);
+          tk.nseg++;
+        }
+      if (tk.nseg > 0) g.tasks.push_back(tk);
+    }
+  const size_t nP = (size_t)h.ml * d * mr, nT = (size_t)h.ml * d * wr * mr, nE = (size_t)mr * wr * mr;
+  finalize_and_tune(c, g, nP, nT, nE);
+  if (g.tasks.empty()) g.ntasks = -1;
+}
+
+// R2L environment: Rnew[a,(w,x)] = sum_{(s,b)} site[a,(s,b)] Z[(w,x),(s,b)]
+void ensure_env_r2l(Ctx* c, BlockHeff& h) {
+  if (h.g_er.ntasks != 0 || !h.g_er.tasks.empty()) return;
+  if (h.packed) throw Error{D3S_EINVAL, "blocks: environment updates need a dense-layout plan"};
+  const Sectors& L = h.left;
+  const int nq = L.nq, d = h.d, wl = h.wl, ml = h.ml, mr = h.mr;
+  build_wmap_r2l(h, h.wm_yz, 0, (long)ml * d * mr);
+  wmap_upload(c, h.wm_yz);
+  GroupedPlan& g = h.g_er;
+  g.a_kc = true;
+  g.b_kc = true;
+  int qq[4];
+  for (int i = 0; i < L.n; ++i)
+    for (int w = 0; w < wl; ++w) {
+      for (int k = 0; k < nq; ++k) qq[k] = L.q[(size_t)i * nq + k] - h.wql[w * nq + k];
+      const int ip = L.find(qq);
+      if (ip < 0) continue;
+      GTask tk;
+      tk.M = L.dim[i];
+      tk.N = L.dim[ip];
+      tk.seg0 = (int)g.segs.size();
+      tk.nseg = 0;
+      tk.tile0 = 0;
+      tk.c_off = ((long)L.off[i] * wl + w) * ml + L.off[ip];
+      tk.ldc = (long)wl * ml;
+      for (int s = 0; s < d; ++s) {
+        const int j = right_of(h, i, s);
+        if (j < 0) continue;
+        GSeg sg;
+        sg.K = h.right.dim[j];
+        sg.a_off = ((long)L.off[i] * d + s) * mr + h.right.off[j];
+        sg.lda = (long)d * mr;
+        sg.b_off = (((long)w * ml + L.off[ip]) * d + s) * mr + h.right.off[j];
+        sg.ldb = (long)d * mr;
+        g.segs.push_back(sg);
+        tk.nseg++;
+      }
+      if (tk.nseg > 0) g.tasks.push_back(tk);
+    }
+  const size_t nP = (size_t)ml * d * mr, nZ = (size_t)wl * ml * d * mr, nE = (size_t)ml * wl * ml;
+  finalize_and_tune(c, g, nP, nZ, nE);
+  if (g.tasks.empty()) g.ntasks = -1;
+}
+
+}  // namespace
+
+void pack_psi(Ctx* c, const BlockHeff& h, const double* dense, double* packed) {
+  if (!h.packed) throw Error{D3S_EINVAL, "blocks: pack needs a packed plan"};
+  copy_blocks(c, dense, packed, psi_blocks(h, true, h.mr));
+}
+
+void unpack_psi(Ctx* c, const BlockHeff& h, const double* packed, double* dense, long rowlen, bool clear) {
+  if (!h.packed) throw Error{D3S_EINVAL, "blocks: unpack needs a packed plan"};
+  if (clear) zero_bytes(c, dense, sizeof(double) * (size_t)h.ml * h.d * rowlen);
+  copy_blocks(c, packed, dense, psi_blocks(h, false, rowlen));
+}
+
+void op_expand_blocks(Ctx* c, BlockHeff& h, d3s_dir dir, const double* env, const double* W, const double* psi,
+                      double alpha, double* Mt) {
+  const int ml = h.ml, d = h.d, mr = h.mr, wl = h.wl, wr = h.wr;
+  if (dir == D3S_L2R) {
+    if (h.wm_x.tasks.empty() && !h.wm_x.d_tasks) {
+      build_wmap_l2r(h, h.wm_x, mr, (long)(1 + wr) * mr, (long)d * (1 + wr) * mr);
+      wmap_upload(c, h.wm_x);
+    }
+    double* T1 = (double*)ws_get(c, WS_T1, sizeof(double) * (size_t)ml * wl * d * mr);
+    grouped_gemm(c, D3S_F64, h.g1, env, psi, T1, 1.0);
+    const long rowlen = (long)(1 + wr) * mr;
+    if (h.packed) {
+      unpack_psi(c, h, psi, Mt, rowlen, true);
+    } else {
+      zero_bytes(c, Mt, sizeof(double) * (size_t)ml * d * rowlen);
+      copy2d_f64(c, psi, mr, Mt, rowlen, (long)ml * d, mr);
+    }
+    wmap_blocks(c, D3S_F64, T1, W, Mt, h.wm_x, alpha);
+  } else {
+    if (h.wm_yx.tasks.empty() && !h.wm_yx.d_tasks) {
+      build_wmap_r2l(h, h.wm_yx, (long)ml * d * mr, (long)ml * d * mr);
+      wmap_upload(c, h.wm_yx);
+    }
+    ensure_y(c, h);
+    double* Y = (double*)ws_get(c, WS_T2, sizeof(double) * (size_t)ml * d * wr * mr);
+    if (h.g_y.ntasks > 0) grouped_gemm(c, D3S_F64, h.g_y, psi, env, Y, 1.0);
+    const size_t nrows = (size_t)(1 + wl) * ml;
+    if (h.packed) {
+      zero_bytes(c, Mt, sizeof(double) * nrows * d * mr);
+      unpack_psi(c, h, psi, Mt, mr, false);
+    } else {
+      zero_bytes(c, Mt + (size_t)ml * d * mr, sizeof(double) * (size_t)wl * ml * d * mr);
+      copy_f64(c, psi, Mt, (long)ml * d * mr);
+    }
+    wmap_blocks(c, D3S_F64, Y, W, Mt, h.wm_yx, alpha);
+  }
+}
+
+void op_update_env_blocks(Ctx* c, BlockHeff& h, d3s_dir dir, const double* env_in, const double* W,
+                          const double* site, double* env_out) {
+  const int ml = h.ml, d = h.d, mr = h.mr, wl = h.wl, wr = h.wr;
+  if (dir == D3S_L2R) {
+    ensure_env_l2r(c, h);
+    double* T1 = (double*)ws_get(c, WS_T1, sizeof(double) * (size_t)ml * wl * d * mr);
+    double* T2 = (double*)ws_get(c, WS_T2, sizeof(double) * (size_t)ml * d * wr * mr);
+    grouped_gemm(c, D3S_F64, h.g1, env_in, site, T1, 1.0);
+    wmap_blocks(c, D3S_F64, T1, W, T2, h.wm, 1.0);
+    zero_bytes(c, env_out, sizeof(double) * (size_t)mr * wr * mr);
+    if (h.g_el.ntasks > 0) grouped_gemm(c, D3S_F64, h.g_el, site, T2, env_out, 1.0);
+  } else {
+    ensure_y(c, h);
+    ensure_env_r2l(c, h);
+    double* Y = (double*)ws_get(c, WS_T2, sizeof(double) * (size_t)ml * d * wr * mr);
+    double* Z = (double*)ws_get(c, WS_T1, sizeof(double) * (size_t)wl * ml * d * mr);
+    if (h.g_y.ntasks > 0) grouped_gemm(c, D3S_F64, h.g_y, site, env_in, Y, 1.0);
+    wmap_blocks(c, D3S_F64, Y, W, Z, h.wm_yz, 1.0);
+    zero_bytes(c, env_out, sizeof(double) * (size_t)ml * wl * ml);
+    if (h.g_er.ntasks > 0) grouped_gemm(c, D3S_F64, h.g_er, site, Z, env_out, 1.0);
+  }
+}
+
 // The four launches of one block-sparse H_eff on stream s.
 static void enqueue_block_heff(Ctx* c, hipStream_t s, const BlockHeff& h, d3s_prec p, const void* L, const void* W,
                                const void* R, const void* psi, void* out, void* T1, void* T2) {
   hipStream_t keep = c->stream;
   c->stream = s;
-  const size_t tsz = (p == D3S_F64) ? 8 : 4;
   const size_t osz = (p == D3S_F64) ? 8 : 4;
-  zero_bytes(c, T1, tsz * (size_t)h.ml * h.wl * h.d * h.mr);
+  // only allowed blocks of T1 / T2 are written and read, so they need no clearing;
+  // the output's forbidden blocks are cleared
   grouped_gemm(c, p, h.g1, L, psi, T1, 1.0);
-  wmap_l2r(c, p, T1, W, T2, (long)h.wr * h.mr, h.ml, h.d, h.mr, h.wl, h.wr, 1.0);
-  zero_bytes(c, out, osz * (size_t)h.ml * h.d * h.mr);
+  wmap_blocks(c, p, T1, W, T2, h.wm, 1.0);
+  // packed outputs have no forbidden entries; dense ones are cleared first
+  if (!h.packed) zero_bytes(c, out, osz * (size_t)h.ml * h.d * h.mr);
   grouped_gemm(c, p, h.g2, T2, R, out, 1.0);
   c->stream = keep;
 }
@@ -583,6 +978,46 @@ void alpha_rule(d3s_sweep_params* p, double lam, double ef, double disc, double 
 
 }  // namespace
 
+double op_energy_blocks(Ctx* c, BlockHeff& h, const double* L, const double* W, const double* R,
+                        const double* psi) {
+  const long n = h.packed ? h.npacked : (long)h.ml * h.d * h.mr;
+  if (n <= 0) throw Error{D3S_ENUMERIC, "energy: the site has no symmetry-allowed block"};
+  const double* x = psi;
+  if (h.packed) {
+    double* xp = (double*)ws_get(c, WS_PK, sizeof(double) * (size_t)n);
+    pack_psi(c, h, psi, xp);
+    x = xp;
+  }
+  double* hp = (double*)ws_get(c, WS_REF, sizeof(double) * (size_t)n);
+  op_apply_heff_blocks(c, h, D3S_F64, L, W, R, x, hp, false);
+  double* r = (double*)ws_get(c, WS_LZ_COEF, sizeof(double) * 512);
+  dot_f64(c, x, hp, n, r);
+  dot_f64(c, x, x, n, r + 1);
+  double v[2];
+  D3S_HIP(hipMemcpyAsync(v, r, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  D3S_HIP(hipStreamSynchronize(c->stream));
+  if (!(v[1] > 0.0)) throw Error{D3S_ENUMERIC, "energy: zero state"};
+  const double e = v[0] / v[1];
+  if (!std::isfinite(e)) throw Error{D3S_ENUMERIC, "energy: not finite"};
+  return e;
+}
+
+namespace {
+
+// plan of site i (bonds i, i+1) of a symmetric chain
+void site_plan(Ctx* c, BlockHeff& h, const d3s_state* s, const SymChain& sym, int i, bool packed, bool with_g2) {
+  build_block_heff(c, h, sym.bonds[i], sym.bonds[i + 1], s->d, s->w[i], s->w[i + 1], sym.phys.data(),
+                   sym.wq[i].data(), sym.wq[i + 1].data(), packed, with_g2);
+}
+
+// owns a plan for the duration of a scope
+struct PlanGuard {
+  BlockHeff h;
+  ~PlanGuard() { release_block_heff(h); }
+};
+
+}  // namespace
+
 double op_prepare_blocks(Ctx* c, d3s_state* s, SymChain& sym, double eps) {
   const int l = s->l, d = s->d;
   for (int i = 0; i < l; ++i) mask_to_bonds(c, s, sym, i);
@@ -608,14 +1043,22 @@ double op_prepare_blocks(Ctx* c, d3s_state* s, SymChain& sym, double eps) {
   scale_f64(c, s->site[l - 1], n, 1.0 / std::sqrt(nrm2));
   fill_f64(c, s->lenv[0], 1, 1.0);
   fill_f64(c, s->renv[l - 1], 1, 1.0);
-  for (int i = 0; i + 1 < l; ++i)
-    op_update_env(c, D3S_L2R, s->m[i], d, s->m[i + 1], s->w[i], s->w[i + 1], s->lenv[i], s->mpo[i], s->site[i],
-                  s->lenv[i + 1]);
+  for (int i = 0; i + 1 < l; ++i) {
+    PlanGuard e;
+    site_plan(c, e.h, s, sym, i, false, false);
+    op_update_env_blocks(c, e.h, D3S_L2R, s->lenv[i], s->mpo[i], s->site[i], s->lenv[i + 1]);
+  }
   s->center = l - 1;
-  return op_energy(c, s->m[l - 1], d, s->m[l], s->w[l - 1], s->w[l], s->lenv[l - 1], s->mpo[l - 1], s->renv[l - 1],
-                   s->site[l - 1]);
+  PlanGuard last;
+  site_plan(c, last.h, s, sym, l - 1, true, true);
+  return op_energy_blocks(c, last.h, s->lenv[l - 1], s->mpo[l - 1], s->renv[l - 1], s->site[l - 1]);
 }
 
+// One sweep with every contraction block-sparse: the eigensolver works on
+// packed vectors with the grouped H_eff (graph-replayed), the expansion
+// term and the environments are grouped contractions on the allowed
+// blocks, and the plan built for the post-truncation energy of the next
+// site is the one its eigensolver uses.
 void op_sweep_blocks(Ctx* c, d3s_state* s, SymChain& sym, d3s_sweep_params* p, d3s_sweep_stats* st, bool use_graph) {
   const int l = s->l, d = s->d;
   if (s->center != l - 1) throw Error{D3S_EINVAL, "sweep: the orthogonality centre must be on site l-1"};
@@ -629,6 +1072,8 @@ void op_sweep_blocks(Ctx* c, d3s_state* s, SymChain& sym, d3s_sweep_params* p, d
   st->count = 0;
   st->nonconverged = 0;
   double lam = p->e_before;
+  PlanGuard cur, nxt;
+  site_plan(c, cur.h, s, sym, l - 1, true, true);
   for (int pass = 0; pass < 2; ++pass) {
     const bool r2l = (pass == 0);
     const int i_first = r2l ? l - 1 : 0, i_last = r2l ? 1 : l - 2, step = r2l ? -1 : 1;
@@ -639,25 +1084,16 @@ void op_sweep_blocks(Ctx* c, d3s_state* s, SymChain& sym, d3s_sweep_params* p, d
       r.e_before = p->e_before;
       const int ml = s->m[i], mr = s->m[i + 1], wl = s->w[i], wr = s->w[i + 1];
       const double t0 = now_s();
-      BlockHeff plan;
-      LanczosResult lz;
-      try {
-        build_block_heff(c, plan, sym.bonds[i], sym.bonds[i + 1], d, wl, wr, sym.phys.data(), sym.wq[i].data(),
-                         sym.wq[i + 1].data());
-        lz = op_lanczos_blocks(c, p->prec, plan, s->lenv[i], s->mpo[i], s->renv[i], s->site[i], p->lanczos_tol,
-                               p->lanczos_kmax, p->lanczos_max_matvecs, use_graph);
-      } catch (...) {
-        release_block_heff(plan);
-        throw;
-      }
-      release_block_heff(plan);
+      double* xp = (double*)ws_get(c, WS_PK, sizeof(double) * (size_t)std::max<long>(1, cur.h.npacked));
+      LanczosResult lz = op_lanczos_blocks(c, p->prec, cur.h, s->lenv[i], s->mpo[i], s->renv[i], s->site[i],
+                                           p->lanczos_tol, p->lanczos_kmax, p->lanczos_max_matvecs, use_graph, xp);
       lam = lz.theta;
       if (!lz.converged) st->nonconverged++;
       const double t1 = now_s();
       TruncBlocksResult t;
       double t2, t3, t4, ef;
       if (r2l) {
-        op_expand(c, D3S_R2L, ml, d, mr, wl, wr, s->renv[i], s->mpo[i], s->site[i], p->alpha, Mt);
+        op_expand_blocks(c, cur.h, D3S_R2L, s->renv[i], s->mpo[i], xp, p->alpha, Mt);
         D3S_HIP(hipStreamSynchronize(c->stream));
         t2 = now_s();
         const int mll = s->m[i - 1];
@@ -669,13 +1105,19 @@ void op_sweep_blocks(Ctx* c, d3s_state* s, SymChain& sym, d3s_sweep_params* p, d
         s->m[i] = t.k;
         sym.bonds[i] = Sectors(sym.nq, (int)t.dim.size(), t.q.data(), t.dim.data());
         t3 = now_s();
-        op_update_env(c, D3S_R2L, t.k, d, mr, wl, wr, s->renv[i], s->mpo[i], s->site[i], s->renv[i - 1]);
+        {
+          PlanGuard e;
+          site_plan(c, e.h, s, sym, i, false, false);
+          op_update_env_blocks(c, e.h, D3S_R2L, s->renv[i], s->mpo[i], s->site[i], s->renv[i - 1]);
+        }
         D3S_HIP(hipStreamSynchronize(c->stream));
         t4 = now_s();
-        ef = op_energy(c, mll, d, t.k, s->w[i - 1], wl, s->lenv[i - 1], s->mpo[i - 1], s->renv[i - 1], s->site[i - 1]);
+        release_block_heff(nxt.h);
+        site_plan(c, nxt.h, s, sym, i - 1, true, true);
+        ef = op_energy_blocks(c, nxt.h, s->lenv[i - 1], s->mpo[i - 1], s->renv[i - 1], s->site[i - 1]);
         s->center = i - 1;
       } else {
-        op_expand(c, D3S_L2R, ml, d, mr, wl, wr, s->lenv[i], s->mpo[i], s->site[i], p->alpha, Mt);
+        op_expand_blocks(c, cur.h, D3S_L2R, s->lenv[i], s->mpo[i], xp, p->alpha, Mt);
         D3S_HIP(hipStreamSynchronize(c->stream));
         t2 = now_s();
         const int mrr = s->m[i + 2];
@@ -687,15 +1129,23 @@ void op_sweep_blocks(Ctx* c, d3s_state* s, SymChain& sym, d3s_sweep_params* p, d
         s->m[i + 1] = t.k;
         sym.bonds[i + 1] = Sectors(sym.nq, (int)t.dim.size(), t.q.data(), t.dim.data());
         t3 = now_s();
-        op_update_env(c, D3S_L2R, ml, d, t.k, wl, wr, s->lenv[i], s->mpo[i], s->site[i], s->lenv[i + 1]);
+        {
+          PlanGuard e;
+          site_plan(c, e.h, s, sym, i, false, false);
+          op_update_env_blocks(c, e.h, D3S_L2R, s->lenv[i], s->mpo[i], s->site[i], s->lenv[i + 1]);
+        }
         D3S_HIP(hipStreamSynchronize(c->stream));
         t4 = now_s();
-        ef = op_energy(c, t.k, d, mrr, wr, s->w[i + 2], s->lenv[i + 1], s->mpo[i + 1], s->renv[i + 1], s->site[i + 1]);
+        release_block_heff(nxt.h);
+        site_plan(c, nxt.h, s, sym, i + 1, true, true);
+        ef = op_energy_blocks(c, nxt.h, s->lenv[i + 1], s->mpo[i + 1], s->renv[i + 1], s->site[i + 1]);
         s->center = i + 1;
       }
+      std::swap(cur.h, nxt.h);
       const double t5 = now_s();
       r.k = t.k;
       r.matvecs = lz.matvecs;
+      r.f64_matvecs = lz.f64_matvecs;
       r.lambda = lam;
       r.e_f = ef;
       r.alpha = p->alpha;

@@ -37,7 +37,7 @@ struct Error {
 enum WsSlot {
   WS_T1 = 0, WS_T2, WS_LZ_V, WS_LZ_W, WS_LZ_COEF, WS_RED, WS_GRAM, WS_EIGVAL,
   WS_EIGTMP, WS_UKT, WS_X, WS_MT, WS_CAST_L, WS_CAST_R, WS_CAST_X, WS_CAST_Y,
-  WS_CAST_W, WS_REF, WS_PSI, WS_INFO, WS_NBR, WS_MISC, WS_SPLITK, WS_DESC, WS_BLK_X, WS_XPACK, WS_GPACK, WS_GVAL, WS_NSLOTS
+  WS_CAST_W, WS_REF, WS_PSI, WS_INFO, WS_NBR, WS_MISC, WS_SPLITK, WS_DESC, WS_BLK_X, WS_XPACK, WS_GPACK, WS_GVAL, WS_TUNE, WS_PK, WS_NSLOTS
 };
 
 struct Ctx {
@@ -52,6 +52,9 @@ struct Ctx {
   std::string last_error;
   int tile_config = -1;              // GEMM tile configuration (-1 = heuristic)
   bool splitk_off = false;           // disable split-K (tests compare both paths)
+  bool autotune = false;             // time tile configurations on first use of a shape
+  std::unordered_map<std::string, int> tune_cache;
+  std::string tune_path;
   // per-kernel profiling of H_eff: events around GEMM-1, W-map, GEMM-2
   bool prof = false;
   int prof_cap = 0, prof_n = 0;
@@ -97,6 +100,12 @@ int grouped_tile(int cfg);
 // sort tasks largest-first, pick the tile size, compute tile prefix sums and
 // upload the tables (synchronises the stream)
 void grouped_finalize(Ctx* c, GroupedPlan& g);
+// recompute the tile prefix sums for g.cfg and upload the task table again
+void grouped_retile(Ctx* c, GroupedPlan& g);
+// autotuner (autotune.hip)
+void autotune_load(Ctx* c);
+void tuned_gemm(Ctx* c, d3s_prec p, const GemmArgs& g);
+void tune_grouped(Ctx* c, GroupedPlan& g, const void* A, const void* B, void* C);
 void grouped_release(GroupedPlan& g);
 void grouped_gemm(Ctx* c, d3s_prec p, const GroupedPlan& g, const void* A, const void* B, void* C,
                   double alpha);
@@ -112,6 +121,26 @@ void wmap_l2r(Ctx* c, d3s_prec p, const void* T1, const void* W, void* out, long
 // Y contiguous (ml, d, mr, wr); Z contiguous (wl, ml, d, mr).
 void wmap_r2l(Ctx* c, d3s_prec p, const void* Y, const void* W, void* Z,
               int ml, int d, int mr, int wl, int wr, double alpha);
+
+// Block-sparse W-map (see kernels.hip): tasks over (left sector, right sector)
+// pairs; ents[idx0 .. idx0+nin) are the input entries, the next nout the
+// output entries; chunk0 = first 256-element chunk of the task.
+struct WmapTask { int i_off, di, j_off, dj, nin, nout, idx0, chunk0; };
+struct WmapEnt { long off; int wp, pad_; };
+struct WmapPlan {
+  std::vector<WmapTask> tasks;
+  std::vector<WmapEnt> ents;
+  WmapTask* d_tasks = nullptr;
+  WmapEnt* d_ents = nullptr;
+  int chunks = 0, maxk = 1;
+  long in_rs = 0, out_rs = 0;
+};
+// append a task (skipped when it has no outputs); upload() copies the tables
+void wmap_add(WmapPlan& w, int i_off, int di, int j_off, int dj, const std::vector<WmapEnt>& ins,
+              const std::vector<WmapEnt>& outs);
+void wmap_upload(Ctx* c, WmapPlan& w);
+void wmap_release(WmapPlan& w);
+void wmap_blocks(Ctx* c, d3s_prec p, const void* in, const void* W, void* out, const WmapPlan& w, double alpha);
 
 // deterministic reductions (FP64)
 void dot_f64(Ctx* c, const double* x, const double* y, long n, double* out_dev);
@@ -156,7 +185,7 @@ TruncResult op_truncate(Ctx* c, d3s_dir dir, int ml, int d, int mr, long width,
                         const double* Mt, const double* psi, int kmax, double eps,
                         const double* nbr, long nbr_other, double* site_out, double* nbr_out,
                         double* s_host, bool renormalize);
-struct LanczosResult { double theta; int matvecs; bool converged; int restarts; };
+struct LanczosResult { double theta; int matvecs; bool converged; int restarts; int f64_matvecs = 0; };
 LanczosResult op_lanczos(Ctx* c, d3s_prec p, int ml, int d, int mr, int wl, int wr,
                          const double* L, const double* W, const double* R, double* psi,
                          double tol, int kmax, int max_matvecs);
@@ -183,7 +212,22 @@ struct Sectors {
 // Grouped-GEMM plans of one block-sparse H_eff (and its captured graph).
 struct BlockHeff {
   int ml = 0, mr = 0, d = 0, wl = 0, wr = 0;
-  GroupedPlan g1, g2;
+  Sectors left, right;                   // the bonds the plan was built for
+  std::vector<int> pq, wql, wqr;         // charges: physical (d*nq), MPO bonds (wl*nq, wr*nq)
+  // psi / out layout of the H_eff products: dense (ml, d, mr), or packed:
+  // the allowed blocks (i, s) one after the other, each dim_i x dim_j row-major
+  bool packed = false;
+  std::vector<long> poff;                // packed offset of block (i, s) at i*d + s, -1 if forbidden
+  long npacked = 0;
+  GroupedPlan g1, g2;                    // H_eff: GEMM-1 and GEMM-2
+  WmapPlan wm;                           // H_eff: T1 -> T2
+  // built on first use:
+  WmapPlan wm_x;                         // L2R expansion: T1 -> P columns of [psi | P]
+  GroupedPlan g_el;                      // L2R environment: site^T * T2
+  GroupedPlan g_y;                       // R2L: Y = psi * R^T
+  WmapPlan wm_yx;                        // R2L expansion: Y -> P rows of [psi ; P]
+  WmapPlan wm_yz;                        // R2L environment: Y -> Z
+  GroupedPlan g_er;                      // R2L environment: site * Z^T
   double flops = 0.0;
   void* graph = nullptr;
   void* graph_exec = nullptr;
@@ -194,10 +238,27 @@ struct BlockHeff {
   int graph_prec = -1;
 };
 void build_block_heff(Ctx* c, BlockHeff& h, const Sectors& left, const Sectors& right, int d, int wl, int wr,
-                      const int* phys_q, const int* wq_left, const int* wq_right);
+                      const int* phys_q, const int* wq_left, const int* wq_right, bool packed = false,
+                      bool with_g2 = true);
+// dense (ml, d, mr) site tensor <-> packed blocks of a packed plan; unpack
+// clears the rest of the dense tensor; `rowlen` is the length of a dense
+// (a, s) row (mr for a site tensor, (1+wr)*mr for [psi | P]).
+void pack_psi(Ctx* c, const BlockHeff& h, const double* dense, double* packed);
+void unpack_psi(Ctx* c, const BlockHeff& h, const double* packed, double* dense, long rowlen, bool clear);
 void release_block_heff(BlockHeff& h);
 void op_apply_heff_blocks(Ctx* c, BlockHeff& h, d3s_prec p, const void* L, const void* W, const void* R,
                           const void* psi, void* out, bool use_graph);
+// Block-sparse expansion (FP64): writes the allowed blocks of Mt = [psi | P]
+// (L2R, env = L, row length (1+wr)*mr) or [psi ; P] (R2L, env = R, row length
+// d*mr) and zeroes the rest.
+void op_expand_blocks(Ctx* c, BlockHeff& h, d3s_dir dir, const double* env, const double* W, const double* psi,
+                      double alpha, double* Mt);
+// Block-sparse environment update (FP64) for a site tensor on the plan's bonds.
+void op_update_env_blocks(Ctx* c, BlockHeff& h, d3s_dir dir, const double* env_in, const double* W,
+                          const double* site, double* env_out);
+// <psi|H_eff|psi> / <psi|psi> with the block H_eff (FP64)
+double op_energy_blocks(Ctx* c, BlockHeff& h, const double* L, const double* W, const double* R,
+                        const double* psi);
 
 // Charges of one symmetric chain (host copies of the caller's d3s_symmetry).
 struct SymChain {
@@ -224,9 +285,13 @@ TruncBlocksResult op_truncate_blocks(Ctx* c, d3s_dir dir, const Sectors& left, c
 double op_prepare_blocks(Ctx* c, d3s_state* s, SymChain& sym, double eps);
 void op_sweep_blocks(Ctx* c, d3s_state* s, SymChain& sym, d3s_sweep_params* p, d3s_sweep_stats* st,
                      bool use_graph);
+// Lanczos with block-sparse products on a dense site tensor psi.  With a
+// packed plan the Krylov vectors hold only the allowed blocks (length
+// plan.npacked); the Ritz vector is written back to psi (dense, forbidden
+// entries zero) and, when `packed_out` is given, also kept there packed.
 LanczosResult op_lanczos_blocks(Ctx* c, d3s_prec p, BlockHeff& plan, const double* L, const double* W,
                                 const double* R, double* psi, double tol, int kmax, int max_matvecs,
-                                bool use_graph);
+                                bool use_graph, double* packed_out = nullptr);
 void syevd_batched_f64(Ctx* c, int n, int batch, double* A, double* evals);
 
 // host symmetric eigensolver (cyclic Jacobi) for small tridiagonal projections

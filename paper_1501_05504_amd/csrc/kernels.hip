@@ -150,6 +150,76 @@ void wmap_r2l_t(Ctx* c, const void* Y, const void* W, void* Z, int ml, int d, in
   D3S_HIP(hipGetLastError());
 }
 
+// Block-sparse W-map over a table of tasks, one per (left sector i, right
+// sector j) pair.  A task lists its allowed input channel pairs and output
+// channel pairs as entries {offset within a row, partial W index}; for an
+// element (a, y) of the D_i x D_j block
+//   out[a*out_rs + e_out.off + y] = alpha * sum_k W[e_in[k].wp + e_out.wp] * in[a*in_rs + e_in[k].off + y]
+// (the W index is the sum of the two partial indices).  Workgroups take
+// 256-element chunks of the block; the task's W sub-matrix sits in LDS.
+// Nothing outside the listed blocks is read or written.
+template <typename Tin, typename Tout, typename Tc, int MAXK>
+__global__ __launch_bounds__(kThreads)
+void wmap_blocks_kernel(const Tin* __restrict__ in, const Tc* __restrict__ Wg, Tout* __restrict__ out,
+                        const WmapTask* __restrict__ tasks, int ntasks, const WmapEnt* __restrict__ ents,
+                        long in_rs, long out_rs, Tc alpha) {
+  __shared__ Tc sW[MAXK * MAXK];
+  __shared__ long sInOff[MAXK], sOutOff[MAXK];
+  __shared__ int sInW[MAXK], sOutW[MAXK];
+  int lo = 0, hi = ntasks - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tasks[mid].chunk0 <= (int)blockIdx.x) lo = mid;
+    else hi = mid - 1;
+  }
+  const WmapTask tk = tasks[lo];
+  const int nin = tk.nin, nout = tk.nout;
+  for (int i = threadIdx.x; i < nin; i += blockDim.x) {
+    sInOff[i] = ents[tk.idx0 + i].off;
+    sInW[i] = ents[tk.idx0 + i].wp;
+  }
+  for (int i = threadIdx.x; i < nout; i += blockDim.x) {
+    sOutOff[i] = ents[tk.idx0 + nin + i].off;
+    sOutW[i] = ents[tk.idx0 + nin + i].wp;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nin * nout; i += blockDim.x) {
+    const int o = i / nin, k = i - o * nin;
+    sW[o * MAXK + k] = alpha * Wg[sInW[k] + sOutW[o]];
+  }
+  __syncthreads();
+  const long e = (long)((int)blockIdx.x - tk.chunk0) * blockDim.x + threadIdx.x;
+  if (e >= (long)tk.di * tk.dj) return;
+  const long a = tk.i_off + e / tk.dj, y = tk.j_off + e % tk.dj;
+  const Tin* src = in + a * in_rs + y;
+  Tout* dst = out + a * out_rs + y;
+  Tc v[MAXK];
+#pragma unroll
+  for (int k = 0; k < MAXK; ++k)
+    if (k < nin) v[k] = (Tc)Cvt<Tin>::ld(src[sInOff[k]]);
+  for (int o = 0; o < nout; ++o) {
+    Tc acc = 0;
+#pragma unroll
+    for (int k = 0; k < MAXK; ++k)
+      if (k < nin) acc += sW[o * MAXK + k] * v[k];
+    dst[sOutOff[o]] = Cvt<Tout>::st(acc);
+  }
+}
+
+template <typename Tin, typename Tout, typename Tc>
+void wmap_blocks_t(Ctx* c, const void* in, const void* W, void* out, const WmapPlan& w, double alpha) {
+  dim3 grid((unsigned)w.chunks), block(kThreads);
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, grid, block, 0, c->stream, (const Tin*)in, (const Tc*)W, (Tout*)out, w.d_tasks,
+                       (int)w.tasks.size(), w.d_ents, w.in_rs, w.out_rs, (Tc)alpha);
+  };
+  if (w.maxk <= 16) go(wmap_blocks_kernel<Tin, Tout, Tc, 16>);
+  else if (w.maxk <= 32) go(wmap_blocks_kernel<Tin, Tout, Tc, 32>);
+  else if (w.maxk <= 80) go(wmap_blocks_kernel<Tin, Tout, Tc, 80>);
+  else throw Error{D3S_EINVAL, "block W-map: more than 80 channel pairs"};
+  D3S_HIP(hipGetLastError());
+}
+
 // ---------------------------------------------------------------- reductions
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -334,6 +404,13 @@ void wmap_r2l(Ctx* c, d3s_prec p, const void* Y, const void* W, void* Z, int ml,
   if (p == D3S_F64) wmap_r2l_t<double, double, double>(c, Y, W, Z, ml, d, mr, wl, wr, alpha);
   else if (p == D3S_F32) wmap_r2l_t<float, float, float>(c, Y, W, Z, ml, d, mr, wl, wr, alpha);
   else wmap_r2l_t<float, bf16_t, float>(c, Y, W, Z, ml, d, mr, wl, wr, alpha);
+}
+
+void wmap_blocks(Ctx* c, d3s_prec p, const void* in, const void* W, void* out, const WmapPlan& w, double alpha) {
+  if (w.tasks.empty() || w.chunks <= 0) return;
+  if (p == D3S_F64) wmap_blocks_t<double, double, double>(c, in, W, out, w, alpha);
+  else if (p == D3S_F32) wmap_blocks_t<float, float, float>(c, in, W, out, w, alpha);
+  else wmap_blocks_t<float, bf16_t, float>(c, in, W, out, w, alpha);
 }
 
 void dot_f64(Ctx* c, const double* x, const double* y, long n, double* out_dev) {

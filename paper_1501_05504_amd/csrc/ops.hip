@@ -81,13 +81,13 @@ void op_apply_heff(Ctx* c, d3s_prec p, int ml, int d, int mr, int wl, int wr, co
   if (ev) D3S_HIP(hipEventRecord(ev[0], c->stream));
   GemmArgs g1{ml * wl, d * mr, ml, L, ml, true, 0, psi, (long)d * mr, false, 0, T1, (long)d * mr, 0,
               1.0, 0.0, 1};
-  gemm(c, p, g1);
+  tuned_gemm(c, p, g1);
   if (ev) D3S_HIP(hipEventRecord(ev[1], c->stream));
   wmap_l2r(c, p, T1, W, T2, (long)wr * mr, ml, d, mr, wl, wr, 1.0);
   if (ev) D3S_HIP(hipEventRecord(ev[2], c->stream));
   GemmArgs g2{ml * d, mr, wr * mr, T2, (long)wr * mr, true, 0, R, (long)wr * mr, true, 0, out, mr, 0,
               1.0, 0.0, 1};
-  gemm(c, p, g2);
+  tuned_gemm(c, p, g2);
   if (ev) D3S_HIP(hipEventRecord(ev[3], c->stream));
 }
 
@@ -483,6 +483,7 @@ LanczosResult lanczos_core(Ctx* c, Matvec& mv, double* x, long n, double tol, in
     res.restarts++;
     copy_f64(c, x, V, n);
   }
+  if (use_f64) res.f64_matvecs = res.matvecs;
   return res;
 }
 }  // namespace
@@ -492,14 +493,20 @@ static LanczosResult lanczos_with(Ctx* c, Matvec& mv, d3s_prec p, double* psi, l
 
 LanczosResult op_lanczos_blocks(Ctx* c, d3s_prec p, BlockHeff& plan, const double* L, const double* W,
                                 const double* R, double* psi, double tol, int kmax, int max_matvecs,
-                                bool use_graph) {
-  const long n = (long)plan.ml * plan.d * plan.mr;
+                                bool use_graph, double* packed_out) {
+  const long n = plan.packed ? plan.npacked : (long)plan.ml * plan.d * plan.mr;
+  if (n <= 0) throw Error{D3S_EINVAL, "lanczos: the site has no symmetry-allowed block"};
   Matvec mv{c, p, plan.ml, plan.d, plan.mr, plan.wl, plan.wr, L, W, R};
   mv.n = n;
   mv.plan = &plan;
   mv.use_graph = use_graph;
   mv.prepare();
-  return lanczos_with(c, mv, p, psi, n, tol, kmax, max_matvecs);
+  if (!plan.packed) return lanczos_with(c, mv, p, psi, n, tol, kmax, max_matvecs);
+  double* x = packed_out ? packed_out : (double*)ws_get(c, WS_PK, sizeof(double) * (size_t)n);
+  pack_psi(c, plan, psi, x);
+  LanczosResult r = lanczos_with(c, mv, p, x, n, tol, kmax, max_matvecs);
+  unpack_psi(c, plan, x, psi, plan.mr, true);
+  return r;
 }
 
 LanczosResult op_lanczos(Ctx* c, d3s_prec p, int ml, int d, int mr, int wl, int wr, const double* L,
@@ -515,13 +522,18 @@ LanczosResult op_lanczos(Ctx* c, d3s_prec p, int ml, int d, int mr, int wl, int 
 static LanczosResult lanczos_with(Ctx* c, Matvec& mv, d3s_prec p, double* psi, long n, double tol, int kmax,
                                   int max_matvecs) {
   if (p == D3S_F64) return lanczos_core(c, mv, psi, n, tol, kmax, max_matvecs, true);
-  // Mixed precision: converge on the low-precision operator to its own
-  // accuracy, then refine with FP64 products: Lanczos on the exact operator
-  // warm-started from that Ritz vector needs only a few FP64 products because
-  // the start vector is already close to the eigenvector.
-  const double low_tol = (p == D3S_F32) ? 1e-5 : 3e-3;
-  LanczosResult r1 = lanczos_core(c, mv, psi, n, low_tol, kmax, max_matvecs, false);
-  LanczosResult r2 = lanczos_core(c, mv, psi, n, tol, kmax, std::max(1, max_matvecs - r1.matvecs), true);
+  // Mixed precision (products in FP32 / BF16, Krylov vectors, orthogonalisation
+  // and the tridiagonal problem in FP64):
+  // 1. Lanczos on the low-precision operator down to what it resolves;
+  // 2. FP64 refinement: Lanczos with FP64 products warm-started from that Ritz
+  //    vector.  Its first product already gives the FP64 Rayleigh quotient and
+  //    the exact FP64 residual; it stops once the residual is below
+  //    max(tol, 1e-7) |theta|.  The Ritz value is then an FP64 Rayleigh
+  //    quotient, whose error is quadratic in the residual (<= r^2 / gap).
+  const double low_tol = (p == D3S_F32) ? 1e-6 : 3e-3;
+  const double refine_tol = std::max(tol, 1e-7);
+  LanczosResult r1 = lanczos_core(c, mv, psi, n, std::max(tol, low_tol), kmax, max_matvecs, false);
+  LanczosResult r2 = lanczos_core(c, mv, psi, n, refine_tol, kmax, std::max(1, max_matvecs - r1.matvecs), true);
   r2.matvecs += r1.matvecs;
   r2.restarts += r1.restarts;
   return r2;

@@ -151,6 +151,7 @@ void op_sweep(Ctx* c, d3s_state* s, d3s_sweep_params* p, d3s_sweep_stats* st) {
     double t5 = now();
     r.k = t.k;
     r.matvecs = lz.matvecs;
+    r.f64_matvecs = lz.f64_matvecs;
     r.lambda = lam;
     r.e_f = ef;
     r.alpha = p->alpha;
@@ -193,6 +194,7 @@ void op_sweep(Ctx* c, d3s_state* s, d3s_sweep_params* p, d3s_sweep_stats* st) {
     double t5 = now();
     r.k = t.k;
     r.matvecs = lz.matvecs;
+    r.f64_matvecs = lz.f64_matvecs;
     r.lambda = lam;
     r.e_f = ef;
     r.alpha = p->alpha;

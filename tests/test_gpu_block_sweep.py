@@ -113,3 +113,50 @@ def test_block_sweep_mixed_precision(ctx):
     H = ed.spin_chain_hamiltonian(l, {(i, i + 1): 1.0 for i in range(l - 1)})
     e_ed = ed.ground_energy(H, mask=ed.spin_sz(l) == 0)
     assert abs(E - e_ed) < 1e-8
+
+
+def test_local_minimum_escape_sec7_1(ctx):
+    """Sec. 7.1: a U(1) spin chain (l = 20, Sz = 0, m = 20) started from a
+    state whose three rightmost sites carry Sz = +1/2 in every basis state.
+    Without enrichment (alpha = 0) the sweep can only remove states and stays
+    stuck; with subspace expansion it reaches the paper's m = 20 energy
+    -8.6824724 and restores the +-Sz symmetry of the bond sectors."""
+    l, m = 20, 20
+    phys = abi.SPIN_HALF_CHARGES
+    mpo = abi.heisenberg_mpo(l)
+    chan = abi.mpo_bond_charges(mpo, abi.mpo_spin_charges(1))
+
+    def crafted():
+        secs = synth.initial_sectors(l, phys, [0], m)
+        secs[l - 3] = (np.array([[-1]]), np.array([3]))      # left part 2Sz = -1 <-> right part +1
+        rng_tensors = []
+        rng = np.random.default_rng(61)
+        for i in range(l):
+            ql, qr = synth.expand_charges(*secs[i]), synth.expand_charges(*secs[i + 1])
+            t = rng.standard_normal((len(ql), 2, len(qr))) * synth.mask_site(ql, np.array(phys), qr)
+            rng_tensors.append(t)
+        return rng_tensors, secs
+
+    def run(alpha, adaptive, sweeps):
+        tensors, secs = crafted()
+        st = abi.State(mpo, tensors, m, device=DEV)
+        sym = abi.Symmetry(phys, chan, secs)
+        e0 = ctx.prepare_blocks(st, sym)
+        params = abi.sweep_params(alpha=alpha, adaptive=adaptive, e_before=e0)
+        E = None
+        for _ in range(sweeps):
+            _, stats, _ = ctx.sweep_blocks(st, sym, params)
+            E = stats.energy
+        return E, sym
+
+    E_stuck, sym0 = run(0.0, False, 8)
+    E_free, sym1 = run(1e-3, True, 16)
+    # without enrichment the bond can only lose states: its charges stay those of the input
+    q17, _ = sym0.sectors(l - 3)
+    assert set(q17.ravel().tolist()) <= {-1}
+    assert E_stuck > E_free + 0.1
+    assert abs(E_free - (-8.6824724)) < 2e-6
+    # the sector distribution of the middle bond is symmetric under Sz -> -Sz again
+    qm, dm = sym1.sectors(l // 2)
+    pairs = dict(zip(qm.ravel().tolist(), dm.tolist()))
+    assert all(pairs.get(-q) == d for q, d in pairs.items())

@@ -105,3 +105,62 @@ def test_block_heff_graph_replays(ctx):
         x.mul_(0.5).add_(out_e / (1.0 + out_e.abs().max()))      # eager work, new input in place
         x.mul_(dev(case["mask"].astype(np.float64)))
     plan.close()
+
+
+def test_block_heff_autotuned_plan(tmp_path):
+    """A plan built with autotuning on (both grouped tile sizes timed) gives
+    the oracle's result."""
+    case = hubbard_block_case(160, 150, 9)
+    ref = C.apply_heff(case["L"], case["W"], case["R"], case["psi"])
+    c = abi.Context(0)
+    try:
+        c.set_autotune(True, tmp_path / "tune.txt")
+        plan = make_plan(c, case)
+        out = torch.empty(case["psi"].shape, dtype=torch.float64, device=DEV)
+        plan.apply(dev(case["L"]), dev(case["W"]), dev(case["R"]), dev(case["psi"]), out)
+        torch.cuda.synchronize()
+        assert rel_err(out.cpu().numpy(), ref) < 1e-12
+        plan.close()
+    finally:
+        c.close()
+
+
+@pytest.mark.parametrize("ml,mr,seed", [(40, 52, 11), (300, 257, 12)])
+def test_block_expand_equals_dense_oracle(ctx, ml, mr, seed):
+    """[psi | alpha P] and [psi ; alpha P] from the grouped launches equal the
+    oracle's dense expansion entry by entry (zeros outside the blocks)."""
+    case = hubbard_block_case(ml, mr, seed)
+    L, W, R, psi = case["L"], case["W"], case["R"], case["psi"]
+    ml, mr = psi.shape[0], psi.shape[2]
+    wl, wr = W.shape[0], W.shape[1]
+    alpha = 0.43
+    plan = make_plan(ctx, case)
+    Mt = torch.full((ml * 4, (1 + wr) * mr), float("nan"), dtype=torch.float64, device=DEV)
+    plan.expand_subspace(abi.L2R, dev(L), dev(W), dev(psi), alpha, Mt)
+    Mt2 = torch.full(((1 + wl) * ml, 4 * mr), float("nan"), dtype=torch.float64, device=DEV)
+    plan.expand_subspace(abi.R2L, dev(R), dev(W), dev(psi), alpha, Mt2)
+    torch.cuda.synchronize()
+    ref = C.expanded_tensor_l2r(psi, C.expansion_term_l2r(L, W, psi, alpha))
+    ref2 = C.expanded_tensor_r2l(psi, C.expansion_term_r2l(R, W, psi, alpha))
+    assert rel_err(Mt.cpu().numpy(), ref) < 1e-12
+    assert rel_err(Mt2.cpu().numpy(), ref2) < 1e-12
+    plan.close()
+
+
+@pytest.mark.parametrize("ml,mr,seed", [(40, 52, 21), (300, 257, 22)])
+def test_block_update_env_equals_dense_oracle(ctx, ml, mr, seed):
+    """Both environment updates from the grouped launches equal the oracle's
+    dense ones entry by entry (zeros outside the allowed blocks)."""
+    case = hubbard_block_case(ml, mr, seed)
+    L, W, R, psi = case["L"], case["W"], case["R"], case["psi"]
+    ml, mr = psi.shape[0], psi.shape[2]
+    wl, wr = W.shape[0], W.shape[1]
+    plan = make_plan(ctx, case)
+    out = torch.full((mr, wr, mr), float("nan"), dtype=torch.float64, device=DEV)
+    plan.update_env(abi.L2R, dev(L), dev(W), dev(psi), out)
+    out2 = torch.full((ml, wl, ml), float("nan"), dtype=torch.float64, device=DEV)
+    plan.update_env(abi.R2L, dev(R), dev(W), dev(psi), out2)
+    torch.cuda.synchronize()
+    assert rel_err(out.cpu().numpy(), C.update_left(L, W, psi)) < 1e-12
+    assert rel_err(out2.cpu().numpy(), C.update_right(R, W, psi)) < 1e-12
+    plan.close()

@@ -112,6 +112,34 @@ def test_apply_heff_split_k_equals_unsplit(ctx, shape):
     assert np.array_equal(out.cpu().numpy(), outs[0])
 
 
+def test_autotune_picks_a_config_and_keeps_parity(tmp_path):
+    """With autotuning on, the first product of each GEMM shape is timed in
+    every tile configuration; results still match the oracle, the decisions
+    land in the cache file, and a new context reads them back without timing
+    again."""
+    cache = tmp_path / "tune.txt"
+    shape = (200, 4, 257, 6, 6)
+    L, W, R, psi = _inputs(*shape, seed=13)
+    ref = C.apply_heff(L, W, R, psi)
+    for round_ in range(2):
+        c = abi.Context(0)
+        try:
+            c.set_autotune(True, cache)
+            out = torch.empty(psi.shape, dtype=torch.float64, device=DEV)
+            for _ in range(2):
+                c.apply_heff(dev(L), dev(W), dev(R), dev(psi), out)
+                torch.cuda.synchronize()
+                assert rel_err(out.cpu().numpy(), ref) < 1e-12
+        finally:
+            c.close()
+        lines = cache.read_text().split("\n")
+        lines = [ln for ln in lines if ln]
+        assert len(lines) == 2, lines          # GEMM-1 and GEMM-2, tuned once only
+        for ln in lines:
+            key, cfg = ln.split()
+            assert key.startswith("gemm:") and int(cfg) in (0, 1, 2, 3)
+
+
 @pytest.mark.parametrize("shape", SHAPES[2:], ids=[str(s) for s in SHAPES[2:]])
 def test_apply_heff_f32(ctx, shape):
     ml, d, mr, wl, wr = shape
