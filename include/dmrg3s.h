@@ -93,6 +93,12 @@ d3s_status d3s_set_tile_config(d3s_ctx ctx, int cfg);
  * of "key config" lines read now and appended to on every new decision.
  * Tuning never happens during graph capture or for accumulating products. */
 d3s_status d3s_set_autotune(d3s_ctx ctx, int enable, const char* cache_path);
+/* Batched eigensolver of the per-sector Gram matrices in the block-sparse
+ * truncation (rocSOLVER, FP64): kind 1 = divide and conquer (syevd), 2 =
+ * Jacobi (syevj), 0 = Jacobi for sizes <= jacobi_max_n and divide and
+ * conquer above (the default: kind 0, jacobi_max_n 0, i.e. syevd).  Both
+ * give the eigenpairs to FP64 accuracy; only the speed differs. */
+d3s_status d3s_set_eigensolver(d3s_ctx ctx, int kind, int jacobi_max_n);
 /* Split-K of GEMMs whose tiles cannot fill the device (default on; the
  * partial products are summed in a fixed order, so results stay
  * deterministic).  enable = 0 turns it off. */
@@ -313,6 +319,8 @@ typedef struct {
   int lanczos_max_matvecs; /* products per site update (2000) */
   d3s_prec prec;         /* arithmetic of the eigensolver's H_eff products */
   double e_before;       /* in/out: energy of the state entering the next site update */
+  int m_limit;           /* bond dimension limit of this sweep (<= 0 or > mmax: the state's mmax);
+                            lets a run grow m from sweep to sweep in one allocation */
 } d3s_sweep_params;
 
 /* One record per site update (steps 1-8 of Sec. 5). */

@@ -42,7 +42,7 @@ class d3s_state(ctypes.Structure):
 class d3s_sweep_params(ctypes.Structure):
     _fields_ = [("alpha", c_double), ("adaptive_alpha", c_int), ("eps", c_double),
                 ("lanczos_tol", c_double), ("lanczos_kmax", c_int), ("lanczos_max_matvecs", c_int),
-                ("prec", c_int), ("e_before", c_double)]
+                ("prec", c_int), ("e_before", c_double), ("m_limit", c_int)]
 
 
 class d3s_site_record(ctypes.Structure):
@@ -73,6 +73,7 @@ _version = _sig("d3s_version", ctypes.c_char_p, [])
 _set_tile_config = _sig("d3s_set_tile_config", c_int, [c_void_p, c_int])
 _set_splitk = _sig("d3s_set_splitk", c_int, [c_void_p, c_int])
 _set_autotune = _sig("d3s_set_autotune", c_int, [c_void_p, c_int, ctypes.c_char_p])
+_set_eig = _sig("d3s_set_eigensolver", c_int, [c_void_p, c_int, c_int])
 _profile_begin = _sig("d3s_profile_begin", c_int, [c_void_p, c_int])
 _profile_end = _sig("d3s_profile_end", c_int, [c_void_p, c_double_p, c_int_p])
 _apply_heff = _sig("d3s_apply_heff", c_int, [c_void_p, c_int] + [c_int] * 5 + [c_void_p] * 5)
@@ -198,6 +199,10 @@ class Context:
     def set_autotune(self, enable, cache_path=None):
         self._check(_set_autotune(self.h, 1 if enable else 0,
                                   None if cache_path is None else str(cache_path).encode()))
+
+    def set_eigensolver(self, kind, jacobi_max_n=0):
+        """0 auto (Jacobi up to jacobi_max_n), 1 divide and conquer, 2 Jacobi."""
+        self._check(_set_eig(self.h, int(kind), int(jacobi_max_n)))
 
     def set_splitk(self, enable):
         self._check(_set_splitk(self.h, 1 if enable else 0))
@@ -478,8 +483,8 @@ def mpo_bond_charges(mpo_blocks, channel_q):
 
 
 def sweep_params(alpha=1e-3, adaptive=True, eps=1e-14, tol=1e-12, kmax=40, max_matvecs=2000, prec=F64,
-                 e_before=0.0):
-    return d3s_sweep_params(alpha, 1 if adaptive else 0, eps, tol, kmax, max_matvecs, prec, e_before)
+                 e_before=0.0, m_limit=0):
+    return d3s_sweep_params(alpha, 1 if adaptive else 0, eps, tol, kmax, max_matvecs, prec, e_before, m_limit)
 
 
 # --- symmetry blocks -------------------------------------------------------

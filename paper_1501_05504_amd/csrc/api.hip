@@ -81,7 +81,7 @@ d3s_status d3s_create(d3s_ctx* out, int device, void* stream, const d3s_allocato
     ctx->c.has_alloc = true;
   }
   if (hipSetDevice(device) != hipSuccess ||
-      hipHostMalloc((void**)&ctx->c.host_red, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc((void**)&ctx->c.host_red, 512 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
     delete ctx;
     return D3S_EDEVICE;
@@ -98,6 +98,8 @@ void d3s_destroy(d3s_ctx ctx) {
   d3s::ws_release_all(&ctx->c);
   if (ctx->c.solver) rocblas_destroy_handle((rocblas_handle)ctx->c.solver);
   if (ctx->c.host_red) (void)hipHostFree(ctx->c.host_red);
+  for (void* e : ctx->c.lz_ev)
+    if (e) (void)hipEventDestroy((hipEvent_t)e);
   delete ctx;
 }
 
@@ -130,6 +132,16 @@ d3s_status d3s_set_autotune(d3s_ctx ctx, int enable, const char* cache_path) {
     ctx->c.autotune = (enable != 0);
     ctx->c.tune_path = cache_path ? std::string(cache_path) : std::string();
     d3s::autotune_load(&ctx->c);
+    return D3S_OK;
+  });
+}
+
+d3s_status d3s_set_eigensolver(d3s_ctx ctx, int kind, int jacobi_max_n) {
+  return guarded(ctx, [&] {
+    D3S_REQUIRE(kind >= 0 && kind <= 2, "kind must be 0 (auto), 1 (divide and conquer) or 2 (Jacobi)");
+    D3S_REQUIRE(jacobi_max_n >= 0, "jacobi_max_n must be >= 0");
+    ctx->c.eig_kind = kind;
+    ctx->c.eig_jacobi_max = jacobi_max_n;
     return D3S_OK;
   });
 }

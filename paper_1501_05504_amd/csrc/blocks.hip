@@ -1060,6 +1060,7 @@ double op_prepare_blocks(Ctx* c, d3s_state* s, SymChain& sym, double eps) {
 // blocks, and the plan built for the post-truncation energy of the next
 // site is the one its eigensolver uses.
 void op_sweep_blocks(Ctx* c, d3s_state* s, SymChain& sym, d3s_sweep_params* p, d3s_sweep_stats* st, bool use_graph) {
+  const int mlim = (p->m_limit > 0 && p->m_limit < s->mmax) ? p->m_limit : s->mmax;
   const int l = s->l, d = s->d;
   if (s->center != l - 1) throw Error{D3S_EINVAL, "sweep: the orthogonality centre must be on site l-1"};
   int wmax = 1;
@@ -1098,7 +1099,7 @@ void op_sweep_blocks(Ctx* c, d3s_state* s, SymChain& sym, d3s_sweep_params* p, d
         t2 = now_s();
         const int mll = s->m[i - 1];
         t = op_truncate_blocks(c, D3S_R2L, sym.bonds[i], sym.bonds[i + 1], d, sym.phys.data(), sym.wq[i].data(), wl,
-                               (long)(1 + wl) * ml, Mt, s->site[i], (int)budget_of(l, d, s->mmax, i), p->eps,
+                               (long)(1 + wl) * ml, Mt, s->site[i], (int)budget_of(l, d, mlim, i), p->eps,
                                s->site[i - 1], (long)mll * d, tmpS, tmpN, true);
         copy_f64(c, tmpS, s->site[i], (long)t.k * d * mr);
         copy_f64(c, tmpN, s->site[i - 1], (long)mll * d * t.k);
@@ -1122,7 +1123,7 @@ void op_sweep_blocks(Ctx* c, d3s_state* s, SymChain& sym, d3s_sweep_params* p, d
         t2 = now_s();
         const int mrr = s->m[i + 2];
         t = op_truncate_blocks(c, D3S_L2R, sym.bonds[i], sym.bonds[i + 1], d, sym.phys.data(), sym.wq[i + 1].data(),
-                               wr, (long)(1 + wr) * mr, Mt, s->site[i], (int)budget_of(l, d, s->mmax, i + 1), p->eps,
+                               wr, (long)(1 + wr) * mr, Mt, s->site[i], (int)budget_of(l, d, mlim, i + 1), p->eps,
                                s->site[i + 1], (long)d * mrr, tmpS, tmpN, true);
         copy_f64(c, tmpS, s->site[i], (long)ml * d * t.k);
         copy_f64(c, tmpN, s->site[i + 1], (long)t.k * d * mrr);

@@ -37,7 +37,7 @@ struct Error {
 enum WsSlot {
   WS_T1 = 0, WS_T2, WS_LZ_V, WS_LZ_W, WS_LZ_COEF, WS_RED, WS_GRAM, WS_EIGVAL,
   WS_EIGTMP, WS_UKT, WS_X, WS_MT, WS_CAST_L, WS_CAST_R, WS_CAST_X, WS_CAST_Y,
-  WS_CAST_W, WS_REF, WS_PSI, WS_INFO, WS_NBR, WS_MISC, WS_SPLITK, WS_DESC, WS_BLK_X, WS_XPACK, WS_GPACK, WS_GVAL, WS_TUNE, WS_PK, WS_NSLOTS
+  WS_CAST_W, WS_REF, WS_PSI, WS_INFO, WS_NBR, WS_MISC, WS_SPLITK, WS_DESC, WS_BLK_X, WS_XPACK, WS_GPACK, WS_GVAL, WS_TUNE, WS_PK, WS_LZ_K, WS_NSLOTS
 };
 
 struct Ctx {
@@ -48,11 +48,14 @@ struct Ctx {
   void* ws_ptr[WS_NSLOTS] = {};
   size_t ws_cap[WS_NSLOTS] = {};
   void* solver = nullptr;            // rocblas_handle, created lazily
-  double* host_red = nullptr;        // pinned host staging for scalars
+  double* host_red = nullptr;        // pinned host staging for scalars (512 doubles)
+  void* lz_ev[2] = {nullptr, nullptr};   // Lanczos step events
   std::string last_error;
   int tile_config = -1;              // GEMM tile configuration (-1 = heuristic)
   bool splitk_off = false;           // disable split-K (tests compare both paths)
   bool autotune = false;             // time tile configurations on first use of a shape
+  int eig_kind = 0;                  // batched eigensolver: 0 auto, 1 divide and conquer, 2 Jacobi
+  int eig_jacobi_max = 0;            // auto: Jacobi up to this size
   std::unordered_map<std::string, int> tune_cache;
   std::string tune_path;
   // per-kernel profiling of H_eff: events around GEMM-1, W-map, GEMM-2
@@ -144,11 +147,20 @@ void wmap_blocks(Ctx* c, d3s_prec p, const void* in, const void* W, void* out, c
 
 // deterministic reductions (FP64)
 void dot_f64(Ctx* c, const double* x, const double* y, long n, double* out_dev);
-// coef[j] = <V_j, w> for j < k, V rows of length n with stride ldv
-void mdot_f64(Ctx* c, const double* V, long ldv, int k, const double* w, long n, double* coef_dev);
-// w += sign * sum_j coef[j] V_j  (coef on device)
+// coef[j] = <V_j, w> for j < k, V rows of length n with stride ldv.  With
+// kdev the row count is *kdev + 1 (read on the device; k is then the
+// largest possible count), so one captured launch serves every step.
+void mdot_f64(Ctx* c, const double* V, long ldv, int k, const double* w, long n, double* coef_dev,
+              const int* kdev = nullptr);
+// Lanczos step end (k from the host, or *kdev): V_{k+1} = w / sqrt(*nrm2) unless k+1 = kk;
+// ab[2k] = c1[k] + c2[k], ab[2k+1] = sqrt(*nrm2)
+void lanczos_tail(Ctx* c, const double* w, long n, const double* nrm2, const double* c1, const double* c2, int k,
+                  const int* kdev, int kk, double* V, double* ab);
+void copy_row_f64(Ctx* c, const double* V, long n, const int* kdev, double* dst);   // dst = V_{*kdev}
+void set_int_dev(Ctx* c, int* p, int v, bool add);                                   // *p = v or *p += v
+// w += sign * sum_j coef[j] V_j  (coef on device; row count k or *kdev + 1)
 void maxpy_f64(Ctx* c, const double* V, long ldv, int k, const double* coef_dev, double sign,
-               double* w, long n);
+               double* w, long n, const int* kdev = nullptr);
 void scale_f64(Ctx* c, double* x, long n, double s_host);
 void scale_by_dev_f64(Ctx* c, double* x, long n, const double* s_dev, bool reciprocal);
 void axpby_f64(Ctx* c, double a, const double* x, double b, double* y, long n);

@@ -244,26 +244,86 @@ void dot_partial_kernel(const double* __restrict__ x, const double* __restrict__
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// coef-partials for k rows: part[j * gridDim.x + block]
+// coef-partials for up to KMAX rows at once: each thread keeps one running
+// sum per row over its grid-stride elements (w is read once), then every row
+// is reduced over the block; part[j * gridDim.x + block].
+template <int KMAX>
 __global__ __launch_bounds__(kThreads)
-void mdot_partial_kernel(const double* __restrict__ V, long ldv, int k, const double* __restrict__ w,
-                         long n, double* __restrict__ part) {
-  __shared__ double sh[kThreads / 64];
-  for (int j = 0; j < k; ++j) {
-    const double* vj = V + (long)j * ldv;
-    double acc = 0.0;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-      acc += vj[i] * w[i];
-    const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) part[(long)j * gridDim.x + blockIdx.x] = s;
+void mdot_partial_kernel(const double* __restrict__ V, long ldv, int k, const int* __restrict__ kdev, int j0,
+                         const double* __restrict__ w, long n, double* __restrict__ part) {
+  __shared__ double sh[kThreads / 64][KMAX];
+  // rows of this launch: j0 .. j0 + kc - 1 of the k (or *kdev + 1) rows
+  const int rows = kdev ? (*kdev + 1) : k;
+  const int kc = min(rows - j0, KMAX);
+  if (kc <= 0) return;
+  const double* Vj = V + (long)j0 * ldv;
+  double acc[KMAX];
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j) acc[j] = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double wi = w[i];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j)
+      if (j < kc) acc[j] += Vj[(long)j * ldv + i] * wi;
   }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j) {
+    if (j < kc) {
+      double v = acc[j];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+      if (lane == 0) sh[wave][j] = v;
+    }
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < kc; j += blockDim.x) {
+    double t = 0.0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += sh[q][j];
+    part[(long)(j0 + j) * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+// End of a Lanczos step k (k from the host, or *kdev): V_{k+1} = w / beta
+// with beta = sqrt(|w|^2) (zero when beta is not positive; skipped when
+// k+1 = kk), and ab[2k] = alpha_k (the projections of both Gram-Schmidt
+// passes on V_k), ab[2k+1] = beta.
+__global__ __launch_bounds__(kThreads)
+void lanczos_tail_kernel(const double* __restrict__ w, long n, const double* __restrict__ nrm2,
+                         const double* __restrict__ c1, const double* __restrict__ c2, int k,
+                         const int* __restrict__ kdev, int kk, double* __restrict__ V, double* __restrict__ ab) {
+  if (kdev) k = *kdev;
+  const double b = sqrt(fmax(*nrm2, 0.0));
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ab[2 * k] = c1[k] + c2[k];
+    ab[2 * k + 1] = b;
+  }
+  if (k + 1 >= kk) return;
+  double* vnext = V + (long)(k + 1) * n;
+  const double f = (b > 0.0) ? 1.0 / b : 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    vnext[i] = w[i] * f;
+}
+
+// dst = V_{*kdev}
+__global__ __launch_bounds__(kThreads)
+void copy_row_kernel(const double* __restrict__ V, long n, const int* __restrict__ kdev, double* __restrict__ dst) {
+  const double* src = V + (long)(*kdev) * n;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+// *p = v, or *p += v
+__global__ void set_int_kernel(int* p, int v, int add) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *p = add ? (*p + v) : v;
 }
 
 // out[j] = sum_b part[j * nb + b] in a fixed order; one block per j
 __global__ __launch_bounds__(kThreads)
-void reduce_rows_kernel(const double* __restrict__ part, int nb, double* __restrict__ out) {
+void reduce_rows_kernel(const double* __restrict__ part, int nb, double* __restrict__ out,
+                        const int* __restrict__ kdev) {
   __shared__ double sh[kThreads / 64];
   const int j = blockIdx.x;
+  if (kdev && j >= *kdev + 1) return;
   double acc = 0.0;
   for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += part[(long)j * nb + b];
   const double s = block_sum(acc, sh);
@@ -271,9 +331,10 @@ void reduce_rows_kernel(const double* __restrict__ part, int nb, double* __restr
 }
 
 __global__ __launch_bounds__(kThreads)
-void maxpy_kernel(const double* __restrict__ V, long ldv, int k, const double* __restrict__ coef,
-                  double sign, double* __restrict__ w, long n) {
+void maxpy_kernel(const double* __restrict__ V, long ldv, int k, const int* __restrict__ kdev,
+                  const double* __restrict__ coef, double sign, double* __restrict__ w, long n) {
   __shared__ double sc[128];
+  if (kdev) k = *kdev + 1;
   for (int j = threadIdx.x; j < k; j += blockDim.x) sc[j] = sign * coef[j];
   __syncthreads();
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
@@ -416,24 +477,54 @@ void wmap_blocks(Ctx* c, d3s_prec p, const void* in, const void* W, void* out, c
 void dot_f64(Ctx* c, const double* x, const double* y, long n, double* out_dev) {
   double* part = (double*)ws_get(c, WS_RED, sizeof(double) * kRedBlocks);
   hipLaunchKernelGGL(dot_partial_kernel, dim3(kRedBlocks), dim3(kThreads), 0, c->stream, x, y, n, part);
-  hipLaunchKernelGGL(reduce_rows_kernel, dim3(1), dim3(kThreads), 0, c->stream, part, kRedBlocks, out_dev);
+  hipLaunchKernelGGL(reduce_rows_kernel, dim3(1), dim3(kThreads), 0, c->stream, part, kRedBlocks, out_dev,
+                     (const int*)nullptr);
   D3S_HIP(hipGetLastError());
 }
 
-void mdot_f64(Ctx* c, const double* V, long ldv, int k, const double* w, long n, double* coef_dev) {
+void mdot_f64(Ctx* c, const double* V, long ldv, int k, const double* w, long n, double* coef_dev,
+              const int* kdev) {
   if (k <= 0) return;
-  const int nb = 256;
+  if (k > 128) throw Error{D3S_EINVAL, "mdot: more than 128 vectors"};
+  // partial count fixed by n (deterministic), at most 256
+  const int nb = (int)std::max<long>(1, std::min<long>(256, (n + 8L * kThreads - 1) / (8L * kThreads)));
   double* part = (double*)ws_get(c, WS_RED, sizeof(double) * (size_t)nb * k);
-  hipLaunchKernelGGL(mdot_partial_kernel, dim3(nb), dim3(kThreads), 0, c->stream, V, ldv, k, w, n, part);
-  hipLaunchKernelGGL(reduce_rows_kernel, dim3(k), dim3(kThreads), 0, c->stream, part, nb, coef_dev);
+  for (int j0 = 0; j0 < k; j0 += 64) {
+    const int kc = std::min(64, k - j0);
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(nb), dim3(kThreads), 0, c->stream, V, ldv, k, kdev, j0, w, n, part);
+    };
+    if (kc <= 8) go(mdot_partial_kernel<8>);
+    else if (kc <= 16) go(mdot_partial_kernel<16>);
+    else if (kc <= 32) go(mdot_partial_kernel<32>);
+    else go(mdot_partial_kernel<64>);
+  }
+  hipLaunchKernelGGL(reduce_rows_kernel, dim3(k), dim3(kThreads), 0, c->stream, part, nb, coef_dev, kdev);
+  D3S_HIP(hipGetLastError());
+}
+
+void lanczos_tail(Ctx* c, const double* w, long n, const double* nrm2, const double* c1, const double* c2, int k,
+                  const int* kdev, int kk, double* V, double* ab) {
+  hipLaunchKernelGGL(lanczos_tail_kernel, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, w, n, nrm2, c1, c2, k,
+                     kdev, kk, V, ab);
+  D3S_HIP(hipGetLastError());
+}
+
+void copy_row_f64(Ctx* c, const double* V, long n, const int* kdev, double* dst) {
+  hipLaunchKernelGGL(copy_row_kernel, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, V, n, kdev, dst);
+  D3S_HIP(hipGetLastError());
+}
+
+void set_int_dev(Ctx* c, int* p, int v, bool add) {
+  hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, c->stream, p, v, add ? 1 : 0);
   D3S_HIP(hipGetLastError());
 }
 
 void maxpy_f64(Ctx* c, const double* V, long ldv, int k, const double* coef_dev, double sign, double* w,
-               long n) {
+               long n, const int* kdev) {
   if (k <= 0) return;
   if (k > 128) throw Error{D3S_EINVAL, "maxpy: more than 128 vectors"};
-  hipLaunchKernelGGL(maxpy_kernel, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, V, ldv, k, coef_dev,
+  hipLaunchKernelGGL(maxpy_kernel, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, V, ldv, k, kdev, coef_dev,
                      sign, w, n);
   D3S_HIP(hipGetLastError());
 }

@@ -177,18 +177,29 @@ void syevd_batched_f64(Ctx* c, int n, int batch, double* A, double* evals) {
   rocblas_handle h = (rocblas_handle)c->solver;
   if (rocblas_set_stream(h, c->stream) != rocblas_status_success)
     throw Error{D3S_EDEVICE, "rocblas_set_stream failed"};
-  double* E = (double*)ws_get(c, WS_EIGTMP, sizeof(double) * (size_t)n * batch);
-  rocblas_int* info = (rocblas_int*)ws_get(c, WS_INFO, sizeof(rocblas_int) * (size_t)std::max(batch, 16));
-  rocblas_status st = rocsolver_dsyevd_strided_batched(h, rocblas_evect_original, rocblas_fill_upper, n, A, n,
-                                                       (rocblas_stride)n * n, evals, n, E, n, info, batch);
+  rocblas_int* info = (rocblas_int*)ws_get(c, WS_INFO, sizeof(rocblas_int) * (size_t)std::max(batch, 16) * 2);
+  // Jacobi (one kernel family, few launches) for small matrices, divide and
+  // conquer for large ones; d3s_set_eigensolver overrides the choice
+  const bool jacobi = (c->eig_kind == 2) || (c->eig_kind == 0 && n <= c->eig_jacobi_max);
+  rocblas_status st;
+  if (jacobi) {
+    double* res = (double*)ws_get(c, WS_EIGTMP, sizeof(double) * (size_t)std::max(batch, 16));
+    st = rocsolver_dsyevj_strided_batched(h, rocblas_esort_ascending, rocblas_evect_original, rocblas_fill_upper, n,
+                                          A, n, (rocblas_stride)n * n, 0.0, res, 100, info + batch, evals, n, info,
+                                          batch);
+  } else {
+    double* E = (double*)ws_get(c, WS_EIGTMP, sizeof(double) * (size_t)n * batch);
+    st = rocsolver_dsyevd_strided_batched(h, rocblas_evect_original, rocblas_fill_upper, n, A, n,
+                                          (rocblas_stride)n * n, evals, n, E, n, info, batch);
+  }
   if (st != rocblas_status_success)
-    throw Error{D3S_EDEVICE, "rocsolver_dsyevd_strided_batched failed (status " + std::to_string((int)st) + ")"};
+    throw Error{D3S_EDEVICE, "rocsolver batched eigensolver failed (status " + std::to_string((int)st) + ")"};
   std::vector<rocblas_int> hinfo(batch);
   D3S_HIP(hipMemcpyAsync(hinfo.data(), info, sizeof(rocblas_int) * batch, hipMemcpyDeviceToHost, c->stream));
   D3S_HIP(hipStreamSynchronize(c->stream));
   for (int b = 0; b < batch; ++b)
     if (hinfo[b] != 0)
-      throw Error{D3S_EDEVICE, "rocsolver_dsyevd_strided_batched did not converge (info " +
+      throw Error{D3S_EDEVICE, "rocsolver batched eigensolver did not converge (info " +
                                    std::to_string(hinfo[b]) + ")"};
 }
 
@@ -378,6 +389,20 @@ struct Matvec {
     }
     yout = (float*)ws_get(c, WS_CAST_Y, 4 * n);
   }
+  // y = H x without any per-product graph (the caller may be capturing):
+  // FP64, or the low-precision product with casts around it
+  void product(const double* x, double* y, bool f64) {
+    if (f64 || p == D3S_F64) {
+      if (plan) op_apply_heff_blocks(c, *plan, D3S_F64, L, W, R, x, y, false);
+      else op_apply_heff(c, D3S_F64, ml, d, mr, wl, wr, L, W, R, x, y);
+      return;
+    }
+    if (p == D3S_F32) cast_f64_to_f32(c, x, (float*)xin, n);
+    else cast_f64_to_bf16(c, x, (bf16_t*)xin, n);
+    if (plan) op_apply_heff_blocks(c, *plan, p, Lc, Wc, Rc, xin, yout, false);
+    else op_apply_heff(c, p, ml, d, mr, wl, wr, Lc, Wc, Rc, xin, yout);
+    cast_f32_to_f64(c, yout, y, n);
+  }
   // low-precision (or FP64) product
   void apply(const double* x, double* y) {
     if (p == D3S_F64) {
@@ -404,17 +429,38 @@ struct Matvec {
 
 // One Lanczos run (with restarts) on the operator `mv`, starting from x
 // (normalised in place, overwritten by the Ritz vector).
+//
+// A step runs entirely on the device and reads its index k from device
+// memory: V_k is copied to a fixed input buffer, multiplied, orthogonalised
+// twice (classical Gram-Schmidt) against V_0..V_k, normalised into V_{k+1},
+// (alpha_k, beta_k) are stored and k is incremented.  Because nothing in it
+// depends on the host, the same step serves every k: with mv.use_graph it
+// is captured once into a hipGraph (after a first eager step has sized
+// every buffer) and replayed per step.  The host copies (alpha_k, beta_k)
+// to pinned memory, enqueues step k+1 before it reads step k and solves the
+// tridiagonal problem, so the device does not idle while the host tests
+// convergence; a step enqueued past convergence is discarded (the Ritz
+// vector uses V_0..V_k only).
 LanczosResult lanczos_core(Ctx* c, Matvec& mv, double* x, long n, double tol, int kmax, int max_mv,
                            bool use_f64) {
   const int kk = (int)std::min<long>(kmax, n);
+  if (kk > 120) throw Error{D3S_EINVAL, "lanczos: at most 120 Krylov vectors"};
   double* V = (double*)ws_get(c, WS_LZ_V, sizeof(double) * (size_t)(kk + 1) * n);
   double* w = (double*)ws_get(c, WS_LZ_W, sizeof(double) * n);
-  double* cf = (double*)ws_get(c, WS_LZ_COEF, sizeof(double) * 512);
+  double* xin = (double*)ws_get(c, WS_BLK_X, sizeof(double) * n);
+  double* cf = (double*)ws_get(c, WS_LZ_COEF, sizeof(double) * 1024);
+  int* kdev = (int*)ws_get(c, WS_LZ_K, 256);
   double* cf1 = cf;          // first Gram-Schmidt coefficients
   double* cf2 = cf + 128;    // second pass
   double* sc = cf + 256;     // scalars
   double* ydev = cf + 384;   // Ritz coefficients
+  double* ab = cf + 512;     // (alpha_k, beta_k) per step
+  double* hab = c->host_red + 256;   // pinned host copy of ab
   LanczosResult res{0.0, 0, false, 0};
+  if (!c->lz_ev[0]) {
+    D3S_HIP(hipEventCreateWithFlags((hipEvent_t*)&c->lz_ev[0], hipEventDisableTiming));
+    D3S_HIP(hipEventCreateWithFlags((hipEvent_t*)&c->lz_ev[1], hipEventDisableTiming));
+  }
   // normalise the start vector
   dot_f64(c, x, x, n, sc);
   double nrm2 = read_scalar(c, sc);
@@ -424,65 +470,117 @@ LanczosResult lanczos_core(Ctx* c, Matvec& mv, double* x, long n, double tol, in
   }
   scale_f64(c, x, n, 1.0 / std::sqrt(nrm2));
   copy_f64(c, x, V, n);
-  std::vector<double> alphas, betas, T, ev, evec;
-  double h[4];
-  for (;;) {
-    alphas.clear();
-    betas.clear();
-    int k = 0;
-    bool stop = false;
-    std::vector<double> y;
-    for (k = 0; k < kk; ++k) {
-      double* vk = V + (long)k * n;
-      if (use_f64) mv.apply_f64(vk, w);
-      else mv.apply(vk, w);
-      res.matvecs++;
-      mdot_f64(c, V, n, k + 1, w, n, cf1);
-      maxpy_f64(c, V, n, k + 1, cf1, -1.0, w, n);
-      mdot_f64(c, V, n, k + 1, w, n, cf2);
-      maxpy_f64(c, V, n, k + 1, cf2, -1.0, w, n);
-      dot_f64(c, w, w, n, sc + 1);
-      D3S_HIP(hipMemcpyAsync(h, cf1 + k, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-      D3S_HIP(hipMemcpyAsync(h + 1, cf2 + k, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-      D3S_HIP(hipMemcpyAsync(h + 2, sc + 1, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-      D3S_HIP(hipStreamSynchronize(c->stream));
-      const double a = h[0] + h[1];
-      const double b = std::sqrt(std::max(h[2], 0.0));
-      if (!std::isfinite(a) || !std::isfinite(b)) throw Error{D3S_ENUMERIC, "lanczos: non-finite value"};
-      alphas.push_back(a);
-      const int m = k + 1;
-      T.assign((size_t)m * m, 0.0);
-      for (int i = 0; i < m; ++i) T[(size_t)i * m + i] = alphas[i];
-      for (int i = 0; i + 1 < m; ++i) T[(size_t)i * m + i + 1] = T[(size_t)(i + 1) * m + i] = betas[i];
-      jacobi_eigh(m, T, ev, evec);
-      res.theta = ev[0];
-      y.assign(evec.begin(), evec.begin() + m);
-      const double scale = std::max(1.0, std::fabs(res.theta));
-      const double resid = std::fabs(b * y[m - 1]);
-      if (resid <= tol * scale || b <= 1e-15 * scale || m == n) {
-        res.converged = true;
-        stop = true;
-        break;
+  auto body = [&]() {
+    copy_row_f64(c, V, n, kdev, xin);
+    mv.product(xin, w, use_f64);
+    mdot_f64(c, V, n, kk, w, n, cf1, kdev);
+    maxpy_f64(c, V, n, kk, cf1, -1.0, w, n, kdev);
+    mdot_f64(c, V, n, kk, w, n, cf2, kdev);
+    maxpy_f64(c, V, n, kk, cf2, -1.0, w, n, kdev);
+    dot_f64(c, w, w, n, sc + 1);
+    lanczos_tail(c, w, n, sc + 1, cf1, cf2, 0, kdev, kk, V, ab);
+    set_int_dev(c, kdev, 1, true);
+  };
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t cap = nullptr;
+  const bool want_graph = mv.use_graph && !c->prof;
+  auto cleanup = [&]() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap) (void)hipStreamDestroy(cap);
+    gexec = nullptr;
+    graph = nullptr;
+    cap = nullptr;
+  };
+  auto enqueue_step = [&](int k) {
+    if (gexec) {
+      D3S_HIP(hipGraphLaunch(gexec, c->stream));
+    } else {
+      body();
+      if (want_graph) {
+        // every buffer is sized now: capture the step on a private stream
+        hipStream_t keep = c->stream;
+        D3S_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        c->stream = cap;
+        D3S_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+        try {
+          body();
+        } catch (...) {
+          hipGraph_t g = nullptr;
+          (void)hipStreamEndCapture(cap, &g);
+          if (g) (void)hipGraphDestroy(g);
+          c->stream = keep;
+          throw;
+        }
+        c->stream = keep;
+        D3S_HIP(hipStreamEndCapture(cap, &graph));
+        D3S_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
       }
-      if (res.matvecs >= max_mv) {
-        stop = true;
-        break;
-      }
-      betas.push_back(b);
-      if (k + 1 < kk) axpby_f64(c, 1.0 / b, w, 0.0, V + (long)(k + 1) * n, n);
     }
-    const int m = (int)y.size();
-    // Ritz vector x = sum_j y_j V_j
-    write_many(c, ydev, y.data(), m);
-    fill_f64(c, x, n, 0.0);
-    maxpy_f64(c, V, n, m, ydev, 1.0, x, n);
-    dot_f64(c, x, x, n, sc);
-    const double xn = read_scalar(c, sc);
-    scale_f64(c, x, n, 1.0 / std::sqrt(xn));
-    if (stop) break;
-    res.restarts++;
-    copy_f64(c, x, V, n);
+    D3S_HIP(hipMemcpyAsync(hab + 2 * k, ab + 2 * k, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    D3S_HIP(hipEventRecord((hipEvent_t)c->lz_ev[k & 1], c->stream));
+    res.matvecs++;
+  };
+  std::vector<double> alphas, betas, T, ev, evec;
+  try {
+    for (;;) {
+      alphas.clear();
+      betas.clear();
+      bool stop = false;
+      std::vector<double> y;
+      set_int_dev(c, kdev, 0, false);
+      enqueue_step(0);
+      int enq = 1;
+      for (int k = 0; k < kk; ++k) {
+        if (enq == k + 1 && k + 1 < kk && res.matvecs < max_mv) {
+          enqueue_step(k + 1);
+          ++enq;
+        }
+        D3S_HIP(hipEventSynchronize((hipEvent_t)c->lz_ev[k & 1]));
+        const double a = hab[2 * k];
+        const double b = hab[2 * k + 1];
+        if (!std::isfinite(a) || !std::isfinite(b)) throw Error{D3S_ENUMERIC, "lanczos: non-finite value"};
+        alphas.push_back(a);
+        const int m = k + 1;
+        T.assign((size_t)m * m, 0.0);
+        for (int i = 0; i < m; ++i) T[(size_t)i * m + i] = alphas[i];
+        for (int i = 0; i + 1 < m; ++i) T[(size_t)i * m + i + 1] = T[(size_t)(i + 1) * m + i] = betas[i];
+        jacobi_eigh(m, T, ev, evec);
+        res.theta = ev[0];
+        y.assign(evec.begin(), evec.begin() + m);
+        const double scale = std::max(1.0, std::fabs(res.theta));
+        const double resid = std::fabs(b * y[m - 1]);
+        if (resid <= tol * scale || b <= 1e-15 * scale || m == n) {
+          res.converged = true;
+          stop = true;
+          break;
+        }
+        if (enq == k + 1 && res.matvecs >= max_mv) {
+          stop = true;
+          break;
+        }
+        betas.push_back(b);
+      }
+      const int m = (int)y.size();
+      // Ritz vector x = sum_j y_j V_j (stream-ordered after any step still in flight)
+      write_many(c, ydev, y.data(), m);
+      fill_f64(c, x, n, 0.0);
+      maxpy_f64(c, V, n, m, ydev, 1.0, x, n);
+      dot_f64(c, x, x, n, sc);
+      const double xn = read_scalar(c, sc);
+      scale_f64(c, x, n, 1.0 / std::sqrt(xn));
+      if (stop) break;
+      res.restarts++;
+      copy_f64(c, x, V, n);
+    }
+  } catch (...) {
+    (void)hipStreamSynchronize(c->stream);
+    cleanup();
+    throw;
   }
+  D3S_HIP(hipStreamSynchronize(c->stream));
+  cleanup();
   if (use_f64) res.f64_matvecs = res.matvecs;
   return res;
 }
@@ -527,11 +625,11 @@ static LanczosResult lanczos_with(Ctx* c, Matvec& mv, d3s_prec p, double* psi, l
   // 1. Lanczos on the low-precision operator down to what it resolves;
   // 2. FP64 refinement: Lanczos with FP64 products warm-started from that Ritz
   //    vector.  Its first product already gives the FP64 Rayleigh quotient and
-  //    the exact FP64 residual; it stops once the residual is below
-  //    max(tol, 1e-7) |theta|.  The Ritz value is then an FP64 Rayleigh
-  //    quotient, whose error is quadratic in the residual (<= r^2 / gap).
+  //    the exact FP64 residual; it stops at the caller's tolerance, like
+  //    the FP64 path.  The Ritz value is then an FP64 Rayleigh quotient,
+  //    whose error is quadratic in the residual (<= r^2 / gap).
   const double low_tol = (p == D3S_F32) ? 1e-6 : 3e-3;
-  const double refine_tol = std::max(tol, 1e-7);
+  const double refine_tol = tol;
   LanczosResult r1 = lanczos_core(c, mv, psi, n, std::max(tol, low_tol), kmax, max_matvecs, false);
   LanczosResult r2 = lanczos_core(c, mv, psi, n, refine_tol, kmax, std::max(1, max_matvecs - r1.matvecs), true);
   r2.matvecs += r1.matvecs;

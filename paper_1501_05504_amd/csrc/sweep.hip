@@ -104,6 +104,7 @@ double op_prepare(Ctx* c, d3s_state* s, double eps) {
 }
 
 void op_sweep(Ctx* c, d3s_state* s, d3s_sweep_params* p, d3s_sweep_stats* st) {
+  const int mlim = (p->m_limit > 0 && p->m_limit < s->mmax) ? p->m_limit : s->mmax;
   const int l = s->l, d = s->d;
   if (s->center != l - 1) throw Error{D3S_EINVAL, "sweep: the orthogonality centre must be on site l-1"};
   const int wmax = wmax_of(s);
@@ -137,7 +138,7 @@ void op_sweep(Ctx* c, d3s_state* s, d3s_sweep_params* p, d3s_sweep_stats* st) {
     double t2 = now();
     const int mll = s->m[i - 1];
     TruncResult t = op_truncate(c, D3S_R2L, ml, d, mr, (long)(1 + wl) * ml, Mt, s->site[i],
-                                (int)bond_budget(l, d, s->mmax, i), p->eps, s->site[i - 1], (long)mll * d,
+                                (int)bond_budget(l, d, mlim, i), p->eps, s->site[i - 1], (long)mll * d,
                                 tmpS, tmpN, nullptr, true);
     copy_f64(c, tmpS, s->site[i], (long)t.k * d * mr);
     copy_f64(c, tmpN, s->site[i - 1], (long)mll * d * t.k);
@@ -180,7 +181,7 @@ void op_sweep(Ctx* c, d3s_state* s, d3s_sweep_params* p, d3s_sweep_stats* st) {
     double t2 = now();
     const int mrr = s->m[i + 2];
     TruncResult t = op_truncate(c, D3S_L2R, ml, d, mr, (long)(1 + wr) * mr, Mt, s->site[i],
-                                (int)bond_budget(l, d, s->mmax, i + 1), p->eps, s->site[i + 1], (long)d * mrr,
+                                (int)bond_budget(l, d, mlim, i + 1), p->eps, s->site[i + 1], (long)d * mrr,
                                 tmpS, tmpN, nullptr, true);
     copy_f64(c, tmpS, s->site[i], (long)ml * d * t.k);
     copy_f64(c, tmpN, s->site[i + 1], (long)t.k * d * mrr);

@@ -54,6 +54,21 @@ def test_block_sweep_heisenberg12_sz0_equals_ed(ctx):
         assert d.sum() == st.m[b]
 
 
+def test_block_sweep_jacobi_eigensolver_equals_ed():
+    """The Jacobi batched eigensolver in the block truncation gives the same
+    converged energy as the default divide and conquer one."""
+    c = abi.Context(0)
+    try:
+        c.set_eigensolver(2)
+        l, m = 12, 64
+        mpo = abi.heisenberg_mpo(l)
+        E, *_ = run_blocks(c, mpo, abi.mpo_spin_charges(1), abi.SPIN_HALF_CHARGES, [0], m, 12, 21)
+    finally:
+        c.close()
+    H = ed.spin_chain_hamiltonian(l, {(i, i + 1): 1.0 for i in range(l - 1)})
+    assert abs(E - ed.ground_energy(H, mask=ed.spin_sz(l) == 0)) < 1e-10
+
+
 def test_block_sweep_hubbard6_equals_ed_and_oracle(ctx):
     """Hubbard l = 6, U = 8, N = 6, 2Sz = 0, m = 64 (exact): block sweeps on the
     GPU, the dense oracle from the same symmetric initial state, and Fock ED
