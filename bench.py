@@ -27,8 +27,8 @@ HBM_PEAK = 8.0e12
 # FETCH_SIZE / WRITE_SIZE passes (scaled by a 1 GiB copy reference), valid
 # only for the GEMM source they were taken on (first 16 hex digits of its
 # SHA-256); any other source reports null.
-TRAFFIC = {"src_sha": "pending", "m": 2048,
-           "gemm1": 4.029e9 + 0.805e9, "gemm2": 4.161e9 + 0.134e9}
+TRAFFIC = {"src_sha": "5089802e4ddde374", "m": 2048,
+           "gemm1": 4.031e9 + 0.805e9, "gemm2": 4.167e9 + 0.134e9}
 
 
 def gemm_source_sha():
@@ -168,37 +168,83 @@ def block_heff_bench(ctx, abi, synth, torch, np, m, dev, steps):
     return info
 
 
-def block_sweep_bench(ctx, abi, synth, torch, np, dev, l, m, U, max_sweeps, tol):
-    """DMRG3S block sweeps on the Hubbard chain (half filling, 2Sz = 0) from
-    one seeded symmetric state, plain FP64 products vs FP32 products with FP64
-    refinement: wall time until the normalised sweep energy change < tol."""
-    out = {"workload": "hubbard_chain_blocks", "l": l, "m": m, "U": U, "tol": tol}
+def hubbard_sweep_bench(ctx, abi, synth, torch, dev, l, sched, U, tol, lanczos_tol, max_final):
+    """DMRG3S block sweeps on the Hubbard chain (t = 1, half filling, 2Sz = 0)
+    from one seeded symmetric state with a growing bond limit: two sweeps at
+    each m of the schedule, then sweeps at the last m until the normalised
+    sweep energy change is below `tol`.  Plain FP64 products against FP32
+    products with FP64 refinement of every Ritz vector to the same residual
+    tolerance; wall time from the first environment build on."""
+    out = {"workload": "hubbard_chain_blocks", "l": l, "U": U, "filling": "half, 2Sz=0", "m_schedule": sched,
+           "tol": tol, "lanczos_tol": lanczos_tol}
     phys = abi.HUBBARD_CHARGES
     mpo = abi.hubbard_chain_mpo(l, t=1.0, U=U)
     for name, prec in (("f64", abi.F64), ("mixed_f32", abi.F32)):
-        tensors, secs = synth.random_symmetric_mps(l, phys, [l, 0], m, seed=synth.SEED_MPS)
-        st = abi.State(mpo, tensors, m, device=dev)
+        tensors, secs = synth.random_symmetric_mps(l, phys, [l, 0], sched[0], seed=synth.SEED_MPS)
+        st = abi.State(mpo, tensors, max(sched), device=dev)
         sym = abi.Symmetry(phys, abi.mpo_bond_charges(mpo, abi.mpo_fermion_charges(1)), secs)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         e0 = ctx.prepare_blocks(st, sym)
-        params = abi.sweep_params(alpha=1e-3, e_before=e0, prec=prec)
-        prev, energies, t_conv = None, [], None
-        for sweep in range(max_sweeps):
-            _, stats, recs = ctx.sweep_blocks(st, sym, params, use_graph=True)
-            energies.append(stats.energy)
-            if prev is not None and abs(stats.energy - prev) / abs(stats.energy) < tol:
-                t_conv = time.perf_counter() - t0
-                break
-            prev = stats.energy
+        params = abi.sweep_params(alpha=1e-3, e_before=e0, prec=prec, tol=lanczos_tol)
+        energies, t_conv, prev, nsweeps, mv, mv64 = [], None, None, 0, 0, 0
+        plan = [(m, 2) for m in sched[:-1]] + [(sched[-1], max_final)]
+        for m, count in plan:
+            params.m_limit = m
+            for _ in range(count):
+                _, stats, recs = ctx.sweep_blocks(st, sym, params, use_graph=True)
+                nsweeps += 1
+                mv += sum(r.matvecs for r in recs)
+                mv64 += sum(r.f64_matvecs for r in recs)
+                energies.append(stats.energy)
+                done = (m == sched[-1] and prev is not None and abs(stats.energy - prev) / abs(stats.energy) < tol)
+                prev = stats.energy
+                if done:
+                    t_conv = time.perf_counter() - t0
+                    break
         wall = time.perf_counter() - t0
         split = {k: round(sum(getattr(r, k) for r in recs), 3) for k in ("t_eig", "t_expand", "t_trunc", "t_env", "t_energy")}
         out[name] = {"seconds_to_tol": None if t_conv is None else round(t_conv, 3), "seconds": round(wall, 3),
-                     "sweeps": len(energies), "energy": energies[-1], "last_sweep_split_s": split,
-                     "max_bond": max(st.m)}
-        print("bench: block sweep %s: %d sweeps %.2f s  E=%.12f" % (name, len(energies), wall, energies[-1]),
-              file=sys.stderr, flush=True)
+                     "sweeps": nsweeps, "energy": energies[-1], "matvecs": mv, "f64_matvecs": mv64,
+                     "last_sweep_split_s": split, "max_bond": max(st.m),
+                     "sectors_mid_bond": int(sym._nsec[l // 2])}
+        print("bench: hubbard sweeps %s: %d sweeps %.2f s  E=%.12f  max bond %d" % (
+            name, nsweeps, wall, energies[-1], max(st.m)), file=sys.stderr, flush=True)
+        del st
+        torch.cuda.empty_cache()
     out["energy_diff"] = abs(out["f64"]["energy"] - out["mixed_f32"]["energy"])
+    return out
+
+
+def dense_vs_blocks_bench(ctx, abi, synth, torch, dev, l, m, U):
+    """One FP64 sweep of the dense path and one of the block-sparse path from
+    the same seeded symmetric state of the Hubbard chain at bond limit m.  The
+    chemical potential mu = U/2 makes half filling the ground-state sector, so
+    the dense path (which does not fix N) and the block path (N = l) solve the
+    same problem."""
+    phys = abi.HUBBARD_CHARGES
+    mpo = abi.hubbard_chain_mpo(l, t=1.0, U=U, mu=[U / 2] * l)
+    out = {"workload": "hubbard_chain", "l": l, "m": m, "U": U, "mu": U / 2}
+    for name in ("dense", "blocks"):
+        tensors, secs = synth.random_symmetric_mps(l, phys, [l, 0], m, seed=synth.SEED_MPS)
+        st = abi.State(mpo, tensors, m, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if name == "dense":
+            e0 = ctx.prepare(st)
+            params = abi.sweep_params(alpha=1e-3, e_before=e0, tol=1e-10)
+            _, stats, _ = ctx.sweep(st, params)
+        else:
+            sym = abi.Symmetry(phys, abi.mpo_bond_charges(mpo, abi.mpo_fermion_charges(1)), secs)
+            e0 = ctx.prepare_blocks(st, sym)
+            params = abi.sweep_params(alpha=1e-3, e_before=e0, tol=1e-10)
+            _, stats, _ = ctx.sweep_blocks(st, sym, params, use_graph=True)
+        out[name] = {"seconds": round(time.perf_counter() - t0, 3), "energy": stats.energy}
+        print("bench: one sweep %s m=%d: %.2f s  E=%.10f" % (name, m, out[name]["seconds"], stats.energy),
+              file=sys.stderr, flush=True)
+        del st
+        torch.cuda.empty_cache()
+    out["speedup_blocks"] = round(out["dense"]["seconds"] / out["blocks"]["seconds"], 2)
     return out
 
 
@@ -240,9 +286,11 @@ def main():
                     help="Gaussian L and R instead of MPS-built environments (same kernels and shapes; "
                          "no eigensolver calls, for counter runs)")
     ap.add_argument("--no-blocks", action="store_true", help="skip the block-sparse H_eff and sweep measurements")
-    ap.add_argument("--sweep-l", type=int, default=32)
-    ap.add_argument("--sweep-m", type=int, default=256)
-    ap.add_argument("--sweep-max", type=int, default=10)
+    ap.add_argument("--sweep-l", type=int, default=64)
+    ap.add_argument("--sweep-sched", type=str, default="128,256,512,1024,2048",
+                    help="bond limits of the block sweep run (two sweeps each, then to convergence at the last)")
+    ap.add_argument("--sweep-max", type=int, default=8, help="sweeps at the last bond limit")
+    ap.add_argument("--dense-m", type=int, default=256, help="bond limit of the dense-vs-block one-sweep comparison")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 1 GiB read + 1 GiB write elementwise kernel (torch.neg) first, "
                          "as the reference for HBM byte counters")
@@ -343,8 +391,12 @@ def main():
         print("bench: block-sparse H_eff ...", file=sys.stderr, flush=True)
         line["blocks"] = block_heff_bench(ctx, abi, synth, torch, np, m, dev, max(10, steps // 2))
         print("bench: blocks %s" % line["blocks"], file=sys.stderr, flush=True)
-        line["sweep"] = block_sweep_bench(ctx, abi, synth, torch, np, dev, args.sweep_l, args.sweep_m, 8.0,
-                                          args.sweep_max, 1e-8)
+        sched = [int(x) for x in args.sweep_sched.split(",")]
+        line["sweep"] = hubbard_sweep_bench(ctx, abi, synth, torch, dev, args.sweep_l, sched, 8.0, 1e-8, 1e-10,
+                                            args.sweep_max)
+        if args.dense_m > 0:
+            line["dense_vs_blocks"] = dense_vs_blocks_bench(ctx, abi, synth, torch, dev, args.sweep_l, args.dense_m,
+                                                            8.0)
     if not args.no_cpu:
         print("bench: cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         Ln, Wn, Rn, pn = [x.cpu().numpy() for x in (L, W, R, psi)]
