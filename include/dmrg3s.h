@@ -284,6 +284,11 @@ typedef struct {
   int* nsec;
   int* const* sec_q;
   int* const* sec_dim;
+  long env_cap;   /* elements of every lenv/renv buffer of the state; 0 = mmax*wmax*mmax.
+                     The block calls store environments packed: the allowed blocks (i, c)
+                     of a bond (partner sector of q_i - Delta_c), each dim_i x dim_partner
+                     row-major, in sector-major then channel order.  A packed environment
+                     that would not fit is an error (D3S_EINVAL), never an overflow. */
 } d3s_symmetry;
 
 /* ---------------------------------------------------------------- sweeps */
@@ -373,7 +378,10 @@ d3s_status d3s_energy_gradients(d3s_ctx ctx, d3s_state* state, double** grads);
  * truncation is block-diagonal: one FP64 Gram matrix and one batched
  * rocSOLVER eigensolve per charge sector of the truncated bond, the kept
  * states chosen globally by singular value.  The bond sectors are updated
- * in `sym` after every truncation.  Synchronise. */
+ * in `sym` after every truncation.  Environments are kept in the packed
+ * layout described at d3s_symmetry (so a state swept by these calls needs
+ * d3s_prepare before dense calls such as d3s_sweep or d3s_energy_gradients
+ * use its environments).  Synchronise. */
 d3s_status d3s_prepare_blocks(d3s_ctx ctx, d3s_state* state, d3s_symmetry* sym, double* energy);
 d3s_status d3s_sweep_blocks(d3s_ctx ctx, d3s_state* state, d3s_symmetry* sym, d3s_sweep_params* params,
                             d3s_sweep_stats* stats, int use_graph);

@@ -117,7 +117,8 @@ _fermion_charges = _sig("d3s_mpo_fermion_charges", c_int, [c_int, c_int_p])
 
 class d3s_symmetry(ctypes.Structure):
     _fields_ = [("nq", c_int), ("phys_q", c_int_p), ("mpo_q", ctypes.POINTER(c_int_p)), ("maxsec", c_int),
-                ("nsec", c_int_p), ("sec_q", ctypes.POINTER(c_int_p)), ("sec_dim", ctypes.POINTER(c_int_p))]
+                ("nsec", c_int_p), ("sec_q", ctypes.POINTER(c_int_p)), ("sec_dim", ctypes.POINTER(c_int_p)),
+                ("env_cap", ctypes.c_long)]
 
 
 _prepare_blocks = _sig("d3s_prepare_blocks", c_int, [c_void_p, ctypes.POINTER(d3s_state),
@@ -355,6 +356,7 @@ class Context:
     def prepare_blocks(self, state, sym):
         self._sync_stream()
         e = c_double()
+        sym.c.env_cap = state.env_cap
         self._check(_prepare_blocks(self.h, ctypes.byref(state.c), ctypes.byref(sym.c), ctypes.byref(e)))
         state.pull_dims()
         return e.value
@@ -364,6 +366,7 @@ class Context:
         cap = 2 * state.l
         recs = (d3s_site_record * cap)()
         stats = d3s_sweep_stats(cap, 0, recs, 0.0, 0.0, 0)
+        sym.c.env_cap = state.env_cap
         st = self._check(_sweep_blocks(self.h, ctypes.byref(state.c), ctypes.byref(sym.c), ctypes.byref(params),
                                        ctypes.byref(stats), 1 if use_graph else 0), warn_ok=True)
         state.pull_dims()
@@ -385,14 +388,19 @@ class State:
     """Device buffers of an MPS, its MPO and its environments (torch-owned),
     described to the library by a d3s_state."""
 
-    def __init__(self, mpo_blocks, site_tensors, mmax, device="cuda"):
+    def __init__(self, mpo_blocks, site_tensors, mmax, device="cuda", env_cap=None):
+        """env_cap: elements per environment buffer (default the dense size
+        mmax*wmax*mmax).  The block-sparse calls store environments packed
+        and can run with far smaller buffers; the dense calls need the
+        default."""
         self.l = len(site_tensors)
         self.d = site_tensors[0].shape[1]
         self.mmax = mmax
         w = [1] + [int(b.shape[1]) for b in mpo_blocks]
         self.wmax = max(w)
         cap_site = mmax * self.d * mmax
-        cap_env = mmax * self.wmax * mmax
+        cap_env = mmax * self.wmax * mmax if env_cap is None else int(env_cap)
+        self.env_cap = cap_env
         self.site = [torch.zeros(cap_site, dtype=torch.float64, device=device) for _ in range(self.l)]
         self.lenv = [torch.zeros(cap_env, dtype=torch.float64, device=device) for _ in range(self.l)]
         self.renv = [torch.zeros(cap_env, dtype=torch.float64, device=device) for _ in range(self.l)]
@@ -461,7 +469,7 @@ class Symmetry:
         self._secq_p = (c_int_p * (self.l + 1))(*[a.ctypes.data_as(c_int_p) for a in self._secq])
         self._secd_p = (c_int_p * (self.l + 1))(*[a.ctypes.data_as(c_int_p) for a in self._secd])
         self.c = d3s_symmetry(self.nq, self._phys.ctypes.data_as(c_int_p), self._mpo_p, maxsec, self._nsec,
-                              self._secq_p, self._secd_p)
+                              self._secq_p, self._secd_p, 0)
 
     def sectors(self, b):
         n = self._nsec[b]

@@ -425,6 +425,11 @@ static d3s::SymChain read_sym(const d3s_state* s, const d3s_symmetry* y) {
               "symmetry: null array");
   d3s::SymChain c;
   c.nq = y->nq;
+  int wmax = 1;
+  for (int b = 0; b <= s->l; ++b) wmax = std::max(wmax, s->w[b]);
+  const long dense_cap = (long)s->mmax * wmax * s->mmax;
+  D3S_REQUIRE(y->env_cap >= 0, "symmetry: env_cap must be >= 0");
+  c.env_cap = y->env_cap > 0 ? y->env_cap : dense_cap;
   c.phys.assign(y->phys_q, y->phys_q + (size_t)s->d * y->nq);
   for (int b = 0; b <= s->l; ++b) {
     D3S_REQUIRE(y->mpo_q[b] && y->sec_q[b] && y->sec_dim[b], "symmetry: null per-bond array");

@@ -120,6 +120,17 @@ long psi_off(const BlockHeff& h, int i, int t, int j) {
 }
 long psi_ld(const BlockHeff& h, int j) { return h.packed ? (long)h.right.dim[j] : (long)h.d * h.mr; }
 
+// block (i, c, ip) of an environment on the left bond (L, or the new R of a
+// right-to-left update) / on the right bond (R, or the new L)
+long envl_off(const BlockHeff& h, int i, int c, int ip) {
+  return h.penv ? h.epl.off[(size_t)i * h.wl + c] : ((long)h.left.off[i] * h.wl + c) * h.ml + h.left.off[ip];
+}
+long envl_ld(const BlockHeff& h, int ip) { return h.penv ? (long)h.left.dim[ip] : (long)h.wl * h.ml; }
+long envr_off(const BlockHeff& h, int j, int c, int jp) {
+  return h.penv ? h.epr.off[(size_t)j * h.wr + c] : ((long)h.right.off[j] * h.wr + c) * h.mr + h.right.off[jp];
+}
+long envr_ld(const BlockHeff& h, int jp) { return h.penv ? (long)h.right.dim[jp] : (long)h.wr * h.mr; }
+
 const int* qv(const std::vector<int>& q, int i, int nq) { return q.data() + (size_t)i * nq; }
 
 // right sector of q_i + q_t (or -1)
@@ -251,8 +262,24 @@ void wmap_release(WmapPlan& w) {
   w.d_ents = nullptr;
 }
 
+EnvPack build_envpack(const Sectors& s, const int* wq, int w) {
+  EnvPack e;
+  const int nq = s.nq;
+  e.off.assign((size_t)s.n * w, -1);
+  int qq[4];
+  for (int i = 0; i < s.n; ++i)
+    for (int c = 0; c < w; ++c) {
+      for (int k = 0; k < nq; ++k) qq[k] = s.q[(size_t)i * nq + k] - wq[c * nq + k];
+      const int ip = s.find(qq);
+      if (ip < 0) continue;
+      e.off[(size_t)i * w + c] = e.total;
+      e.total += (long)s.dim[i] * s.dim[ip];
+    }
+  return e;
+}
+
 void build_block_heff(Ctx* c, BlockHeff& h, const Sectors& left, const Sectors& right, int d, int wl, int wr,
-                      const int* pq, const int* wql, const int* wqr, bool packed, bool with_g2) {
+                      const int* pq, const int* wql, const int* wqr, bool packed, bool with_g2, bool packed_env) {
   const int nq = left.nq;
   if (nq < 1 || nq > 4) throw Error{D3S_EINVAL, "blocks: 1 to 4 charges per state"};
   const int ml = left.total, mr = right.total;
@@ -267,6 +294,14 @@ void build_block_heff(Ctx* c, BlockHeff& h, const Sectors& left, const Sectors& 
   h.wql.assign(wql, wql + (size_t)wl * nq);
   h.wqr.assign(wqr, wqr + (size_t)wr * nq);
   h.packed = packed;
+  h.penv = packed_env;
+  if (packed_env) {
+    h.epl = build_envpack(left, wql, wl);
+    h.epr = build_envpack(right, wqr, wr);
+  } else {
+    h.epl = EnvPack();
+    h.epr = EnvPack();
+  }
   h.poff.assign((size_t)left.n * d, -1);
   h.npacked = 0;
   for (int i = 0; i < left.n; ++i)
@@ -292,8 +327,8 @@ void build_block_heff(Ctx* c, BlockHeff& h, const Sectors& left, const Sectors& 
         if (jp < 0) continue;
         GSeg sg;
         sg.K = left.dim[ip];
-        sg.a_off = ((long)left.off[i] * wl + w) * ml + left.off[ip];
-        sg.lda = (long)wl * ml;
+        sg.a_off = envl_off(h, i, w, ip);
+        sg.lda = envl_ld(h, ip);
         sg.b_off = psi_off(h, ip, t, jp);
         sg.ldb = psi_ld(h, jp);
         GTask tk;
@@ -332,8 +367,8 @@ void build_block_heff(Ctx* c, BlockHeff& h, const Sectors& left, const Sectors& 
           sg.K = right.dim[jpp];
           sg.a_off = (((long)left.off[i] * d + s) * wr + v) * mr + right.off[jpp];
           sg.lda = (long)d * wr * mr;
-          sg.b_off = ((long)right.off[j] * wr + v) * mr + right.off[jpp];
-          sg.ldb = (long)wr * mr;
+          sg.b_off = envr_off(h, j, v, jpp);
+          sg.ldb = envr_ld(h, jpp);
           h.g2.segs.push_back(sg);
           tk.nseg++;
         }
@@ -412,8 +447,8 @@ void ensure_y(Ctx* c, BlockHeff& h) {
         sg.K = R.dim[jp];
         sg.a_off = psi_off(h, i, t, jp);
         sg.lda = psi_ld(h, jp);
-        sg.b_off = ((long)R.off[j] * wr + v) * mr + R.off[jp];
-        sg.ldb = (long)wr * mr;
+        sg.b_off = envr_off(h, j, v, jp);
+        sg.ldb = envr_ld(h, jp);
         GTask tk;
         tk.M = L.dim[i];
         tk.N = R.dim[j];
@@ -452,8 +487,8 @@ void ensure_env_l2r(Ctx* c, BlockHeff& h) {
       tk.seg0 = (int)g.segs.size();
       tk.nseg = 0;
       tk.tile0 = 0;
-      tk.c_off = ((long)R.off[j] * wr + v) * mr + R.off[jpp];
-      tk.ldc = (long)wr * mr;
+      tk.c_off = envr_off(h, j, v, jpp);
+      tk.ldc = envr_ld(h, jpp);
       for (int i = 0; i < L.n; ++i)
         for (int s = 0; s < d; ++s) {
           if (right_of(h, i, s) != j) continue;
@@ -496,8 +531,8 @@ void ensure_env_r2l(Ctx* c, BlockHeff& h) {
       tk.seg0 = (int)g.segs.size();
       tk.nseg = 0;
       tk.tile0 = 0;
-      tk.c_off = ((long)L.off[i] * wl + w) * ml + L.off[ip];
-      tk.ldc = (long)wl * ml;
+      tk.c_off = envl_off(h, i, w, ip);
+      tk.ldc = envl_ld(h, ip);
       for (int s = 0; s < d; ++s) {
         const int j = right_of(h, i, s);
         if (j < 0) continue;
@@ -577,7 +612,7 @@ void op_update_env_blocks(Ctx* c, BlockHeff& h, d3s_dir dir, const double* env_i
     double* T2 = (double*)ws_get(c, WS_T2, sizeof(double) * (size_t)ml * d * wr * mr);
     grouped_gemm(c, D3S_F64, h.g1, env_in, site, T1, 1.0);
     wmap_blocks(c, D3S_F64, T1, W, T2, h.wm, 1.0);
-    zero_bytes(c, env_out, sizeof(double) * (size_t)mr * wr * mr);
+    zero_bytes(c, env_out, sizeof(double) * (size_t)plan_nr(h));
     if (h.g_el.ntasks > 0) grouped_gemm(c, D3S_F64, h.g_el, site, T2, env_out, 1.0);
   } else {
     ensure_y(c, h);
@@ -586,7 +621,7 @@ void op_update_env_blocks(Ctx* c, BlockHeff& h, d3s_dir dir, const double* env_i
     double* Z = (double*)ws_get(c, WS_T1, sizeof(double) * (size_t)wl * ml * d * mr);
     if (h.g_y.ntasks > 0) grouped_gemm(c, D3S_F64, h.g_y, site, env_in, Y, 1.0);
     wmap_blocks(c, D3S_F64, Y, W, Z, h.wm_yz, 1.0);
-    zero_bytes(c, env_out, sizeof(double) * (size_t)ml * wl * ml);
+    zero_bytes(c, env_out, sizeof(double) * (size_t)plan_nl(h));
     if (h.g_er.ntasks > 0) grouped_gemm(c, D3S_F64, h.g_er, site, Z, env_out, 1.0);
   }
 }
@@ -1005,9 +1040,17 @@ double op_energy_blocks(Ctx* c, BlockHeff& h, const double* L, const double* W, 
 namespace {
 
 // plan of site i (bonds i, i+1) of a symmetric chain
+// (environments are stored packed by the block sweeps)
 void site_plan(Ctx* c, BlockHeff& h, const d3s_state* s, const SymChain& sym, int i, bool packed, bool with_g2) {
   build_block_heff(c, h, sym.bonds[i], sym.bonds[i + 1], s->d, s->w[i], s->w[i + 1], sym.phys.data(),
-                   sym.wq[i].data(), sym.wq[i + 1].data(), packed, with_g2);
+                   sym.wq[i].data(), sym.wq[i + 1].data(), packed, with_g2, true);
+}
+
+// the packed environment an update writes must fit the caller's buffers
+void check_env_fits(const SymChain& sym, long need) {
+  if (need > sym.env_cap)
+    throw Error{D3S_EINVAL, "block sweep: a packed environment needs " + std::to_string(need) +
+                                " elements, the environment buffers hold " + std::to_string(sym.env_cap)};
 }
 
 // owns a plan for the duration of a scope
@@ -1046,6 +1089,7 @@ double op_prepare_blocks(Ctx* c, d3s_state* s, SymChain& sym, double eps) {
   for (int i = 0; i + 1 < l; ++i) {
     PlanGuard e;
     site_plan(c, e.h, s, sym, i, false, false);
+    check_env_fits(sym, e.h.epr.total);
     op_update_env_blocks(c, e.h, D3S_L2R, s->lenv[i], s->mpo[i], s->site[i], s->lenv[i + 1]);
   }
   s->center = l - 1;
@@ -1109,6 +1153,7 @@ void op_sweep_blocks(Ctx* c, d3s_state* s, SymChain& sym, d3s_sweep_params* p, d
         {
           PlanGuard e;
           site_plan(c, e.h, s, sym, i, false, false);
+          check_env_fits(sym, e.h.epl.total);
           op_update_env_blocks(c, e.h, D3S_R2L, s->renv[i], s->mpo[i], s->site[i], s->renv[i - 1]);
         }
         D3S_HIP(hipStreamSynchronize(c->stream));
@@ -1133,6 +1178,7 @@ void op_sweep_blocks(Ctx* c, d3s_state* s, SymChain& sym, d3s_sweep_params* p, d
         {
           PlanGuard e;
           site_plan(c, e.h, s, sym, i, false, false);
+          check_env_fits(sym, e.h.epr.total);
           op_update_env_blocks(c, e.h, D3S_L2R, s->lenv[i], s->mpo[i], s->site[i], s->lenv[i + 1]);
         }
         D3S_HIP(hipStreamSynchronize(c->stream));

@@ -221,6 +221,15 @@ struct Sectors {
   int find(const int* charge) const;   // -1 if the charge has no sector
 };
 
+// Packed layout of an environment on a bond with w channels: the allowed
+// blocks (i, c) (partner sector of q_i - Delta_c), each dim_i x dim_partner
+// row-major, one after the other.
+struct EnvPack {
+  std::vector<long> off;   // at i*w + c, -1 if forbidden
+  long total = 0;
+};
+EnvPack build_envpack(const Sectors& s, const int* wq, int w);
+
 // Grouped-GEMM plans of one block-sparse H_eff (and its captured graph).
 struct BlockHeff {
   int ml = 0, mr = 0, d = 0, wl = 0, wr = 0;
@@ -231,6 +240,10 @@ struct BlockHeff {
   bool packed = false;
   std::vector<long> poff;                // packed offset of block (i, s) at i*d + s, -1 if forbidden
   long npacked = 0;
+  // environment layout: dense (m, w, m), or packed (L and new R on the left
+  // bond: epl; R and new L on the right bond: epr)
+  bool penv = false;
+  EnvPack epl, epr;
   GroupedPlan g1, g2;                    // H_eff: GEMM-1 and GEMM-2
   WmapPlan wm;                           // H_eff: T1 -> T2
   // built on first use:
@@ -251,7 +264,10 @@ struct BlockHeff {
 };
 void build_block_heff(Ctx* c, BlockHeff& h, const Sectors& left, const Sectors& right, int d, int wl, int wr,
                       const int* phys_q, const int* wq_left, const int* wq_right, bool packed = false,
-                      bool with_g2 = true);
+                      bool with_g2 = true, bool packed_env = false);
+// elements of the L / R operands of a plan (packed or dense)
+inline long plan_nl(const BlockHeff& h) { return h.penv ? h.epl.total : (long)h.ml * h.wl * h.ml; }
+inline long plan_nr(const BlockHeff& h) { return h.penv ? h.epr.total : (long)h.mr * h.wr * h.mr; }
 // dense (ml, d, mr) site tensor <-> packed blocks of a packed plan; unpack
 // clears the rest of the dense tensor; `rowlen` is the length of a dense
 // (a, s) row (mr for a site tensor, (1+wr)*mr for [psi | P]).
@@ -275,6 +291,7 @@ double op_energy_blocks(Ctx* c, BlockHeff& h, const double* L, const double* W, 
 // Charges of one symmetric chain (host copies of the caller's d3s_symmetry).
 struct SymChain {
   int nq = 1;
+  long env_cap = 0;                      // elements per environment buffer
   std::vector<int> phys;                 // d*nq
   std::vector<std::vector<int>> wq;      // per MPO bond b: w[b]*nq
   std::vector<Sectors> bonds;            // per MPS bond b = 0..l

@@ -364,9 +364,11 @@ struct Matvec {
   BlockHeff* plan = nullptr;     // block-sparse products when set
   bool use_graph = false;
   double* xblk = nullptr;        // fixed FP64 input buffer of the captured block graph
+  long nl_ = 0, nr_ = 0;         // elements of L and R when not dense (packed block environments)
   void prepare() {
     if (p == D3S_F64) return;
-    const long nl = (long)ml * wl * ml, nr = (long)mr * wr * mr, nw = (long)wl * wr * d * d;
+    const long nl = nl_ ? nl_ : (long)ml * wl * ml, nr = nr_ ? nr_ : (long)mr * wr * mr;
+    const long nw = (long)wl * wr * d * d;
     float* Wf = (float*)ws_get(c, WS_CAST_W, 4 * nw);
     cast_f64_to_f32(c, W, Wf, nw);
     Wc = Wf;
@@ -598,6 +600,8 @@ LanczosResult op_lanczos_blocks(Ctx* c, d3s_prec p, BlockHeff& plan, const doubl
   mv.n = n;
   mv.plan = &plan;
   mv.use_graph = use_graph;
+  mv.nl_ = plan_nl(plan);
+  mv.nr_ = plan_nr(plan);
   mv.prepare();
   if (!plan.packed) return lanczos_with(c, mv, p, psi, n, tol, kmax, max_matvecs);
   double* x = packed_out ? packed_out : (double*)ws_get(c, WS_PK, sizeof(double) * (size_t)n);

@@ -23,9 +23,10 @@ def ctx():
     c.close()
 
 
-def run_blocks(ctx, mpo, chan_q, phys, target, m, sweeps, seed, use_graph=True, prec=None, tol=1e-12):
+def run_blocks(ctx, mpo, chan_q, phys, target, m, sweeps, seed, use_graph=True, prec=None, tol=1e-12,
+               env_cap=None):
     tensors, secs = synth.random_symmetric_mps(len(mpo), phys, target, m, seed=seed)
-    st = abi.State(mpo, tensors, m, device=DEV)
+    st = abi.State(mpo, tensors, m, device=DEV, env_cap=env_cap)
     sym = abi.Symmetry(phys, abi.mpo_bond_charges(mpo, chan_q), secs)
     e0 = ctx.prepare_blocks(st, sym)
     params = abi.sweep_params(alpha=1e-3, e_before=e0, prec=abi.F64 if prec is None else prec)
@@ -52,6 +53,22 @@ def test_block_sweep_heisenberg12_sz0_equals_ed(ctx):
     for b in range(l + 1):
         q, d = sym.sectors(b)
         assert d.sum() == st.m[b]
+
+
+def test_block_sweep_small_packed_environments(ctx):
+    """The block sweeps keep environments packed: buffers of a quarter of the
+    dense size give the same converged energy, and buffers too small for a
+    packed environment are refused with EINVAL (no overflow)."""
+    l, m = 12, 64
+    mpo = abi.heisenberg_mpo(l)
+    dense = m * 5 * m
+    E_small, *_ = run_blocks(ctx, mpo, abi.mpo_spin_charges(1), abi.SPIN_HALF_CHARGES, [0], m, 12, 21,
+                             env_cap=dense // 4)
+    E_full, *_ = run_blocks(ctx, mpo, abi.mpo_spin_charges(1), abi.SPIN_HALF_CHARGES, [0], m, 12, 21)
+    assert E_small == E_full
+    with pytest.raises(abi.D3SError) as err:
+        run_blocks(ctx, mpo, abi.mpo_spin_charges(1), abi.SPIN_HALF_CHARGES, [0], m, 2, 21, env_cap=64)
+    assert err.value.status == abi.EINVAL
 
 
 def test_block_sweep_jacobi_eigensolver_equals_ed():
