@@ -216,6 +216,56 @@ def hubbard_sweep_bench(ctx, abi, synth, torch, dev, l, sched, U, tol, lanczos_t
     return out
 
 
+def cylinder_bench(ctx, abi, synth, torch, dev, sched, sweeps_last, lanczos_tol, precs):
+    """4 x 16 Hubbard cylinder (t = 1, U = 4, N = 56, 2Sz = 0, w = 18, every
+    column traversed in the same direction), U(1)xU(1) blocks: one sweep at
+    each bond limit of the schedule, then `sweeps_last` more at the last,
+    from the same seeded symmetric state for every precision of the
+    eigensolver's products (FP64; FP32 / BF16 with FP64 refinement to the
+    same residual).  Reports per-sweep energies and times and the energy
+    difference of each mixed run against the FP64 run, sweep by sweep."""
+    width, length = 4, 16
+    l = width * length
+    mpo = abi.hubbard_cylinder_mpo(width, length, t=1.0, U=4.0)
+    phys = abi.HUBBARD_CHARGES
+    chan = abi.mpo_bond_charges(mpo, abi.mpo_fermion_charges(width))
+    wmax = max(int(b.shape[1]) for b in mpo)
+    mmax = max(sched)
+    out = {"workload": "hubbard_cylinder_blocks", "width": width, "length": length, "U": 4.0, "N": 56, "w": wmax,
+           "m_schedule": sched, "sweeps_at_last_m": sweeps_last, "lanczos_tol": lanczos_tol}
+    plan = [m for m in sched] + [sched[-1]] * sweeps_last
+    for name in precs:
+        prec = {"f64": abi.F64, "mixed_f32": abi.F32, "mixed_bf16": abi.BF16}[name]
+        tensors, secs = synth.random_symmetric_mps(l, phys, [56, 0], sched[0], seed=synth.SEED_MPS)
+        st = abi.State(mpo, tensors, mmax, device=dev, env_cap=mmax * mmax * wmax // 4)
+        sym = abi.Symmetry(phys, chan, secs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0 = ctx.prepare_blocks(st, sym)
+        params = abi.sweep_params(alpha=1e-3, e_before=e0, prec=prec, tol=lanczos_tol)
+        rows = []
+        for m in plan:
+            params.m_limit = m
+            t = time.perf_counter()
+            _, stats, recs = ctx.sweep_blocks(st, sym, params, use_graph=True)
+            rows.append({"m": m, "seconds": round(time.perf_counter() - t, 3), "energy": stats.energy,
+                         "t_eig": round(sum(r.t_eig for r in recs), 3),
+                         "t_trunc": round(sum(r.t_trunc for r in recs), 3),
+                         "matvecs": sum(r.matvecs for r in recs), "f64_matvecs": sum(r.f64_matvecs for r in recs),
+                         "max_bond": max(st.m), "sectors_mid_bond": int(sym._nsec[l // 2])})
+            print("bench: cylinder %s m=%d %.2f s E=%.10f" % (name, m, rows[-1]["seconds"], stats.energy),
+                  file=sys.stderr, flush=True)
+        out[name] = {"sweeps": rows, "seconds": round(time.perf_counter() - t0, 3)}
+        del st
+        torch.cuda.empty_cache()
+    if "f64" in out:
+        for name in precs:
+            if name != "f64":
+                out[name]["energy_diff_vs_f64"] = [abs(a["energy"] - b["energy"])
+                                                   for a, b in zip(out[name]["sweeps"], out["f64"]["sweeps"])]
+    return out
+
+
 def dense_vs_blocks_bench(ctx, abi, synth, torch, dev, l, m, U):
     """One FP64 sweep of the dense path and one of the block-sparse path from
     the same seeded symmetric state of the Hubbard chain at bond limit m.  The
@@ -291,6 +341,11 @@ def main():
                     help="bond limits of the block sweep run (two sweeps each, then to convergence at the last)")
     ap.add_argument("--sweep-max", type=int, default=8, help="sweeps at the last bond limit")
     ap.add_argument("--dense-m", type=int, default=256, help="bond limit of the dense-vs-block one-sweep comparison")
+    ap.add_argument("--cylinder", type=str, default="",
+                    help="bond limits of the 4x16 cylinder run (e.g. 256,512,1024,2048,4096; '' = skip)")
+    ap.add_argument("--cylinder-last", type=int, default=2, help="extra sweeps at the last cylinder bond limit")
+    ap.add_argument("--cylinder-precs", type=str, default="f64,mixed_f32,mixed_bf16")
+
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 1 GiB read + 1 GiB write elementwise kernel (torch.neg) first, "
                          "as the reference for HBM byte counters")
@@ -397,6 +452,9 @@ def main():
         if args.dense_m > 0:
             line["dense_vs_blocks"] = dense_vs_blocks_bench(ctx, abi, synth, torch, dev, args.sweep_l, args.dense_m,
                                                             8.0)
+    if args.cylinder:
+        line["cylinder"] = cylinder_bench(ctx, abi, synth, torch, dev, [int(x) for x in args.cylinder.split(",")],
+                                          args.cylinder_last, 1e-10, args.cylinder_precs.split(","))
     if not args.no_cpu:
         print("bench: cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         Ln, Wn, Rn, pn = [x.cpu().numpy() for x in (L, W, R, psi)]

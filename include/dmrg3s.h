@@ -180,7 +180,7 @@ d3s_status d3s_update_env(d3s_ctx ctx, d3s_dir dir, int ml, int d, int mr, int w
 /*
  * Smallest eigenpair of H_eff (step 1 of Sec. 5: "an eigensolver targeting
  * the smallest eigenvalue"): Lanczos with full FP64 re-orthogonalisation,
- * warm-started from psi, at most kmax Krylov vectors per restart, stopping at
+ * warm-started from psi, at most kmax (2..64) Krylov vectors per restart, stopping at
  * residual <= tol * max(1, |theta|) or after max_matvecs products.  psi (FP64,
  * in/out) receives the normalised Ritz vector, *theta (host) the Ritz value,
  * *matvecs (host, may be NULL) the number of H_eff products.
@@ -191,6 +191,14 @@ d3s_status d3s_update_env(d3s_ctx ctx, d3s_dir dir, int ml, int d, int mr, int w
  * stay FP64).  Returns D3S_ENOCONV (a warning) when the limit was hit.
  * Synchronises.
  */
+/* Host helper of the eigensolver (no GPU involved): the lowest eigenpair of
+ * the symmetric tridiagonal matrix with diagonal alpha[0..n) and
+ * off-diagonal beta[0..n-1) (the Lanczos projection of Sec. 5 step 1), the
+ * eigenvalue by Sturm-sequence bisection, the unit eigenvector y[0..n) by
+ * inverse iteration (sign: largest component positive).  Host arrays.
+ * D3S_EINVAL for bad arguments, D3S_ENUMERIC when no finite vector results. */
+d3s_status d3s_tridiag_lowest(int n, const double* alpha, const double* beta, double* theta, double* y);
+
 d3s_status d3s_lanczos(d3s_ctx ctx, d3s_prec prec, int ml, int d, int mr, int wl, int wr,
                        const double* L, const double* W, const double* R, double* psi,
                        double tol, int kmax, int max_matvecs, double* theta, int* matvecs);
@@ -320,7 +328,7 @@ typedef struct {
   int adaptive_alpha;    /* 1: adapt alpha after every site update (Sec. 6); 0: keep it */
   double eps;            /* singular values s_j <= eps * s_0 are dropped (1e-14) */
   double lanczos_tol;    /* residual tolerance of the eigensolver (1e-12) */
-  int lanczos_kmax;      /* Krylov vectors per restart (40) */
+  int lanczos_kmax;      /* Krylov vectors per restart (40; 2..64) */
   int lanczos_max_matvecs; /* products per site update (2000) */
   d3s_prec prec;         /* arithmetic of the eigensolver's H_eff products */
   double e_before;       /* in/out: energy of the state entering the next site update */

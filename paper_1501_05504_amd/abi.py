@@ -74,6 +74,7 @@ _set_tile_config = _sig("d3s_set_tile_config", c_int, [c_void_p, c_int])
 _set_splitk = _sig("d3s_set_splitk", c_int, [c_void_p, c_int])
 _set_autotune = _sig("d3s_set_autotune", c_int, [c_void_p, c_int, ctypes.c_char_p])
 _set_eig = _sig("d3s_set_eigensolver", c_int, [c_void_p, c_int, c_int])
+_tridiag = _sig("d3s_tridiag_lowest", c_int, [c_int, c_double_p, c_double_p, c_double_p, c_double_p])
 _profile_begin = _sig("d3s_profile_begin", c_int, [c_void_p, c_int])
 _profile_end = _sig("d3s_profile_end", c_int, [c_void_p, c_double_p, c_int_p])
 _apply_heff = _sig("d3s_apply_heff", c_int, [c_void_p, c_int] + [c_int] * 5 + [c_void_p] * 5)
@@ -136,6 +137,23 @@ class D3SError(RuntimeError):
 
 def version():
     return _version().decode()
+
+
+def tridiag_lowest(alpha, beta):
+    """Lowest eigenpair of a symmetric tridiagonal matrix (host helper of the
+    eigensolver): returns (theta, y) as (float, numpy array)."""
+    import numpy as np
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    if b.size != max(a.size - 1, 0):
+        raise ValueError("beta must have len(alpha) - 1 entries")
+    y = np.empty_like(a)
+    th = c_double()
+    st = _tridiag(a.size, a.ctypes.data_as(c_double_p), b.ctypes.data_as(c_double_p) if b.size else None,
+                  ctypes.byref(th), y.ctypes.data_as(c_double_p))
+    if st != OK:
+        raise D3SError(st, "d3s_tridiag_lowest")
+    return th.value, y
 
 
 def _ptr(t):

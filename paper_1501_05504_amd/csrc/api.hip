@@ -136,6 +136,15 @@ d3s_status d3s_set_autotune(d3s_ctx ctx, int enable, const char* cache_path) {
   });
 }
 
+d3s_status d3s_tridiag_lowest(int n, const double* alpha, const double* beta, double* theta, double* y) {
+  if (n < 1 || !alpha || !theta || !y || (n > 1 && !beta)) return D3S_EINVAL;
+  try {
+    return d3s::tridiag_lowest(n, alpha, beta, theta, y) ? D3S_OK : D3S_ENUMERIC;
+  } catch (...) {
+    return D3S_ENOMEM;
+  }
+}
+
 d3s_status d3s_set_eigensolver(d3s_ctx ctx, int kind, int jacobi_max_n) {
   return guarded(ctx, [&] {
     D3S_REQUIRE(kind >= 0 && kind <= 2, "kind must be 0 (auto), 1 (divide and conquer) or 2 (Jacobi)");
@@ -255,7 +264,7 @@ d3s_status d3s_lanczos(d3s_ctx ctx, d3s_prec prec, int ml, int d, int mr, int wl
     check_prec(prec);
     check_dims(ml, d, mr, wl, wr);
     D3S_REQUIRE(L && W && R && psi && theta, "null pointer");
-    D3S_REQUIRE(kmax >= 2 && kmax <= 120, "kmax must be in [2, 120]");
+    D3S_REQUIRE(kmax >= 2 && kmax <= 64, "kmax must be in [2, 64]");
     D3S_REQUIRE(max_matvecs >= 1, "max_matvecs must be >= 1");
     D3S_REQUIRE(tol > 0.0, "tol must be > 0");
     d3s::LanczosResult r = d3s::op_lanczos(&ctx->c, prec, ml, d, mr, wl, wr, L, W, R, psi, tol, kmax, max_matvecs);
@@ -314,7 +323,7 @@ d3s_status d3s_sweep(d3s_ctx ctx, d3s_state* state, d3s_sweep_params* params, d3
     D3S_REQUIRE(params && stats, "null params or stats");
     D3S_REQUIRE(stats->records || stats->capacity == 0, "stats: null records with capacity > 0");
     check_prec(params->prec);
-    D3S_REQUIRE(params->lanczos_kmax >= 2 && params->lanczos_kmax <= 120, "lanczos_kmax must be in [2, 120]");
+    D3S_REQUIRE(params->lanczos_kmax >= 2 && params->lanczos_kmax <= 64, "lanczos_kmax must be in [2, 64]");
     D3S_REQUIRE(params->lanczos_tol > 0.0 && params->lanczos_max_matvecs >= 1, "bad eigensolver limits");
     D3S_REQUIRE(params->alpha >= 0.0 && std::isfinite(params->alpha), "alpha must be finite and >= 0");
     D3S_REQUIRE((long)state->d * state->mmax <= 46340, "d * mmax too large for the Gram route");
@@ -483,7 +492,7 @@ d3s_status d3s_sweep_blocks(d3s_ctx ctx, d3s_state* state, d3s_symmetry* sym, d3
     D3S_REQUIRE(params && stats, "null params or stats");
     D3S_REQUIRE(stats->records || stats->capacity == 0, "stats: null records with capacity > 0");
     check_prec(params->prec);
-    D3S_REQUIRE(params->lanczos_kmax >= 2 && params->lanczos_kmax <= 120, "lanczos_kmax must be in [2, 120]");
+    D3S_REQUIRE(params->lanczos_kmax >= 2 && params->lanczos_kmax <= 64, "lanczos_kmax must be in [2, 64]");
     D3S_REQUIRE(params->lanczos_tol > 0.0 && params->lanczos_max_matvecs >= 1, "bad eigensolver limits");
     D3S_REQUIRE(params->alpha >= 0.0 && std::isfinite(params->alpha), "alpha must be finite and >= 0");
     d3s::SymChain c = read_sym(state, sym);

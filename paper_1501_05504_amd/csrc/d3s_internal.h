@@ -37,7 +37,7 @@ struct Error {
 enum WsSlot {
   WS_T1 = 0, WS_T2, WS_LZ_V, WS_LZ_W, WS_LZ_COEF, WS_RED, WS_GRAM, WS_EIGVAL,
   WS_EIGTMP, WS_UKT, WS_X, WS_MT, WS_CAST_L, WS_CAST_R, WS_CAST_X, WS_CAST_Y,
-  WS_CAST_W, WS_REF, WS_PSI, WS_INFO, WS_NBR, WS_MISC, WS_SPLITK, WS_DESC, WS_BLK_X, WS_XPACK, WS_GPACK, WS_GVAL, WS_TUNE, WS_PK, WS_LZ_K, WS_NSLOTS
+  WS_CAST_W, WS_REF, WS_PSI, WS_INFO, WS_NBR, WS_MISC, WS_SPLITK, WS_DESC, WS_BLK_X, WS_XPACK, WS_GPACK, WS_GVAL, WS_TUNE, WS_PK, WS_LZ_K, WS_GS_NORM, WS_NSLOTS
 };
 
 struct Ctx {
@@ -152,9 +152,17 @@ void dot_f64(Ctx* c, const double* x, const double* y, long n, double* out_dev);
 // largest possible count), so one captured launch serves every step.
 void mdot_f64(Ctx* c, const double* V, long ldv, int k, const double* w, long n, double* coef_dev,
               const int* kdev = nullptr);
-// Lanczos step end (k from the host, or *kdev): V_{k+1} = w / sqrt(*nrm2) unless k+1 = kk;
-// ab[2k] = c1[k] + c2[k], ab[2k+1] = sqrt(*nrm2)
-void lanczos_tail(Ctx* c, const double* w, long n, const double* nrm2, const double* c1, const double* c2, int k,
+// partial-sum count of the Gram-Schmidt kernels for vectors of length n (fixed by n)
+int gs_blocks(long n);
+// fused second pass: w -= sum_j coef1_j V_j, then coef2 = V^T w (rows k or *kdev + 1, <= 64)
+void gs_second_pass(Ctx* c, const double* V, long ldv, int k, const int* kdev, const double* coef1, double* w,
+                    long n, double* coef2);
+// w -= sum_j coef_j V_j with the per-block partials of |w|^2 in npart (gs_blocks(n) entries)
+void gs_update_norm(Ctx* c, const double* V, long ldv, int k, const int* kdev, const double* coef, double* w,
+                    long n, double* npart);
+// Lanczos step end (k from the host, or *kdev): beta = sqrt(sum of npart), V_{k+1} = w / beta
+// unless k+1 = kk; ab[2k] = c1[k] + c2[k], ab[2k+1] = beta
+void lanczos_tail(Ctx* c, const double* w, long n, const double* npart, const double* c1, const double* c2, int k,
                   const int* kdev, int kk, double* V, double* ab);
 void copy_row_f64(Ctx* c, const double* V, long n, const int* kdev, double* dst);   // dst = V_{*kdev}
 void set_int_dev(Ctx* c, int* p, int v, bool add);                                   // *p = v or *p += v
@@ -323,6 +331,8 @@ LanczosResult op_lanczos_blocks(Ctx* c, d3s_prec p, BlockHeff& plan, const doubl
                                 bool use_graph, double* packed_out = nullptr);
 void syevd_batched_f64(Ctx* c, int n, int batch, double* A, double* evals);
 
+// lowest eigenpair of a symmetric tridiagonal matrix (bisection + inverse iteration)
+bool tridiag_lowest(int n, const double* a, const double* b, double* theta, double* y);
 // host symmetric eigensolver (cyclic Jacobi) for small tridiagonal projections
 void jacobi_eigh(int n, std::vector<double>& A, std::vector<double>& evals,
                  std::vector<double>& evecs);

@@ -283,16 +283,93 @@ void mdot_partial_kernel(const double* __restrict__ V, long ldv, int k, const in
   }
 }
 
+// Second Gram-Schmidt pass fused with the first one's update: with
+// c = -coef (the first pass's coefficients), w <- w + sum_j c_j V_j, and the
+// partial sums of <V_j, w_new> for the second pass, reading every V_j once.
+template <int KMAX>
+__global__ __launch_bounds__(kThreads)
+void gs_update_dot_kernel(const double* __restrict__ V, long ldv, int k, const int* __restrict__ kdev,
+                          const double* __restrict__ coef, double* __restrict__ w, long n,
+                          double* __restrict__ part) {
+  __shared__ double sc[KMAX];
+  __shared__ double sh[kThreads / 64][KMAX];
+  const int rows = kdev ? (*kdev + 1) : k;
+  for (int j = threadIdx.x; j < KMAX; j += blockDim.x) sc[j] = (j < rows) ? -coef[j] : 0.0;
+  __syncthreads();
+  double acc[KMAX];
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j) acc[j] = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    double v[KMAX];
+    double x = w[i];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j)
+      if (j < rows) {
+        v[j] = V[(long)j * ldv + i];
+        x += sc[j] * v[j];
+      }
+    w[i] = x;
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j)
+      if (j < rows) acc[j] += v[j] * x;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j) {
+    if (j < rows) {
+      double t = acc[j];
+      for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
+      if (lane == 0) sh[wave][j] = t;
+    }
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < rows; j += blockDim.x) {
+    double t = 0.0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += sh[q][j];
+    part[(long)j * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+// Second pass update fused with the norm: w <- w - sum_j coef_j V_j and the
+// per-block partial sums of |w_new|^2 (part[block]).
+__global__ __launch_bounds__(kThreads)
+void gs_update_norm_kernel(const double* __restrict__ V, long ldv, int k, const int* __restrict__ kdev,
+                           const double* __restrict__ coef, double* __restrict__ w, long n,
+                           double* __restrict__ part) {
+  __shared__ double sc[128];
+  __shared__ double sh[kThreads / 64];
+  const int rows = kdev ? (*kdev + 1) : k;
+  for (int j = threadIdx.x; j < rows; j += blockDim.x) sc[j] = -coef[j];
+  __syncthreads();
+  double acc = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    double x = w[i];
+    for (int j = 0; j < rows; ++j) x += sc[j] * V[(long)j * ldv + i];
+    w[i] = x;
+    acc += x * x;
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
 // End of a Lanczos step k (k from the host, or *kdev): V_{k+1} = w / beta
 // with beta = sqrt(|w|^2) (zero when beta is not positive; skipped when
 // k+1 = kk), and ab[2k] = alpha_k (the projections of both Gram-Schmidt
 // passes on V_k), ab[2k+1] = beta.
 __global__ __launch_bounds__(kThreads)
-void lanczos_tail_kernel(const double* __restrict__ w, long n, const double* __restrict__ nrm2,
+void lanczos_tail_kernel(const double* __restrict__ w, long n, const double* __restrict__ npart, int nnp,
                          const double* __restrict__ c1, const double* __restrict__ c2, int k,
                          const int* __restrict__ kdev, int kk, double* __restrict__ V, double* __restrict__ ab) {
   if (kdev) k = *kdev;
-  const double b = sqrt(fmax(*nrm2, 0.0));
+  // |w|^2 from the per-block partials, summed in a fixed order by every block
+  __shared__ double sb;
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < nnp; ++q) t += npart[q];
+    sb = t;
+  }
+  __syncthreads();
+  const double b = sqrt(fmax(sb, 0.0));
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ab[2 * k] = c1[k] + c2[k];
     ab[2 * k + 1] = b;
@@ -487,8 +564,8 @@ void mdot_f64(Ctx* c, const double* V, long ldv, int k, const double* w, long n,
   if (k <= 0) return;
   if (k > 128) throw Error{D3S_EINVAL, "mdot: more than 128 vectors"};
   // partial count fixed by n (deterministic), at most 256
-  const int nb = (int)std::max<long>(1, std::min<long>(256, (n + 8L * kThreads - 1) / (8L * kThreads)));
-  double* part = (double*)ws_get(c, WS_RED, sizeof(double) * (size_t)nb * k);
+  const int nb = gs_blocks(n);
+  double* part = (double*)ws_get(c, WS_RED, sizeof(double) * (size_t)nb * 128);
   for (int j0 = 0; j0 < k; j0 += 64) {
     const int kc = std::min(64, k - j0);
     auto go = [&](auto kern) {
@@ -503,10 +580,39 @@ void mdot_f64(Ctx* c, const double* V, long ldv, int k, const double* w, long n,
   D3S_HIP(hipGetLastError());
 }
 
-void lanczos_tail(Ctx* c, const double* w, long n, const double* nrm2, const double* c1, const double* c2, int k,
+int gs_blocks(long n) {
+  return (int)std::max<long>(1, std::min<long>(256, (n + 8L * kThreads - 1) / (8L * kThreads)));
+}
+
+void gs_second_pass(Ctx* c, const double* V, long ldv, int k, const int* kdev, const double* coef1, double* w,
+                    long n, double* coef2) {
+  if (k <= 0) return;
+  if (k > 64) throw Error{D3S_EINVAL, "Gram-Schmidt: more than 64 vectors in the fused pass"};
+  const int nb = gs_blocks(n);
+  double* part = (double*)ws_get(c, WS_RED, sizeof(double) * (size_t)nb * 128);
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(kThreads), 0, c->stream, V, ldv, k, kdev, coef1, w, n, part);
+  };
+  if (k <= 16) go(gs_update_dot_kernel<16>);
+  else if (k <= 32) go(gs_update_dot_kernel<32>);
+  else if (k <= 48) go(gs_update_dot_kernel<48>);
+  else go(gs_update_dot_kernel<64>);
+  hipLaunchKernelGGL(reduce_rows_kernel, dim3(k), dim3(kThreads), 0, c->stream, part, nb, coef2, kdev);
+  D3S_HIP(hipGetLastError());
+}
+
+void gs_update_norm(Ctx* c, const double* V, long ldv, int k, const int* kdev, const double* coef, double* w,
+                    long n, double* npart) {
+  if (k > 128) throw Error{D3S_EINVAL, "Gram-Schmidt: more than 128 vectors"};
+  hipLaunchKernelGGL(gs_update_norm_kernel, dim3(gs_blocks(n)), dim3(kThreads), 0, c->stream, V, ldv, k, kdev,
+                     coef, w, n, npart);
+  D3S_HIP(hipGetLastError());
+}
+
+void lanczos_tail(Ctx* c, const double* w, long n, const double* npart, const double* c1, const double* c2, int k,
                   const int* kdev, int kk, double* V, double* ab) {
-  hipLaunchKernelGGL(lanczos_tail_kernel, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, w, n, nrm2, c1, c2, k,
-                     kdev, kk, V, ab);
+  hipLaunchKernelGGL(lanczos_tail_kernel, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, w, n, npart,
+                     gs_blocks(n), c1, c2, k, kdev, kk, V, ab);
   D3S_HIP(hipGetLastError());
 }
 

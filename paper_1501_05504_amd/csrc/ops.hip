@@ -203,6 +203,115 @@ void syevd_batched_f64(Ctx* c, int n, int batch, double* A, double* evals) {
                                    std::to_string(hinfo[b]) + ")"};
 }
 
+// Lowest eigenpair of the symmetric tridiagonal matrix with diagonal a[0..n)
+// and off-diagonal b[0..n-1): the eigenvalue by bisection on the Sturm
+// sequence count (to a few ulps), the eigenvector by inverse iteration with a
+// partially pivoted tridiagonal LU factorisation.  O(n) per bisection step.
+// Returns false when the iteration did not produce a finite unit vector.
+bool tridiag_lowest(int n, const double* a, const double* b, double* theta, double* y) {
+  if (n <= 0) return false;
+  if (n == 1) {
+    *theta = a[0];
+    y[0] = 1.0;
+    return std::isfinite(a[0]);
+  }
+  // Gershgorin interval
+  double lo = a[0], hi = a[0], scale = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+    scale = std::max(scale, std::fabs(a[i]) + r);
+  }
+  if (!(scale > 0.0)) {
+    *theta = 0.0;
+    for (int i = 0; i < n; ++i) y[i] = (i == 0) ? 1.0 : 0.0;
+    return true;
+  }
+  const double tiny = DBL_MIN / DBL_EPSILON;
+  // number of eigenvalues < x (Sturm count of the LDL^T pivots of T - x)
+  auto count_below = [&](double x) {
+    int c = 0;
+    double q = a[0] - x;
+    if (q < 0.0) ++c;
+    for (int i = 1; i < n; ++i) {
+      if (std::fabs(q) < tiny) q = (q < 0.0) ? -tiny : tiny;
+      q = (a[i] - x) - b[i - 1] * b[i - 1] / q;
+      if (q < 0.0) ++c;
+    }
+    return c;
+  };
+  for (int it = 0; it < 200 && hi - lo > 4.0 * DBL_EPSILON * std::max(std::fabs(lo), std::fabs(hi)) + tiny; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (count_below(mid) >= 1) hi = mid;
+    else lo = mid;
+  }
+  const double th = 0.5 * (lo + hi);
+  *theta = th;
+  // inverse iteration on T - th (shifted off the eigenvalue by a few ulps of
+  // the matrix scale so that the factorisation is never exactly singular)
+  const double shift = th - 8.0 * DBL_EPSILON * scale;
+  std::vector<double> d(n), du(n), du2(n), dl(n);
+  std::vector<int> piv(n);
+  for (int i = 0; i < n; ++i) d[i] = a[i] - shift;
+  for (int i = 0; i + 1 < n; ++i) du[i] = dl[i] = b[i];
+  // LU with partial pivoting (rows i, i+1), U has two superdiagonals
+  for (int i = 0; i < n; ++i) du2[i] = 0.0;
+  for (int i = 0; i + 1 < n; ++i) {
+    if (std::fabs(d[i]) >= std::fabs(dl[i])) {
+      piv[i] = i;
+      if (std::fabs(d[i]) < tiny) d[i] = tiny;
+      const double f = dl[i] / d[i];
+      dl[i] = f;
+      d[i + 1] -= f * du[i];
+      du2[i] = 0.0;
+    } else {
+      piv[i] = i + 1;
+      const double f = d[i] / dl[i];
+      d[i] = dl[i];
+      dl[i] = f;
+      const double t = du[i];
+      du[i] = d[i + 1];
+      d[i + 1] = t - f * d[i + 1];
+      if (i + 2 < n) {
+        du2[i] = du[i + 1];
+        du[i + 1] = -f * du[i + 1];
+      }
+    }
+  }
+  if (std::fabs(d[n - 1]) < tiny) d[n - 1] = tiny;
+  piv[n - 1] = n - 1;
+  for (int i = 0; i < n; ++i) y[i] = 1.0 / std::sqrt((double)n) * (1.0 + 1e-3 * (i % 7));
+  for (int rep = 0; rep < 3; ++rep) {
+    // solve L U x = y: forward with the row interchanges, then back substitution
+    for (int i = 0; i + 1 < n; ++i) {
+      if (piv[i] == i) {
+        y[i + 1] -= dl[i] * y[i];
+      } else {
+        const double t = y[i];
+        y[i] = y[i + 1];
+        y[i + 1] = t - dl[i] * y[i + 1];
+      }
+    }
+    y[n - 1] /= d[n - 1];
+    if (n >= 2) y[n - 2] = (y[n - 2] - du[n - 2] * y[n - 1]) / d[n - 2];
+    for (int i = n - 3; i >= 0; --i) y[i] = (y[i] - du[i] * y[i + 1] - du2[i] * y[i + 2]) / d[i];
+    double nrm = 0.0;
+    for (int i = 0; i < n; ++i) nrm += y[i] * y[i];
+    nrm = std::sqrt(nrm);
+    if (!(nrm > 0.0) || !std::isfinite(nrm)) return false;
+    for (int i = 0; i < n; ++i) y[i] /= nrm;
+  }
+  // sign convention: largest component positive
+  int im = 0;
+  for (int i = 1; i < n; ++i)
+    if (std::fabs(y[i]) > std::fabs(y[im])) im = i;
+  if (y[im] < 0.0)
+    for (int i = 0; i < n; ++i) y[i] = -y[i];
+  return true;
+}
+
 // Cyclic Jacobi eigensolver for a small dense symmetric matrix (row-major A,
 // destroyed).  Eigenvalues ascending; evecs[j*n + i] = component i of vector j.
 void jacobi_eigh(int n, std::vector<double>& A, std::vector<double>& evals, std::vector<double>& evecs) {
@@ -446,7 +555,7 @@ struct Matvec {
 LanczosResult lanczos_core(Ctx* c, Matvec& mv, double* x, long n, double tol, int kmax, int max_mv,
                            bool use_f64) {
   const int kk = (int)std::min<long>(kmax, n);
-  if (kk > 120) throw Error{D3S_EINVAL, "lanczos: at most 120 Krylov vectors"};
+  if (kk > 64) throw Error{D3S_EINVAL, "lanczos: at most 64 Krylov vectors"};
   double* V = (double*)ws_get(c, WS_LZ_V, sizeof(double) * (size_t)(kk + 1) * n);
   double* w = (double*)ws_get(c, WS_LZ_W, sizeof(double) * n);
   double* xin = (double*)ws_get(c, WS_BLK_X, sizeof(double) * n);
@@ -472,15 +581,16 @@ LanczosResult lanczos_core(Ctx* c, Matvec& mv, double* x, long n, double tol, in
   }
   scale_f64(c, x, n, 1.0 / std::sqrt(nrm2));
   copy_f64(c, x, V, n);
+  double* npart = (double*)ws_get(c, WS_GS_NORM, sizeof(double) * 256);
   auto body = [&]() {
     copy_row_f64(c, V, n, kdev, xin);
     mv.product(xin, w, use_f64);
+    // classical Gram-Schmidt twice against V_0..V_k, three passes over V:
+    // c1 = V^T w;  w -= V c1 with c2 = V^T w;  w -= V c2 with |w|^2
     mdot_f64(c, V, n, kk, w, n, cf1, kdev);
-    maxpy_f64(c, V, n, kk, cf1, -1.0, w, n, kdev);
-    mdot_f64(c, V, n, kk, w, n, cf2, kdev);
-    maxpy_f64(c, V, n, kk, cf2, -1.0, w, n, kdev);
-    dot_f64(c, w, w, n, sc + 1);
-    lanczos_tail(c, w, n, sc + 1, cf1, cf2, 0, kdev, kk, V, ab);
+    gs_second_pass(c, V, n, kk, kdev, cf1, w, n, cf2);
+    gs_update_norm(c, V, n, kk, kdev, cf2, w, n, npart);
+    lanczos_tail(c, w, n, npart, cf1, cf2, 0, kdev, kk, V, ab);
     set_int_dev(c, kdev, 1, true);
   };
   hipGraph_t graph = nullptr;
@@ -545,12 +655,15 @@ LanczosResult lanczos_core(Ctx* c, Matvec& mv, double* x, long n, double tol, in
         if (!std::isfinite(a) || !std::isfinite(b)) throw Error{D3S_ENUMERIC, "lanczos: non-finite value"};
         alphas.push_back(a);
         const int m = k + 1;
-        T.assign((size_t)m * m, 0.0);
-        for (int i = 0; i < m; ++i) T[(size_t)i * m + i] = alphas[i];
-        for (int i = 0; i + 1 < m; ++i) T[(size_t)i * m + i + 1] = T[(size_t)(i + 1) * m + i] = betas[i];
-        jacobi_eigh(m, T, ev, evec);
-        res.theta = ev[0];
-        y.assign(evec.begin(), evec.begin() + m);
+        y.assign(m, 0.0);
+        if (!tridiag_lowest(m, alphas.data(), betas.data(), &res.theta, y.data())) {
+          T.assign((size_t)m * m, 0.0);
+          for (int i = 0; i < m; ++i) T[(size_t)i * m + i] = alphas[i];
+          for (int i = 0; i + 1 < m; ++i) T[(size_t)i * m + i + 1] = T[(size_t)(i + 1) * m + i] = betas[i];
+          jacobi_eigh(m, T, ev, evec);
+          res.theta = ev[0];
+          y.assign(evec.begin(), evec.begin() + m);
+        }
         const double scale = std::max(1.0, std::fabs(res.theta));
         const double resid = std::fabs(b * y[m - 1]);
         if (resid <= tol * scale || b <= 1e-15 * scale || m == n) {

@@ -91,3 +91,31 @@ def test_mpo_respects_channel_charges():
         assert np.array_equal(sp[s] - sp[t], sq[v] - sq[w])
 
 
+
+
+def test_tridiag_lowest_matches_lapack():
+    """Host helper of the eigensolver: the lowest eigenpair of symmetric
+    tridiagonal matrices (random, split, graded, n = 1..60) against LAPACK."""
+    from scipy.linalg import eigh_tridiagonal
+    from paper_1501_05504_amd import abi
+    rng = np.random.default_rng(7)
+    cases = [(np.array([2.5]), np.array([]))]
+    for n in [2, 3, 5, 17, 40, 60]:
+        cases.append((rng.standard_normal(n), rng.standard_normal(n - 1)))
+        cases.append((1e3 * rng.standard_normal(n), 1e-3 * rng.standard_normal(n - 1)))
+    split = rng.standard_normal(12)
+    bs = rng.standard_normal(11)
+    bs[5] = 0.0
+    cases.append((split, bs))
+    # a Lanczos-like matrix: slowly varying diagonal near -60, off-diagonals ~ 1
+    cases.append((-60 + np.cumsum(rng.uniform(0, 1, 40)), rng.uniform(0.5, 1.5, 39)))
+    for a, b in cases:
+        th, y = abi.tridiag_lowest(a, b)
+        w, v = eigh_tridiagonal(a, b) if len(a) > 1 else (a.copy(), np.ones((1, 1)))
+        scale = max(1.0, np.abs(a).max() + (np.abs(b).max() if len(b) else 0.0))
+        assert abs(th - w[0]) <= 1e-13 * scale, (len(a), th, w[0])
+        assert abs(np.linalg.norm(y) - 1.0) < 1e-12
+        T = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+        assert np.linalg.norm(T @ y - th * y) <= 1e-12 * scale
+        if len(a) > 1 and w[1] - w[0] > 1e-6 * scale:
+            assert abs(abs(y @ v[:, 0]) - 1.0) < 1e-10
