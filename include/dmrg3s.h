@@ -99,6 +99,13 @@ d3s_status d3s_set_autotune(d3s_ctx ctx, int enable, const char* cache_path);
  * conquer above (the default: kind 0, jacobi_max_n 0, i.e. syevd).  Both
  * give the eigenpairs to FP64 accuracy; only the speed differs. */
 d3s_status d3s_set_eigensolver(d3s_ctx ctx, int kind, int jacobi_max_n);
+/* The batched FP64 symmetric eigensolver of the truncations (a6): `batch`
+ * matrices of size n, column-major, stored one after the other in A
+ * (device, n*n*batch), are replaced by their eigenvectors (columns) and W
+ * (device, n*batch) receives the eigenvalues in ascending order; the solver
+ * is the one chosen by d3s_set_eigensolver.  Synchronises; D3S_EDEVICE if an
+ * eigensolve did not converge. */
+d3s_status d3s_eig_batched(d3s_ctx ctx, int n, int batch, double* A, double* W);
 /* Split-K of GEMMs whose tiles cannot fill the device (default on; the
  * partial products are summed in a fixed order, so results stay
  * deterministic).  enable = 0 turns it off. */

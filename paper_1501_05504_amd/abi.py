@@ -74,6 +74,7 @@ _set_tile_config = _sig("d3s_set_tile_config", c_int, [c_void_p, c_int])
 _set_splitk = _sig("d3s_set_splitk", c_int, [c_void_p, c_int])
 _set_autotune = _sig("d3s_set_autotune", c_int, [c_void_p, c_int, ctypes.c_char_p])
 _set_eig = _sig("d3s_set_eigensolver", c_int, [c_void_p, c_int, c_int])
+_eig_batched = _sig("d3s_eig_batched", c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p])
 _tridiag = _sig("d3s_tridiag_lowest", c_int, [c_int, c_double_p, c_double_p, c_double_p, c_double_p])
 _profile_begin = _sig("d3s_profile_begin", c_int, [c_void_p, c_int])
 _profile_end = _sig("d3s_profile_end", c_int, [c_void_p, c_double_p, c_int_p])
@@ -218,6 +219,19 @@ class Context:
     def set_autotune(self, enable, cache_path=None):
         self._check(_set_autotune(self.h, 1 if enable else 0,
                                   None if cache_path is None else str(cache_path).encode()))
+
+    def eig_batched(self, A, W):
+        """A: (batch, n, n) FP64 device tensor of symmetric matrices (the
+        eigensolver reads them column-major, i.e. A[b].T); replaced by the
+        eigenvectors (row j of A[b] = eigenvector j); W: (batch, n) receives
+        the eigenvalues, ascending."""
+        self._sync_stream()
+        if A.dim() != 3 or A.shape[1] != A.shape[2]:
+            raise ValueError("A must be (batch, n, n)")
+        batch, n = A.shape[0], A.shape[1]
+        _need(A, batch * n * n, torch.float64, "A")
+        _need(W, batch * n, torch.float64, "W")
+        return self._check(_eig_batched(self.h, n, batch, _ptr(A), _ptr(W)))
 
     def set_eigensolver(self, kind, jacobi_max_n=0):
         """0 auto (Jacobi up to jacobi_max_n), 1 divide and conquer, 2 Jacobi."""

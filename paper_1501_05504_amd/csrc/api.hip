@@ -145,6 +145,15 @@ d3s_status d3s_tridiag_lowest(int n, const double* alpha, const double* beta, do
   }
 }
 
+d3s_status d3s_eig_batched(d3s_ctx ctx, int n, int batch, double* A, double* W) {
+  return guarded(ctx, [&] {
+    D3S_REQUIRE(n >= 1 && batch >= 1, "n and batch must be >= 1");
+    D3S_REQUIRE(A && W, "null pointer");
+    d3s::syevd_batched_f64(&ctx->c, n, batch, A, W);
+    return D3S_OK;
+  });
+}
+
 d3s_status d3s_set_eigensolver(d3s_ctx ctx, int kind, int jacobi_max_n) {
   return guarded(ctx, [&] {
     D3S_REQUIRE(kind >= 0 && kind <= 2, "kind must be 0 (auto), 1 (divide and conquer) or 2 (Jacobi)");

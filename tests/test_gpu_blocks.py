@@ -164,3 +164,28 @@ def test_block_update_env_equals_dense_oracle(ctx, ml, mr, seed):
     assert rel_err(out.cpu().numpy(), C.update_left(L, W, psi)) < 1e-12
     assert rel_err(out2.cpu().numpy(), C.update_right(R, W, psi)) < 1e-12
     plan.close()
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+@pytest.mark.parametrize("n,batch", [(1, 3), (7, 5), (40, 2), (130, 3)])
+def test_eig_batched_equals_lapack(kind, n, batch):
+    """The batched eigensolver of the truncation (divide and conquer and
+    Jacobi) against LAPACK: eigenvalues, and eigenvectors through A V = V L."""
+    c = abi.Context(0)
+    try:
+        c.set_eigensolver(kind)
+        rng = np.random.default_rng(n * 10 + batch)
+        X = rng.standard_normal((batch, n, n + 3))
+        G = X @ X.transpose(0, 2, 1)
+        A = torch.tensor(G, device=DEV)
+        W = torch.empty((batch, n), dtype=torch.float64, device=DEV)
+        c.eig_batched(A, W)
+        torch.cuda.synchronize()
+        for b in range(batch):
+            w_ref = np.linalg.eigvalsh(G[b])
+            scale = max(1.0, np.abs(w_ref).max())
+            assert np.abs(W[b].cpu().numpy() - w_ref).max() < 1e-12 * scale
+            V = A[b].cpu().numpy()          # row j = eigenvector j
+            assert np.abs(G[b] @ V.T - V.T * W[b].cpu().numpy()).max() < 1e-11 * scale
+    finally:
+        c.close()
