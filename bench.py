@@ -266,6 +266,78 @@ def cylinder_bench(ctx, abi, synth, torch, dev, sched, sweeps_last, lanczos_tol,
     return out
 
 
+def gradient_bench(ctx, abi, synth, torch, dev, l, m_sched, J2, dJ, tol):
+    """J1-J2 chain (J1 = 1, open): converge DMRG3S (block sweeps, growing
+    bond limit, then to a normalised energy change below `tol`), then dE/dJ2
+    through the hand-written adjoint (torch.autograd on the MPO energy),
+    against the Hellmann-Feynman value <Psi|sum_i S_i.S_{i+2}|Psi> (the
+    energy of the same state under the next-nearest-neighbour MPO) and the
+    central finite difference of two further converged runs at J2 -+ dJ,
+    warm-started from the converged state.  The convergence runs with FP64
+    products and with FP32 products plus FP64 refinement."""
+    from paper_1501_05504_amd.autograd import mpo_energy
+    phys = abi.SPIN_HALF_CHARGES
+    chan = abi.mpo_spin_charges(2)
+    mmax = max(m_sched)
+    out = {"workload": "j1j2_chain", "l": l, "J1": 1.0, "J2": J2, "m_schedule": m_sched, "dJ": dJ, "tol": tol}
+
+    def converge(mpo, tensors, secs, prec, sched):
+        st = abi.State(mpo, tensors, mmax, device=dev)
+        sym = abi.Symmetry(phys, abi.mpo_bond_charges(mpo, chan), secs)
+        e0 = ctx.prepare_blocks(st, sym)
+        params = abi.sweep_params(alpha=1e-3, e_before=e0, prec=prec, tol=1e-12)
+        prev, n = None, 0
+        plan = [(mm, 2) for mm in sched[:-1]] + [(sched[-1], 12)]
+        for mm, count in plan:
+            params.m_limit = mm
+            for _ in range(count):
+                _, stats, _ = ctx.sweep_blocks(st, sym, params)
+                n += 1
+                done = mm == sched[-1] and prev is not None and abs(stats.energy - prev) / abs(stats.energy) < tol
+                prev = stats.energy
+                if done:
+                    break
+        return st, sym, stats.energy, n
+
+    for name, prec in (("f64", abi.F64), ("mixed_f32", abi.F32)):
+        t0 = time.perf_counter()
+        tensors, secs = synth.random_symmetric_mps(l, phys, [0], m_sched[0], seed=synth.SEED_MPS)
+        st, sym, E, nsw = converge(abi.j1j2_mpo(l, 1.0, J2), tensors, secs, prec, m_sched)
+        t_conv = time.perf_counter() - t0
+        conv_tensors = [t.cpu().numpy() for t in st.tensors()]
+        conv_secs = [sym.sectors(b) for b in range(l + 1)]
+        # adjoint through autograd (dense environments rebuilt by d3s_prepare)
+        W0 = [torch.tensor(w, dtype=torch.float64, device=dev) for w in abi.j1j2_mpo(l, 1.0, 0.0)]
+        W1 = [torch.tensor(w, dtype=torch.float64, device=dev) for w in abi.j1j2_mpo(l, 1.0, 1.0)]
+        j = torch.tensor(J2, dtype=torch.float64, device=dev, requires_grad=True)
+        t1 = time.perf_counter()
+        Ewf = mpo_energy(ctx, st, [a + j * (b - a) for a, b in zip(W0, W1)])
+        Ewf.backward()
+        t_grad = time.perf_counter() - t1
+        adj = float(j.grad)
+        del st
+        # Hellmann-Feynman: the same state under the next-nearest-neighbour MPO
+        st2 = abi.State(abi.j1j2_mpo(l, 0.0, 1.0), conv_tensors, mmax, device=dev)
+        hf = ctx.prepare(st2)
+        del st2
+        res = {"energy": E, "sweeps": nsw, "seconds_to_converge": round(t_conv, 2), "dE_dJ2_adjoint": adj,
+               "hellmann_feynman": hf, "adjoint_minus_hf": abs(adj - hf), "gradient_seconds": round(t_grad, 3)}
+        if name == "f64":
+            eps = []
+            for sgn in (+1, -1):
+                _, _, Es, _ = converge(abi.j1j2_mpo(l, 1.0, J2 + sgn * dJ), conv_tensors, conv_secs, abi.F64,
+                                       [m_sched[-1]])
+                eps.append(Es)
+            fd = (eps[0] - eps[1]) / (2 * dJ)
+            res.update({"finite_difference": fd, "adjoint_minus_fd": abs(adj - fd)})
+        out[name] = res
+        print("bench: gradient %s E=%.12f adjoint %.10f HF %.10f %s" % (
+            name, E, adj, hf, ("FD %.10f" % res["finite_difference"]) if "finite_difference" in res else ""),
+            file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+    return out
+
+
 def dense_vs_blocks_bench(ctx, abi, synth, torch, dev, l, m, U):
     """One FP64 sweep of the dense path and one of the block-sparse path from
     the same seeded symmetric state of the Hubbard chain at bond limit m.  The
@@ -345,6 +417,8 @@ def main():
                     help="bond limits of the 4x16 cylinder run (e.g. 256,512,1024,2048,4096; '' = skip)")
     ap.add_argument("--cylinder-last", type=int, default=2, help="extra sweeps at the last cylinder bond limit")
     ap.add_argument("--cylinder-precs", type=str, default="f64,mixed_f32,mixed_bf16")
+    ap.add_argument("--gradient", type=str, default="",
+                    help="bond limits of the J1-J2 dE/dJ2 run (l=48, J2=0.24; e.g. 64,128,256,512; '' = skip)")
 
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 1 GiB read + 1 GiB write elementwise kernel (torch.neg) first, "
@@ -452,6 +526,9 @@ def main():
         if args.dense_m > 0:
             line["dense_vs_blocks"] = dense_vs_blocks_bench(ctx, abi, synth, torch, dev, args.sweep_l, args.dense_m,
                                                             8.0)
+    if args.gradient:
+        line["gradient"] = gradient_bench(ctx, abi, synth, torch, dev, 48, [int(x) for x in args.gradient.split(",")],
+                                          0.24, 1e-4, 1e-11)
     if args.cylinder:
         line["cylinder"] = cylinder_bench(ctx, abi, synth, torch, dev, [int(x) for x in args.cylinder.split(",")],
                                           args.cylinder_last, 1e-10, args.cylinder_precs.split(","))

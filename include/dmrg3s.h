@@ -85,6 +85,11 @@ const char* d3s_version(void);
  * block tiles (4 waves of 64x64), 1 = 64x64 (4 waves of 32x32), 2 = 256x128
  * (8 waves of 64x64), 3 = 128x128 (8 waves of 64x32). */
 d3s_status d3s_set_tile_config(d3s_ctx ctx, int cfg);
+/* Tile configuration of the grouped block-sparse launches of plans built
+ * afterwards: -1 = chosen per launch by a work model (or by timing, with
+ * autotuning on; default), 0 = 128x128 tiles, 1 = 64x64, 2 = 96x96,
+ * 3 = 32x32 (four waves each). */
+d3s_status d3s_set_grouped_tile(d3s_ctx ctx, int cfg);
 /* Autotuning of tile configurations (default off: a size heuristic picks
  * them).  When on, the first dense GEMM of every shape class (precision,
  * layouts, M, N, K) is timed in all tile configurations with HIP events and

@@ -72,6 +72,7 @@ _synchronize = _sig("d3s_synchronize", c_int, [c_void_p])
 _version = _sig("d3s_version", ctypes.c_char_p, [])
 _set_tile_config = _sig("d3s_set_tile_config", c_int, [c_void_p, c_int])
 _set_splitk = _sig("d3s_set_splitk", c_int, [c_void_p, c_int])
+_set_gtile = _sig("d3s_set_grouped_tile", c_int, [c_void_p, c_int])
 _set_autotune = _sig("d3s_set_autotune", c_int, [c_void_p, c_int, ctypes.c_char_p])
 _set_eig = _sig("d3s_set_eigensolver", c_int, [c_void_p, c_int, c_int])
 _eig_batched = _sig("d3s_eig_batched", c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p])
@@ -236,6 +237,10 @@ class Context:
     def set_eigensolver(self, kind, jacobi_max_n=0):
         """0 auto (Jacobi up to jacobi_max_n), 1 divide and conquer, 2 Jacobi."""
         self._check(_set_eig(self.h, int(kind), int(jacobi_max_n)))
+
+    def set_grouped_tile(self, cfg):
+        """-1 model/autotuner, 0 = 128, 1 = 64, 2 = 96, 3 = 32 (grouped tile edge)."""
+        self._check(_set_gtile(self.h, int(cfg)))
 
     def set_splitk(self, enable):
         self._check(_set_splitk(self.h, 1 if enable else 0))

@@ -119,6 +119,14 @@ d3s_status d3s_synchronize(d3s_ctx ctx) {
   });
 }
 
+d3s_status d3s_set_grouped_tile(d3s_ctx ctx, int cfg) {
+  return guarded(ctx, [&] {
+    D3S_REQUIRE(cfg >= -1 && cfg <= 3, "grouped tile configuration must be in [-1, 3]");
+    ctx->c.grouped_cfg = cfg;
+    return D3S_OK;
+  });
+}
+
 d3s_status d3s_set_tile_config(d3s_ctx ctx, int cfg) {
   return guarded(ctx, [&] {
     D3S_REQUIRE(cfg >= -1 && cfg <= 3, "tile config must be in [-1, 3]");

@@ -73,13 +73,26 @@ void grouped_finalize(Ctx* c, GroupedPlan& g) {
     g.flops += 2.0 * work(g.tasks[i]);
   }
   g.tasks.swap(sorted);
-  // 128x128 tiles when the blocks are large enough to fill them
-  long t64 = 0, t128 = 0;
-  for (const GTask& t : g.tasks) {
-    t64 += (long)((t.M + 63) / 64) * ((t.N + 63) / 64);
-    t128 += (long)((t.M + 127) / 128) * ((t.N + 127) / 128);
+  // tile size (measured on MI355X with the sectors of a 4096-state cylinder
+  // bond, ~45 sectors: 64x64 tiles beat 96x96 and 128x128 in FP64 and FP32,
+  // their smaller register footprint keeping more waves in flight): 64x64 by
+  // default, 128x128 only when the blocks nearly fill them, 32x32 when
+  // 64x64 tiles would be more than half empty; the autotuner times all four
+  if (c->grouped_cfg >= 0) {
+    g.cfg = c->grouped_cfg;
+  } else {
+    long t64 = 0, t128 = 0;
+    double a32 = 0.0, a64 = 0.0;
+    for (const GTask& t : g.tasks) {
+      t64 += (long)((t.M + 63) / 64) * ((t.N + 63) / 64);
+      t128 += (long)((t.M + 127) / 128) * ((t.N + 127) / 128);
+      a32 += 1024.0 * ((t.M + 31) / 32) * ((t.N + 31) / 32);
+      a64 += 4096.0 * ((t.M + 63) / 64) * ((t.N + 63) / 64);
+    }
+    if (t128 >= 512 && 4 * t128 <= t64 + t64 / 4) g.cfg = 0;
+    else if (a64 > 2.0 * a32) g.cfg = 3;
+    else g.cfg = 1;
   }
-  g.cfg = (t128 >= 512 && 4 * t128 <= t64 + t64 / 4) ? 0 : 1;
   g.ntasks = (int)g.tasks.size();
   grouped_release(g);
   if (g.ntasks == 0) return;

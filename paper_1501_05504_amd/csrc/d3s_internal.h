@@ -52,6 +52,7 @@ struct Ctx {
   void* lz_ev[2] = {nullptr, nullptr};   // Lanczos step events
   std::string last_error;
   int tile_config = -1;              // GEMM tile configuration (-1 = heuristic)
+  int grouped_cfg = -1;              // grouped GEMM tile configuration (-1 = model / autotuner)
   bool splitk_off = false;           // disable split-K (tests compare both paths)
   bool autotune = false;             // time tile configurations on first use of a shape
   int eig_kind = 0;                  // batched eigensolver: 0 auto, 1 divide and conquer, 2 Jacobi
@@ -96,7 +97,7 @@ struct GroupedPlan {
   GSeg* d_segs = nullptr;
   int ntasks = 0, total_tiles = 0;
   bool a_kc = true, b_kc = true;
-  int cfg = 1;                  // 0: 128x128 tiles, 1: 64x64 tiles
+  int cfg = 1;                  // tile edge: 0 -> 128, 1 -> 64, 2 -> 96, 3 -> 32
   double flops = 0.0;
 };
 int grouped_tile(int cfg);

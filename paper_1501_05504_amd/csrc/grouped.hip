@@ -160,21 +160,32 @@ void launch_grouped(Ctx* c, const GroupedPlan& g, const void* A, const void* B, 
 
 }  // namespace
 
-int grouped_tile(int cfg) { return cfg == 0 ? 128 : 64; }
+// tile edge per configuration: 0 = 128 (4 waves of 64x64), 1 = 64 (4 waves
+// of 32x32), 2 = 96 (4 waves of 48x48), 3 = 32 (4 waves of 16x16)
+int grouped_tile(int cfg) {
+  switch (cfg) {
+    case 0: return 128;
+    case 2: return 96;
+    case 3: return 32;
+    default: return 64;
+  }
+}
 
 void grouped_gemm(Ctx* c, d3s_prec prec, const GroupedPlan& g, const void* A, const void* B, void* C,
                   double alpha) {
   if (g.ntasks <= 0 || g.total_tiles <= 0) return;
-  if (prec == D3S_F64) {
-    if (g.cfg == 0) launch_grouped<double, 128, 128, 64, 64>(c, g, A, B, C, alpha);
-    else launch_grouped<double, 64, 64, 32, 32>(c, g, A, B, C, alpha);
-  } else if (prec == D3S_F32) {
-    if (g.cfg == 0) launch_grouped<float, 128, 128, 64, 64>(c, g, A, B, C, alpha);
-    else launch_grouped<float, 64, 64, 32, 32>(c, g, A, B, C, alpha);
-  } else {
-    if (g.cfg == 0) launch_grouped<bf16_t, 128, 128, 64, 64>(c, g, A, B, C, alpha);
-    else launch_grouped<bf16_t, 64, 64, 32, 32>(c, g, A, B, C, alpha);
-  }
+  auto run = [&](auto tag) {
+    typedef decltype(tag) S;
+    switch (g.cfg) {
+      case 0: launch_grouped<S, 128, 128, 64, 64>(c, g, A, B, C, alpha); break;
+      case 2: launch_grouped<S, 96, 96, 48, 48>(c, g, A, B, C, alpha); break;
+      case 3: launch_grouped<S, 32, 32, 16, 16>(c, g, A, B, C, alpha); break;
+      default: launch_grouped<S, 64, 64, 32, 32>(c, g, A, B, C, alpha); break;
+    }
+  };
+  if (prec == D3S_F64) run(double());
+  else if (prec == D3S_F32) run(float());
+  else run(bf16_t());
 }
 
 }  // namespace d3s

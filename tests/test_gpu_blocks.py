@@ -70,6 +70,25 @@ def test_block_heff_equals_dense_oracle(ctx, ml, mr, seed):
     plan.close()
 
 
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+def test_block_heff_every_grouped_tile(cfg):
+    """Every grouped tile size (128, 64, 96, 32) gives the oracle's result."""
+    case = hubbard_block_case(150, 130, 17)
+    ref = C.apply_heff(case["L"], case["W"], case["R"], case["psi"])
+    c = abi.Context(0)
+    try:
+        c.set_grouped_tile(cfg)
+        plan = make_plan(c, case)
+        for dt, tol in ((torch.float64, 1e-12), (torch.float32, 3e-5)):
+            out = torch.empty(case["psi"].shape, dtype=dt, device=DEV)
+            plan.apply(dev(case["L"], dt), dev(case["W"], dt), dev(case["R"], dt), dev(case["psi"], dt), out)
+            torch.cuda.synchronize()
+            assert rel_err(out.double().cpu().numpy(), ref) < tol
+        plan.close()
+    finally:
+        c.close()
+
+
 def test_block_heff_f32(ctx):
     case = hubbard_block_case(120, 100, 5)
     f = torch.float32
