@@ -285,7 +285,7 @@ def gradient_bench(ctx, abi, synth, torch, dev, l, m_sched, J2, dJ, tol):
         st = abi.State(mpo, tensors, mmax, device=dev)
         sym = abi.Symmetry(phys, abi.mpo_bond_charges(mpo, chan), secs)
         e0 = ctx.prepare_blocks(st, sym)
-        params = abi.sweep_params(alpha=1e-3, e_before=e0, prec=prec, tol=1e-12)
+        params = abi.sweep_params(alpha=1e-3, e_before=e0, prec=prec, tol=1e-12, mixed_min_gflop=0.0)
         prev, n = None, 0
         plan = [(mm, 2) for mm in sched[:-1]] + [(sched[-1], 12)]
         for mm, count in plan:

@@ -88,7 +88,8 @@ d3s_status d3s_set_tile_config(d3s_ctx ctx, int cfg);
 /* Tile configuration of the grouped block-sparse launches of plans built
  * afterwards: -1 = chosen per launch by a work model (or by timing, with
  * autotuning on; default), 0 = 128x128 tiles, 1 = 64x64, 2 = 96x96,
- * 3 = 32x32 (four waves each). */
+ * 3 = 32x32 (four waves each), 4 = 128x128 (eight waves), 5 = 256x128
+ * (eight waves). */
 d3s_status d3s_set_grouped_tile(d3s_ctx ctx, int cfg);
 /* Autotuning of tile configurations (default off: a size heuristic picks
  * them).  When on, the first dense GEMM of every shape class (precision,
@@ -342,10 +343,14 @@ typedef struct {
   double lanczos_tol;    /* residual tolerance of the eigensolver (1e-12) */
   int lanczos_kmax;      /* Krylov vectors per restart (40; 2..64) */
   int lanczos_max_matvecs; /* products per site update (2000) */
-  d3s_prec prec;         /* arithmetic of the eigensolver's H_eff products */
+  d3s_prec prec;         /* arithmetic of the eigensolver's H_eff products (see d3s_lanczos) */
   double e_before;       /* in/out: energy of the state entering the next site update */
   int m_limit;           /* bond dimension limit of this sweep (<= 0 or > mmax: the state's mmax);
                             lets a run grow m from sweep to sweep in one allocation */
+  double mixed_min_gflop; /* with prec = D3S_F32 / D3S_BF16: sites whose H_eff product costs
+                             fewer GFLOP (allowed blocks only for block sweeps) use FP64
+                             products, since there the products are launch-bound and low
+                             precision saves nothing; 0 = every site mixed */
 } d3s_sweep_params;
 
 /* One record per site update (steps 1-8 of Sec. 5). */

@@ -42,7 +42,7 @@ class d3s_state(ctypes.Structure):
 class d3s_sweep_params(ctypes.Structure):
     _fields_ = [("alpha", c_double), ("adaptive_alpha", c_int), ("eps", c_double),
                 ("lanczos_tol", c_double), ("lanczos_kmax", c_int), ("lanczos_max_matvecs", c_int),
-                ("prec", c_int), ("e_before", c_double), ("m_limit", c_int)]
+                ("prec", c_int), ("e_before", c_double), ("m_limit", c_int), ("mixed_min_gflop", c_double)]
 
 
 class d3s_site_record(ctypes.Structure):
@@ -239,7 +239,8 @@ class Context:
         self._check(_set_eig(self.h, int(kind), int(jacobi_max_n)))
 
     def set_grouped_tile(self, cfg):
-        """-1 model/autotuner, 0 = 128, 1 = 64, 2 = 96, 3 = 32 (grouped tile edge)."""
+        """-1 rule/autotuner; 0: 128x128, 1: 64x64, 2: 96x96, 3: 32x32 (4 waves),
+        4: 128x128, 5: 256x128 (8 waves)."""
         self._check(_set_gtile(self.h, int(cfg)))
 
     def set_splitk(self, enable):
@@ -528,8 +529,9 @@ def mpo_bond_charges(mpo_blocks, channel_q):
 
 
 def sweep_params(alpha=1e-3, adaptive=True, eps=1e-14, tol=1e-12, kmax=40, max_matvecs=2000, prec=F64,
-                 e_before=0.0, m_limit=0):
-    return d3s_sweep_params(alpha, 1 if adaptive else 0, eps, tol, kmax, max_matvecs, prec, e_before, m_limit)
+                 e_before=0.0, m_limit=0, mixed_min_gflop=2.0):
+    return d3s_sweep_params(alpha, 1 if adaptive else 0, eps, tol, kmax, max_matvecs, prec, e_before, m_limit,
+                            mixed_min_gflop)
 
 
 # --- symmetry blocks -------------------------------------------------------

@@ -121,7 +121,7 @@ d3s_status d3s_synchronize(d3s_ctx ctx) {
 
 d3s_status d3s_set_grouped_tile(d3s_ctx ctx, int cfg) {
   return guarded(ctx, [&] {
-    D3S_REQUIRE(cfg >= -1 && cfg <= 3, "grouped tile configuration must be in [-1, 3]");
+    D3S_REQUIRE(cfg >= -1 && cfg <= 5, "grouped tile configuration must be in [-1, 5]");
     ctx->c.grouped_cfg = cfg;
     return D3S_OK;
   });
@@ -343,6 +343,7 @@ d3s_status d3s_sweep(d3s_ctx ctx, d3s_state* state, d3s_sweep_params* params, d3
     D3S_REQUIRE(params->lanczos_kmax >= 2 && params->lanczos_kmax <= 64, "lanczos_kmax must be in [2, 64]");
     D3S_REQUIRE(params->lanczos_tol > 0.0 && params->lanczos_max_matvecs >= 1, "bad eigensolver limits");
     D3S_REQUIRE(params->alpha >= 0.0 && std::isfinite(params->alpha), "alpha must be finite and >= 0");
+    D3S_REQUIRE(params->mixed_min_gflop >= 0.0, "mixed_min_gflop must be >= 0");
     D3S_REQUIRE((long)state->d * state->mmax <= 46340, "d * mmax too large for the Gram route");
     d3s::op_sweep(&ctx->c, state, params, stats);
     if (!std::isfinite(stats->energy)) throw Error{D3S_ENUMERIC, "sweep: non-finite energy"};
@@ -512,6 +513,7 @@ d3s_status d3s_sweep_blocks(d3s_ctx ctx, d3s_state* state, d3s_symmetry* sym, d3
     D3S_REQUIRE(params->lanczos_kmax >= 2 && params->lanczos_kmax <= 64, "lanczos_kmax must be in [2, 64]");
     D3S_REQUIRE(params->lanczos_tol > 0.0 && params->lanczos_max_matvecs >= 1, "bad eigensolver limits");
     D3S_REQUIRE(params->alpha >= 0.0 && std::isfinite(params->alpha), "alpha must be finite and >= 0");
+    D3S_REQUIRE(params->mixed_min_gflop >= 0.0, "mixed_min_gflop must be >= 0");
     d3s::SymChain c = read_sym(state, sym);
     try {
       d3s::op_sweep_blocks(&ctx->c, state, c, params, stats, use_graph != 0);

@@ -6,7 +6,7 @@
 // context's cache (and appended to an optional on-disk cache file of
 // "key cfg" lines, loaded when autotuning is switched on).  Grouped block
 // plans: both tile sizes of the grouped launch are timed on scratch buffers
-// right after the plan is built (all four tile sizes).  Tuning is skipped while a stream is being
+// right after the plan is built (all six tile configurations).  Tuning is skipped while a stream is being
 // captured into a graph and for products that accumulate into C (beta != 0).
 #include <fstream>
 #include <sstream>
@@ -106,7 +106,7 @@ void tune_grouped(Ctx* c, GroupedPlan& g, const void* A, const void* B, void* C)
   if (!c->autotune || g.ntasks == 0 || capturing(c)) return;
   double best = 1e300;
   int best_cfg = g.cfg;
-  for (int cfg = 0; cfg <= 3; ++cfg) {
+  for (int cfg = 0; cfg <= 5; ++cfg) {
     g.cfg = cfg;
     grouped_retile(c, g);
     const double ms = time_ms(c, [&] { grouped_gemm(c, D3S_F64, g, A, B, C, 1.0); }, 2);

@@ -105,11 +105,12 @@ void grouped_finalize(Ctx* c, GroupedPlan& g) {
 }
 
 void grouped_retile(Ctx* c, GroupedPlan& g) {
-  const int tile = grouped_tile(g.cfg);
+  int bm, bn;
+  grouped_tile_dims(g.cfg, bm, bn);
   int acc = 0;
   for (GTask& t : g.tasks) {
     t.tile0 = acc;
-    acc += ((t.M + tile - 1) / tile) * ((t.N + tile - 1) / tile);
+    acc += ((t.M + bm - 1) / bm) * ((t.N + bn - 1) / bn);
   }
   g.total_tiles = acc;
   if (g.ntasks == 0 || !g.d_tasks) return;
@@ -1168,7 +1169,8 @@ void op_sweep_blocks(Ctx* c, d3s_state* s, SymChain& sym, d3s_sweep_params* p, d
       const int ml = s->m[i], mr = s->m[i + 1], wl = s->w[i], wr = s->w[i + 1];
       const double t0 = now_s();
       double* xp = (double*)ws_get(c, WS_PK, sizeof(double) * (size_t)std::max<long>(1, cur.h.npacked));
-      LanczosResult lz = op_lanczos_blocks(c, p->prec, cur.h, s->lenv[i], s->mpo[i], s->renv[i], s->site[i],
+      const d3s_prec prec = (cur.h.flops * 1e-9 >= p->mixed_min_gflop) ? p->prec : D3S_F64;
+      LanczosResult lz = op_lanczos_blocks(c, prec, cur.h, s->lenv[i], s->mpo[i], s->renv[i], s->site[i],
                                            p->lanczos_tol, p->lanczos_kmax, p->lanczos_max_matvecs, use_graph, xp);
       lam = lz.theta;
       if (!lz.converged) st->nonconverged++;

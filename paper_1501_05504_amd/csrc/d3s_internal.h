@@ -37,7 +37,7 @@ struct Error {
 enum WsSlot {
   WS_T1 = 0, WS_T2, WS_LZ_V, WS_LZ_W, WS_LZ_COEF, WS_RED, WS_GRAM, WS_EIGVAL,
   WS_EIGTMP, WS_UKT, WS_X, WS_MT, WS_CAST_L, WS_CAST_R, WS_CAST_X, WS_CAST_Y,
-  WS_CAST_W, WS_REF, WS_PSI, WS_INFO, WS_NBR, WS_MISC, WS_SPLITK, WS_DESC, WS_BLK_X, WS_XPACK, WS_GPACK, WS_GVAL, WS_TUNE, WS_PK, WS_LZ_K, WS_GS_NORM, WS_NSLOTS
+  WS_CAST_W, WS_REF, WS_PSI, WS_INFO, WS_NBR, WS_MISC, WS_SPLITK, WS_DESC, WS_BLK_X, WS_XPACK, WS_GPACK, WS_GVAL, WS_TUNE, WS_PK, WS_LZ_K, WS_GS_NORM, WS_JD_V, WS_JD_W, WS_JD_Z, WS_JD_COEF, WS_NSLOTS
 };
 
 struct Ctx {
@@ -97,10 +97,10 @@ struct GroupedPlan {
   GSeg* d_segs = nullptr;
   int ntasks = 0, total_tiles = 0;
   bool a_kc = true, b_kc = true;
-  int cfg = 1;                  // tile edge: 0 -> 128, 1 -> 64, 2 -> 96, 3 -> 32
+  int cfg = 1;                  // tile configuration (grouped_tile_dims)
   double flops = 0.0;
 };
-int grouped_tile(int cfg);
+void grouped_tile_dims(int cfg, int& bm, int& bn);   // block tile of a grouped configuration
 // sort tasks largest-first, pick the tile size, compute tile prefix sums and
 // upload the tables (synchronises the stream)
 void grouped_finalize(Ctx* c, GroupedPlan& g);

@@ -9,7 +9,11 @@
 // contraction, whose right-bond sectors differ from term to term) are
 // accumulated in registers, without atomics and in a fixed order.
 //
-// Workgroup b takes tile (b - tile0) of the task with the largest tile0 <= b
+// The hardware hands consecutive workgroup ids to the eight XCDs in turn,
+// each with its own L2.  Workgroup ids are therefore remapped so that runs of
+// kChunk consecutive tiles (mostly tiles of one task, which share operand
+// blocks) execute on the same XCD, the runs dealt to the XCDs round-robin for
+// balance.  Tile t then belongs to the task with the largest tile0 <= t
 // (binary search over the prefix sums).  Tasks are sorted largest-first by
 // the host so that long tiles start early.
 #include "mfma_tile.h"
@@ -19,10 +23,14 @@ namespace {
 
 using namespace tile;
 
+constexpr int kChunk = 8;   // consecutive tiles kept on one XCD
+constexpr int kXcd = 8;
+
 struct GParams {
   const GTask* tasks;
   const GSeg* segs;
   int ntasks;
+  int total;                // tiles
   const void* A;
   const void* B;
   void* C;
@@ -42,7 +50,9 @@ void grouped_kernel(GParams p) {
   __shared__ __align__(16) S sA[2][BM * LDK];
   __shared__ __align__(16) S sB[2][BN * LDK];
 
-  const int bid = blockIdx.x;
+  const int xcd = (int)blockIdx.x % kXcd, slot = (int)blockIdx.x / kXcd;
+  const int bid = ((slot / kChunk) * kXcd + xcd) * kChunk + slot % kChunk;
+  if (bid >= p.total) return;
   int lo = 0, hi = p.ntasks - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -145,8 +155,9 @@ void grouped_kernel(GParams p) {
 
 template <typename S, int BM, int BN, int WM, int WN>
 void launch_grouped(Ctx* c, const GroupedPlan& g, const void* A, const void* B, void* C, double alpha) {
-  GParams p{g.d_tasks, g.d_segs, g.ntasks, A, B, C, alpha};
-  dim3 grid((unsigned)g.total_tiles), block((BM / WM) * (BN / WN) * 64);
+  GParams p{g.d_tasks, g.d_segs, g.ntasks, g.total_tiles, A, B, C, alpha};
+  const long span = (long)kXcd * kChunk;
+  dim3 grid((unsigned)((g.total_tiles + span - 1) / span * span)), block((BM / WM) * (BN / WN) * 64);
   if (g.a_kc && g.b_kc)
     hipLaunchKernelGGL((grouped_kernel<S, BM, BN, WM, WN, true, true>), grid, block, 0, c->stream, p);
   else if (g.a_kc && !g.b_kc)
@@ -160,14 +171,17 @@ void launch_grouped(Ctx* c, const GroupedPlan& g, const void* A, const void* B, 
 
 }  // namespace
 
-// tile edge per configuration: 0 = 128 (4 waves of 64x64), 1 = 64 (4 waves
-// of 32x32), 2 = 96 (4 waves of 48x48), 3 = 32 (4 waves of 16x16)
-int grouped_tile(int cfg) {
+// block tile per configuration (rows x columns, waves):
+//   0: 128x128 (4 waves of 64x64)   1: 64x64 (4 of 32x32)    2: 96x96 (4 of 48x48)
+//   3: 32x32 (4 of 16x16)           4: 128x128 (8 of 64x32)  5: 256x128 (8 of 64x64)
+void grouped_tile_dims(int cfg, int& bm, int& bn) {
   switch (cfg) {
-    case 0: return 128;
-    case 2: return 96;
-    case 3: return 32;
-    default: return 64;
+    case 0: bm = bn = 128; break;
+    case 2: bm = bn = 96; break;
+    case 3: bm = bn = 32; break;
+    case 4: bm = bn = 128; break;
+    case 5: bm = 256; bn = 128; break;
+    default: bm = bn = 64; break;
   }
 }
 
@@ -180,6 +194,8 @@ void grouped_gemm(Ctx* c, d3s_prec prec, const GroupedPlan& g, const void* A, co
       case 0: launch_grouped<S, 128, 128, 64, 64>(c, g, A, B, C, alpha); break;
       case 2: launch_grouped<S, 96, 96, 48, 48>(c, g, A, B, C, alpha); break;
       case 3: launch_grouped<S, 32, 32, 16, 16>(c, g, A, B, C, alpha); break;
+      case 4: launch_grouped<S, 128, 128, 64, 32>(c, g, A, B, C, alpha); break;
+      case 5: launch_grouped<S, 256, 128, 64, 64>(c, g, A, B, C, alpha); break;
       default: launch_grouped<S, 64, 64, 32, 32>(c, g, A, B, C, alpha); break;
     }
   };

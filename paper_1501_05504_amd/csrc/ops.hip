@@ -734,21 +734,162 @@ LanczosResult op_lanczos(Ctx* c, d3s_prec p, int ml, int d, int mr, int wl, int 
   return lanczos_with(c, mv, p, psi, n, tol, kmax, max_matvecs);
 }
 
+// FP64 iterative refinement of a Ritz pair with low-precision inner solves
+// (the mixed-precision eigensolver's second phase).
+//
+// An FP64 search space V (orthonormal) with W = H V (FP64 products) is
+// grown one vector per outer step.  The lowest Ritz pair (theta, u = V s)
+// of V^T W gives the exact FP64 residual r = W s - theta u without another
+// product.  The new direction t approximately solves the projected
+// correction equation (I - u u^T)(H - theta)(I - u u^T) t = -r, t _|_ u
+// (Jacobi-Davidson), by conjugate gradients whose products are the
+// low-precision ones (the projected operator is positive definite on u's
+// complement once theta is below the second eigenvalue); the FP64 outer
+// step then removes the error the low-precision products leave.  So nearly
+// all products run in low precision and each outer step costs one FP64
+// product.  The space restarts from u after kJdMax vectors.
+namespace {
+constexpr int kJdMax = 12;
+
+LanczosResult jd_refine(Ctx* c, Matvec& mv, double* x, long n, double tol, int max_mv, int n_inner,
+                        double eta) {
+  LanczosResult res{0.0, 0, false, 0};
+  double* V = (double*)ws_get(c, WS_JD_V, sizeof(double) * (size_t)(kJdMax + 1) * n);
+  double* Wm = (double*)ws_get(c, WS_JD_W, sizeof(double) * (size_t)(kJdMax + 1) * n);
+  // work vectors, contiguous rows: u, p, rs (CG residual), q, t, r
+  double* Z = (double*)ws_get(c, WS_JD_Z, sizeof(double) * (size_t)6 * n);
+  double* u = Z;
+  double* pv = Z + n;
+  double* rs = Z + 2 * n;
+  double* q = Z + 3 * n;
+  double* t = Z + 4 * n;
+  double* r = Z + 5 * n;
+  double* cf = (double*)ws_get(c, WS_JD_COEF, sizeof(double) * 256);
+  double h[8];
+  auto dots = [&](const double* rows, int k, const double* v, double* out_host) {
+    mdot_f64(c, rows, n, k, v, n, cf);
+    D3S_HIP(hipMemcpyAsync(out_host, cf, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
+    D3S_HIP(hipStreamSynchronize(c->stream));
+  };
+  // start: V = [x / |x|], W = [H x]
+  dots(x, 1, x, h);
+  if (!(h[0] > 0.0) || !std::isfinite(h[0])) throw Error{D3S_ENUMERIC, "refinement: zero start vector"};
+  axpby_f64(c, 1.0 / std::sqrt(h[0]), x, 0.0, V, n);
+  mv.product(V, Wm, true);
+  res.matvecs++;
+  res.f64_matvecs++;
+  int k = 1;
+  std::vector<double> S((size_t)kJdMax * kJdMax, 0.0);
+  dots(V, 1, Wm, h);
+  S[0] = h[0];
+  std::vector<double> A, ev, evec, sv;
+  for (;;) {
+    // lowest Ritz pair of S = V^T W (symmetric, k x k)
+    A.assign((size_t)k * k, 0.0);
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < k; ++j) A[(size_t)i * k + j] = 0.5 * (S[(size_t)i * kJdMax + j] + S[(size_t)j * kJdMax + i]);
+    jacobi_eigh(k, A, ev, evec);
+    const double th = ev[0];
+    sv.assign(evec.begin(), evec.begin() + k);
+    res.theta = th;
+    // u = V s, r = W s - th u, |r|
+    write_many(c, cf + 128, sv.data(), k);
+    fill_f64(c, u, n, 0.0);
+    maxpy_f64(c, V, n, k, cf + 128, 1.0, u, n);
+    fill_f64(c, r, n, 0.0);
+    maxpy_f64(c, Wm, n, k, cf + 128, 1.0, r, n);
+    axpby_f64(c, -th, u, 1.0, r, n);
+    dots(r, 1, r, h);
+    const double rn = std::sqrt(std::max(h[0], 0.0));
+    const double scale = std::max(1.0, std::fabs(th));
+    if (!std::isfinite(rn)) throw Error{D3S_ENUMERIC, "refinement: non-finite residual"};
+    if (rn <= tol * scale) {
+      res.converged = true;
+      break;
+    }
+    if (res.matvecs >= max_mv) break;
+    // restart the search space from u, with W_0 = H u = r + th u
+    if (k >= kJdMax) {
+      copy_f64(c, u, V, n);
+      axpby_f64(c, 1.0, r, 0.0, Wm, n);
+      axpby_f64(c, th, u, 1.0, Wm, n);
+      k = 1;
+      S.assign((size_t)kJdMax * kJdMax, 0.0);
+      S[0] = th;
+      res.restarts++;
+    }
+    // CG on the projected correction equation; t = 0, rs = -r (_|_ u), p = rs
+    fill_f64(c, t, n, 0.0);
+    axpby_f64(c, -1.0, r, 0.0, rs, n);
+    copy_f64(c, rs, pv, n);
+    double rr = h[0];
+    for (int it = 0; it < n_inner && res.matvecs < max_mv; ++it) {
+      mv.product(pv, q, false);
+      res.matvecs++;
+      axpby_f64(c, -th, pv, 1.0, q, n);                 // q = (H - th) p
+      dots(u, 2, q, h);                                 // h0 = u.q, h1 = p.q
+      axpby_f64(c, -h[0], u, 1.0, q, n);                // q -= u (u.q); p.q is unchanged as p _|_ u
+      const double pq = h[1];
+      if (!(pq > 0.0) || !std::isfinite(pq)) break;     // not positive definite here: keep t
+      const double al = rr / pq;
+      axpby_f64(c, al, pv, 1.0, t, n);
+      axpby_f64(c, -al, q, 1.0, rs, n);
+      dots(rs, 1, rs, h + 2);
+      const double rr_new = h[2];
+      if (std::sqrt(std::max(rr_new, 0.0)) <= eta * rn) break;
+      axpby_f64(c, 1.0, rs, rr_new / rr, pv, n);        // p = rs + beta p
+      dots(u, 1, pv, h + 3);
+      axpby_f64(c, -h[3], u, 1.0, pv, n);               // keep p _|_ u
+      rr = rr_new;
+    }
+    // first step broke down: fall back to the residual direction
+    dots(t, 1, t, h);
+    if (!(h[0] > 0.0)) axpby_f64(c, -1.0, r, 0.0, t, n);
+    // orthonormalise t against V (twice) and extend V, W
+    for (int pass = 0; pass < 2; ++pass) {
+      mdot_f64(c, V, n, k, t, n, cf);
+      maxpy_f64(c, V, n, k, cf, -1.0, t, n);
+    }
+    dots(t, 1, t, h);
+    if (!(h[0] > 1e-28)) break;                           // nothing new: as converged as it gets
+    double* vk = V + (long)k * n;
+    double* wk = Wm + (long)k * n;
+    axpby_f64(c, 1.0 / std::sqrt(h[0]), t, 0.0, vk, n);
+    mv.product(vk, wk, true);
+    res.matvecs++;
+    res.f64_matvecs++;
+    std::vector<double> col(k + 1);
+    dots(V, k + 1, wk, col.data());
+    for (int i = 0; i <= k; ++i) {
+      S[(size_t)i * kJdMax + k] = col[i];
+      S[(size_t)k * kJdMax + i] = col[i];
+    }
+    ++k;
+  }
+  // x = u (normalised)
+  copy_f64(c, u, x, n);
+  return res;
+}
+}  // namespace
+
 static LanczosResult lanczos_with(Ctx* c, Matvec& mv, d3s_prec p, double* psi, long n, double tol, int kmax,
                                   int max_matvecs) {
   if (p == D3S_F64) return lanczos_core(c, mv, psi, n, tol, kmax, max_matvecs, true);
-  // Mixed precision (products in FP32 / BF16, Krylov vectors, orthogonalisation
-  // and the tridiagonal problem in FP64):
+  // Mixed precision (products in FP32 / BF16; Krylov and search vectors,
+  // orthogonalisation and the small eigenproblems in FP64):
   // 1. Lanczos on the low-precision operator down to what it resolves;
-  // 2. FP64 refinement: Lanczos with FP64 products warm-started from that Ritz
-  //    vector.  Its first product already gives the FP64 Rayleigh quotient and
-  //    the exact FP64 residual; it stops at the caller's tolerance, like
-  //    the FP64 path.  The Ritz value is then an FP64 Rayleigh quotient,
-  //    whose error is quadratic in the residual (<= r^2 / gap).
+  // 2. FP64 iterative refinement of that Ritz vector (jd_refine) to the
+  //    caller's tolerance on the exact FP64 residual.  The Ritz value is an
+  //    FP64 Rayleigh quotient, whose error is quadratic in the residual.
   const double low_tol = (p == D3S_F32) ? 1e-6 : 3e-3;
-  const double refine_tol = tol;
   LanczosResult r1 = lanczos_core(c, mv, psi, n, std::max(tol, low_tol), kmax, max_matvecs, false);
-  LanczosResult r2 = lanczos_core(c, mv, psi, n, refine_tol, kmax, std::max(1, max_matvecs - r1.matvecs), true);
+  if (n <= 2 * kJdMax) {
+    LanczosResult r2 = lanczos_core(c, mv, psi, n, tol, kmax, std::max(1, max_matvecs - r1.matvecs), true);
+    r2.matvecs += r1.matvecs;
+    r2.restarts += r1.restarts;
+    return r2;
+  }
+  LanczosResult r2 = jd_refine(c, mv, psi, n, tol, std::max(2, max_matvecs - r1.matvecs), 20, 0.1);
   r2.matvecs += r1.matvecs;
   r2.restarts += r1.restarts;
   return r2;

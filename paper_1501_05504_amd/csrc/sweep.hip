@@ -128,7 +128,9 @@ void op_sweep(Ctx* c, d3s_state* s, d3s_sweep_params* p, d3s_sweep_stats* st) {
     r.e_before = p->e_before;
     const int ml = s->m[i], mr = s->m[i + 1], wl = s->w[i], wr = s->w[i + 1];
     double t0 = now();
-    LanczosResult lz = op_lanczos(c, p->prec, ml, d, mr, wl, wr, s->lenv[i], s->mpo[i], s->renv[i], s->site[i],
+    const double gf = 2e-9 * ((double)wl * d * ml * ml * mr + (double)d * d * wl * wr * ml * mr + (double)wr * d * ml * mr * mr);
+    const d3s_prec prec = (gf >= p->mixed_min_gflop) ? p->prec : D3S_F64;
+    LanczosResult lz = op_lanczos(c, prec, ml, d, mr, wl, wr, s->lenv[i], s->mpo[i], s->renv[i], s->site[i],
                                   p->lanczos_tol, p->lanczos_kmax, p->lanczos_max_matvecs);
     lam = lz.theta;
     if (!lz.converged) st->nonconverged++;
@@ -171,7 +173,9 @@ void op_sweep(Ctx* c, d3s_state* s, d3s_sweep_params* p, d3s_sweep_stats* st) {
     r.e_before = p->e_before;
     const int ml = s->m[i], mr = s->m[i + 1], wl = s->w[i], wr = s->w[i + 1];
     double t0 = now();
-    LanczosResult lz = op_lanczos(c, p->prec, ml, d, mr, wl, wr, s->lenv[i], s->mpo[i], s->renv[i], s->site[i],
+    const double gf = 2e-9 * ((double)wl * d * ml * ml * mr + (double)d * d * wl * wr * ml * mr + (double)wr * d * ml * mr * mr);
+    const d3s_prec prec = (gf >= p->mixed_min_gflop) ? p->prec : D3S_F64;
+    LanczosResult lz = op_lanczos(c, prec, ml, d, mr, wl, wr, s->lenv[i], s->mpo[i], s->renv[i], s->site[i],
                                   p->lanczos_tol, p->lanczos_kmax, p->lanczos_max_matvecs);
     lam = lz.theta;
     if (!lz.converged) st->nonconverged++;
