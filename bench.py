@@ -407,16 +407,17 @@ def main():
     ap.add_argument("--gaussian-env", action="store_true",
                     help="Gaussian L and R instead of MPS-built environments (same kernels and shapes; "
                          "no eigensolver calls, for counter runs)")
-    ap.add_argument("--no-blocks", action="store_true", help="skip the block-sparse H_eff and sweep measurements")
+    ap.add_argument("--no-blocks", action="store_true", help="skip the block-sparse H_eff, sweep and cylinder measurements")
     ap.add_argument("--sweep-l", type=int, default=64)
     ap.add_argument("--sweep-sched", type=str, default="128,256,512,1024,2048",
                     help="bond limits of the block sweep run (two sweeps each, then to convergence at the last)")
     ap.add_argument("--sweep-max", type=int, default=8, help="sweeps at the last bond limit")
     ap.add_argument("--dense-m", type=int, default=256, help="bond limit of the dense-vs-block one-sweep comparison")
-    ap.add_argument("--cylinder", type=str, default="",
-                    help="bond limits of the 4x16 cylinder run (e.g. 256,512,1024,2048,4096; '' = skip)")
-    ap.add_argument("--cylinder-last", type=int, default=2, help="extra sweeps at the last cylinder bond limit")
-    ap.add_argument("--cylinder-precs", type=str, default="f64,mixed_f32,mixed_bf16")
+    ap.add_argument("--cylinder", type=str, default="256,512,1024,2048,4096",
+                    help="bond limits of the 4x16 cylinder run ('' = skip)")
+    ap.add_argument("--cylinder-last", type=int, default=0, help="extra sweeps at the last cylinder bond limit")
+    ap.add_argument("--cylinder-precs", type=str, default="f64,mixed_bf16",
+                    help="eigensolver product precisions compared (f64, mixed_f32, mixed_bf16)")
     ap.add_argument("--gradient", type=str, default="",
                     help="bond limits of the J1-J2 dE/dJ2 run (l=48, J2=0.24; e.g. 64,128,256,512; '' = skip)")
 
@@ -529,7 +530,7 @@ def main():
     if args.gradient:
         line["gradient"] = gradient_bench(ctx, abi, synth, torch, dev, 48, [int(x) for x in args.gradient.split(",")],
                                           0.24, 1e-4, 1e-11)
-    if args.cylinder:
+    if args.cylinder and not args.no_blocks:
         line["cylinder"] = cylinder_bench(ctx, abi, synth, torch, dev, [int(x) for x in args.cylinder.split(",")],
                                           args.cylinder_last, 1e-10, args.cylinder_precs.split(","))
     if not args.no_cpu:
