@@ -91,6 +91,12 @@ d3s_status d3s_set_tile_config(d3s_ctx ctx, int cfg);
  * 3 = 32x32 (four waves each), 4 = 128x128 (eight waves), 5 = 256x128
  * (eight waves). */
 d3s_status d3s_set_grouped_tile(d3s_ctx ctx, int cfg);
+/* Split-K of the second grouped GEMM in the block sweeps' H_eff (packed
+ * vectors): from min_gflop GFLOP of that product on (default 1.0; < 0 never),
+ * when its output blocks give too few tiles to fill the device, each
+ * block's channel segments are dealt to up to four partial outputs that are
+ * summed afterwards in a fixed order (results stay deterministic). */
+d3s_status d3s_set_block_split(d3s_ctx ctx, double min_gflop);
 /* Autotuning of tile configurations (default off: a size heuristic picks
  * them).  When on, the first dense GEMM of every shape class (precision,
  * layouts, M, N, K) is timed in all tile configurations with HIP events and

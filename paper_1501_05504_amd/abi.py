@@ -73,6 +73,7 @@ _version = _sig("d3s_version", ctypes.c_char_p, [])
 _set_tile_config = _sig("d3s_set_tile_config", c_int, [c_void_p, c_int])
 _set_splitk = _sig("d3s_set_splitk", c_int, [c_void_p, c_int])
 _set_gtile = _sig("d3s_set_grouped_tile", c_int, [c_void_p, c_int])
+_set_bsplit = _sig("d3s_set_block_split", c_int, [c_void_p, c_double])
 _set_autotune = _sig("d3s_set_autotune", c_int, [c_void_p, c_int, ctypes.c_char_p])
 _set_eig = _sig("d3s_set_eigensolver", c_int, [c_void_p, c_int, c_int])
 _eig_batched = _sig("d3s_eig_batched", c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p])
@@ -237,6 +238,10 @@ class Context:
     def set_eigensolver(self, kind, jacobi_max_n=0):
         """0 auto (Jacobi up to jacobi_max_n), 1 divide and conquer, 2 Jacobi."""
         self._check(_set_eig(self.h, int(kind), int(jacobi_max_n)))
+
+    def set_block_split(self, min_gflop):
+        """Split the block sweeps' second GEMM from min_gflop GFLOP on (< 0: never)."""
+        self._check(_set_bsplit(self.h, float(min_gflop)))
 
     def set_grouped_tile(self, cfg):
         """-1 rule/autotuner; 0: 128x128, 1: 64x64, 2: 96x96, 3: 32x32 (4 waves),

@@ -119,6 +119,14 @@ d3s_status d3s_synchronize(d3s_ctx ctx) {
   });
 }
 
+d3s_status d3s_set_block_split(d3s_ctx ctx, double min_gflop) {
+  return guarded(ctx, [&] {
+    D3S_REQUIRE(std::isfinite(min_gflop), "min_gflop must be finite");
+    ctx->c.block_split_gflop = min_gflop;
+    return D3S_OK;
+  });
+}
+
 d3s_status d3s_set_grouped_tile(d3s_ctx ctx, int cfg) {
   return guarded(ctx, [&] {
     D3S_REQUIRE(cfg >= -1 && cfg <= 5, "grouped tile configuration must be in [-1, 5]");

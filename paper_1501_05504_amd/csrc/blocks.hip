@@ -388,12 +388,47 @@ void build_block_heff(Ctx* c, BlockHeff& h, const Sectors& left, const Sectors& 
         }
         h.g2.tasks.push_back(tk);
       }
+  // Split-K of the second GEMM for packed outputs: its tasks (one per output
+  // block, K up to w_r blocks long) are few, so when they would not give the
+  // device a few thousand tiles each task's channel segments are dealt to
+  // up to four sub-tasks writing separate partial outputs, summed afterwards
+  // in a fixed order (deterministic).
+  h.g2_split = 1;
+  if (with_g2 && packed && !h.g2.tasks.empty()) {
+    long tiles = 0;
+    int maxseg = 1;
+    double fl = 0.0;
+    for (const GTask& t : h.g2.tasks) {
+      tiles += (long)((t.M + 63) / 64) * ((t.N + 63) / 64);
+      maxseg = std::max(maxseg, t.nseg);
+      for (int q = t.seg0; q < t.seg0 + t.nseg; ++q) fl += 2.0 * t.M * t.N * h.g2.segs[q].K;
+    }
+    // small products are launch-bound: the extra summation launch would cost more than it saves
+    const bool on = c->block_split_gflop >= 0.0 && fl >= c->block_split_gflop * 1e9;
+    const int S = !on ? 1 : (int)std::min<long>(std::min(4, maxseg), std::max<long>(1, (4096 + tiles - 1) / tiles));
+    if (S > 1) {
+      std::vector<GTask> split;
+      split.reserve(h.g2.tasks.size() * S);
+      for (const GTask& t : h.g2.tasks) {
+        const int per = (t.nseg + S - 1) / S;
+        for (int j = 0; j < S; ++j) {
+          GTask u = t;
+          u.seg0 = t.seg0 + std::min(t.nseg, j * per);
+          u.nseg = std::max(0, std::min(t.nseg, (j + 1) * per) - std::min(t.nseg, j * per));
+          u.c_off = t.c_off + (long)j * h.npacked;
+          split.push_back(u);
+        }
+      }
+      h.g2.tasks.swap(split);
+      h.g2_split = S;
+    }
+  }
   build_wmap_l2r(h, h.wm, 0, (long)wr * mr, (long)d * wr * mr);
   wmap_upload(c, h.wm);
   const size_t nL = (size_t)ml * wl * ml, nP = (size_t)ml * d * mr, nR = (size_t)mr * wr * mr;
   const size_t nT = (size_t)ml * std::max(wl, wr) * d * mr;
   finalize_and_tune(c, h.g1, nL, nP, nT);
-  finalize_and_tune(c, h.g2, nT, nR, nP);
+  finalize_and_tune(c, h.g2, nT, nR, nP * h.g2_split);
   // flops of the allowed block products of the two GEMMs (the W-map is not counted)
   h.flops = h.g1.flops + h.g2.flops;
 }
@@ -640,9 +675,9 @@ void op_update_env_blocks(Ctx* c, BlockHeff& h, d3s_dir dir, const double* env_i
   }
 }
 
-// The four launches of one block-sparse H_eff on stream s.
+// The launches of one block-sparse H_eff on stream s.
 static void enqueue_block_heff(Ctx* c, hipStream_t s, const BlockHeff& h, d3s_prec p, const void* L, const void* W,
-                               const void* R, const void* psi, void* out, void* T1, void* T2) {
+                               const void* R, const void* psi, void* out, void* T1, void* T2, void* part) {
   hipStream_t keep = c->stream;
   c->stream = s;
   const size_t osz = (p == D3S_F64) ? 8 : 4;
@@ -652,7 +687,12 @@ static void enqueue_block_heff(Ctx* c, hipStream_t s, const BlockHeff& h, d3s_pr
   wmap_blocks(c, p, T1, W, T2, h.wm, 1.0);
   // packed outputs have no forbidden entries; dense ones are cleared first
   if (!h.packed) zero_bytes(c, out, osz * (size_t)h.ml * h.d * h.mr);
-  grouped_gemm(c, p, h.g2, T2, R, out, 1.0);
+  if (h.g2_split > 1) {
+    grouped_gemm(c, p, h.g2, T2, R, part, 1.0);
+    sum_partials(c, p == D3S_F64, part, h.g2_split, h.npacked, out);
+  } else {
+    grouped_gemm(c, p, h.g2, T2, R, out, 1.0);
+  }
   c->stream = keep;
 }
 
@@ -662,16 +702,17 @@ void op_apply_heff_blocks(Ctx* c, BlockHeff& h, d3s_prec p, const void* L, const
   const size_t t2sz = (p == D3S_F64) ? 8 : (p == D3S_F32 ? 4 : 2);
   void* T1 = ws_get(c, WS_T1, tsz * (size_t)h.ml * h.wl * h.d * h.mr);
   void* T2 = ws_get(c, WS_T2, t2sz * (size_t)h.ml * h.d * h.wr * h.mr);
+  void* part = (h.g2_split > 1) ? ws_get(c, WS_G2_PART, tsz * (size_t)h.g2_split * h.npacked) : nullptr;
   if (!use_graph) {
-    enqueue_block_heff(c, c->stream, h, p, L, W, R, psi, out, T1, T2);
+    enqueue_block_heff(c, c->stream, h, p, L, W, R, psi, out, T1, T2, part);
     return;
   }
   // One hipGraph per (plan, buffers): captured on a private stream on first
   // use, replayed afterwards; events order it after / before the context's
   // stream work.
-  const void* key[7] = {L, W, R, psi, out, T1, T2};
+  const void* key[8] = {L, W, R, psi, out, T1, T2, part};
   bool same = h.graph_exec != nullptr && h.graph_prec == (int)p;
-  for (int i = 0; i < 7 && same; ++i) same = (h.graph_key[i] == key[i]);
+  for (int i = 0; i < 8 && same; ++i) same = (h.graph_key[i] == key[i]);
   if (!h.cap_stream) {
     hipStream_t cs;
     D3S_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -689,7 +730,7 @@ void op_apply_heff_blocks(Ctx* c, BlockHeff& h, d3s_prec p, const void* L, const
     h.graph_exec = h.graph = nullptr;
     D3S_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     try {
-      enqueue_block_heff(c, cs, h, p, L, W, R, psi, out, T1, T2);
+      enqueue_block_heff(c, cs, h, p, L, W, R, psi, out, T1, T2, part);
     } catch (...) {
       hipGraph_t g;
       (void)hipStreamEndCapture(cs, &g);
@@ -702,7 +743,7 @@ void op_apply_heff_blocks(Ctx* c, BlockHeff& h, d3s_prec p, const void* L, const
     hipGraphExec_t ge;
     D3S_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
     h.graph_exec = ge;
-    for (int i = 0; i < 7; ++i) h.graph_key[i] = key[i];
+    for (int i = 0; i < 8; ++i) h.graph_key[i] = key[i];
     h.graph_prec = (int)p;
   }
   D3S_HIP(hipEventRecord((hipEvent_t)h.ev_in, c->stream));

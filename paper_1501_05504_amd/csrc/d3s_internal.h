@@ -37,7 +37,7 @@ struct Error {
 enum WsSlot {
   WS_T1 = 0, WS_T2, WS_LZ_V, WS_LZ_W, WS_LZ_COEF, WS_RED, WS_GRAM, WS_EIGVAL,
   WS_EIGTMP, WS_UKT, WS_X, WS_MT, WS_CAST_L, WS_CAST_R, WS_CAST_X, WS_CAST_Y,
-  WS_CAST_W, WS_REF, WS_PSI, WS_INFO, WS_NBR, WS_MISC, WS_SPLITK, WS_DESC, WS_BLK_X, WS_XPACK, WS_GPACK, WS_GVAL, WS_TUNE, WS_PK, WS_LZ_K, WS_GS_NORM, WS_JD_V, WS_JD_W, WS_JD_Z, WS_JD_COEF, WS_NSLOTS
+  WS_CAST_W, WS_REF, WS_PSI, WS_INFO, WS_NBR, WS_MISC, WS_SPLITK, WS_DESC, WS_BLK_X, WS_XPACK, WS_GPACK, WS_GVAL, WS_TUNE, WS_PK, WS_LZ_K, WS_GS_NORM, WS_JD_V, WS_JD_W, WS_JD_Z, WS_JD_COEF, WS_G2_PART, WS_NSLOTS
 };
 
 struct Ctx {
@@ -53,6 +53,7 @@ struct Ctx {
   std::string last_error;
   int tile_config = -1;              // GEMM tile configuration (-1 = heuristic)
   int grouped_cfg = -1;              // grouped GEMM tile configuration (-1 = model / autotuner)
+  double block_split_gflop = 1.0;    // split the block GEMM-2 from this many GFLOP on (< 0: never)
   bool splitk_off = false;           // disable split-K (tests compare both paths)
   bool autotune = false;             // time tile configurations on first use of a shape
   int eig_kind = 0;                  // batched eigensolver: 0 auto, 1 divide and conquer, 2 Jacobi
@@ -176,6 +177,8 @@ void axpby_f64(Ctx* c, double a, const double* x, double b, double* y, long n);
 void copy_f64(Ctx* c, const double* x, double* y, long n);
 void fill_f64(Ctx* c, double* x, long n, double v);
 void zero_bytes(Ctx* c, void* x, size_t bytes);   // kernel fill (safe inside graph capture)
+// out[i] = sum_{j < parts} part[j*n + i] in a fixed order (FP64, or FP32 when !f64)
+void sum_partials(Ctx* c, bool f64, const void* part, int parts, long n, void* out);
 // strided 2D block copies: dst[dst_off + r*dst_rs + c*dst_cs] = src[src_off + r*src_rs + c*src_cs]
 struct CopyDesc { long src_off, src_rs, src_cs, dst_off, dst_rs, dst_cs; int rows, cols; };
 void copy_blocks(Ctx* c, const double* src, double* dst, const std::vector<CopyDesc>& desc);
@@ -254,6 +257,7 @@ struct BlockHeff {
   bool penv = false;
   EnvPack epl, epr;
   GroupedPlan g1, g2;                    // H_eff: GEMM-1 and GEMM-2
+  int g2_split = 1;                      // GEMM-2 split-K factor (packed outputs)
   WmapPlan wm;                           // H_eff: T1 -> T2
   // built on first use:
   WmapPlan wm_x;                         // L2R expansion: T1 -> P columns of [psi | P]
@@ -268,7 +272,7 @@ struct BlockHeff {
   void* cap_stream = nullptr;
   void* ev_in = nullptr;
   void* ev_out = nullptr;
-  const void* graph_key[7] = {};
+  const void* graph_key[8] = {};
   int graph_prec = -1;
 };
 void build_block_heff(Ctx* c, BlockHeff& h, const Sectors& left, const Sectors& right, int d, int wl, int wr,

@@ -432,7 +432,14 @@ __global__ void scale_dev_kernel(double* __restrict__ x, long n, const double* _
     x[i] *= f;
 }
 
+// y = a x + b y; with b = 0 the old y is not read (it may hold anything,
+// including NaN bit patterns of fresh workspace)
 __global__ void axpby_kernel(double a, const double* __restrict__ x, double b, double* __restrict__ y, long n) {
+  if (b == 0.0) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+      y[i] = a * x[i];
+    return;
+  }
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
     y[i] = a * x[i] + b * y[i];
 }
@@ -658,6 +665,27 @@ void copy_f64(Ctx* c, const double* x, double* y, long n) {
 
 void fill_f64(Ctx* c, double* x, long n, double v) {
   hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, x, n, v);
+  D3S_HIP(hipGetLastError());
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads)
+void sum_partials_kernel(const T* __restrict__ part, int parts, long n, T* __restrict__ out) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    T acc = part[i];
+    for (int j = 1; j < parts; ++j) acc += part[(long)j * n + i];
+    out[i] = acc;
+  }
+}
+
+void sum_partials(Ctx* c, bool f64, const void* part, int parts, long n, void* out) {
+  if (n <= 0) return;
+  if (f64)
+    hipLaunchKernelGGL(sum_partials_kernel<double>, dim3(grid_for(n)), dim3(kThreads), 0, c->stream,
+                       (const double*)part, parts, n, (double*)out);
+  else
+    hipLaunchKernelGGL(sum_partials_kernel<float>, dim3(grid_for(n)), dim3(kThreads), 0, c->stream,
+                       (const float*)part, parts, n, (float*)out);
   D3S_HIP(hipGetLastError());
 }
 

@@ -199,3 +199,20 @@ def test_local_minimum_escape_sec7_1(ctx):
     qm, dm = sym1.sectors(l // 2)
     pairs = dict(zip(qm.ravel().tolist(), dm.tolist()))
     assert all(pairs.get(-q) == d for q, d in pairs.items())
+
+
+@pytest.mark.parametrize("split", [0.0, -1.0])
+def test_block_sweep_split_second_gemm(split):
+    """Block sweeps with the second GEMM split into partial outputs at every
+    site (threshold 0) and never (-1) reach the exact sector energy, and the
+    split does not change the converged energy."""
+    c = abi.Context(0)
+    try:
+        c.set_block_split(split)
+        l, m = 12, 64
+        mpo = abi.heisenberg_mpo(l)
+        E, *_ = run_blocks(c, mpo, abi.mpo_spin_charges(1), abi.SPIN_HALF_CHARGES, [0], m, 12, 21)
+    finally:
+        c.close()
+    H = ed.spin_chain_hamiltonian(l, {(i, i + 1): 1.0 for i in range(l - 1)})
+    assert abs(E - ed.ground_energy(H, mask=ed.spin_sz(l) == 0)) < 1e-10
