@@ -472,7 +472,6 @@ struct Matvec {
   long n;
   BlockHeff* plan = nullptr;     // block-sparse products when set
   bool use_graph = false;
-  double* xblk = nullptr;        // fixed FP64 input buffer of the captured block graph
   long nl_ = 0, nr_ = 0;         // elements of L and R when not dense (packed block environments)
   void prepare() {
     if (p == D3S_F64) return;
@@ -513,28 +512,6 @@ struct Matvec {
     if (plan) op_apply_heff_blocks(c, *plan, p, Lc, Wc, Rc, xin, yout, false);
     else op_apply_heff(c, p, ml, d, mr, wl, wr, Lc, Wc, Rc, xin, yout);
     cast_f32_to_f64(c, yout, y, n);
-  }
-  // low-precision (or FP64) product
-  void apply(const double* x, double* y) {
-    if (p == D3S_F64) {
-      apply_f64(x, y);
-      return;
-    }
-    if (p == D3S_F32) cast_f64_to_f32(c, x, (float*)xin, n);
-    else cast_f64_to_bf16(c, x, (bf16_t*)xin, n);
-    if (plan) op_apply_heff_blocks(c, *plan, p, Lc, Wc, Rc, xin, yout, use_graph);
-    else op_apply_heff(c, p, ml, d, mr, wl, wr, Lc, Wc, Rc, xin, yout);
-    cast_f32_to_f64(c, yout, y, n);
-  }
-  void apply_f64(const double* x, double* y) {
-    if (plan) {
-      // the captured graph reads a fixed input buffer
-      if (!xblk) xblk = (double*)ws_get(c, WS_BLK_X, sizeof(double) * n);
-      copy_f64(c, x, xblk, n);
-      op_apply_heff_blocks(c, *plan, D3S_F64, L, W, R, xblk, y, use_graph);
-      return;
-    }
-    op_apply_heff(c, D3S_F64, ml, d, mr, wl, wr, L, W, R, x, y);
   }
 };
 
