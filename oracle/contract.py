@@ -110,3 +110,47 @@ def truncate_r2l(Mt, psi, nbr, kmax, eps):
 def energy(L, W, R, psi):
     """<psi|H_eff|psi> / <psi|psi>."""
     return float(np.vdot(psi, apply_heff(L, W, R, psi)) / np.vdot(psi, psi))
+
+
+# --- comparison methods (two-site DMRG of Sec. 7.2, CWF of Sec. 3.3) --------
+
+def apply_heff_two_site(L, W1, W2, R, psi2):
+    """Two-site H_eff psi2 for psi2[x, t1, t2, y] of shape (m_l, d, d, m_r)
+    (the two-site DMRG local problem, compared with in Sec. 7.2), contracted like the single-site
+    one: L over the left MPS bond, W1 over (w, t1), W2 over (v1, t2), R over
+    the right MPO and MPS bonds.  out[a, s1, s2, b]."""
+    T = np.tensordot(L, psi2, axes=([2], [0]))            # [a, w, t1, t2, y]
+    T = np.tensordot(T, W1, axes=([1, 2], [0, 3]))        # [a, t2, y, v1, s1]
+    T = np.tensordot(T, W2, axes=([3, 1], [0, 3]))        # [a, y, s1, v2, s2]
+    return np.tensordot(T, R, axes=([3, 1], [1, 2]))      # [a, s1, s2, b]
+
+
+def cwf_environment(L, W):
+    """The enlarged left environment of the centre-matrix formalism (Sec. 3.3):
+    Lt[(a, s), v, (x, t)] = sum_w L[a, w, x] W[w, v, s, t], shape
+    (m_l d, w_r, m_l d)."""
+    ml, d, wr = L.shape[0], W.shape[2], W.shape[1]
+    Lt = np.einsum("awx,wvst->asvxt", L, W)
+    return Lt.reshape(ml * d, wr, ml * d)
+
+
+def apply_cwf(Lt, R, C):
+    """H applied to the centre matrix C[(x, t), y] of shape (m_l d, m_r) with the
+    enlarged environment: out[(a, s), b] = sum Lt[(a,s), v, (x,t)] C[(x,t), y]
+    R[b, v, y] (Sec. 3.3); 2 w m^3 d (d + 1) flops against 4 w m^3 d (plus the
+    W-map) for the three-step single-site order of Sec. 5, a ratio (d + 1)/2."""
+    T = np.tensordot(Lt, C, axes=([2], [0]))              # [(a,s), v, y]
+    return np.tensordot(T, R, axes=([1, 2], [1, 2]))      # [(a,s), b]
+
+
+def two_site_split(psi2, kmax, eps):
+    """Truncated SVD split of a two-site tensor psi2 (m_l, d, d, m_r) as the
+    (m_l d) x (d m_r) matrix, as two-site DMRG does after its eigensolver:
+    A = U_k (m_l, d, k) and the right factor S_k V_k^T (k, d, m_r).  Returns
+    (A, SVt, s, discarded)."""
+    ml, d, d2, mr = psi2.shape
+    U, s, Vt = np.linalg.svd(psi2.reshape(ml * d, d2 * mr), full_matrices=False)
+    k = truncation_size(s, kmax, eps)
+    A = U[:, :k].reshape(ml, d, k)
+    SVt = (s[:k, None] * Vt[:k]).reshape(k, d2, mr)
+    return A, SVt, s, float(np.sum(s[k:] ** 2))

@@ -450,3 +450,78 @@ def test_hellmann_feynman_and_finite_difference_j1j2():
         return ed.ground_energy(ed.spin_chain_hamiltonian(l, c))
     fd = (e_ed(J2 + dJ) - e_ed(J2 - dJ)) / (2 * dJ)
     assert abs(dEdJ - fd) < 1e-6
+
+
+def test_two_site_heff_pins():
+    """Two-site H_eff: (i) equals its explicit Kronecker matrix; (ii) on a
+    product psi2 = A B its expectation equals the single-site one of B with
+    the left environment grown by A (associativity of the Sec. 2
+    contractions), for a non-orthonormal A too."""
+    rng = np.random.default_rng(5)
+    ml, d, mk, mr, wl, wc, wr = 3, 2, 4, 3, 3, 4, 2
+    L = rng.standard_normal((ml, wl, ml))
+    W1 = rng.standard_normal((wl, wc, d, d))
+    W2 = rng.standard_normal((wc, wr, d, d))
+    R = rng.standard_normal((mr, wr, mr))
+    psi2 = rng.standard_normal((ml, d, d, mr))
+    out = C.apply_heff_two_site(L, W1, W2, R, psi2)
+    H = np.einsum("awx,wvst,vuzr,buy->aszbxtry", L, W1, W2, R).reshape(ml * d * d * mr, -1)
+    assert np.allclose(out.ravel(), H @ psi2.ravel(), atol=1e-12)
+    A = rng.standard_normal((ml, d, mk))
+    B = rng.standard_normal((mk, d, mr))
+    p2 = np.tensordot(A, B, axes=([2], [0]))
+    e2 = np.vdot(p2, C.apply_heff_two_site(L, W1, W2, R, p2))
+    L1 = C.update_left(L, W1, A)
+    e1 = np.vdot(B, C.apply_heff(L1, W2, R, B))
+    assert abs(e2 - e1) < 1e-10 * max(1.0, abs(e1))
+
+
+def test_cwf_application_equals_single_site_heff():
+    """The centre-matrix (CWF) H application with the enlarged environment is
+    the same operator as the single-site H_eff (a different contraction
+    order of the same sums), on random tensors."""
+    rng = np.random.default_rng(6)
+    ml, d, mr, wl, wr = 4, 3, 5, 3, 4
+    L = rng.standard_normal((ml, wl, ml))
+    W = rng.standard_normal((wl, wr, d, d))
+    R = rng.standard_normal((mr, wr, mr))
+    psi = rng.standard_normal((ml, d, mr))
+    Lt = C.cwf_environment(L, W)
+    got = C.apply_cwf(Lt, R, psi.reshape(ml * d, mr))
+    assert np.allclose(got, C.apply_heff(L, W, R, psi).reshape(ml * d, mr), atol=1e-12)
+    # brute force of the enlarged environment
+    Lb = np.zeros((ml, d, wr, ml, d))
+    for a in range(ml):
+        for s in range(d):
+            for v in range(wr):
+                for x in range(ml):
+                    for t in range(d):
+                        Lb[a, s, v, x, t] = sum(L[a, w, x] * W[w, v, s, t] for w in range(wl))
+    assert np.allclose(Lt, Lb.reshape(ml * d, wr, ml * d), atol=1e-13)
+
+
+def test_two_site_split_pins():
+    """Two-site split: on psi2 = U0 diag(sigma) V0^T with orthonormal U0, V0
+    (closed form) the singular values are sigma; the kept factors rebuild the
+    best rank-k approximation, whose squared Frobenius error is the
+    discarded weight (Eckart-Young); A has orthonormal columns; with no
+    truncation psi2 is rebuilt exactly."""
+    rng = np.random.default_rng(8)
+    ml, d, mr, r = 5, 3, 4, 7
+    U0, _ = np.linalg.qr(rng.standard_normal((ml * d, r)))
+    V0, _ = np.linalg.qr(rng.standard_normal((d * mr, r)))
+    sigma = np.array([3.0, 2.5, 1.0, 0.5, 0.25, 1e-3, 1e-5])
+    psi2 = (U0 * sigma) @ V0.T
+    A, SVt, s, disc = C.two_site_split(psi2.reshape(ml, d, d, mr), kmax=4, eps=0.0)
+    assert np.allclose(s[:r], sigma, atol=1e-13) and np.all(s[r:] < 1e-13)
+    Am = A.reshape(ml * d, 4)
+    assert np.allclose(Am.T @ Am, np.eye(4), atol=1e-13)
+    approx = Am @ SVt.reshape(4, d * mr)
+    best = (U0[:, :4] * sigma[:4]) @ V0[:, :4].T
+    assert np.allclose(approx, best, atol=1e-12)
+    assert abs(disc - np.sum(sigma[4:] ** 2)) < 1e-13
+    assert abs(np.linalg.norm(psi2 - approx) ** 2 - disc) < 1e-12
+    A, SVt, s, disc = C.two_site_split(psi2.reshape(ml, d, d, mr), kmax=ml * d, eps=1e-3)
+    assert A.shape[2] == 5                                   # sigma_j > 1e-3 sigma_0 = 3e-3
+    A, SVt, s, disc = C.two_site_split(psi2.reshape(ml, d, d, mr), kmax=ml * d, eps=0.0)
+    assert np.allclose(A.reshape(ml * d, -1) @ SVt.reshape(A.shape[2], -1), psi2, atol=1e-12)
