@@ -370,6 +370,63 @@ def dense_vs_blocks_bench(ctx, abi, synth, torch, dev, l, m, U):
     return out
 
 
+def comparison_bench(ctx, abi, synth, torch, dev, ms_list, steps, warmup=3):
+    """FP64 H application of the three local problems on the Hubbard MPO
+    shape (d = 4, w = 6), same GEMM machinery: the single-site product, the
+    centre-matrix (CWF) form with its enlarged environment, and the two-site
+    product.  Timed with events on the context's stream; flop counts are the
+    algorithmic ones of each contraction order."""
+    d, w = 4, 6
+    W = torch.tensor(abi.hubbard_chain_mpo(3, t=1.0, U=8.0)[1], dtype=torch.float64, device=dev)
+    out = {"workload": "local_problem_comparison_hubbard", "d": d, "w": w}
+
+    def timed(fn, n):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(n):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / n
+
+    for m in ms_list:
+        L = torch.tensor(synth.gaussian((m, w, m), synth.SEED_LEFT), dtype=torch.float64, device=dev) / m
+        R = torch.tensor(synth.gaussian((m, w, m), synth.SEED_RIGHT), dtype=torch.float64, device=dev) / m
+        psi = torch.tensor(synth.gaussian((m, d, m), synth.SEED_PSI), dtype=torch.float64, device=dev)
+        y = torch.empty_like(psi)
+        f1 = heff_flops(m, d, m, w, w)
+        t1 = timed(lambda: ctx.apply_heff(L, W, R, psi, y), steps)
+        Lt = torch.empty((m * d, w, m * d), dtype=torch.float64, device=dev)
+        t_env = timed(lambda: ctx.cwf_environment(L, W, Lt), max(3, steps // 4))
+        yc = torch.empty((m * d, m), dtype=torch.float64, device=dev)
+        pc = psi.view(m * d, m)
+        fc = 2.0 * w * d * d * m ** 3 + 2.0 * w * d * m ** 3
+        tc = timed(lambda: ctx.apply_cwf(Lt, R, pc, yc), steps)
+        del Lt, yc
+        torch.cuda.empty_cache()
+        p2 = torch.tensor(synth.gaussian((m, d, d, m), synth.SEED_PSI + 1), dtype=torch.float64, device=dev)
+        y2 = torch.empty_like(p2)
+        f2 = (2.0 * w * d * d * m ** 3 + 2.0 * d ** 3 * w * w * m * m * 2 + 2.0 * w * d * d * m ** 3)
+        t2 = timed(lambda: ctx.apply_heff_two_site(L, W, W, R, p2, y2), max(5, steps // 2))
+        del p2, y2, L, R, psi, y
+        torch.cuda.empty_cache()
+        e = {"single_site": {"ms": round(t1, 4), "gflop": round(f1 * 1e-9, 2), "tflops": round(f1 / t1 * 1e-9, 2)},
+             "cwf": {"ms": round(tc, 4), "gflop": round(fc * 1e-9, 2), "tflops": round(fc / tc * 1e-9, 2),
+                     "env_build_ms": round(t_env, 4)},
+             "two_site": {"ms": round(t2, 4), "gflop": round(f2 * 1e-9, 2), "tflops": round(f2 / t2 * 1e-9, 2)},
+             "time_ratio_cwf": round(tc / t1, 3), "flop_ratio_cwf": round(fc / f1, 3),
+             "time_ratio_two_site": round(t2 / t1, 3), "flop_ratio_two_site": round(f2 / f1, 3)}
+        out[str(m)] = e
+        print("bench: local problems m=%d: single-site %.3f ms, CWF %.3f ms (x%.2f, flops x%.2f), "
+              "two-site %.3f ms (x%.2f, flops x%.2f)" % (m, t1, tc, tc / t1, fc / f1, t2, t2 / t1, f2 / f1),
+              file=sys.stderr, flush=True)
+    return out
+
+
 def cpu_baseline(L, W, R, psi, budget_s):
     """The oracle's H_eff (NumPy FP64, tensordot in the paper's order) on the
     same arrays, repeated until `budget_s` seconds are used (at least once)."""
@@ -421,6 +478,8 @@ def main():
     ap.add_argument("--gradient", type=str, default="",
                     help="bond limits of the J1-J2 dE/dJ2 run (l=48, J2=0.24; e.g. 64,128,256,512; '' = skip)")
 
+    ap.add_argument("--compare", type=str, default="1024,2048",
+                    help="bond dimensions of the single-site / CWF / two-site H application comparison ('' = skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 1 GiB read + 1 GiB write elementwise kernel (torch.neg) first, "
                          "as the reference for HBM byte counters")
@@ -530,6 +589,9 @@ def main():
     if args.gradient:
         line["gradient"] = gradient_bench(ctx, abi, synth, torch, dev, 48, [int(x) for x in args.gradient.split(",")],
                                           0.24, 1e-4, 1e-11)
+    if args.compare:
+        line["local_problems"] = comparison_bench(ctx, abi, synth, torch, dev,
+                                                  [int(x) for x in args.compare.split(",")], 20)
     if args.cylinder and not args.no_blocks:
         line["cylinder"] = cylinder_bench(ctx, abi, synth, torch, dev, [int(x) for x in args.cylinder.split(",")],
                                           args.cylinder_last, 1e-10, args.cylinder_precs.split(","))

@@ -173,6 +173,10 @@ d3s_status d3s_expand_subspace(d3s_ctx ctx, d3s_dir dir, int ml, int d, int mr, 
  *        becomes nbr_out = A (psi_mat V_k), nbr_other x k.
  * k = min(kmax, #{ j : s_j > rel_cutoff * s_0 }).  Singular values come from
  * the FP64 Gram matrix of Mtilde on its smaller side and rocSOLVER's dsyevd.
+ * nbr_in may be NULL, with nbr_other = m_r (L2R) or m_l (R2L): then nbr_out
+ * is U_k^T psi_mat = S_k V_k^T (k x m_r), or psi_mat V_k = U_k S_k (m_l x k),
+ * the truncated SVD split of a two-site tensor (Mtilde = psi = the two-site
+ * tensor as (m_l d) x (d' m_r'), passed with m_r = d' m_r').
  * `renormalize` != 0 scales nbr_out to unit Frobenius norm.
  * s_host (host, may be NULL) receives the min(m_l d, width) (L2R) or
  * min(width, d m_r) (R2L) singular values, descending.  *k_out (host) and
@@ -182,6 +186,38 @@ d3s_status d3s_truncate(d3s_ctx ctx, d3s_dir dir, int ml, int d, int mr, long wi
                         const double* Mtilde, const double* psi, int kmax, double rel_cutoff,
                         const double* nbr_in, long nbr_other, double* site_out, double* nbr_out,
                         int renormalize, double* s_host, int* k_out, double* discarded);
+
+/*
+ * Two-site H_eff * psi2 (the local problem of two-site DMRG, the comparison
+ * method of the numerical examples, Sec. 7.2; its eigenproblem is d times
+ * larger than the single-site one):
+ *   out[a,s1,s2,b] = sum L[a,w,x] W1[w,v,s1,t1] W2[v,u,s2,t2] psi2[x,t1,t2,y] R[b,u,y]
+ * L (ml, wl, ml), W1 (wl, wc, d, d), W2 (wc, wr, d, d), R (mr, wr, mr),
+ * psi2 and out (ml, d, d, mr), all dense row-major device arrays.  The same
+ * order as the single-site product: GEMM over the left MPS bond, one W-map
+ * per site, GEMM over (u, y).  prec D3S_F64 (double everywhere) or D3S_F32
+ * (float everywhere).  wl*d, wc*d <= 80.  out must not alias psi2.
+ * Asynchronous.
+ */
+d3s_status d3s_apply_heff_two_site(d3s_ctx ctx, d3s_prec prec, int ml, int d, int mr, int wl, int wc, int wr,
+                                   const void* L, const void* W1, const void* W2, const void* R,
+                                   const void* psi2, void* out);
+
+/*
+ * Centre-matrix (CWF) form of the H application (Sec. 3.3; its cost
+ * O(w (d^2 + d) m^3) is compared with the single-site order in Sec. 5):
+ *   Lt[(a,s), v, (x,t)] = sum_w L[a,w,x] W[w,v,s,t]        (d3s_cwf_environment, FP64)
+ *   out[(a,s), b] = sum Lt[(a,s),v,(x,t)] C[(x,t),y] R[b,v,y]   (d3s_apply_cwf)
+ * Lt is (ml d, wr, ml d); C and out are (mlp, mr) with mlp = ml d.  The
+ * application is two GEMMs: over (x,t), then over (v,y).  d3s_apply_cwf
+ * takes prec D3S_F64 or D3S_F32 (Lt, R, C and out in that type).  For
+ * d3s_cwf_environment w_l <= 32 and W must fit 64 KiB.  Device pointers,
+ * caller-owned.  Asynchronous.
+ */
+d3s_status d3s_cwf_environment(d3s_ctx ctx, int ml, int d, int wl, int wr, const double* L, const double* W,
+                               double* Lt);
+d3s_status d3s_apply_cwf(d3s_ctx ctx, d3s_prec prec, int mlp, int mr, int wr, const void* Lt, const void* R,
+                         const void* C, void* out);
 
 /*
  * Environment update (Sec. 2: L_i = L_{i-1} A_i^+ W_i A_i, R_i = R_{i+1} B_i^+ W_i B_i;

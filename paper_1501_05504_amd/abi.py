@@ -81,6 +81,9 @@ _tridiag = _sig("d3s_tridiag_lowest", c_int, [c_int, c_double_p, c_double_p, c_d
 _profile_begin = _sig("d3s_profile_begin", c_int, [c_void_p, c_int])
 _profile_end = _sig("d3s_profile_end", c_int, [c_void_p, c_double_p, c_int_p])
 _apply_heff = _sig("d3s_apply_heff", c_int, [c_void_p, c_int] + [c_int] * 5 + [c_void_p] * 5)
+_apply_heff2 = _sig("d3s_apply_heff_two_site", c_int, [c_void_p, c_int] + [c_int] * 6 + [c_void_p] * 6)
+_cwf_env = _sig("d3s_cwf_environment", c_int, [c_void_p] + [c_int] * 4 + [c_void_p] * 3)
+_apply_cwf = _sig("d3s_apply_cwf", c_int, [c_void_p, c_int] + [c_int] * 3 + [c_void_p] * 4)
 _expand = _sig("d3s_expand_subspace", c_int, [c_void_p, c_int] + [c_int] * 5 + [c_void_p] * 3 +
                [c_double, c_void_p])
 _truncate = _sig("d3s_truncate", c_int, [c_void_p, c_int, c_int, c_int, c_int, c_long, c_void_p, c_void_p,
@@ -276,6 +279,52 @@ class Context:
         return self._check(_apply_heff(self.h, prec, ml, d, mr, wl, wr, _ptr(L), _ptr(W), _ptr(R),
                                        _ptr(psi), _ptr(out)))
 
+    def apply_heff_two_site(self, L, W1, W2, R, psi2, out):
+        """Two-site H_eff * psi2, psi2 and out (ml, d, d, mr); FP64 or FP32."""
+        self._sync_stream()
+        ml, d, d2, mr = psi2.shape
+        wl, wc, wr = W1.shape[0], W1.shape[1], W2.shape[1]
+        if d2 != d or W2.shape[0] != wc:
+            raise ValueError("two-site shapes do not match")
+        prec = _PREC[psi2.dtype]
+        if prec == BF16:
+            raise ValueError("two-site H_eff takes float64 or float32")
+        t = psi2.dtype
+        _need(L, ml * wl * ml, t, "L")
+        _need(W1, wl * wc * d * d, t, "W1")
+        _need(W2, wc * wr * d * d, t, "W2")
+        _need(R, mr * wr * mr, t, "R")
+        _need(psi2, ml * d * d * mr, t, "psi2")
+        _need(out, ml * d * d * mr, t, "out")
+        return self._check(_apply_heff2(self.h, prec, ml, d, mr, wl, wc, wr, _ptr(L), _ptr(W1), _ptr(W2),
+                                        _ptr(R), _ptr(psi2), _ptr(out)))
+
+    def cwf_environment(self, L, W, Lt):
+        """Lt[(a,s), v, (x,t)] = sum_w L[a,w,x] W[w,v,s,t], FP64."""
+        self._sync_stream()
+        ml, wl = L.shape[0], L.shape[1]
+        wr, d = W.shape[1], W.shape[2]
+        f = torch.float64
+        _need(L, ml * wl * ml, f, "L")
+        _need(W, wl * wr * d * d, f, "W")
+        _need(Lt, ml * d * wr * ml * d, f, "Lt")
+        return self._check(_cwf_env(self.h, ml, d, wl, wr, _ptr(L), _ptr(W), _ptr(Lt)))
+
+    def apply_cwf(self, Lt, R, C, out):
+        """out[(a,s), b] = sum Lt[(a,s),v,(x,t)] C[(x,t),y] R[b,v,y]; FP64 or FP32."""
+        self._sync_stream()
+        mlp, mr = C.shape
+        wr = R.shape[1]
+        prec = _PREC[C.dtype]
+        if prec == BF16:
+            raise ValueError("the centre-matrix application takes float64 or float32")
+        t = C.dtype
+        _need(Lt, mlp * wr * mlp, t, "Lt")
+        _need(R, mr * wr * mr, t, "R")
+        _need(C, mlp * mr, t, "C")
+        _need(out, mlp * mr, t, "out")
+        return self._check(_apply_cwf(self.h, prec, mlp, mr, wr, _ptr(Lt), _ptr(R), _ptr(C), _ptr(out)))
+
     def expand_subspace(self, direction, env, W, psi, alpha, Mtilde):
         self._sync_stream()
         ml, d, mr = psi.shape
@@ -293,26 +342,29 @@ class Context:
                                    float(alpha), _ptr(Mtilde)))
 
     def truncate(self, direction, Mtilde, psi, kmax, rel_cutoff, nbr, site_out, nbr_out, renormalize=True):
-        """Returns (k, discarded, singular values)."""
+        """Returns (k, discarded, singular values).  nbr=None: nbr_out receives
+        S_k V_k^T (L2R) or U_k S_k (R2L), the split of a two-site tensor."""
         self._sync_stream()
         ml, d, mr = psi.shape
         f = torch.float64
         if direction == L2R:
             width = Mtilde.shape[1]
-            other = nbr.numel() // mr
+            other = nbr.numel() // mr if nbr is not None else mr
             n = ml * d
             if Mtilde.shape[0] != n:
                 raise ValueError("L2R: Mtilde must have m_l*d rows")
-            _need(nbr, mr * other, f, "nbr")
+            if nbr is not None:
+                _need(nbr, mr * other, f, "nbr")
             _need(site_out, n * min(kmax, n), f, "site_out")
             _need(nbr_out, min(kmax, n) * other, f, "nbr_out")
         else:
             width = Mtilde.shape[0]
-            other = nbr.numel() // ml
+            other = nbr.numel() // ml if nbr is not None else ml
             n = d * mr
             if Mtilde.shape[1] != n:
                 raise ValueError("R2L: Mtilde must have d*m_r columns")
-            _need(nbr, ml * other, f, "nbr")
+            if nbr is not None:
+                _need(nbr, ml * other, f, "nbr")
             _need(site_out, n * min(kmax, n), f, "site_out")
             _need(nbr_out, min(kmax, n) * other, f, "nbr_out")
         _need(Mtilde, Mtilde.shape[0] * Mtilde.shape[1], f, "Mtilde")
@@ -321,7 +373,8 @@ class Context:
         k = c_int()
         disc = c_double()
         self._check(_truncate(self.h, direction, ml, d, mr, width, _ptr(Mtilde), _ptr(psi), kmax,
-                              float(rel_cutoff), _ptr(nbr), other, _ptr(site_out), _ptr(nbr_out),
+                              float(rel_cutoff), _ptr(nbr) if nbr is not None else None, other,
+                              _ptr(site_out), _ptr(nbr_out),
                               1 if renormalize else 0, s, ctypes.byref(k), ctypes.byref(disc)))
         return k.value, disc.value, list(s)
 

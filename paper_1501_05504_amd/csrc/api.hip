@@ -254,7 +254,10 @@ d3s_status d3s_truncate(d3s_ctx ctx, d3s_dir dir, int ml, int d, int mr, long wi
     check_dir(dir);
     D3S_REQUIRE(ml >= 1 && d >= 1 && mr >= 1 && width >= 1 && nbr_other >= 1 && kmax >= 1,
                 "dimensions must be >= 1");
-    D3S_REQUIRE(Mtilde && psi && nbr_in && site_out && nbr_out && k_out && discarded, "null pointer");
+    D3S_REQUIRE(Mtilde && psi && site_out && nbr_out && k_out && discarded, "null pointer");
+    if (!nbr_in)
+      D3S_REQUIRE(nbr_other == (dir == D3S_L2R ? mr : ml),
+                  "without a neighbour, nbr_other must be m_r (L2R) or m_l (R2L)");
     D3S_REQUIRE(rel_cutoff >= 0.0, "rel_cutoff must be >= 0");
     const long n = (dir == D3S_L2R) ? (long)ml * d : (long)d * mr;
     D3S_REQUIRE(n <= 46340, "Gram dimension too large (n^2 must fit in int)");
@@ -425,6 +428,46 @@ d3s_status d3s_apply_heff_blocks(d3s_ctx ctx, d3s_block_plan plan, d3s_prec prec
     D3S_REQUIRE(L && W && R && psi && out, "null tensor pointer");
     D3S_REQUIRE(out != psi && out != L && out != R, "out must not alias an input");
     d3s::op_apply_heff_blocks(&ctx->c, plan->h, prec, L, W, R, psi, out, use_graph != 0);
+    return D3S_OK;
+  });
+}
+
+d3s_status d3s_apply_heff_two_site(d3s_ctx ctx, d3s_prec prec, int ml, int d, int mr, int wl, int wc, int wr,
+                                   const void* L, const void* W1, const void* W2, const void* R, const void* psi2,
+                                   void* out) {
+  return guarded(ctx, [&] {
+    D3S_REQUIRE(prec == D3S_F64 || prec == D3S_F32, "two-site H_eff: prec must be D3S_F64 or D3S_F32");
+    check_dims(ml, d, mr, wl, wr);
+    D3S_REQUIRE(wc >= 1 && wc <= 80, "wc out of range");
+    D3S_REQUIRE((long)d * d * mr <= (1L << 30) && (long)ml * d * d <= (1L << 30) && (long)ml * d <= 65535 &&
+                    (long)wl * d <= 80 && (long)wc * d <= 80 && (long)ml * wl * d * d * mr < (1L << 40) &&
+                    (long)ml * wc * d * d * mr < (1L << 40) && (long)ml * wr * d * d * mr < (1L << 40),
+                "two-site H_eff: dimensions out of range");
+    D3S_REQUIRE(L && W1 && W2 && R && psi2 && out, "null tensor pointer");
+    D3S_REQUIRE(out != psi2, "out must not alias psi2");
+    d3s::op_apply_heff_two_site(&ctx->c, prec, ml, d, mr, wl, wc, wr, L, W1, W2, R, psi2, out);
+    return D3S_OK;
+  });
+}
+
+d3s_status d3s_cwf_environment(d3s_ctx ctx, int ml, int d, int wl, int wr, const double* L, const double* W,
+                               double* Lt) {
+  return guarded(ctx, [&] {
+    check_dims(ml, d, 1, wl, wr);
+    D3S_REQUIRE(L && W && Lt, "null tensor pointer");
+    d3s::cwf_environment(&ctx->c, ml, d, wl, wr, L, W, Lt);
+    return D3S_OK;
+  });
+}
+
+d3s_status d3s_apply_cwf(d3s_ctx ctx, d3s_prec prec, int mlp, int mr, int wr, const void* Lt, const void* R,
+                         const void* C, void* out) {
+  return guarded(ctx, [&] {
+    D3S_REQUIRE(prec == D3S_F64 || prec == D3S_F32, "centre-matrix application: prec must be D3S_F64 or D3S_F32");
+    check_dims(mlp, 1, mr, wr, wr);
+    D3S_REQUIRE(Lt && R && C && out, "null tensor pointer");
+    D3S_REQUIRE(out != C, "out must not alias C");
+    d3s::op_apply_cwf(&ctx->c, prec, mlp, mr, wr, Lt, R, C, out);
     return D3S_OK;
   });
 }

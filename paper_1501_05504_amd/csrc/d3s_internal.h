@@ -200,6 +200,11 @@ void adjoint_reduce_f64(Ctx* c, const double* T1, const double* U, double* G,
 // ---------------------------------------------------------------- host-side ops
 void op_apply_heff(Ctx* c, d3s_prec p, int ml, int d, int mr, int wl, int wr,
                    const void* L, const void* W, const void* R, const void* psi, void* out);
+void op_apply_heff_two_site(Ctx* c, d3s_prec p, int ml, int d, int mr, int wl, int wc, int wr, const void* L,
+                            const void* W1, const void* W2, const void* R, const void* psi2, void* out);
+void op_apply_cwf(Ctx* c, d3s_prec p, int mlp, int mr, int wr, const void* Lt, const void* R, const void* C,
+                  void* out);
+void cwf_environment(Ctx* c, int ml, int d, int wl, int wr, const double* L, const double* W, double* Lt);
 void op_expand(Ctx* c, d3s_dir dir, int ml, int d, int mr, int wl, int wr,
                const double* env, const double* W, const double* psi, double alpha, double* Mt);
 void op_update_env(Ctx* c, d3s_dir dir, int ml, int d, int mr, int wl, int wr,

@@ -668,6 +668,51 @@ void fill_f64(Ctx* c, double* x, long n, double v) {
   D3S_HIP(hipGetLastError());
 }
 
+// Enlarged environment of the centre-matrix formalism:
+// Lt[(a,s), v, (x,t)] = sum_w L[a,w,x] W[w,v,s,t]; one thread per (a, x) with
+// L[a, :, x] in registers and W in LDS.
+template <int MAXW>
+__global__ __launch_bounds__(kThreads)
+void cwf_env_kernel(const double* __restrict__ L, const double* __restrict__ Wg, double* __restrict__ Lt, int ml,
+                    int d, int wl, int wr) {
+  extern __shared__ double sW[];
+  const int nw = wl * wr * d * d;
+  for (int i = threadIdx.x; i < nw; i += blockDim.x) sW[i] = Wg[i];
+  __syncthreads();
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)ml * ml) return;
+  const int a = (int)(e / ml), x = (int)(e % ml);
+  double l[MAXW];
+#pragma unroll
+  for (int w = 0; w < MAXW; ++w) l[w] = (w < wl) ? L[((long)a * wl + w) * ml + x] : 0.0;
+  const long mlp = (long)ml * d;
+  for (int sg = 0; sg < d; ++sg)
+    for (int v = 0; v < wr; ++v) {
+      double* dst = Lt + (((long)a * d + sg) * wr + v) * mlp + (long)x * d;
+      for (int t = 0; t < d; ++t) {
+        double acc = 0.0;
+#pragma unroll
+        for (int w = 0; w < MAXW; ++w)
+          if (w < wl) acc += l[w] * sW[((w * wr + v) * d + sg) * d + t];
+        dst[t] = acc;
+      }
+    }
+}
+
+void cwf_environment(Ctx* c, int ml, int d, int wl, int wr, const double* L, const double* W, double* Lt) {
+  const long n = (long)ml * ml;
+  const size_t sh = sizeof(double) * (size_t)wl * wr * d * d;
+  if (sh > 64 * 1024) throw Error{D3S_EINVAL, "centre-matrix environment: MPO tensor too large for LDS"};
+  const dim3 grid((unsigned)((n + kThreads - 1) / kThreads));
+  if (wl <= 8)
+    hipLaunchKernelGGL(cwf_env_kernel<8>, grid, dim3(kThreads), sh, c->stream, L, W, Lt, ml, d, wl, wr);
+  else if (wl <= 32)
+    hipLaunchKernelGGL(cwf_env_kernel<32>, grid, dim3(kThreads), sh, c->stream, L, W, Lt, ml, d, wl, wr);
+  else
+    throw Error{D3S_EINVAL, "centre-matrix environment: w_l > 32"};
+  D3S_HIP(hipGetLastError());
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads)
 void sum_partials_kernel(const T* __restrict__ part, int parts, long n, T* __restrict__ out) {

@@ -91,6 +91,42 @@ void op_apply_heff(Ctx* c, d3s_prec p, int ml, int d, int mr, int wl, int wr, co
   if (ev) D3S_HIP(hipEventRecord(ev[3], c->stream));
 }
 
+// ---------------------------------------------------------------- comparison methods
+// Two-site H_eff (the two-site DMRG local problem): GEMM over the left MPS
+// bond, a W-map per site MPO, GEMM over the right MPO and MPS bonds; the
+// W-maps are the single-site one with the second site's (t2, y) as the
+// trailing index, then with the first site's (a, s1) as the row.
+void op_apply_heff_two_site(Ctx* c, d3s_prec p, int ml, int d, int mr, int wl, int wc, int wr, const void* L,
+                            const void* W1, const void* W2, const void* R, const void* psi2, void* out) {
+  if (p == D3S_BF16) throw Error{D3S_EINVAL, "two-site H_eff: FP64 or FP32"};
+  const size_t esz = (p == D3S_F64) ? 8 : 4;
+  const long dm = (long)d * mr;
+  void* T1 = ws_get(c, WS_T1, esz * (size_t)std::max((long)ml * wl * d * dm, (long)ml * d * d * wr * mr));
+  void* T2 = ws_get(c, WS_T2, esz * (size_t)ml * d * wc * dm);
+  GemmArgs g1{ml * wl, (int)(d * dm), ml, L, ml, true, 0, psi2, d * dm, false, 0, T1, d * dm, 0, 1.0, 0.0, 1};
+  tuned_gemm(c, p, g1);
+  // T1[a, w, t1, (t2, y)] -> T2[(a, s1), (v1, t2, y)]
+  wmap_l2r(c, p, T1, W1, T2, (long)wc * dm, ml, d, (int)dm, wl, wc, 1.0);
+  // T2[(a, s1), v1, t2, y] -> T3[(a, s1, s2), (v2, y)] (into T1's buffer)
+  wmap_l2r(c, p, T2, W2, T1, (long)wr * mr, ml * d, d, mr, wc, wr, 1.0);
+  GemmArgs g2{ml * d * d, mr, wr * mr, T1, (long)wr * mr, true, 0, R, (long)wr * mr, true, 0, out, mr, 0,
+              1.0, 0.0, 1};
+  tuned_gemm(c, p, g2);
+}
+
+// Centre-matrix (CWF) application with the enlarged environment
+// Lt[(a,s), v, (x,t)]: GEMM over (x,t), then over (v, y).
+void op_apply_cwf(Ctx* c, d3s_prec p, int mlp, int mr, int wr, const void* Lt, const void* R, const void* C,
+                  void* out) {
+  if (p == D3S_BF16) throw Error{D3S_EINVAL, "centre-matrix application: FP64 or FP32"};
+  const size_t esz = (p == D3S_F64) ? 8 : 4;
+  void* T1 = ws_get(c, WS_T1, esz * (size_t)mlp * wr * mr);
+  GemmArgs g1{mlp * wr, mr, mlp, Lt, mlp, true, 0, C, mr, false, 0, T1, mr, 0, 1.0, 0.0, 1};
+  tuned_gemm(c, p, g1);
+  GemmArgs g2{mlp, mr, wr * mr, T1, (long)wr * mr, true, 0, R, (long)wr * mr, true, 0, out, mr, 0, 1.0, 0.0, 1};
+  tuned_gemm(c, p, g2);
+}
+
 // ---------------------------------------------------------------- expansion
 void op_expand(Ctx* c, d3s_dir dir, int ml, int d, int mr, int wl, int wr, const double* env,
                const double* W, const double* psi, double alpha, double* Mt) {
@@ -400,19 +436,24 @@ TruncResult op_truncate(Ctx* c, d3s_dir dir, int ml, int d, int mr, long width, 
   copy2d_f64(c, G + (long)(n - 1) * n, -(long)n, Ukt, n, k, n);
   if (dir == D3S_L2R) {
     transpose_f64(c, Ukt, k, n, site_out);                      // A = U_k, (ml d) x k
-    double* X = (double*)ws_get(c, WS_X, sizeof(double) * (size_t)k * mr);
+    // without a neighbour (the split of a two-site tensor) X = S_k V_k^T is the output
+    double* X = nbr ? (double*)ws_get(c, WS_X, sizeof(double) * (size_t)k * mr) : nbr_out;
     GemmArgs g1{k, mr, n, Ukt, n, true, 0, psi, mr, false, 0, X, mr, 0, 1.0, 0.0, 1};
     gemm_f64(c, g1);                                            // X = U_k^T psi_mat
-    GemmArgs g2{k, (int)nbr_other, mr, X, mr, true, 0, nbr, nbr_other, false, 0, nbr_out, nbr_other, 0,
-                1.0, 0.0, 1};
-    gemm_f64(c, g2);                                            // B~ = X B
+    if (nbr) {
+      GemmArgs g2{k, (int)nbr_other, mr, X, mr, true, 0, nbr, nbr_other, false, 0, nbr_out, nbr_other, 0,
+                  1.0, 0.0, 1};
+      gemm_f64(c, g2);                                          // B~ = X B
+    }
   } else {
     copy_f64(c, Ukt, site_out, (long)k * n);                    // B = V_k^T, k x (d mr)
-    double* X = (double*)ws_get(c, WS_X, sizeof(double) * (size_t)ml * k);
+    double* X = nbr ? (double*)ws_get(c, WS_X, sizeof(double) * (size_t)ml * k) : nbr_out;
     GemmArgs g1{ml, k, n, psi, n, true, 0, Ukt, n, true, 0, X, k, 0, 1.0, 0.0, 1};
     gemm_f64(c, g1);                                            // X = psi_mat V_k
-    GemmArgs g2{(int)nbr_other, k, ml, nbr, ml, true, 0, X, k, false, 0, nbr_out, k, 0, 1.0, 0.0, 1};
-    gemm_f64(c, g2);                                            // A~ = A X
+    if (nbr) {
+      GemmArgs g2{(int)nbr_other, k, ml, nbr, ml, true, 0, X, k, false, 0, nbr_out, k, 0, 1.0, 0.0, 1};
+      gemm_f64(c, g2);                                          // A~ = A X
+    }
   }
   if (renormalize) {
     const long nn = (long)k * nbr_other;
