@@ -154,3 +154,110 @@ def two_site_split(psi2, kmax, eps):
     A = U[:, :k].reshape(ml, d, k)
     SVt = (s[:k, None] * Vt[:k]).reshape(k, d2, mr)
     return A, SVt, s, float(np.sum(s[k:] ** 2))
+
+
+# --- exact-residual expansion term (the residual Z = H Psi - E Psi of the
+# Sec. 4 opening, in place of the cheap term of eq. subexp-ourt) ------------
+#
+# At site i of a left-to-right sweep the residual is kept with its left part
+# projected onto the current left basis A_{<i} (those rows are what the
+# expanded tensor's left bond can take up) and its right part exact.  Its
+# coefficients on |A_a s> are then spread over the right-side vectors
+# |B_y> (from -E Psi) and H_{>i,v} |B_y> (from H Psi, the local H Psi
+# coefficients being L M W), which are not orthonormal: the metric between
+# them needs <H_v B_y | H_v' B_y'>, the right environment of the channel
+# pairs of H^2.  Right-to-left is the mirror.
+
+def update_left_h2(G, W, A):
+    """G_new[b, v, u, y] = <H_v A_b | H_u A_y> for the left-part MPO
+    operators H_v (channel v of the bond right of the site):
+    sum G[a, w, c, x] A[a, t, b] W[w, v, s, t] W[c, u, s, e] A[x, e, y]."""
+    X = np.tensordot(G, A, axes=([3], [0]))               # [a, w, c, e, y]
+    X = np.tensordot(X, W, axes=([2, 3], [0, 3]))         # [a, w, y, u, s]
+    X = np.tensordot(X, W, axes=([1, 4], [0, 2]))         # [a, y, u, v, t]
+    X = np.tensordot(A, X, axes=([0, 1], [0, 4]))         # [b, y, u, v]
+    return X.transpose(0, 3, 2, 1)
+
+
+def update_right_h2(G, W, B):
+    """G_new[y, v, z, x] = <H_v B_y | H_z B_x> for the right-part MPO
+    operators H_v (channel v of the bond left of the site):
+    sum B[y, t, b] W[v, u, s, t] W[z, c, s, e] B[x, e, q] G[b, u, c, q]."""
+    X = np.tensordot(B, G, axes=([2], [3]))               # [x, e, b, u, c]
+    X = np.tensordot(X, W, axes=([1, 4], [3, 1]))         # [x, b, u, z, s]
+    X = np.tensordot(X, W, axes=([2, 4], [1, 2]))         # [x, b, z, v, t]
+    X = np.tensordot(B, X, axes=([1, 2], [4, 1]))         # [y, x, z, v]
+    return X.transpose(0, 3, 2, 1)
+
+
+def residual_gram_l2r(L, W, R, Gr, psi, E, alpha):
+    """Left Gram matrix (m_l d) x (m_l d) of the expanded tensor [M | alpha Z]
+    whose expansion part is the exact residual: M M^T + alpha^2 <z|z>, with
+    z_{(a,s)} = sum_y (-E M[a,s,y]) |B_y> + sum_{v,y} (L M W)[a,s,v,y] H_v|B_y>.
+    R is the right environment of the site and Gr the H^2 one (bond right
+    of the site)."""
+    ml, d, mr = psi.shape
+    wr = W.shape[1]
+    Mm = psi.reshape(ml * d, mr)
+    Pm = expansion_term_l2r(L, W, psi, 1.0).reshape(ml * d, wr * mr)
+    Zc = np.hstack([-E * Mm, Pm])
+    Rm = R.reshape(mr, wr * mr)                              # <B_y'|H_v B_y> = R[y', v, y]
+    Ghh = Gr.transpose(1, 0, 2, 3).reshape(wr * mr, wr * mr)
+    G = np.block([[np.eye(mr), Rm], [Rm.T, Ghh]])
+    return Mm @ Mm.T + alpha ** 2 * (Zc @ G @ Zc.T)
+
+
+def residual_gram_r2l(L, W, R, Gl, psi, E, alpha):
+    """Right Gram matrix (d m_r) x (d m_r) of [M ; alpha Z] (mirror of
+    residual_gram_l2r): z_{(s,b)} = sum_a (-E M[a,s,b]) |A_a> +
+    sum_{w,a} (W M R)[w,a,s,b] H_w|A_a>, with the metric <A_a'|H_w A_a> =
+    L[a', w, a] and <H_w A_a | H_w' A_a'> = Gl[a, w, w', a']."""
+    ml, d, mr = psi.shape
+    wl = W.shape[0]
+    Mm = psi.reshape(ml, d * mr)
+    Pm = expansion_term_r2l(R, W, psi, 1.0).reshape(wl * ml, d * mr)
+    Zc = np.vstack([-E * Mm, Pm])
+    Lm = L.reshape(ml, wl * ml)
+    Ghh = Gl.transpose(1, 0, 2, 3).reshape(wl * ml, wl * ml)
+    G = np.block([[np.eye(ml), Lm], [Lm.T, Ghh]])
+    return Mm.T @ Mm + alpha ** 2 * (Zc.T @ G @ Zc)
+
+
+GRAM_RESOLUTION = np.finfo(np.float64).eps
+
+
+def _gram_spectrum(Gram, kmax, eps):
+    """Eigenpairs of a Gram matrix, descending, and the number kept: at most
+    kmax, and only s_j^2 > max(eps^2, n u) s_0^2 (a Gram matrix resolves
+    s_j^2 only to about n u s_0^2)."""
+    lam, V = np.linalg.eigh(Gram)
+    order = np.argsort(lam)[::-1]
+    s2 = np.maximum(lam[order], 0.0)
+    V = V[:, order]
+    n = Gram.shape[0]
+    floor2 = max(eps * eps, n * GRAM_RESOLUTION) * s2[0]
+    k = int(min(kmax, np.count_nonzero(s2 > floor2)))
+    return s2, V, k
+
+
+def truncate_gram_l2r(Gram, psi, nbr, kmax, eps):
+    """Steps 4-5 of the site update from the left Gram matrix of the expanded
+    tensor: A = its top-k eigenvectors (the left singular vectors of M~),
+    B~ = (A^T M) B.  Returns (A, B~, s, discarded)."""
+    ml, d, mr = psi.shape
+    s2, V, k = _gram_spectrum(Gram, kmax, eps)
+    U = V[:, :k]
+    X = U.T @ psi.reshape(ml * d, mr)
+    nb = X @ nbr.reshape(mr, -1)
+    return U.reshape(ml, d, k), nb.reshape(k, nbr.shape[1], nbr.shape[2]), np.sqrt(s2), float(np.sum(s2[k:]))
+
+
+def truncate_gram_r2l(Gram, psi, nbr, kmax, eps):
+    """Mirror of truncate_gram_l2r: B = top-k eigenvectors as rows,
+    A~ = A (M B^T)."""
+    ml, d, mr = psi.shape
+    s2, V, k = _gram_spectrum(Gram, kmax, eps)
+    Vk = V[:, :k]
+    X = psi.reshape(ml, d * mr) @ Vk
+    na = nbr.reshape(-1, ml) @ X
+    return Vk.T.reshape(k, d, mr), na.reshape(nbr.shape[0], nbr.shape[1], k), np.sqrt(s2), float(np.sum(s2[k:]))

@@ -26,6 +26,12 @@ not code):
     state and alpha is left unchanged; elif |dE_O| < 1e-13 |E| shrink alpha
     by 0.8; elif dE_T < 0.3 |dE_O| (including dE_T < 0) grow it by 1.25;
     else shrink it by 0.8; alpha is kept in [1e-16, 1];
+  * expansion="residual" replaces P by the exact residual H Psi - E Psi
+    (the Sec. 4 opening), with E the eigenvalue lambda* of step 1, its far
+    side projected onto the current basis and its near side exact (see
+    contract.residual_gram_l2r); the truncation then works on the Gram
+    matrix of the expanded tensor, whose eigenvalues are resolved down to
+    n u s_0^2;
   * one sweep is right-to-left over sites l..2 followed by left-to-right over
     sites 1..l-1 (the initial state is left-canonical with its centre on
     site l); E_s is the last lambda* of sweep s and the run stops when
@@ -48,7 +54,10 @@ ALPHA_MAX = 1.0
 
 class DMRG3S:
     def __init__(self, mpo, tensors, mmax, alpha0=1e-3, eps=1e-14,
-                 lanczos_tol=1e-12, lanczos_kmax=40, adaptive_alpha=True):
+                 lanczos_tol=1e-12, lanczos_kmax=40, adaptive_alpha=True, expansion="heuristic"):
+        if expansion not in ("heuristic", "residual"):
+            raise ValueError("expansion must be 'heuristic' or 'residual'")
+        self.expansion = expansion
         self.W = [np.asarray(w, dtype=np.float64) for w in mpo]
         self.l = len(mpo)
         self.d = self.W[0].shape[2]
@@ -66,6 +75,14 @@ class DMRG3S:
         for i in range(l - 1):
             self.Lenv[i + 1] = C.update_left(self.Lenv[i], self.W[i], self.M[i])
         self.Renv[l] = np.ones((1, 1, 1))
+        if expansion == "residual":
+            # environments of the channel pairs of H^2 (metric of the residual)
+            self.H2L = [None] * (l + 1)
+            self.H2R = [None] * (l + 1)
+            self.H2L[0] = np.ones((1, 1, 1, 1))
+            for i in range(l - 1):
+                self.H2L[i + 1] = C.update_left_h2(self.H2L[i], self.W[i], self.M[i])
+            self.H2R[l] = np.ones((1, 1, 1, 1))
         self.E_before = C.energy(self.Lenv[l - 1], self.W[l - 1], self.Renv[l], self.M[l - 1])
         self.history = []
         self.sweep_energies = []
@@ -98,13 +115,19 @@ class DMRG3S:
 
     def step_r2l(self, i):
         lam, psi, nmv = self.eigensolve(i)
-        P = C.expansion_term_r2l(self.Renv[i + 1], self.W[i], psi, self.alpha)
-        Mt = C.expanded_tensor_r2l(psi, P)
-        B, A, s, disc = C.truncate_r2l(Mt, psi, self.M[i - 1], self.budget[i], self.eps)
+        if self.expansion == "residual":
+            Gm = C.residual_gram_r2l(self.Lenv[i], self.W[i], self.Renv[i + 1], self.H2L[i], psi, lam, self.alpha)
+            B, A, s, disc = C.truncate_gram_r2l(Gm, psi, self.M[i - 1], self.budget[i], self.eps)
+        else:
+            P = C.expansion_term_r2l(self.Renv[i + 1], self.W[i], psi, self.alpha)
+            Mt = C.expanded_tensor_r2l(psi, P)
+            B, A, s, disc = C.truncate_r2l(Mt, psi, self.M[i - 1], self.budget[i], self.eps)
         A = A / np.linalg.norm(A)
         self.M[i] = B
         self.M[i - 1] = A
         self.Renv[i] = C.update_right(self.Renv[i + 1], self.W[i], B)
+        if self.expansion == "residual":
+            self.H2R[i] = C.update_right_h2(self.H2R[i + 1], self.W[i], B)
         Ef = C.energy(self.Lenv[i - 1], self.W[i - 1], self.Renv[i], A)
         self._record(i, "r2l", lam, Ef, B.shape[0], disc, nmv)
         self.update_alpha(lam, Ef, disc, float(np.sum(s ** 2)))
@@ -113,13 +136,19 @@ class DMRG3S:
 
     def step_l2r(self, i):
         lam, psi, nmv = self.eigensolve(i)
-        P = C.expansion_term_l2r(self.Lenv[i], self.W[i], psi, self.alpha)
-        Mt = C.expanded_tensor_l2r(psi, P)
-        A, B, s, disc = C.truncate_l2r(Mt, psi, self.M[i + 1], self.budget[i + 1], self.eps)
+        if self.expansion == "residual":
+            Gm = C.residual_gram_l2r(self.Lenv[i], self.W[i], self.Renv[i + 1], self.H2R[i + 1], psi, lam, self.alpha)
+            A, B, s, disc = C.truncate_gram_l2r(Gm, psi, self.M[i + 1], self.budget[i + 1], self.eps)
+        else:
+            P = C.expansion_term_l2r(self.Lenv[i], self.W[i], psi, self.alpha)
+            Mt = C.expanded_tensor_l2r(psi, P)
+            A, B, s, disc = C.truncate_l2r(Mt, psi, self.M[i + 1], self.budget[i + 1], self.eps)
         B = B / np.linalg.norm(B)
         self.M[i] = A
         self.M[i + 1] = B
         self.Lenv[i + 1] = C.update_left(self.Lenv[i], self.W[i], A)
+        if self.expansion == "residual":
+            self.H2L[i + 1] = C.update_left_h2(self.H2L[i], self.W[i], A)
         Ef = C.energy(self.Lenv[i + 1], self.W[i + 1], self.Renv[i + 2], B)
         self._record(i, "l2r", lam, Ef, A.shape[2], disc, nmv)
         self.update_alpha(lam, Ef, disc, float(np.sum(s ** 2)))

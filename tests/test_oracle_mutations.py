@@ -78,3 +78,27 @@ def test_wrong_neighbour_update_is_caught(monkeypatch):
     monkeypatch.setattr(C, "truncate_l2r", bad)
     with pytest.raises(AssertionError):
         pins.test_truncation_without_cut_keeps_state_and_discarded_weight("l2r")
+
+
+def test_swapped_channel_pair_in_h2_environment_is_caught(monkeypatch):
+    good = C.update_right_h2
+    monkeypatch.setattr(C, "update_right_h2",
+                        lambda G, W, B: np.ascontiguousarray(good(G, W, B).transpose(0, 2, 1, 3)))
+    with pytest.raises(AssertionError):
+        pins.test_h2_environments_equal_bruteforce("heisenberg")
+
+
+@pytest.mark.parametrize("mistake", ["energy_sign", "no_cross_terms", "alpha_once"])
+def test_wrong_residual_metric_is_caught(monkeypatch, mistake):
+    good = C.residual_gram_l2r
+
+    def bad(L, W, R, Gr, psi, E, alpha):
+        if mistake == "energy_sign":
+            return good(L, W, R, Gr, psi, -E, alpha)
+        if mistake == "alpha_once":
+            return good(L, W, R, Gr, psi, E, np.sqrt(alpha))
+        return good(L, W, np.zeros_like(R), Gr, psi, E, alpha) + \
+            (good(L, W, R, Gr, psi, E, 0.0) - good(L, W, np.zeros_like(R), Gr, psi, E, 0.0))
+    monkeypatch.setattr(C, "residual_gram_l2r", bad)
+    with pytest.raises(AssertionError):
+        pins.test_residual_gram_equals_bruteforce("l2r", "heisenberg")

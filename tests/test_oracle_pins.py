@@ -525,3 +525,170 @@ def test_two_site_split_pins():
     assert A.shape[2] == 5                                   # sigma_j > 1e-3 sigma_0 = 3e-3
     A, SVt, s, disc = C.two_site_split(psi2.reshape(ml, d, d, mr), kmax=ml * d, eps=0.0)
     assert np.allclose(A.reshape(ml * d, -1) @ SVt.reshape(A.shape[2], -1), psi2, atol=1e-12)
+
+
+# ---------------------------------------------------------------- exact residual (f2)
+def _left_channel_ops(mpo, k):
+    """Dense operators H_{<k, w} of the MPO's left part (sites 0..k-1), one per
+    channel w of bond k, built by Kronecker products site by site."""
+    ops = [np.ones((1, 1))]
+    for j in range(k):
+        W = mpo[j]
+        ops = [sum(np.kron(ops[w], W[w, v]) for w in range(W.shape[0])) for v in range(W.shape[1])]
+    return ops
+
+
+def _right_channel_ops(mpo, k):
+    """Dense operators H_{>=k, v} of the MPO's right part (sites k..l-1)."""
+    ops = [np.ones((1, 1))]
+    for j in range(len(mpo) - 1, k - 1, -1):
+        W = mpo[j]
+        ops = [sum(np.kron(W[v, u], ops[u]) for u in range(W.shape[1])) for v in range(W.shape[0])]
+    return ops
+
+
+def _left_basis(M, k):
+    """Left basis states of bond k as columns, (d^k, m_k)."""
+    Phi = np.ones((1, 1))
+    for j in range(k):
+        Phi = np.tensordot(Phi, M[j], axes=([1], [0])).reshape(-1, M[j].shape[2])
+    return Phi
+
+
+def _right_basis(M, k):
+    """Right basis states of bond k as rows, (m_k, d^(l-k))."""
+    Bf = np.ones((1, 1))
+    for j in range(len(M) - 1, k - 1, -1):
+        Bf = np.tensordot(M[j], Bf, axes=([2], [0])).reshape(M[j].shape[0], -1)
+    return Bf
+
+
+@pytest.mark.parametrize("model", ["heisenberg", "hubbard"])
+def test_h2_environments_equal_bruteforce(model):
+    """<H_v A_b | H_u A_y> and <H_v B_y | H_u B_x> from the recursions equal
+    the products of the dense channel operators with the dense basis states."""
+    if model == "heisenberg":
+        l, d, m, center = 6, 2, 4, 3
+        mpo = MPO.heisenberg_mpo(l)
+    else:
+        l, d, m, center = 4, 4, 5, 2
+        mpo = MPO.hubbard_chain_mpo(l, t=1.0, U=4.0)
+    M = _mixed_canonical(synth.random_mps(l, d, m, seed=21), center)
+    G = np.ones((1, 1, 1, 1))
+    for j in range(center):
+        G = C.update_left_h2(G, mpo[j], M[j])
+    ops, Phi = _left_channel_ops(mpo, center), _left_basis(M, center)
+    ref = np.array([[(ops[v] @ Phi).T @ (ops[u] @ Phi) for u in range(len(ops))] for v in range(len(ops))])
+    assert np.allclose(G, ref.transpose(2, 0, 1, 3), atol=1e-12)
+    G = np.ones((1, 1, 1, 1))
+    for j in range(l - 1, center, -1):
+        G = C.update_right_h2(G, mpo[j], M[j])
+    ops, Bf = _right_channel_ops(mpo, center + 1), _right_basis(M, center + 1)
+    ref = np.array([[(ops[v] @ Bf.T).T @ (ops[u] @ Bf.T) for u in range(len(ops))] for v in range(len(ops))])
+    assert np.allclose(G, ref.transpose(2, 0, 1, 3), atol=1e-12)
+
+
+@pytest.mark.parametrize("direction", ["l2r", "r2l"])
+@pytest.mark.parametrize("model", ["heisenberg", "hubbard"])
+def test_residual_gram_equals_bruteforce(direction, model):
+    """The Gram matrix of [M | alpha Z] (or [M ; alpha Z]) from environments
+    equals the one of the dense residual (H - E)|Psi> with its far side
+    projected onto the state's basis, H from exact diagonalisation's own
+    construction; projecting the near side too leaves H_eff M - E M."""
+    if model == "heisenberg":
+        l, d, m, center = 6, 2, 4, 2
+        mpo = MPO.heisenberg_mpo(l)
+        H = ed.spin_chain_hamiltonian(l, {(i, i + 1): 1.0 for i in range(l - 1)}).toarray()
+    else:
+        l, d, m, center = 4, 4, 5, 1
+        mpo = MPO.hubbard_chain_mpo(l, t=1.0, U=4.0)
+        H = ed.hubbard_hamiltonian(l, {(i, i + 1): 1.0 for i in range(l - 1)}, U=4.0).toarray()
+    M = _mixed_canonical(synth.random_mps(l, d, m, seed=22), center)
+    psi = M[center]
+    ml, _, mr = psi.shape
+    v = state_vector(M)
+    E, alpha = 0.37, 0.6
+    z = H @ v - E * v
+    Lenv, Renv = _envs(mpo, M, center)
+    Phi, Bf = _left_basis(M, center), _right_basis(M, center + 1)
+    if direction == "l2r":
+        Zl = np.tensordot(Phi, z.reshape(Phi.shape[0], d, -1), axes=([0], [0])).reshape(ml * d, -1)
+        Mf = (psi.reshape(ml * d, mr) @ Bf)
+        brute = Mf @ Mf.T + alpha ** 2 * Zl @ Zl.T
+        G = np.ones((1, 1, 1, 1))
+        for j in range(l - 1, center, -1):
+            G = C.update_right_h2(G, mpo[j], M[j])
+        got = C.residual_gram_l2r(Lenv, mpo[center], Renv, G, psi, E, alpha)
+        proj = (Zl @ Bf.T).reshape(ml, d, mr)
+    else:
+        Zr = np.tensordot(z.reshape(-1, d, Bf.shape[1]), Bf, axes=([2], [1]))    # [left, s, b]
+        Zr = Zr.reshape(-1, d * mr)
+        Mf = Phi @ psi.reshape(ml, d * mr)
+        brute = Mf.T @ Mf + alpha ** 2 * Zr.T @ Zr
+        G = np.ones((1, 1, 1, 1))
+        for j in range(center):
+            G = C.update_left_h2(G, mpo[j], M[j])
+        got = C.residual_gram_r2l(Lenv, mpo[center], Renv, G, psi, E, alpha)
+        proj = (Phi.T @ Zr).reshape(ml, d, mr)
+    assert np.abs(got - brute).max() < 1e-11 * np.abs(brute).max()
+    heff = C.apply_heff(Lenv, mpo[center], Renv, psi) - E * psi
+    assert np.allclose(proj, heff, atol=1e-12)
+
+
+def test_truncate_gram_equals_svd_truncation():
+    """With the Gram matrix of an explicit M~ the Gram truncation keeps the
+    same subspace, singular values and neighbour as the SVD truncation."""
+    ml, d, mr, width = 4, 2, 5, 20
+    Mt = synth.gaussian((ml * d, width), 31)
+    psi = Mt[:, :mr].reshape(ml, d, mr).copy()
+    nbr = synth.gaussian((mr, d, 3), 32)
+    A1, B1, s1, d1 = C.truncate_l2r(Mt, psi, nbr, 5, 1e-14)
+    A2, B2, s2, d2 = C.truncate_gram_l2r(Mt @ Mt.T, psi, nbr, 5, 1e-14)
+    P1 = A1.reshape(ml * d, -1) @ A1.reshape(ml * d, -1).T
+    P2 = A2.reshape(ml * d, -1) @ A2.reshape(ml * d, -1).T
+    assert np.allclose(P1, P2, atol=1e-10)
+    assert np.allclose(s1, s2[:s1.size], atol=1e-10 * s1[0])
+    assert abs(d1 - d2) < 1e-10 * np.sum(s1 ** 2)
+    # the neighbour matches up to the sign of each kept vector
+    sign = np.sign(np.sum(A1.reshape(ml * d, -1) * A2.reshape(ml * d, -1), axis=0))
+    assert np.allclose(B1, B2 * sign[:, None, None], atol=1e-10)
+    Mr = synth.gaussian((width, d * mr), 33)
+    psi_r = Mr[:ml].reshape(ml, d, mr).copy()
+    nbr_r = synth.gaussian((3, d, ml), 34)
+    B1, A1, s1, d1 = C.truncate_r2l(Mr, psi_r, nbr_r, 6, 1e-14)
+    B2, A2, s2, d2 = C.truncate_gram_r2l(Mr.T @ Mr, psi_r, nbr_r, 6, 1e-14)
+    V1, V2 = B1.reshape(-1, d * mr), B2.reshape(-1, d * mr)
+    assert np.allclose(V1.T @ V1, V2.T @ V2, atol=1e-10)
+    assert abs(d1 - d2) < 1e-10 * np.sum(s1 ** 2)
+
+
+def test_dmrg3s_residual_expansion(heis12_ed):
+    """The exact-residual expansion reaches ED at the exact bond, and at a
+    truncated bond its converged energy is as good as the cheap term's
+    (Sec. 4.2: the two work essentially equally well)."""
+    l = 12
+    run = DMRG3S(MPO.heisenberg_mpo(l), synth.random_mps(l, 2, 64), mmax=64, alpha0=1e-3, expansion="residual")
+    E, _ = run.run(tol=1e-12, max_sweeps=12)
+    assert abs(E - heis12_ed) < 1e-10
+    for h in run.history:
+        assert h["lam"] >= heis12_ed - 1e-10
+    res = DMRG3S(MPO.heisenberg_mpo(l), synth.random_mps(l, 2, 16), mmax=16, alpha0=1e-3, expansion="residual")
+    E_res, _ = res.run(tol=1e-12, max_sweeps=30)
+    heu = DMRG3S(MPO.heisenberg_mpo(l), synth.random_mps(l, 2, 16), mmax=16, alpha0=1e-3)
+    E_heu, _ = heu.run(tol=1e-12, max_sweeps=30)
+    assert E_res >= heis12_ed - 1e-12 and E_res - heis12_ed < 1e-5
+    assert abs(E_res - E_heu) < 1e-6
+
+
+def test_dmrg3s_residual_expansion_hubbard():
+    """Hubbard l = 6, U = 8, mu = U/2 with the exact-residual expansion: Fock
+    ED of the half-filled sector."""
+    l, U = 6, 8.0
+    mu = [U / 2] * l
+    mpo = MPO.fermion_hopping_mpo(l, {(i, i + 1): 1.0 for i in range(l - 1)}, U=U, mu=mu)
+    run = DMRG3S(mpo, synth.random_mps(l, 4, 64, seed=8), mmax=64, alpha0=1e-3, expansion="residual")
+    E, _ = run.run(tol=1e-12, max_sweeps=12)
+    H = ed.hubbard_hamiltonian(l, {(i, i + 1): 1.0 for i in range(l - 1)}, U=U)
+    N, S = ed.particle_numbers(l)
+    e_ed = ed.ground_energy(H, mask=(N == l) & (S == 0))
+    assert abs(E + U / 2 * l - e_ed) < 1e-9
