@@ -427,6 +427,46 @@ def comparison_bench(ctx, abi, synth, torch, dev, ms_list, steps, warmup=3):
     return out
 
 
+def residual_bench(ctx, abi, synth, torch, dev, l, m, U, max_sweeps, tol):
+    """Convergence per sweep of the two expansion terms, FP64 dense sweeps
+    from the same seeded state: the cheap term of eq. subexp-ourt and the
+    exact residual H Psi - E Psi.  Heisenberg l = 12, m = 16, and the Hubbard
+    chain (mu = U/2, so half filling is the ground-state sector) at bond
+    limit m, where the exact residual is still affordable."""
+    out = {"workload": "expansion_term_comparison"}
+    cases = [("heisenberg_l12_m16", abi.heisenberg_mpo(12), synth.random_mps(12, 2, 16), 16),
+             ("hubbard_l%d_m%d" % (l, m), abi.hubbard_chain_mpo(l, t=1.0, U=U, mu=[U / 2] * l),
+              synth.random_mps(l, 4, m, seed=synth.SEED_MPS), m)]
+    for name, mpo, tensors, mm in cases:
+        entry = {}
+        for kind in ("heuristic", "residual"):
+            st = abi.State(mpo, tensors, mm, device=dev)
+            e0 = ctx.prepare(st)
+            params = abi.sweep_params(alpha=1e-3, e_before=e0, tol=1e-10, expansion=kind)
+            energies, secs, t_exp = [], [], 0.0
+            prev = None
+            for _ in range(max_sweeps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, stats, recs = ctx.sweep(st, params)
+                torch.cuda.synchronize()
+                secs.append(round(time.perf_counter() - t0, 3))
+                t_exp += sum(r.t_expand + r.t_trunc for r in recs)
+                energies.append(stats.energy)
+                if prev is not None and abs(stats.energy - prev) / abs(stats.energy) < tol:
+                    break
+                prev = stats.energy
+            entry[kind] = {"energies": energies, "sweep_seconds": secs,
+                           "expand_plus_truncate_seconds": round(t_exp, 3), "max_bond": max(st.m)}
+            print("bench: expansion %s %s: %d sweeps, E=%.12f, %.2f s (expansion+truncation %.2f s)"
+                  % (name, kind, len(energies), energies[-1], sum(secs), t_exp), file=sys.stderr, flush=True)
+            del st
+            torch.cuda.empty_cache()
+        entry["final_energy_diff"] = entry["residual"]["energies"][-1] - entry["heuristic"]["energies"][-1]
+        out[name] = entry
+    return out
+
+
 def cpu_baseline(L, W, R, psi, budget_s):
     """The oracle's H_eff (NumPy FP64, tensordot in the paper's order) on the
     same arrays, repeated until `budget_s` seconds are used (at least once)."""
@@ -478,6 +518,8 @@ def main():
     ap.add_argument("--gradient", type=str, default="",
                     help="bond limits of the J1-J2 dE/dJ2 run (l=48, J2=0.24; e.g. 64,128,256,512; '' = skip)")
 
+    ap.add_argument("--residual-m", type=int, default=128,
+                    help="bond limit of the Hubbard chain in the expansion-term comparison (0 = skip)")
     ap.add_argument("--compare", type=str, default="1024,2048",
                     help="bond dimensions of the single-site / CWF / two-site H application comparison ('' = skip)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -589,6 +631,9 @@ def main():
     if args.gradient:
         line["gradient"] = gradient_bench(ctx, abi, synth, torch, dev, 48, [int(x) for x in args.gradient.split(",")],
                                           0.24, 1e-4, 1e-11)
+    if args.residual_m > 0:
+        line["expansion_terms"] = residual_bench(ctx, abi, synth, torch, dev, args.sweep_l, args.residual_m, 8.0,
+                                                 10, 1e-10)
     if args.compare:
         line["local_problems"] = comparison_bench(ctx, abi, synth, torch, dev,
                                                   [int(x) for x in args.compare.split(",")], 20)

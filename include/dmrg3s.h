@@ -220,6 +220,42 @@ d3s_status d3s_apply_cwf(d3s_ctx ctx, d3s_prec prec, int mlp, int mr, int wr, co
                          const void* C, void* out);
 
 /*
+ * Exact-residual expansion (the residual Z = H Psi - E Psi of the Sec. 4
+ * opening, used in place of the term of eq. subexp-ourt).  At a site of a
+ * left-to-right sweep the residual is taken with its left part projected
+ * onto the state's left basis and its right part exact; its coefficients
+ * then sit on the right-side vectors |B_y> (from -E Psi) and H_v|B_y> (the
+ * right-part MPO operator of channel v applied to them, from H Psi), which
+ * are not orthonormal.  Their metric needs the ordinary right environment
+ * and the H^2 environment <H_v B_y | H_z B_x>.  Right-to-left mirrors this.
+ *
+ * d3s_update_env_h2: the H^2 environment update, FP64.  Layouts: L2R env_in
+ *   (ml, wl*wl, ml) [a, (w,w'), x], env_out (mr, wr*wr, mr); R2L env_in
+ *   (mr, wr*wr, mr), env_out (ml, wl*wl, ml); the channel pair (w,w') at
+ *   w*wl + w' (bra channel first).  Boundary environments are 1x1x1 ones.
+ *   It is d3s_update_env with the channel-pair MPO
+ *   W2[(w,w'),(v,v'),p,q] = sum_r W[w,v,r,p] W[w',v',r,q].  Asynchronous.
+ * d3s_residual_gram: the Gram matrix of the expanded tensor on the site
+ *   side, gram (n x n): L2R n = ml*d, gram = M M^T + alpha^2 <z|z> with
+ *   h2 = the right H^2 environment of the site (mr, wr*wr, mr); R2L
+ *   n = d*mr, gram = M^T M + alpha^2 <z|z> with h2 = the left one
+ *   (ml, wl*wl, ml).  L, R: the site's ordinary environments; energy: E
+ *   (the eigenvalue of the site's local problem).  Costs O((w m)^2 d m) and
+ *   a metric of (1+w) m squared: meant for m of a few hundred.  Asynchronous.
+ * d3s_truncate_gram: steps 4-5 of the site update from such a Gram matrix
+ *   (overwritten): as d3s_truncate, with the same outputs, cutoff rule and
+ *   neighbour handling (nbr_in may be NULL).  Synchronises.
+ */
+d3s_status d3s_update_env_h2(d3s_ctx ctx, d3s_dir dir, int ml, int d, int mr, int wl, int wr,
+                             const double* env_in, const double* W, const double* site, double* env_out);
+d3s_status d3s_residual_gram(d3s_ctx ctx, d3s_dir dir, int ml, int d, int mr, int wl, int wr, const double* L,
+                             const double* R, const double* h2, const double* W, const double* psi, double energy,
+                             double alpha, double* gram);
+d3s_status d3s_truncate_gram(d3s_ctx ctx, d3s_dir dir, int ml, int d, int mr, double* gram, const double* psi,
+                             int kmax, double rel_cutoff, const double* nbr_in, long nbr_other, double* site_out,
+                             double* nbr_out, int renormalize, double* s_host, int* k_out, double* discarded);
+
+/*
  * Environment update (Sec. 2: L_i = L_{i-1} A_i^+ W_i A_i, R_i = R_{i+1} B_i^+ W_i B_i;
  * step 6 of Sec. 5), FP64.
  *   L2R: env_in = L (m_l, w_l, m_l), site = A (m_l, d, m_r)
@@ -393,6 +429,11 @@ typedef struct {
                              fewer GFLOP (allowed blocks only for block sweeps) use FP64
                              products, since there the products are launch-bound and low
                              precision saves nothing; 0 = every site mixed */
+  int expansion;         /* 0: the expansion term P of eq. subexp-ourt (Sec. 4.2);
+                            1: the exact residual H Psi - E Psi (Sec. 4 opening), see
+                            d3s_residual_gram; dense sweeps only.  The library then keeps
+                            the H^2 environments of every bond in its own workspace,
+                            sum over bonds of m_b^2 w_b^2 doubles per side */
 } d3s_sweep_params;
 
 /* One record per site update (steps 1-8 of Sec. 5). */

@@ -42,7 +42,8 @@ class d3s_state(ctypes.Structure):
 class d3s_sweep_params(ctypes.Structure):
     _fields_ = [("alpha", c_double), ("adaptive_alpha", c_int), ("eps", c_double),
                 ("lanczos_tol", c_double), ("lanczos_kmax", c_int), ("lanczos_max_matvecs", c_int),
-                ("prec", c_int), ("e_before", c_double), ("m_limit", c_int), ("mixed_min_gflop", c_double)]
+                ("prec", c_int), ("e_before", c_double), ("m_limit", c_int), ("mixed_min_gflop", c_double),
+                ("expansion", c_int)]
 
 
 class d3s_site_record(ctypes.Structure):
@@ -90,6 +91,12 @@ _truncate = _sig("d3s_truncate", c_int, [c_void_p, c_int, c_int, c_int, c_int, c
                                          c_int, c_double, c_void_p, c_long, c_void_p, c_void_p, c_int,
                                          c_double_p, c_int_p, c_double_p])
 _update_env = _sig("d3s_update_env", c_int, [c_void_p, c_int] + [c_int] * 5 + [c_void_p] * 4)
+_update_env_h2 = _sig("d3s_update_env_h2", c_int, [c_void_p, c_int] + [c_int] * 5 + [c_void_p] * 4)
+_residual_gram = _sig("d3s_residual_gram", c_int, [c_void_p, c_int] + [c_int] * 5 + [c_void_p] * 5 +
+                      [c_double, c_double, c_void_p])
+_truncate_gram = _sig("d3s_truncate_gram", c_int, [c_void_p, c_int, c_int, c_int, c_int, c_void_p, c_void_p,
+                                                   c_int, c_double, c_void_p, c_long, c_void_p, c_void_p, c_int,
+                                                   c_double_p, c_int_p, c_double_p])
 _lanczos = _sig("d3s_lanczos", c_int, [c_void_p, c_int] + [c_int] * 5 + [c_void_p] * 4 +
                 [c_double, c_int, c_int, c_double_p, c_int_p])
 _energy = _sig("d3s_energy", c_int, [c_void_p] + [c_int] * 5 + [c_void_p] * 4 + [c_double_p])
@@ -378,6 +385,68 @@ class Context:
                               1 if renormalize else 0, s, ctypes.byref(k), ctypes.byref(disc)))
         return k.value, disc.value, list(s)
 
+    def update_env_h2(self, direction, env_in, W, site, env_out):
+        """Environment of the channel pairs of H^2: L2R env_in (ml, wl^2, ml) ->
+        env_out (mr, wr^2, mr); R2L env_in (mr, wr^2, mr) -> env_out (ml, wl^2, ml)."""
+        self._sync_stream()
+        ml, d, mr = site.shape
+        wl, wr = W.shape[0], W.shape[1]
+        f = torch.float64
+        _need(W, wl * wr * d * d, f, "W")
+        _need(site, ml * d * mr, f, "site")
+        if direction == L2R:
+            _need(env_in, ml * wl * wl * ml, f, "env_in")
+            _need(env_out, mr * wr * wr * mr, f, "env_out")
+        else:
+            _need(env_in, mr * wr * wr * mr, f, "env_in")
+            _need(env_out, ml * wl * wl * ml, f, "env_out")
+        return self._check(_update_env_h2(self.h, direction, ml, d, mr, wl, wr, _ptr(env_in), _ptr(W),
+                                          _ptr(site), _ptr(env_out)))
+
+    def residual_gram(self, direction, L, R, h2, W, psi, energy, alpha, gram):
+        """Gram matrix of the expanded tensor with the exact residual as its
+        expansion part: (ml d)^2 for L2R (h2 = right H^2 environment), (d mr)^2
+        for R2L (h2 = left one)."""
+        self._sync_stream()
+        ml, d, mr = psi.shape
+        wl, wr = W.shape[0], W.shape[1]
+        f = torch.float64
+        _need(L, ml * wl * ml, f, "L")
+        _need(R, mr * wr * mr, f, "R")
+        _need(W, wl * wr * d * d, f, "W")
+        _need(psi, ml * d * mr, f, "psi")
+        if direction == L2R:
+            _need(h2, mr * wr * wr * mr, f, "h2")
+            _need(gram, (ml * d) ** 2, f, "gram")
+        else:
+            _need(h2, ml * wl * wl * ml, f, "h2")
+            _need(gram, (d * mr) ** 2, f, "gram")
+        return self._check(_residual_gram(self.h, direction, ml, d, mr, wl, wr, _ptr(L), _ptr(R), _ptr(h2),
+                                          _ptr(W), _ptr(psi), float(energy), float(alpha), _ptr(gram)))
+
+    def truncate_gram(self, direction, gram, psi, kmax, rel_cutoff, nbr, site_out, nbr_out, renormalize=True):
+        """Truncation from the Gram matrix (overwritten) of the expanded tensor;
+        returns (k, discarded, singular values) like truncate."""
+        self._sync_stream()
+        ml, d, mr = psi.shape
+        f = torch.float64
+        n = ml * d if direction == L2R else d * mr
+        side = mr if direction == L2R else ml
+        other = nbr.numel() // side if nbr is not None else side
+        if nbr is not None:
+            _need(nbr, side * other, f, "nbr")
+        _need(gram, n * n, f, "gram")
+        _need(psi, ml * d * mr, f, "psi")
+        _need(site_out, n * min(kmax, n), f, "site_out")
+        _need(nbr_out, min(kmax, n) * other, f, "nbr_out")
+        s = (ctypes.c_double * n)()
+        k = c_int()
+        disc = c_double()
+        self._check(_truncate_gram(self.h, direction, ml, d, mr, _ptr(gram), _ptr(psi), kmax, float(rel_cutoff),
+                                   _ptr(nbr) if nbr is not None else None, other, _ptr(site_out), _ptr(nbr_out),
+                                   1 if renormalize else 0, s, ctypes.byref(k), ctypes.byref(disc)))
+        return k.value, disc.value, list(s)
+
     def update_env(self, direction, env_in, W, site, env_out):
         self._sync_stream()
         ml, d, mr = site.shape
@@ -587,9 +656,13 @@ def mpo_bond_charges(mpo_blocks, channel_q):
 
 
 def sweep_params(alpha=1e-3, adaptive=True, eps=1e-14, tol=1e-12, kmax=40, max_matvecs=2000, prec=F64,
-                 e_before=0.0, m_limit=0, mixed_min_gflop=2.0):
+                 e_before=0.0, m_limit=0, mixed_min_gflop=2.0, expansion="heuristic"):
+    """expansion: "heuristic" (the term P of eq. subexp-ourt) or "residual"
+    (the exact residual H Psi - E Psi; dense sweeps only)."""
+    if expansion not in ("heuristic", "residual"):
+        raise ValueError("expansion must be 'heuristic' or 'residual'")
     return d3s_sweep_params(alpha, 1 if adaptive else 0, eps, tol, kmax, max_matvecs, prec, e_before, m_limit,
-                            mixed_min_gflop)
+                            mixed_min_gflop, 1 if expansion == "residual" else 0)
 
 
 # --- symmetry blocks -------------------------------------------------------

@@ -273,6 +273,59 @@ d3s_status d3s_truncate(d3s_ctx ctx, d3s_dir dir, int ml, int d, int mr, long wi
   });
 }
 
+d3s_status d3s_update_env_h2(d3s_ctx ctx, d3s_dir dir, int ml, int d, int mr, int wl, int wr,
+                             const double* env_in, const double* W, const double* site, double* env_out) {
+  return guarded(ctx, [&] {
+    check_dir(dir);
+    D3S_REQUIRE(ml >= 1 && d >= 1 && mr >= 1 && wl >= 1 && wr >= 1, "dimensions must be >= 1");
+    D3S_REQUIRE(wl <= 64 && wr <= 64 && d <= 64, "H^2 environment: w and d must be <= 64");
+    D3S_REQUIRE((long)ml * wl * wl * d * mr < (1L << 36) && (long)ml * wr * wr * d * mr < (1L << 36),
+                "H^2 environment: tensors too large");
+    D3S_REQUIRE(env_in && W && site && env_out, "null tensor pointer");
+    d3s::op_update_env_h2(&ctx->c, dir, ml, d, mr, wl, wr, env_in, W, site, env_out);
+    return D3S_OK;
+  });
+}
+
+d3s_status d3s_residual_gram(d3s_ctx ctx, d3s_dir dir, int ml, int d, int mr, int wl, int wr, const double* L,
+                             const double* R, const double* h2, const double* W, const double* psi, double energy,
+                             double alpha, double* gram) {
+  return guarded(ctx, [&] {
+    check_dir(dir);
+    check_dims(ml, d, mr, wl, wr);
+    D3S_REQUIRE(wl <= 64 && wr <= 64, "residual: w must be <= 64");
+    D3S_REQUIRE(std::isfinite(energy) && std::isfinite(alpha), "energy and alpha must be finite");
+    const long n = (dir == D3S_L2R) ? (long)ml * d : (long)d * mr;
+    const long ng = (dir == D3S_L2R) ? (long)(1 + wr) * mr : (long)(1 + wl) * ml;
+    D3S_REQUIRE(n <= 46340 && ng <= 46340, "residual: Gram or metric dimension too large");
+    D3S_REQUIRE(L && R && h2 && W && psi && gram, "null tensor pointer");
+    d3s::op_residual_gram(&ctx->c, dir, ml, d, mr, wl, wr, L, R, h2, W, psi, energy, alpha, gram);
+    return D3S_OK;
+  });
+}
+
+d3s_status d3s_truncate_gram(d3s_ctx ctx, d3s_dir dir, int ml, int d, int mr, double* gram, const double* psi,
+                             int kmax, double rel_cutoff, const double* nbr_in, long nbr_other, double* site_out,
+                             double* nbr_out, int renormalize, double* s_host, int* k_out, double* discarded) {
+  return guarded(ctx, [&] {
+    check_dir(dir);
+    D3S_REQUIRE(ml >= 1 && d >= 1 && mr >= 1 && nbr_other >= 1 && kmax >= 1, "dimensions must be >= 1");
+    D3S_REQUIRE(gram && psi && site_out && nbr_out && k_out && discarded, "null pointer");
+    D3S_REQUIRE(rel_cutoff >= 0.0, "rel_cutoff must be >= 0");
+    const long n = (dir == D3S_L2R) ? (long)ml * d : (long)d * mr;
+    D3S_REQUIRE(n <= 46340, "Gram dimension too large (n^2 must fit in int)");
+    if (!nbr_in)
+      D3S_REQUIRE(nbr_other == (dir == D3S_L2R ? mr : ml),
+                  "without a neighbour, nbr_other must be m_r (L2R) or m_l (R2L)");
+    d3s::TruncResult t = d3s::truncate_from_gram(&ctx->c, dir, ml, d, mr, gram, psi, kmax, rel_cutoff, nbr_in,
+                                                 nbr_other, site_out, nbr_out, s_host, renormalize != 0);
+    D3S_HIP(hipStreamSynchronize(ctx->c.stream));
+    *k_out = t.k;
+    *discarded = t.discarded;
+    return D3S_OK;
+  });
+}
+
 d3s_status d3s_update_env(d3s_ctx ctx, d3s_dir dir, int ml, int d, int mr, int wl, int wr, const double* env_in,
                           const double* W, const double* site, double* env_out) {
   return guarded(ctx, [&] {
@@ -355,6 +408,7 @@ d3s_status d3s_sweep(d3s_ctx ctx, d3s_state* state, d3s_sweep_params* params, d3
     D3S_REQUIRE(params->lanczos_tol > 0.0 && params->lanczos_max_matvecs >= 1, "bad eigensolver limits");
     D3S_REQUIRE(params->alpha >= 0.0 && std::isfinite(params->alpha), "alpha must be finite and >= 0");
     D3S_REQUIRE(params->mixed_min_gflop >= 0.0, "mixed_min_gflop must be >= 0");
+    D3S_REQUIRE(params->expansion == 0 || params->expansion == 1, "expansion must be 0 or 1");
     D3S_REQUIRE((long)state->d * state->mmax <= 46340, "d * mmax too large for the Gram route");
     d3s::op_sweep(&ctx->c, state, params, stats);
     if (!std::isfinite(stats->energy)) throw Error{D3S_ENUMERIC, "sweep: non-finite energy"};
@@ -565,6 +619,7 @@ d3s_status d3s_sweep_blocks(d3s_ctx ctx, d3s_state* state, d3s_symmetry* sym, d3
     D3S_REQUIRE(params->lanczos_tol > 0.0 && params->lanczos_max_matvecs >= 1, "bad eigensolver limits");
     D3S_REQUIRE(params->alpha >= 0.0 && std::isfinite(params->alpha), "alpha must be finite and >= 0");
     D3S_REQUIRE(params->mixed_min_gflop >= 0.0, "mixed_min_gflop must be >= 0");
+    D3S_REQUIRE(params->expansion == 0, "block sweeps: only the expansion term of eq. subexp-ourt (expansion = 0)");
     d3s::SymChain c = read_sym(state, sym);
     try {
       d3s::op_sweep_blocks(&ctx->c, state, c, params, stats, use_graph != 0);

@@ -37,7 +37,7 @@ struct Error {
 enum WsSlot {
   WS_T1 = 0, WS_T2, WS_LZ_V, WS_LZ_W, WS_LZ_COEF, WS_RED, WS_GRAM, WS_EIGVAL,
   WS_EIGTMP, WS_UKT, WS_X, WS_MT, WS_CAST_L, WS_CAST_R, WS_CAST_X, WS_CAST_Y,
-  WS_CAST_W, WS_REF, WS_PSI, WS_INFO, WS_NBR, WS_MISC, WS_SPLITK, WS_DESC, WS_BLK_X, WS_XPACK, WS_GPACK, WS_GVAL, WS_TUNE, WS_PK, WS_LZ_K, WS_GS_NORM, WS_JD_V, WS_JD_W, WS_JD_Z, WS_JD_COEF, WS_G2_PART, WS_NSLOTS
+  WS_CAST_W, WS_REF, WS_PSI, WS_INFO, WS_NBR, WS_MISC, WS_SPLITK, WS_DESC, WS_BLK_X, WS_XPACK, WS_GPACK, WS_GVAL, WS_TUNE, WS_PK, WS_LZ_K, WS_GS_NORM, WS_JD_V, WS_JD_W, WS_JD_Z, WS_JD_COEF, WS_G2_PART, WS_W2, WS_RMET, WS_RZ, WS_RT, WS_RGRAM, WS_H2, WS_NSLOTS
 };
 
 struct Ctx {
@@ -205,6 +205,14 @@ void op_apply_heff_two_site(Ctx* c, d3s_prec p, int ml, int d, int mr, int wl, i
 void op_apply_cwf(Ctx* c, d3s_prec p, int mlp, int mr, int wr, const void* Lt, const void* R, const void* C,
                   void* out);
 void cwf_environment(Ctx* c, int ml, int d, int wl, int wr, const double* L, const double* W, double* Lt);
+void mpo_square(Ctx* c, const double* W, double* W2, int wl, int wr, int d);
+void residual_metric(Ctx* c, const double* env, const double* h2, int m, int w, double* G);
+void scale2d_f64(Ctx* c, double* x, long ld, long rows, long cols, double f);
+void op_update_env_h2(Ctx* c, d3s_dir dir, int ml, int d, int mr, int wl, int wr, const double* env_in,
+                      const double* W, const double* site, double* env_out);
+void op_residual_gram(Ctx* c, d3s_dir dir, int ml, int d, int mr, int wl, int wr, const double* L,
+                      const double* R, const double* h2, const double* W, const double* psi, double energy,
+                      double alpha, double* gram);
 void op_expand(Ctx* c, d3s_dir dir, int ml, int d, int mr, int wl, int wr,
                const double* env, const double* W, const double* psi, double alpha, double* Mt);
 void op_update_env(Ctx* c, d3s_dir dir, int ml, int d, int mr, int wl, int wr,
@@ -214,6 +222,9 @@ TruncResult op_truncate(Ctx* c, d3s_dir dir, int ml, int d, int mr, long width,
                         const double* Mt, const double* psi, int kmax, double eps,
                         const double* nbr, long nbr_other, double* site_out, double* nbr_out,
                         double* s_host, bool renormalize);
+TruncResult truncate_from_gram(Ctx* c, d3s_dir dir, int ml, int d, int mr, double* G, const double* psi, int kmax,
+                               double eps, const double* nbr, long nbr_other, double* site_out, double* nbr_out,
+                               double* s_host, bool renormalize);
 struct LanczosResult { double theta; int matvecs; bool converged; int restarts; int f64_matvecs = 0; };
 LanczosResult op_lanczos(Ctx* c, d3s_prec p, int ml, int d, int mr, int wl, int wr,
                          const double* L, const double* W, const double* R, double* psi,

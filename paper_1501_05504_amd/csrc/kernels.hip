@@ -114,6 +114,47 @@ void wmap_r2l_kernel(const Tin* __restrict__ Y, const Tc* __restrict__ Wg, Tout*
   }
 }
 
+// W-maps for MPO bonds too wide for the register/LDS kernels above (the
+// channel-pair MPO of H^2): one thread per output element, W read from
+// global memory (every lane of a wave reads the same W entry, a broadcast).
+template <typename Tin, typename Tout, typename Tc>
+__global__ __launch_bounds__(kThreads)
+void wmap_l2r_wide_kernel(const Tin* __restrict__ T1, const Tc* __restrict__ Wg, Tout* __restrict__ out,
+                          long ld_out, int ml, int d, int mr, int wl, int wr, Tc alpha) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)ml * d * wr * mr) return;
+  const int y = (int)(e % mr);
+  long r = e / mr;
+  const int v = (int)(r % wr);
+  r /= wr;
+  const int s = (int)(r % d);
+  const int a = (int)(r / d);
+  Tc acc = 0;
+  for (int w = 0; w < wl; ++w)
+    for (int t = 0; t < d; ++t)
+      acc += Wg[((w * wr + v) * d + s) * d + t] * (Tc)Cvt<Tin>::ld(T1[(((long)a * wl + w) * d + t) * mr + y]);
+  out[((long)a * d + s) * ld_out + (long)v * mr + y] = Cvt<Tout>::st(alpha * acc);
+}
+
+template <typename Tin, typename Tout, typename Tc>
+__global__ __launch_bounds__(kThreads)
+void wmap_r2l_wide_kernel(const Tin* __restrict__ Y, const Tc* __restrict__ Wg, Tout* __restrict__ Z, int ml,
+                          int d, int mr, int wl, int wr, Tc alpha) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)wl * ml * d * mr) return;
+  const int b = (int)(e % mr);
+  long r = e / mr;
+  const int s = (int)(r % d);
+  r /= d;
+  const int x = (int)(r % ml);
+  const int w = (int)(r / ml);
+  Tc acc = 0;
+  for (int t = 0; t < d; ++t)
+    for (int v = 0; v < wr; ++v)
+      acc += Wg[((w * wr + v) * d + s) * d + t] * (Tc)Cvt<Tin>::ld(Y[(((long)x * d + t) * mr + b) * wr + v]);
+  Z[e] = Cvt<Tout>::st(alpha * acc);
+}
+
 template <typename Tin, typename Tout, typename Tc>
 void wmap_l2r_t(Ctx* c, const void* T1, const void* W, void* out, long ld_out, int ml, int d,
                 int mr, int wl, int wr, double alpha) {
@@ -124,11 +165,16 @@ void wmap_l2r_t(Ctx* c, const void* T1, const void* W, void* out, long ld_out, i
     hipLaunchKernelGGL(kern, grid, dim3(kThreads), sh, c->stream, (const Tin*)T1, (const Tc*)W,
                        (Tout*)out, ld_out, ml, d, mr, wl, wr, (Tc)alpha);
   };
-  if (K <= 8) args(wmap_l2r_kernel<Tin, Tout, Tc, 8>);
-  else if (K <= 16) args(wmap_l2r_kernel<Tin, Tout, Tc, 16>);
-  else if (K <= 32) args(wmap_l2r_kernel<Tin, Tout, Tc, 32>);
-  else if (K <= 80) args(wmap_l2r_kernel<Tin, Tout, Tc, 80>);
-  else throw Error{D3S_EINVAL, "W-map: w_l * d > 80 is not supported"};
+  if (K <= 8 && d * wr <= 80) args(wmap_l2r_kernel<Tin, Tout, Tc, 8>);
+  else if (K <= 16 && d * wr <= 80) args(wmap_l2r_kernel<Tin, Tout, Tc, 16>);
+  else if (K <= 32 && d * wr <= 80) args(wmap_l2r_kernel<Tin, Tout, Tc, 32>);
+  else if (K <= 80 && d * wr <= 80) args(wmap_l2r_kernel<Tin, Tout, Tc, 80>);
+  else {
+    const long n = (long)ml * d * wr * mr;
+    hipLaunchKernelGGL((wmap_l2r_wide_kernel<Tin, Tout, Tc>), dim3((unsigned)((n + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, c->stream, (const Tin*)T1, (const Tc*)W, (Tout*)out, ld_out, ml, d, mr,
+                       wl, wr, (Tc)alpha);
+  }
   D3S_HIP(hipGetLastError());
 }
 
@@ -142,11 +188,16 @@ void wmap_r2l_t(Ctx* c, const void* Y, const void* W, void* Z, int ml, int d, in
     hipLaunchKernelGGL(kern, grid, dim3(kThreads), sh, c->stream, (const Tin*)Y, (const Tc*)W,
                        (Tout*)Z, ml, d, mr, wl, wr, (Tc)alpha);
   };
-  if (K <= 8) args(wmap_r2l_kernel<Tin, Tout, Tc, 8>);
-  else if (K <= 16) args(wmap_r2l_kernel<Tin, Tout, Tc, 16>);
-  else if (K <= 32) args(wmap_r2l_kernel<Tin, Tout, Tc, 32>);
-  else if (K <= 80) args(wmap_r2l_kernel<Tin, Tout, Tc, 80>);
-  else throw Error{D3S_EINVAL, "W-map: w_r * d > 80 is not supported"};
+  if (K <= 8 && d * wl <= 80) args(wmap_r2l_kernel<Tin, Tout, Tc, 8>);
+  else if (K <= 16 && d * wl <= 80) args(wmap_r2l_kernel<Tin, Tout, Tc, 16>);
+  else if (K <= 32 && d * wl <= 80) args(wmap_r2l_kernel<Tin, Tout, Tc, 32>);
+  else if (K <= 80 && d * wl <= 80) args(wmap_r2l_kernel<Tin, Tout, Tc, 80>);
+  else {
+    const long n = (long)wl * ml * d * mr;
+    hipLaunchKernelGGL((wmap_r2l_wide_kernel<Tin, Tout, Tc>), dim3((unsigned)((n + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, c->stream, (const Tin*)Y, (const Tc*)W, (Tout*)Z, ml, d, mr, wl, wr,
+                       (Tc)alpha);
+  }
   D3S_HIP(hipGetLastError());
 }
 
@@ -665,6 +716,80 @@ void copy_f64(Ctx* c, const double* x, double* y, long n) {
 
 void fill_f64(Ctx* c, double* x, long n, double v) {
   hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n)), dim3(kThreads), 0, c->stream, x, n, v);
+  D3S_HIP(hipGetLastError());
+}
+
+// Channel-pair MPO of H^2 between bra and ket copies of the state:
+// W2[(w,c), (v,u), p, q] = sum_r W[w,v,r,p] W[c,u,r,q].
+__global__ __launch_bounds__(kThreads)
+void mpo_square_kernel(const double* __restrict__ W, double* __restrict__ W2, int wl, int wr, int d) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long n = (long)wl * wl * wr * wr * d * d;
+  if (e >= n) return;
+  const int q = (int)(e % d);
+  long r = e / d;
+  const int p = (int)(r % d);
+  r /= d;
+  const int vu = (int)(r % ((long)wr * wr));
+  const int wc = (int)(r / ((long)wr * wr));
+  const int v = vu / wr, u = vu % wr, w = wc / wl, cc = wc % wl;
+  double acc = 0.0;
+  for (int k = 0; k < d; ++k) acc += W[((w * wr + v) * d + k) * d + p] * W[((cc * wr + u) * d + k) * d + q];
+  W2[e] = acc;
+}
+
+void mpo_square(Ctx* c, const double* W, double* W2, int wl, int wr, int d) {
+  const long n = (long)wl * wl * wr * wr * d * d;
+  hipLaunchKernelGGL(mpo_square_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0,
+                     c->stream, W, W2, wl, wr, d);
+  D3S_HIP(hipGetLastError());
+}
+
+// Metric of the residual's near-side vectors, ordered |S_y> (y < m), then
+// H_v|S_y> at m + v*m + y:  G = [[1, E], [E^T, H2]] with E[y', (v,y)] =
+// env[y', v, y] and H2[(v,y), (z,x)] = h2[y, v, z, x].
+__global__ __launch_bounds__(kThreads)
+void residual_metric_kernel(const double* __restrict__ env, const double* __restrict__ h2, int m, int w,
+                            double* __restrict__ G) {
+  const long n = (long)(1 + w) * m;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * n) return;
+  const long r = e / n, col = e % n;
+  double val;
+  if (r < m && col < m) {
+    val = (r == col) ? 1.0 : 0.0;
+  } else if (r < m) {
+    val = env[r * w * m + (col - m)];
+  } else if (col < m) {
+    val = env[col * w * m + (r - m)];
+  } else {
+    const long rv = r - m, cz = col - m;
+    const long v = rv / m, y = rv % m, z = cz / m, x = cz % m;
+    val = h2[((y * w + v) * w + z) * m + x];
+  }
+  G[e] = val;
+}
+
+void residual_metric(Ctx* c, const double* env, const double* h2, int m, int w, double* G) {
+  const long n = (long)(1 + w) * m;
+  hipLaunchKernelGGL(residual_metric_kernel, dim3((unsigned)((n * n + kThreads - 1) / kThreads)), dim3(kThreads),
+                     0, c->stream, env, h2, m, w, G);
+  D3S_HIP(hipGetLastError());
+}
+
+__global__ __launch_bounds__(kThreads)
+void scale2d_kernel(double* __restrict__ x, long ld, long rows, long cols, double f) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * cols) return;
+  const long r = e / cols, col = e % cols;
+  x[r * ld + col] *= f;
+}
+
+void scale2d_f64(Ctx* c, double* x, long ld, long rows, long cols, double f) {
+  const long n = rows * cols;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(scale2d_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0,
+                     c->stream, x, ld, rows, cols, f);
   D3S_HIP(hipGetLastError());
 }
 

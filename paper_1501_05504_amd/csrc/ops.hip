@@ -176,6 +176,59 @@ void op_update_env(Ctx* c, d3s_dir dir, int ml, int d, int mr, int wl, int wr, c
   }
 }
 
+// ---------------------------------------------------------------- exact residual
+// Environment of the channel pairs of H^2 (the metric of the residual's
+// near-side vectors): the ordinary environment update with the channel-pair
+// MPO W2 of bond w^2.
+void op_update_env_h2(Ctx* c, d3s_dir dir, int ml, int d, int mr, int wl, int wr, const double* env_in,
+                      const double* W, const double* site, double* env_out) {
+  double* W2 = (double*)ws_get(c, WS_W2, sizeof(double) * (size_t)wl * wl * wr * wr * d * d);
+  mpo_square(c, W, W2, wl, wr, d);
+  op_update_env(c, dir, ml, d, mr, wl * wl, wr * wr, env_in, W2, site, env_out);
+}
+
+// Gram matrix of the expanded tensor with the exact residual
+// Z = H Psi - E Psi as its expansion part (far side projected onto the
+// state's basis, near side exact):
+//   L2R: G = M M^T + alpha^2 Zc Q Zc^T,  Zc = [-E M | L M W]   ((ml d) x (1+wr) mr)
+//   R2L: G = M^T M + alpha^2 Zc^T Q Zc,  Zc = [-E M ; W M R]   ((1+wl) ml x (d mr))
+// with Q the metric of the near-side vectors (residual_metric) built from
+// the ordinary and the H^2 environment of that side.
+void op_residual_gram(Ctx* c, d3s_dir dir, int ml, int d, int mr, int wl, int wr, const double* L,
+                      const double* R, const double* h2, const double* W, const double* psi, double energy,
+                      double alpha, double* gram) {
+  const double a2 = alpha * alpha;
+  if (dir == D3S_L2R) {
+    const int n = ml * d, ng = (1 + wr) * mr;
+    double* Zc = (double*)ws_get(c, WS_RZ, sizeof(double) * (size_t)n * ng);
+    op_expand(c, D3S_L2R, ml, d, mr, wl, wr, L, W, psi, 1.0, Zc);
+    scale2d_f64(c, Zc, ng, n, mr, -energy);
+    double* Q = (double*)ws_get(c, WS_RMET, sizeof(double) * (size_t)ng * ng);
+    residual_metric(c, R, h2, mr, wr, Q);
+    double* T = (double*)ws_get(c, WS_RT, sizeof(double) * (size_t)n * ng);
+    GemmArgs g1{n, ng, ng, Zc, ng, true, 0, Q, ng, false, 0, T, ng, 0, 1.0, 0.0, 1};
+    gemm_f64(c, g1);
+    GemmArgs g2{n, n, ng, T, ng, true, 0, Zc, ng, true, 0, gram, n, 0, a2, 0.0, 1};
+    gemm_f64(c, g2);
+    GemmArgs g3{n, n, mr, psi, mr, true, 0, psi, mr, true, 0, gram, n, 0, 1.0, 1.0, 1};
+    gemm_f64(c, g3);
+  } else {
+    const int n = d * mr, ng = (1 + wl) * ml;
+    double* Zc = (double*)ws_get(c, WS_RZ, sizeof(double) * (size_t)ng * n);
+    op_expand(c, D3S_R2L, ml, d, mr, wl, wr, R, W, psi, 1.0, Zc);
+    scale_f64(c, Zc, (long)ml * n, -energy);
+    double* Q = (double*)ws_get(c, WS_RMET, sizeof(double) * (size_t)ng * ng);
+    residual_metric(c, L, h2, ml, wl, Q);
+    double* T = (double*)ws_get(c, WS_RT, sizeof(double) * (size_t)ng * n);
+    GemmArgs g1{ng, n, ng, Q, ng, true, 0, Zc, n, false, 0, T, n, 0, 1.0, 0.0, 1};
+    gemm_f64(c, g1);
+    GemmArgs g2{n, n, ng, Zc, n, false, 0, T, n, false, 0, gram, n, 0, a2, 0.0, 1};
+    gemm_f64(c, g2);
+    GemmArgs g3{n, n, ml, psi, n, false, 0, psi, n, false, 0, gram, n, 0, 1.0, 1.0, 1};
+    gemm_f64(c, g3);
+  }
+}
+
 // ---------------------------------------------------------------- eigensolvers
 void syevd_f64(Ctx* c, int n, double* A, double* evals_dev) {
   if (!c->solver) {
@@ -410,6 +463,17 @@ TruncResult op_truncate(Ctx* c, d3s_dir dir, int ml, int d, int mr, long width, 
     GemmArgs g{n, n, (int)width, Mt, n, false, 0, Mt, n, false, 0, G, n, 0, 1.0, 0.0, 1};
     gemm_f64(c, g);
   }
+  return truncate_from_gram(c, dir, ml, d, mr, G, psi, kmax, eps, nbr, nbr_other, site_out, nbr_out, s_host,
+                            renormalize);
+}
+
+// Steps 4-5 from the Gram matrix G (n x n, overwritten) of the expanded
+// tensor on its site side: its eigenvectors are the singular vectors that
+// are kept, its eigenvalues the squared singular values.
+TruncResult truncate_from_gram(Ctx* c, d3s_dir dir, int ml, int d, int mr, double* G, const double* psi, int kmax,
+                               double eps, const double* nbr, long nbr_other, double* site_out, double* nbr_out,
+                               double* s_host, bool renormalize) {
+  const int n = (dir == D3S_L2R) ? ml * d : d * mr;
   double* ev = (double*)ws_get(c, WS_EIGVAL, sizeof(double) * (size_t)n);
   syevd_f64(c, n, G, ev);
   std::vector<double> lam(n);

@@ -13,9 +13,15 @@
 //    1e-13 |E|, grow by 1.25 when dE_T < 0.3 |dE_O|, else shrink by 0.8;
 //    clamped to [1e-16, 1];
 //  - a sweep is right-to-left over sites l-1..1 followed by left-to-right
-//    over sites 0..l-2.
+//    over sites 0..l-2;
+//  - with the exact-residual expansion E is the eigenvalue of the site's
+//    local problem, and the truncation works from the Gram matrix of the
+//    expanded tensor (singular values resolved down to sqrt(n u) s_0, as
+//    for the explicit expanded tensor).
 #include <chrono>
 #include <cmath>
+#include <string>
+#include <vector>
 
 #include "d3s_internal.h"
 
@@ -75,11 +81,14 @@ double op_prepare(Ctx* c, d3s_state* s, double eps) {
   const size_t cap = (size_t)s->mmax * d * s->mmax;
   double* tmpS = (double*)ws_get(c, WS_PSI, sizeof(double) * cap);
   double* tmpN = (double*)ws_get(c, WS_NBR, sizeof(double) * cap);
+  // the neighbour is renormalised at every step: the state's direction is
+  // unchanged, and the norm of a long random MPS cannot overflow the Gram
+  // matrices on the way
   for (int i = 0; i + 1 < l; ++i) {
     const int ml = s->m[i], mr = s->m[i + 1];
     const long other = (long)d * s->m[i + 2];
     TruncResult t = op_truncate(c, D3S_L2R, ml, d, mr, mr, s->site[i], s->site[i], (int)bond_budget(l, d, s->mmax, i + 1),
-                                eps, s->site[i + 1], other, tmpS, tmpN, nullptr, false);
+                                eps, s->site[i + 1], other, tmpS, tmpN, nullptr, true);
     copy_f64(c, tmpS, s->site[i], (long)ml * d * t.k);
     copy_f64(c, tmpN, s->site[i + 1], (long)t.k * other);
     s->m[i + 1] = t.k;
@@ -109,9 +118,41 @@ void op_sweep(Ctx* c, d3s_state* s, d3s_sweep_params* p, d3s_sweep_stats* st) {
   if (s->center != l - 1) throw Error{D3S_EINVAL, "sweep: the orthogonality centre must be on site l-1"};
   const int wmax = wmax_of(s);
   const size_t cap = (size_t)s->mmax * d * s->mmax;
+  const bool residual = p->expansion == 1;
+  // exact residual: H^2 environments, left ones per bond 0..l-1 (h2l[i] left
+  // of site i) and right ones per site (h2r[i] right of site i), in one
+  // workspace buffer sized for the largest bond each may reach
+  std::vector<double*> h2l, h2r;
+  double* gram = nullptr;
+  if (residual) {
+    std::vector<size_t> off_l(l), off_r(l);
+    size_t total = 0;
+    for (int b = 0; b < l; ++b) {
+      const size_t m = (size_t)bond_budget(l, d, s->mmax, b);
+      off_l[b] = total;
+      total += m * m * s->w[b] * s->w[b];
+    }
+    for (int i = 0; i < l; ++i) {
+      const size_t m = (size_t)bond_budget(l, d, s->mmax, i + 1);
+      off_r[i] = total;
+      total += m * m * s->w[i + 1] * s->w[i + 1];
+    }
+    if (total > ((size_t)1 << 32))
+      throw Error{D3S_EINVAL, "sweep: the exact-residual expansion needs " + std::to_string(total * 8 >> 30) +
+                                  " GiB of H^2 environments; use a smaller mmax"};
+    double* base = (double*)ws_get(c, WS_H2, sizeof(double) * total);
+    for (int b = 0; b < l; ++b) h2l.push_back(base + off_l[b]);
+    for (int i = 0; i < l; ++i) h2r.push_back(base + off_r[i]);
+    gram = (double*)ws_get(c, WS_RGRAM, sizeof(double) * (size_t)d * s->mmax * d * s->mmax);
+    fill_f64(c, h2l[0], 1, 1.0);
+    fill_f64(c, h2r[l - 1], 1, 1.0);
+    for (int i = 0; i + 1 < l; ++i)
+      op_update_env_h2(c, D3S_L2R, s->m[i], d, s->m[i + 1], s->w[i], s->w[i + 1], h2l[i], s->mpo[i], s->site[i],
+                       h2l[i + 1]);
+  }
   double* tmpS = (double*)ws_get(c, WS_PSI, sizeof(double) * cap);
   double* tmpN = (double*)ws_get(c, WS_NBR, sizeof(double) * cap);
-  double* Mt = (double*)ws_get(c, WS_MT, sizeof(double) * (size_t)(1 + wmax) * cap);
+  double* Mt = residual ? nullptr : (double*)ws_get(c, WS_MT, sizeof(double) * (size_t)(1 + wmax) * cap);
   const double t_start = now();
   st->count = 0;
   st->nonconverged = 0;
@@ -135,18 +176,27 @@ void op_sweep(Ctx* c, d3s_state* s, d3s_sweep_params* p, d3s_sweep_stats* st) {
     lam = lz.theta;
     if (!lz.converged) st->nonconverged++;
     double t1 = now();
-    op_expand(c, D3S_R2L, ml, d, mr, wl, wr, s->renv[i], s->mpo[i], s->site[i], p->alpha, Mt);
+    if (residual)
+      op_residual_gram(c, D3S_R2L, ml, d, mr, wl, wr, s->lenv[i], s->renv[i], h2l[i], s->mpo[i], s->site[i], lam,
+                       p->alpha, gram);
+    else
+      op_expand(c, D3S_R2L, ml, d, mr, wl, wr, s->renv[i], s->mpo[i], s->site[i], p->alpha, Mt);
     D3S_HIP(hipStreamSynchronize(c->stream));
     double t2 = now();
     const int mll = s->m[i - 1];
-    TruncResult t = op_truncate(c, D3S_R2L, ml, d, mr, (long)(1 + wl) * ml, Mt, s->site[i],
-                                (int)bond_budget(l, d, mlim, i), p->eps, s->site[i - 1], (long)mll * d,
-                                tmpS, tmpN, nullptr, true);
+    TruncResult t = residual
+        ? truncate_from_gram(c, D3S_R2L, ml, d, mr, gram, s->site[i], (int)bond_budget(l, d, mlim, i), p->eps,
+                             s->site[i - 1], (long)mll * d, tmpS, tmpN, nullptr, true)
+        : op_truncate(c, D3S_R2L, ml, d, mr, (long)(1 + wl) * ml, Mt, s->site[i],
+                      (int)bond_budget(l, d, mlim, i), p->eps, s->site[i - 1], (long)mll * d,
+                      tmpS, tmpN, nullptr, true);
     copy_f64(c, tmpS, s->site[i], (long)t.k * d * mr);
     copy_f64(c, tmpN, s->site[i - 1], (long)mll * d * t.k);
     s->m[i] = t.k;
     double t3 = now();
     op_update_env(c, D3S_R2L, t.k, d, mr, wl, wr, s->renv[i], s->mpo[i], s->site[i], s->renv[i - 1]);
+    if (residual)
+      op_update_env_h2(c, D3S_R2L, t.k, d, mr, wl, wr, h2r[i], s->mpo[i], s->site[i], h2r[i - 1]);
     D3S_HIP(hipStreamSynchronize(c->stream));
     double t4 = now();
     const double ef = op_energy(c, mll, d, t.k, s->w[i - 1], wl, s->lenv[i - 1], s->mpo[i - 1], s->renv[i - 1],
@@ -180,18 +230,27 @@ void op_sweep(Ctx* c, d3s_state* s, d3s_sweep_params* p, d3s_sweep_stats* st) {
     lam = lz.theta;
     if (!lz.converged) st->nonconverged++;
     double t1 = now();
-    op_expand(c, D3S_L2R, ml, d, mr, wl, wr, s->lenv[i], s->mpo[i], s->site[i], p->alpha, Mt);
+    if (residual)
+      op_residual_gram(c, D3S_L2R, ml, d, mr, wl, wr, s->lenv[i], s->renv[i], h2r[i], s->mpo[i], s->site[i], lam,
+                       p->alpha, gram);
+    else
+      op_expand(c, D3S_L2R, ml, d, mr, wl, wr, s->lenv[i], s->mpo[i], s->site[i], p->alpha, Mt);
     D3S_HIP(hipStreamSynchronize(c->stream));
     double t2 = now();
     const int mrr = s->m[i + 2];
-    TruncResult t = op_truncate(c, D3S_L2R, ml, d, mr, (long)(1 + wr) * mr, Mt, s->site[i],
-                                (int)bond_budget(l, d, mlim, i + 1), p->eps, s->site[i + 1], (long)d * mrr,
-                                tmpS, tmpN, nullptr, true);
+    TruncResult t = residual
+        ? truncate_from_gram(c, D3S_L2R, ml, d, mr, gram, s->site[i], (int)bond_budget(l, d, mlim, i + 1), p->eps,
+                             s->site[i + 1], (long)d * mrr, tmpS, tmpN, nullptr, true)
+        : op_truncate(c, D3S_L2R, ml, d, mr, (long)(1 + wr) * mr, Mt, s->site[i],
+                      (int)bond_budget(l, d, mlim, i + 1), p->eps, s->site[i + 1], (long)d * mrr,
+                      tmpS, tmpN, nullptr, true);
     copy_f64(c, tmpS, s->site[i], (long)ml * d * t.k);
     copy_f64(c, tmpN, s->site[i + 1], (long)t.k * d * mrr);
     s->m[i + 1] = t.k;
     double t3 = now();
     op_update_env(c, D3S_L2R, ml, d, t.k, wl, wr, s->lenv[i], s->mpo[i], s->site[i], s->lenv[i + 1]);
+    if (residual)
+      op_update_env_h2(c, D3S_L2R, ml, d, t.k, wl, wr, h2l[i], s->mpo[i], s->site[i], h2l[i + 1]);
     D3S_HIP(hipStreamSynchronize(c->stream));
     double t4 = now();
     const double ef = op_energy(c, t.k, d, mrr, wr, s->w[i + 2], s->lenv[i + 1], s->mpo[i + 1], s->renv[i + 1],
