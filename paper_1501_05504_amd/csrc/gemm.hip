@@ -46,7 +46,7 @@ struct KParams {
 
 
 template <typename S, int BM, int BN, int WM, int WN, bool AKC, bool BKC>
-__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64)
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, 2)
 void gemm_kernel(KParams p) {
   typedef typename Acc<S>::T AT;
   typedef typename Acc<S>::V AV;
@@ -83,46 +83,78 @@ void gemm_kernel(KParams p) {
   Stager<S, BM, NT, AKC> ga;
   Stager<S, BN, NT, BKC> gb;
   const int nk = (kend - kbeg + BK - 1) / BK;
-  if (nk > 0) {
-    ga.load(A, p.lda, m0, p.M, kbeg, kend);
-    gb.load(B, p.ldb, n0, p.N, kbeg, kend);
-    ga.store(sA[0]);
-    gb.store(sB[0]);
-  }
-  __syncthreads();
+  // k-tiles [0, nfull) of an interior tile load without bounds tests
+  int nfull = 0;
+  if (nk > 0 && Stager<S, BM, NT, AKC>::full_ok(A, p.lda, m0, p.M, kbeg, kend) &&
+      Stager<S, BN, NT, BKC>::full_ok(B, p.ldb, n0, p.N, kbeg, kend))
+    nfull = (kend - kbeg) / BK;
+  auto fetch = [&](int t) {
+    const int k0 = kbeg + t * BK;
+    if (t < nfull) {
+      ga.load_full(A, p.lda, m0, k0);
+      gb.load_full(B, p.ldb, n0, k0);
+    } else {
+      ga.load(A, p.lda, m0, p.M, k0, kend);
+      gb.load(B, p.ldb, n0, p.N, k0, kend);
+    }
+  };
 
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) {
-      ga.load(A, p.lda, m0, p.M, kbeg + (kt + 1) * BK, kend);
-      gb.load(B, p.ldb, n0, p.N, kbeg + (kt + 1) * BK, kend);
-    }
-    Frag fa[TM], fb[TN];
-    const int koff = lgrp * (32 / (int)sizeof(S));
+  // Pipeline over k-tiles, two LDS stages, one barrier per tile.  The
+  // register groups of tile kt+1 are read between the MFMA steps of tile kt
+  // (each group as soon as the MFMAs that used its registers are issued), and
+  // tile kt+2 goes global -> registers -> LDS stage kt%2 during tile kt, so
+  // after the barrier the MFMAs never wait for LDS.
+  typedef Grp<S> G;
+  constexpr int NG = G::NG;
+  constexpr int GE = G::GB / (int)sizeof(S);       // elements per group
+  typename G::U ra[NG][TM], rb[NG][TN];
+  const int koff = lgrp * (32 / (int)sizeof(S));
+  auto read_group = [&](int stage, int g) {
 #pragma unroll
-    for (int i = 0; i < TM; ++i) {
-      const S* src = sA[cur] + (wm * WM + i * 16 + lrow) * LDK + koff;
-      fa[i].q[0] = *reinterpret_cast<const uint4*>(src);
-      fa[i].q[1] = *reinterpret_cast<const uint4*>(src + 16 / sizeof(S));
-    }
+    for (int i = 0; i < TM; ++i) G::read(ra[g][i], sA[stage] + (wm * WM + i * 16 + lrow) * LDK + koff + g * GE);
 #pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const S* src = sB[cur] + (wn * WN + j * 16 + lrow) * LDK + koff;
-      fb[j].q[0] = *reinterpret_cast<const uint4*>(src);
-      fb[j].q[1] = *reinterpret_cast<const uint4*>(src + 16 / sizeof(S));
-    }
-    // step outermost: TM*TN independent accumulators between two dependent MFMAs
+    for (int j = 0; j < TN; ++j) G::read(rb[g][j], sB[stage] + (wn * WN + j * 16 + lrow) * LDK + koff + g * GE);
+  };
+  auto mma_group = [&](int g) {
 #pragma unroll
-    for (int st = 0; st < kSteps<S>(); ++st)
+    for (int st = 0; st < G::STEPS; ++st)
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j) mma_step<S>(acc[i][j], fa[i], fb[j], st);
-    if (kt + 1 < nk) {
-      ga.store(sA[cur ^ 1]);
-      gb.store(sB[cur ^ 1]);
+        for (int j = 0; j < TN; ++j) G::mma(acc[i][j], ra[g][i], rb[g][j], st);
+  };
+
+  if (nk > 0) {
+    fetch(0);
+    ga.store(sA[0]);
+    gb.store(sB[0]);
+    if (nk > 1) {
+      fetch(1);
+      ga.store(sA[1]);
+      gb.store(sB[1]);
     }
+  }
+  __syncthreads();
+  if (nk > 0) {
+#pragma unroll
+    for (int g = 0; g < NG; ++g) read_group(0, g);
+  }
+  for (int kt = 0; kt < nk; ++kt) {
+    const bool has1 = kt + 1 < nk, has2 = kt + 2 < nk;
+    const int nxt = (kt + 1) & 1;
+    if (has2) fetch(kt + 2);
+    mma_group(0);
     __syncthreads();
+#pragma unroll
+    for (int g = 1; g < NG; ++g) {
+      if (has1) read_group(nxt, g - 1);
+      mma_group(g);
+      if (g == NG / 2 && has2) {
+        ga.store(sA[kt & 1]);
+        gb.store(sB[kt & 1]);
+      }
+    }
+    if (has1) read_group(nxt, NG - 1);
   }
 
   const AT alpha = (AT)p.alpha, beta = (AT)p.beta;

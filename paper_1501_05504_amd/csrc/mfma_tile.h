@@ -34,6 +34,33 @@ __device__ __forceinline__ void mma_step(typename Acc<S>::V& c, const Frag& a, c
 // MFMA steps per 32-byte fragment: 4 (FP64), 8 (FP32), 2 (BF16)
 template <typename S> constexpr int kSteps() { return sizeof(S) == 8 ? 4 : (sizeof(S) == 4 ? 8 : 2); }
 
+// A 32-byte fragment split into register groups that are read from LDS one
+// at a time: 4 groups of 8 bytes (FP64: one MFMA step each; FP32: two) or 2
+// groups of 16 bytes (BF16: one step each).  The group g of lane group lg
+// holds bytes [32 lg + g*GB, 32 lg + (g+1)*GB) of an LDS row, the same
+// k-slot assignment as the whole fragment.
+template <typename S> struct Grp {
+  static constexpr int NG = sizeof(S) == 2 ? 2 : 4;
+  static constexpr int GB = 32 / NG;
+  static constexpr int STEPS = kSteps<S>() / NG;
+  union U {
+    uint2 q2;
+    uint4 q4;
+    double d;
+    float f[2];
+    bf8v h;
+  };
+  __device__ __forceinline__ static void read(U& u, const S* src) {
+    if constexpr (GB == 8) u.q2 = *reinterpret_cast<const uint2*>(src);
+    else u.q4 = *reinterpret_cast<const uint4*>(src);
+  }
+  __device__ __forceinline__ static void mma(typename Acc<S>::V& c, const U& a, const U& b, int s) {
+    if constexpr (sizeof(S) == 8) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a.d, b.d, c, 0, 0, 0);
+    else if constexpr (sizeof(S) == 4) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.f[s], b.f[s], c, 0, 0, 0);
+    else c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.h, c, 0, 0, 0);
+  }
+};
+
 
 __device__ __forceinline__ void tile_coords(int nTm, int nTn, int& tm, int& tn) {
   const int nt = nTm * nTn;
@@ -89,6 +116,29 @@ struct Stager {
       }
       r[p] = u.q;
     }
+  }
+
+  // Interior tiles: every chunk in bounds and 16-byte aligned (the caller
+  // checks this once per tile with wave-uniform values), so the loads carry
+  // no per-element tests and no divergent branches.
+  __device__ __forceinline__ void load_full(const S* __restrict__ X, long ld, int o0, int k0) {
+#pragma unroll
+    for (int p = 0; p < LPT; ++p) {
+      const int c = threadIdx.x + p * NT;
+      int o, k;
+      if constexpr (KC) { o = c / (BK / VE); k = (c % (BK / VE)) * VE; }
+      else { k = c / (O / VE); o = (c % (O / VE)) * VE; }
+      const S* src = KC ? X + (long)(o0 + o) * ld + (k0 + k) : X + (long)(k0 + k) * ld + (o0 + o);
+      r[p] = *reinterpret_cast<const uint4*>(src);
+    }
+  }
+
+  // whether a tile starting at (o0, k0) may use load_full
+  __device__ __forceinline__ static bool full_ok(const S* X, long ld, int o0, int Odim, int k0, int K) {
+    const bool in = (o0 + O <= Odim) && (k0 + BK <= K);
+    const bool al = ((reinterpret_cast<uintptr_t>(X) & 15) == 0) && (ld % VE == 0) &&
+                    (KC ? (k0 % VE == 0) : (o0 % VE == 0));
+    return in && al;
   }
 
   __device__ __forceinline__ void store(S* __restrict__ s) const {
