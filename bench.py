@@ -168,15 +168,19 @@ def block_heff_bench(ctx, abi, synth, torch, np, m, dev, steps):
     return info
 
 
-def hubbard_sweep_bench(ctx, abi, synth, torch, dev, l, sched, U, tol, lanczos_tol, max_final):
+def hubbard_sweep_bench(ctx, abi, synth, torch, dev, l, sched, U, tol, lanczos_tol, max_final, growth_tol):
     """DMRG3S block sweeps on the Hubbard chain (t = 1, half filling, 2Sz = 0)
     from one seeded symmetric state with a growing bond limit: two sweeps at
     each m of the schedule, then sweeps at the last m until the normalised
-    sweep energy change is below `tol`.  Plain FP64 products against FP32
-    products with FP64 refinement of every Ritz vector to the same residual
-    tolerance; wall time from the first environment build on."""
+    sweep energy change is below `tol`.  Once the bonds stay below the
+    current limit (the truncation, not the limit, sets them) larger limits
+    change nothing and the run moves to the final stage.  The growth sweeps
+    solve the local problems to `growth_tol`, the final ones to
+    `lanczos_tol`.  Plain FP64 products against FP32 products with FP64
+    refinement of every Ritz vector to the same residual tolerance; wall time
+    from the first environment build on."""
     out = {"workload": "hubbard_chain_blocks", "l": l, "U": U, "filling": "half, 2Sz=0", "m_schedule": sched,
-           "tol": tol, "lanczos_tol": lanczos_tol}
+           "tol": tol, "lanczos_tol": lanczos_tol, "growth_lanczos_tol": growth_tol}
     phys = abi.HUBBARD_CHARGES
     mpo = abi.hubbard_chain_mpo(l, t=1.0, U=U)
     for name, prec in (("f64", abi.F64), ("mixed_f32", abi.F32)):
@@ -189,19 +193,26 @@ def hubbard_sweep_bench(ctx, abi, synth, torch, dev, l, sched, U, tol, lanczos_t
         params = abi.sweep_params(alpha=1e-3, e_before=e0, prec=prec, tol=lanczos_tol)
         energies, t_conv, prev, nsweeps, mv, mv64 = [], None, None, 0, 0, 0
         plan = [(m, 2) for m in sched[:-1]] + [(sched[-1], max_final)]
+        saturated = False
         for m, count in plan:
+            final = m == sched[-1]
+            if saturated and not final:
+                continue
             params.m_limit = m
+            params.lanczos_tol = lanczos_tol if final else growth_tol
             for _ in range(count):
                 _, stats, recs = ctx.sweep_blocks(st, sym, params, use_graph=True)
                 nsweeps += 1
                 mv += sum(r.matvecs for r in recs)
                 mv64 += sum(r.f64_matvecs for r in recs)
                 energies.append(stats.energy)
-                done = (m == sched[-1] and prev is not None and abs(stats.energy - prev) / abs(stats.energy) < tol)
+                done = (final and prev is not None and abs(stats.energy - prev) / abs(stats.energy) < tol)
                 prev = stats.energy
                 if done:
                     t_conv = time.perf_counter() - t0
                     break
+            if not final and max(st.m) < m:
+                saturated = True
         wall = time.perf_counter() - t0
         split = {k: round(sum(getattr(r, k) for r in recs), 3) for k in ("t_eig", "t_expand", "t_trunc", "t_env", "t_energy")}
         out[name] = {"seconds_to_tol": None if t_conv is None else round(t_conv, 3), "seconds": round(wall, 3),
@@ -509,6 +520,8 @@ def main():
     ap.add_argument("--sweep-sched", type=str, default="128,256,512,1024,2048",
                     help="bond limits of the block sweep run (two sweeps each, then to convergence at the last)")
     ap.add_argument("--sweep-max", type=int, default=8, help="sweeps at the last bond limit")
+    ap.add_argument("--growth-tol", type=float, default=1e-10,
+                    help="eigensolver residual tolerance of the bond-growth sweeps of the Hubbard chain run")
     ap.add_argument("--dense-m", type=int, default=256, help="bond limit of the dense-vs-block one-sweep comparison")
     ap.add_argument("--cylinder", type=str, default="256,512,1024,2048,4096",
                     help="bond limits of the 4x16 cylinder run ('' = skip)")
@@ -624,7 +637,7 @@ def main():
         print("bench: blocks %s" % line["blocks"], file=sys.stderr, flush=True)
         sched = [int(x) for x in args.sweep_sched.split(",")]
         line["sweep"] = hubbard_sweep_bench(ctx, abi, synth, torch, dev, args.sweep_l, sched, 8.0, 1e-8, 1e-10,
-                                            args.sweep_max)
+                                            args.sweep_max, args.growth_tol)
         if args.dense_m > 0:
             line["dense_vs_blocks"] = dense_vs_blocks_bench(ctx, abi, synth, torch, dev, args.sweep_l, args.dense_m,
                                                             8.0)

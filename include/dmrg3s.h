@@ -83,7 +83,8 @@ d3s_status d3s_synchronize(d3s_ctx ctx);
 const char* d3s_version(void);
 /* GEMM tile configuration: -1 = size heuristic (default), 0 = 128x128
  * block tiles (4 waves of 64x64), 1 = 64x64 (4 waves of 32x32), 2 = 256x128
- * (8 waves of 64x64), 3 = 128x128 (8 waves of 64x32). */
+ * (8 waves of 64x64), 3 = 128x128 (8 waves of 64x32), 4 = 256x128 (4 waves
+ * of 128x64; FP32 and BF16, FP64 runs 2). */
 d3s_status d3s_set_tile_config(d3s_ctx ctx, int cfg);
 /* Tile configuration of the grouped block-sparse launches of plans built
  * afterwards: -1 = chosen per launch by a work model (or by timing, with

@@ -137,7 +137,7 @@ d3s_status d3s_set_grouped_tile(d3s_ctx ctx, int cfg) {
 
 d3s_status d3s_set_tile_config(d3s_ctx ctx, int cfg) {
   return guarded(ctx, [&] {
-    D3S_REQUIRE(cfg >= -1 && cfg <= 3, "tile config must be in [-1, 3]");
+    D3S_REQUIRE(cfg >= -1 && cfg <= 4, "tile config must be in [-1, 4]");
     ctx->c.tile_config = cfg;
     return D3S_OK;
   });

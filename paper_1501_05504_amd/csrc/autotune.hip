@@ -66,7 +66,7 @@ void autotune_load(Ctx* c) {
   std::string key;
   int cfg;
   while (f >> key >> cfg)
-    if (cfg >= 0 && cfg <= 3) c->tune_cache[key] = cfg;
+    if (cfg >= 0 && cfg <= 5) c->tune_cache[key] = cfg;
 }
 
 void tuned_gemm(Ctx* c, d3s_prec p, const GemmArgs& g) {
@@ -81,7 +81,7 @@ void tuned_gemm(Ctx* c, d3s_prec p, const GemmArgs& g) {
     cfg = it->second;
   } else if (g.beta == 0.0 && !capturing(c)) {
     double best = 1e300;
-    for (int k = 0; k <= 3; ++k) {
+    for (int k = 0; k <= 4; ++k) {
       c->tile_config = k;
       const double ms = time_ms(c, [&] { gemm(c, p, g); }, 3);
       if (ms < best) {

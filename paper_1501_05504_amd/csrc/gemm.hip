@@ -46,7 +46,7 @@ struct KParams {
 
 
 template <typename S, int BM, int BN, int WM, int WN, bool AKC, bool BKC>
-__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, 2)
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, (kMinWaves<BM, BN>()))
 void gemm_kernel(KParams p) {
   typedef typename Acc<S>::T AT;
   typedef typename Acc<S>::V AV;
@@ -237,6 +237,8 @@ void launch_cfg(Ctx* c, const GemmArgs& g, int splits) {
 // Tile configurations (block tile / wave tile / waves):
 //   0: 128x128 / 64x64 / 4      1: 64x64 / 32x32 / 4
 //   2: 256x128 / 64x64 / 8      3: 128x128 / 64x32 / 8
+//   4: 256x128 / 128x64 / 4 (one wave per SIMD, accumulators in AGPRs;
+//      FP32 and BF16 only, FP64 runs configuration 2)
 template <typename S>
 void gemm_dispatch(Ctx* c, const GemmArgs& g) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
@@ -251,7 +253,7 @@ void gemm_dispatch(Ctx* c, const GemmArgs& g) {
   long tiles;
   switch (cfg) {
     case 0: case 3: tiles = t128; break;
-    case 2: tiles = (long)((g.M + 255) / 256) * ((g.N + 127) / 128) * g.batch; break;
+    case 2: case 4: tiles = (long)((g.M + 255) / 256) * ((g.N + 127) / 128) * g.batch; break;
     default: tiles = (long)((g.M + 63) / 64) * ((g.N + 63) / 64) * g.batch; break;
   }
   // split K when the tiles cannot fill the 256 CUs and K is long enough for
@@ -266,6 +268,11 @@ void gemm_dispatch(Ctx* c, const GemmArgs& g) {
     case 0: launch_cfg<S, 128, 128, 64, 64>(c, g, splits); break;
     case 2: launch_cfg<S, 256, 128, 64, 64>(c, g, splits); break;
     case 3: launch_cfg<S, 128, 128, 64, 32>(c, g, splits); break;
+    case 4:
+      // FP64 accumulators of a 128x64 wave tile do not fit the register file
+      if constexpr (sizeof(S) == 8) launch_cfg<S, 256, 128, 64, 64>(c, g, splits);
+      else launch_cfg<S, 256, 128, 128, 64>(c, g, splits);
+      break;
     default: launch_cfg<S, 64, 64, 32, 32>(c, g, splits); break;
   }
 }

@@ -38,7 +38,7 @@ struct GParams {
 };
 
 template <typename S, int BM, int BN, int WM, int WN, bool AKC, bool BKC>
-__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64)
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, (kMinWaves<BM, BN>()))
 void grouped_kernel(GParams p) {
   typedef typename Acc<S>::T AT;
   typedef typename Acc<S>::V AV;
@@ -82,60 +82,84 @@ void grouped_kernel(GParams p) {
   Stager<S, BM, NT, AKC> ga;
   Stager<S, BN, NT, BKC> gb;
   const int send = t.seg0 + t.nseg;
-  // first non-empty segment
-  int cs = t.seg0, ck = 0;
-  while (cs < send && p.segs[cs].K <= 0) ++cs;
-  if (cs < send) {
-    const GSeg sg = p.segs[cs];
-    ga.load(Ab + sg.a_off, sg.lda, m0, t.M, 0, sg.K);
-    gb.load(Bb + sg.b_off, sg.ldb, n0, t.N, 0, sg.K);
-    ga.store(sA[0]);
-    gb.store(sB[0]);
+  int ntiles = 0;
+  for (int q = t.seg0; q < send; ++q) {
+    const int K = p.segs[q].K;
+    if (K > 0) ntiles += (K + BK - 1) / BK;
   }
-  __syncthreads();
-  int cur = 0;
-  while (cs < send) {
-    // the (segment, k-tile) after the current one
-    int ns = cs, nk = ck + 1;
-    if (nk * BK >= p.segs[cs].K) {
-      ns = cs + 1;
-      nk = 0;
-      while (ns < send && p.segs[ns].K <= 0) ++ns;
+  int fs = t.seg0, fk = 0;
+  while (fs < send && p.segs[fs].K <= 0) ++fs;
+  auto fetch_next = [&]() {
+    const GSeg sg = p.segs[fs];
+    const S* As = Ab + sg.a_off;
+    const S* Bs = Bb + sg.b_off;
+    const int k0 = fk * BK;
+    if (Stager<S, BM, NT, AKC>::full_ok(As, sg.lda, m0, t.M, k0, sg.K) &&
+        Stager<S, BN, NT, BKC>::full_ok(Bs, sg.ldb, n0, t.N, k0, sg.K)) {
+      ga.load_full(As, sg.lda, m0, k0);
+      gb.load_full(Bs, sg.ldb, n0, k0);
+    } else {
+      ga.load(As, sg.lda, m0, t.M, k0, sg.K);
+      gb.load(Bs, sg.ldb, n0, t.N, k0, sg.K);
     }
-    const bool more = ns < send;
-    if (more) {
-      const GSeg sg = p.segs[ns];
-      ga.load(Ab + sg.a_off, sg.lda, m0, t.M, nk * BK, sg.K);
-      gb.load(Bb + sg.b_off, sg.ldb, n0, t.N, nk * BK, sg.K);
+    if ((fk + 1) * BK >= sg.K) {
+      ++fs;
+      fk = 0;
+      while (fs < send && p.segs[fs].K <= 0) ++fs;
+    } else {
+      ++fk;
     }
-    Frag fa[TM], fb[TN];
-    const int koff = lgrp * (32 / (int)sizeof(S));
+  };
+  typedef Grp<S> G;
+  constexpr int NG = G::NG;
+  constexpr int GE = G::GB / (int)sizeof(S);
+  typename G::U ra[NG][TM], rb[NG][TN];
+  const int koff = lgrp * (32 / (int)sizeof(S));
+  auto read_group = [&](int stage, int g) {
 #pragma unroll
-    for (int i = 0; i < TM; ++i) {
-      const S* src = sA[cur] + (wm * WM + i * 16 + lrow) * LDK + koff;
-      fa[i].q[0] = *reinterpret_cast<const uint4*>(src);
-      fa[i].q[1] = *reinterpret_cast<const uint4*>(src + 16 / sizeof(S));
-    }
+    for (int i = 0; i < TM; ++i) G::read(ra[g][i], sA[stage] + (wm * WM + i * 16 + lrow) * LDK + koff + g * GE);
 #pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const S* src = sB[cur] + (wn * WN + j * 16 + lrow) * LDK + koff;
-      fb[j].q[0] = *reinterpret_cast<const uint4*>(src);
-      fb[j].q[1] = *reinterpret_cast<const uint4*>(src + 16 / sizeof(S));
-    }
+    for (int j = 0; j < TN; ++j) G::read(rb[g][j], sB[stage] + (wn * WN + j * 16 + lrow) * LDK + koff + g * GE);
+  };
+  auto mma_group = [&](int g) {
 #pragma unroll
-    for (int st = 0; st < kSteps<S>(); ++st)
+    for (int st = 0; st < G::STEPS; ++st)
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j) mma_step<S>(acc[i][j], fa[i], fb[j], st);
-    if (more) {
-      ga.store(sA[cur ^ 1]);
-      gb.store(sB[cur ^ 1]);
+        for (int j = 0; j < TN; ++j) G::mma(acc[i][j], ra[g][i], rb[g][j], st);
+  };
+  if (ntiles > 0) {
+    fetch_next();
+    ga.store(sA[0]);
+    gb.store(sB[0]);
+    if (ntiles > 1) {
+      fetch_next();
+      ga.store(sA[1]);
+      gb.store(sB[1]);
     }
+  }
+  __syncthreads();
+  if (ntiles > 0) {
+#pragma unroll
+    for (int g = 0; g < NG; ++g) read_group(0, g);
+  }
+  for (int kt = 0; kt < ntiles; ++kt) {
+    const bool has1 = kt + 1 < ntiles, has2 = kt + 2 < ntiles;
+    const int nxt = (kt + 1) & 1;
+    if (has2) fetch_next();
+    mma_group(0);
     __syncthreads();
-    cur ^= 1;
-    cs = ns;
-    ck = nk;
+#pragma unroll
+    for (int g = 1; g < NG; ++g) {
+      if (has1) read_group(nxt, g - 1);
+      mma_group(g);
+      if (g == NG / 2 && has2) {
+        ga.store(sA[kt & 1]);
+        gb.store(sB[kt & 1]);
+      }
+    }
+    if (has1) read_group(nxt, NG - 1);
   }
 
   const AT alpha = (AT)p.alpha;

@@ -34,6 +34,11 @@ __device__ __forceinline__ void mma_step(typename Acc<S>::V& c, const Frag& a, c
 // MFMA steps per 32-byte fragment: 4 (FP64), 8 (FP32), 2 (BF16)
 template <typename S> constexpr int kSteps() { return sizeof(S) == 8 ? 4 : (sizeof(S) == 4 ? 8 : 2); }
 
+// Waves per SIMD a tile configuration is compiled for: the 4-wave 64x64 and
+// smaller tiles need 16 KB-class LDS and run four workgroups per CU, so
+// their registers are capped at 128; 96x96 tiles run two.
+template <int BM, int BN> constexpr int kMinWaves() { return BM * BN <= 64 * 64 ? 4 : (BM == 96 ? 2 : 1); }
+
 // A 32-byte fragment split into register groups that are read from LDS one
 // at a time: 4 groups of 8 bytes (FP64: one MFMA step each; FP32: two) or 2
 // groups of 16 bytes (BF16: one step each).  The group g of lane group lg
