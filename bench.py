@@ -27,8 +27,8 @@ HBM_PEAK = 8.0e12
 # FETCH_SIZE / WRITE_SIZE passes (scaled by a 1 GiB copy reference), valid
 # only for the GEMM source they were taken on (first 16 hex digits of its
 # SHA-256); any other source reports null.
-TRAFFIC = {"src_sha": "5089802e4ddde374", "m": 2048,
-           "gemm1": 4.031e9 + 0.805e9, "gemm2": 4.167e9 + 0.134e9}
+TRAFFIC = {"src_sha": "0df620b01dc2054d", "m": 2048,
+           "gemm1": 4.047e9 + 0.805e9, "gemm2": 4.569e9 + 0.134e9}
 
 
 def gemm_source_sha():
@@ -520,7 +520,7 @@ def main():
     ap.add_argument("--sweep-sched", type=str, default="128,256,512,1024,2048",
                     help="bond limits of the block sweep run (two sweeps each, then to convergence at the last)")
     ap.add_argument("--sweep-max", type=int, default=8, help="sweeps at the last bond limit")
-    ap.add_argument("--growth-tol", type=float, default=1e-10,
+    ap.add_argument("--growth-tol", type=float, default=1e-8,
                     help="eigensolver residual tolerance of the bond-growth sweeps of the Hubbard chain run")
     ap.add_argument("--dense-m", type=int, default=256, help="bond limit of the dense-vs-block one-sweep comparison")
     ap.add_argument("--cylinder", type=str, default="256,512,1024,2048,4096",
