@@ -137,9 +137,39 @@ void gemm_kernel(KParams p) {
   __syncthreads();
   if (nk > 0) {
 #pragma unroll
-    for (int g = 0; g < NG; ++g) read_group(0, g);
+    for (int g = 0; g < NG - 1; ++g) read_group(0, g);
   }
-  for (int kt = 0; kt < nk; ++kt) {
+  // Steady state (every tile fetched here is interior): one branch-free
+  // block per half, so the memory instructions can be spread between the
+  // MFMAs.  The last register group of tile kt is read at the top of
+  // iteration kt (its LDS stage is rewritten only after this iteration's
+  // barrier), with the global loads of tile kt+2, during the MFMAs of group
+  // 0; after the barrier each group of tile kt+1 is read during the MFMAs
+  // of the next group of tile kt, and tile kt+2 is stored with the last one.
+  constexpr int QM = G::STEPS * TM * TN;            // MFMAs per group
+  int kt = 0;
+  for (; kt + 2 < nfull; ++kt) {
+    const int cur = kt & 1, nxt = cur ^ 1;
+    ga.load_full(A, p.lda, m0, kbeg + (kt + 2) * BK);
+    gb.load_full(B, p.ldb, n0, kbeg + (kt + 2) * BK);
+    read_group(cur, NG - 1);
+    mma_group(0);
+    interleave<QM, TM + TN, 0, Stager<S, BM, NT, AKC>::LPT + Stager<S, BN, NT, BKC>::LPT>();
+    __syncthreads();
+#pragma unroll
+    for (int g = 1; g < NG; ++g) {
+      read_group(nxt, g - 1);
+      if (g == NG - 1) {
+        ga.store(sA[cur]);
+        gb.store(sB[cur]);
+      }
+      mma_group(g);
+      if (g == NG - 1) interleave<QM, TM + TN, 2 * (Stager<S, BM, NT, AKC>::LPT + Stager<S, BN, NT, BKC>::LPT), 0>();
+      else interleave<QM, TM + TN, 0, 0>();
+    }
+  }
+  if (kt < nk) read_group(kt & 1, NG - 1);
+  for (; kt < nk; ++kt) {
     const bool has1 = kt + 1 < nk, has2 = kt + 2 < nk;
     const int nxt = (kt + 1) & 1;
     if (has2) fetch(kt + 2);

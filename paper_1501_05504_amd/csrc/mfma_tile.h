@@ -34,6 +34,23 @@ __device__ __forceinline__ void mma_step(typename Acc<S>::V& c, const Frag& a, c
 // MFMA steps per 32-byte fragment: 4 (FP64), 8 (FP32), 2 (BF16)
 template <typename S> constexpr int kSteps() { return sizeof(S) == 8 ? 4 : (sizeof(S) == 4 ? 8 : 2); }
 
+// Scheduling hint for one branch-free block: spread R LDS reads, W LDS
+// writes and V global loads between Q MFMAs (one memory instruction after
+// each MFMA, reads first, then writes, then global loads; the rest of the
+// MFMAs after them), so that they issue while the matrix core is busy.
+template <int Q, int R, int W, int V>
+__device__ __forceinline__ void interleave() {
+  constexpr int P = (R + W + V < Q) ? R + W + V : Q;
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    if (i < R) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    else if (i < R + W) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+    else __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+  }
+  if constexpr (Q > P) __builtin_amdgcn_sched_group_barrier(0x008, Q - P, 0);
+}
+
 // Waves per SIMD a tile configuration is compiled for: the 4-wave 64x64 and
 // smaller tiles need 16 KB-class LDS and run four workgroups per CU, so
 // their registers are capped at 128; 96x96 tiles run two.
