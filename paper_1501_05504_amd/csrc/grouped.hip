@@ -142,24 +142,34 @@ void grouped_kernel(GParams p) {
   __syncthreads();
   if (ntiles > 0) {
 #pragma unroll
-    for (int g = 0; g < NG; ++g) read_group(0, g);
+    for (int g = 0; g < NG - 1; ++g) read_group(0, g);
   }
+  // As in the plain GEMM: the last register group of tile kt is read at the
+  // top of iteration kt, the groups of tile kt+1 after the barrier during the
+  // MFMAs of the next group of tile kt, and the staged tile kt+2 is stored
+  // with the last group.  After the fetch each iteration is branch-free:
+  // past the end of the list the reads and the store move data that is
+  // never used (the store's stage holds a tile that has been read in full).
+  constexpr int QM = G::STEPS * TM * TN;
+  constexpr int NW = 2 * (Stager<S, BM, NT, AKC>::LPT + Stager<S, BN, NT, BKC>::LPT);
   for (int kt = 0; kt < ntiles; ++kt) {
-    const bool has1 = kt + 1 < ntiles, has2 = kt + 2 < ntiles;
-    const int nxt = (kt + 1) & 1;
-    if (has2) fetch_next();
+    const int cur = kt & 1, nxt = cur ^ 1;
+    if (kt + 2 < ntiles) fetch_next();
+    read_group(cur, NG - 1);
     mma_group(0);
+    interleave<QM, TM + TN, 0, 0>();
     __syncthreads();
 #pragma unroll
     for (int g = 1; g < NG; ++g) {
-      if (has1) read_group(nxt, g - 1);
-      mma_group(g);
-      if (g == NG / 2 && has2) {
-        ga.store(sA[kt & 1]);
-        gb.store(sB[kt & 1]);
+      read_group(nxt, g - 1);
+      if (g == NG - 1) {
+        ga.store(sA[cur]);
+        gb.store(sB[cur]);
       }
+      mma_group(g);
+      if (g == NG - 1) interleave<QM, TM + TN, NW, 0>();
+      else interleave<QM, TM + TN, 0, 0>();
     }
-    if (has1) read_group(nxt, NG - 1);
   }
 
   const AT alpha = (AT)p.alpha;
