@@ -587,6 +587,14 @@ def main():
             entry["f32"] = {"ms": ms32, "gflops": F / ms32 * 1e-6,
                             "kernel_ms": dict(zip(["gemm1", "wmap", "gemm2"], kern32))}
             print("bench: m=%d f32 %.3f ms  %.1f GFLOP/s" % (m, ms32, F / ms32 * 1e-6), file=sys.stderr, flush=True)
+            # BF16 operands (L, R, psi; W in FP32), FP32 accumulation and output
+            Lb, Rb, pb = L.to(torch.bfloat16), R.to(torch.bfloat16), psi.to(torch.bfloat16)
+            msb, _, kernb = time_heff(ctx, torch, Lb, Wf, Rb, pb, of, steps, args.warmup)
+            entry["bf16"] = {"ms": msb, "gflops": F / msb * 1e-6,
+                             "kernel_ms": dict(zip(["gemm1", "wmap", "gemm2"], kernb))}
+            print("bench: m=%d bf16 %.3f ms  %.1f GFLOP/s  kernels %s" % (m, msb, F / msb * 1e-6, kernb),
+                  file=sys.stderr, flush=True)
+            del Lb, Rb, pb
         results[m] = entry
         if m == args.m:
             heads = (L, W, R, psi, out, ms, kern, steps)
@@ -628,6 +636,9 @@ def main():
                            "f64_pct_peak": round(100 * v["gflops"] * 1e9 / PEAK["f64"], 2),
                            "f32_gflops": round(v["f32"]["gflops"], 1) if "f32" in v else None,
                            "f32_pct_peak": round(100 * v["f32"]["gflops"] * 1e9 / PEAK["f32"], 2) if "f32" in v else None,
+                           "bf16_gflops": round(v["bf16"]["gflops"], 1) if "bf16" in v else None,
+                           "bf16_kernel_ms": ({a: round(b, 4) for a, b in v["bf16"]["kernel_ms"].items()}
+                                              if "bf16" in v else None),
                            "kernel_ms_f64": {a: round(b, 4) for a, b in v["kernel_ms"].items()}}
                   for k, v in results.items()},
     }

@@ -37,7 +37,7 @@ struct Error {
 enum WsSlot {
   WS_T1 = 0, WS_T2, WS_LZ_V, WS_LZ_W, WS_LZ_COEF, WS_RED, WS_GRAM, WS_EIGVAL,
   WS_EIGTMP, WS_UKT, WS_X, WS_MT, WS_CAST_L, WS_CAST_R, WS_CAST_X, WS_CAST_Y,
-  WS_CAST_W, WS_REF, WS_PSI, WS_INFO, WS_NBR, WS_MISC, WS_SPLITK, WS_DESC, WS_BLK_X, WS_XPACK, WS_GPACK, WS_GVAL, WS_TUNE, WS_PK, WS_LZ_K, WS_GS_NORM, WS_JD_V, WS_JD_W, WS_JD_Z, WS_JD_COEF, WS_G2_PART, WS_W2, WS_RMET, WS_RZ, WS_RT, WS_RGRAM, WS_H2, WS_NSLOTS
+  WS_CAST_W, WS_REF, WS_PSI, WS_INFO, WS_NBR, WS_MISC, WS_SPLITK, WS_DESC, WS_BLK_X, WS_XPACK, WS_GPACK, WS_GVAL, WS_TUNE, WS_PK, WS_LZ_K, WS_GS_NORM, WS_JD_V, WS_JD_W, WS_JD_Z, WS_JD_COEF, WS_G2_PART, WS_W2, WS_RMET, WS_RZ, WS_RT, WS_RGRAM, WS_H2, WS_PSIT, WS_NSLOTS
 };
 
 struct Ctx {
@@ -187,6 +187,8 @@ void mask_site(Ctx* c, double* M, int ml, int d, int mr, const std::vector<int>&
                const std::vector<int>& kb);
 // out[r][col] = in[col][r] for an R x C input (row-major), i.e. out is C x R
 void transpose_f64(Ctx* c, const double* in, long R, long C, double* out);
+// out[C][R] = in[R][C] for 8-, 4- or 2-byte elements (esz)
+void transpose_any(Ctx* c, int esz, const void* in, long R, long C, void* out);
 // copy a rows x cols block with leading dimensions
 void copy2d_f64(Ctx* c, const double* src, long lds, double* dst, long ldd, long rows, long cols);
 // casts for the mixed-precision path

@@ -529,8 +529,9 @@ __global__ void mask_site_kernel(double* __restrict__ M, int ml, int d, int mr, 
   }
 }
 
-__global__ void transpose_kernel(const double* __restrict__ in, long R, long C, double* __restrict__ out) {
-  __shared__ double tile[32][33];
+template <typename T>
+__global__ void transpose_kernel(const T* __restrict__ in, long R, long C, T* __restrict__ out) {
+  __shared__ T tile[32][33];
   const long r0 = (long)blockIdx.y * 32, c0 = (long)blockIdx.x * 32;
   for (int i = threadIdx.y; i < 32; i += blockDim.y) {
     const long r = r0 + i, cc = c0 + threadIdx.x;
@@ -894,8 +895,22 @@ void mask_site(Ctx* c, double* M, int ml, int d, int mr, const std::vector<int>&
 }
 
 void transpose_f64(Ctx* c, const double* in, long R, long C, double* out) {
+  transpose_any(c, 8, in, R, C, out);
+}
+
+void transpose_any(Ctx* c, int esz, const void* in, long R, long C, void* out) {
+  if (R <= 0 || C <= 0) return;
+  if ((R + 31) / 32 > 65535) throw Error{D3S_EINVAL, "transpose: too many rows"};
   dim3 grid((unsigned)((C + 31) / 32), (unsigned)((R + 31) / 32));
-  hipLaunchKernelGGL(transpose_kernel, grid, dim3(32, 8), 0, c->stream, in, R, C, out);
+  if (esz == 8)
+    hipLaunchKernelGGL(transpose_kernel<double>, grid, dim3(32, 8), 0, c->stream, (const double*)in, R, C,
+                       (double*)out);
+  else if (esz == 4)
+    hipLaunchKernelGGL(transpose_kernel<float>, grid, dim3(32, 8), 0, c->stream, (const float*)in, R, C,
+                       (float*)out);
+  else
+    hipLaunchKernelGGL(transpose_kernel<unsigned short>, grid, dim3(32, 8), 0, c->stream,
+                       (const unsigned short*)in, R, C, (unsigned short*)out);
   D3S_HIP(hipGetLastError());
 }
 

@@ -79,8 +79,13 @@ void op_apply_heff(Ctx* c, d3s_prec p, int ml, int d, int mr, int wl, int wr, co
   hipEvent_t* ev = nullptr;
   if (c->prof && c->prof_n < c->prof_cap) ev = &c->prof_ev[4 * (size_t)c->prof_n++];
   if (ev) D3S_HIP(hipEventRecord(ev[0], c->stream));
-  GemmArgs g1{ml * wl, d * mr, ml, L, ml, true, 0, psi, (long)d * mr, false, 0, T1, (long)d * mr, 0,
-              1.0, 0.0, 1};
+  // GEMM-1's B operand psi[x][(t,y)] runs along N; a copy psi^T[(t,y)][x]
+  // runs along K, which keeps the LDS staging of B in 16-byte vector stores
+  // (the transposing stores cost most in BF16).  Counted in GEMM-1's time.
+  const size_t esz = (p == D3S_F64) ? 8 : (p == D3S_F32 ? 4 : 2);
+  void* psiT = ws_get(c, WS_PSIT, esz * (size_t)ml * d * mr);
+  transpose_any(c, (int)esz, psi, ml, (long)d * mr, psiT);
+  GemmArgs g1{ml * wl, d * mr, ml, L, ml, true, 0, psiT, ml, true, 0, T1, (long)d * mr, 0, 1.0, 0.0, 1};
   tuned_gemm(c, p, g1);
   if (ev) D3S_HIP(hipEventRecord(ev[1], c->stream));
   wmap_l2r(c, p, T1, W, T2, (long)wr * mr, ml, d, mr, wl, wr, 1.0);
