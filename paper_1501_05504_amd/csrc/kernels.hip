@@ -48,11 +48,13 @@ void wmap_l2r_kernel(const Tin* __restrict__ T1, const Tc* __restrict__ Wg, Tout
   Tc* sW = reinterpret_cast<Tc*>(smem_raw);
   const int K = wl * d;
   const int nOut = d * wr;
-  for (int i = threadIdx.x; i < K * nOut; i += blockDim.x) {
-    const int o = i / K, k = i - o * K;        // o = s*wr + v, k = w*d + t
+  // rows of MAXK entries, zero beyond K: the inner loop has no bounds test and
+  // reads W with vector LDS loads
+  for (int i = threadIdx.x; i < MAXK * nOut; i += blockDim.x) {
+    const int o = i / MAXK, k = i - o * MAXK;  // o = s*wr + v, k = w*d + t
     const int s = o / wr, v = o - s * wr;
     const int w = k / d, t = k - w * d;
-    sW[i] = alpha * Wg[((w * wr + v) * d + s) * d + t];
+    sW[i] = (k < K) ? alpha * Wg[((w * wr + v) * d + s) * d + t] : Tc(0);
   }
   __syncthreads();
   const int a = blockIdx.y;
@@ -63,11 +65,10 @@ void wmap_l2r_kernel(const Tin* __restrict__ T1, const Tc* __restrict__ Wg, Tout
 #pragma unroll
   for (int k = 0; k < MAXK; ++k) in[k] = (k < K) ? (Tc)Cvt<Tin>::ld(src[(long)k * mr]) : Tc(0);
   for (int o = 0; o < nOut; ++o) {
-    const Tc* wrow = sW + o * K;
+    const Tc* wrow = sW + o * MAXK;
     Tc acc = 0;
 #pragma unroll
-    for (int k = 0; k < MAXK; ++k)
-      if (k < K) acc += wrow[k] * in[k];
+    for (int k = 0; k < MAXK; ++k) acc += wrow[k] * in[k];
     const int s = o / wr, v = o - s * wr;
     out[(long)(a * d + s) * ld_out + (long)v * mr + y] = Cvt<Tout>::st(acc);
   }
@@ -83,11 +84,11 @@ void wmap_r2l_kernel(const Tin* __restrict__ Y, const Tc* __restrict__ Wg, Tout*
   Tc* sW = reinterpret_cast<Tc*>(smem_raw);
   const int K = d * wr;
   const int nOut = wl * d;
-  for (int i = threadIdx.x; i < K * nOut; i += blockDim.x) {
-    const int o = i / K, k = i - o * K;        // o = w*d + s, k = t*wr + v
+  for (int i = threadIdx.x; i < MAXK * nOut; i += blockDim.x) {
+    const int o = i / MAXK, k = i - o * MAXK;  // o = w*d + s, k = t*wr + v
     const int w = o / d, s = o - w * d;
     const int t = k / wr, v = k - t * wr;
-    sW[i] = alpha * Wg[((w * wr + v) * d + s) * d + t];
+    sW[i] = (k < K) ? alpha * Wg[((w * wr + v) * d + s) * d + t] : Tc(0);
   }
   __syncthreads();
   const int x = blockIdx.y;
@@ -104,11 +105,10 @@ void wmap_r2l_kernel(const Tin* __restrict__ Y, const Tc* __restrict__ Wg, Tout*
     }
   }
   for (int o = 0; o < nOut; ++o) {
-    const Tc* wrow = sW + o * K;
+    const Tc* wrow = sW + o * MAXK;
     Tc acc = 0;
 #pragma unroll
-    for (int k = 0; k < MAXK; ++k)
-      if (k < K) acc += wrow[k] * in[k];
+    for (int k = 0; k < MAXK; ++k) acc += wrow[k] * in[k];
     const int w = o / d, s = o - w * d;
     Z[((long)(w * ml + x) * d + s) * mr + b] = Cvt<Tout>::st(acc);
   }
@@ -160,15 +160,18 @@ void wmap_l2r_t(Ctx* c, const void* T1, const void* W, void* out, long ld_out, i
                 int mr, int wl, int wr, double alpha) {
   const int K = wl * d;
   dim3 grid((mr + kThreads - 1) / kThreads, ml);
-  size_t sh = sizeof(Tc) * (size_t)K * d * wr;
-  auto args = [&](auto kern) {
+  auto args = [&](auto kern, int maxk) {
+    const size_t sh = sizeof(Tc) * (size_t)maxk * d * wr;
     hipLaunchKernelGGL(kern, grid, dim3(kThreads), sh, c->stream, (const Tin*)T1, (const Tc*)W,
                        (Tout*)out, ld_out, ml, d, mr, wl, wr, (Tc)alpha);
   };
-  if (K <= 8 && d * wr <= 80) args(wmap_l2r_kernel<Tin, Tout, Tc, 8>);
-  else if (K <= 16 && d * wr <= 80) args(wmap_l2r_kernel<Tin, Tout, Tc, 16>);
-  else if (K <= 32 && d * wr <= 80) args(wmap_l2r_kernel<Tin, Tout, Tc, 32>);
-  else if (K <= 80 && d * wr <= 80) args(wmap_l2r_kernel<Tin, Tout, Tc, 80>);
+  const bool fits = d * wr <= 80;
+  if (fits && K <= 8) args(wmap_l2r_kernel<Tin, Tout, Tc, 8>, 8);
+  else if (fits && K <= 16) args(wmap_l2r_kernel<Tin, Tout, Tc, 16>, 16);
+  else if (fits && K <= 24) args(wmap_l2r_kernel<Tin, Tout, Tc, 24>, 24);
+  else if (fits && K <= 32) args(wmap_l2r_kernel<Tin, Tout, Tc, 32>, 32);
+  else if (fits && K <= 48) args(wmap_l2r_kernel<Tin, Tout, Tc, 48>, 48);
+  else if (fits && K <= 80) args(wmap_l2r_kernel<Tin, Tout, Tc, 80>, 80);
   else {
     const long n = (long)ml * d * wr * mr;
     hipLaunchKernelGGL((wmap_l2r_wide_kernel<Tin, Tout, Tc>), dim3((unsigned)((n + kThreads - 1) / kThreads)),
@@ -183,15 +186,18 @@ void wmap_r2l_t(Ctx* c, const void* Y, const void* W, void* Z, int ml, int d, in
                 int wr, double alpha) {
   const int K = d * wr;
   dim3 grid((mr + kThreads - 1) / kThreads, ml);
-  size_t sh = sizeof(Tc) * (size_t)K * d * wl;
-  auto args = [&](auto kern) {
+  auto args = [&](auto kern, int maxk) {
+    const size_t sh = sizeof(Tc) * (size_t)maxk * d * wl;
     hipLaunchKernelGGL(kern, grid, dim3(kThreads), sh, c->stream, (const Tin*)Y, (const Tc*)W,
                        (Tout*)Z, ml, d, mr, wl, wr, (Tc)alpha);
   };
-  if (K <= 8 && d * wl <= 80) args(wmap_r2l_kernel<Tin, Tout, Tc, 8>);
-  else if (K <= 16 && d * wl <= 80) args(wmap_r2l_kernel<Tin, Tout, Tc, 16>);
-  else if (K <= 32 && d * wl <= 80) args(wmap_r2l_kernel<Tin, Tout, Tc, 32>);
-  else if (K <= 80 && d * wl <= 80) args(wmap_r2l_kernel<Tin, Tout, Tc, 80>);
+  const bool fits = d * wl <= 80;
+  if (fits && K <= 8) args(wmap_r2l_kernel<Tin, Tout, Tc, 8>, 8);
+  else if (fits && K <= 16) args(wmap_r2l_kernel<Tin, Tout, Tc, 16>, 16);
+  else if (fits && K <= 24) args(wmap_r2l_kernel<Tin, Tout, Tc, 24>, 24);
+  else if (fits && K <= 32) args(wmap_r2l_kernel<Tin, Tout, Tc, 32>, 32);
+  else if (fits && K <= 48) args(wmap_r2l_kernel<Tin, Tout, Tc, 48>, 48);
+  else if (fits && K <= 80) args(wmap_r2l_kernel<Tin, Tout, Tc, 80>, 80);
   else {
     const long n = (long)wl * ml * d * mr;
     hipLaunchKernelGGL((wmap_r2l_wide_kernel<Tin, Tout, Tc>), dim3((unsigned)((n + kThreads - 1) / kThreads)),
