@@ -522,7 +522,7 @@ def main():
     ap.add_argument("--sweep-sched", type=str, default="128,256,512,1024,2048",
                     help="bond limits of the block sweep run (two sweeps each, then to convergence at the last)")
     ap.add_argument("--sweep-max", type=int, default=8, help="sweeps at the last bond limit")
-    ap.add_argument("--growth-tol", type=float, default=1e-8,
+    ap.add_argument("--growth-tol", type=float, default=1e-6,
                     help="eigensolver residual tolerance of the bond-growth sweeps of the Hubbard chain run")
     ap.add_argument("--dense-m", type=int, default=256, help="bond limit of the dense-vs-block one-sweep comparison")
     ap.add_argument("--cylinder", type=str, default="256,512,1024,2048,4096",
