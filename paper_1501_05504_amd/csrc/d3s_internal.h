@@ -155,6 +155,8 @@ void dot_f64(Ctx* c, const double* x, const double* y, long n, double* out_dev);
 void mdot_f64(Ctx* c, const double* V, long ldv, int k, const double* w, long n, double* coef_dev,
               const int* kdev = nullptr);
 // partial-sum count of the Gram-Schmidt kernels for vectors of length n (fixed by n)
+// partial sums per Gram-Schmidt pass: one per workgroup, at most kGsMaxBlocks
+constexpr int kGsMaxBlocks = 1024;
 int gs_blocks(long n);
 // fused second pass: w -= sum_j coef1_j V_j, then coef2 = V^T w (rows k or *kdev + 1, <= 64)
 void gs_second_pass(Ctx* c, const double* V, long ldv, int k, const int* kdev, const double* coef1, double* w,

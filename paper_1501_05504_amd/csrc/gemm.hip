@@ -12,8 +12,10 @@
 // MFMA k-slot permutation: an MFMA sums over its k slots, so any bijection
 // between slots and actual k is valid as long as A and B use the same one.
 // Lane group g = lane/16 takes the 32 contiguous bytes [32g, 32g+32) of the
-// LDS row for the whole BK tile and feeds them to consecutive MFMA steps.
-// Each lane therefore issues two 16-byte LDS reads per operand tile per BK.
+// LDS row for the whole BK tile and feeds them to consecutive MFMA steps,
+// read as register groups of 8 bytes (FP64, FP32) or 16 bytes (BF16) so that
+// each group can be refilled for the next tile as soon as its MFMAs issue
+// (the K-loop pipeline below).
 //
 // Output layout of the 16x16 MFMA blocks, lane l, accumulator r:
 //   FP32 / BF16 variants: D[4*(l/16) + r][l % 16]

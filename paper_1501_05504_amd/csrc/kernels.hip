@@ -4,6 +4,8 @@
 // mixed-precision path and the reduction of the W-adjoint.
 #include <algorithm>
 
+#include <type_traits>
+
 #include "d3s_internal.h"
 
 namespace d3s {
@@ -304,8 +306,23 @@ void dot_partial_kernel(const double* __restrict__ x, const double* __restrict__
 // coef-partials for up to KMAX rows at once: each thread keeps one running
 // sum per row over its grid-stride elements (w is read once), then every row
 // is reduced over the block; part[j * gridDim.x + block].
+// The row count of a Lanczos step is read from device memory, so the kernels
+// below branch once, uniformly, to a body compiled for the next multiple of
+// eight rows (rows past the last one are clamped to it and weighted by
+// zero): every load of an element's rows is issued without a test, so a
+// wave keeps many loads in flight.
+template <int R>
+__device__ __forceinline__ void mdot_rows(const double* __restrict__ Vj, long ldv, int kc,
+                                          const double* __restrict__ w, long n, double* acc) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double wi = w[i];
+#pragma unroll
+    for (int j = 0; j < R; ++j) acc[j] += Vj[(long)min(j, kc - 1) * ldv + i] * wi;
+  }
+}
+
 template <int KMAX>
-__global__ __launch_bounds__(kThreads)
+__global__ __launch_bounds__(kThreads, 2)
 void mdot_partial_kernel(const double* __restrict__ V, long ldv, int k, const int* __restrict__ kdev, int j0,
                          const double* __restrict__ w, long n, double* __restrict__ part) {
   __shared__ double sh[kThreads / 64][KMAX];
@@ -317,11 +334,15 @@ void mdot_partial_kernel(const double* __restrict__ V, long ldv, int k, const in
   double acc[KMAX];
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) acc[j] = 0.0;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    const double wi = w[i];
-#pragma unroll
-    for (int j = 0; j < KMAX; ++j)
-      if (j < kc) acc[j] += Vj[(long)j * ldv + i] * wi;
+  switch ((kc + 7) / 8) {
+    case 1: mdot_rows<(KMAX < 8 ? KMAX : 8)>(Vj, ldv, kc, w, n, acc); break;
+    case 2: if constexpr (KMAX >= 16) mdot_rows<16>(Vj, ldv, kc, w, n, acc); break;
+    case 3: if constexpr (KMAX >= 24) mdot_rows<24>(Vj, ldv, kc, w, n, acc); break;
+    case 4: if constexpr (KMAX >= 32) mdot_rows<32>(Vj, ldv, kc, w, n, acc); break;
+    case 5: if constexpr (KMAX >= 40) mdot_rows<40>(Vj, ldv, kc, w, n, acc); break;
+    case 6: if constexpr (KMAX >= 48) mdot_rows<48>(Vj, ldv, kc, w, n, acc); break;
+    case 7: if constexpr (KMAX >= 56) mdot_rows<56>(Vj, ldv, kc, w, n, acc); break;
+    default: if constexpr (KMAX >= 64) mdot_rows<64>(Vj, ldv, kc, w, n, acc); break;
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -343,8 +364,26 @@ void mdot_partial_kernel(const double* __restrict__ V, long ldv, int k, const in
 // Second Gram-Schmidt pass fused with the first one's update: with
 // c = -coef (the first pass's coefficients), w <- w + sum_j c_j V_j, and the
 // partial sums of <V_j, w_new> for the second pass, reading every V_j once.
+template <int R>
+__device__ __forceinline__ void gs_update_dot_rows(const double* __restrict__ V, long ldv, int rows,
+                                                   const double* sc, double* __restrict__ w, long n,
+                                                   double* acc) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    double v[R];
+    double x = w[i];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      v[j] = V[(long)min(j, rows - 1) * ldv + i];
+      x += sc[j] * v[j];
+    }
+    w[i] = x;
+#pragma unroll
+    for (int j = 0; j < R; ++j) acc[j] += v[j] * x;
+  }
+}
+
 template <int KMAX>
-__global__ __launch_bounds__(kThreads)
+__global__ __launch_bounds__(kThreads, 2)
 void gs_update_dot_kernel(const double* __restrict__ V, long ldv, int k, const int* __restrict__ kdev,
                           const double* __restrict__ coef, double* __restrict__ w, long n,
                           double* __restrict__ part) {
@@ -356,19 +395,15 @@ void gs_update_dot_kernel(const double* __restrict__ V, long ldv, int k, const i
   double acc[KMAX];
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) acc[j] = 0.0;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    double v[KMAX];
-    double x = w[i];
-#pragma unroll
-    for (int j = 0; j < KMAX; ++j)
-      if (j < rows) {
-        v[j] = V[(long)j * ldv + i];
-        x += sc[j] * v[j];
-      }
-    w[i] = x;
-#pragma unroll
-    for (int j = 0; j < KMAX; ++j)
-      if (j < rows) acc[j] += v[j] * x;
+  switch ((rows + 7) / 8) {
+    case 1: gs_update_dot_rows<8>(V, ldv, rows, sc, w, n, acc); break;
+    case 2: gs_update_dot_rows<16>(V, ldv, rows, sc, w, n, acc); break;
+    case 3: if constexpr (KMAX >= 24) gs_update_dot_rows<24>(V, ldv, rows, sc, w, n, acc); break;
+    case 4: if constexpr (KMAX >= 32) gs_update_dot_rows<32>(V, ldv, rows, sc, w, n, acc); break;
+    case 5: if constexpr (KMAX >= 40) gs_update_dot_rows<40>(V, ldv, rows, sc, w, n, acc); break;
+    case 6: if constexpr (KMAX >= 48) gs_update_dot_rows<48>(V, ldv, rows, sc, w, n, acc); break;
+    case 7: if constexpr (KMAX >= 56) gs_update_dot_rows<56>(V, ldv, rows, sc, w, n, acc); break;
+    default: if constexpr (KMAX >= 64) gs_update_dot_rows<64>(V, ldv, rows, sc, w, n, acc); break;
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -389,21 +424,50 @@ void gs_update_dot_kernel(const double* __restrict__ V, long ldv, int k, const i
 
 // Second pass update fused with the norm: w <- w - sum_j coef_j V_j and the
 // per-block partial sums of |w_new|^2 (part[block]).
-__global__ __launch_bounds__(kThreads)
+__global__ __launch_bounds__(kThreads, 2)
 void gs_update_norm_kernel(const double* __restrict__ V, long ldv, int k, const int* __restrict__ kdev,
                            const double* __restrict__ coef, double* __restrict__ w, long n,
                            double* __restrict__ part) {
   __shared__ double sc[128];
   __shared__ double sh[kThreads / 64];
   const int rows = kdev ? (*kdev + 1) : k;
-  for (int j = threadIdx.x; j < rows; j += blockDim.x) sc[j] = -coef[j];
+  for (int j = threadIdx.x; j < 128; j += blockDim.x) sc[j] = (j < rows) ? -coef[j] : 0.0;
   __syncthreads();
   double acc = 0.0;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    double x = w[i];
-    for (int j = 0; j < rows; ++j) x += sc[j] * V[(long)j * ldv + i];
-    w[i] = x;
-    acc += x * x;
+  // rows in chunks of 8 (runtime count R/8): loads within a chunk are
+  // issued together, and the register use stays bounded for any R
+  auto pass = [&](auto rt) {
+    constexpr int R = decltype(rt)::value;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+      double x = w[i];
+#pragma unroll 2
+      for (int jc = 0; jc < R; jc += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = V[(long)min(jc + u, rows - 1) * ldv + i];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x += sc[jc + u] * v[u];
+      }
+      w[i] = x;
+      acc += x * x;
+    }
+  };
+  switch ((rows + 7) / 8) {
+    case 1: pass(std::integral_constant<int, 8>()); break;
+    case 2: pass(std::integral_constant<int, 16>()); break;
+    case 3: pass(std::integral_constant<int, 24>()); break;
+    case 4: pass(std::integral_constant<int, 32>()); break;
+    case 5: pass(std::integral_constant<int, 40>()); break;
+    case 6: pass(std::integral_constant<int, 48>()); break;
+    case 7: pass(std::integral_constant<int, 56>()); break;
+    case 8: pass(std::integral_constant<int, 64>()); break;
+    default:
+      for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        double x = w[i];
+        for (int j = 0; j < rows; ++j) x += sc[j] * V[(long)j * ldv + i];
+        w[i] = x;
+        acc += x * x;
+      }
   }
   const double t = block_sum(acc, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = t;
@@ -420,11 +484,11 @@ void lanczos_tail_kernel(const double* __restrict__ w, long n, const double* __r
   if (kdev) k = *kdev;
   // |w|^2 from the per-block partials, summed in a fixed order by every block
   __shared__ double sb;
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int q = 0; q < nnp; ++q) t += npart[q];
-    sb = t;
-  }
+  __shared__ double sh[kThreads / 64];
+  double part = 0.0;
+  for (int q = threadIdx.x; q < nnp; q += blockDim.x) part += npart[q];
+  const double tot = block_sum(part, sh);
+  if (threadIdx.x == 0) sb = tot;
   __syncthreads();
   const double b = sqrt(fmax(sb, 0.0));
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -628,7 +692,7 @@ void mdot_f64(Ctx* c, const double* V, long ldv, int k, const double* w, long n,
               const int* kdev) {
   if (k <= 0) return;
   if (k > 128) throw Error{D3S_EINVAL, "mdot: more than 128 vectors"};
-  // partial count fixed by n (deterministic), at most 256
+  // partial count fixed by n (deterministic), at most kGsMaxBlocks
   const int nb = gs_blocks(n);
   double* part = (double*)ws_get(c, WS_RED, sizeof(double) * (size_t)nb * 128);
   for (int j0 = 0; j0 < k; j0 += 64) {
@@ -646,7 +710,7 @@ void mdot_f64(Ctx* c, const double* V, long ldv, int k, const double* w, long n,
 }
 
 int gs_blocks(long n) {
-  return (int)std::max<long>(1, std::min<long>(256, (n + 8L * kThreads - 1) / (8L * kThreads)));
+  return (int)std::max<long>(1, std::min<long>(kGsMaxBlocks, (n + 4L * kThreads - 1) / (4L * kThreads)));
 }
 
 void gs_second_pass(Ctx* c, const double* V, long ldv, int k, const int* kdev, const double* coef1, double* w,
@@ -659,7 +723,9 @@ void gs_second_pass(Ctx* c, const double* V, long ldv, int k, const int* kdev, c
     hipLaunchKernelGGL(kern, dim3(nb), dim3(kThreads), 0, c->stream, V, ldv, k, kdev, coef1, w, n, part);
   };
   if (k <= 16) go(gs_update_dot_kernel<16>);
+  else if (k <= 24) go(gs_update_dot_kernel<24>);
   else if (k <= 32) go(gs_update_dot_kernel<32>);
+  else if (k <= 40) go(gs_update_dot_kernel<40>);
   else if (k <= 48) go(gs_update_dot_kernel<48>);
   else go(gs_update_dot_kernel<64>);
   hipLaunchKernelGGL(reduce_rows_kernel, dim3(k), dim3(kThreads), 0, c->stream, part, nb, coef2, kdev);

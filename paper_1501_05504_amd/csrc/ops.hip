@@ -668,7 +668,7 @@ LanczosResult lanczos_core(Ctx* c, Matvec& mv, double* x, long n, double tol, in
   }
   scale_f64(c, x, n, 1.0 / std::sqrt(nrm2));
   copy_f64(c, x, V, n);
-  double* npart = (double*)ws_get(c, WS_GS_NORM, sizeof(double) * 256);
+  double* npart = (double*)ws_get(c, WS_GS_NORM, sizeof(double) * kGsMaxBlocks);
   auto body = [&]() {
     copy_row_f64(c, V, n, kdev, xin);
     mv.product(xin, w, use_f64);
