@@ -242,9 +242,11 @@ void wmap_blocks_kernel(const Tin* __restrict__ in, const Tc* __restrict__ Wg, T
     sOutW[i] = ents[tk.idx0 + nin + i].wp;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < nin * nout; i += blockDim.x) {
-    const int o = i / nin, k = i - o * nin;
-    sW[o * MAXK + k] = alpha * Wg[sInW[k] + sOutW[o]];
+  // W rows zero-padded to MAXK, input rows past nin clamped to the last one:
+  // the loads and the inner loop carry no bounds tests
+  for (int i = threadIdx.x; i < nout * MAXK; i += blockDim.x) {
+    const int o = i / MAXK, k = i - o * MAXK;
+    sW[i] = (k < nin) ? alpha * Wg[sInW[k] + sOutW[o]] : Tc(0);
   }
   __syncthreads();
   const long e = (long)((int)blockIdx.x - tk.chunk0) * blockDim.x + threadIdx.x;
@@ -252,15 +254,17 @@ void wmap_blocks_kernel(const Tin* __restrict__ in, const Tc* __restrict__ Wg, T
   const long a = tk.i_off + e / tk.dj, y = tk.j_off + e % tk.dj;
   const Tin* src = in + a * in_rs + y;
   Tout* dst = out + a * out_rs + y;
+  if (nin == 0) {
+    for (int o = 0; o < nout; ++o) dst[sOutOff[o]] = Cvt<Tout>::st(Tc(0));
+    return;
+  }
   Tc v[MAXK];
 #pragma unroll
-  for (int k = 0; k < MAXK; ++k)
-    if (k < nin) v[k] = (Tc)Cvt<Tin>::ld(src[sInOff[k]]);
+  for (int k = 0; k < MAXK; ++k) v[k] = (Tc)Cvt<Tin>::ld(src[sInOff[min(k, nin - 1)]]);
   for (int o = 0; o < nout; ++o) {
     Tc acc = 0;
 #pragma unroll
-    for (int k = 0; k < MAXK; ++k)
-      if (k < nin) acc += sW[o * MAXK + k] * v[k];
+    for (int k = 0; k < MAXK; ++k) acc += sW[o * MAXK + k] * v[k];
     dst[sOutOff[o]] = Cvt<Tout>::st(acc);
   }
 }
@@ -272,8 +276,11 @@ void wmap_blocks_t(Ctx* c, const void* in, const void* W, void* out, const WmapP
     hipLaunchKernelGGL(kern, grid, block, 0, c->stream, (const Tin*)in, (const Tc*)W, (Tout*)out, w.d_tasks,
                        (int)w.tasks.size(), w.d_ents, w.in_rs, w.out_rs, (Tc)alpha);
   };
-  if (w.maxk <= 16) go(wmap_blocks_kernel<Tin, Tout, Tc, 16>);
+  if (w.maxk <= 8) go(wmap_blocks_kernel<Tin, Tout, Tc, 8>);
+  else if (w.maxk <= 16) go(wmap_blocks_kernel<Tin, Tout, Tc, 16>);
+  else if (w.maxk <= 24) go(wmap_blocks_kernel<Tin, Tout, Tc, 24>);
   else if (w.maxk <= 32) go(wmap_blocks_kernel<Tin, Tout, Tc, 32>);
+  else if (w.maxk <= 48) go(wmap_blocks_kernel<Tin, Tout, Tc, 48>);
   else if (w.maxk <= 80) go(wmap_blocks_kernel<Tin, Tout, Tc, 80>);
   else throw Error{D3S_EINVAL, "block W-map: more than 80 channel pairs"};
   D3S_HIP(hipGetLastError());
