@@ -226,7 +226,9 @@ class Context:
         self._check(_synchronize(self.h))
 
     def set_tile_config(self, cfg):
-        self._check(_set_tile_config(self.h, cfg))
+        """-1 size rule (default); 0: 128x128 (4 waves), 1: 64x64, 2: 256x128
+        (8 waves), 3: 128x128 (8 waves), 4: 256x128 (4 waves; FP32/BF16)."""
+        self._check(_set_tile_config(self.h, int(cfg)))
 
     def set_autotune(self, enable, cache_path=None):
         self._check(_set_autotune(self.h, 1 if enable else 0,
