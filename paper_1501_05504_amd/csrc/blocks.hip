@@ -326,11 +326,15 @@ void build_block_heff(Ctx* c, BlockHeff& h, const Sectors& left, const Sectors& 
       h.npacked += (long)left.dim[i] * right.dim[j];
     }
   h.g1 = GroupedPlan();
+  h.g1t = GroupedPlan();
   h.g2 = GroupedPlan();
   int qq[4];
-  // GEMM-1: T1[(a,w),(t,y)] = sum_x L[(a,w),x] psi[x,(t,y)]
+  // GEMM-1: T1[(a,w),(t,y)] = sum_x L[(a,w),x] psi[x,(t,y)]; g1t reads the
+  // block-transposed psi (block (x-sector, t) at poff, dim_y rows of length dim_x)
   h.g1.a_kc = true;
   h.g1.b_kc = false;
+  h.g1t.a_kc = true;
+  h.g1t.b_kc = true;
   for (int i = 0; i < left.n; ++i)
     for (int w = 0; w < wl; ++w) {
       for (int k = 0; k < nq; ++k) qq[k] = left.q[(size_t)i * nq + k] - wql[w * nq + k];
@@ -355,8 +359,34 @@ void build_block_heff(Ctx* c, BlockHeff& h, const Sectors& left, const Sectors& 
         tk.ldc = (long)wl * d * mr;
         h.g1.segs.push_back(sg);
         h.g1.tasks.push_back(tk);
+        sg.b_off = h.poff[(size_t)ip * d + t];
+        sg.ldb = left.dim[ip];
+        h.g1t.segs.push_back(sg);
+        h.g1t.tasks.push_back(tk);
       }
     }
+  // tiles of the block transpose psi -> psi^T
+  {
+    std::vector<TrTile> trt;
+    for (int i = 0; i < left.n; ++i)
+      for (int t = 0; t < d; ++t) {
+        const int j = right_of(h, i, t);
+        if (j < 0) continue;
+        const long src = psi_off(h, i, t, j), dst = h.poff[(size_t)i * d + t];
+        const int R = left.dim[i], C = right.dim[j];
+        const int sld = (int)psi_ld(h, j);
+        for (int r0 = 0; r0 < R; r0 += 32)
+          for (int c0 = 0; c0 < C; c0 += 32)
+            trt.push_back(TrTile{src + (long)r0 * sld + c0, dst + (long)c0 * R + r0, sld, R, std::min(32, R - r0),
+                                 std::min(32, C - c0)});
+      }
+    h.ntrt = (int)trt.size();
+    if (!trt.empty()) {
+      D3S_HIP(hipMalloc((void**)&h.d_trt, sizeof(TrTile) * trt.size()));
+      D3S_HIP(hipMemcpyAsync(h.d_trt, trt.data(), sizeof(TrTile) * trt.size(), hipMemcpyHostToDevice, c->stream));
+      D3S_HIP(hipStreamSynchronize(c->stream));
+    }
+  }
   // GEMM-2: out[(a,s), b] = sum_{v,y} T2[(a,s),(v,y)] R[b,(v,y)]
   h.g2.a_kc = true;
   h.g2.b_kc = true;
@@ -428,6 +458,7 @@ void build_block_heff(Ctx* c, BlockHeff& h, const Sectors& left, const Sectors& 
   const size_t nL = (size_t)ml * wl * ml, nP = (size_t)ml * d * mr, nR = (size_t)mr * wr * mr;
   const size_t nT = (size_t)ml * std::max(wl, wr) * d * mr;
   finalize_and_tune(c, h.g1, nL, nP, nT);
+  finalize_and_tune(c, h.g1t, nL, nP, nT);
   finalize_and_tune(c, h.g2, nT, nR, nP * h.g2_split);
   // flops of the allowed block products of the two GEMMs (the W-map is not counted)
   h.flops = h.g1.flops + h.g2.flops;
@@ -435,6 +466,10 @@ void build_block_heff(Ctx* c, BlockHeff& h, const Sectors& left, const Sectors& 
 
 void release_block_heff(BlockHeff& h) {
   grouped_release(h.g1);
+  grouped_release(h.g1t);
+  if (h.d_trt) (void)hipFree(h.d_trt);
+  h.d_trt = nullptr;
+  h.ntrt = 0;
   grouped_release(h.g2);
   grouped_release(h.g_el);
   grouped_release(h.g_y);
@@ -676,14 +711,25 @@ void op_update_env_blocks(Ctx* c, BlockHeff& h, d3s_dir dir, const double* env_i
 }
 
 // The launches of one block-sparse H_eff on stream s.
+// FP32 / BF16 products run GEMM-1 on the block-transposed psi (psiT, at
+// least npacked elements): a K-contiguous operand is staged into LDS with
+// 16-byte writes instead of one write per element.
+static bool uses_psit(const BlockHeff& h, d3s_prec p) { return p != D3S_F64 && h.ntrt > 0; }
+
 static void enqueue_block_heff(Ctx* c, hipStream_t s, const BlockHeff& h, d3s_prec p, const void* L, const void* W,
-                               const void* R, const void* psi, void* out, void* T1, void* T2, void* part) {
+                               const void* R, const void* psi, void* out, void* T1, void* T2, void* part,
+                               void* psiT) {
   hipStream_t keep = c->stream;
   c->stream = s;
   const size_t osz = (p == D3S_F64) ? 8 : 4;
   // only allowed blocks of T1 / T2 are written and read, so they need no clearing;
   // the output's forbidden blocks are cleared
-  grouped_gemm(c, p, h.g1, L, psi, T1, 1.0);
+  if (uses_psit(h, p)) {
+    transpose_tiles(c, p == D3S_F64 ? 8 : (p == D3S_F32 ? 4 : 2), psi, psiT, h.d_trt, h.ntrt);
+    grouped_gemm(c, p, h.g1t, L, psiT, T1, 1.0);
+  } else {
+    grouped_gemm(c, p, h.g1, L, psi, T1, 1.0);
+  }
   wmap_blocks(c, p, T1, W, T2, h.wm, 1.0);
   // packed outputs have no forbidden entries; dense ones are cleared first
   if (!h.packed) zero_bytes(c, out, osz * (size_t)h.ml * h.d * h.mr);
@@ -703,16 +749,17 @@ void op_apply_heff_blocks(Ctx* c, BlockHeff& h, d3s_prec p, const void* L, const
   void* T1 = ws_get(c, WS_T1, tsz * (size_t)h.ml * h.wl * h.d * h.mr);
   void* T2 = ws_get(c, WS_T2, t2sz * (size_t)h.ml * h.d * h.wr * h.mr);
   void* part = (h.g2_split > 1) ? ws_get(c, WS_G2_PART, tsz * (size_t)h.g2_split * h.npacked) : nullptr;
+  void* psiT = uses_psit(h, p) ? ws_get(c, WS_PSIT, t2sz * (size_t)h.npacked) : nullptr;
   if (!use_graph) {
-    enqueue_block_heff(c, c->stream, h, p, L, W, R, psi, out, T1, T2, part);
+    enqueue_block_heff(c, c->stream, h, p, L, W, R, psi, out, T1, T2, part, psiT);
     return;
   }
   // One hipGraph per (plan, buffers): captured on a private stream on first
   // use, replayed afterwards; events order it after / before the context's
   // stream work.
-  const void* key[8] = {L, W, R, psi, out, T1, T2, part};
+  const void* key[9] = {L, W, R, psi, out, T1, T2, part, psiT};
   bool same = h.graph_exec != nullptr && h.graph_prec == (int)p;
-  for (int i = 0; i < 8 && same; ++i) same = (h.graph_key[i] == key[i]);
+  for (int i = 0; i < 9 && same; ++i) same = (h.graph_key[i] == key[i]);
   if (!h.cap_stream) {
     hipStream_t cs;
     D3S_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -730,7 +777,7 @@ void op_apply_heff_blocks(Ctx* c, BlockHeff& h, d3s_prec p, const void* L, const
     h.graph_exec = h.graph = nullptr;
     D3S_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     try {
-      enqueue_block_heff(c, cs, h, p, L, W, R, psi, out, T1, T2, part);
+      enqueue_block_heff(c, cs, h, p, L, W, R, psi, out, T1, T2, part, psiT);
     } catch (...) {
       hipGraph_t g;
       (void)hipStreamEndCapture(cs, &g);
@@ -743,7 +790,7 @@ void op_apply_heff_blocks(Ctx* c, BlockHeff& h, d3s_prec p, const void* L, const
     hipGraphExec_t ge;
     D3S_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
     h.graph_exec = ge;
-    for (int i = 0; i < 8; ++i) h.graph_key[i] = key[i];
+    for (int i = 0; i < 9; ++i) h.graph_key[i] = key[i];
     h.graph_prec = (int)p;
   }
   D3S_HIP(hipEventRecord((hipEvent_t)h.ev_in, c->stream));

@@ -263,6 +263,11 @@ struct EnvPack {
 EnvPack build_envpack(const Sectors& s, const int* wq, int w);
 
 // Grouped-GEMM plans of one block-sparse H_eff (and its captured graph).
+// One tile (at most 32 x 32) of a batched block transpose:
+// out[dst + c*dst_ld + r] = in[src + r*src_ld + c] for r < rows, c < cols.
+struct TrTile { long src, dst; int src_ld, dst_ld, rows, cols; };
+void transpose_tiles(Ctx* c, int esz, const void* in, void* out, const TrTile* tiles, int ntiles);
+
 struct BlockHeff {
   int ml = 0, mr = 0, d = 0, wl = 0, wr = 0;
   Sectors left, right;                   // the bonds the plan was built for
@@ -277,6 +282,12 @@ struct BlockHeff {
   bool penv = false;
   EnvPack epl, epr;
   GroupedPlan g1, g2;                    // H_eff: GEMM-1 and GEMM-2
+  // GEMM-1 on the block-transposed psi (K-contiguous B operand: block (i, t)
+  // stored dim_j x dim_i at poff), used for FP32 / BF16 products; the tiles
+  // of the block transpose (device table)
+  GroupedPlan g1t;
+  TrTile* d_trt = nullptr;
+  int ntrt = 0;
   int g2_split = 1;                      // GEMM-2 split-K factor (packed outputs)
   WmapPlan wm;                           // H_eff: T1 -> T2
   // built on first use:
@@ -292,7 +303,7 @@ struct BlockHeff {
   void* cap_stream = nullptr;
   void* ev_in = nullptr;
   void* ev_out = nullptr;
-  const void* graph_key[8] = {};
+  const void* graph_key[9] = {};
   int graph_prec = -1;
 };
 void build_block_heff(Ctx* c, BlockHeff& h, const Sectors& left, const Sectors& right, int d, int wl, int wr,

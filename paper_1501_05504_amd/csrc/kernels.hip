@@ -621,6 +621,20 @@ __global__ void transpose_kernel(const T* __restrict__ in, long R, long C, T* __
   }
 }
 
+// One 32 x 32 tile per workgroup, staged through LDS so that both the
+// reads and the writes run along rows.
+template <typename T>
+__global__ void transpose_tiles_kernel(const T* __restrict__ in, T* __restrict__ out,
+                                       const TrTile* __restrict__ tiles) {
+  __shared__ T tile[32][33];
+  const TrTile t = tiles[blockIdx.x];
+  for (int i = threadIdx.y; i < t.rows; i += blockDim.y)
+    if ((int)threadIdx.x < t.cols) tile[i][threadIdx.x] = in[t.src + (long)i * t.src_ld + threadIdx.x];
+  __syncthreads();
+  for (int i = threadIdx.y; i < t.cols; i += blockDim.y)
+    if ((int)threadIdx.x < t.rows) out[t.dst + (long)i * t.dst_ld + threadIdx.x] = tile[threadIdx.x][i];
+}
+
 __global__ void copy2d_kernel(const double* __restrict__ src, long lds, double* __restrict__ dst, long ldd,
                               long rows, long cols) {
   const long total = rows * cols;
@@ -990,6 +1004,20 @@ void transpose_any(Ctx* c, int esz, const void* in, long R, long C, void* out) {
   else
     hipLaunchKernelGGL(transpose_kernel<unsigned short>, grid, dim3(32, 8), 0, c->stream,
                        (const unsigned short*)in, R, C, (unsigned short*)out);
+  D3S_HIP(hipGetLastError());
+}
+
+void transpose_tiles(Ctx* c, int esz, const void* in, void* out, const TrTile* tiles, int ntiles) {
+  if (ntiles <= 0) return;
+  if (esz == 8)
+    hipLaunchKernelGGL(transpose_tiles_kernel<double>, dim3(ntiles), dim3(32, 8), 0, c->stream,
+                       (const double*)in, (double*)out, tiles);
+  else if (esz == 4)
+    hipLaunchKernelGGL(transpose_tiles_kernel<float>, dim3(ntiles), dim3(32, 8), 0, c->stream,
+                       (const float*)in, (float*)out, tiles);
+  else
+    hipLaunchKernelGGL(transpose_tiles_kernel<unsigned short>, dim3(ntiles), dim3(32, 8), 0, c->stream,
+                       (const unsigned short*)in, (unsigned short*)out, tiles);
   D3S_HIP(hipGetLastError());
 }
 

@@ -103,6 +103,32 @@ def test_block_heff_f32(ctx):
     plan.close()
 
 
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+@pytest.mark.parametrize("ml,mr,seed", [(40, 52, 11), (300, 257, 12)])
+def test_block_heff_low_precision_transposed_psi(ctx, prec, ml, mr, seed):
+    """FP32 / BF16 block products, whose first GEMM reads the block-transposed
+    psi, against the oracle on the rounded operands (FP32 3e-5; BF16 2e-2,
+    the intermediate T2 being rounded to 8 bits), eager and replayed from a
+    captured graph; the forbidden blocks stay zero."""
+    case = hubbard_block_case(ml, mr, seed)
+    t = torch.float32 if prec == "f32" else torch.bfloat16
+    Lt, Rt, pt = dev(case["L"], t), dev(case["R"], t), dev(case["psi"], t)
+    Wf = dev(case["W"], torch.float32)
+    ref = C.apply_heff(Lt.double().cpu().numpy(), Wf.double().cpu().numpy(), Rt.double().cpu().numpy(),
+                       pt.double().cpu().numpy())
+    plan = make_plan(ctx, case)
+    tol = 3e-5 if prec == "f32" else 2e-2
+    forbidden = case["mask"] == 0
+    for use_graph in (False, True, True):
+        out = torch.full(tuple(pt.shape), float("nan"), dtype=torch.float32, device=DEV)
+        plan.apply(Lt, Wf, Rt, pt, out, use_graph=use_graph)
+        torch.cuda.synchronize()
+        o = out.double().cpu().numpy()
+        assert rel_err(o, ref) < tol, use_graph
+        assert np.all(o[forbidden] == 0.0)
+    plan.close()
+
+
 def test_block_heff_graph_replays(ctx):
     """Captured once, replayed several times with eager work (and a changed
     input in place) between the replays; every replay equals the eager
