@@ -464,7 +464,108 @@ void build_block_heff(Ctx* c, BlockHeff& h, const Sectors& left, const Sectors& 
   h.flops = h.g1.flops + h.g2.flops;
 }
 
+namespace {
+
+// tiles of one block: real R x C (row stride sld) -> padded PR x PC (row
+// stride dld), zeros in the padding
+void add_rl_tiles(std::vector<RlTile>& v, long src, int sld, long dst, int dld, int R, int C, int PR, int PC) {
+  for (int r0 = 0; r0 < PR; r0 += 32)
+    for (int c0 = 0; c0 < PC; c0 += 32) {
+      RlTile t;
+      t.prows = std::min(32, PR - r0);
+      t.pcols = std::min(32, PC - c0);
+      t.rows = std::max(0, std::min(t.prows, R - r0));
+      t.cols = std::max(0, std::min(t.pcols, C - c0));
+      t.src = (t.rows > 0 && t.cols > 0) ? src + (long)r0 * sld + c0 : 0;
+      t.dst = dst + (long)r0 * dld + c0;
+      t.src_ld = sld;
+      t.dst_ld = dld;
+      v.push_back(t);
+    }
+}
+
+RlTile* upload_rl(Ctx* c, const std::vector<RlTile>& v) {
+  if (v.empty()) return nullptr;
+  RlTile* d = nullptr;
+  D3S_HIP(hipMalloc((void**)&d, sizeof(RlTile) * v.size()));
+  D3S_HIP(hipMemcpyAsync(d, v.data(), sizeof(RlTile) * v.size(), hipMemcpyHostToDevice, c->stream));
+  D3S_HIP(hipStreamSynchronize(c->stream));
+  return d;
+}
+
+Sectors padded_sectors(const Sectors& s) {
+  std::vector<int> pd(s.dim);
+  for (int& x : pd) x = (x + 7) / 8 * 8;
+  return Sectors(s.nq, s.n, s.q.data(), pd.data());
+}
+
+}  // namespace
+
+LowpTwin& ensure_lowp(Ctx* c, BlockHeff& h) {
+  if (h.padded) throw Error{D3S_EINVAL, "blocks: a padded plan has no twin"};
+  if (h.lp) return *h.lp;
+  LowpTwin* tw = new LowpTwin();
+  try {
+    const Sectors pl = padded_sectors(h.left), pr = padded_sectors(h.right);
+    const int nq = h.left.nq;
+    build_block_heff(c, tw->h, pl, pr, h.d, h.wl, h.wr, h.pq.data(), h.wql.data(), h.wqr.data(), true, true, true);
+    tw->h.padded = true;
+    const BlockHeff& t = tw->h;
+    std::vector<RlTile> vl, vr, vx, vy;
+    int qq[4];
+    for (int i = 0; i < h.left.n; ++i)
+      for (int w = 0; w < h.wl; ++w) {
+        for (int k = 0; k < nq; ++k) qq[k] = h.left.q[(size_t)i * nq + k] - h.wql[w * nq + k];
+        const int ip = h.left.find(qq);
+        if (ip < 0) continue;
+        add_rl_tiles(vl, envl_off(h, i, w, ip), (int)envl_ld(h, ip), t.epl.off[(size_t)i * h.wl + w], pl.dim[ip],
+                     h.left.dim[i], h.left.dim[ip], pl.dim[i], pl.dim[ip]);
+      }
+    for (int j = 0; j < h.right.n; ++j)
+      for (int v = 0; v < h.wr; ++v) {
+        for (int k = 0; k < nq; ++k) qq[k] = h.right.q[(size_t)j * nq + k] - h.wqr[v * nq + k];
+        const int jp = h.right.find(qq);
+        if (jp < 0) continue;
+        add_rl_tiles(vr, envr_off(h, j, v, jp), (int)envr_ld(h, jp), t.epr.off[(size_t)j * h.wr + v], pr.dim[jp],
+                     h.right.dim[j], h.right.dim[jp], pr.dim[j], pr.dim[jp]);
+      }
+    for (int i = 0; i < h.left.n; ++i)
+      for (int s = 0; s < h.d; ++s) {
+        const int j = right_of(h, i, s);
+        if (j < 0) continue;
+        const long po = t.poff[(size_t)i * h.d + s];
+        add_rl_tiles(vx, psi_off(h, i, s, j), (int)psi_ld(h, j), po, pr.dim[j], h.left.dim[i], h.right.dim[j],
+                     pl.dim[i], pr.dim[j]);
+        add_rl_tiles(vy, po, pr.dim[j], psi_off(h, i, s, j), (int)psi_ld(h, j), h.left.dim[i], h.right.dim[j],
+                     h.left.dim[i], h.right.dim[j]);
+      }
+    tw->d_L = upload_rl(c, vl);
+    tw->d_R = upload_rl(c, vr);
+    tw->d_X = upload_rl(c, vx);
+    tw->d_Y = upload_rl(c, vy);
+    tw->nL = (int)vl.size();
+    tw->nR = (int)vr.size();
+    tw->nX = (int)vx.size();
+    tw->nY = (int)vy.size();
+  } catch (...) {
+    release_block_heff(tw->h);
+    for (RlTile* p : {tw->d_L, tw->d_R, tw->d_X, tw->d_Y})
+      if (p) (void)hipFree(p);
+    delete tw;
+    throw;
+  }
+  h.lp = tw;
+  return *tw;
+}
+
 void release_block_heff(BlockHeff& h) {
+  if (h.lp) {
+    release_block_heff(h.lp->h);
+    for (RlTile* p : {h.lp->d_L, h.lp->d_R, h.lp->d_X, h.lp->d_Y})
+      if (p) (void)hipFree(p);
+    delete h.lp;
+    h.lp = nullptr;
+  }
   grouped_release(h.g1);
   grouped_release(h.g1t);
   if (h.d_trt) (void)hipFree(h.d_trt);
@@ -744,6 +845,24 @@ static void enqueue_block_heff(Ctx* c, hipStream_t s, const BlockHeff& h, d3s_pr
 
 void op_apply_heff_blocks(Ctx* c, BlockHeff& h, d3s_prec p, const void* L, const void* W, const void* R,
                           const void* psi, void* out, bool use_graph) {
+  if (p != D3S_F64 && !h.padded) {
+    // operands of the plan's layouts, in the product's element type: moved
+    // into the padded twin's layouts, multiplied there, the product moved back
+    LowpTwin& tw = ensure_lowp(c, h);
+    const int kind = (p == D3S_F32) ? RL_F32 : RL_BF16;
+    const size_t esz = (p == D3S_F32) ? 4 : 2;
+    void* Lp = ws_get(c, WS_LP_L, esz * (size_t)plan_nl(tw.h));
+    void* Rp = ws_get(c, WS_LP_R, esz * (size_t)plan_nr(tw.h));
+    void* Xp = ws_get(c, WS_LP_X, esz * (size_t)tw.h.npacked);
+    float* Yp = (float*)ws_get(c, WS_LP_Y, 4 * (size_t)tw.h.npacked);
+    relayout_tiles(c, kind, kind, L, Lp, tw.d_L, tw.nL);
+    relayout_tiles(c, kind, kind, R, Rp, tw.d_R, tw.nR);
+    relayout_tiles(c, kind, kind, psi, Xp, tw.d_X, tw.nX);
+    op_apply_heff_blocks(c, tw.h, p, Lp, W, Rp, Xp, Yp, use_graph);
+    if (!h.packed) zero_bytes(c, out, 4 * (size_t)h.ml * h.d * h.mr);
+    relayout_tiles(c, RL_F32, RL_F32, Yp, out, tw.d_Y, tw.nY);
+    return;
+  }
   const size_t tsz = (p == D3S_F64) ? 8 : 4;
   const size_t t2sz = (p == D3S_F64) ? 8 : (p == D3S_F32 ? 4 : 2);
   void* T1 = ws_get(c, WS_T1, tsz * (size_t)h.ml * h.wl * h.d * h.mr);

@@ -37,7 +37,7 @@ struct Error {
 enum WsSlot {
   WS_T1 = 0, WS_T2, WS_LZ_V, WS_LZ_W, WS_LZ_COEF, WS_RED, WS_GRAM, WS_EIGVAL,
   WS_EIGTMP, WS_UKT, WS_X, WS_MT, WS_CAST_L, WS_CAST_R, WS_CAST_X, WS_CAST_Y,
-  WS_CAST_W, WS_REF, WS_PSI, WS_INFO, WS_NBR, WS_MISC, WS_SPLITK, WS_DESC, WS_BLK_X, WS_XPACK, WS_GPACK, WS_GVAL, WS_TUNE, WS_PK, WS_LZ_K, WS_GS_NORM, WS_JD_V, WS_JD_W, WS_JD_Z, WS_JD_COEF, WS_G2_PART, WS_W2, WS_RMET, WS_RZ, WS_RT, WS_RGRAM, WS_H2, WS_PSIT, WS_NSLOTS
+  WS_CAST_W, WS_REF, WS_PSI, WS_INFO, WS_NBR, WS_MISC, WS_SPLITK, WS_DESC, WS_BLK_X, WS_XPACK, WS_GPACK, WS_GVAL, WS_TUNE, WS_PK, WS_LZ_K, WS_GS_NORM, WS_JD_V, WS_JD_W, WS_JD_Z, WS_JD_COEF, WS_G2_PART, WS_W2, WS_RMET, WS_RZ, WS_RT, WS_RGRAM, WS_H2, WS_PSIT, WS_LP_L, WS_LP_R, WS_LP_X, WS_LP_Y, WS_NSLOTS
 };
 
 struct Ctx {
@@ -263,6 +263,15 @@ struct EnvPack {
 EnvPack build_envpack(const Sectors& s, const int* wq, int w);
 
 // Grouped-GEMM plans of one block-sparse H_eff (and its captured graph).
+// One tile (at most 32 x 32) of a block relayout: the destination tile
+// (prows x pcols at dst, row stride dst_ld) receives the source entries
+// (rows x cols at src, row stride src_ld) converted to its element type and
+// zeros in the rest.
+struct RlTile { long src, dst; int src_ld, dst_ld, rows, cols, prows, pcols; };
+enum { RL_F64 = 0, RL_F32 = 1, RL_BF16 = 2 };
+void relayout_tiles(Ctx* c, int in_kind, int out_kind, const void* in, void* out, const RlTile* tiles, int ntiles);
+struct LowpTwin;
+
 // One tile (at most 32 x 32) of a batched block transpose:
 // out[dst + c*dst_ld + r] = in[src + r*src_ld + c] for r < rows, c < cols.
 struct TrTile { long src, dst; int src_ld, dst_ld, rows, cols; };
@@ -288,6 +297,12 @@ struct BlockHeff {
   GroupedPlan g1t;
   TrTile* d_trt = nullptr;
   int ntrt = 0;
+  // FP32 / BF16 products run on a twin plan whose sector dimensions are
+  // rounded up to multiples of 8 (every block offset and row length a
+  // multiple of 16 bytes, so the GEMM operand loads are whole 16-byte
+  // vectors); built on first use; `padded` marks a twin
+  LowpTwin* lp = nullptr;
+  bool padded = false;
   int g2_split = 1;                      // GEMM-2 split-K factor (packed outputs)
   WmapPlan wm;                           // H_eff: T1 -> T2
   // built on first use:
@@ -306,6 +321,16 @@ struct BlockHeff {
   const void* graph_key[9] = {};
   int graph_prec = -1;
 };
+// The padded twin of a plan and the relayout tables between the plan's
+// layouts (dense or packed) and the twin's packed ones: L and R into the
+// twin's packed environments, psi into its packed blocks, and the product
+// back into the plan's psi layout.
+struct LowpTwin {
+  BlockHeff h;
+  RlTile *d_L = nullptr, *d_R = nullptr, *d_X = nullptr, *d_Y = nullptr;
+  int nL = 0, nR = 0, nX = 0, nY = 0;
+};
+LowpTwin& ensure_lowp(Ctx* c, BlockHeff& h);
 void build_block_heff(Ctx* c, BlockHeff& h, const Sectors& left, const Sectors& right, int d, int wl, int wr,
                       const int* phys_q, const int* wq_left, const int* wq_right, bool packed = false,
                       bool with_g2 = true, bool packed_env = false);

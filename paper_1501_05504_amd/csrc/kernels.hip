@@ -621,6 +621,27 @@ __global__ void transpose_kernel(const T* __restrict__ in, long R, long C, T* __
   }
 }
 
+template <typename Tin, typename Tout>
+__device__ __forceinline__ Tout rl_convert(Tin v) {
+  if constexpr (std::is_same<Tin, Tout>::value) return v;
+  else if constexpr (std::is_same<Tout, bf16_t>::value) return f32_to_bf16((float)v);
+  else return (Tout)v;
+}
+
+// One destination tile per workgroup (32 x 8 threads, rows along x).
+template <typename Tin, typename Tout>
+__global__ void relayout_tiles_kernel(const Tin* __restrict__ in, Tout* __restrict__ out,
+                                      const RlTile* __restrict__ tiles) {
+  const RlTile t = tiles[blockIdx.x];
+  const int x = threadIdx.x;
+  if (x >= t.pcols) return;
+  for (int i = threadIdx.y; i < t.prows; i += blockDim.y) {
+    Tout v = rl_convert<float, Tout>(0.0f);
+    if (i < t.rows && x < t.cols) v = rl_convert<Tin, Tout>(in[t.src + (long)i * t.src_ld + x]);
+    out[t.dst + (long)i * t.dst_ld + x] = v;
+  }
+}
+
 // One 32 x 32 tile per workgroup, staged through LDS so that both the
 // reads and the writes run along rows.
 template <typename T>
@@ -1018,6 +1039,30 @@ void transpose_tiles(Ctx* c, int esz, const void* in, void* out, const TrTile* t
   else
     hipLaunchKernelGGL(transpose_tiles_kernel<unsigned short>, dim3(ntiles), dim3(32, 8), 0, c->stream,
                        (const unsigned short*)in, (unsigned short*)out, tiles);
+  D3S_HIP(hipGetLastError());
+}
+
+void relayout_tiles(Ctx* c, int in_kind, int out_kind, const void* in, void* out, const RlTile* tiles,
+                    int ntiles) {
+  if (ntiles <= 0) return;
+  const dim3 g(ntiles), b(32, 8);
+  if (in_kind == RL_F64 && out_kind == RL_BF16)
+    hipLaunchKernelGGL((relayout_tiles_kernel<double, bf16_t>), g, b, 0, c->stream, (const double*)in, (bf16_t*)out,
+                       tiles);
+  else if (in_kind == RL_F64 && out_kind == RL_F32)
+    hipLaunchKernelGGL((relayout_tiles_kernel<double, float>), g, b, 0, c->stream, (const double*)in, (float*)out,
+                       tiles);
+  else if (in_kind == RL_F32 && out_kind == RL_F64)
+    hipLaunchKernelGGL((relayout_tiles_kernel<float, double>), g, b, 0, c->stream, (const float*)in, (double*)out,
+                       tiles);
+  else if (in_kind == RL_F32 && out_kind == RL_F32)
+    hipLaunchKernelGGL((relayout_tiles_kernel<float, float>), g, b, 0, c->stream, (const float*)in, (float*)out,
+                       tiles);
+  else if (in_kind == RL_BF16 && out_kind == RL_BF16)
+    hipLaunchKernelGGL((relayout_tiles_kernel<bf16_t, bf16_t>), g, b, 0, c->stream, (const bf16_t*)in,
+                       (bf16_t*)out, tiles);
+  else
+    throw Error{D3S_EINVAL, "relayout: unsupported element types"};
   D3S_HIP(hipGetLastError());
 }
 

@@ -581,6 +581,7 @@ struct Matvec {
   float* yout = nullptr;
   long n;
   BlockHeff* plan = nullptr;     // block-sparse products when set
+  LowpTwin* tw = nullptr;        // their low-precision products run on the plan's padded twin
   bool use_graph = false;
   long nl_ = 0, nr_ = 0;         // elements of L and R when not dense (packed block environments)
   void prepare() {
@@ -590,6 +591,21 @@ struct Matvec {
     float* Wf = (float*)ws_get(c, WS_CAST_W, 4 * nw);
     cast_f64_to_f32(c, W, Wf, nw);
     Wc = Wf;
+    if (plan) {
+      // L and R converted once into the twin's padded packed layouts
+      tw = &ensure_lowp(c, *plan);
+      const int kind = (p == D3S_F32) ? RL_F32 : RL_BF16;
+      const size_t esz = (p == D3S_F32) ? 4 : 2;
+      void* Lp = ws_get(c, WS_CAST_L, esz * (size_t)plan_nl(tw->h));
+      void* Rp = ws_get(c, WS_CAST_R, esz * (size_t)plan_nr(tw->h));
+      relayout_tiles(c, RL_F64, kind, L, Lp, tw->d_L, tw->nL);
+      relayout_tiles(c, RL_F64, kind, R, Rp, tw->d_R, tw->nR);
+      Lc = Lp;
+      Rc = Rp;
+      xin = ws_get(c, WS_CAST_X, esz * (size_t)tw->h.npacked);
+      yout = (float*)ws_get(c, WS_CAST_Y, 4 * (size_t)tw->h.npacked);
+      return;
+    }
     if (p == D3S_F32) {
       float* Lf = (float*)ws_get(c, WS_CAST_L, 4 * nl);
       float* Rf = (float*)ws_get(c, WS_CAST_R, 4 * nr);
@@ -617,10 +633,17 @@ struct Matvec {
       else op_apply_heff(c, D3S_F64, ml, d, mr, wl, wr, L, W, R, x, y);
       return;
     }
+    if (tw) {
+      relayout_tiles(c, RL_F64, p == D3S_F32 ? RL_F32 : RL_BF16, x, xin, tw->d_X, tw->nX);
+      op_apply_heff_blocks(c, tw->h, p, Lc, Wc, Rc, xin, yout, false);
+      // the dense layout's forbidden entries are not written by the relayout
+      if (!plan->packed) zero_bytes(c, y, sizeof(double) * (size_t)n);
+      relayout_tiles(c, RL_F32, RL_F64, yout, y, tw->d_Y, tw->nY);
+      return;
+    }
     if (p == D3S_F32) cast_f64_to_f32(c, x, (float*)xin, n);
     else cast_f64_to_bf16(c, x, (bf16_t*)xin, n);
-    if (plan) op_apply_heff_blocks(c, *plan, p, Lc, Wc, Rc, xin, yout, false);
-    else op_apply_heff(c, p, ml, d, mr, wl, wr, Lc, Wc, Rc, xin, yout);
+    op_apply_heff(c, p, ml, d, mr, wl, wr, Lc, Wc, Rc, xin, yout);
     cast_f32_to_f64(c, yout, y, n);
   }
 };
