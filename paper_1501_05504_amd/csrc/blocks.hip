@@ -248,7 +248,7 @@ void wmap_add(WmapPlan& w, int i_off, int di, int j_off, int dj, const std::vect
   t.nout = (int)outs.size();
   t.idx0 = (int)w.ents.size();
   t.chunk0 = w.chunks;
-  w.chunks += (int)(((long)di * dj + 255) / 256);
+  w.chunks += (int)(((long)di * dj + kWmapChunk - 1) / kWmapChunk);
   w.ents.insert(w.ents.end(), ins.begin(), ins.end());
   w.ents.insert(w.ents.end(), outs.begin(), outs.end());
   w.maxk = std::max(w.maxk, std::max(t.nin, t.nout));
@@ -261,6 +261,15 @@ void wmap_upload(Ctx* c, WmapPlan& w) {
   if (w.tasks.empty()) return;
   D3S_HIP(hipMalloc((void**)&w.d_tasks, sizeof(WmapTask) * w.tasks.size()));
   D3S_HIP(hipMalloc((void**)&w.d_ents, sizeof(WmapEnt) * std::max<size_t>(1, w.ents.size())));
+  std::vector<int> ct((size_t)w.chunks);
+  for (size_t t = 0; t < w.tasks.size(); ++t) {
+    const WmapTask& k = w.tasks[t];
+    const int n = (int)(((long)k.di * k.dj + kWmapChunk - 1) / kWmapChunk);
+    for (int q = 0; q < n; ++q) ct[(size_t)k.chunk0 + q] = (int)t;
+  }
+  D3S_HIP(hipMalloc((void**)&w.d_ctask, sizeof(int) * std::max<size_t>(1, ct.size())));
+  if (!ct.empty())
+    D3S_HIP(hipMemcpyAsync(w.d_ctask, ct.data(), sizeof(int) * ct.size(), hipMemcpyHostToDevice, c->stream));
   D3S_HIP(hipMemcpyAsync(w.d_tasks, w.tasks.data(), sizeof(WmapTask) * w.tasks.size(), hipMemcpyHostToDevice,
                          c->stream));
   if (!w.ents.empty())
@@ -272,6 +281,8 @@ void wmap_upload(Ctx* c, WmapPlan& w) {
 void wmap_release(WmapPlan& w) {
   if (w.d_tasks) (void)hipFree(w.d_tasks);
   if (w.d_ents) (void)hipFree(w.d_ents);
+  if (w.d_ctask) (void)hipFree(w.d_ctask);
+  w.d_ctask = nullptr;
   w.d_tasks = nullptr;
   w.d_ents = nullptr;
 }

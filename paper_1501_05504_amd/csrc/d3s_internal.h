@@ -132,11 +132,15 @@ void wmap_r2l(Ctx* c, d3s_prec p, const void* Y, const void* W, void* Z,
 // output entries; chunk0 = first 256-element chunk of the task.
 struct WmapTask { int i_off, di, j_off, dj, nin, nout, idx0, chunk0; };
 struct WmapEnt { long off; int wp, pad_; };
+// elements of a block W-map chunk (one workgroup of 256 threads, four
+// elements per thread)
+constexpr int kWmapChunk = 1024;
 struct WmapPlan {
   std::vector<WmapTask> tasks;
   std::vector<WmapEnt> ents;
   WmapTask* d_tasks = nullptr;
   WmapEnt* d_ents = nullptr;
+  int* d_ctask = nullptr;       // task of each chunk
   int chunks = 0, maxk = 1;
   long in_rs = 0, out_rs = 0;
 };

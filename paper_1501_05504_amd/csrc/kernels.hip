@@ -215,23 +215,20 @@ void wmap_r2l_t(Ctx* c, const void* Y, const void* W, void* Z, int ml, int d, in
 // element (a, y) of the D_i x D_j block
 //   out[a*out_rs + e_out.off + y] = alpha * sum_k W[e_in[k].wp + e_out.wp] * in[a*in_rs + e_in[k].off + y]
 // (the W index is the sum of the two partial indices).  Workgroups take
-// 256-element chunks of the block; the task's W sub-matrix sits in LDS.
-// Nothing outside the listed blocks is read or written.
+// chunks of kWmapChunk elements of a block (a per-chunk table names the
+// task), four per thread, 256 apart so that loads and stores stay
+// coalesced; the task's W sub-matrix sits in LDS.  Nothing outside the
+// listed blocks is read or written.
 template <typename Tin, typename Tout, typename Tc, int MAXK>
 __global__ __launch_bounds__(kThreads)
 void wmap_blocks_kernel(const Tin* __restrict__ in, const Tc* __restrict__ Wg, Tout* __restrict__ out,
-                        const WmapTask* __restrict__ tasks, int ntasks, const WmapEnt* __restrict__ ents,
-                        long in_rs, long out_rs, Tc alpha) {
+                        const WmapTask* __restrict__ tasks, const int* __restrict__ ctask,
+                        const WmapEnt* __restrict__ ents, long in_rs, long out_rs, Tc alpha) {
+  constexpr int EPT = kWmapChunk / kThreads;
   __shared__ Tc sW[MAXK * MAXK];
   __shared__ long sInOff[MAXK], sOutOff[MAXK];
   __shared__ int sInW[MAXK], sOutW[MAXK];
-  int lo = 0, hi = ntasks - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (tasks[mid].chunk0 <= (int)blockIdx.x) lo = mid;
-    else hi = mid - 1;
-  }
-  const WmapTask tk = tasks[lo];
+  const WmapTask tk = tasks[ctask[blockIdx.x]];
   const int nin = tk.nin, nout = tk.nout;
   for (int i = threadIdx.x; i < nin; i += blockDim.x) {
     sInOff[i] = ents[tk.idx0 + i].off;
@@ -249,23 +246,27 @@ void wmap_blocks_kernel(const Tin* __restrict__ in, const Tc* __restrict__ Wg, T
     sW[i] = (k < nin) ? alpha * Wg[sInW[k] + sOutW[o]] : Tc(0);
   }
   __syncthreads();
-  const long e = (long)((int)blockIdx.x - tk.chunk0) * blockDim.x + threadIdx.x;
-  if (e >= (long)tk.di * tk.dj) return;
-  const long a = tk.i_off + e / tk.dj, y = tk.j_off + e % tk.dj;
-  const Tin* src = in + a * in_rs + y;
-  Tout* dst = out + a * out_rs + y;
-  if (nin == 0) {
-    for (int o = 0; o < nout; ++o) dst[sOutOff[o]] = Cvt<Tout>::st(Tc(0));
-    return;
-  }
-  Tc v[MAXK];
+  const long n = (long)tk.di * tk.dj;
+  const long e0 = (long)((int)blockIdx.x - tk.chunk0) * kWmapChunk + threadIdx.x;
+  for (int r = 0; r < EPT; ++r) {
+    const long e = e0 + (long)r * kThreads;
+    if (e >= n) return;
+    const long a = tk.i_off + e / tk.dj, y = tk.j_off + e % tk.dj;
+    const Tin* src = in + a * in_rs + y;
+    Tout* dst = out + a * out_rs + y;
+    if (nin == 0) {
+      for (int o = 0; o < nout; ++o) dst[sOutOff[o]] = Cvt<Tout>::st(Tc(0));
+      continue;
+    }
+    Tc v[MAXK];
 #pragma unroll
-  for (int k = 0; k < MAXK; ++k) v[k] = (Tc)Cvt<Tin>::ld(src[sInOff[min(k, nin - 1)]]);
-  for (int o = 0; o < nout; ++o) {
-    Tc acc = 0;
+    for (int k = 0; k < MAXK; ++k) v[k] = (Tc)Cvt<Tin>::ld(src[sInOff[min(k, nin - 1)]]);
+    for (int o = 0; o < nout; ++o) {
+      Tc acc = 0;
 #pragma unroll
-    for (int k = 0; k < MAXK; ++k) acc += sW[o * MAXK + k] * v[k];
-    dst[sOutOff[o]] = Cvt<Tout>::st(acc);
+      for (int k = 0; k < MAXK; ++k) acc += sW[o * MAXK + k] * v[k];
+      dst[sOutOff[o]] = Cvt<Tout>::st(acc);
+    }
   }
 }
 
@@ -274,7 +275,7 @@ void wmap_blocks_t(Ctx* c, const void* in, const void* W, void* out, const WmapP
   dim3 grid((unsigned)w.chunks), block(kThreads);
   auto go = [&](auto kern) {
     hipLaunchKernelGGL(kern, grid, block, 0, c->stream, (const Tin*)in, (const Tc*)W, (Tout*)out, w.d_tasks,
-                       (int)w.tasks.size(), w.d_ents, w.in_rs, w.out_rs, (Tc)alpha);
+                       w.d_ctask, w.d_ents, w.in_rs, w.out_rs, (Tc)alpha);
   };
   if (w.maxk <= 8) go(wmap_blocks_kernel<Tin, Tout, Tc, 8>);
   else if (w.maxk <= 16) go(wmap_blocks_kernel<Tin, Tout, Tc, 16>);
