@@ -324,8 +324,8 @@ typedef struct {
 typedef struct d3s_block_plan_s* d3s_block_plan;
 
 /* Plan the block-sparse H_eff of one site (the paper uses U(1) symmetries
- * throughout Sec. 7 without describing the blocks; see DESIGN notes in the
- * source for the rules).  Tensors keep the dense layouts above with bond
+ * throughout Sec. 7 without describing the blocks; the block rules are the
+ * charge-conservation conditions stated here).  Tensors keep the dense layouts above with bond
  * states ordered by sector; psi must vanish outside q_a + q_s = q_b, L outside
  * q_a - q_x = Delta_w and R outside q_b - q_y = Delta_v, where phys_q (d*nq)
  * are the physical charges and wq_left (w_l*nq) / wq_right (w_r*nq) the MPO
@@ -343,7 +343,12 @@ void d3s_block_plan_destroy(d3s_ctx ctx, d3s_block_plan plan);
  * symmetric inputs, computing only the allowed blocks; `out` is zero outside
  * the allowed blocks.  use_graph != 0 captures the launches into a hipGraph
  * on first use with these buffers and replays it afterwards (ordered after /
- * before the context's stream by events).  Asynchronous. */
+ * before the context's stream by events).  FP32 / BF16 products copy L, R
+ * and psi into internal buffers laid out over the sectors with their
+ * dimensions rounded up to multiples of 8 (zero-filled, so every block is
+ * 16-byte aligned), multiply there and copy the product back; the plan
+ * builds the tables of that padded layout on the first such call, which
+ * therefore synchronises.  Asynchronous otherwise. */
 d3s_status d3s_apply_heff_blocks(d3s_ctx ctx, d3s_block_plan plan, d3s_prec prec, const void* L,
                                  const void* W, const void* R, const void* psi, void* out, int use_graph);
 
