@@ -467,7 +467,7 @@ d3s_status d3s_prepare(d3s_ctx ctx, d3s_state* state, double* energy);
 
 /* One full sweep: right-to-left over sites l-1..1, then left-to-right over
  * sites 0..l-2, every site update being steps 1-8 of Sec. 5 with the
- * alpha rule of Sec. 6 (see DESIGN notes in the source for the readings).
+ * alpha rule of Sec. 6 when adaptive_alpha is set.
  * Requires the centre on site l-1 (as left by d3s_prepare or a previous
  * sweep).  Synchronises. */
 d3s_status d3s_sweep(d3s_ctx ctx, d3s_state* state, d3s_sweep_params* params,

@@ -311,7 +311,7 @@ def test_heff_grad_W(ctx):
 
 
 def test_sweep_heisenberg12_exact_bond(ctx):
-    """BASELINE configuration 1 with m = 64 (exact): the GPU DMRG3S energy
+    """The l = 12 Heisenberg chain with m = 64 (exact): the GPU DMRG3S energy
     equals ED to 1e-10."""
     l, m = 12, 64
     e_ed = ed.ground_energy(ed.spin_chain_hamiltonian(l, {(i, i + 1): 1.0 for i in range(l - 1)}))
@@ -330,7 +330,7 @@ def test_sweep_heisenberg12_exact_bond(ctx):
 
 
 def test_sweep_heisenberg12_m16_matches_oracle(ctx):
-    """BASELINE configuration 1 (m = 16): GPU and oracle DMRG3S from the same
+    """The l = 12 Heisenberg chain at m = 16: GPU and oracle DMRG3S from the same
     seeded state converge to the same energy (plain FP64 path: 1e-10)."""
     l, m = 12, 16
     tensors = synth.random_mps(l, 2, m)

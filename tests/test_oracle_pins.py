@@ -334,7 +334,7 @@ def heis12_ed():
 
 def test_dmrg3s_heisenberg12_exact_bond(heis12_ed):
     """m = 64 represents the l = 12 ground state exactly: DMRG3S reaches the
-    ED energy (BASELINE configuration 1, exact variant)."""
+    ED energy (the small Heisenberg workload, exact variant)."""
     l = 12
     run = DMRG3S(MPO.heisenberg_mpo(l), synth.random_mps(l, 2, 64), mmax=64, alpha0=1e-3)
     E, nsw = run.run(tol=1e-12, max_sweeps=12)
