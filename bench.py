@@ -542,7 +542,7 @@ def main():
                          "as the reference for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the H_eff hot path of one GPU's share); "
+        print("bench.py: measures one GPU only (the H_eff hot path of one GPU's share); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
