@@ -267,6 +267,11 @@ void wmap_upload(Ctx* c, WmapPlan& w) {
     const int n = (int)(((long)k.di * k.dj + kWmapChunk - 1) / kWmapChunk);
     for (int q = 0; q < n; ++q) ct[(size_t)k.chunk0 + q] = (int)t;
   }
+  // four consecutive elements of a row per thread where every start and
+  // length is a multiple of 4 (the padded twin's tables)
+  w.vec4 = (w.in_rs % 4 == 0) && (w.out_rs % 4 == 0);
+  for (const WmapTask& k : w.tasks) w.vec4 = w.vec4 && (k.j_off % 4 == 0) && (k.dj % 4 == 0);
+  for (const WmapEnt& e : w.ents) w.vec4 = w.vec4 && (e.off % 4 == 0);
   D3S_HIP(hipMalloc((void**)&w.d_ctask, sizeof(int) * std::max<size_t>(1, ct.size())));
   if (!ct.empty())
     D3S_HIP(hipMemcpyAsync(w.d_ctask, ct.data(), sizeof(int) * ct.size(), hipMemcpyHostToDevice, c->stream));

@@ -141,6 +141,7 @@ struct WmapPlan {
   WmapTask* d_tasks = nullptr;
   WmapEnt* d_ents = nullptr;
   int* d_ctask = nullptr;       // task of each chunk
+  bool vec4 = false;            // every offset, row length and block width a multiple of 4
   int chunks = 0, maxk = 1;
   long in_rs = 0, out_rs = 0;
 };

@@ -270,6 +270,72 @@ void wmap_blocks_kernel(const Tin* __restrict__ in, const Tc* __restrict__ Wg, T
   }
 }
 
+// Four consecutive elements of a block row per thread, moved with one
+// vector load / store per channel pair: for tables whose offsets, row
+// lengths and block widths are all multiples of 4 (so the four elements
+// share a row and the vectors are aligned).  Same chunks and task table as
+// wmap_blocks_kernel.
+template <typename T> struct alignas(4 * sizeof(T)) Vec4 { T v[4]; };
+
+template <typename Tin, typename Tout, typename Tc, int MAXK>
+__global__ __launch_bounds__(kThreads)
+void wmap_blocks_vec4_kernel(const Tin* __restrict__ in, const Tc* __restrict__ Wg, Tout* __restrict__ out,
+                             const WmapTask* __restrict__ tasks, const int* __restrict__ ctask,
+                             const WmapEnt* __restrict__ ents, long in_rs, long out_rs, Tc alpha) {
+  static_assert(kWmapChunk == 4 * kThreads, "one vector of four elements per thread");
+  __shared__ Tc sW[MAXK * MAXK];
+  __shared__ long sInOff[MAXK], sOutOff[MAXK];
+  __shared__ int sInW[MAXK], sOutW[MAXK];
+  const WmapTask tk = tasks[ctask[blockIdx.x]];
+  const int nin = tk.nin, nout = tk.nout;
+  for (int i = threadIdx.x; i < nin; i += blockDim.x) {
+    sInOff[i] = ents[tk.idx0 + i].off;
+    sInW[i] = ents[tk.idx0 + i].wp;
+  }
+  for (int i = threadIdx.x; i < nout; i += blockDim.x) {
+    sOutOff[i] = ents[tk.idx0 + nin + i].off;
+    sOutW[i] = ents[tk.idx0 + nin + i].wp;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nout * MAXK; i += blockDim.x) {
+    const int o = i / MAXK, k = i - o * MAXK;
+    sW[i] = (k < nin) ? alpha * Wg[sInW[k] + sOutW[o]] : Tc(0);
+  }
+  __syncthreads();
+  const long e = (long)((int)blockIdx.x - tk.chunk0) * kWmapChunk + 4L * threadIdx.x;
+  if (e >= (long)tk.di * tk.dj) return;
+  const long a = tk.i_off + e / tk.dj, y = tk.j_off + e % tk.dj;
+  const Tin* src = in + a * in_rs + y;
+  Tout* dst = out + a * out_rs + y;
+  if (nin == 0) {
+    Vec4<Tout> z;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) z.v[j] = Cvt<Tout>::st(Tc(0));
+    for (int o = 0; o < nout; ++o) *reinterpret_cast<Vec4<Tout>*>(dst + sOutOff[o]) = z;
+    return;
+  }
+  Tc v[MAXK][4];
+#pragma unroll
+  for (int k = 0; k < MAXK; ++k) {
+    const Vec4<Tin> q = *reinterpret_cast<const Vec4<Tin>*>(src + sInOff[min(k, nin - 1)]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[k][j] = (Tc)Cvt<Tin>::ld(q.v[j]);
+  }
+  for (int o = 0; o < nout; ++o) {
+    Tc acc[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < MAXK; ++k) {
+      const Tc wk = sW[o * MAXK + k];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[j] += wk * v[k][j];
+    }
+    Vec4<Tout> r;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) r.v[j] = Cvt<Tout>::st(acc[j]);
+    *reinterpret_cast<Vec4<Tout>*>(dst + sOutOff[o]) = r;
+  }
+}
+
 template <typename Tin, typename Tout, typename Tc>
 void wmap_blocks_t(Ctx* c, const void* in, const void* W, void* out, const WmapPlan& w, double alpha) {
   dim3 grid((unsigned)w.chunks), block(kThreads);
@@ -277,6 +343,18 @@ void wmap_blocks_t(Ctx* c, const void* in, const void* W, void* out, const WmapP
     hipLaunchKernelGGL(kern, grid, block, 0, c->stream, (const Tin*)in, (const Tc*)W, (Tout*)out, w.d_tasks,
                        w.d_ctask, w.d_ents, w.in_rs, w.out_rs, (Tc)alpha);
   };
+  // the vector form: 4-byte (or smaller) elements, vector-aligned buffers
+  if constexpr (sizeof(Tin) <= 4 && sizeof(Tout) <= 4) {
+    const bool v4 = w.vec4 && w.maxk <= 24 && (reinterpret_cast<uintptr_t>(in) % (4 * sizeof(Tin)) == 0) &&
+                    (reinterpret_cast<uintptr_t>(out) % (4 * sizeof(Tout)) == 0);
+    if (v4) {
+      if (w.maxk <= 8) go(wmap_blocks_vec4_kernel<Tin, Tout, Tc, 8>);
+      else if (w.maxk <= 16) go(wmap_blocks_vec4_kernel<Tin, Tout, Tc, 16>);
+      else go(wmap_blocks_vec4_kernel<Tin, Tout, Tc, 24>);
+      D3S_HIP(hipGetLastError());
+      return;
+    }
+  }
   if (w.maxk <= 8) go(wmap_blocks_kernel<Tin, Tout, Tc, 8>);
   else if (w.maxk <= 16) go(wmap_blocks_kernel<Tin, Tout, Tc, 16>);
   else if (w.maxk <= 24) go(wmap_blocks_kernel<Tin, Tout, Tc, 24>);
