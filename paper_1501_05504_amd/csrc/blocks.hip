@@ -20,6 +20,7 @@
 // Tasks are the "uneven blocks" of a symmetric DMRG; all of them go into one
 // grouped launch per contraction.
 #include <algorithm>
+#include <cstring>
 #include <cfloat>
 #include <chrono>
 #include <cmath>
@@ -259,37 +260,39 @@ void wmap_upload(Ctx* c, WmapPlan& w) {
   wmap_release(w);
   if (w.maxk > 80) throw Error{D3S_EINVAL, "block W-map: more than 80 channel pairs per block"};
   if (w.tasks.empty()) return;
-  D3S_HIP(hipMalloc((void**)&w.d_tasks, sizeof(WmapTask) * w.tasks.size()));
-  D3S_HIP(hipMalloc((void**)&w.d_ents, sizeof(WmapEnt) * std::max<size_t>(1, w.ents.size())));
-  std::vector<int> ct((size_t)w.chunks);
-  for (size_t t = 0; t < w.tasks.size(); ++t) {
-    const WmapTask& k = w.tasks[t];
-    const int n = (int)(((long)k.di * k.dj + kWmapChunk - 1) / kWmapChunk);
-    for (int q = 0; q < n; ++q) ct[(size_t)k.chunk0 + q] = (int)t;
-  }
   // four consecutive elements of a row per thread where every start and
   // length is a multiple of 4 (the padded twin's tables)
   w.vec4 = (w.in_rs % 4 == 0) && (w.out_rs % 4 == 0);
   for (const WmapTask& k : w.tasks) w.vec4 = w.vec4 && (k.j_off % 4 == 0) && (k.dj % 4 == 0);
   for (const WmapEnt& e : w.ents) w.vec4 = w.vec4 && (e.off % 4 == 0);
-  D3S_HIP(hipMalloc((void**)&w.d_ctask, sizeof(int) * std::max<size_t>(1, ct.size())));
-  if (!ct.empty())
-    D3S_HIP(hipMemcpyAsync(w.d_ctask, ct.data(), sizeof(int) * ct.size(), hipMemcpyHostToDevice, c->stream));
-  D3S_HIP(hipMemcpyAsync(w.d_tasks, w.tasks.data(), sizeof(WmapTask) * w.tasks.size(), hipMemcpyHostToDevice,
-                         c->stream));
-  if (!w.ents.empty())
-    D3S_HIP(hipMemcpyAsync(w.d_ents, w.ents.data(), sizeof(WmapEnt) * w.ents.size(), hipMemcpyHostToDevice,
-                           c->stream));
+  // tasks, entries and the chunk -> task table in one allocation, one copy
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t bt = up(sizeof(WmapTask) * w.tasks.size()), be = up(sizeof(WmapEnt) * w.ents.size());
+  const size_t bc = up(sizeof(int) * (size_t)w.chunks);
+  std::vector<unsigned char> host(bt + be + bc, 0);
+  std::memcpy(host.data(), w.tasks.data(), sizeof(WmapTask) * w.tasks.size());
+  if (!w.ents.empty()) std::memcpy(host.data() + bt, w.ents.data(), sizeof(WmapEnt) * w.ents.size());
+  int* ct = reinterpret_cast<int*>(host.data() + bt + be);
+  for (size_t t = 0; t < w.tasks.size(); ++t) {
+    const WmapTask& k = w.tasks[t];
+    const int n = (int)(((long)k.di * k.dj + kWmapChunk - 1) / kWmapChunk);
+    for (int q = 0; q < n; ++q) ct[(size_t)k.chunk0 + q] = (int)t;
+  }
+  unsigned char* base = nullptr;
+  D3S_HIP(hipMalloc((void**)&base, host.size()));
+  w.d_tasks = reinterpret_cast<WmapTask*>(base);
+  w.d_ents = reinterpret_cast<WmapEnt*>(base + bt);
+  w.d_ctask = reinterpret_cast<int*>(base + bt + be);
+  D3S_HIP(hipMemcpyAsync(base, host.data(), host.size(), hipMemcpyHostToDevice, c->stream));
   D3S_HIP(hipStreamSynchronize(c->stream));
 }
 
 void wmap_release(WmapPlan& w) {
+  // one allocation holds the tasks, the entries and the chunk table
   if (w.d_tasks) (void)hipFree(w.d_tasks);
-  if (w.d_ents) (void)hipFree(w.d_ents);
-  if (w.d_ctask) (void)hipFree(w.d_ctask);
-  w.d_ctask = nullptr;
   w.d_tasks = nullptr;
   w.d_ents = nullptr;
+  w.d_ctask = nullptr;
 }
 
 EnvPack build_envpack(const Sectors& s, const int* wq, int w) {
@@ -309,7 +312,8 @@ EnvPack build_envpack(const Sectors& s, const int* wq, int w) {
 }
 
 void build_block_heff(Ctx* c, BlockHeff& h, const Sectors& left, const Sectors& right, int d, int wl, int wr,
-                      const int* pq, const int* wql, const int* wqr, bool packed, bool with_g2, bool packed_env) {
+                      const int* pq, const int* wql, const int* wqr, bool packed, bool with_g2, bool packed_env,
+                      bool with_psit) {
   const int nq = left.nq;
   if (nq < 1 || nq > 4) throw Error{D3S_EINVAL, "blocks: 1 to 4 charges per state"};
   const int ml = left.total, mr = right.total;
@@ -375,6 +379,7 @@ void build_block_heff(Ctx* c, BlockHeff& h, const Sectors& left, const Sectors& 
         tk.ldc = (long)wl * d * mr;
         h.g1.segs.push_back(sg);
         h.g1.tasks.push_back(tk);
+        if (!with_psit) continue;
         sg.b_off = h.poff[(size_t)ip * d + t];
         sg.ldb = left.dim[ip];
         h.g1t.segs.push_back(sg);
@@ -382,7 +387,7 @@ void build_block_heff(Ctx* c, BlockHeff& h, const Sectors& left, const Sectors& 
       }
     }
   // tiles of the block transpose psi -> psi^T
-  {
+  if (with_psit) {
     std::vector<TrTile> trt;
     for (int i = 0; i < left.n; ++i)
       for (int t = 0; t < d; ++t) {
@@ -474,7 +479,7 @@ void build_block_heff(Ctx* c, BlockHeff& h, const Sectors& left, const Sectors& 
   const size_t nL = (size_t)ml * wl * ml, nP = (size_t)ml * d * mr, nR = (size_t)mr * wr * mr;
   const size_t nT = (size_t)ml * std::max(wl, wr) * d * mr;
   finalize_and_tune(c, h.g1, nL, nP, nT);
-  finalize_and_tune(c, h.g1t, nL, nP, nT);
+  if (with_psit) finalize_and_tune(c, h.g1t, nL, nP, nT);
   finalize_and_tune(c, h.g2, nT, nR, nP * h.g2_split);
   // flops of the allowed block products of the two GEMMs (the W-map is not counted)
   h.flops = h.g1.flops + h.g2.flops;
@@ -524,7 +529,8 @@ LowpTwin& ensure_lowp(Ctx* c, BlockHeff& h) {
   try {
     const Sectors pl = padded_sectors(h.left), pr = padded_sectors(h.right);
     const int nq = h.left.nq;
-    build_block_heff(c, tw->h, pl, pr, h.d, h.wl, h.wr, h.pq.data(), h.wql.data(), h.wqr.data(), true, true, true);
+    build_block_heff(c, tw->h, pl, pr, h.d, h.wl, h.wr, h.pq.data(), h.wql.data(), h.wqr.data(), true, true, true,
+                     true);
     tw->h.padded = true;
     const BlockHeff& t = tw->h;
     std::vector<RlTile> vl, vr, vx, vy;

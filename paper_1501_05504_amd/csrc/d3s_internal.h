@@ -297,8 +297,9 @@ struct BlockHeff {
   EnvPack epl, epr;
   GroupedPlan g1, g2;                    // H_eff: GEMM-1 and GEMM-2
   // GEMM-1 on the block-transposed psi (K-contiguous B operand: block (i, t)
-  // stored dim_j x dim_i at poff), used for FP32 / BF16 products; the tiles
-  // of the block transpose (device table)
+  // stored dim_j x dim_i at poff), used for FP32 / BF16 products (built for
+  // the padded twins, which run them); the tiles of the block transpose
+  // (device table)
   GroupedPlan g1t;
   TrTile* d_trt = nullptr;
   int ntrt = 0;
@@ -338,7 +339,7 @@ struct LowpTwin {
 LowpTwin& ensure_lowp(Ctx* c, BlockHeff& h);
 void build_block_heff(Ctx* c, BlockHeff& h, const Sectors& left, const Sectors& right, int d, int wl, int wr,
                       const int* phys_q, const int* wq_left, const int* wq_right, bool packed = false,
-                      bool with_g2 = true, bool packed_env = false);
+                      bool with_g2 = true, bool packed_env = false, bool with_psit = false);
 // elements of the L / R operands of a plan (packed or dense)
 inline long plan_nl(const BlockHeff& h) { return h.penv ? h.epl.total : (long)h.ml * h.wl * h.ml; }
 inline long plan_nr(const BlockHeff& h) { return h.penv ? h.epr.total : (long)h.mr * h.wr * h.mr; }
