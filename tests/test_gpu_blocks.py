@@ -104,7 +104,7 @@ def test_block_heff_f32(ctx):
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
-@pytest.mark.parametrize("ml,mr,seed", [(40, 52, 11), (300, 257, 12)])
+@pytest.mark.parametrize("ml,mr,seed", [(20, 17, 13), (40, 52, 11), (300, 257, 12)])
 def test_block_heff_low_precision_transposed_psi(ctx, prec, ml, mr, seed):
     """FP32 / BF16 block products against the oracle on the rounded operands
     (FP32 3e-5; BF16 2e-2, the intermediate T2 being rounded to 8 bits),
@@ -112,7 +112,8 @@ def test_block_heff_low_precision_transposed_psi(ctx, prec, ml, mr, seed):
     zero.  The product runs on the plan's twin over sectors padded to
     multiples of 8 (operands moved in and the product moved back), whose
     first GEMM reads the block-transposed psi; odd sector dimensions make
-    the padding non-trivial."""
+    the padding non-trivial (with ml = 20 the sectors hold 1-3 states and
+    the padded blocks are mostly zeros)."""
     case = hubbard_block_case(ml, mr, seed)
     t = torch.float32 if prec == "f32" else torch.bfloat16
     Lt, Rt, pt = dev(case["L"], t), dev(case["R"], t), dev(case["psi"], t)
