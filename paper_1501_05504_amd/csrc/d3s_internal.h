@@ -129,7 +129,7 @@ void wmap_r2l(Ctx* c, d3s_prec p, const void* Y, const void* W, void* Z,
 
 // Block-sparse W-map (see kernels.hip): tasks over (left sector, right sector)
 // pairs; ents[idx0 .. idx0+nin) are the input entries, the next nout the
-// output entries; chunk0 = first 256-element chunk of the task.
+// output entries; chunk0 = first kWmapChunk-element chunk of the task.
 struct WmapTask { int i_off, di, j_off, dj, nin, nout, idx0, chunk0; };
 struct WmapEnt { long off; int wp, pad_; };
 // elements of a block W-map chunk (one workgroup of 256 threads, four
@@ -267,7 +267,6 @@ struct EnvPack {
 };
 EnvPack build_envpack(const Sectors& s, const int* wq, int w);
 
-// Grouped-GEMM plans of one block-sparse H_eff (and its captured graph).
 // One tile (at most 32 x 32) of a block relayout: the destination tile
 // (prows x pcols at dst, row stride dst_ld) receives the source entries
 // (rows x cols at src, row stride src_ld) converted to its element type and
@@ -282,6 +281,7 @@ struct LowpTwin;
 struct TrTile { long src, dst; int src_ld, dst_ld, rows, cols; };
 void transpose_tiles(Ctx* c, int esz, const void* in, void* out, const TrTile* tiles, int ntiles);
 
+// Grouped-GEMM plans of one block-sparse H_eff (and its captured graph).
 struct BlockHeff {
   int ml = 0, mr = 0, d = 0, wl = 0, wr = 0;
   Sectors left, right;                   // the bonds the plan was built for
