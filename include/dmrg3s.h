@@ -107,10 +107,15 @@ d3s_status d3s_set_block_split(d3s_ctx ctx, double min_gflop);
  * Tuning never happens during graph capture or for accumulating products. */
 d3s_status d3s_set_autotune(d3s_ctx ctx, int enable, const char* cache_path);
 /* Batched eigensolver of the per-sector Gram matrices in the block-sparse
- * truncation (rocSOLVER, FP64): kind 1 = divide and conquer (syevd), 2 =
- * Jacobi (syevj), 0 = Jacobi for sizes <= jacobi_max_n and divide and
- * conquer above (the default: kind 0, jacobi_max_n 0, i.e. syevd).  Both
- * give the eigenpairs to FP64 accuracy; only the speed differs. */
+ * truncation (FP64): kind 1 = rocSOLVER divide and conquer (syevd), 2 =
+ * rocSOLVER Jacobi (syevj), 0 = Jacobi for sizes <= jacobi_max_n and divide
+ * and conquer above (the default: kind 0, jacobi_max_n 0, i.e. syevd),
+ * 3 = the library's own solver for n <= 128 (one workgroup per matrix with
+ * the matrix in LDS: Householder tridiagonalisation and implicit QL; faster
+ * than rocSOLVER only on batches of matrices of a few tens of rows) and
+ * divide and conquer above.  All give the eigenpairs to FP64 accuracy
+ * (eigenvectors of repeated eigenvalues may differ by a rotation within
+ * their eigenspace); only the speed differs.  D3S_EINVAL outside 0..3. */
 d3s_status d3s_set_eigensolver(d3s_ctx ctx, int kind, int jacobi_max_n);
 /* The batched FP64 symmetric eigensolver of the truncations (a6): `batch`
  * matrices of size n, column-major, stored one after the other in A

@@ -248,7 +248,8 @@ class Context:
         return self._check(_eig_batched(self.h, n, batch, _ptr(A), _ptr(W)))
 
     def set_eigensolver(self, kind, jacobi_max_n=0):
-        """0 auto (Jacobi up to jacobi_max_n), 1 divide and conquer, 2 Jacobi."""
+        """0 auto (Jacobi up to jacobi_max_n), 1 divide and conquer, 2 Jacobi,
+        3 the library's LDS solver up to n = 128."""
         self._check(_set_eig(self.h, int(kind), int(jacobi_max_n)))
 
     def set_block_split(self, min_gflop):

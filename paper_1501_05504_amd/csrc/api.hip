@@ -165,14 +165,15 @@ d3s_status d3s_eig_batched(d3s_ctx ctx, int n, int batch, double* A, double* W) 
   return guarded(ctx, [&] {
     D3S_REQUIRE(n >= 1 && batch >= 1, "n and batch must be >= 1");
     D3S_REQUIRE(A && W, "null pointer");
-    d3s::syevd_batched_f64(&ctx->c, n, batch, A, W);
+    d3s::eig_batched_f64(&ctx->c, n, batch, A, W);
     return D3S_OK;
   });
 }
 
 d3s_status d3s_set_eigensolver(d3s_ctx ctx, int kind, int jacobi_max_n) {
   return guarded(ctx, [&] {
-    D3S_REQUIRE(kind >= 0 && kind <= 2, "kind must be 0 (auto), 1 (divide and conquer) or 2 (Jacobi)");
+    D3S_REQUIRE(kind >= 0 && kind <= 3,
+                "kind must be 0 (auto), 1 (divide and conquer), 2 (Jacobi) or 3 (LDS solver up to n = 128)");
     D3S_REQUIRE(jacobi_max_n >= 0, "jacobi_max_n must be >= 0");
     ctx->c.eig_kind = kind;
     ctx->c.eig_jacobi_max = jacobi_max_n;

@@ -1065,20 +1065,28 @@ TruncBlocksResult op_truncate_blocks(Ctx* c, d3s_dir dir, const Sectors& left, c
   // 24 us per matrix column whatever the batch size (launch-bound) plus
   // ~1.6e-12 n^3 s per matrix, while below n = 96 its small-size path grows
   // steeply with the batch (n = 64, 40 matrices: 18 ms against 2 ms at
-  // n = 96).  So every matrix is padded (zero rows and columns, whose zero
-  // eigenvalues sort below every kept one) to at least 96, sizes are sorted,
-  // and the contiguous grouping of least modelled cost is found by dynamic
-  // programming, each group padded to its largest member rounded up to 16.
+  // n = 96).  With the LDS solver chosen, matrices up to 128 may go to it
+  // instead (one workgroup per matrix, nothing launched per column, about
+  // 5e-5 + 6.5e-7 n^2 s per batch of up to 256).  Matrices are
+  // padded with zero rows and columns (whose zero eigenvalues sort below
+  // every kept one): to a multiple of 8 for the LDS solver, else to at least
+  // 96 and a multiple of 16; sizes are sorted and the contiguous grouping of
+  // least modelled cost is found by dynamic programming.
   {
     const int G = (int)gs.size();
     std::vector<int> ord(G);
     for (int i = 0; i < G; ++i) ord[i] = i;
     auto gdim = [&](int gi) { return (dir == D3S_L2R) ? gs[gi].nrows : gs[gi].ncols; };
     std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return gdim(a) < gdim(b); });
-    auto pad = [](int n) { return std::max(96, (n + 15) / 16 * 16); };
+    // sizes the LDS solver takes (see eig_batched_f64) are padded to
+    // multiples of 8 only
+    auto small = [&](int n) { return eig_small_used(c, (n + 7) / 8 * 8); };
+    auto pad = [&](int n) { return small(n) ? (n + 7) / 8 * 8 : std::max(96, (n + 15) / 16 * 16); };
     auto cost = [&](int i, int j) {   // group ord[i..j]
       const double np = pad(gdim(ord[j]));
-      return 2.4e-5 * np + 1.6e-12 * (double)(j - i + 1) * np * np * np;
+      const int cnt = j - i + 1;
+      if (small(gdim(ord[j]))) return (5e-5 + 6.5e-7 * np * np) * ((cnt + 255) / 256);
+      return 2.4e-5 * np + 1.6e-12 * (double)cnt * np * np * np;
     };
     std::vector<double> best(G + 1, 0.0);
     std::vector<int> cut(G + 1, 0);
@@ -1148,7 +1156,7 @@ TruncBlocksResult op_truncate_blocks(Ctx* c, d3s_dir dir, const Sectors& left, c
   grouped_release(gp);
   double* V = (double*)ws_get(c, WS_GVAL, sizeof(double) * (size_t)vtot);
   for (size_t b = 0; b < bucket_n.size(); ++b)
-    syevd_batched_f64(c, bucket_n[b], (int)bucket_members[b].size(), G + bucket_goff[b], V + bucket_voff[b]);
+    eig_batched_f64(c, bucket_n[b], (int)bucket_members[b].size(), G + bucket_goff[b], V + bucket_voff[b]);
   std::vector<double> ev(vtot);
   D3S_HIP(hipMemcpyAsync(ev.data(), V, sizeof(double) * (size_t)vtot, hipMemcpyDeviceToHost, c->stream));
   D3S_HIP(hipStreamSynchronize(c->stream));

@@ -56,7 +56,7 @@ struct Ctx {
   double block_split_gflop = 1.0;    // split the block GEMM-2 from this many GFLOP on (< 0: never)
   bool splitk_off = false;           // disable split-K (tests compare both paths)
   bool autotune = false;             // time tile configurations on first use of a shape
-  int eig_kind = 0;                  // batched eigensolver: 0 auto, 1 divide and conquer, 2 Jacobi
+  int eig_kind = 0;                  // batched eigensolver: 0 auto, 1 divide and conquer, 2 Jacobi, 3 LDS solver
   int eig_jacobi_max = 0;            // auto: Jacobi up to this size
   std::unordered_map<std::string, int> tune_cache;
   std::string tune_path;
@@ -397,6 +397,11 @@ LanczosResult op_lanczos_blocks(Ctx* c, d3s_prec p, BlockHeff& plan, const doubl
                                 const double* R, double* psi, double tol, int kmax, int max_matvecs,
                                 bool use_graph, double* packed_out = nullptr);
 void syevd_batched_f64(Ctx* c, int n, int batch, double* A, double* evals);
+// the batched eigensolver of the truncations: an LDS-resident solver for
+// n <= kEigSmallMax (eigensolver kind 3), rocSOLVER otherwise
+constexpr int kEigSmallMax = 128;
+bool eig_small_used(const Ctx* c, int n);
+void eig_batched_f64(Ctx* c, int n, int batch, double* A, double* evals);
 
 // lowest eigenpair of a symmetric tridiagonal matrix (bisection + inverse iteration)
 bool tridiag_lowest(int n, const double* a, const double* b, double* theta, double* y);

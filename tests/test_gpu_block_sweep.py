@@ -72,12 +72,14 @@ def test_block_sweep_small_packed_environments(ctx):
     assert err.value.status == abi.EINVAL
 
 
-def test_block_sweep_jacobi_eigensolver_equals_ed():
-    """The Jacobi batched eigensolver in the block truncation gives the same
-    converged energy as the default divide and conquer one."""
+@pytest.mark.parametrize("kind", [2, 3])
+def test_block_sweep_jacobi_eigensolver_equals_ed(kind):
+    """The Jacobi batched eigensolver (kind 2) and the library's LDS solver
+    (kind 3) in the block truncation reach the sector's exact energy, as the
+    default divide and conquer one does."""
     c = abi.Context(0)
     try:
-        c.set_eigensolver(2)
+        c.set_eigensolver(kind)
         l, m = 12, 64
         mpo = abi.heisenberg_mpo(l)
         E, *_ = run_blocks(c, mpo, abi.mpo_spin_charges(1), abi.SPIN_HALF_CHARGES, [0], m, 12, 21)

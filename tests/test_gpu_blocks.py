@@ -215,11 +215,13 @@ def test_block_update_env_equals_dense_oracle(ctx, ml, mr, seed):
     plan.close()
 
 
-@pytest.mark.parametrize("kind", [1, 2])
-@pytest.mark.parametrize("n,batch", [(1, 3), (7, 5), (40, 2), (130, 3)])
+@pytest.mark.parametrize("kind", [1, 2, 3])
+@pytest.mark.parametrize("n,batch", [(1, 3), (7, 5), (40, 2), (96, 40), (128, 3), (130, 3)])
 def test_eig_batched_equals_lapack(kind, n, batch):
-    """The batched eigensolver of the truncation (divide and conquer and
-    Jacobi) against LAPACK: eigenvalues, and eigenvectors through A V = V L."""
+    """The batched eigensolvers of the truncation against LAPACK:
+    eigenvalues, eigenvectors through A V = V L, and V orthonormal.  Kind 1
+    runs rocSOLVER divide and conquer, kind 2 rocSOLVER Jacobi, kind 3 the
+    LDS solver up to n = 128 (divide and conquer above)."""
     c = abi.Context(0)
     try:
         c.set_eigensolver(kind)
@@ -236,5 +238,41 @@ def test_eig_batched_equals_lapack(kind, n, batch):
             assert np.abs(W[b].cpu().numpy() - w_ref).max() < 1e-12 * scale
             V = A[b].cpu().numpy()          # row j = eigenvector j
             assert np.abs(G[b] @ V.T - V.T * W[b].cpu().numpy()).max() < 1e-11 * scale
+            assert np.abs(V @ V.T - np.eye(n)).max() < 1e-12 * n
+    finally:
+        c.close()
+
+
+def test_eig_small_solver_degenerate_and_padded():
+    """The LDS eigensolver on what the truncation hands it: rank-deficient
+    Gram matrices padded with zero rows and columns, and exactly repeated
+    eigenvalues; eigenvalues against LAPACK, A V = V L and V orthonormal."""
+    c = abi.Context(0)
+    try:
+        c.set_eigensolver(3)
+        rng = np.random.default_rng(5)
+        n = 72
+        mats = []
+        X = rng.standard_normal((50, 20))
+        G = np.zeros((n, n))
+        G[:50, :50] = X @ X.T                          # rank 20, 22 padded zero rows
+        mats.append(G)
+        Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        lam = np.repeat([0.0, 1.0, 2.5, 7.0], n // 4)  # four eigenvalues, 18 times each
+        mats.append((Q * lam) @ Q.T)
+        mats.append(np.zeros((n, n)))
+        Gs = np.stack(mats)
+        A = torch.tensor(Gs, device=DEV)
+        W = torch.empty((len(mats), n), dtype=torch.float64, device=DEV)
+        c.eig_batched(A, W)
+        torch.cuda.synchronize()
+        for b in range(len(mats)):
+            w_ref = np.linalg.eigvalsh(Gs[b])
+            scale = max(1.0, np.abs(w_ref).max())
+            w = W[b].cpu().numpy()
+            assert np.abs(w - w_ref).max() < 1e-12 * scale
+            V = A[b].cpu().numpy()
+            assert np.abs(Gs[b] @ V.T - V.T * w).max() < 1e-11 * scale
+            assert np.abs(V @ V.T - np.eye(n)).max() < 1e-12 * n
     finally:
         c.close()
