@@ -1363,8 +1363,9 @@ void relayout_tiles(Ctx* c, int in_kind, int out_kind, const void* in, void* out
 // n <= kEigSmallMax when chosen (d3s_set_eigensolver kind 3), rocSOLVER
 // otherwise.  Measured on MI355X the LDS solver takes about 0.11 / 0.8 /
 // 2.6 / 6.1 ms for n = 8 / 32 / 64 / 96 whatever the batch (up to 256
-// matrices side by side): its QL recurrence runs on one thread at LDS
-// latency, so it beats rocSOLVER only on batches of small matrices.
+// matrices side by side): the Householder and accumulation phases have
+// about n threads each walking O(n) dependent LDS operations, so it beats
+// rocSOLVER only on batches of small matrices.
 bool eig_small_used(const Ctx* c, int n) { return c->eig_kind == 3 && n >= 1 && n <= kEigSmallMax; }
 
 void eig_batched_f64(Ctx* c, int n, int batch, double* A, double* evals) {
