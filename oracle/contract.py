@@ -201,9 +201,7 @@ def residual_gram_l2r(L, W, R, Gr, psi, E, alpha):
     Mm = psi.reshape(ml * d, mr)
     Pm = expansion_term_l2r(L, W, psi, 1.0).reshape(ml * d, wr * mr)
     Zc = np.hstack([-E * Mm, Pm])
-    Rm = R.reshape(mr, wr * mr)                              # <B_y'|H_v B_y> = R[y', v, y]
-    Ghh = Gr.transpose(1, 0, 2, 3).reshape(wr * mr, wr * mr)
-    G = np.block([[np.eye(mr), Rm], [Rm.T, Ghh]])
+    G = residual_metric_l2r(R, Gr)
     return Mm @ Mm.T + alpha ** 2 * (Zc @ G @ Zc.T)
 
 
@@ -217,47 +215,60 @@ def residual_gram_r2l(L, W, R, Gl, psi, E, alpha):
     Mm = psi.reshape(ml, d * mr)
     Pm = expansion_term_r2l(R, W, psi, 1.0).reshape(wl * ml, d * mr)
     Zc = np.vstack([-E * Mm, Pm])
-    Lm = L.reshape(ml, wl * ml)
-    Ghh = Gl.transpose(1, 0, 2, 3).reshape(wl * ml, wl * ml)
-    G = np.block([[np.eye(ml), Lm], [Lm.T, Ghh]])
+    G = residual_metric_r2l(L, Gl)
     return Mm.T @ Mm + alpha ** 2 * (Zc.T @ G @ Zc)
 
 
-GRAM_RESOLUTION = np.finfo(np.float64).eps
+def _metric_factor(G):
+    """F (n x r) with G = F F^T for the metric G of the residual's
+    vectors, from the eigen-decomposition of G.  Those vectors are linearly
+    dependent (the far-side operator of the completed MPO channel is the
+    identity, so it repeats |B_y>); eigenvalues of G at or below
+    n u lambda_max are such exact dependences and are taken as zero."""
+    lam, Q = np.linalg.eigh(G)
+    keep = lam > G.shape[0] * np.finfo(np.float64).eps * lam.max()
+    return Q[:, keep] * np.sqrt(lam[keep])
 
 
-def _gram_spectrum(Gram, kmax, eps):
-    """Eigenpairs of a Gram matrix, descending, and the number kept: at most
-    kmax, and only s_j^2 > max(eps^2, n u) s_0^2 (a Gram matrix resolves
-    s_j^2 only to about n u s_0^2)."""
-    lam, V = np.linalg.eigh(Gram)
-    order = np.argsort(lam)[::-1]
-    s2 = np.maximum(lam[order], 0.0)
-    V = V[:, order]
-    n = Gram.shape[0]
-    floor2 = max(eps * eps, n * GRAM_RESOLUTION) * s2[0]
-    k = int(min(kmax, np.count_nonzero(s2 > floor2)))
-    return s2, V, k
+def residual_metric_l2r(R, Gr):
+    """Metric of |B_y> and H_v|B_y> (the right-side vectors of a left-to-right
+    residual): [[1, R], [R^T, Gr]] with <B_y'|H_v B_y> = R[y', v, y]."""
+    mr, wr = R.shape[0], R.shape[1]
+    Rm = R.reshape(mr, wr * mr)
+    Ghh = Gr.transpose(1, 0, 2, 3).reshape(wr * mr, wr * mr)
+    return np.block([[np.eye(mr), Rm], [Rm.T, Ghh]])
 
 
-def truncate_gram_l2r(Gram, psi, nbr, kmax, eps):
-    """Steps 4-5 of the site update from the left Gram matrix of the expanded
-    tensor: A = its top-k eigenvectors (the left singular vectors of M~),
-    B~ = (A^T M) B.  Returns (A, B~, s, discarded)."""
+def residual_metric_r2l(L, Gl):
+    """Mirror of residual_metric_l2r for |A_a> and H_w|A_a>."""
+    ml, wl = L.shape[0], L.shape[1]
+    Lm = L.reshape(ml, wl * ml)
+    Ghh = Gl.transpose(1, 0, 2, 3).reshape(wl * ml, wl * ml)
+    return np.block([[np.eye(ml), Lm], [Lm.T, Ghh]])
+
+
+def residual_expanded_l2r(L, W, R, Gr, psi, E, alpha):
+    """The expanded tensor [M | alpha Z] with the exact residual as its
+    expansion part, written on an orthonormal basis of the span of the
+    residual's right-side vectors: [M | alpha Z_c F] with G = F F^T, an
+    (m_l d) x (m_r + r) matrix whose SVD is the truncation's (its Gram
+    matrix is residual_gram_l2r)."""
     ml, d, mr = psi.shape
-    s2, V, k = _gram_spectrum(Gram, kmax, eps)
-    U = V[:, :k]
-    X = U.T @ psi.reshape(ml * d, mr)
-    nb = X @ nbr.reshape(mr, -1)
-    return U.reshape(ml, d, k), nb.reshape(k, nbr.shape[1], nbr.shape[2]), np.sqrt(s2), float(np.sum(s2[k:]))
+    wr = W.shape[1]
+    Mm = psi.reshape(ml * d, mr)
+    Pm = expansion_term_l2r(L, W, psi, 1.0).reshape(ml * d, wr * mr)
+    Zc = np.hstack([-E * Mm, Pm])
+    F = _metric_factor(residual_metric_l2r(R, Gr))
+    return np.hstack([Mm, alpha * (Zc @ F)])
 
 
-def truncate_gram_r2l(Gram, psi, nbr, kmax, eps):
-    """Mirror of truncate_gram_l2r: B = top-k eigenvectors as rows,
-    A~ = A (M B^T)."""
+def residual_expanded_r2l(L, W, R, Gl, psi, E, alpha):
+    """Mirror of residual_expanded_l2r: [M ; alpha F^T Z_c], an
+    (m_l + r) x (d m_r) matrix."""
     ml, d, mr = psi.shape
-    s2, V, k = _gram_spectrum(Gram, kmax, eps)
-    Vk = V[:, :k]
-    X = psi.reshape(ml, d * mr) @ Vk
-    na = nbr.reshape(-1, ml) @ X
-    return Vk.T.reshape(k, d, mr), na.reshape(nbr.shape[0], nbr.shape[1], k), np.sqrt(s2), float(np.sum(s2[k:]))
+    wl = W.shape[0]
+    Mm = psi.reshape(ml, d * mr)
+    Pm = expansion_term_r2l(R, W, psi, 1.0).reshape(wl * ml, d * mr)
+    Zc = np.vstack([-E * Mm, Pm])
+    F = _metric_factor(residual_metric_r2l(L, Gl))
+    return np.vstack([Mm, alpha * (F.T @ Zc)])

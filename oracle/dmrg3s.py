@@ -29,9 +29,10 @@ not code):
   * expansion="residual" replaces P by the exact residual H Psi - E Psi
     (the Sec. 4 opening), with E the eigenvalue lambda* of step 1, its far
     side projected onto the current basis and its near side exact (see
-    contract.residual_gram_l2r); the truncation then works on the Gram
-    matrix of the expanded tensor, whose eigenvalues are resolved down to
-    n u s_0^2;
+    contract.residual_expanded_l2r); its right-side vectors are written on
+    an orthonormal basis of their span (metric eigenvalues at or below
+    n u lambda_max are exact linear dependences), and the expanded tensor is
+    then truncated by the same SVD and the same eps rule as the cheap term;
   * one sweep is right-to-left over sites l..2 followed by left-to-right over
     sites 1..l-1 (the initial state is left-canonical with its centre on
     site l); E_s is the last lambda* of sweep s and the run stops when
@@ -116,12 +117,12 @@ class DMRG3S:
     def step_r2l(self, i):
         lam, psi, nmv = self.eigensolve(i)
         if self.expansion == "residual":
-            Gm = C.residual_gram_r2l(self.Lenv[i], self.W[i], self.Renv[i + 1], self.H2L[i], psi, lam, self.alpha)
-            B, A, s, disc = C.truncate_gram_r2l(Gm, psi, self.M[i - 1], self.budget[i], self.eps)
+            Mt = C.residual_expanded_r2l(self.Lenv[i], self.W[i], self.Renv[i + 1], self.H2L[i], psi, lam,
+                                         self.alpha)
         else:
             P = C.expansion_term_r2l(self.Renv[i + 1], self.W[i], psi, self.alpha)
             Mt = C.expanded_tensor_r2l(psi, P)
-            B, A, s, disc = C.truncate_r2l(Mt, psi, self.M[i - 1], self.budget[i], self.eps)
+        B, A, s, disc = C.truncate_r2l(Mt, psi, self.M[i - 1], self.budget[i], self.eps)
         A = A / np.linalg.norm(A)
         self.M[i] = B
         self.M[i - 1] = A
@@ -137,12 +138,12 @@ class DMRG3S:
     def step_l2r(self, i):
         lam, psi, nmv = self.eigensolve(i)
         if self.expansion == "residual":
-            Gm = C.residual_gram_l2r(self.Lenv[i], self.W[i], self.Renv[i + 1], self.H2R[i + 1], psi, lam, self.alpha)
-            A, B, s, disc = C.truncate_gram_l2r(Gm, psi, self.M[i + 1], self.budget[i + 1], self.eps)
+            Mt = C.residual_expanded_l2r(self.Lenv[i], self.W[i], self.Renv[i + 1], self.H2R[i + 1], psi, lam,
+                                         self.alpha)
         else:
             P = C.expansion_term_l2r(self.Lenv[i], self.W[i], psi, self.alpha)
             Mt = C.expanded_tensor_l2r(psi, P)
-            A, B, s, disc = C.truncate_l2r(Mt, psi, self.M[i + 1], self.budget[i + 1], self.eps)
+        A, B, s, disc = C.truncate_l2r(Mt, psi, self.M[i + 1], self.budget[i + 1], self.eps)
         B = B / np.linalg.norm(B)
         self.M[i] = A
         self.M[i + 1] = B

@@ -1,7 +1,7 @@
 """Lanczos eigensolver for the smallest eigenpair (oracle; test infrastructure only).
 
-The paper only asks for "an eigensolver targeting the smallest eigenvalue"
-(Sec. 5, step 1).  This is the textbook Lanczos three-term recurrence with
+Step 1 of the site update (Sec. 5) needs only a solver for the lowest
+eigenpair of H_eff.  This is the textbook Lanczos three-term recurrence with
 full re-orthogonalisation against all previous Krylov vectors (classical
 Gram-Schmidt applied twice), a Krylov basis of at most `kmax` vectors and an
 explicit restart from the current Ritz vector.  Convergence: the residual

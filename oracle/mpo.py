@@ -153,6 +153,22 @@ def worked_example_mpo():
     return [W1, W2]
 
 
+def mpo_apply(mpo, v):
+    """H v for the operator of an open-boundary MPO without forming its
+    matrix (v has d^l entries, site 1 the most significant digit): the sites
+    are applied one at a time to the not yet reached digits of v, keeping the
+    open MPO channel as the leading index."""
+    d = mpo[0].shape[2]
+    X = np.asarray(v, dtype=np.float64).reshape(1, 1, -1)      # [w, done digits, remaining digits]
+    for W in mpo:
+        w, n_done, n_rest = X.shape
+        X = X.reshape(w, n_done, d, n_rest // d)                 # [w, O, t, rest]
+        Y = np.tensordot(W, X, axes=([0, 3], [0, 2]))            # [v, s, O, rest]
+        X = Y.transpose(0, 2, 1, 3).reshape(W.shape[1], n_done * d, n_rest // d)
+    assert X.shape[0] == 1 and X.shape[2] == 1
+    return X.reshape(-1)
+
+
 def mpo_to_dense(mpo):
     """Contract an open-boundary MPO into the full d^l x d^l matrix
     (site 1 is the most significant digit of the basis index)."""

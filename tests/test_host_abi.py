@@ -67,6 +67,22 @@ def test_product_mpo_builders_equal_oracle():
         assert np.abs(MPO.mpo_to_dense(got) - MPO.mpo_to_dense(ref)).max() < 1e-14
 
 
+def test_product_cylinder_mpo_equals_oracle_4x2():
+    """The product's w = 18 cylinder MPO (its own channel order) applies the
+    same operator as the oracle's on the 4 x 2 cylinder, whose length bonds
+    have range 4 (the oracle's builder is pinned to Fock-space ED there)."""
+    from oracle import mpo as MPO
+    from paper_1501_05504_amd import abi
+    got = abi.hubbard_cylinder_mpo(4, 2, 1.0, 4.0)
+    ref = MPO.hubbard_cylinder_mpo(4, 2, 1.0, 4.0)
+    assert [g.shape for g in got] == [r.shape for r in ref]
+    rng = np.random.default_rng(29)
+    for _ in range(2):
+        v = rng.standard_normal(4 ** 8)
+        a, b = MPO.mpo_apply(got, v), MPO.mpo_apply(ref, v)
+        assert np.abs(a - b).max() < 1e-12 * np.abs(b).max()
+
+
 def test_product_mpo_with_chemical_potential():
     from oracle import mpo as MPO
     from paper_1501_05504_amd import abi

@@ -56,6 +56,55 @@ def test_missing_jordan_wigner_string_is_caught(monkeypatch):
         pins.test_long_range_hopping_mpo_equals_fock_ed()
 
 
+def test_missing_range4_string_is_caught(monkeypatch):
+    """Identity in place of F only on the last string step of a range-4
+    hop: the range-3 pin on the 4 x 1 ring cannot see it, the 4 x 2 cylinder
+    pin must."""
+    ops = MPO.fermion_site()
+    good = MPO._finite_state_mpo
+
+    def bad(l, d, starts, strings, finishers, coupling, onsite, R):
+        mpo = good(l, d, starts, strings, finishers, coupling, onsite, R)
+        nk = len(starts)
+        if d == 4 and R >= 4:
+            for W in mpo:
+                for k in range(nk):
+                    a, b = 1 + 2 * nk + k, 1 + 3 * nk + k      # channels of ranges 3 and 4
+                    if a < W.shape[0] and b < W.shape[1] and np.abs(W[a, b]).max() > 0:
+                        W[a, b] = ops["I"]
+        return mpo
+    monkeypatch.setattr(MPO, "_finite_state_mpo", bad)
+    pins.test_long_range_hopping_mpo_equals_fock_ed()
+    bonds = MPO.cylinder_bonds(4, 2)
+    hop = {b: 1.0 + 0.1 * k for k, b in enumerate(bonds)}
+    H_unit = pins.ed.hubbard_hamiltonian(8, {b: 1.0 for b in bonds}, U=4.0)
+    with pytest.raises(AssertionError):
+        pins.test_cylinder_4x2_mpo_equals_fock_ed((bonds, hop, H_unit, H_unit))
+
+
+def test_gram_floor_in_residual_truncation_is_caught(monkeypatch):
+    """A residual truncation that drops values below the FP64 Gram
+    resolution sqrt(n u) s_0 fails the dense-residual SVD pin."""
+    good = C.truncation_size
+
+    def floored(s, kmax, eps):
+        return good(s, kmax, max(eps, np.sqrt(s.size * np.finfo(np.float64).eps)))
+    monkeypatch.setattr(C, "truncation_size", floored)
+    with pytest.raises(AssertionError):
+        pins.test_residual_expanded_tensor_equals_dense_residual_svd("l2r", "heisenberg")
+
+
+def test_residual_metric_without_square_root_is_caught(monkeypatch):
+    good = C._metric_factor
+
+    def bad(G):
+        F = good(G)
+        return F / np.sqrt(np.linalg.norm(F, axis=0))
+    monkeypatch.setattr(C, "_metric_factor", bad)
+    with pytest.raises(AssertionError):
+        pins.test_residual_expanded_tensor_equals_dense_residual_svd("r2l", "hubbard")
+
+
 def test_wrong_hopping_sign_is_caught(monkeypatch):
     ops = MPO.fermion_site()
     good = MPO._finite_state_mpo

@@ -120,6 +120,77 @@ def test_cylinder_mpo_bond_dimension():
     assert len(bonds) == 4 * 16 + 4 * 15
 
 
+@pytest.fixture(scope="module")
+def cyl4x2():
+    """Bonds of the 4 x 2 cylinder (column-major path), bond-specific
+    amplitudes, and the Fock-space ED Hamiltonians of both."""
+    bonds = MPO.cylinder_bonds(4, 2)
+    hop = {b: 1.0 + 0.1 * k for k, b in enumerate(bonds)}
+    H_unit = ed.hubbard_hamiltonian(8, {b: 1.0 for b in bonds}, U=4.0)
+    H_var = ed.hubbard_hamiltonian(8, hop, U=2.5)
+    return bonds, hop, H_unit, H_var
+
+
+def _sector_ground_energy_of_mpo(W, l, n_part, two_sz):
+    """Lowest eigenvalue of the MPO's operator in one (N, 2Sz) sector, by
+    Lanczos on MPO-vector products (the 4^l matrix is never formed)."""
+    import scipy.sparse.linalg as spla
+    N, S = ed.particle_numbers(l)
+    idx = np.nonzero((N == n_part) & (S == two_sz))[0]
+    full = np.zeros(4 ** l)
+
+    def mv(x):
+        full[:] = 0.0
+        full[idx] = np.ravel(x)
+        return MPO.mpo_apply(W, full)[idx]
+    op = spla.LinearOperator((idx.size, idx.size), matvec=mv, dtype=np.float64)
+    return float(spla.eigsh(op, k=1, which="SA", tol=1e-13)[0][0])
+
+
+def test_cylinder_4x2_mpo_equals_fock_ed(cyl4x2):
+    """The width-4 cylinder on the column-major path has ring bonds of range
+    1 and 3 and length bonds of range 4, so its w = 18 MPO carries
+    Jordan-Wigner strings across up to three sites.  On the 4 x 2 cylinder
+    (8 sites, 4^8 states) the MPO applied to random vectors equals Fock-space
+    ED, for the uniform model and for bond-specific amplitudes (so that an
+    exchanged bond would show)."""
+    bonds, hop, H_unit, H_var = cyl4x2
+    assert max(j - i for i, j in bonds) == 4
+    assert sorted({j - i for i, j in bonds}) == [1, 3, 4]
+    rng = np.random.default_rng(17)
+    for W, H in [(MPO.hubbard_cylinder_mpo(4, 2, t=1.0, U=4.0), H_unit),
+                 (MPO.fermion_hopping_mpo(8, hop, U=2.5), H_var)]:
+        assert max(w.shape[1] for w in W) == 18
+        for _ in range(2):
+            v = rng.standard_normal(4 ** 8)
+            ref = H @ v
+            assert np.abs(MPO.mpo_apply(W, v) - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_cylinder_4x2_ground_energies(cyl4x2):
+    """U = 0, N = 6 (3 up, 3 down): the single-particle levels of the 4 x 2
+    cylinder are the ring's -2 cos(2 pi k / 4) plus or minus the rung's 1,
+    i.e. -3, -1 (three times), 1 (three times), 3, so E0 = 2 (-3 - 1 - 1) =
+    -10.  U = 4: the MPO's sector ground energy equals sector ED
+    (-7.4170990096)."""
+    bonds, _, H_unit, _ = cyl4x2
+    e0 = _sector_ground_energy_of_mpo(MPO.hubbard_cylinder_mpo(4, 2, 1.0, 0.0), 8, 6, 0)
+    assert abs(e0 + 10.0) < 1e-10
+    assert abs(ed.free_fermion_energy(8, {b: 1.0 for b in bonds}, 3, 3) + 10.0) < 1e-12
+    e4 = _sector_ground_energy_of_mpo(MPO.hubbard_cylinder_mpo(4, 2, 1.0, 4.0), 8, 6, 0)
+    N, S = ed.particle_numbers(8)
+    e_ed = ed.ground_energy(H_unit, mask=(N == 6) & (S == 0))
+    assert abs(e4 - e_ed) < 1e-10
+    assert abs(e_ed + 7.4170990096) < 1e-9
+
+
+def test_mpo_apply_equals_dense_matrix():
+    """The MPO-vector product used above equals the contracted matrix."""
+    W = MPO.hubbard_chain_mpo(4, 1.0, 3.0)
+    v = synth.gaussian(4 ** 4, 19)
+    assert np.abs(MPO.mpo_apply(W, v) - MPO.mpo_to_dense(W) @ v).max() < 1e-13
+
+
 # ---------------------------------------------------------------- closed forms
 def test_heisenberg_closed_forms():
     for l, e0 in [(2, -0.75), (4, -0.75 - math.sqrt(3) / 2)]:
@@ -635,37 +706,112 @@ def test_residual_gram_equals_bruteforce(direction, model):
     assert np.allclose(proj, heff, atol=1e-12)
 
 
-def test_truncate_gram_equals_svd_truncation():
-    """With the Gram matrix of an explicit M~ the Gram truncation keeps the
-    same subspace, singular values and neighbour as the SVD truncation."""
-    ml, d, mr, width = 4, 2, 5, 20
-    Mt = synth.gaussian((ml * d, width), 31)
-    psi = Mt[:, :mr].reshape(ml, d, mr).copy()
-    nbr = synth.gaussian((mr, d, 3), 32)
-    A1, B1, s1, d1 = C.truncate_l2r(Mt, psi, nbr, 5, 1e-14)
-    A2, B2, s2, d2 = C.truncate_gram_l2r(Mt @ Mt.T, psi, nbr, 5, 1e-14)
-    P1 = A1.reshape(ml * d, -1) @ A1.reshape(ml * d, -1).T
-    P2 = A2.reshape(ml * d, -1) @ A2.reshape(ml * d, -1).T
-    assert np.allclose(P1, P2, atol=1e-10)
-    assert np.allclose(s1, s2[:s1.size], atol=1e-10 * s1[0])
-    assert abs(d1 - d2) < 1e-10 * np.sum(s1 ** 2)
-    # the neighbour matches up to the sign of each kept vector
-    sign = np.sign(np.sum(A1.reshape(ml * d, -1) * A2.reshape(ml * d, -1), axis=0))
-    assert np.allclose(B1, B2 * sign[:, None, None], atol=1e-10)
-    Mr = synth.gaussian((width, d * mr), 33)
-    psi_r = Mr[:ml].reshape(ml, d, mr).copy()
-    nbr_r = synth.gaussian((3, d, ml), 34)
-    B1, A1, s1, d1 = C.truncate_r2l(Mr, psi_r, nbr_r, 6, 1e-14)
-    B2, A2, s2, d2 = C.truncate_gram_r2l(Mr.T @ Mr, psi_r, nbr_r, 6, 1e-14)
-    V1, V2 = B1.reshape(-1, d * mr), B2.reshape(-1, d * mr)
-    assert np.allclose(V1.T @ V1, V2.T @ V2, atol=1e-10)
-    assert abs(d1 - d2) < 1e-10 * np.sum(s1 ** 2)
+def _spread_psi(psi, smin, seed):
+    """psi with its (m_l d) x m_r singular values replaced by a geometric
+    sequence from 1 down to smin (same singular vectors)."""
+    ml, d, mr = psi.shape
+    U, s, Vt = np.linalg.svd(psi.reshape(ml * d, mr), full_matrices=False)
+    s = np.geomspace(1.0, smin, s.size)
+    return ((U * s) @ Vt).reshape(ml, d, mr)
+
+
+@pytest.mark.parametrize("direction", ["l2r", "r2l"])
+@pytest.mark.parametrize("model", ["heisenberg", "hubbard"])
+def test_residual_expanded_tensor_equals_dense_residual_svd(direction, model):
+    """The exact-residual expanded tensor written on an orthonormal basis of
+    its right-side (left-side) vectors has the singular values of the same
+    tensor built from the dense residual (H - E)|Psi> in the full Hilbert
+    space of the far side (H from exact diagonalisation's own construction,
+    far side projected onto the state's basis); its Gram matrix is the
+    environment-built one.  The spectra span 1 ... 1e-9 to 1e-13, so a cut
+    resolved only to sqrt(n u) s_0 (the resolution of an FP64 Gram matrix)
+    would keep fewer states than the eps = 1e-14 rule, which must keep the
+    same number as the dense SVD."""
+    if model == "heisenberg":
+        l, d, m, center = 8, 2, 8, 3
+        mpo = MPO.heisenberg_mpo(l)
+        H = ed.spin_chain_hamiltonian(l, {(i, i + 1): 1.0 for i in range(l - 1)}).toarray()
+    else:
+        l, d, m, center = 4, 4, 5, 1
+        mpo = MPO.hubbard_chain_mpo(l, t=1.0, U=4.0)
+        H = ed.hubbard_hamiltonian(l, {(i, i + 1): 1.0 for i in range(l - 1)}, U=4.0).toarray()
+    M = _mixed_canonical(synth.random_mps(l, d, m, seed=23), center)
+    M[center] = _spread_psi(M[center], 1e-5, 24)
+    psi = M[center]
+    ml, _, mr = psi.shape
+    v = state_vector(M)
+    E, alpha = 0.37, 1e-7
+    z = H @ v - E * v
+    Lenv, Renv = _envs(mpo, M, center)
+    Phi, Bf = _left_basis(M, center), _right_basis(M, center + 1)
+    if direction == "l2r":
+        Zl = np.tensordot(Phi, z.reshape(Phi.shape[0], d, -1), axes=([0], [0])).reshape(ml * d, -1)
+        dense = np.hstack([psi.reshape(ml * d, mr), alpha * Zl])
+        G = np.ones((1, 1, 1, 1))
+        for j in range(l - 1, center, -1):
+            G = C.update_right_h2(G, mpo[j], M[j])
+        Mt = C.residual_expanded_l2r(Lenv, mpo[center], Renv, G, psi, E, alpha)
+        gram = C.residual_gram_l2r(Lenv, mpo[center], Renv, G, psi, E, alpha)
+        assert np.abs(Mt @ Mt.T - gram).max() < 1e-14 * np.abs(gram).max()
+        Pm, Pd = Mt, dense
+    else:
+        Zr = np.tensordot(z.reshape(-1, d, Bf.shape[1]), Bf, axes=([2], [1])).reshape(-1, d * mr)
+        dense = np.vstack([psi.reshape(ml, d * mr), alpha * Zr])
+        G = np.ones((1, 1, 1, 1))
+        for j in range(center):
+            G = C.update_left_h2(G, mpo[j], M[j])
+        Mt = C.residual_expanded_r2l(Lenv, mpo[center], Renv, G, psi, E, alpha)
+        gram = C.residual_gram_r2l(Lenv, mpo[center], Renv, G, psi, E, alpha)
+        assert np.abs(Mt.T @ Mt - gram).max() < 1e-14 * np.abs(gram).max()
+        Pm, Pd = Mt.T, dense.T
+    s = np.linalg.svd(Pm, compute_uv=False)
+    sd = np.linalg.svd(Pd, compute_uv=False)
+    n = min(s.size, sd.size)
+    assert np.abs(s[:n] - sd[:n]).max() < 2e-15 * sd[0]
+    k = C.truncation_size(s, 1000, 1e-14)
+    kd = C.truncation_size(sd, 1000, 1e-14)
+    assert k == kd
+    # the spectrum reaches far below the Gram resolution
+    floor = math.sqrt(Pm.shape[0] * np.finfo(np.float64).eps) * s[0]
+    assert np.count_nonzero((s[:k] < floor)) >= 3
+    assert s[k - 1] < 1e-8 * s[0]
+    # the kept subspace is the dense one (a clear gap follows the kept values)
+    U = np.linalg.svd(Pm, full_matrices=False)[0][:, :k]
+    Ud = np.linalg.svd(Pd, full_matrices=False)[0][:, :k]
+    if k < n:
+        assert sd[k] < 1e-2 * sd[k - 1]
+        assert np.abs(U @ U.T - Ud @ Ud.T).max() < 1e-8
+
+
+def test_truncation_keeps_every_value_above_eps():
+    """Steps 4-5 with a prescribed spectrum 1 ... 1e-12 (twenty values) on a
+    rank-20 matrix: the SVD truncation keeps exactly the twenty (every one
+    above 1e-14 s_0), reproduces the values, and drops the null part."""
+    rng = np.random.default_rng(41)
+    n, width, r = 40, 70, 20
+    s_true = np.geomspace(1.0, 1e-12, r)
+    Q1 = np.linalg.qr(rng.standard_normal((n, r)))[0]
+    Q2 = np.linalg.qr(rng.standard_normal((width, r)))[0]
+    Mt = (Q1 * s_true) @ Q2.T
+    psi = Mt[:, :10].reshape(8, 5, 10).copy()
+    nbr = rng.standard_normal((10, 5, 6))
+    A, B, s, disc = C.truncate_l2r(Mt, psi, nbr, kmax=100, eps=1e-14)
+    assert A.shape[2] == r
+    assert np.abs(s[:r] - s_true).max() < 1e-15
+    assert s[r:].max() < 1e-15
+    Ak = A.reshape(n, r)
+    assert np.abs(Ak @ Ak.T - Q1 @ Q1.T).max() < 1e-3     # the 1e-12 direction is resolved to u / 1e-12
+    assert np.abs(Ak.T @ Ak - np.eye(r)).max() < 1e-14
+    A5, _, _, disc5 = C.truncate_l2r(Mt, psi, nbr, kmax=5, eps=1e-14)
+    assert A5.shape[2] == 5 and abs(disc5 - np.sum(s_true[5:] ** 2)) < 1e-15
+    Ae, _, _, _ = C.truncate_l2r(Mt, psi, nbr, kmax=100, eps=1e-6)
+    assert Ae.shape[2] == np.count_nonzero(s_true > 1e-6)
 
 
 def test_dmrg3s_residual_expansion(heis12_ed):
     """The exact-residual expansion reaches ED at the exact bond, and at a
     truncated bond its converged energy is as good as the cheap term's
-    (Sec. 4.2: the two work essentially equally well)."""
+    (Sec. 4.2 finds the two terms about equally effective)."""
     l = 12
     run = DMRG3S(MPO.heisenberg_mpo(l), synth.random_mps(l, 2, 64), mmax=64, alpha0=1e-3, expansion="residual")
     E, _ = run.run(tol=1e-12, max_sweeps=12)
