@@ -121,8 +121,10 @@ d3s_status d3s_set_eigensolver(d3s_ctx ctx, int kind, int jacobi_max_n);
  * matrices of size n, column-major, stored one after the other in A
  * (device, n*n*batch), are replaced by their eigenvectors (columns) and W
  * (device, n*batch) receives the eigenvalues in ascending order; the solver
- * is the one chosen by d3s_set_eigensolver.  Synchronises; D3S_EDEVICE if an
- * eigensolve did not converge. */
+ * is the one chosen by d3s_set_eigensolver.  Each matrix is divided by its
+ * largest diagonal entry before the solve and its eigenvalues scaled back
+ * (rocSOLVER's divide and conquer loses accuracy in proportion to a small
+ * matrix norm).  Synchronises; D3S_EDEVICE if an eigensolve did not converge. */
 d3s_status d3s_eig_batched(d3s_ctx ctx, int n, int batch, double* A, double* W);
 /* Split-K of GEMMs whose tiles cannot fill the device (default on; the
  * partial products are summed in a fixed order, so results stay
@@ -178,14 +180,19 @@ d3s_status d3s_expand_subspace(d3s_ctx ctx, d3s_dir dir, int ml, int d, int mr, 
  *        site_out = V_k^T as (k, d, m_r).  The neighbour A (nbr_other x m_l)
  *        becomes nbr_out = A (psi_mat V_k), nbr_other x k.
  * k = min(kmax, #{ j : s_j > rel_cutoff * s_0 }).  Singular values come from
- * the FP64 Gram matrix of Mtilde on its smaller side and rocSOLVER's dsyevd.
+ * the FP64 Gram matrix of Mtilde on the site side (an MFMA GEMM) and its
+ * eigen-decomposition, refined by deflated passes wherever a single Gram
+ * matrix cannot resolve a value that the cut may keep (one pass resolves
+ * s_j down to about sqrt(n u) s_0), so the cut is the SVD's down to the
+ * FP64 rounding of the singular values (about n u s_0).
  * nbr_in may be NULL, with nbr_other = m_r (L2R) or m_l (R2L): then nbr_out
  * is U_k^T psi_mat = S_k V_k^T (k x m_r), or psi_mat V_k = U_k S_k (m_l x k),
  * the truncated SVD split of a two-site tensor (Mtilde = psi = the two-site
  * tensor as (m_l d) x (d' m_r'), passed with m_r = d' m_r').
  * `renormalize` != 0 scales nbr_out to unit Frobenius norm.
- * s_host (host, may be NULL) receives the min(m_l d, width) (L2R) or
- * min(width, d m_r) (R2L) singular values, descending.  *k_out (host) and
+ * s_host (host, may be NULL) receives n = m_l d (L2R) or d m_r (R2L)
+ * singular values, descending (zeros beyond the rank; values below the
+ * resolution the cut needed are estimates).  *k_out (host) and
  * *discarded (host, sum of the dropped s_j^2) are set.  Synchronises.
  */
 d3s_status d3s_truncate(d3s_ctx ctx, d3s_dir dir, int ml, int d, int mr, long width,
@@ -248,18 +255,28 @@ d3s_status d3s_apply_cwf(d3s_ctx ctx, d3s_prec prec, int mlp, int mr, int wr, co
  *   (ml, wl*wl, ml).  L, R: the site's ordinary environments; energy: E
  *   (the eigenvalue of the site's local problem).  Costs O((w m)^2 d m) and
  *   a metric of (1+w) m squared: meant for m of a few hundred.  Asynchronous.
- * d3s_truncate_gram: steps 4-5 of the site update from such a Gram matrix
- *   (overwritten): as d3s_truncate, with the same outputs, cutoff rule and
- *   neighbour handling (nbr_in may be NULL).  Synchronises.
+ * d3s_residual_expand: the same expanded tensor written out on an
+ *   orthonormal basis of the far-side vectors, so that d3s_truncate applies
+ *   the same cut as for the expansion term of eq. subexp-ourt.  The metric Q
+ *   of those vectors ((1+w) m square) is factored as F F^T through its
+ *   eigen-decomposition; its eigenvalues at or below n_Q u lambda_max are
+ *   exact linear dependences (the far-side operator of the completed MPO
+ *   channel is the identity) and are dropped, leaving r columns of F.
+ *   L2R: Mtilde = [M | alpha Zc F], (ml*d) x (mr + r), *extent = mr + r
+ *   (the row length); R2L: Mtilde = [M ; alpha F^T Zc], (ml + r) x (d*mr),
+ *   *extent = ml + r (the row count).  Mtilde needs room for
+ *   (ml*d) x ((2+wr)*mr) (L2R) or ((2+wl)*ml) x (d*mr) (R2L) doubles.
+ *   Mtilde Mtilde^T (Mtilde^T Mtilde) equals d3s_residual_gram's matrix.
+ *   Synchronises (the rank r is read back).
  */
 d3s_status d3s_update_env_h2(d3s_ctx ctx, d3s_dir dir, int ml, int d, int mr, int wl, int wr,
                              const double* env_in, const double* W, const double* site, double* env_out);
 d3s_status d3s_residual_gram(d3s_ctx ctx, d3s_dir dir, int ml, int d, int mr, int wl, int wr, const double* L,
                              const double* R, const double* h2, const double* W, const double* psi, double energy,
                              double alpha, double* gram);
-d3s_status d3s_truncate_gram(d3s_ctx ctx, d3s_dir dir, int ml, int d, int mr, double* gram, const double* psi,
-                             int kmax, double rel_cutoff, const double* nbr_in, long nbr_other, double* site_out,
-                             double* nbr_out, int renormalize, double* s_host, int* k_out, double* discarded);
+d3s_status d3s_residual_expand(d3s_ctx ctx, d3s_dir dir, int ml, int d, int mr, int wl, int wr, const double* L,
+                               const double* R, const double* h2, const double* W, const double* psi, double energy,
+                               double alpha, double* Mtilde, long* extent);
 
 /*
  * Environment update (Sec. 2: L_i = L_{i-1} A_i^+ W_i A_i, R_i = R_{i+1} B_i^+ W_i B_i;
@@ -367,6 +384,23 @@ d3s_status d3s_apply_heff_blocks(d3s_ctx ctx, d3s_block_plan plan, d3s_prec prec
  * pointers, caller-owned.  Asynchronous. */
 d3s_status d3s_expand_subspace_blocks(d3s_ctx ctx, d3s_block_plan plan, d3s_dir dir, const double* env,
                                       const double* W, const double* psi, double alpha, double* Mt);
+/* Block-diagonal truncation of an expanded tensor on the plan's bonds (steps
+ * 4-5 of the site update, Sec. 5; the paper uses U(1) symmetries in Sec. 7):
+ * Mt is [psi | alpha P] (L2R, (ml*d) x ((1+wr)*mr)) or [psi ; alpha P] (R2L,
+ * ((1+wl)*ml) x (d*mr)) as written by d3s_expand_subspace_blocks.  Every
+ * charge Q of the new bond has its own block of Mt (the rows (a,s) with
+ * q_a + q_s = Q and the columns of charge Q, or the mirror); each is
+ * truncated as in d3s_truncate (same cut: k = min(kmax, #{s_j > rel_cutoff *
+ * s_0}) over all sectors together, s_0 the largest of all), and the kept
+ * states are ordered by sector.  site_out: L2R (ml*d) x k, R2L k x (d*mr);
+ * nbr_out as in d3s_truncate with the neighbour nbr_in (L2R: mr x nbr_other,
+ * R2L: nbr_other x ml).  new_q / new_dim (host, room for maxsec sectors of
+ * nq charges) receive the sectors of the new bond, *new_nsec their number;
+ * D3S_EINVAL if there are more than maxsec.  Synchronises. */
+d3s_status d3s_truncate_blocks(d3s_ctx ctx, d3s_block_plan plan, d3s_dir dir, const double* Mt, const double* psi,
+                               int kmax, double rel_cutoff, const double* nbr_in, long nbr_other, double* site_out,
+                               double* nbr_out, int renormalize, int maxsec, int* new_nsec, int* new_q,
+                               int* new_dim, int* k_out, double* discarded);
 /* Block-sparse environment update with the site tensor on the plan's bonds
  * (Sec. 2 definitions of L_i and R_i): the same FP64 result as
  * d3s_update_env on symmetric inputs.  L2R: env_in = L (ml, wl, ml),

@@ -94,9 +94,8 @@ _update_env = _sig("d3s_update_env", c_int, [c_void_p, c_int] + [c_int] * 5 + [c
 _update_env_h2 = _sig("d3s_update_env_h2", c_int, [c_void_p, c_int] + [c_int] * 5 + [c_void_p] * 4)
 _residual_gram = _sig("d3s_residual_gram", c_int, [c_void_p, c_int] + [c_int] * 5 + [c_void_p] * 5 +
                       [c_double, c_double, c_void_p])
-_truncate_gram = _sig("d3s_truncate_gram", c_int, [c_void_p, c_int, c_int, c_int, c_int, c_void_p, c_void_p,
-                                                   c_int, c_double, c_void_p, c_long, c_void_p, c_void_p, c_int,
-                                                   c_double_p, c_int_p, c_double_p])
+_residual_expand = _sig("d3s_residual_expand", c_int, [c_void_p, c_int] + [c_int] * 5 + [c_void_p] * 5 +
+                        [c_double, c_double, c_void_p, ctypes.POINTER(c_long)])
 _lanczos = _sig("d3s_lanczos", c_int, [c_void_p, c_int] + [c_int] * 5 + [c_void_p] * 4 +
                 [c_double, c_int, c_int, c_double_p, c_int_p])
 _energy = _sig("d3s_energy", c_int, [c_void_p] + [c_int] * 5 + [c_void_p] * 4 + [c_double_p])
@@ -124,6 +123,9 @@ _plan_destroy = _sig("d3s_block_plan_destroy", None, [c_void_p, c_void_p])
 _apply_blocks = _sig("d3s_apply_heff_blocks", c_int, [c_void_p, c_void_p, c_int] + [c_void_p] * 5 + [c_int])
 _expand_blocks = _sig("d3s_expand_subspace_blocks", c_int,
                       [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_double, c_void_p])
+_trunc_blocks = _sig("d3s_truncate_blocks", c_int, [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_int, c_double,
+                                                    c_void_p, c_long, c_void_p, c_void_p, c_int, c_int, c_int_p,
+                                                    c_int_p, c_int_p, c_int_p, c_double_p])
 _env_blocks = _sig("d3s_update_env_blocks", c_int, [c_void_p, c_void_p, c_int] + [c_void_p] * 4)
 _spin_charges = _sig("d3s_mpo_spin_charges", c_int, [c_int, c_int_p])
 _fermion_charges = _sig("d3s_mpo_fermion_charges", c_int, [c_int, c_int_p])
@@ -427,28 +429,29 @@ class Context:
         return self._check(_residual_gram(self.h, direction, ml, d, mr, wl, wr, _ptr(L), _ptr(R), _ptr(h2),
                                           _ptr(W), _ptr(psi), float(energy), float(alpha), _ptr(gram)))
 
-    def truncate_gram(self, direction, gram, psi, kmax, rel_cutoff, nbr, site_out, nbr_out, renormalize=True):
-        """Truncation from the Gram matrix (overwritten) of the expanded tensor;
-        returns (k, discarded, singular values) like truncate."""
+    def residual_expand(self, direction, L, R, h2, W, psi, energy, alpha, Mt):
+        """The exact-residual expanded tensor on an orthonormal basis of its
+        far-side vectors, written into Mt (capacity (ml d)(2+wr) mr for L2R,
+        (2+wl) ml (d mr) for R2L); returns its row length (L2R, mr + r) or row
+        count (R2L, ml + r).  Pass the matrix it fills to truncate()."""
         self._sync_stream()
         ml, d, mr = psi.shape
+        wl, wr = W.shape[0], W.shape[1]
         f = torch.float64
-        n = ml * d if direction == L2R else d * mr
-        side = mr if direction == L2R else ml
-        other = nbr.numel() // side if nbr is not None else side
-        if nbr is not None:
-            _need(nbr, side * other, f, "nbr")
-        _need(gram, n * n, f, "gram")
+        _need(L, ml * wl * ml, f, "L")
+        _need(R, mr * wr * mr, f, "R")
+        _need(W, wl * wr * d * d, f, "W")
         _need(psi, ml * d * mr, f, "psi")
-        _need(site_out, n * min(kmax, n), f, "site_out")
-        _need(nbr_out, min(kmax, n) * other, f, "nbr_out")
-        s = (ctypes.c_double * n)()
-        k = c_int()
-        disc = c_double()
-        self._check(_truncate_gram(self.h, direction, ml, d, mr, _ptr(gram), _ptr(psi), kmax, float(rel_cutoff),
-                                   _ptr(nbr) if nbr is not None else None, other, _ptr(site_out), _ptr(nbr_out),
-                                   1 if renormalize else 0, s, ctypes.byref(k), ctypes.byref(disc)))
-        return k.value, disc.value, list(s)
+        if direction == L2R:
+            _need(h2, mr * wr * wr * mr, f, "h2")
+            _need(Mt, ml * d * (2 + wr) * mr, f, "Mt")
+        else:
+            _need(h2, ml * wl * wl * ml, f, "h2")
+            _need(Mt, (2 + wl) * ml * d * mr, f, "Mt")
+        ext = c_long()
+        self._check(_residual_expand(self.h, direction, ml, d, mr, wl, wr, _ptr(L), _ptr(R), _ptr(h2), _ptr(W),
+                                     _ptr(psi), float(energy), float(alpha), _ptr(Mt), ctypes.byref(ext)))
+        return ext.value
 
     def update_env(self, direction, env_in, W, site, env_out):
         self._sync_stream()
@@ -693,7 +696,7 @@ class BlockPlan:
         ra, rp = _ints(wq_right)
         self._keep += [pa, la, ra]
         self.ml, self.mr = int(sum(left_dim)), int(sum(right_dim))
-        self.d, self.wl, self.wr = d, wl, wr
+        self.d, self.wl, self.wr, self.nq = d, wl, wr, nq
         h = c_void_p()
         fl = c_double()
         nt = c_int()
@@ -734,6 +737,39 @@ class BlockPlan:
             _need(Mtilde, (1 + wl) * ml * d * mr, f, "Mtilde")
         return ctx._check(_expand_blocks(ctx.h, self.h, direction, _ptr(env), _ptr(W), _ptr(psi), float(alpha),
                                          _ptr(Mtilde)))
+
+    def truncate(self, direction, Mtilde, psi, kmax, rel_cutoff, nbr, site_out, nbr_out, renormalize=True,
+                 maxsec=4096):
+        """Block-diagonal d3s_truncate of [psi | alpha P] / [psi ; alpha P] on the
+        plan's bonds.  Returns (k, discarded, new sector charges (nsec x nq),
+        new sector dims)."""
+        import numpy as np
+        ctx = self.ctx
+        ctx._sync_stream()
+        ml, d, mr, wl, wr = self.ml, self.d, self.mr, self.wl, self.wr
+        f = torch.float64
+        _need(psi, ml * d * mr, f, "psi")
+        if direction == L2R:
+            other = nbr.numel() // mr
+            _need(Mtilde, ml * d * (1 + wr) * mr, f, "Mtilde")
+            _need(site_out, ml * d * min(kmax, ml * d), f, "site_out")
+        else:
+            other = nbr.numel() // ml
+            _need(Mtilde, (1 + wl) * ml * d * mr, f, "Mtilde")
+            _need(site_out, d * mr * min(kmax, d * mr), f, "site_out")
+        _need(nbr_out, min(kmax, ml * d if direction == L2R else d * mr) * other, f, "nbr_out")
+        nq = self.nq
+        nsec = c_int()
+        q = np.zeros(maxsec * nq, dtype=np.int32)
+        dims = np.zeros(maxsec, dtype=np.int32)
+        k = c_int()
+        disc = c_double()
+        ctx._check(_trunc_blocks(ctx.h, self.h, direction, _ptr(Mtilde), _ptr(psi), kmax, float(rel_cutoff),
+                                 _ptr(nbr), other, _ptr(site_out), _ptr(nbr_out), 1 if renormalize else 0, maxsec,
+                                 ctypes.byref(nsec), q.ctypes.data_as(c_int_p), dims.ctypes.data_as(c_int_p),
+                                 ctypes.byref(k), ctypes.byref(disc)))
+        ns = nsec.value
+        return k.value, disc.value, q[: ns * nq].reshape(ns, nq), dims[:ns]
 
     def update_env(self, direction, env_in, W, site, env_out):
         """Block-sparse d3s_update_env (FP64) for a site tensor on the plan's bonds."""

@@ -165,7 +165,28 @@ d3s_status d3s_eig_batched(d3s_ctx ctx, int n, int batch, double* A, double* W) 
   return guarded(ctx, [&] {
     D3S_REQUIRE(n >= 1 && batch >= 1, "n and batch must be >= 1");
     D3S_REQUIRE(A && W, "null pointer");
-    d3s::eig_batched_f64(&ctx->c, n, batch, A, W);
+    // one batch of equal size through the normalised solve of the truncations
+    d3s::EigPlan ep;
+    std::vector<int> ns(batch, n);
+    ep.npad.assign(batch, n);
+    ep.goff.resize(batch);
+    ep.voff.resize(batch);
+    ep.members.emplace_back();
+    for (int b = 0; b < batch; ++b) {
+      ep.goff[b] = (long)b * n * n;
+      ep.voff[b] = (long)b * n;
+      ep.members[0].push_back(b);
+    }
+    ep.bucket_n = {n};
+    ep.bucket_goff = {0};
+    ep.bucket_voff = {0};
+    ep.gtot = (long)batch * n * n;
+    ep.vtot = (long)batch * n;
+    std::vector<double> scale;
+    d3s::eig_run(&ctx->c, ep, ns, A, W, scale);
+    for (int b = 0; b < batch; ++b)
+      if (scale[b] != 1.0) d3s::scale_f64(&ctx->c, W + (long)b * n, n, scale[b]);
+    D3S_HIP(hipStreamSynchronize(ctx->c.stream));
     return D3S_OK;
   });
 }
@@ -305,24 +326,19 @@ d3s_status d3s_residual_gram(d3s_ctx ctx, d3s_dir dir, int ml, int d, int mr, in
   });
 }
 
-d3s_status d3s_truncate_gram(d3s_ctx ctx, d3s_dir dir, int ml, int d, int mr, double* gram, const double* psi,
-                             int kmax, double rel_cutoff, const double* nbr_in, long nbr_other, double* site_out,
-                             double* nbr_out, int renormalize, double* s_host, int* k_out, double* discarded) {
+d3s_status d3s_residual_expand(d3s_ctx ctx, d3s_dir dir, int ml, int d, int mr, int wl, int wr, const double* L,
+                               const double* R, const double* h2, const double* W, const double* psi, double energy,
+                               double alpha, double* Mtilde, long* extent) {
   return guarded(ctx, [&] {
     check_dir(dir);
-    D3S_REQUIRE(ml >= 1 && d >= 1 && mr >= 1 && nbr_other >= 1 && kmax >= 1, "dimensions must be >= 1");
-    D3S_REQUIRE(gram && psi && site_out && nbr_out && k_out && discarded, "null pointer");
-    D3S_REQUIRE(rel_cutoff >= 0.0, "rel_cutoff must be >= 0");
+    check_dims(ml, d, mr, wl, wr);
+    D3S_REQUIRE(wl <= 64 && wr <= 64, "residual: w must be <= 64");
+    D3S_REQUIRE(std::isfinite(energy) && std::isfinite(alpha), "energy and alpha must be finite");
     const long n = (dir == D3S_L2R) ? (long)ml * d : (long)d * mr;
-    D3S_REQUIRE(n <= 46340, "Gram dimension too large (n^2 must fit in int)");
-    if (!nbr_in)
-      D3S_REQUIRE(nbr_other == (dir == D3S_L2R ? mr : ml),
-                  "without a neighbour, nbr_other must be m_r (L2R) or m_l (R2L)");
-    d3s::TruncResult t = d3s::truncate_from_gram(&ctx->c, dir, ml, d, mr, gram, psi, kmax, rel_cutoff, nbr_in,
-                                                 nbr_other, site_out, nbr_out, s_host, renormalize != 0);
-    D3S_HIP(hipStreamSynchronize(ctx->c.stream));
-    *k_out = t.k;
-    *discarded = t.discarded;
+    const long ng = (dir == D3S_L2R) ? (long)(1 + wr) * mr : (long)(1 + wl) * ml;
+    D3S_REQUIRE(n <= 46340 && ng <= 46340, "residual: Gram or metric dimension too large");
+    D3S_REQUIRE(L && R && h2 && W && psi && Mtilde && extent, "null pointer");
+    *extent = d3s::op_residual_expand(&ctx->c, dir, ml, d, mr, wl, wr, L, R, h2, W, psi, energy, alpha, Mtilde);
     return D3S_OK;
   });
 }
@@ -536,6 +552,39 @@ d3s_status d3s_expand_subspace_blocks(d3s_ctx ctx, d3s_block_plan plan, d3s_dir 
     D3S_REQUIRE(Mt != psi && Mt != env, "Mt must not alias an input");
     D3S_REQUIRE(std::isfinite(alpha), "alpha must be finite");
     d3s::op_expand_blocks(&ctx->c, plan->h, dir, env, W, psi, alpha, Mt);
+    return D3S_OK;
+  });
+}
+
+d3s_status d3s_truncate_blocks(d3s_ctx ctx, d3s_block_plan plan, d3s_dir dir, const double* Mt, const double* psi,
+                               int kmax, double rel_cutoff, const double* nbr_in, long nbr_other, double* site_out,
+                               double* nbr_out, int renormalize, int maxsec, int* new_nsec, int* new_q,
+                               int* new_dim, int* k_out, double* discarded) {
+  return guarded(ctx, [&] {
+    D3S_REQUIRE(plan, "null plan");
+    D3S_REQUIRE(dir == D3S_L2R || dir == D3S_R2L, "dir must be D3S_L2R or D3S_R2L");
+    D3S_REQUIRE(Mt && psi && nbr_in && site_out && nbr_out, "null tensor pointer");
+    D3S_REQUIRE(new_nsec && new_q && new_dim && k_out && discarded, "null output pointer");
+    D3S_REQUIRE(kmax >= 1 && nbr_other >= 1 && maxsec >= 1, "kmax, nbr_other and maxsec must be >= 1");
+    D3S_REQUIRE(rel_cutoff >= 0.0, "rel_cutoff must be >= 0");
+    const d3s::BlockHeff& h = plan->h;
+    const bool l2r = dir == D3S_L2R;
+    const long width = l2r ? (long)(1 + h.wr) * h.mr : (long)(1 + h.wl) * h.ml;
+    d3s::TruncBlocksResult t =
+        d3s::op_truncate_blocks(&ctx->c, dir, h.left, h.right, h.d, h.pq.data(), l2r ? h.wqr.data() : h.wql.data(),
+                                l2r ? h.wr : h.wl, width, Mt, psi, kmax, rel_cutoff, nbr_in, nbr_other, site_out,
+                                nbr_out, renormalize != 0);
+    D3S_HIP(hipStreamSynchronize(ctx->c.stream));
+    const int ns = (int)t.dim.size();
+    D3S_REQUIRE(ns <= maxsec, "truncate_blocks: the new bond has more than maxsec sectors");
+    const int nq = h.left.nq;
+    for (int i = 0; i < ns; ++i) {
+      new_dim[i] = t.dim[i];
+      for (int k = 0; k < nq; ++k) new_q[i * nq + k] = t.q[(size_t)i * nq + k];
+    }
+    *new_nsec = ns;
+    *k_out = t.k;
+    *discarded = t.discarded;
     return D3S_OK;
   });
 }

@@ -97,8 +97,16 @@ void grouped_finalize(Ctx* c, GroupedPlan& g) {
   g.ntasks = (int)g.tasks.size();
   grouped_release(g);
   if (g.ntasks == 0) return;
-  D3S_HIP(hipMalloc((void**)&g.d_tasks, sizeof(GTask) * g.tasks.size()));
-  D3S_HIP(hipMalloc((void**)&g.d_segs, sizeof(GSeg) * std::max<size_t>(1, g.segs.size())));
+  if (g.table_slot >= 0) {
+    // a short-lived plan: both tables in one workspace slot
+    const size_t tb = (sizeof(GTask) * g.tasks.size() + 255) & ~(size_t)255;
+    char* base = (char*)ws_get(c, g.table_slot, tb + sizeof(GSeg) * std::max<size_t>(1, g.segs.size()));
+    g.d_tasks = (GTask*)base;
+    g.d_segs = (GSeg*)(base + tb);
+  } else {
+    D3S_HIP(hipMalloc((void**)&g.d_tasks, sizeof(GTask) * g.tasks.size()));
+    D3S_HIP(hipMalloc((void**)&g.d_segs, sizeof(GSeg) * std::max<size_t>(1, g.segs.size())));
+  }
   if (!g.segs.empty())
     D3S_HIP(hipMemcpyAsync(g.d_segs, g.segs.data(), sizeof(GSeg) * g.segs.size(), hipMemcpyHostToDevice,
                            c->stream));
@@ -121,8 +129,10 @@ void grouped_retile(Ctx* c, GroupedPlan& g) {
 }
 
 void grouped_release(GroupedPlan& g) {
-  if (g.d_tasks) (void)hipFree(g.d_tasks);
-  if (g.d_segs) (void)hipFree(g.d_segs);
+  if (g.table_slot < 0) {
+    if (g.d_tasks) (void)hipFree(g.d_tasks);
+    if (g.d_segs) (void)hipFree(g.d_segs);
+  }
   g.d_tasks = nullptr;
   g.d_segs = nullptr;
 }
@@ -958,8 +968,6 @@ struct SecGroup {
   std::vector<ColGroup> cols;
   int nrows = 0, ncols = 0;
   long xoff = 0;          // offset of the packed X_Q
-  int npad = 0, bucket = -1, idx = 0;
-  long goff = 0;          // offset of G_Q in the packed Gram buffer
   int keep = 0, new_off = 0;
 };
 
@@ -1044,151 +1052,41 @@ TruncBlocksResult op_truncate_blocks(Ctx* c, d3s_dir dir, const Sectors& left, c
   for (SecGroup& g : groups)
     if (g.nrows > 0 && g.ncols > 0) gs.push_back(std::move(g));
   if (gs.empty()) throw Error{D3S_ENUMERIC, "truncate: the expanded tensor has no symmetry-allowed block"};
-  // ---- pack X_Q and plan the Gram products
+  // ---- pack X_Q with its Gram side as rows (L2R: the (a,s) rows of the
+  // sector; R2L: the transpose of its (s,b) columns)
+  const bool l2r = (dir == D3S_L2R);
   long xtot = 0;
   std::vector<CopyDesc> gather;
+  TruncMats tm;
   for (SecGroup& g : gs) {
     g.xoff = xtot;
     xtot += (long)g.nrows * g.ncols;
+    const int nside = l2r ? g.nrows : g.ncols, nother = l2r ? g.ncols : g.nrows;
+    tm.xoff.push_back(g.xoff);
+    tm.nr.push_back(nside);
+    tm.nc.push_back(nother);
     for (const RowGroup& rg : g.rows)
-      for (const ColGroup& cg : g.cols)
-        gather.push_back(CopyDesc{rg.start * rowlen + cg.start, rg.stride * rowlen, 1, g.xoff + (long)rg.local * g.ncols + cg.local,
-                                  (long)g.ncols, 1, rg.count, cg.count});
+      for (const ColGroup& cg : g.cols) {
+        if (l2r)
+          gather.push_back(CopyDesc{rg.start * rowlen + cg.start, rg.stride * rowlen, 1,
+                                    g.xoff + (long)rg.local * g.ncols + cg.local, (long)g.ncols, 1, rg.count,
+                                    cg.count});
+        else
+          gather.push_back(CopyDesc{rg.start * rowlen + cg.start, rg.stride * rowlen, 1,
+                                    g.xoff + (long)cg.local * g.nrows + rg.local, 1, (long)g.nrows, rg.count,
+                                    cg.count});
+      }
   }
   double* X = (double*)ws_get(c, WS_XPACK, sizeof(double) * (size_t)xtot);
   copy_blocks(c, Mt, X, gather);
-  // buckets of equal padded size
-  std::vector<int> bucket_n;
-  std::vector<std::vector<int>> bucket_members;
-  // Batches of equal padded size for the eigensolver.  Measured on MI355X
-  // (rocSOLVER dsyevd_strided_batched): from n = 96 on a call costs about
-  // 24 us per matrix column whatever the batch size (launch-bound) plus
-  // ~1.6e-12 n^3 s per matrix, while below n = 96 its small-size path grows
-  // steeply with the batch (n = 64, 40 matrices: 18 ms against 2 ms at
-  // n = 96).  With the LDS solver chosen, matrices up to 128 may go to it
-  // instead (one workgroup per matrix, nothing launched per column, about
-  // 5e-5 + 6.5e-7 n^2 s per batch of up to 256).  Matrices are
-  // padded with zero rows and columns (whose zero eigenvalues sort below
-  // every kept one): to a multiple of 8 for the LDS solver, else to at least
-  // 96 and a multiple of 16; sizes are sorted and the contiguous grouping of
-  // least modelled cost is found by dynamic programming.
-  {
-    const int G = (int)gs.size();
-    std::vector<int> ord(G);
-    for (int i = 0; i < G; ++i) ord[i] = i;
-    auto gdim = [&](int gi) { return (dir == D3S_L2R) ? gs[gi].nrows : gs[gi].ncols; };
-    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return gdim(a) < gdim(b); });
-    // sizes the LDS solver takes (see eig_batched_f64) are padded to
-    // multiples of 8 only
-    auto small = [&](int n) { return eig_small_used(c, (n + 7) / 8 * 8); };
-    auto pad = [&](int n) { return small(n) ? (n + 7) / 8 * 8 : std::max(96, (n + 15) / 16 * 16); };
-    auto cost = [&](int i, int j) {   // group ord[i..j]
-      const double np = pad(gdim(ord[j]));
-      const int cnt = j - i + 1;
-      if (small(gdim(ord[j]))) return (5e-5 + 6.5e-7 * np * np) * ((cnt + 255) / 256);
-      return 2.4e-5 * np + 1.6e-12 * (double)cnt * np * np * np;
-    };
-    std::vector<double> best(G + 1, 0.0);
-    std::vector<int> cut(G + 1, 0);
-    for (int j = 1; j <= G; ++j) {
-      best[j] = 1e300;
-      for (int i = 0; i < j; ++i) {
-        const double v = best[i] + cost(i, j - 1);
-        if (v < best[j]) {
-          best[j] = v;
-          cut[j] = i;
-        }
-      }
-    }
-    std::vector<std::pair<int, int>> ranges;
-    for (int j = G; j > 0; j = cut[j]) ranges.push_back({cut[j], j - 1});
-    for (auto& r : ranges) {
-      const int b = (int)bucket_n.size();
-      bucket_n.push_back(pad(gdim(ord[r.second])));
-      bucket_members.emplace_back();
-      for (int q = r.first; q <= r.second; ++q) {
-        SecGroup& g = gs[ord[q]];
-        g.npad = bucket_n[b];
-        g.bucket = b;
-        g.idx = (int)bucket_members[b].size();
-        bucket_members[b].push_back(ord[q]);
-      }
-    }
-  }
-  std::vector<long> bucket_goff(bucket_n.size()), bucket_voff(bucket_n.size());
-  long gtot = 0, vtot = 0;
-  for (size_t b = 0; b < bucket_n.size(); ++b) {
-    bucket_goff[b] = gtot;
-    bucket_voff[b] = vtot;
-    gtot += (long)bucket_members[b].size() * bucket_n[b] * bucket_n[b];
-    vtot += (long)bucket_members[b].size() * bucket_n[b];
-  }
-  double* G = (double*)ws_get(c, WS_GPACK, sizeof(double) * (size_t)gtot);
-  zero_bytes(c, G, sizeof(double) * (size_t)gtot);
-  GroupedPlan gp;
-  gp.a_kc = (dir == D3S_L2R);
-  gp.b_kc = (dir == D3S_L2R);
-  for (SecGroup& g : gs) {
-    g.goff = bucket_goff[g.bucket] + (long)g.idx * g.npad * g.npad;
-    GTask t;
-    GSeg sg;
-    if (dir == D3S_L2R) {    // X X^T over rows
-      t.M = t.N = g.nrows;
-      sg.K = g.ncols;
-      sg.a_off = g.xoff; sg.lda = g.ncols;
-      sg.b_off = g.xoff; sg.ldb = g.ncols;
-    } else {                 // X^T X over columns
-      t.M = t.N = g.ncols;
-      sg.K = g.nrows;
-      sg.a_off = g.xoff; sg.lda = g.ncols;
-      sg.b_off = g.xoff; sg.ldb = g.ncols;
-    }
-    t.seg0 = (int)gp.segs.size();
-    t.nseg = 1;
-    t.tile0 = 0;
-    t.c_off = g.goff;
-    t.ldc = g.npad;
-    gp.segs.push_back(sg);
-    gp.tasks.push_back(t);
-  }
-  grouped_finalize(c, gp);
-  grouped_gemm(c, D3S_F64, gp, X, X, G, 1.0);
-  grouped_release(gp);
-  double* V = (double*)ws_get(c, WS_GVAL, sizeof(double) * (size_t)vtot);
-  for (size_t b = 0; b < bucket_n.size(); ++b)
-    eig_batched_f64(c, bucket_n[b], (int)bucket_members[b].size(), G + bucket_goff[b], V + bucket_voff[b]);
-  std::vector<double> ev(vtot);
-  D3S_HIP(hipMemcpyAsync(ev.data(), V, sizeof(double) * (size_t)vtot, hipMemcpyDeviceToHost, c->stream));
-  D3S_HIP(hipStreamSynchronize(c->stream));
-  // ---- global selection of the kept states
-  struct Cand { double lam; int g, rank; };
-  std::vector<Cand> cand;
-  double total = 0.0, s0 = 0.0;
-  long nsum = 0;
-  for (int gi = 0; gi < (int)gs.size(); ++gi) {
-    const SecGroup& g = gs[gi];
-    const int ng = (dir == D3S_L2R) ? g.nrows : g.ncols;
-    nsum += ng;
-    const double* e = ev.data() + bucket_voff[g.bucket] + (long)g.idx * g.npad;
-    for (int r = 0; r < ng; ++r) {
-      const double lam = std::max(e[g.npad - 1 - r], 0.0);
-      total += lam;
-      s0 = std::max(s0, lam);
-      cand.push_back({lam, gi, r});
-    }
-  }
-  if (!(s0 > 0.0) || !std::isfinite(total))
+  tm.X = X;
+  TruncSel sel;
+  trunc_solve(c, tm, kmax, eps, sel);
+  if (!(sel.total > 0.0) || !std::isfinite(sel.total))
     throw Error{D3S_ENUMERIC, "truncate: the expanded tensor is zero or not finite"};
-  const double floor2 = std::max(eps * eps, (double)nsum * DBL_EPSILON) * s0;
-  std::stable_sort(cand.begin(), cand.end(), [](const Cand& a, const Cand& b) { return a.lam > b.lam; });
-  int k = 0;
-  double kept = 0.0;
-  for (const Cand& cd : cand) {
-    if (k >= kmax || !(cd.lam > floor2)) break;
-    gs[cd.g].keep++;
-    kept += cd.lam;
-    ++k;
-  }
+  const int k = sel.k;
+  if (k <= 0) throw Error{D3S_ENUMERIC, "truncate: no singular value above the cutoff"};
+  for (size_t gi = 0; gi < gs.size(); ++gi) gs[gi].keep = sel.keep[gi];
   // ---- new bond sectors (ordered by charge key)
   std::vector<int> order;
   for (int gi = 0; gi < (int)gs.size(); ++gi)
@@ -1198,8 +1096,8 @@ TruncBlocksResult op_truncate_blocks(Ctx* c, d3s_dir dir, const Sectors& left, c
   });
   TruncBlocksResult res;
   res.k = k;
-  res.total = total;
-  res.discarded = std::max(0.0, total - kept);
+  res.total = sel.total;
+  res.discarded = std::max(0.0, sel.total - sel.kept);
   int off = 0;
   for (int gi : order) {
     gs[gi].new_off = off;
@@ -1207,26 +1105,24 @@ TruncBlocksResult op_truncate_blocks(Ctx* c, d3s_dir dir, const Sectors& left, c
     res.q.insert(res.q.end(), gs[gi].q.begin(), gs[gi].q.end());
     res.dim.push_back(gs[gi].keep);
   }
-  // ---- the new site tensor from the kept eigenvectors (rank r <-> column npad-1-r)
-  std::vector<CopyDesc> scatter;
-  if (dir == D3S_L2R) {
+  // ---- the new site tensor from the kept vectors of every sector
+  std::map<const double*, std::vector<CopyDesc>> scatter;
+  if (l2r) {
     zero_bytes(c, site_out, sizeof(double) * (size_t)n * k);
     for (int gi : order) {
       const SecGroup& g = gs[gi];
       for (const RowGroup& rg : g.rows)
-        scatter.push_back(CopyDesc{g.goff + (long)(g.npad - 1) * g.npad + rg.local, 1, -(long)g.npad,
-                                   rg.start * k + g.new_off, rg.stride * k, 1, rg.count, g.keep});
+        kept_copies(sel, gi, rg.local, rg.count, rg.start * k + g.new_off, 1, rg.stride * k, scatter);
     }
   } else {
     zero_bytes(c, site_out, sizeof(double) * (size_t)k * n);
     for (int gi : order) {
       const SecGroup& g = gs[gi];
       for (const ColGroup& cg : g.cols)
-        scatter.push_back(CopyDesc{g.goff + (long)(g.npad - 1) * g.npad + cg.local, -(long)g.npad, 1,
-                                   (long)g.new_off * n + cg.start, n, 1, g.keep, cg.count});
+        kept_copies(sel, gi, cg.local, cg.count, (long)g.new_off * n + cg.start, n, 1, scatter);
     }
   }
-  copy_blocks(c, G, site_out, scatter);
+  run_copies(c, scatter, site_out);
   // ---- neighbour: the dense products on the structured layout
   if (dir == D3S_L2R) {
     double* Xn = (double*)ws_get(c, WS_X, sizeof(double) * (size_t)k * mr);

@@ -5,6 +5,7 @@
 #include <hip/hip_bf16.h>
 #include <cstddef>
 #include <cstdint>
+#include <map>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -37,7 +38,9 @@ struct Error {
 enum WsSlot {
   WS_T1 = 0, WS_T2, WS_LZ_V, WS_LZ_W, WS_LZ_COEF, WS_RED, WS_GRAM, WS_EIGVAL,
   WS_EIGTMP, WS_UKT, WS_X, WS_MT, WS_CAST_L, WS_CAST_R, WS_CAST_X, WS_CAST_Y,
-  WS_CAST_W, WS_REF, WS_PSI, WS_INFO, WS_NBR, WS_MISC, WS_SPLITK, WS_DESC, WS_BLK_X, WS_XPACK, WS_GPACK, WS_GVAL, WS_TUNE, WS_PK, WS_LZ_K, WS_GS_NORM, WS_JD_V, WS_JD_W, WS_JD_Z, WS_JD_COEF, WS_G2_PART, WS_W2, WS_RMET, WS_RZ, WS_RT, WS_RGRAM, WS_H2, WS_PSIT, WS_LP_L, WS_LP_R, WS_LP_X, WS_LP_Y, WS_NSLOTS
+  WS_CAST_W, WS_REF, WS_PSI, WS_INFO, WS_NBR, WS_MISC, WS_SPLITK, WS_DESC, WS_BLK_X, WS_XPACK, WS_GPACK, WS_GVAL, WS_TUNE, WS_PK, WS_LZ_K, WS_GS_NORM, WS_JD_V, WS_JD_W, WS_JD_Z, WS_JD_COEF, WS_G2_PART, WS_W2, WS_RMET, WS_RZ, WS_RT, WS_RGRAM, WS_H2, WS_PSIT, WS_LP_L, WS_LP_R, WS_LP_X, WS_LP_Y,
+  WS_TR_G, WS_TR_V, WS_TR_W0, WS_TR_W1, WS_TR_T2, WS_TR_T3, WS_TR_T4, WS_TR_P, WS_TR_TAB, WS_TR_AUX, WS_TR_XT,
+  WS_NSLOTS
 };
 
 struct Ctx {
@@ -100,6 +103,7 @@ struct GroupedPlan {
   bool a_kc = true, b_kc = true;
   int cfg = 1;                  // tile configuration (grouped_tile_dims)
   double flops = 0.0;
+  int table_slot = -1;          // >= 0: the device tables live in this workspace slot (not owned)
 };
 void grouped_tile_dims(int cfg, int& bm, int& bn);   // block tile of a grouped configuration
 // sort tasks largest-first, pick the tile size, compute tile prefix sums and
@@ -113,7 +117,7 @@ void tuned_gemm(Ctx* c, d3s_prec p, const GemmArgs& g);
 void tune_grouped(Ctx* c, GroupedPlan& g, const void* A, const void* B, void* C);
 void grouped_release(GroupedPlan& g);
 void grouped_gemm(Ctx* c, d3s_prec p, const GroupedPlan& g, const void* A, const void* B, void* C,
-                  double alpha);
+                  double alpha, double beta = 0.0);
 
 // ---------------------------------------------------------------- kernels
 // W-map of a left-to-right contraction:
@@ -226,14 +230,64 @@ void op_expand(Ctx* c, d3s_dir dir, int ml, int d, int mr, int wl, int wr,
                const double* env, const double* W, const double* psi, double alpha, double* Mt);
 void op_update_env(Ctx* c, d3s_dir dir, int ml, int d, int mr, int wl, int wr,
                    const double* env_in, const double* W, const double* site, double* env_out);
+// ---------------------------------------------------------------- truncation engine (trunc.hip)
+// Batches of the eigensolver: per matrix its padded size and the offsets of
+// its (column-major) matrix and eigenvalues; matrices of a bucket share a size.
+struct EigPlan {
+  std::vector<int> npad;
+  std::vector<long> goff, voff;
+  std::vector<int> bucket_n;
+  std::vector<std::vector<int>> members;
+  std::vector<long> bucket_goff, bucket_voff;
+  long gtot = 0, vtot = 0;
+};
+EigPlan plan_eig(Ctx* c, const std::vector<int>& n);          // n[q] <= 0: matrix q not in the plan
+// normalise every matrix (largest diagonal entry 1, padded diagonal -1) and
+// solve; scale[q] multiplies matrix q's eigenvalues back
+void eig_run(Ctx* c, const EigPlan& ep, const std::vector<int>& n, double* G, double* V,
+             std::vector<double>& scale);
+// A set of matrices truncated together: X_q (nr[q] x nc[q], row-major, row
+// stride nc[q]) at X + xoff[q]; the singular vectors sought are the left ones.
+struct TruncMats {
+  const double* X = nullptr;
+  std::vector<long> xoff;
+  std::vector<int> nr, nc;
+};
+// `count` unit vectors of length nr: vector j at base + start + j*step, elements contiguous
+struct TruncVecSeg { const double* base; long start, step; int count; };
+struct TruncSel {
+  std::vector<std::vector<double>> s;            // per matrix: accepted singular values, descending
+  std::vector<std::vector<TruncVecSeg>> vecs;    // per matrix: their left singular vectors, same order
+  std::vector<std::vector<double>> rest;         // per matrix: estimates of the values left unresolved
+  std::vector<int> keep;                         // per matrix: kept states (a prefix of s)
+  int k = 0;
+  double total = 0.0, kept = 0.0;                // sum of all / of the kept squared singular values
+};
+// Singular values and left singular vectors of every matrix, resolved by
+// deflated passes down to what the cut needs, and the global choice of the
+// kept states (at most kmax, only s > eps * s_0).  The vectors live in the
+// context's workspace until the next truncation.  Synchronises.
+void trunc_solve(Ctx* c, const TruncMats& tm, int kmax, double eps, TruncSel& out);
+// copies of elements [e0, e0 + ne) of the kept vectors of matrix q:
+// dst[dst_off + j*dst_js + (e - e0)*dst_es] = vector_j[e], grouped by source buffer
+void kept_copies(const TruncSel& sel, int q, int e0, int ne, long dst_off, long dst_js, long dst_es,
+                 std::map<const double*, std::vector<CopyDesc>>& out);
+void run_copies(Ctx* c, const std::map<const double*, std::vector<CopyDesc>>& cp, double* dst);
+// X[r*ld + col] *= f[r] for r < rows, col < cols (f on the host)
+void scale_rows_f64(Ctx* c, double* X, long ld, int rows, int cols, const std::vector<double>& f);
+
 struct TruncResult { int k; double discarded; double total; };
 TruncResult op_truncate(Ctx* c, d3s_dir dir, int ml, int d, int mr, long width,
                         const double* Mt, const double* psi, int kmax, double eps,
                         const double* nbr, long nbr_other, double* site_out, double* nbr_out,
                         double* s_host, bool renormalize);
-TruncResult truncate_from_gram(Ctx* c, d3s_dir dir, int ml, int d, int mr, double* G, const double* psi, int kmax,
-                               double eps, const double* nbr, long nbr_other, double* site_out, double* nbr_out,
-                               double* s_host, bool renormalize);
+// The exact-residual expanded tensor on an orthonormal basis of its far-side
+// vectors: L2R [psi | alpha Zc F] ((ml d) x (mr + r)), R2L [psi ; alpha F^T Zc]
+// ((ml + r) x (d mr)), G = F F^T the metric; returns the width (L2R) or row
+// count (R2L) mr + r / ml + r.
+long op_residual_expand(Ctx* c, d3s_dir dir, int ml, int d, int mr, int wl, int wr, const double* L,
+                        const double* R, const double* h2, const double* W, const double* psi, double energy,
+                        double alpha, double* Mt);
 struct LanczosResult { double theta; int matvecs; bool converged; int restarts; int f64_matvecs = 0; };
 LanczosResult op_lanczos(Ctx* c, d3s_prec p, int ml, int d, int mr, int wl, int wr,
                          const double* L, const double* W, const double* R, double* psi,

@@ -4,7 +4,8 @@
 // Each task owns an output block C[M x N] (at c_off, row stride ldc) and a
 // list of K-segments; a segment is one product A_s[M x K_s] * B_s[K_s x N]
 // (at a_off / b_off with its own leading dimensions).  The task's output is
-// alpha * sum over its segments, so contributions that land on the same
+// alpha * sum over its segments (+ beta * C when beta != 0), so contributions
+// that land on the same
 // output block (the sum over the right MPO bond of the last H_eff
 // contraction, whose right-bond sectors differ from term to term) are
 // accumulated in registers, without atomics and in a fixed order.
@@ -34,7 +35,7 @@ struct GParams {
   const void* A;
   const void* B;
   void* C;
-  double alpha;
+  double alpha, beta;
 };
 
 template <typename S, int BM, int BN, int WM, int WN, bool AKC, bool BKC>
@@ -172,7 +173,8 @@ void grouped_kernel(GParams p) {
     }
   }
 
-  const AT alpha = (AT)p.alpha;
+  const AT alpha = (AT)p.alpha, beta = (AT)p.beta;
+  const bool accumulate = p.beta != 0.0;
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -182,14 +184,18 @@ void grouped_kernel(GParams p) {
       for (int r = 0; r < 4; ++r) {
         const int rr = (sizeof(S) == 8) ? (r * 4 + lgrp) : (lgrp * 4 + r);
         const int row = m0 + wm * WM + i * 16 + rr;
-        if (row < t.M && col < t.N) C[(long)row * t.ldc + col] = alpha * acc[i][j][r];
+        if (row < t.M && col < t.N) {
+          AT* dst = C + (long)row * t.ldc + col;
+          *dst = accumulate ? alpha * acc[i][j][r] + beta * *dst : alpha * acc[i][j][r];
+        }
       }
     }
 }
 
 template <typename S, int BM, int BN, int WM, int WN>
-void launch_grouped(Ctx* c, const GroupedPlan& g, const void* A, const void* B, void* C, double alpha) {
-  GParams p{g.d_tasks, g.d_segs, g.ntasks, g.total_tiles, A, B, C, alpha};
+void launch_grouped(Ctx* c, const GroupedPlan& g, const void* A, const void* B, void* C, double alpha,
+                    double beta) {
+  GParams p{g.d_tasks, g.d_segs, g.ntasks, g.total_tiles, A, B, C, alpha, beta};
   const long span = (long)kXcd * kChunk;
   dim3 grid((unsigned)((g.total_tiles + span - 1) / span * span)), block((BM / WM) * (BN / WN) * 64);
   if (g.a_kc && g.b_kc)
@@ -220,17 +226,17 @@ void grouped_tile_dims(int cfg, int& bm, int& bn) {
 }
 
 void grouped_gemm(Ctx* c, d3s_prec prec, const GroupedPlan& g, const void* A, const void* B, void* C,
-                  double alpha) {
+                  double alpha, double beta) {
   if (g.ntasks <= 0 || g.total_tiles <= 0) return;
   auto run = [&](auto tag) {
     typedef decltype(tag) S;
     switch (g.cfg) {
-      case 0: launch_grouped<S, 128, 128, 64, 64>(c, g, A, B, C, alpha); break;
-      case 2: launch_grouped<S, 96, 96, 48, 48>(c, g, A, B, C, alpha); break;
-      case 3: launch_grouped<S, 32, 32, 16, 16>(c, g, A, B, C, alpha); break;
-      case 4: launch_grouped<S, 128, 128, 64, 32>(c, g, A, B, C, alpha); break;
-      case 5: launch_grouped<S, 256, 128, 64, 64>(c, g, A, B, C, alpha); break;
-      default: launch_grouped<S, 64, 64, 32, 32>(c, g, A, B, C, alpha); break;
+      case 0: launch_grouped<S, 128, 128, 64, 64>(c, g, A, B, C, alpha, beta); break;
+      case 2: launch_grouped<S, 96, 96, 48, 48>(c, g, A, B, C, alpha, beta); break;
+      case 3: launch_grouped<S, 32, 32, 16, 16>(c, g, A, B, C, alpha, beta); break;
+      case 4: launch_grouped<S, 128, 128, 64, 32>(c, g, A, B, C, alpha, beta); break;
+      case 5: launch_grouped<S, 256, 128, 64, 64>(c, g, A, B, C, alpha, beta); break;
+      default: launch_grouped<S, 64, 64, 32, 32>(c, g, A, B, C, alpha, beta); break;
     }
   };
   if (prec == D3S_F64) run(double());

@@ -1063,8 +1063,30 @@ void zero_bytes(Ctx* c, void* x, size_t bytes) {
   D3S_HIP(hipGetLastError());
 }
 
-void copy_blocks(Ctx* c, const double* src, double* dst, const std::vector<CopyDesc>& desc) {
-  if (desc.empty()) return;
+void copy_blocks(Ctx* c, const double* src, double* dst, const std::vector<CopyDesc>& desc_in) {
+  if (desc_in.empty()) return;
+  // one workgroup per descriptor: blocks of more than kPiece elements are
+  // cut into row ranges (and long rows into column ranges) first
+  constexpr long kPiece = 16384;
+  std::vector<CopyDesc> desc;
+  desc.reserve(desc_in.size());
+  for (const CopyDesc& q : desc_in) {
+    if ((long)q.rows * q.cols <= kPiece) {
+      desc.push_back(q);
+      continue;
+    }
+    const int cstep = (int)std::min<long>(q.cols, kPiece);
+    const int rstep = (int)std::max<long>(1, kPiece / cstep);
+    for (int r0 = 0; r0 < q.rows; r0 += rstep)
+      for (int c0 = 0; c0 < q.cols; c0 += cstep) {
+        CopyDesc p = q;
+        p.src_off = q.src_off + (long)r0 * q.src_rs + (long)c0 * q.src_cs;
+        p.dst_off = q.dst_off + (long)r0 * q.dst_rs + (long)c0 * q.dst_cs;
+        p.rows = std::min(rstep, q.rows - r0);
+        p.cols = std::min(cstep, q.cols - c0);
+        desc.push_back(p);
+      }
+  }
   CopyDesc* d = (CopyDesc*)ws_get(c, WS_DESC, sizeof(CopyDesc) * desc.size());
   D3S_HIP(hipMemcpyAsync(d, desc.data(), sizeof(CopyDesc) * desc.size(), hipMemcpyHostToDevice, c->stream));
   hipLaunchKernelGGL(copy_desc_kernel, dim3((unsigned)desc.size()), dim3(kThreads), 0, c->stream, src, dst, d);

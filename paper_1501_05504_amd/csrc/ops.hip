@@ -9,6 +9,8 @@
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
+#include <functional>
+#include <map>
 
 #include "d3s_internal.h"
 
@@ -456,53 +458,46 @@ void jacobi_eigh(int n, std::vector<double>& A, std::vector<double>& evals, std:
 }
 
 // ---------------------------------------------------------------- truncation
+// Steps 4-5 of the site update on a dense expanded tensor: its left (L2R) or
+// right (R2L) singular vectors from the truncation engine (the rows of Mt,
+// or of its transpose, are the matrix whose left vectors it finds), the new
+// site tensor from the kept ones, and the neighbour through U_k^T psi_mat
+// (or psi_mat V_k): only that block of S V^T meets the nonzero rows of the
+// zero-padded neighbour.
 TruncResult op_truncate(Ctx* c, d3s_dir dir, int ml, int d, int mr, long width, const double* Mt,
                         const double* psi, int kmax, double eps, const double* nbr, long nbr_other,
                         double* site_out, double* nbr_out, double* s_host, bool renormalize) {
   const int n = (dir == D3S_L2R) ? ml * d : d * mr;
-  double* G = (double*)ws_get(c, WS_GRAM, sizeof(double) * (size_t)n * n);
+  TruncMats tm;
   if (dir == D3S_L2R) {
-    GemmArgs g{n, n, (int)width, Mt, width, true, 0, Mt, width, true, 0, G, n, 0, 1.0, 0.0, 1};
-    gemm_f64(c, g);
+    tm.X = Mt;
   } else {
-    GemmArgs g{n, n, (int)width, Mt, n, false, 0, Mt, n, false, 0, G, n, 0, 1.0, 0.0, 1};
-    gemm_f64(c, g);
+    double* Xt = (double*)ws_get(c, WS_TR_XT, sizeof(double) * (size_t)n * width);
+    transpose_f64(c, Mt, width, n, Xt);
+    tm.X = Xt;
   }
-  return truncate_from_gram(c, dir, ml, d, mr, G, psi, kmax, eps, nbr, nbr_other, site_out, nbr_out, s_host,
-                            renormalize);
-}
-
-// Steps 4-5 from the Gram matrix G (n x n, overwritten) of the expanded
-// tensor on its site side: its eigenvectors are the singular vectors that
-// are kept, its eigenvalues the squared singular values.
-TruncResult truncate_from_gram(Ctx* c, d3s_dir dir, int ml, int d, int mr, double* G, const double* psi, int kmax,
-                               double eps, const double* nbr, long nbr_other, double* site_out, double* nbr_out,
-                               double* s_host, bool renormalize) {
-  const int n = (dir == D3S_L2R) ? ml * d : d * mr;
-  double* ev = (double*)ws_get(c, WS_EIGVAL, sizeof(double) * (size_t)n);
-  syevd_f64(c, n, G, ev);
-  std::vector<double> lam(n);
-  read_many(c, lam.data(), ev, n);
-  std::vector<double> s2(n);
-  double total = 0.0;
-  for (int j = 0; j < n; ++j) {
-    s2[j] = std::max(lam[n - 1 - j], 0.0);
-    total += s2[j];
-  }
-  if (!(s2[0] > 0.0) || !std::isfinite(total))
+  tm.xoff = {0};
+  tm.nr = {n};
+  tm.nc = {(int)width};
+  TruncSel sel;
+  trunc_solve(c, tm, kmax, eps, sel);
+  if (!(sel.total > 0.0) || !std::isfinite(sel.total))
     throw Error{D3S_ENUMERIC, "truncate: the expanded tensor is zero or not finite"};
-  // The Gram route resolves s_j^2 only down to ~n u s_0^2; below that floor a
-  // singular value is indistinguishable from zero.
-  const double floor2 = std::max(eps * eps, (double)n * DBL_EPSILON) * s2[0];
-  int k = 0;
-  while (k < n && k < kmax && s2[k] > floor2) ++k;
-  double disc = 0.0;
-  for (int j = k; j < n; ++j) disc += s2[j];
-  if (s_host)
-    for (int j = 0; j < n; ++j) s_host[j] = std::sqrt(s2[j]);
-  // U_k^T (k x n): eigenvector n-1-j is column n-1-j of the column-major G
+  const int k = sel.k;
+  if (k <= 0) throw Error{D3S_ENUMERIC, "truncate: no singular value above the cutoff"};
+  if (s_host) {
+    std::vector<double> all(sel.s[0]);
+    all.insert(all.end(), sel.rest[0].begin(), sel.rest[0].end());
+    std::sort(all.begin(), all.end(), std::greater<double>());
+    for (int j = 0; j < n; ++j) s_host[j] = j < (int)all.size() ? all[j] : 0.0;
+  }
+  // U_k^T (k x n), one kept vector per row
   double* Ukt = (double*)ws_get(c, WS_UKT, sizeof(double) * (size_t)k * n);
-  copy2d_f64(c, G + (long)(n - 1) * n, -(long)n, Ukt, n, k, n);
+  {
+    std::map<const double*, std::vector<CopyDesc>> cp;
+    kept_copies(sel, 0, 0, n, 0, n, 1, cp);
+    run_copies(c, cp, Ukt);
+  }
   if (dir == D3S_L2R) {
     transpose_f64(c, Ukt, k, n, site_out);                      // A = U_k, (ml d) x k
     // without a neighbour (the split of a two-site tensor) X = S_k V_k^T is the output
@@ -533,7 +528,56 @@ TruncResult truncate_from_gram(Ctx* c, d3s_dir dir, int ml, int d, int mr, doubl
       throw Error{D3S_ENUMERIC, "truncate: neighbour norm is zero or not finite"};
     scale_f64(c, nbr_out, nn, 1.0 / std::sqrt(nrm2));
   }
-  return TruncResult{k, disc, total};
+  return TruncResult{k, std::max(0.0, sel.total - sel.kept), sel.total};
+}
+
+// The exact-residual expanded tensor with its expansion part written on an
+// orthonormal basis of the far-side vectors |B_y>, H_v|B_y> (L2R; |A_a>,
+// H_w|A_a> R2L).  Those vectors are linearly dependent (the far-side
+// operator of the completed MPO channel is the identity), so their metric
+// Q = F F^T is factored through its eigen-decomposition, eigenvalues at or
+// below ng u lambda_max taken as the exact zeros of those dependences:
+//   L2R: [M | alpha Zc F],  Zc = [-E M | L M W]  ((ml d) x (mr + r))
+//   R2L: [M ; alpha F^T Zc], Zc = [-E M ; W M R] ((ml + r) x (d mr))
+// Its SVD is the truncation of the residual expansion; Mt Mt^T (M^T M) is
+// the Gram matrix of op_residual_gram.
+long op_residual_expand(Ctx* c, d3s_dir dir, int ml, int d, int mr, int wl, int wr, const double* L,
+                        const double* R, const double* h2, const double* W, const double* psi, double energy,
+                        double alpha, double* Mt) {
+  const bool l2r = dir == D3S_L2R;
+  const int n = l2r ? ml * d : d * mr;
+  const int ng = l2r ? (1 + wr) * mr : (1 + wl) * ml;
+  const int mnear = l2r ? mr : ml;
+  double* Zc = (double*)ws_get(c, WS_RZ, sizeof(double) * (size_t)n * ng);
+  op_expand(c, dir, ml, d, mr, wl, wr, l2r ? L : R, W, psi, 1.0, Zc);
+  if (l2r) scale2d_f64(c, Zc, ng, n, mr, -energy);
+  else scale_f64(c, Zc, (long)ml * n, -energy);
+  double* Q = (double*)ws_get(c, WS_RMET, sizeof(double) * (size_t)ng * ng);
+  residual_metric(c, l2r ? R : L, h2, mnear, l2r ? wr : wl, Q);
+  double* ev = (double*)ws_get(c, WS_EIGVAL, sizeof(double) * (size_t)ng);
+  syevd_f64(c, ng, Q, ev);
+  std::vector<double> lam(ng);
+  read_many(c, lam.data(), ev, ng);
+  const double lmax = lam[ng - 1];
+  if (!(lmax > 0.0) || !std::isfinite(lmax)) throw Error{D3S_ENUMERIC, "residual: metric is zero or not finite"};
+  int r = 0;
+  while (r < ng && lam[ng - 1 - r] > (double)ng * DBL_EPSILON * lmax) ++r;
+  // F^T (r x ng): eigenvectors ng-r .. ng-1 (rows of the column-major Q) scaled by sqrt(lambda)
+  double* Ft = Q + (long)(ng - r) * ng;
+  std::vector<double> f(r);
+  for (int j = 0; j < r; ++j) f[j] = std::sqrt(lam[ng - r + j]);
+  scale_rows_f64(c, Ft, ng, r, ng, f);
+  if (l2r) {
+    const long ldm = (long)mr + r;
+    GemmArgs g{n, r, ng, Zc, ng, true, 0, Ft, ng, true, 0, Mt + mr, ldm, 0, alpha, 0.0, 1};
+    gemm_f64(c, g);
+    copy2d_f64(c, psi, mr, Mt, ldm, n, mr);
+    return ldm;
+  }
+  GemmArgs g{r, n, ng, Ft, ng, true, 0, Zc, n, false, 0, Mt + (long)ml * n, n, 0, alpha, 0.0, 1};
+  gemm_f64(c, g);
+  copy_f64(c, psi, Mt, (long)ml * n);
+  return (long)ml + r;
 }
 
 // ---------------------------------------------------------------- energy

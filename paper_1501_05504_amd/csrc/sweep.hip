@@ -123,7 +123,6 @@ void op_sweep(Ctx* c, d3s_state* s, d3s_sweep_params* p, d3s_sweep_stats* st) {
   // of site i) and right ones per site (h2r[i] right of site i), in one
   // workspace buffer sized for the largest bond each may reach
   std::vector<double*> h2l, h2r;
-  double* gram = nullptr;
   if (residual) {
     std::vector<size_t> off_l(l), off_r(l);
     size_t total = 0;
@@ -143,7 +142,6 @@ void op_sweep(Ctx* c, d3s_state* s, d3s_sweep_params* p, d3s_sweep_stats* st) {
     double* base = (double*)ws_get(c, WS_H2, sizeof(double) * total);
     for (int b = 0; b < l; ++b) h2l.push_back(base + off_l[b]);
     for (int i = 0; i < l; ++i) h2r.push_back(base + off_r[i]);
-    gram = (double*)ws_get(c, WS_RGRAM, sizeof(double) * (size_t)d * s->mmax * d * s->mmax);
     fill_f64(c, h2l[0], 1, 1.0);
     fill_f64(c, h2r[l - 1], 1, 1.0);
     for (int i = 0; i + 1 < l; ++i)
@@ -152,7 +150,9 @@ void op_sweep(Ctx* c, d3s_state* s, d3s_sweep_params* p, d3s_sweep_stats* st) {
   }
   double* tmpS = (double*)ws_get(c, WS_PSI, sizeof(double) * cap);
   double* tmpN = (double*)ws_get(c, WS_NBR, sizeof(double) * cap);
-  double* Mt = residual ? nullptr : (double*)ws_get(c, WS_MT, sizeof(double) * (size_t)(1 + wmax) * cap);
+  // [psi | alpha P] has (1 + w) m columns; the residual's expanded tensor at
+  // most m + (1 + w) m
+  double* Mt = (double*)ws_get(c, WS_MT, sizeof(double) * (size_t)((residual ? 2 : 1) + wmax) * cap);
   const double t_start = now();
   st->count = 0;
   st->nonconverged = 0;
@@ -176,20 +176,17 @@ void op_sweep(Ctx* c, d3s_state* s, d3s_sweep_params* p, d3s_sweep_stats* st) {
     lam = lz.theta;
     if (!lz.converged) st->nonconverged++;
     double t1 = now();
+    long rows = (long)(1 + wl) * ml;
     if (residual)
-      op_residual_gram(c, D3S_R2L, ml, d, mr, wl, wr, s->lenv[i], s->renv[i], h2l[i], s->mpo[i], s->site[i], lam,
-                       p->alpha, gram);
+      rows = op_residual_expand(c, D3S_R2L, ml, d, mr, wl, wr, s->lenv[i], s->renv[i], h2l[i], s->mpo[i],
+                                s->site[i], lam, p->alpha, Mt);
     else
       op_expand(c, D3S_R2L, ml, d, mr, wl, wr, s->renv[i], s->mpo[i], s->site[i], p->alpha, Mt);
     D3S_HIP(hipStreamSynchronize(c->stream));
     double t2 = now();
     const int mll = s->m[i - 1];
-    TruncResult t = residual
-        ? truncate_from_gram(c, D3S_R2L, ml, d, mr, gram, s->site[i], (int)bond_budget(l, d, mlim, i), p->eps,
-                             s->site[i - 1], (long)mll * d, tmpS, tmpN, nullptr, true)
-        : op_truncate(c, D3S_R2L, ml, d, mr, (long)(1 + wl) * ml, Mt, s->site[i],
-                      (int)bond_budget(l, d, mlim, i), p->eps, s->site[i - 1], (long)mll * d,
-                      tmpS, tmpN, nullptr, true);
+    TruncResult t = op_truncate(c, D3S_R2L, ml, d, mr, rows, Mt, s->site[i], (int)bond_budget(l, d, mlim, i),
+                                p->eps, s->site[i - 1], (long)mll * d, tmpS, tmpN, nullptr, true);
     copy_f64(c, tmpS, s->site[i], (long)t.k * d * mr);
     copy_f64(c, tmpN, s->site[i - 1], (long)mll * d * t.k);
     s->m[i] = t.k;
@@ -230,20 +227,17 @@ void op_sweep(Ctx* c, d3s_state* s, d3s_sweep_params* p, d3s_sweep_stats* st) {
     lam = lz.theta;
     if (!lz.converged) st->nonconverged++;
     double t1 = now();
+    long width = (long)(1 + wr) * mr;
     if (residual)
-      op_residual_gram(c, D3S_L2R, ml, d, mr, wl, wr, s->lenv[i], s->renv[i], h2r[i], s->mpo[i], s->site[i], lam,
-                       p->alpha, gram);
+      width = op_residual_expand(c, D3S_L2R, ml, d, mr, wl, wr, s->lenv[i], s->renv[i], h2r[i], s->mpo[i],
+                                 s->site[i], lam, p->alpha, Mt);
     else
       op_expand(c, D3S_L2R, ml, d, mr, wl, wr, s->lenv[i], s->mpo[i], s->site[i], p->alpha, Mt);
     D3S_HIP(hipStreamSynchronize(c->stream));
     double t2 = now();
     const int mrr = s->m[i + 2];
-    TruncResult t = residual
-        ? truncate_from_gram(c, D3S_L2R, ml, d, mr, gram, s->site[i], (int)bond_budget(l, d, mlim, i + 1), p->eps,
-                             s->site[i + 1], (long)d * mrr, tmpS, tmpN, nullptr, true)
-        : op_truncate(c, D3S_L2R, ml, d, mr, (long)(1 + wr) * mr, Mt, s->site[i],
-                      (int)bond_budget(l, d, mlim, i + 1), p->eps, s->site[i + 1], (long)d * mrr,
-                      tmpS, tmpN, nullptr, true);
+    TruncResult t = op_truncate(c, D3S_L2R, ml, d, mr, width, Mt, s->site[i], (int)bond_budget(l, d, mlim, i + 1),
+                                p->eps, s->site[i + 1], (long)d * mrr, tmpS, tmpN, nullptr, true);
     copy_f64(c, tmpS, s->site[i], (long)ml * d * t.k);
     copy_f64(c, tmpN, s->site[i + 1], (long)t.k * d * mrr);
     s->m[i + 1] = t.k;
@@ -276,9 +270,9 @@ void op_sweep(Ctx* c, d3s_state* s, d3s_sweep_params* p, d3s_sweep_stats* st) {
 // dE/dW_i of <Psi|H|Psi> for every site i, each taken with the environments
 // of the gauge centred on i (product rule over the MPO tensors).  Starts from
 // the centre on site l-1 with lenv[0..l-1] valid, walks right to left moving
-// the centre by an uncut truncation (alpha = 0: the state is unchanged up to
-// the resolution of the Gram route), and leaves the centre on site 0 with
-// renv[0..l-1] valid.
+// the centre by a truncation without expansion that drops only singular
+// values below 1e-14 s_0 (the state is unchanged to rounding), and leaves the
+// centre on site 0 with renv[0..l-1] valid.
 void op_gradients(Ctx* c, d3s_state* s, double** grads) {
   const int l = s->l, d = s->d;
   if (s->center != l - 1) throw Error{D3S_EINVAL, "gradients: the orthogonality centre must be on site l-1"};
@@ -290,7 +284,7 @@ void op_gradients(Ctx* c, d3s_state* s, double** grads) {
     op_heff_grad_W(c, ml, d, mr, wl, wr, s->lenv[i], s->renv[i], s->site[i], s->site[i], grads[i]);
     if (i == 0) break;
     const int mll = s->m[i - 1];
-    TruncResult t = op_truncate(c, D3S_R2L, ml, d, mr, ml, s->site[i], s->site[i], ml, 0.0, s->site[i - 1],
+    TruncResult t = op_truncate(c, D3S_R2L, ml, d, mr, ml, s->site[i], s->site[i], ml, 1e-14, s->site[i - 1],
                                 (long)mll * d, tmpS, tmpN, nullptr, false);
     copy_f64(c, tmpS, s->site[i], (long)t.k * d * mr);
     copy_f64(c, tmpN, s->site[i - 1], (long)mll * d * t.k);

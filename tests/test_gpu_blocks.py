@@ -196,6 +196,96 @@ def test_block_expand_equals_dense_oracle(ctx, ml, mr, seed):
     plan.close()
 
 
+def _sector_spectrum_case(case, direction, seed):
+    """An expanded tensor with the block structure of [psi | P] (L2R) or
+    [psi ; P] (R2L) on the case's bonds: every charge Q of the new bond gets
+    a block of rank about half its size with singular values
+    scale_Q * geomspace(1, 1e-12, r_Q), scale_Q spread over 1 ... 1e-3, and
+    zeros elsewhere.  Returns (Mt, psi, expected kept dims by charge key)."""
+    rng = np.random.default_rng(seed)
+    sl = synth.expand_charges(case["qL"], case["dL"])
+    sr = synth.expand_charges(case["qR"], case["dR"])
+    phys, wq = case["phys"], case["wq"]
+    ml, mr, d, w = len(sl), len(sr), phys.shape[0], wq.shape[0]
+    key = lambda q: (int(q[0]), int(q[1]))
+    if direction == "l2r":
+        side = [key(sl[a] + phys[s]) for a in range(ml) for s in range(d)]
+        other = [key(sr[y]) for y in range(mr)] + [key(sr[y] + wq[v]) for v in range(w) for y in range(mr)]
+        Mt = np.zeros((ml * d, (1 + w) * mr))
+    else:
+        side = [key(sr[b] - phys[s]) for s in range(d) for b in range(mr)]
+        other = [key(sl[a]) for a in range(ml)] + [key(sl[a] + wq[v]) for v in range(w) for a in range(ml)]
+        Mt = np.zeros(((1 + w) * ml, d * mr))
+    side, other = np.array(side), np.array(other)
+    charges = sorted(set(map(tuple, side)) & set(map(tuple, other)))
+    values = {}
+    for qi, Q in enumerate(charges):
+        ri = np.nonzero(np.all(side == Q, axis=1))[0]
+        ci = np.nonzero(np.all(other == Q, axis=1))[0]
+        r = max(1, min(len(ri), len(ci)) // 2)
+        sv = 10.0 ** (-3.0 * qi / max(1, len(charges) - 1)) * np.geomspace(1.0, 1e-12, r)
+        U = np.linalg.qr(rng.standard_normal((len(ri), r)))[0]
+        V = np.linalg.qr(rng.standard_normal((len(ci), r)))[0]
+        blk = (U * sv) @ V.T
+        if direction == "l2r":
+            Mt[np.ix_(ri, ci)] = blk
+        else:
+            Mt[np.ix_(ci, ri)] = blk.T
+        values[Q] = sv
+    if direction == "l2r":
+        psi = Mt[:, :mr].reshape(ml, d, mr).copy()
+    else:
+        psi = Mt[:ml].reshape(ml, d, mr).copy()
+    s0 = max(v[0] for v in values.values())
+    kept = {Q: int(np.count_nonzero(v > 1e-14 * s0)) for Q, v in values.items()}
+    return Mt, psi, kept
+
+
+@pytest.mark.parametrize("direction", ["l2r", "r2l"])
+@pytest.mark.parametrize("ml,mr,seed", [(40, 52, 31), (300, 257, 32)])
+def test_block_truncate_keeps_every_value_above_eps(ctx, direction, ml, mr, seed):
+    """d3s_truncate_blocks on a block-structured expanded tensor whose sectors
+    hold spectra reaching 1e-15 s_0: every value above 1e-14 s_0 is kept (most
+    lie far below what one FP64 Gram matrix resolves), sector by sector; the
+    dense LAPACK truncation of the same matrix keeps as many; the kept
+    subspace, the site tensor's isometry and the neighbour agree with it."""
+    case = hubbard_block_case(ml, mr, seed)
+    ml, mr = case["psi"].shape[0], case["psi"].shape[2]
+    d = 4
+    Mt, psi, kept = _sector_spectrum_case(case, direction, seed + 100)
+    plan = make_plan(ctx, case)
+    rng = np.random.default_rng(seed)
+    n = ml * d if direction == "l2r" else d * mr
+    site = torch.empty(n * n, dtype=torch.float64, device=DEV)
+    if direction == "l2r":
+        nbr = rng.standard_normal((mr, d, 3))
+        nout = torch.empty(n * d * 3, dtype=torch.float64, device=DEV)
+        k, disc, q, dims = plan.truncate(abi.L2R, dev(Mt), dev(psi), n, 1e-14, dev(nbr), site, nout,
+                                         renormalize=False)
+        A, B, s, disc_ref = C.truncate_l2r(Mt, psi, nbr, n, 1e-14)
+        U = site[: n * k].view(n, k).cpu().numpy()
+        X = nout[: k * d * 3].view(k, -1).cpu().numpy()
+        Ur, Xr = A.reshape(n, -1), B.reshape(A.shape[2], -1)
+    else:
+        nbr = rng.standard_normal((3, d, ml))
+        nout = torch.empty(3 * d * n, dtype=torch.float64, device=DEV)
+        k, disc, q, dims = plan.truncate(abi.R2L, dev(Mt), dev(psi), n, 1e-14, dev(nbr), site, nout,
+                                         renormalize=False)
+        Bs, A, s, disc_ref = C.truncate_r2l(Mt, psi, nbr, n, 1e-14)
+        U = site[: k * n].view(k, n).cpu().numpy().T
+        X = nout[: 3 * d * k].view(-1, k).cpu().numpy().T
+        Ur, Xr = Bs.reshape(Bs.shape[0], -1).T, A.reshape(-1, Bs.shape[0]).T
+    plan.close()
+    assert k == sum(kept.values()) == Ur.shape[1]
+    got = {(int(a), int(b)): int(m) for (a, b), m in zip(q, dims)}
+    assert got == {Q: v for Q, v in kept.items() if v > 0}
+    # sectors are ordered by charge and the site tensor is an isometry
+    assert np.abs(U.T @ U - np.eye(k)).max() < 1e-13
+    assert np.abs(U @ U.T - Ur @ Ur.T).max() < 1e-3
+    assert rel_err(U @ X, Ur @ Xr) < 1e-9
+    assert abs(disc - disc_ref) < 1e-14 * float(np.sum(s ** 2))
+
+
 @pytest.mark.parametrize("ml,mr,seed", [(40, 52, 21), (300, 257, 22)])
 def test_block_update_env_equals_dense_oracle(ctx, ml, mr, seed):
     """Both environment updates from the grouped launches equal the oracle's

@@ -215,14 +215,21 @@ def _mixed(tensors, mpo, center):
     return M, Lenv, Renv
 
 
+def _s_tol(s, s0):
+    """Accuracy of the singular values of the Gram route: an eigenvalue of
+    X X^T carries an absolute error of about K u s_0^2 (K <= 2e4 terms), so
+    s_j is good to ~1e-14 s_0 + 5e-14 s_0^2 / s_j until the deflated passes
+    take over (below ~1e-5 s_0, where their own scale is that small)."""
+    return 2e-14 * s0 + 5e-14 * s0 * s0 / np.maximum(s, 1e-300)
+
+
 @pytest.mark.parametrize("direction", ["l2r", "r2l"])
 @pytest.mark.parametrize("kmax", [3, 64])
 def test_truncate(ctx, direction, kmax):
-    """Singular values equal LAPACK's; the kept projector and the contracted
-    two-site block are gauge invariant and must match the oracle.  The Gram
-    route cannot resolve s_j below ~1e-7 s_0, so the GPU may keep fewer
-    (numerically null) states than LAPACK; the oracle is then re-run with the
-    GPU's k, which must only have dropped such states."""
+    """Steps 4-5 against the oracle's LAPACK SVD at the same kmax and eps =
+    1e-14: the same number of kept states, the same singular values, and the
+    same gauge-invariant kept projector, contracted two-site block and
+    discarded weight."""
     l, center = 8, 4
     mpo = MPO.heisenberg_mpo(l)
     M, Lenv, Renv = _mixed(synth.random_mps(l, 2, 16, seed=31), mpo, center)
@@ -237,11 +244,13 @@ def test_truncate(ctx, direction, kmax):
         nout = torch.empty(n * nbr.shape[1] * nbr.shape[2], dtype=torch.float64, device=DEV)
         kk, dd, sv = ctx.truncate(abi.L2R, dev(Mt), dev(psi), kmax, 1e-14, dev(nbr), site, nout,
                                   renormalize=False)
-        _, _, s, _ = C.truncate_l2r(Mt, psi, nbr, kmax, 1e-14)
-        A, B, _, disc = C.truncate_l2r(Mt, psi, nbr, kk, 1e-14)
+        A, B, s, disc = C.truncate_l2r(Mt, psi, nbr, kmax, 1e-14)
+        k_lapack = A.shape[2]
+        assert kk == k_lapack
         Ag = site[: n * kk].cpu().numpy().reshape(n, kk)
         Bg = nout[: kk * nbr.shape[1] * nbr.shape[2]].cpu().numpy().reshape(kk, -1)
         Ao = A.reshape(n, kk)
+        assert np.abs(Ag.T @ Ag - np.eye(kk)).max() < 1e-13
         assert np.abs(Ag @ Ag.T - Ao @ Ao.T).max() < 1e-10
         two, ref_two = Ag @ Bg, Ao @ B.reshape(kk, -1)
     else:
@@ -252,20 +261,80 @@ def test_truncate(ctx, direction, kmax):
         nout = torch.empty(nbr.shape[0] * nbr.shape[1] * n, dtype=torch.float64, device=DEV)
         kk, dd, sv = ctx.truncate(abi.R2L, dev(Mt), dev(psi), kmax, 1e-14, dev(nbr), site, nout,
                                   renormalize=False)
-        _, _, s, _ = C.truncate_r2l(Mt, psi, nbr, kmax, 1e-14)
-        Bs, A, _, disc = C.truncate_r2l(Mt, psi, nbr, kk, 1e-14)
+        Bs, A, s, disc = C.truncate_r2l(Mt, psi, nbr, kmax, 1e-14)
+        k_lapack = Bs.shape[0]
+        assert kk == k_lapack
         Bg = site[: kk * n].cpu().numpy().reshape(kk, n)
         Ag = nout[: nbr.shape[0] * nbr.shape[1] * kk].cpu().numpy().reshape(-1, kk)
         Bo = Bs.reshape(kk, n)
+        assert np.abs(Bg @ Bg.T - np.eye(kk)).max() < 1e-13
         assert np.abs(Bg.T @ Bg - Bo.T @ Bo).max() < 1e-10
         two, ref_two = Ag @ Bg, A.reshape(-1, kk) @ Bo
-    k_lapack = C.truncation_size(s, kmax, 1e-14)
-    assert kk <= k_lapack
-    assert kk == k_lapack or s[kk] < 1e-6 * s[0]
     m = min(len(sv), len(s))
-    assert np.allclose(sv[:m], s[:m], atol=1e-7 * s[0])
+    sv, s = np.asarray(sv[:m]), s[:m]
+    assert np.all(np.abs(sv - s) <= _s_tol(s, s[0]) + 2e-15 * s[0])
     assert abs(dd - disc) < 1e-10
     assert rel_err(two, ref_two) < 1e-9
+
+
+def _prescribed(n, width, r, smin, seed):
+    """An n x width matrix of rank r with singular values geomspace(1, smin, r)."""
+    rng = np.random.default_rng(seed)
+    s_true = np.geomspace(1.0, smin, r)
+    Q1 = np.linalg.qr(rng.standard_normal((n, r)))[0]
+    Q2 = np.linalg.qr(rng.standard_normal((width, r)))[0]
+    return (Q1 * s_true) @ Q2.T, s_true, Q1, Q2
+
+
+@pytest.mark.parametrize("direction", ["l2r", "r2l"])
+@pytest.mark.parametrize("ml,d,mr,width,r", [(10, 4, 10, 70, 20), (128, 4, 256, 1536, 300), (512, 4, 512, 3072, 700)])
+def test_truncate_resolves_every_value_above_eps(ctx, direction, ml, d, mr, width, r):
+    """A prescribed spectrum 1 ... 1e-12 on a rank-r matrix: a single FP64
+    Gram matrix resolves only s_j > ~1e-6 s_0, so the kept count, values and
+    subspace need the deflated passes.  The GPU keeps exactly the r states
+    LAPACK keeps (all above 1e-14 s_0), with the prescribed values and the
+    LAPACK subspace, and an isometric site tensor."""
+    n = ml * d if direction == "l2r" else d * mr
+    Xm, s_true, Q1, Q2 = _prescribed(n, width, r, 1e-12, 51 + r)
+    rng = np.random.default_rng(3)
+    kmax = n
+    if direction == "l2r":
+        Mt = Xm
+        psi = Mt[:, :mr].reshape(ml, d, mr).copy()
+        nbr = rng.standard_normal((mr, d, 5))
+        A, B, s, disc = C.truncate_l2r(Mt, psi, nbr, kmax, 1e-14)
+        site = torch.empty(n * kmax, dtype=torch.float64, device=DEV)
+        nout = torch.empty(kmax * d * 5, dtype=torch.float64, device=DEV)
+        kk, dd, sv = ctx.truncate(abi.L2R, dev(Mt), dev(psi), kmax, 1e-14, dev(nbr), site, nout, renormalize=False)
+        U = site[: n * kk].cpu().numpy().reshape(n, kk)
+        Uo = A.reshape(n, -1)
+        Bg = nout[: kk * d * 5].cpu().numpy().reshape(kk, -1)
+        two, ref_two = U @ Bg, Uo @ B.reshape(kk, -1)
+    else:
+        Mt = Xm.T.copy()                                   # width x (d mr): the right vectors are Q1
+        psi = Mt[:ml].reshape(ml, d, mr).copy()
+        nbr = rng.standard_normal((5, d, ml))
+        Bs, A, s, disc = C.truncate_r2l(Mt, psi, nbr, kmax, 1e-14)
+        site = torch.empty(n * kmax, dtype=torch.float64, device=DEV)
+        nout = torch.empty(5 * d * kmax, dtype=torch.float64, device=DEV)
+        kk, dd, sv = ctx.truncate(abi.R2L, dev(Mt), dev(psi), kmax, 1e-14, dev(nbr), site, nout, renormalize=False)
+        U = site[: kk * n].cpu().numpy().reshape(kk, n).T
+        Uo = Bs.reshape(-1, n).T
+        Ag = nout[: 5 * d * kk].cpu().numpy().reshape(-1, kk)
+        two, ref_two = Ag @ U.T, A.reshape(-1, kk) @ Uo.T
+    assert Uo.shape[1] == r
+    assert kk == r
+    sv = np.asarray(sv)
+    assert np.all(np.abs(sv[:r] - s_true) <= _s_tol(s_true, 1.0) + 2e-15)
+    assert np.all(np.abs(sv[r:]) < 1e-14)
+    assert np.abs(U.T @ U - np.eye(r)).max() < 1e-13
+    # the kept subspace: a direction with singular value s is resolved to about u / s
+    P, Po = U @ U.T, Uo @ Uo.T
+    assert np.abs(P - Po).max() < 1e-3
+    assert np.abs(P - Q1 @ Q1.T).max() < 1e-3
+    # the state (and the neighbour through it) is reproduced to rounding
+    assert rel_err(two, ref_two) < 1e-9
+    assert abs(dd - disc) < 1e-14 * float(np.sum(s_true ** 2))
 
 
 def test_lanczos_matches_oracle_eigenvalue(ctx):
