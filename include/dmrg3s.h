@@ -143,6 +143,24 @@ d3s_status d3s_set_splitk(d3s_ctx ctx, int enable);
 d3s_status d3s_apply_heff(d3s_ctx ctx, d3s_prec prec, int ml, int d, int mr, int wl, int wr,
                           const void* L, const void* W, const void* R, const void* psi, void* out);
 
+/*
+ * H_eff * psi with no device allocation, for callers that cannot allocate:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  The same product as d3s_apply_heff (same arguments, element
+ * types and results up to rounding), but its intermediates -- T1 (ml wl d mr
+ * elements: double for D3S_F64, float otherwise), T2 and the K-contiguous
+ * copy of psi (ml d wr mr and ml d mr elements of the operand type) -- and
+ * the split-K partial products live in a 64 MiB array of device memory that
+ * the library holds per GPU until the process ends (set up by d3s_create;
+ * no autotuning, no profiling events).  A product whose intermediates need
+ * more than 64 MiB (each rounded up to 256 bytes) returns D3S_EINVAL before
+ * any launch; e.g. d = 4, w = 6 in FP64 fits up to m_l = m_r = 400.  Every
+ * call on a GPU uses that GPU's one array: calls that overlap on one GPU
+ * (other streams, other contexts) race.  Asynchronous on the context's stream.
+ */
+d3s_status d3s_apply_heff_noalloc(d3s_ctx ctx, d3s_prec prec, int ml, int d, int mr, int wl, int wr,
+                                  const void* L, const void* W, const void* R, const void* psi, void* out);
+
 /* Per-kernel timing of d3s_apply_heff: while enabled, HIP events are
  * recorded on the context's stream around each of its three launches (GEMM
  * over the left bond, W-map, GEMM over (v, y)) for up to `capacity` calls.

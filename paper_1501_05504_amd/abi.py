@@ -85,6 +85,7 @@ _apply_heff = _sig("d3s_apply_heff", c_int, [c_void_p, c_int] + [c_int] * 5 + [c
 _apply_heff2 = _sig("d3s_apply_heff_two_site", c_int, [c_void_p, c_int] + [c_int] * 6 + [c_void_p] * 6)
 _cwf_env = _sig("d3s_cwf_environment", c_int, [c_void_p] + [c_int] * 4 + [c_void_p] * 3)
 _apply_cwf = _sig("d3s_apply_cwf", c_int, [c_void_p, c_int] + [c_int] * 3 + [c_void_p] * 4)
+_apply_heff_noalloc = _sig("d3s_apply_heff_noalloc", c_int, [c_void_p, c_int] + [c_int] * 5 + [c_void_p] * 5)
 _expand = _sig("d3s_expand_subspace", c_int, [c_void_p, c_int] + [c_int] * 5 + [c_void_p] * 3 +
                [c_double, c_void_p])
 _truncate = _sig("d3s_truncate", c_int, [c_void_p, c_int, c_int, c_int, c_int, c_long, c_void_p, c_void_p,
@@ -290,6 +291,22 @@ class Context:
         _need(out, ml * d * mr, to, "out")
         return self._check(_apply_heff(self.h, prec, ml, d, mr, wl, wr, _ptr(L), _ptr(W), _ptr(R),
                                        _ptr(psi), _ptr(out)))
+
+    def apply_heff_noalloc(self, L, W, R, psi, out):
+        """apply_heff whose intermediates live in the library's fixed 64 MiB
+        per-GPU scratch array (no device allocation)."""
+        self._sync_stream()
+        ml, d, mr = psi.shape
+        wl, wr = W.shape[0], W.shape[1]
+        prec = _PREC[psi.dtype]
+        te, tw, to = _ELT[prec]
+        _need(L, ml * wl * ml, te, "L")
+        _need(W, wl * wr * d * d, tw, "W")
+        _need(R, mr * wr * mr, te, "R")
+        _need(psi, ml * d * mr, te, "psi")
+        _need(out, ml * d * mr, to, "out")
+        return self._check(_apply_heff_noalloc(self.h, prec, ml, d, mr, wl, wr, _ptr(L), _ptr(W), _ptr(R),
+                                               _ptr(psi), _ptr(out)))
 
     def apply_heff_two_site(self, L, W1, W2, R, psi2, out):
         """Two-site H_eff * psi2, psi2 and out (ml, d, d, mr); FP64 or FP32."""

@@ -86,6 +86,13 @@ d3s_status d3s_create(d3s_ctx* out, int device, void* stream, const d3s_allocato
     delete ctx;
     return D3S_EDEVICE;
   }
+  try {
+    d3s::noalloc_init(device);   // the device address of this GPU's scratch array
+  } catch (...) {
+    (void)hipHostFree(ctx->c.host_red);
+    delete ctx;
+    return D3S_EDEVICE;
+  }
   *out = ctx;
   return D3S_OK;
 }
@@ -251,6 +258,18 @@ d3s_status d3s_apply_heff(d3s_ctx ctx, d3s_prec prec, int ml, int d, int mr, int
     D3S_REQUIRE(L && W && R && psi && out, "null tensor pointer");
     D3S_REQUIRE(out != psi && out != L && out != R, "out must not alias an input");
     d3s::op_apply_heff(&ctx->c, prec, ml, d, mr, wl, wr, L, W, R, psi, out);
+    return D3S_OK;
+  });
+}
+
+d3s_status d3s_apply_heff_noalloc(d3s_ctx ctx, d3s_prec prec, int ml, int d, int mr, int wl, int wr,
+                                  const void* L, const void* W, const void* R, const void* psi, void* out) {
+  return guarded(ctx, [&] {
+    check_prec(prec);
+    check_dims(ml, d, mr, wl, wr);
+    D3S_REQUIRE(L && W && R && psi && out, "null tensor pointer");
+    D3S_REQUIRE(out != psi && out != L && out != R, "out must not alias an input");
+    d3s::op_apply_heff_noalloc(&ctx->c, prec, ml, d, mr, wl, wr, L, W, R, psi, out);
     return D3S_OK;
   });
 }

@@ -77,6 +77,8 @@ void ws_release_all(Ctx* c);
 // A is "K-contiguous" (A[m*lda + k]) when a_kc, else "M-contiguous" (A[k*lda + m]).
 // B is "K-contiguous" (B[n*ldb + k]) when b_kc, else "N-contiguous" (B[k*ldb + n]).
 // Batched over `batch` with element strides sA, sB, sC.
+// part / part_cap: a caller buffer for the split-K partial products (the
+// split count is then limited to what fits); null = the context workspace.
 struct GemmArgs {
   int M, N, K;
   const void* A; long lda; bool a_kc; long sA;
@@ -84,6 +86,8 @@ struct GemmArgs {
   void* C; long ldc; long sC;
   double alpha, beta;
   int batch;
+  void* part = nullptr;
+  size_t part_cap = 0;
 };
 void gemm_f64(Ctx* c, const GemmArgs& g);
 void gemm_f32(Ctx* c, const GemmArgs& g);
@@ -213,6 +217,19 @@ void adjoint_reduce_f64(Ctx* c, const double* T1, const double* U, double* G,
 // ---------------------------------------------------------------- host-side ops
 void op_apply_heff(Ctx* c, d3s_prec p, int ml, int d, int mr, int wl, int wr,
                    const void* L, const void* W, const void* R, const void* psi, void* out);
+// the same product on caller buffers T1 (ml wl d mr), T2 (ml d wr mr), psiT
+// (ml d mr) and split-K space `part`; plain: no autotuning, no profiling
+// events, no context workspace
+void heff_product(Ctx* c, d3s_prec p, int ml, int d, int mr, int wl, int wr, const void* L, const void* W,
+                  const void* R, const void* psi, void* out, void* T1, void* T2, void* psiT, void* part,
+                  size_t part_cap, bool plain);
+// allocation-free H_eff (noalloc.hip): bytes of scratch a product needs, the
+// per-device scratch set-up (d3s_create) and the product itself
+size_t noalloc_bytes(d3s_prec p, int ml, int d, int mr, int wl, int wr);
+size_t noalloc_capacity();
+void noalloc_init(int device);
+void op_apply_heff_noalloc(Ctx* c, d3s_prec p, int ml, int d, int mr, int wl, int wr, const void* L,
+                           const void* W, const void* R, const void* psi, void* out);
 void op_apply_heff_two_site(Ctx* c, d3s_prec p, int ml, int d, int mr, int wl, int wc, int wr, const void* L,
                             const void* W1, const void* W2, const void* R, const void* psi2, void* out);
 void op_apply_cwf(Ctx* c, d3s_prec p, int mlp, int mr, int wr, const void* Lt, const void* R, const void* C,

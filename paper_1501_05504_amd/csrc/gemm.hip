@@ -232,12 +232,18 @@ void launch_cfg(Ctx* c, const GemmArgs& g, int splits) {
   const int nTm = (g.M + BM - 1) / BM, nTn = (g.N + BN - 1) / BN;
   KParams p{g.M, g.N, g.K, g.A, g.lda, g.sA, g.B, g.ldb, g.sB, g.C, g.ldc, g.sC, g.alpha, g.beta, g.K, 0};
   AT* part = nullptr;
+  if (splits > 1 && g.part) {
+    // the caller's buffer bounds the number of partial products
+    const size_t per = sizeof(AT) * (size_t)g.M * g.N;
+    splits = (int)std::min<size_t>((size_t)splits, g.part_cap / per);
+    if (splits < 2) splits = 1;
+  }
   if (splits > 1) {
     // chunk = ceil(K / splits) rounded up to BK; recompute the number of splits
     int chunk = (g.K + splits - 1) / splits;
     chunk = (chunk + BK - 1) / BK * BK;
     splits = (g.K + chunk - 1) / chunk;
-    part = (AT*)ws_get(c, WS_SPLITK, sizeof(AT) * (size_t)splits * g.M * g.N);
+    part = g.part ? (AT*)g.part : (AT*)ws_get(c, WS_SPLITK, sizeof(AT) * (size_t)splits * g.M * g.N);
     p.C = part;
     p.ldc = g.N;
     p.sC = 0;

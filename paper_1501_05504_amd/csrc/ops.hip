@@ -76,25 +76,38 @@ void op_apply_heff(Ctx* c, d3s_prec p, int ml, int d, int mr, int wl, int wr, co
                    const void* W, const void* R, const void* psi, void* out) {
   const size_t tsz = (p == D3S_F64) ? 8 : 4;       // T1 element size (fp32 for BF16 too)
   const size_t t2sz = (p == D3S_F64) ? 8 : (p == D3S_F32 ? 4 : 2);
+  const size_t esz = t2sz;
   void* T1 = ws_get(c, WS_T1, tsz * (size_t)ml * wl * d * mr);
   void* T2 = ws_get(c, WS_T2, t2sz * (size_t)ml * d * wr * mr);
+  void* psiT = ws_get(c, WS_PSIT, esz * (size_t)ml * d * mr);
+  heff_product(c, p, ml, d, mr, wl, wr, L, W, R, psi, out, T1, T2, psiT, nullptr, 0, false);
+}
+
+void heff_product(Ctx* c, d3s_prec p, int ml, int d, int mr, int wl, int wr, const void* L, const void* W,
+                  const void* R, const void* psi, void* out, void* T1, void* T2, void* psiT, void* part,
+                  size_t part_cap, bool plain) {
   hipEvent_t* ev = nullptr;
-  if (c->prof && c->prof_n < c->prof_cap) ev = &c->prof_ev[4 * (size_t)c->prof_n++];
+  if (!plain && c->prof && c->prof_n < c->prof_cap) ev = &c->prof_ev[4 * (size_t)c->prof_n++];
   if (ev) D3S_HIP(hipEventRecord(ev[0], c->stream));
   // GEMM-1's B operand psi[x][(t,y)] runs along N; a copy psi^T[(t,y)][x]
   // runs along K, which keeps the LDS staging of B in 16-byte vector stores
   // (the transposing stores cost most in BF16).  Counted in GEMM-1's time.
   const size_t esz = (p == D3S_F64) ? 8 : (p == D3S_F32 ? 4 : 2);
-  void* psiT = ws_get(c, WS_PSIT, esz * (size_t)ml * d * mr);
   transpose_any(c, (int)esz, psi, ml, (long)d * mr, psiT);
   GemmArgs g1{ml * wl, d * mr, ml, L, ml, true, 0, psiT, ml, true, 0, T1, (long)d * mr, 0, 1.0, 0.0, 1};
-  tuned_gemm(c, p, g1);
+  g1.part = part;
+  g1.part_cap = part_cap;
+  if (plain) gemm(c, p, g1);
+  else tuned_gemm(c, p, g1);
   if (ev) D3S_HIP(hipEventRecord(ev[1], c->stream));
   wmap_l2r(c, p, T1, W, T2, (long)wr * mr, ml, d, mr, wl, wr, 1.0);
   if (ev) D3S_HIP(hipEventRecord(ev[2], c->stream));
   GemmArgs g2{ml * d, mr, wr * mr, T2, (long)wr * mr, true, 0, R, (long)wr * mr, true, 0, out, mr, 0,
               1.0, 0.0, 1};
-  tuned_gemm(c, p, g2);
+  g2.part = part;
+  g2.part_cap = part_cap;
+  if (plain) gemm(c, p, g2);
+  else tuned_gemm(c, p, g2);
   if (ev) D3S_HIP(hipEventRecord(ev[3], c->stream));
 }
 
