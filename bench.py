@@ -170,7 +170,8 @@ def block_heff_bench(ctx, abi, synth, torch, np, m, dev, steps):
     return info
 
 
-def hubbard_sweep_bench(ctx, abi, synth, torch, dev, l, sched, U, tol, lanczos_tol, max_final, growth_tol):
+def hubbard_sweep_bench(ctx, abi, synth, torch, dev, l, sched, U, tol, lanczos_tol, max_final, growth_tol,
+                        mixed_min_gflop):
     """DMRG3S block sweeps on the Hubbard chain (t = 1, half filling, 2Sz = 0)
     from one seeded symmetric state with a growing bond limit: two sweeps at
     each m of the schedule, then sweeps at the last m until the normalised
@@ -179,8 +180,9 @@ def hubbard_sweep_bench(ctx, abi, synth, torch, dev, l, sched, U, tol, lanczos_t
     change nothing and the run moves to the final stage.  The growth sweeps
     solve the local problems to `growth_tol`, the final ones to
     `lanczos_tol`.  Plain FP64 products against FP32 products with FP64
-    refinement of every Ritz vector to the same residual tolerance; wall time
-    from the first environment build on."""
+    refinement of every Ritz vector to the same residual tolerance (at every
+    site whose product costs at least `mixed_min_gflop`; 0 = all sites); wall
+    time from the first environment build on."""
     out = {"workload": "hubbard_chain_blocks", "l": l, "U": U, "filling": "half, 2Sz=0", "m_schedule": sched,
            "tol": tol, "lanczos_tol": lanczos_tol, "growth_lanczos_tol": growth_tol}
     phys = abi.HUBBARD_CHARGES
@@ -193,6 +195,8 @@ def hubbard_sweep_bench(ctx, abi, synth, torch, dev, l, sched, U, tol, lanczos_t
         t0 = time.perf_counter()
         e0 = ctx.prepare_blocks(st, sym)
         params = abi.sweep_params(alpha=1e-3, e_before=e0, prec=prec, tol=lanczos_tol)
+        if prec != abi.F64:
+            params.mixed_min_gflop = mixed_min_gflop
         energies, t_conv, prev, nsweeps, mv, mv64 = [], None, None, 0, 0, 0
         plan = [(m, 2) for m in sched[:-1]] + [(sched[-1], max_final)]
         saturated = False
@@ -219,6 +223,7 @@ def hubbard_sweep_bench(ctx, abi, synth, torch, dev, l, sched, U, tol, lanczos_t
         split = {k: round(sum(getattr(r, k) for r in recs), 3) for k in ("t_eig", "t_expand", "t_trunc", "t_env", "t_energy")}
         out[name] = {"seconds_to_tol": None if t_conv is None else round(t_conv, 3), "seconds": round(wall, 3),
                      "sweeps": nsweeps, "energy": energies[-1], "matvecs": mv, "f64_matvecs": mv64,
+                     "low_precision_share": round(1.0 - mv64 / max(mv, 1), 4),
                      "last_sweep_split_s": split, "max_bond": max(st.m),
                      "sectors_mid_bond": int(sym._nsec[l // 2])}
         print("bench: hubbard sweeps %s: %d sweeps %.2f s  E=%.12f  max bond %d" % (
@@ -226,17 +231,22 @@ def hubbard_sweep_bench(ctx, abi, synth, torch, dev, l, sched, U, tol, lanczos_t
         del st
         torch.cuda.empty_cache()
     out["energy_diff"] = abs(out["f64"]["energy"] - out["mixed_f32"]["energy"])
+    out["mixed_min_gflop"] = mixed_min_gflop
     return out
 
 
-def cylinder_bench(ctx, abi, synth, torch, dev, sched, sweeps_last, lanczos_tol, precs):
+def cylinder_bench(ctx, abi, synth, torch, dev, sched, sweeps_last, lanczos_tol, precs, tol):
     """4 x 16 Hubbard cylinder (t = 1, U = 4, N = 56, 2Sz = 0, w = 18, every
-    column traversed in the same direction), U(1)xU(1) blocks: one sweep at
-    each bond limit of the schedule, then `sweeps_last` more at the last,
-    from the same seeded symmetric state for every precision of the
-    eigensolver's products (FP64; FP32 / BF16 with FP64 refinement to the
-    same residual).  Reports per-sweep energies and times and the energy
-    difference of each mixed run against the FP64 run, sweep by sweep."""
+    column traversed in the same direction), U(1)xU(1) blocks.  The bond
+    grows with FP64 products, one sweep at each limit of the schedule but
+    the last; that state is saved (site tensors and sectors), and for every
+    precision of the eigensolver's products (FP64; FP32 / BF16 with FP64
+    refinement to the same residual) a fresh state is rebuilt from it
+    (environments by d3s_prepare_blocks) and swept at the last limit until
+    the normalised sweep energy change is below `tol`, at most `sweeps_last`
+    sweeps.  Reports per-sweep energies, times and energy changes, the time
+    to `tol` (null if not reached), and each mixed run's energy difference
+    against the FP64 run, sweep by sweep."""
     width, length = 4, 16
     l = width * length
     mpo = abi.hubbard_cylinder_mpo(width, length, t=1.0, U=4.0)
@@ -244,31 +254,59 @@ def cylinder_bench(ctx, abi, synth, torch, dev, sched, sweeps_last, lanczos_tol,
     chan = abi.mpo_bond_charges(mpo, abi.mpo_fermion_charges(width))
     wmax = max(int(b.shape[1]) for b in mpo)
     mmax = max(sched)
+    cap = mmax * mmax * wmax // 4
     out = {"workload": "hubbard_cylinder_blocks", "width": width, "length": length, "U": 4.0, "N": 56, "w": wmax,
-           "m_schedule": sched, "sweeps_at_last_m": sweeps_last, "lanczos_tol": lanczos_tol}
-    plan = [m for m in sched] + [sched[-1]] * sweeps_last
+           "m_schedule": sched, "max_sweeps_at_last_m": sweeps_last, "lanczos_tol": lanczos_tol, "tol": tol}
+    tensors, secs = synth.random_symmetric_mps(l, phys, [56, 0], sched[0], seed=synth.SEED_MPS)
+    st = abi.State(mpo, tensors, mmax, device=dev, env_cap=cap)
+    sym = abi.Symmetry(phys, chan, secs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0 = ctx.prepare_blocks(st, sym)
+    params = abi.sweep_params(alpha=1e-3, e_before=e0, prec=abi.F64, tol=lanczos_tol)
+    growth = []
+    for m in sched[:-1]:
+        params.m_limit = m
+        t = time.perf_counter()
+        _, stats, recs = ctx.sweep_blocks(st, sym, params, use_graph=True)
+        growth.append({"m": m, "seconds": round(time.perf_counter() - t, 3), "energy": stats.energy,
+                       "t_eig": round(sum(r.t_eig for r in recs), 3), "t_trunc": round(sum(r.t_trunc for r in recs), 3),
+                       "max_bond": max(st.m), "sectors_mid_bond": int(sym._nsec[l // 2])})
+        print("bench: cylinder growth m=%d %.2f s E=%.10f" % (m, growth[-1]["seconds"], stats.energy),
+              file=sys.stderr, flush=True)
+    out["growth_f64"] = {"sweeps": growth, "seconds": round(time.perf_counter() - t0, 3)}
+    saved = [t.cpu() for t in st.tensors()]
+    saved_secs = [sym.sectors(b) for b in range(l + 1)]
+    alpha = params.alpha
+    del st
+    torch.cuda.empty_cache()
     for name in precs:
         prec = {"f64": abi.F64, "mixed_f32": abi.F32, "mixed_bf16": abi.BF16}[name]
-        tensors, secs = synth.random_symmetric_mps(l, phys, [56, 0], sched[0], seed=synth.SEED_MPS)
-        st = abi.State(mpo, tensors, mmax, device=dev, env_cap=mmax * mmax * wmax // 4)
-        sym = abi.Symmetry(phys, chan, secs)
+        st = abi.State(mpo, saved, mmax, device=dev, env_cap=cap)
+        sym = abi.Symmetry(phys, chan, saved_secs)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         e0 = ctx.prepare_blocks(st, sym)
-        params = abi.sweep_params(alpha=1e-3, e_before=e0, prec=prec, tol=lanczos_tol)
-        rows = []
-        for m in plan:
-            params.m_limit = m
+        params = abi.sweep_params(alpha=alpha, e_before=e0, prec=prec, tol=lanczos_tol)
+        params.m_limit = sched[-1]
+        rows, prev, t_conv = [], None, None
+        for _ in range(sweeps_last):
             t = time.perf_counter()
             _, stats, recs = ctx.sweep_blocks(st, sym, params, use_graph=True)
-            rows.append({"m": m, "seconds": round(time.perf_counter() - t, 3), "energy": stats.energy,
-                         "t_eig": round(sum(r.t_eig for r in recs), 3),
+            dE = None if prev is None else abs(stats.energy - prev) / abs(stats.energy)
+            rows.append({"m": sched[-1], "seconds": round(time.perf_counter() - t, 3), "energy": stats.energy,
+                         "rel_energy_change": dE, "t_eig": round(sum(r.t_eig for r in recs), 3),
                          "t_trunc": round(sum(r.t_trunc for r in recs), 3),
                          "matvecs": sum(r.matvecs for r in recs), "f64_matvecs": sum(r.f64_matvecs for r in recs),
                          "max_bond": max(st.m), "sectors_mid_bond": int(sym._nsec[l // 2])})
-            print("bench: cylinder %s m=%d %.2f s E=%.10f" % (name, m, rows[-1]["seconds"], stats.energy),
-                  file=sys.stderr, flush=True)
-        out[name] = {"sweeps": rows, "seconds": round(time.perf_counter() - t0, 3)}
+            print("bench: cylinder %s m=%d %.2f s E=%.10f dE=%s" % (name, sched[-1], rows[-1]["seconds"],
+                                                                    stats.energy, dE), file=sys.stderr, flush=True)
+            prev = stats.energy
+            if dE is not None and dE < tol:
+                t_conv = time.perf_counter() - t0
+                break
+        out[name] = {"sweeps": rows, "seconds": round(time.perf_counter() - t0, 3),
+                     "seconds_to_tol": None if t_conv is None else round(t_conv, 3)}
         del st
         torch.cuda.empty_cache()
     if "f64" in out:
@@ -508,7 +546,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--m", type=int, default=2048)
-    ap.add_argument("--extra-m", type=str, default="256,1024",
+    ap.add_argument("--extra-m", type=str, default="256,1024,4096",
                     help="other bond dimensions reported beside the headline (comma list, '' = none)")
     ap.add_argument("--no-f32", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
@@ -524,14 +562,18 @@ def main():
     ap.add_argument("--sweep-max", type=int, default=8, help="sweeps at the last bond limit")
     ap.add_argument("--growth-tol", type=float, default=1e-6,
                     help="eigensolver residual tolerance of the bond-growth sweeps of the Hubbard chain run")
+    ap.add_argument("--mixed-min-gflop", type=float, default=0.0,
+                    help="mixed-precision leg of the Hubbard chain run: sites whose product costs fewer GFLOP use "
+                         "FP64 products (0 = every site mixed)")
     ap.add_argument("--dense-m", type=int, default=256, help="bond limit of the dense-vs-block one-sweep comparison")
     ap.add_argument("--cylinder", type=str, default="256,512,1024,2048,4096",
                     help="bond limits of the 4x16 cylinder run ('' = skip)")
-    ap.add_argument("--cylinder-last", type=int, default=0, help="extra sweeps at the last cylinder bond limit")
+    ap.add_argument("--cylinder-last", type=int, default=3,
+                    help="at most this many sweeps at the last cylinder bond limit (until dE < 1e-8)")
     ap.add_argument("--cylinder-precs", type=str, default="f64,mixed_bf16",
                     help="eigensolver product precisions compared (f64, mixed_f32, mixed_bf16)")
-    ap.add_argument("--gradient", type=str, default="",
-                    help="bond limits of the J1-J2 dE/dJ2 run (l=48, J2=0.24; e.g. 64,128,256,512; '' = skip)")
+    ap.add_argument("--gradient", type=str, default="64,128,256,512",
+                    help="bond limits of the J1-J2 dE/dJ2 run (l=48, J2=0.24; '' = skip)")
 
     ap.add_argument("--residual-m", type=int, default=128,
                     help="bond limit of the Hubbard chain in the expansion-term comparison (0 = skip)")
@@ -650,7 +692,7 @@ def main():
         print("bench: blocks %s" % line["blocks"], file=sys.stderr, flush=True)
         sched = [int(x) for x in args.sweep_sched.split(",")]
         line["sweep"] = hubbard_sweep_bench(ctx, abi, synth, torch, dev, args.sweep_l, sched, 8.0, 1e-8, 1e-10,
-                                            args.sweep_max, args.growth_tol)
+                                            args.sweep_max, args.growth_tol, args.mixed_min_gflop)
         if args.dense_m > 0:
             line["dense_vs_blocks"] = dense_vs_blocks_bench(ctx, abi, synth, torch, dev, args.sweep_l, args.dense_m,
                                                             8.0)
@@ -665,7 +707,7 @@ def main():
                                                   [int(x) for x in args.compare.split(",")], 20)
     if args.cylinder and not args.no_blocks:
         line["cylinder"] = cylinder_bench(ctx, abi, synth, torch, dev, [int(x) for x in args.cylinder.split(",")],
-                                          args.cylinder_last, 1e-10, args.cylinder_precs.split(","))
+                                          args.cylinder_last, 1e-10, args.cylinder_precs.split(","), 1e-8)
     if not args.no_cpu:
         print("bench: cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         Ln, Wn, Rn, pn = [x.cpu().numpy() for x in (L, W, R, psi)]

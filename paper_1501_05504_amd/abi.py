@@ -7,6 +7,7 @@ handed to the C-ABI.  Importing this module loads the library and raises
 ImportError when it has not been built.
 """
 import ctypes
+import weakref
 import os
 
 import torch
@@ -28,8 +29,29 @@ c_int, c_long, c_double, c_void_p = ctypes.c_int, ctypes.c_long, ctypes.c_double
 c_int_p, c_double_p = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
 
 
+_ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, ctypes.c_size_t, c_void_p, c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, c_void_p, c_void_p)
+
+
 class d3s_allocator(ctypes.Structure):
-    _fields_ = [("alloc", c_void_p), ("free", c_void_p), ("user", c_void_p)]
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", c_void_p)]
+
+
+def torch_allocator(device):
+    """(alloc, free) callbacks that take the library's device memory (its
+    workspace and the tables of block plans) from torch's caching allocator,
+    stream-ordered on the stream the library passes; a failed allocation
+    returns NULL, which the library reports as D3S_ENOMEM."""
+    def alloc(nbytes, stream, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device, int(stream or 0))
+        except Exception:
+            return None
+
+    def free(ptr, stream, user):
+        if ptr:
+            torch.cuda.caching_allocator_delete(ptr)
+    return alloc, free
 
 
 class d3s_state(ctypes.Structure):
@@ -195,19 +217,32 @@ _ELT = {F64: (torch.float64, torch.float64, torch.float64),     # (L/R/psi, W, o
 
 
 class Context:
-    """A library context bound to a device and to torch's current stream."""
+    """A library context bound to a device and to torch's current stream.
+    allocator: "torch" (default: torch's caching allocator owns every device
+    buffer of the library), None (the library's hipMalloc), or a pair of
+    Python callables alloc(nbytes, stream, user) -> address or None and
+    free(address, stream, user)."""
 
-    def __init__(self, device=0):
+    def __init__(self, device=0, allocator="torch"):
         self.device = device
         h = c_void_p()
         stream = torch.cuda.current_stream(device).cuda_stream
-        st = _create(ctypes.byref(h), device, c_void_p(stream), None)
+        self._alloc = None
+        if allocator is not None:
+            fa, ff = torch_allocator(device) if allocator == "torch" else allocator
+            # the callbacks must outlive the context
+            self._alloc = d3s_allocator(_ALLOC_FN(fa), _FREE_FN(ff), None)
+        st = _create(ctypes.byref(h), device, c_void_p(stream),
+                     ctypes.byref(self._alloc) if self._alloc is not None else None)
         if st != OK:
             raise D3SError(st, "d3s_create failed")
         self.h = h
+        self._plans = weakref.WeakSet()      # block plans whose tables this context holds
 
     def close(self):
         if self.h:
+            for p in list(self._plans):
+                p.close()
             _destroy(self.h)
             self.h = None
 
@@ -700,6 +735,7 @@ class BlockPlan:
 
     def __init__(self, ctx, nq, d, wl, wr, left_q, left_dim, right_q, right_dim, phys_q, wq_left, wq_right):
         self.ctx = ctx
+        self.h = None
         self._keep = []
 
         def sec(q, dim):
@@ -723,6 +759,7 @@ class BlockPlan:
         self.h = h
         self.flops = fl.value
         self.ntasks = nt.value
+        ctx._plans.add(self)
 
     def apply(self, L, W, R, psi, out, use_graph=False):
         ctx = self.ctx
@@ -805,9 +842,9 @@ class BlockPlan:
         return ctx._check(_env_blocks(ctx.h, self.h, direction, _ptr(env_in), _ptr(W), _ptr(site), _ptr(env_out)))
 
     def close(self):
-        if self.h:
+        if self.h and self.ctx.h:
             _plan_destroy(self.ctx.h, self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         try:

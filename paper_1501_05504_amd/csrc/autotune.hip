@@ -109,7 +109,7 @@ void tune_grouped(Ctx* c, GroupedPlan& g, const void* A, const void* B, void* C)
   for (int cfg = 0; cfg <= 5; ++cfg) {
     g.cfg = cfg;
     grouped_retile(c, g);
-    const double ms = time_ms(c, [&] { grouped_gemm(c, D3S_F64, g, A, B, C, 1.0); }, 2);
+    const double ms = time_ms(c, [&] { grouped_gemm(c, c->tune_prec, g, A, B, C, 1.0); }, 2);
     if (ms < best) {
       best = ms;
       best_cfg = cfg;

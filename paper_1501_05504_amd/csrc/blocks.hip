@@ -104,8 +104,9 @@ void grouped_finalize(Ctx* c, GroupedPlan& g) {
     g.d_tasks = (GTask*)base;
     g.d_segs = (GSeg*)(base + tb);
   } else {
-    D3S_HIP(hipMalloc((void**)&g.d_tasks, sizeof(GTask) * g.tasks.size()));
-    D3S_HIP(hipMalloc((void**)&g.d_segs, sizeof(GSeg) * std::max<size_t>(1, g.segs.size())));
+    g.owner = c;
+    g.d_tasks = (GTask*)dev_alloc(c, sizeof(GTask) * g.tasks.size());
+    g.d_segs = (GSeg*)dev_alloc(c, sizeof(GSeg) * std::max<size_t>(1, g.segs.size()));
   }
   if (!g.segs.empty())
     D3S_HIP(hipMemcpyAsync(g.d_segs, g.segs.data(), sizeof(GSeg) * g.segs.size(), hipMemcpyHostToDevice,
@@ -130,8 +131,8 @@ void grouped_retile(Ctx* c, GroupedPlan& g) {
 
 void grouped_release(GroupedPlan& g) {
   if (g.table_slot < 0) {
-    if (g.d_tasks) (void)hipFree(g.d_tasks);
-    if (g.d_segs) (void)hipFree(g.d_segs);
+    dev_free(g.owner, g.d_tasks);
+    dev_free(g.owner, g.d_segs);
   }
   g.d_tasks = nullptr;
   g.d_segs = nullptr;
@@ -288,8 +289,8 @@ void wmap_upload(Ctx* c, WmapPlan& w) {
     const int n = (int)(((long)k.di * k.dj + kWmapChunk - 1) / kWmapChunk);
     for (int q = 0; q < n; ++q) ct[(size_t)k.chunk0 + q] = (int)t;
   }
-  unsigned char* base = nullptr;
-  D3S_HIP(hipMalloc((void**)&base, host.size()));
+  w.owner = c;
+  unsigned char* base = (unsigned char*)dev_alloc(c, host.size());
   w.d_tasks = reinterpret_cast<WmapTask*>(base);
   w.d_ents = reinterpret_cast<WmapEnt*>(base + bt);
   w.d_ctask = reinterpret_cast<int*>(base + bt + be);
@@ -299,7 +300,7 @@ void wmap_upload(Ctx* c, WmapPlan& w) {
 
 void wmap_release(WmapPlan& w) {
   // one allocation holds the tasks, the entries and the chunk table
-  if (w.d_tasks) (void)hipFree(w.d_tasks);
+  dev_free(w.owner, w.d_tasks);
   w.d_tasks = nullptr;
   w.d_ents = nullptr;
   w.d_ctask = nullptr;
@@ -327,6 +328,7 @@ void build_block_heff(Ctx* c, BlockHeff& h, const Sectors& left, const Sectors& 
   const int nq = left.nq;
   if (nq < 1 || nq > 4) throw Error{D3S_EINVAL, "blocks: 1 to 4 charges per state"};
   const int ml = left.total, mr = right.total;
+  h.owner = c;
   h.left = left;
   h.right = right;
   h.ml = ml;
@@ -413,7 +415,7 @@ void build_block_heff(Ctx* c, BlockHeff& h, const Sectors& left, const Sectors& 
       }
     h.ntrt = (int)trt.size();
     if (!trt.empty()) {
-      D3S_HIP(hipMalloc((void**)&h.d_trt, sizeof(TrTile) * trt.size()));
+      h.d_trt = (TrTile*)dev_alloc(c, sizeof(TrTile) * trt.size());
       D3S_HIP(hipMemcpyAsync(h.d_trt, trt.data(), sizeof(TrTile) * trt.size(), hipMemcpyHostToDevice, c->stream));
       D3S_HIP(hipStreamSynchronize(c->stream));
     }
@@ -517,8 +519,7 @@ void add_rl_tiles(std::vector<RlTile>& v, long src, int sld, long dst, int dld, 
 
 RlTile* upload_rl(Ctx* c, const std::vector<RlTile>& v) {
   if (v.empty()) return nullptr;
-  RlTile* d = nullptr;
-  D3S_HIP(hipMalloc((void**)&d, sizeof(RlTile) * v.size()));
+  RlTile* d = (RlTile*)dev_alloc(c, sizeof(RlTile) * v.size());
   D3S_HIP(hipMemcpyAsync(d, v.data(), sizeof(RlTile) * v.size(), hipMemcpyHostToDevice, c->stream));
   D3S_HIP(hipStreamSynchronize(c->stream));
   return d;
@@ -532,15 +533,22 @@ Sectors padded_sectors(const Sectors& s) {
 
 }  // namespace
 
-LowpTwin& ensure_lowp(Ctx* c, BlockHeff& h) {
+LowpTwin& ensure_lowp(Ctx* c, BlockHeff& h, d3s_prec p) {
   if (h.padded) throw Error{D3S_EINVAL, "blocks: a padded plan has no twin"};
   if (h.lp) return *h.lp;
   LowpTwin* tw = new LowpTwin();
   try {
     const Sectors pl = padded_sectors(h.left), pr = padded_sectors(h.right);
     const int nq = h.left.nq;
-    build_block_heff(c, tw->h, pl, pr, h.d, h.wl, h.wr, h.pq.data(), h.wql.data(), h.wqr.data(), true, true, true,
-                     true);
+    c->tune_prec = p;
+    try {
+      build_block_heff(c, tw->h, pl, pr, h.d, h.wl, h.wr, h.pq.data(), h.wql.data(), h.wqr.data(), true, true,
+                       true, true);
+    } catch (...) {
+      c->tune_prec = D3S_F64;
+      throw;
+    }
+    c->tune_prec = D3S_F64;
     tw->h.padded = true;
     const BlockHeff& t = tw->h;
     std::vector<RlTile> vl, vr, vx, vy;
@@ -581,8 +589,7 @@ LowpTwin& ensure_lowp(Ctx* c, BlockHeff& h) {
     tw->nY = (int)vy.size();
   } catch (...) {
     release_block_heff(tw->h);
-    for (RlTile* p : {tw->d_L, tw->d_R, tw->d_X, tw->d_Y})
-      if (p) (void)hipFree(p);
+    for (RlTile* p : {tw->d_L, tw->d_R, tw->d_X, tw->d_Y}) dev_free(c, p);
     delete tw;
     throw;
   }
@@ -593,14 +600,13 @@ LowpTwin& ensure_lowp(Ctx* c, BlockHeff& h) {
 void release_block_heff(BlockHeff& h) {
   if (h.lp) {
     release_block_heff(h.lp->h);
-    for (RlTile* p : {h.lp->d_L, h.lp->d_R, h.lp->d_X, h.lp->d_Y})
-      if (p) (void)hipFree(p);
+    for (RlTile* p : {h.lp->d_L, h.lp->d_R, h.lp->d_X, h.lp->d_Y}) dev_free(h.owner, p);
     delete h.lp;
     h.lp = nullptr;
   }
   grouped_release(h.g1);
   grouped_release(h.g1t);
-  if (h.d_trt) (void)hipFree(h.d_trt);
+  dev_free(h.owner, h.d_trt);
   h.d_trt = nullptr;
   h.ntrt = 0;
   grouped_release(h.g2);
@@ -880,7 +886,7 @@ void op_apply_heff_blocks(Ctx* c, BlockHeff& h, d3s_prec p, const void* L, const
   if (p != D3S_F64 && !h.padded) {
     // operands of the plan's layouts, in the product's element type: moved
     // into the padded twin's layouts, multiplied there, the product moved back
-    LowpTwin& tw = ensure_lowp(c, h);
+    LowpTwin& tw = ensure_lowp(c, h, p);
     const int kind = (p == D3S_F32) ? RL_F32 : RL_BF16;
     const size_t esz = (p == D3S_F32) ? 4 : 2;
     void* Lp = ws_get(c, WS_LP_L, esz * (size_t)plan_nl(tw.h));

@@ -59,6 +59,7 @@ struct Ctx {
   double block_split_gflop = 1.0;    // split the block GEMM-2 from this many GFLOP on (< 0: never)
   bool splitk_off = false;           // disable split-K (tests compare both paths)
   bool autotune = false;             // time tile configurations on first use of a shape
+  d3s_prec tune_prec = D3S_F64;      // precision the grouped plans being built will run in
   int eig_kind = 0;                  // batched eigensolver: 0 auto, 1 divide and conquer, 2 Jacobi, 3 LDS solver
   int eig_jacobi_max = 0;            // auto: Jacobi up to this size
   std::unordered_map<std::string, int> tune_cache;
@@ -71,6 +72,11 @@ struct Ctx {
 
 void* ws_get(Ctx* c, int slot, size_t bytes);
 void ws_release_all(Ctx* c);
+// Device memory the library keeps outside the workspace (the tables of block
+// plans): from the context's allocator when one was given, else hipMalloc.
+// A null context in dev_free means hipFree.  D3S_ENOMEM on failure.
+void* dev_alloc(Ctx* c, size_t bytes);
+void dev_free(Ctx* c, void* p);
 
 // ---------------------------------------------------------------- GEMM
 // C[M x N] = alpha * A[M x K] * B[K x N] + beta * C, row-major C with ldc.
@@ -108,6 +114,7 @@ struct GroupedPlan {
   int cfg = 1;                  // tile configuration (grouped_tile_dims)
   double flops = 0.0;
   int table_slot = -1;          // >= 0: the device tables live in this workspace slot (not owned)
+  Ctx* owner = nullptr;         // context whose allocator holds the tables
 };
 void grouped_tile_dims(int cfg, int& bm, int& bn);   // block tile of a grouped configuration
 // sort tasks largest-first, pick the tile size, compute tile prefix sums and
@@ -152,6 +159,7 @@ struct WmapPlan {
   bool vec4 = false;            // every offset, row length and block width a multiple of 4
   int chunks = 0, maxk = 1;
   long in_rs = 0, out_rs = 0;
+  Ctx* owner = nullptr;         // context whose allocator holds the tables
 };
 // append a task (skipped when it has no outputs); upload() copies the tables
 void wmap_add(WmapPlan& w, int i_off, int di, int j_off, int dj, const std::vector<WmapEnt>& ins,
@@ -354,6 +362,7 @@ void transpose_tiles(Ctx* c, int esz, const void* in, void* out, const TrTile* t
 
 // Grouped-GEMM plans of one block-sparse H_eff (and its captured graph).
 struct BlockHeff {
+  Ctx* owner = nullptr;                  // context whose allocator holds the device tables
   int ml = 0, mr = 0, d = 0, wl = 0, wr = 0;
   Sectors left, right;                   // the bonds the plan was built for
   std::vector<int> pq, wql, wqr;         // charges: physical (d*nq), MPO bonds (wl*nq, wr*nq)
@@ -407,7 +416,9 @@ struct LowpTwin {
   RlTile *d_L = nullptr, *d_R = nullptr, *d_X = nullptr, *d_Y = nullptr;
   int nL = 0, nR = 0, nX = 0, nY = 0;
 };
-LowpTwin& ensure_lowp(Ctx* c, BlockHeff& h);
+// built on the first FP32 / BF16 product; its grouped launches are tuned
+// (autotuning on) in that product's precision
+LowpTwin& ensure_lowp(Ctx* c, BlockHeff& h, d3s_prec p);
 void build_block_heff(Ctx* c, BlockHeff& h, const Sectors& left, const Sectors& right, int d, int wl, int wr,
                       const int* phys_q, const int* wq_left, const int* wq_right, bool packed = false,
                       bool with_g2 = true, bool packed_env = false, bool with_psit = false);
@@ -480,8 +491,6 @@ bool tridiag_lowest(int n, const double* a, const double* b, double* theta, doub
 void jacobi_eigh(int n, std::vector<double>& A, std::vector<double>& evals,
                  std::vector<double>& evecs);
 
-// rocSOLVER symmetric eigensolver (FP64, column-major, ascending eigenvalues)
-void syevd_f64(Ctx* c, int n, double* A, double* evals_dev);
 
 double read_scalar(Ctx* c, const double* dev);
 

@@ -54,6 +54,25 @@ void ws_release_all(Ctx* c) {
   }
 }
 
+void* dev_alloc(Ctx* c, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  void* p = nullptr;
+  if (c->has_alloc) {
+    p = c->alloc.alloc(bytes, c->stream, c->alloc.user);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+  }
+  if (!p) throw Error{D3S_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
+  return p;
+}
+
+void dev_free(Ctx* c, void* p) {
+  if (!p) return;
+  if (c && c->has_alloc) c->alloc.free(p, c->stream, c->alloc.user);
+  else (void)hipFree(p);
+}
+
 double read_scalar(Ctx* c, const double* dev) {
   D3S_HIP(hipMemcpyAsync(c->host_red, dev, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   D3S_HIP(hipStreamSynchronize(c->stream));
@@ -250,29 +269,6 @@ void op_residual_gram(Ctx* c, d3s_dir dir, int ml, int d, int mr, int wl, int wr
 }
 
 // ---------------------------------------------------------------- eigensolvers
-void syevd_f64(Ctx* c, int n, double* A, double* evals_dev) {
-  if (!c->solver) {
-    rocblas_handle h = nullptr;
-    if (rocblas_create_handle(&h) != rocblas_status_success)
-      throw Error{D3S_EDEVICE, "rocblas_create_handle failed"};
-    c->solver = h;
-  }
-  rocblas_handle h = (rocblas_handle)c->solver;
-  if (rocblas_set_stream(h, c->stream) != rocblas_status_success)
-    throw Error{D3S_EDEVICE, "rocblas_set_stream failed"};
-  double* E = (double*)ws_get(c, WS_EIGTMP, sizeof(double) * (size_t)n);
-  rocblas_int* info = (rocblas_int*)ws_get(c, WS_INFO, 64);
-  rocblas_status st = rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper, n, A, n,
-                                       evals_dev, E, info);
-  if (st != rocblas_status_success)
-    throw Error{D3S_EDEVICE, "rocsolver_dsyevd failed (status " + std::to_string((int)st) + ")"};
-  rocblas_int hinfo = 0;
-  D3S_HIP(hipMemcpyAsync(&hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, c->stream));
-  D3S_HIP(hipStreamSynchronize(c->stream));
-  if (hinfo != 0)
-    throw Error{D3S_EDEVICE, "rocsolver_dsyevd did not converge (info " + std::to_string(hinfo) + ")"};
-}
-
 // `batch` symmetric n x n matrices stored one after the other (column-major);
 // eigenvalues ascending into evals[b*n + i], eigenvectors overwrite A.
 void syevd_batched_f64(Ctx* c, int n, int batch, double* A, double* evals) {
@@ -568,7 +564,7 @@ long op_residual_expand(Ctx* c, d3s_dir dir, int ml, int d, int mr, int wl, int 
   double* Q = (double*)ws_get(c, WS_RMET, sizeof(double) * (size_t)ng * ng);
   residual_metric(c, l2r ? R : L, h2, mnear, l2r ? wr : wl, Q);
   double* ev = (double*)ws_get(c, WS_EIGVAL, sizeof(double) * (size_t)ng);
-  syevd_f64(c, ng, Q, ev);
+  eig_batched_f64(c, ng, 1, Q, ev);          // the metric holds an identity block: norm >= 1
   std::vector<double> lam(ng);
   read_many(c, lam.data(), ev, ng);
   const double lmax = lam[ng - 1];
@@ -650,7 +646,7 @@ struct Matvec {
     Wc = Wf;
     if (plan) {
       // L and R converted once into the twin's padded packed layouts
-      tw = &ensure_lowp(c, *plan);
+      tw = &ensure_lowp(c, *plan, p);
       const int kind = (p == D3S_F32) ? RL_F32 : RL_BF16;
       const size_t esz = (p == D3S_F32) ? 4 : 2;
       void* Lp = ws_get(c, WS_CAST_L, esz * (size_t)plan_nl(tw->h));
@@ -739,10 +735,12 @@ LanczosResult lanczos_core(Ctx* c, Matvec& mv, double* x, long n, double tol, in
     D3S_HIP(hipEventCreateWithFlags((hipEvent_t*)&c->lz_ev[0], hipEventDisableTiming));
     D3S_HIP(hipEventCreateWithFlags((hipEvent_t*)&c->lz_ev[1], hipEventDisableTiming));
   }
-  // normalise the start vector
+  // normalise the start vector (a zero one has no direction: start from the
+  // constant vector; a non-finite one is an error)
   dot_f64(c, x, x, n, sc);
   double nrm2 = read_scalar(c, sc);
-  if (!(nrm2 > 0.0) || !std::isfinite(nrm2)) {
+  if (!std::isfinite(nrm2)) throw Error{D3S_ENUMERIC, "lanczos: the start vector is not finite"};
+  if (!(nrm2 > 0.0)) {
     fill_f64(c, x, n, 1.0);
     nrm2 = (double)n;
   }

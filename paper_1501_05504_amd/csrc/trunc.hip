@@ -55,8 +55,13 @@ __global__ __launch_bounds__(kThr) void gram_scale_kernel(const double* __restri
                                                           double* __restrict__ scale) {
   const PadDesc p = desc[blockIdx.x];
   __shared__ double red[kThr];
+  // a non-finite diagonal entry (a NaN or Inf in the matrix's rows) makes the
+  // maximum +Inf, which the host reports
   double mx = 0.0;
-  for (int i = threadIdx.x; i < p.n; i += kThr) mx = fmax(mx, fabs(G[p.off + (long)i * p.npad + i]));
+  for (int i = threadIdx.x; i < p.n; i += kThr) {
+    const double g = G[p.off + (long)i * p.npad + i];
+    mx = isfinite(g) ? fmax(mx, fabs(g)) : INFINITY;
+  }
   red[threadIdx.x] = mx;
   __syncthreads();
   for (int s = kThr / 2; s > 0; s >>= 1) {
@@ -222,14 +227,16 @@ void eig_run(Ctx* c, const EigPlan& ep, const std::vector<int>& n, double* G, do
   D3S_HIP(hipMemcpyAsync(d, mats.data(), sizeof(PadDesc) * mats.size(), hipMemcpyHostToDevice, c->stream));
   hipLaunchKernelGGL(gram_scale_kernel, dim3((unsigned)mats.size()), dim3(kThr), 0, c->stream, G, d, sc);
   D3S_HIP(hipGetLastError());
+  std::vector<double> hs(mats.size());
+  D3S_HIP(hipMemcpyAsync(hs.data(), sc, sizeof(double) * mats.size(), hipMemcpyDeviceToHost, c->stream));
+  D3S_HIP(hipStreamSynchronize(c->stream));
+  for (double v : hs)
+    if (!std::isfinite(v)) throw Error{D3S_ENUMERIC, "truncate: the expanded tensor is not finite"};
   const unsigned gx = (unsigned)std::min<long>((maxel + kThr - 1) / kThr, 2048);
   hipLaunchKernelGGL(gram_normalize_kernel, dim3(gx, (unsigned)mats.size()), dim3(kThr), 0, c->stream, G, d, sc);
   D3S_HIP(hipGetLastError());
   for (size_t b = 0; b < ep.bucket_n.size(); ++b)
     eig_batched_f64(c, ep.bucket_n[b], (int)ep.members[b].size(), G + ep.bucket_goff[b], V + ep.bucket_voff[b]);
-  std::vector<double> hs(mats.size());
-  D3S_HIP(hipMemcpyAsync(hs.data(), sc, sizeof(double) * mats.size(), hipMemcpyDeviceToHost, c->stream));
-  D3S_HIP(hipStreamSynchronize(c->stream));
   for (size_t i = 0; i < qs.size(); ++i) scale[qs[i]] = hs[i];
 }
 

@@ -72,9 +72,17 @@ def test_block_heff_equals_dense_oracle(ctx, ml, mr, seed):
 
 @pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5])
 def test_block_heff_every_grouped_tile(cfg):
-    """Every grouped tile configuration gives the oracle's result."""
+    """Every grouped tile configuration gives the oracle's result in FP64,
+    FP32 and BF16 (the low-precision products run on the padded twin; BF16
+    against the oracle on rounded operands with the rounding model of the
+    dense tests)."""
+    from tests.test_gpu_parity import bf16_bound, bf16_round
     case = hubbard_block_case(150, 130, 17)
     ref = C.apply_heff(case["L"], case["W"], case["R"], case["psi"])
+    Lb, Rb, pb = bf16_round(case["L"]), bf16_round(case["R"]), bf16_round(case["psi"])
+    Wf = np.asarray(case["W"], dtype=np.float32).astype(np.float64)
+    ref_b = C.apply_heff(Lb, Wf, Rb, pb)
+    bound_b = bf16_bound(Lb, Wf, Rb, pb)
     c = abi.Context(0)
     try:
         c.set_grouped_tile(cfg)
@@ -84,6 +92,11 @@ def test_block_heff_every_grouped_tile(cfg):
             plan.apply(dev(case["L"], dt), dev(case["W"], dt), dev(case["R"], dt), dev(case["psi"], dt), out)
             torch.cuda.synchronize()
             assert rel_err(out.double().cpu().numpy(), ref) < tol
+        out = torch.empty(case["psi"].shape, dtype=torch.float32, device=DEV)
+        plan.apply(dev(Lb, torch.bfloat16), dev(Wf, torch.float32), dev(Rb, torch.bfloat16), dev(pb, torch.bfloat16),
+                   out)
+        torch.cuda.synchronize()
+        assert np.all(np.abs(out.double().cpu().numpy() - ref_b) <= bound_b)
         plan.close()
     finally:
         c.close()
@@ -107,7 +120,8 @@ def test_block_heff_f32(ctx):
 @pytest.mark.parametrize("ml,mr,seed", [(20, 17, 13), (40, 52, 11), (300, 257, 12)])
 def test_block_heff_low_precision_transposed_psi(ctx, prec, ml, mr, seed):
     """FP32 / BF16 block products against the oracle on the rounded operands
-    (FP32 3e-5; BF16 2e-2, the intermediate T2 being rounded to 8 bits),
+    (FP32 3e-5; BF16 the element-wise model of the rounding of T2 to 8 bits,
+    test_gpu_parity.bf16_bound),
     eager and replayed from a captured graph; the forbidden blocks stay
     zero.  The product runs on the plan's twin over sectors padded to
     multiples of 8 (operands moved in and the product moved back), whose
@@ -120,15 +134,20 @@ def test_block_heff_low_precision_transposed_psi(ctx, prec, ml, mr, seed):
     Wf = dev(case["W"], torch.float32)
     ref = C.apply_heff(Lt.double().cpu().numpy(), Wf.double().cpu().numpy(), Rt.double().cpu().numpy(),
                        pt.double().cpu().numpy())
+    from tests.test_gpu_parity import bf16_bound
     plan = make_plan(ctx, case)
-    tol = 3e-5 if prec == "f32" else 2e-2
+    bound = None if prec == "f32" else bf16_bound(Lt.double().cpu().numpy(), Wf.double().cpu().numpy(),
+                                                  Rt.double().cpu().numpy(), pt.double().cpu().numpy())
     forbidden = case["mask"] == 0
     for use_graph in (False, True, True):
         out = torch.full(tuple(pt.shape), float("nan"), dtype=torch.float32, device=DEV)
         plan.apply(Lt, Wf, Rt, pt, out, use_graph=use_graph)
         torch.cuda.synchronize()
         o = out.double().cpu().numpy()
-        assert rel_err(o, ref) < tol, use_graph
+        if bound is None:
+            assert rel_err(o, ref) < 3e-5, use_graph
+        else:
+            assert np.all(np.abs(o - ref) <= bound), use_graph
         assert np.all(o[forbidden] == 0.0)
     plan.close()
 

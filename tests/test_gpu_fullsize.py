@@ -3,7 +3,10 @@
 the CPU FP64 oracle computes one left index at a time; and the argument
 checks at the edges of the accepted sizes.
 Tolerances as for the small shapes: FP64 1e-12, FP32 3e-5 relative to the
-largest entry of the sampled rows.
+largest entry of the sampled rows, BF16 the element-wise rounding model of
+test_gpu_parity.bf16_bound.  64 rows are sampled: the first and last, both
+sides of GEMM tile boundaries (256-row tiles of the (a, w) rows of the first
+GEMM and of the (a, s) rows of the second), and seeded random ones.
 """
 import ctypes
 
@@ -31,26 +34,50 @@ def rel_err(got, ref):
     return float(np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300))
 
 
-@pytest.mark.parametrize("m,prec", [(2048, "f64"), (2048, "f32"), (4096, "f64")])
+def sampled_rows(m, w, n=64, seed=0):
+    """n left indices: 0, m-1, both sides of GEMM-1 tile boundaries (its rows
+    are (a, w); 256-row tiles), then seeded random ones."""
+    rows = {0, m - 1}
+    for step in (256 // w, 256 // 4):        # GEMM-1 rows (a, w); GEMM-2 rows (a, s), d = 4
+        b = step
+        while len(rows) < n // 2 and b < m:
+            rows.update({b - 1, b})
+            b += 11 * step
+    rng = np.random.default_rng(seed)
+    while len(rows) < n:
+        rows.add(int(rng.integers(0, m)))
+    return np.array(sorted(rows))
+
+
+@pytest.mark.parametrize("m,prec", [(2048, "f64"), (2048, "f32"), (2048, "bf16"), (4096, "f64"), (4096, "f32")])
 def test_heff_full_size_sampled_rows(ctx, m, prec):
-    """Hubbard MPO shape (d = 4, w = 6) at the benchmark's bond dimensions."""
+    """Hubbard MPO shape (d = 4, w = 6) at the benchmark's bond dimensions, in
+    the precisions the benchmark times, on 64 sampled output rows."""
+    from tests.test_gpu_parity import bf16_bound
     d, w = 4, 6
     g = torch.Generator(device="cpu").manual_seed(900 + m)
     L = torch.randn((m, w, m), generator=g, dtype=torch.float64) / m
     W = torch.randn((w, w, d, d), generator=g, dtype=torch.float64)
     R = torch.randn((m, w, m), generator=g, dtype=torch.float64) / m
     psi = torch.randn((m, d, m), generator=g, dtype=torch.float64)
-    t = torch.float64 if prec == "f64" else torch.float32
-    out = torch.full((m, d, m), float("nan"), dtype=t, device=DEV)
+    t = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[prec]
+    tw = torch.float64 if prec == "f64" else torch.float32
+    to = torch.float64 if prec == "f64" else torch.float32
+    Lt, Wt, Rt, pt = L.to(t), W.to(tw), R.to(t), psi.to(t)
+    out = torch.full((m, d, m), float("nan"), dtype=to, device=DEV)
     ctx.set_tile_config(-1)
-    ctx.apply_heff(L.to(t).to(DEV), W.to(t).to(DEV), R.to(t).to(DEV), psi.to(t).to(DEV), out)
+    ctx.apply_heff(Lt.to(DEV), Wt.to(DEV), Rt.to(DEV), pt.to(DEV), out)
     torch.cuda.synchronize()
-    got = out.double().cpu().numpy()
+    rows = sampled_rows(m, w, 64, seed=m)
+    got = out[torch.tensor(rows, device=DEV)].double().cpu().numpy()
+    del out
     assert np.isfinite(got).all()
-    Lh, Wh, Rh, ph = (x.numpy() for x in (L, W, R, psi))
-    for a in (0, 255, 256, m // 2 + 7, m - 1):        # first/last rows, a tile boundary
-        ref = C.apply_heff(Lh[a:a + 1], Wh, Rh, ph)
-        assert rel_err(got[a:a + 1], ref) < (1e-12 if prec == "f64" else 3e-5), a
+    Lh, Wh, Rh, ph = (x.double().numpy() for x in (Lt, Wt, Rt, pt))
+    ref = C.apply_heff(Lh[rows], Wh, Rh, ph)
+    if prec == "bf16":
+        assert np.all(np.abs(got - ref) <= bf16_bound(Lh[rows], Wh, Rh, ph))
+    else:
+        assert rel_err(got, ref) < (1e-12 if prec == "f64" else 3e-5)
 
 
 def _raw_apply(ctx, dims, ptr=None):

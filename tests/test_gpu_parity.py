@@ -3,7 +3,12 @@ seeded inputs.  Tolerances:
   FP64: max |gpu - oracle| <= 1e-12 * max |oracle| (sums of <= 10^5 products
         with unit-scale Gaussian entries round to ~1e-15 relative each);
   FP32: 3e-5 relative (K <= 2e4 terms at 6e-8 unit roundoff, random signs);
-  BF16: 2e-2 relative (operands and the intermediate T2 rounded to 8 bits).
+  BF16: the oracle runs on the BF16-rounded L, R, psi (W in FP32); the GPU
+        also rounds the W-mapped intermediate T2 to BF16 before the last
+        GEMM, so out[a,s,b] = sum_k T2_k R_k (k = (v, y), K = w m terms)
+        carries sum_k d_k T2_k R_k with independent |d_k| <= 2^-9: the
+        element-wise bound is 6 sigma of that sum, 6 * 2^-9 / sqrt(3) *
+        sqrt(sum_k (T2_k R_k)^2), plus FP32 accumulation (bf16_bound).
 """
 import math
 
@@ -37,6 +42,23 @@ def dev(a, dtype=torch.float64):
 
 def rel_err(got, ref):
     return float(np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+def bf16_round(a):
+    return torch.tensor(np.asarray(a)).to(torch.bfloat16).double().numpy()
+
+
+def bf16_bound(L, W, R, psi):
+    """Element-wise error bound of the BF16 product (see the module notes) for
+    rounded operands: T2 of the oracle's order, then 6 sigma of the rounding
+    of T2 over the K = w m terms of the last contraction, plus the FP32
+    accumulation of both GEMMs."""
+    T1 = np.tensordot(L, psi, axes=([2], [0]))             # [a, w, t, y]
+    T2 = np.tensordot(T1, W, axes=([1, 2], [0, 3]))        # [a, y, v, s]
+    sig = np.sqrt(np.tensordot(T2 ** 2, R ** 2, axes=([2, 1], [1, 2])))   # [a, s, b]
+    absT2R = np.tensordot(np.abs(T2), np.abs(R), axes=([2, 1], [1, 2]))
+    K = R.shape[1] * R.shape[2]
+    return 6.0 * 2.0 ** -9 / np.sqrt(3.0) * sig + 4 * K * 2.0 ** -24 * absT2R
 
 
 SHAPES = [  # (ml, d, mr, wl, wr): tiny, boundary w=1, ragged tails, several tiles
@@ -165,7 +187,43 @@ def test_apply_heff_bf16(ctx, shape):
     out = torch.empty((ml, d, mr), dtype=torch.float32, device=DEV)
     ctx.apply_heff(Lb, Wf, Rb, pb, out)
     torch.cuda.synchronize()
-    assert rel_err(out.double().cpu().numpy(), ref) < 2e-2
+    bound = bf16_bound(Lb.double().cpu().numpy(), Wf.double().cpu().numpy(), Rb.double().cpu().numpy(),
+                       pb.double().cpu().numpy())
+    assert np.all(np.abs(out.double().cpu().numpy() - ref) <= bound)
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+@pytest.mark.parametrize("cfg", [-1, 0, 1, 2, 3, 4])
+def test_apply_heff_every_tile_config_low_precision(ctx, cfg, prec):
+    """FP32 and BF16 in every GEMM tile configuration (and the size rule, -1)
+    on a shape whose operands are 16-byte aligned with several K tiles
+    (512 x 4 x 512, w = 6: GEMM-1 K = 512, GEMM-2 K = 3072), so the
+    branch-free steady-state K loop runs; configuration 4 is a separate
+    128 x 64 wave-tile kernel in these precisions."""
+    ml, d, mr, wl, wr = 512, 4, 512, 6, 6
+    L, W, R, psi = _inputs(ml, d, mr, wl, wr, seed=17)
+    L, R, psi = L / ml, R / mr, psi
+    if prec == "f32":
+        L, W, R, psi = [np.asarray(x, dtype=np.float32).astype(np.float64) for x in (L, W, R, psi)]
+        t, tw = torch.float32, torch.float32
+    else:
+        L, R, psi = bf16_round(L), bf16_round(R), bf16_round(psi)
+        W = np.asarray(W, dtype=np.float32).astype(np.float64)
+        t, tw = torch.bfloat16, torch.float32
+    ref = C.apply_heff(L, W, R, psi)
+    out = torch.full((ml, d, mr), float("nan"), dtype=torch.float32, device=DEV)
+    ctx.set_tile_config(cfg)
+    try:
+        ctx.apply_heff(dev(L, t), dev(W, tw), dev(R, t), dev(psi, t), out)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_tile_config(-1)
+    got = out.double().cpu().numpy()
+    assert np.isfinite(got).all()
+    if prec == "f32":
+        assert rel_err(got, ref) < 3e-5
+    else:
+        assert np.all(np.abs(got - ref) <= bf16_bound(L, W, R, psi))
 
 
 def test_apply_heff_rejects_bad_arguments(ctx):
