@@ -170,6 +170,93 @@ def block_heff_bench(ctx, abi, synth, torch, np, m, dev, steps):
     return info
 
 
+def cylinder_site_bench(ctx, abi, synth, torch, np, m, dev, steps):
+    """Block-sparse H_eff of a middle site of the 4-leg Hubbard cylinder MPO
+    (w = 18, d = 4) at bond dimension m, U(1)xU(1) sectors of Gaussian
+    weight exp(-(N-N0)^2/(2 1.5^2) - (2Sz)^2/(2 1.5^2)) normalised to m on
+    both bonds (45 sectors at m = 4096, as at the middle bond of the
+    cylinder sweeps), tensors in the packed layout the sweeps use (Gaussian
+    entries).  FP64: the plan's product; FP32 / BF16: the eigensolver's
+    product (operator bound once, FP64 vector in and out, conversions
+    included).  Graph replay, events around `steps` products.  Reports the
+    rate against each precision's dense MFMA peak and the time against the
+    HBM floor of this three-kernel scheme (operands read once, output
+    written once, the T1 and T2 intermediates each written and read once)."""
+    qL, dL = synth.gaussian_sectors((28, 0), (1.5, 1.5), m, (8, 8))
+    qR, dR = synth.gaussian_sectors((29, 1), (1.5, 1.5), m, (8, 8))
+    mpo = abi.hubbard_cylinder_mpo(4, 16, t=1.0, U=4.0)
+    W = mpo[len(mpo) // 2]
+    w = int(W.shape[0])
+    wq = abi.mpo_fermion_charges(4)
+    phys = np.array(abi.HUBBARD_CHARGES)
+    plan = abi.BlockPlan(ctx, 2, 4, w, w, qL, dL, qR, dR, phys, wq, wq, layout=abi.LAYOUT_PACKED)
+    L = torch.tensor(synth.gaussian((plan.nl,), synth.SEED_LEFT) / m, device=dev)
+    R = torch.tensor(synth.gaussian((plan.nr,), synth.SEED_RIGHT) / m, device=dev)
+    psi = torch.tensor(synth.gaussian((plan.npsi,), synth.SEED_PSI), device=dev)
+    Wd = torch.tensor(W, device=dev)
+    # allowed elements of the intermediates T1[a,w,t,y] and T2[a,s,v,y]
+    key = {tuple(q): k for k, q in enumerate(np.asarray(qL).tolist())}
+    keyr = {tuple(q): k for k, q in enumerate(np.asarray(qR).tolist())}
+    nt1 = nt2 = 0
+    for i, q in enumerate(np.asarray(qL).tolist()):
+        for c in np.asarray(wq).tolist():
+            ip = key.get((q[0] - c[0], q[1] - c[1]))
+            if ip is None:
+                continue
+            qp = np.asarray(qL)[ip]
+            for t in phys.tolist():
+                jp = keyr.get((int(qp[0]) + t[0], int(qp[1]) + t[1]))
+                if jp is not None:
+                    nt1 += int(dL[i]) * int(dR[jp])
+        for sg in phys.tolist():
+            j = keyr.get((q[0] + sg[0], q[1] + sg[1]))
+            if j is None:
+                continue
+            for c in np.asarray(wq).tolist():
+                jpp = keyr.get((int(qR[j][0]) - c[0], int(qR[j][1]) - c[1]))
+                if jpp is not None:
+                    nt2 += int(dL[i]) * int(dR[jpp])
+    out = {"workload": "block_heff_hubbard_cylinder_site", "m": m, "d": 4, "w": w, "sectors_left": len(dL),
+           "sectors_right": len(dR), "tasks": plan.ntasks, "gflop": round(plan.flops / 1e9, 2),
+           "layout": "packed", "steps": steps}
+    ref = torch.empty((plan.npsi,), dtype=torch.float64, device=dev)
+    for name in ("f64", "f32", "bf16"):
+        y = torch.empty_like(ref)
+        if name == "f64":
+            run = lambda: plan.apply(L, Wd, R, psi, y, use_graph=True)
+            esz, tsz = 8, 8
+        else:
+            plan.bind(L, Wd, R, abi.F32 if name == "f32" else abi.BF16)
+            run = lambda: plan.apply_bound(psi, y, use_graph=True)
+            esz, tsz = (4, 4) if name == "f32" else (2, 4)
+        for _ in range(3):
+            run()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            run()
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        if name == "f64":
+            ref.copy_(y)
+        # operands once (the low-precision ones in their type, psi and out in
+        # FP64 around the conversions), T1 (FP32 or FP64) and T2 (the operand
+        # type) written and read once
+        byt = esz * (plan.nl + plan.nr) + 8 * 2 * plan.npsi + 2 * tsz * nt1 + 2 * esz * nt2
+        floor_ms = byt / HBM_PEAK * 1e3
+        tf = plan.flops / ms * 1e-9
+        out[name] = {"ms": round(ms, 4), "tflops": round(tf, 2),
+                     "pct_mfma_peak": round(100.0 * tf * 1e12 / PEAK[name], 2),
+                     "hbm_floor_ms": round(floor_ms, 4), "frac_of_hbm_floor": round(floor_ms / ms, 3),
+                     "max_rel_diff_vs_f64": float((y - ref).abs().max() / ref.abs().max())}
+        print("bench: cylinder site %s %.4f ms %.1f TFLOP/s (%.1f%% of peak; HBM floor %.4f ms)"
+              % (name, ms, tf, out[name]["pct_mfma_peak"], floor_ms), file=sys.stderr, flush=True)
+    plan.close()
+    return out
+
+
 def hubbard_sweep_bench(ctx, abi, synth, torch, dev, l, sched, U, tol, lanczos_tol, max_final, growth_tol,
                         mixed_min_gflop):
     """DMRG3S block sweeps on the Hubbard chain (t = 1, half filling, 2Sz = 0)
@@ -568,6 +655,8 @@ def main():
     ap.add_argument("--dense-m", type=int, default=256, help="bond limit of the dense-vs-block one-sweep comparison")
     ap.add_argument("--cylinder", type=str, default="256,512,1024,2048,4096",
                     help="bond limits of the 4x16 cylinder run ('' = skip)")
+    ap.add_argument("--site-m", type=int, default=4096,
+                    help="bond dimension of the cylinder-site block H_eff microbenchmark (0 = skip)")
     ap.add_argument("--cylinder-last", type=int, default=3,
                     help="at most this many sweeps at the last cylinder bond limit (until dE < 1e-8)")
     ap.add_argument("--cylinder-precs", type=str, default="f64,mixed_bf16",
@@ -690,6 +779,8 @@ def main():
         print("bench: block-sparse H_eff ...", file=sys.stderr, flush=True)
         line["blocks"] = block_heff_bench(ctx, abi, synth, torch, np, m, dev, max(10, steps // 2))
         print("bench: blocks %s" % line["blocks"], file=sys.stderr, flush=True)
+        if args.site_m > 0:
+            line["cylinder_site"] = cylinder_site_bench(ctx, abi, synth, torch, np, args.site_m, dev, 20)
         sched = [int(x) for x in args.sweep_sched.split(",")]
         line["sweep"] = hubbard_sweep_bench(ctx, abi, synth, torch, dev, args.sweep_l, sched, 8.0, 1e-8, 1e-10,
                                             args.sweep_max, args.growth_tol, args.mixed_min_gflop)

@@ -363,6 +363,20 @@ typedef struct {
 
 typedef struct d3s_block_plan_s* d3s_block_plan;
 
+/* Layouts of the tensors of a block plan.
+ * D3S_LAYOUT_DENSE: the dense layouts above (psi (m_l, d, m_r), L (m_l, w_l,
+ *   m_l), R (m_r, w_r, m_r)), bond states ordered by sector, zero outside the
+ *   allowed blocks.
+ * D3S_LAYOUT_PACKED (the block sweeps' layout): only the allowed blocks,
+ *   one after the other, each row-major.  psi / out: blocks (i, s) in the
+ *   order of the left sector i, then the physical state s, block (i, s)
+ *   being dim_i x dim_j with q_j = q_i + q_s (row a, column b).  L: blocks
+ *   (i, w) in the order of i, then the channel w, block (i, w) being
+ *   dim_i x dim_i' with q_i - q_i' = Delta_w (row a, column x); R likewise on
+ *   the right bond.  Missing sectors contribute no block.  Element counts:
+ *   d3s_block_plan_sizes. */
+typedef enum { D3S_LAYOUT_DENSE = 0, D3S_LAYOUT_PACKED = 1 } d3s_layout;
+
 /* Plan the block-sparse H_eff of one site (the paper uses U(1) symmetries
  * throughout Sec. 7 without describing the blocks; the block rules are the
  * charge-conservation conditions stated here).  Tensors keep the dense layouts above with bond
@@ -377,6 +391,18 @@ typedef struct d3s_block_plan_s* d3s_block_plan;
 d3s_status d3s_block_plan_create(d3s_ctx ctx, int nq, int d, int wl, int wr, const d3s_sectors* left,
                                  const d3s_sectors* right, const int* phys_q, const int* wq_left,
                                  const int* wq_right, d3s_block_plan* plan, double* flops, int* ntasks);
+/* The same plan for tensors of the given layout (d3s_layout); a plan of the
+ * packed layout serves d3s_apply_heff_blocks, d3s_block_plan_bind and
+ * d3s_apply_heff_blocks_bound (the expansion, truncation and environment
+ * entries below take dense-layout plans: D3S_EINVAL otherwise).
+ * d3s_block_plan_create is this call with D3S_LAYOUT_DENSE. */
+d3s_status d3s_block_plan_create_layout(d3s_ctx ctx, int nq, int d, int wl, int wr, const d3s_sectors* left,
+                                        const d3s_sectors* right, const int* phys_q, const int* wq_left,
+                                        const int* wq_right, int layout, d3s_block_plan* plan, double* flops,
+                                        int* ntasks);
+/* Element counts (host) of L, R and psi / out in the plan's layout.
+ * D3S_EINVAL on a null argument. */
+d3s_status d3s_block_plan_sizes(d3s_block_plan plan, long* nl, long* nr, long* npsi);
 void d3s_block_plan_destroy(d3s_ctx ctx, d3s_block_plan plan);
 
 /* Block-sparse H_eff * psi with a plan: the same result as d3s_apply_heff on
@@ -391,6 +417,27 @@ void d3s_block_plan_destroy(d3s_ctx ctx, d3s_block_plan plan);
  * therefore synchronises.  Asynchronous otherwise. */
 d3s_status d3s_apply_heff_blocks(d3s_ctx ctx, d3s_block_plan plan, d3s_prec prec, const void* L,
                                  const void* W, const void* R, const void* psi, void* out, int use_graph);
+
+/* The low-precision product of the eigensolver (Sec. 5 step 1 with FP32 /
+ * BF16 MFMA products; FP64 vectors in and out), with the operator bound once:
+ * d3s_block_plan_bind converts FP64 L, W, R (device, the plan's layout) into
+ * copies the plan owns (allocated through the context's allocator, released
+ * with the plan or by the next bind): L and R in `prec` (D3S_F32 or
+ * D3S_BF16; D3S_EINVAL otherwise) in the padded layout of
+ * d3s_apply_heff_blocks' low-precision path, W in FP32; the caller's
+ * tensors may be freed afterwards.  Synchronises on its first call on a
+ * plan (the padded layout's tables are built then).
+ * d3s_apply_heff_blocks_bound computes out = H_eff psi with the bound
+ * operator: psi (FP64, the plan's layout) is rounded to `prec`, multiplied
+ * (FP32 accumulation, T2 in `prec`), and the product is written to out
+ * (FP64, the plan's layout; zero outside the allowed blocks).  D3S_EINVAL
+ * if nothing is bound or out aliases psi.  use_graph as for
+ * d3s_apply_heff_blocks (the graph holds the multiplication; the two
+ * conversions are launched around it).  Asynchronous. */
+d3s_status d3s_block_plan_bind(d3s_ctx ctx, d3s_block_plan plan, d3s_prec prec, const double* L, const double* W,
+                               const double* R);
+d3s_status d3s_apply_heff_blocks_bound(d3s_ctx ctx, d3s_block_plan plan, const double* psi, double* out,
+                                       int use_graph);
 
 /* Block-sparse expansion of a site on the plan's bonds (Sec. 4.1-4.2, the
  * expansion term of eq. subexp-ourt): the same FP64 result as

@@ -142,6 +142,14 @@ _plan_create = _sig("d3s_block_plan_create", c_int, [c_void_p, c_int, c_int, c_i
                                                      ctypes.POINTER(d3s_sectors), ctypes.POINTER(d3s_sectors),
                                                      c_int_p, c_int_p, c_int_p, ctypes.POINTER(c_void_p),
                                                      c_double_p, c_int_p])
+_plan_create_layout = _sig("d3s_block_plan_create_layout", c_int,
+                           [c_void_p, c_int, c_int, c_int, c_int, ctypes.POINTER(d3s_sectors),
+                            ctypes.POINTER(d3s_sectors), c_int_p, c_int_p, c_int_p, c_int,
+                            ctypes.POINTER(c_void_p), c_double_p, c_int_p])
+_plan_sizes = _sig("d3s_block_plan_sizes", c_int, [c_void_p, ctypes.POINTER(c_long), ctypes.POINTER(c_long),
+                                                   ctypes.POINTER(c_long)])
+_plan_bind = _sig("d3s_block_plan_bind", c_int, [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_void_p])
+_apply_bound = _sig("d3s_apply_heff_blocks_bound", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int])
 _plan_destroy = _sig("d3s_block_plan_destroy", None, [c_void_p, c_void_p])
 _apply_blocks = _sig("d3s_apply_heff_blocks", c_int, [c_void_p, c_void_p, c_int] + [c_void_p] * 5 + [c_int])
 _expand_blocks = _sig("d3s_expand_subspace_blocks", c_int,
@@ -730,10 +738,16 @@ def _ints(a):
     return arr, arr.ctypes.data_as(c_int_p)
 
 
-class BlockPlan:
-    """Task tables of one block-sparse H_eff (d3s_block_plan)."""
+LAYOUT_DENSE, LAYOUT_PACKED = 0, 1
 
-    def __init__(self, ctx, nq, d, wl, wr, left_q, left_dim, right_q, right_dim, phys_q, wq_left, wq_right):
+
+class BlockPlan:
+    """Task tables of one block-sparse H_eff (d3s_block_plan_create_layout);
+    `layout` LAYOUT_DENSE (tensors in the dense layouts) or LAYOUT_PACKED (only
+    the allowed blocks; the sizes are self.nl, self.nr, self.npsi)."""
+
+    def __init__(self, ctx, nq, d, wl, wr, left_q, left_dim, right_q, right_dim, phys_q, wq_left, wq_right,
+                 layout=LAYOUT_DENSE):
         self.ctx = ctx
         self.h = None
         self._keep = []
@@ -754,12 +768,36 @@ class BlockPlan:
         fl = c_double()
         nt = c_int()
         ctx._sync_stream()
-        ctx._check(_plan_create(ctx.h, nq, d, wl, wr, ctypes.byref(self.left), ctypes.byref(self.right), pp, lp,
-                                rp, ctypes.byref(h), ctypes.byref(fl), ctypes.byref(nt)))
+        ctx._check(_plan_create_layout(ctx.h, nq, d, wl, wr, ctypes.byref(self.left), ctypes.byref(self.right), pp,
+                                       lp, rp, int(layout), ctypes.byref(h), ctypes.byref(fl), ctypes.byref(nt)))
         self.h = h
+        self.layout = int(layout)
         self.flops = fl.value
         self.ntasks = nt.value
         ctx._plans.add(self)
+        nl, nr, npsi = c_long(), c_long(), c_long()
+        ctx._check(_plan_sizes(h, ctypes.byref(nl), ctypes.byref(nr), ctypes.byref(npsi)))
+        self.nl, self.nr, self.npsi = nl.value, nr.value, npsi.value
+
+    def bind(self, L, W, R, prec):
+        """d3s_block_plan_bind: FP64 L, W, R (the plan's layout) converted for
+        FP32 / BF16 products held by the plan."""
+        ctx = self.ctx
+        ctx._sync_stream()
+        f = torch.float64
+        _need(L, self.nl, f, "L")
+        _need(W, self.wl * self.wr * self.d * self.d, f, "W")
+        _need(R, self.nr, f, "R")
+        return ctx._check(_plan_bind(ctx.h, self.h, int(prec), _ptr(L), _ptr(W), _ptr(R)))
+
+    def apply_bound(self, psi, out, use_graph=False):
+        """d3s_apply_heff_blocks_bound: out = H psi (FP64, the plan's layout)
+        with the bound operator."""
+        ctx = self.ctx
+        ctx._sync_stream()
+        _need(psi, self.npsi, torch.float64, "psi")
+        _need(out, self.npsi, torch.float64, "out")
+        return ctx._check(_apply_bound(ctx.h, self.h, _ptr(psi), _ptr(out), 1 if use_graph else 0))
 
     def apply(self, L, W, R, psi, out, use_graph=False):
         ctx = self.ctx
@@ -767,11 +805,11 @@ class BlockPlan:
         ml, d, mr, wl, wr = self.ml, self.d, self.mr, self.wl, self.wr
         prec = _PREC[psi.dtype]
         te, tw, to = _ELT[prec]
-        _need(L, ml * wl * ml, te, "L")
+        _need(L, self.nl, te, "L")
         _need(W, wl * wr * d * d, tw, "W")
-        _need(R, mr * wr * mr, te, "R")
-        _need(psi, ml * d * mr, te, "psi")
-        _need(out, ml * d * mr, to, "out")
+        _need(R, self.nr, te, "R")
+        _need(psi, self.npsi, te, "psi")
+        _need(out, self.npsi, to, "out")
         return ctx._check(_apply_blocks(ctx.h, self.h, prec, _ptr(L), _ptr(W), _ptr(R), _ptr(psi), _ptr(out),
                                         1 if use_graph else 0))
 

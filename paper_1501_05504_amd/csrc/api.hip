@@ -475,13 +475,15 @@ static void check_sectors(const d3s_sectors* s, int nq, const char* name) {
   D3S_REQUIRE((int)tmp.index.size() == s->nsec, std::string(name) + ": repeated charge");
 }
 
-d3s_status d3s_block_plan_create(d3s_ctx ctx, int nq, int d, int wl, int wr, const d3s_sectors* left,
-                                 const d3s_sectors* right, const int* phys_q, const int* wq_left,
-                                 const int* wq_right, d3s_block_plan* plan, double* flops, int* ntasks) {
+d3s_status d3s_block_plan_create_layout(d3s_ctx ctx, int nq, int d, int wl, int wr, const d3s_sectors* left,
+                                        const d3s_sectors* right, const int* phys_q, const int* wq_left,
+                                        const int* wq_right, int layout, d3s_block_plan* plan, double* flops,
+                                        int* ntasks) {
   return guarded(ctx, [&] {
     D3S_REQUIRE(plan, "null plan pointer");
     *plan = nullptr;
     D3S_REQUIRE(nq == 1 || nq == 2, "nq must be 1 or 2");
+    D3S_REQUIRE(layout == D3S_LAYOUT_DENSE || layout == D3S_LAYOUT_PACKED, "layout must be dense or packed");
     D3S_REQUIRE(phys_q && wq_left && wq_right, "null charge array");
     check_sectors(left, nq, "left");
     check_sectors(right, nq, "right");
@@ -490,7 +492,9 @@ d3s_status d3s_block_plan_create(d3s_ctx ctx, int nq, int d, int wl, int wr, con
     p->right = d3s::Sectors(nq, right->nsec, right->q, right->dim);
     try {
       check_dims(p->left.total, d, p->right.total, wl, wr);
-      d3s::build_block_heff(&ctx->c, p->h, p->left, p->right, d, wl, wr, phys_q, wq_left, wq_right);
+      const bool packed = (layout == D3S_LAYOUT_PACKED);
+      d3s::build_block_heff(&ctx->c, p->h, p->left, p->right, d, wl, wr, phys_q, wq_left, wq_right, packed, true,
+                            packed);
     } catch (...) {
       d3s::release_block_heff(p->h);
       delete p;
@@ -501,6 +505,21 @@ d3s_status d3s_block_plan_create(d3s_ctx ctx, int nq, int d, int wl, int wr, con
     *plan = p;
     return D3S_OK;
   });
+}
+
+d3s_status d3s_block_plan_create(d3s_ctx ctx, int nq, int d, int wl, int wr, const d3s_sectors* left,
+                                 const d3s_sectors* right, const int* phys_q, const int* wq_left,
+                                 const int* wq_right, d3s_block_plan* plan, double* flops, int* ntasks) {
+  return d3s_block_plan_create_layout(ctx, nq, d, wl, wr, left, right, phys_q, wq_left, wq_right, D3S_LAYOUT_DENSE,
+                                      plan, flops, ntasks);
+}
+
+d3s_status d3s_block_plan_sizes(d3s_block_plan plan, long* nl, long* nr, long* npsi) {
+  if (!plan || !nl || !nr || !npsi) return D3S_EINVAL;
+  *nl = d3s::plan_nl(plan->h);
+  *nr = d3s::plan_nr(plan->h);
+  *npsi = plan->h.packed ? plan->h.npacked : (long)plan->h.ml * plan->h.d * plan->h.mr;
+  return D3S_OK;
 }
 
 void d3s_block_plan_destroy(d3s_ctx ctx, d3s_block_plan plan) {
@@ -518,6 +537,28 @@ d3s_status d3s_apply_heff_blocks(d3s_ctx ctx, d3s_block_plan plan, d3s_prec prec
     D3S_REQUIRE(L && W && R && psi && out, "null tensor pointer");
     D3S_REQUIRE(out != psi && out != L && out != R, "out must not alias an input");
     d3s::op_apply_heff_blocks(&ctx->c, plan->h, prec, L, W, R, psi, out, use_graph != 0);
+    return D3S_OK;
+  });
+}
+
+d3s_status d3s_block_plan_bind(d3s_ctx ctx, d3s_block_plan plan, d3s_prec prec, const double* L, const double* W,
+                               const double* R) {
+  return guarded(ctx, [&] {
+    D3S_REQUIRE(plan, "null plan");
+    D3S_REQUIRE(prec == D3S_F32 || prec == D3S_BF16, "bind: prec must be D3S_F32 or D3S_BF16");
+    D3S_REQUIRE(L && W && R, "null tensor pointer");
+    d3s::op_block_bind(&ctx->c, plan->h, prec, L, W, R);
+    return D3S_OK;
+  });
+}
+
+d3s_status d3s_apply_heff_blocks_bound(d3s_ctx ctx, d3s_block_plan plan, const double* psi, double* out,
+                                       int use_graph) {
+  return guarded(ctx, [&] {
+    D3S_REQUIRE(plan, "null plan");
+    D3S_REQUIRE(psi && out, "null tensor pointer");
+    D3S_REQUIRE(out != psi, "out must not alias psi");
+    d3s::op_apply_heff_blocks_bound(&ctx->c, plan->h, psi, out, use_graph != 0);
     return D3S_OK;
   });
 }
@@ -566,6 +607,7 @@ d3s_status d3s_expand_subspace_blocks(d3s_ctx ctx, d3s_block_plan plan, d3s_dir 
                                       const double* W, const double* psi, double alpha, double* Mt) {
   return guarded(ctx, [&] {
     D3S_REQUIRE(plan, "null plan");
+    D3S_REQUIRE(!plan->h.packed, "this operation needs a plan of the dense layout");
     D3S_REQUIRE(dir == D3S_L2R || dir == D3S_R2L, "dir must be D3S_L2R or D3S_R2L");
     D3S_REQUIRE(env && W && psi && Mt, "null tensor pointer");
     D3S_REQUIRE(Mt != psi && Mt != env, "Mt must not alias an input");
@@ -581,6 +623,7 @@ d3s_status d3s_truncate_blocks(d3s_ctx ctx, d3s_block_plan plan, d3s_dir dir, co
                                int* new_dim, int* k_out, double* discarded) {
   return guarded(ctx, [&] {
     D3S_REQUIRE(plan, "null plan");
+    D3S_REQUIRE(!plan->h.packed, "this operation needs a plan of the dense layout");
     D3S_REQUIRE(dir == D3S_L2R || dir == D3S_R2L, "dir must be D3S_L2R or D3S_R2L");
     D3S_REQUIRE(Mt && psi && nbr_in && site_out && nbr_out, "null tensor pointer");
     D3S_REQUIRE(new_nsec && new_q && new_dim && k_out && discarded, "null output pointer");
@@ -612,6 +655,7 @@ d3s_status d3s_update_env_blocks(d3s_ctx ctx, d3s_block_plan plan, d3s_dir dir, 
                                  const double* W, const double* site, double* env_out) {
   return guarded(ctx, [&] {
     D3S_REQUIRE(plan, "null plan");
+    D3S_REQUIRE(!plan->h.packed, "this operation needs a plan of the dense layout");
     D3S_REQUIRE(dir == D3S_L2R || dir == D3S_R2L, "dir must be D3S_L2R or D3S_R2L");
     D3S_REQUIRE(env_in && W && site && env_out, "null tensor pointer");
     D3S_REQUIRE(env_out != env_in && env_out != site, "env_out must not alias an input");

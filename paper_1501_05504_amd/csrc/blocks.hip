@@ -97,17 +97,50 @@ void grouped_finalize(Ctx* c, GroupedPlan& g) {
   g.ntasks = (int)g.tasks.size();
   grouped_release(g);
   if (g.ntasks == 0) return;
+  // low-precision launches load whole 16-byte chunks: every offset and
+  // leading dimension, and the extent that is cut into chunks (K of a
+  // K-contiguous operand, else its row or column count), a multiple of the
+  // chunk's element count
+  auto chunked = [&](long ve) {
+    for (const GTask& t : g.tasks)
+      for (int q = t.seg0; q < t.seg0 + t.nseg; ++q) {
+        const GSeg& sg = g.segs[q];
+        if (sg.a_off % ve || sg.lda % ve || sg.b_off % ve || sg.ldb % ve) return false;
+        if ((g.a_kc ? sg.K : t.M) % ve || (g.b_kc ? sg.K : t.N) % ve) return false;
+      }
+    return true;
+  };
+  g.chunked32 = chunked(4);
+  g.chunked16 = chunked(8);
+  // the grouped kernel addresses a tile's chunks by 32-bit byte offsets
+  for (const GSeg& sg : g.segs)
+    if (std::max(sg.lda, sg.ldb) > ((1L << 31) - (1L << 20)) / (256 * 8))
+      throw Error{D3S_EINVAL, "grouped GEMM: leading dimension above 2^20 elements"};
+  // one allocation: tasks, segments and the tile -> task table, the latter
+  // sized for the configuration with the most tiles (the autotuner may
+  // switch configurations)
+  g.tile_cap = 1;
+  for (int cfg = 0; cfg <= 5; ++cfg) {
+    int bm, bn;
+    grouped_tile_dims(cfg, bm, bn);
+    long n = 0;
+    for (const GTask& t : g.tasks) n += (long)((t.M + bm - 1) / bm) * ((t.N + bn - 1) / bn);
+    g.tile_cap = std::max(g.tile_cap, n);
+  }
+  if (g.tile_cap > (1L << 30)) throw Error{D3S_EINVAL, "grouped GEMM: too many tiles"};
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t tb = up(sizeof(GTask) * g.tasks.size()), sb = up(sizeof(GSeg) * std::max<size_t>(1, g.segs.size()));
+  const size_t bytes = tb + sb + sizeof(int) * (size_t)g.tile_cap;
+  char* base;
   if (g.table_slot >= 0) {
-    // a short-lived plan: both tables in one workspace slot
-    const size_t tb = (sizeof(GTask) * g.tasks.size() + 255) & ~(size_t)255;
-    char* base = (char*)ws_get(c, g.table_slot, tb + sizeof(GSeg) * std::max<size_t>(1, g.segs.size()));
-    g.d_tasks = (GTask*)base;
-    g.d_segs = (GSeg*)(base + tb);
+    base = (char*)ws_get(c, g.table_slot, bytes);      // a short-lived plan: not owned
   } else {
     g.owner = c;
-    g.d_tasks = (GTask*)dev_alloc(c, sizeof(GTask) * g.tasks.size());
-    g.d_segs = (GSeg*)dev_alloc(c, sizeof(GSeg) * std::max<size_t>(1, g.segs.size()));
+    base = (char*)dev_alloc(c, bytes);
   }
+  g.d_tasks = (GTask*)base;
+  g.d_segs = (GSeg*)(base + tb);
+  g.d_tile = (int*)(base + tb + sb);
   if (!g.segs.empty())
     D3S_HIP(hipMemcpyAsync(g.d_segs, g.segs.data(), sizeof(GSeg) * g.segs.size(), hipMemcpyHostToDevice,
                            c->stream));
@@ -124,18 +157,26 @@ void grouped_retile(Ctx* c, GroupedPlan& g) {
   }
   g.total_tiles = acc;
   if (g.ntasks == 0 || !g.d_tasks) return;
+  if (acc > g.tile_cap) throw Error{D3S_EDEVICE, "grouped GEMM: tile table too small"};
+  std::vector<int> tt((size_t)acc);
+  for (int k = 0; k < g.ntasks; ++k) {
+    const GTask& t = g.tasks[k];
+    const int n = ((t.M + bm - 1) / bm) * ((t.N + bn - 1) / bn);
+    for (int q = 0; q < n; ++q) tt[(size_t)t.tile0 + q] = k;
+  }
   D3S_HIP(hipMemcpyAsync(g.d_tasks, g.tasks.data(), sizeof(GTask) * g.tasks.size(), hipMemcpyHostToDevice,
                          c->stream));
+  if (acc > 0)
+    D3S_HIP(hipMemcpyAsync(g.d_tile, tt.data(), sizeof(int) * (size_t)acc, hipMemcpyHostToDevice, c->stream));
   D3S_HIP(hipStreamSynchronize(c->stream));
 }
 
 void grouped_release(GroupedPlan& g) {
-  if (g.table_slot < 0) {
-    dev_free(g.owner, g.d_tasks);
-    dev_free(g.owner, g.d_segs);
-  }
+  if (g.table_slot < 0) dev_free(g.owner, g.d_tasks);
   g.d_tasks = nullptr;
   g.d_segs = nullptr;
+  g.d_tile = nullptr;
+  g.tile_cap = 0;
 }
 
 namespace {
@@ -601,6 +642,7 @@ void release_block_heff(BlockHeff& h) {
   if (h.lp) {
     release_block_heff(h.lp->h);
     for (RlTile* p : {h.lp->d_L, h.lp->d_R, h.lp->d_X, h.lp->d_Y}) dev_free(h.owner, p);
+    for (void* p : {h.lp->bL, h.lp->bR, h.lp->bW}) dev_free(h.owner, p);
     delete h.lp;
     h.lp = nullptr;
   }
@@ -955,6 +997,47 @@ void op_apply_heff_blocks(Ctx* c, BlockHeff& h, d3s_prec p, const void* L, const
   D3S_HIP(hipGraphLaunch((hipGraphExec_t)h.graph_exec, cs));
   D3S_HIP(hipEventRecord((hipEvent_t)h.ev_out, cs));
   D3S_HIP(hipStreamWaitEvent(c->stream, (hipEvent_t)h.ev_out, 0));
+}
+
+void lowp_product(Ctx* c, BlockHeff& h, LowpTwin& tw, d3s_prec p, const void* Lc, const void* Wc, const void* Rc,
+                  const double* x, double* y, void* xin, float* yout, bool use_graph) {
+  relayout_tiles(c, RL_F64, p == D3S_F32 ? RL_F32 : RL_BF16, x, xin, tw.d_X, tw.nX);
+  op_apply_heff_blocks(c, tw.h, p, Lc, Wc, Rc, xin, yout, use_graph);
+  // the dense layout's forbidden entries are not written by the relayout
+  if (!h.packed) zero_bytes(c, y, sizeof(double) * (size_t)h.ml * h.d * h.mr);
+  relayout_tiles(c, RL_F32, RL_F64, yout, y, tw.d_Y, tw.nY);
+}
+
+void op_block_bind(Ctx* c, BlockHeff& h, d3s_prec p, const double* L, const double* W, const double* R) {
+  if (p != D3S_F32 && p != D3S_BF16) throw Error{D3S_EINVAL, "bind: prec must be D3S_F32 or D3S_BF16"};
+  if (h.padded) throw Error{D3S_EINVAL, "blocks: a padded plan has no twin"};
+  LowpTwin& tw = ensure_lowp(c, h, p);
+  dev_free(h.owner, tw.bL);
+  dev_free(h.owner, tw.bR);
+  dev_free(h.owner, tw.bW);
+  tw.bL = tw.bR = tw.bW = nullptr;
+  tw.bprec = D3S_F64;
+  const size_t esz = (p == D3S_F32) ? 4 : 2;
+  const long nw = (long)h.wl * h.wr * h.d * h.d;
+  tw.bL = dev_alloc(c, esz * (size_t)std::max(1L, plan_nl(tw.h)));
+  tw.bR = dev_alloc(c, esz * (size_t)std::max(1L, plan_nr(tw.h)));
+  tw.bW = dev_alloc(c, sizeof(float) * (size_t)nw);
+  // the relayout tiles cover every padded block, padding included (zeros)
+  const int kind = (p == D3S_F32) ? RL_F32 : RL_BF16;
+  relayout_tiles(c, RL_F64, kind, L, tw.bL, tw.d_L, tw.nL);
+  relayout_tiles(c, RL_F64, kind, R, tw.bR, tw.d_R, tw.nR);
+  cast_f64_to_f32(c, W, (float*)tw.bW, nw);
+  tw.bprec = p;
+}
+
+void op_apply_heff_blocks_bound(Ctx* c, BlockHeff& h, const double* psi, double* out, bool use_graph) {
+  if (!h.lp || h.lp->bprec == D3S_F64) throw Error{D3S_EINVAL, "no operator bound to the plan"};
+  LowpTwin& tw = *h.lp;
+  const d3s_prec p = tw.bprec;
+  const size_t esz = (p == D3S_F32) ? 4 : 2;
+  void* xin = ws_get(c, WS_LP_X, esz * (size_t)tw.h.npacked);
+  float* yout = (float*)ws_get(c, WS_LP_Y, 4 * (size_t)tw.h.npacked);
+  lowp_product(c, h, tw, p, tw.bL, tw.bW, tw.bR, psi, out, xin, yout, use_graph);
 }
 
 }  // namespace d3s

@@ -107,9 +107,13 @@ struct GSeg { int K; long a_off, lda, b_off, ldb; };
 struct GroupedPlan {
   std::vector<GTask> tasks;
   std::vector<GSeg> segs;
-  GTask* d_tasks = nullptr;     // device copies (owned by the plan)
+  GTask* d_tasks = nullptr;     // device copies (owned by the plan; one allocation from d_tasks on)
   GSeg* d_segs = nullptr;
+  int* d_tile = nullptr;        // task of every tile of the current configuration
   int ntasks = 0, total_tiles = 0;
+  long tile_cap = 0;            // entries of d_tile (the most tiles of any configuration)
+  bool chunked32 = false;       // every block made of whole 16-byte chunks with 4-byte elements
+  bool chunked16 = false;       // ... with 2-byte elements (FP32 / BF16 launches require it)
   bool a_kc = true, b_kc = true;
   int cfg = 1;                  // tile configuration (grouped_tile_dims)
   double flops = 0.0;
@@ -415,6 +419,10 @@ struct LowpTwin {
   BlockHeff h;
   RlTile *d_L = nullptr, *d_R = nullptr, *d_X = nullptr, *d_Y = nullptr;
   int nL = 0, nR = 0, nX = 0, nY = 0;
+  // an operator bound by op_block_bind: L, R in the twin's layouts and the
+  // product's element type, W in FP32 (owned, from the plan owner's allocator)
+  void *bL = nullptr, *bR = nullptr, *bW = nullptr;
+  d3s_prec bprec = D3S_F64;                 // D3S_F64: nothing bound
 };
 // built on the first FP32 / BF16 product; its grouped launches are tuned
 // (autotuning on) in that product's precision
@@ -431,6 +439,16 @@ inline long plan_nr(const BlockHeff& h) { return h.penv ? h.epr.total : (long)h.
 void pack_psi(Ctx* c, const BlockHeff& h, const double* dense, double* packed);
 void unpack_psi(Ctx* c, const BlockHeff& h, const double* packed, double* dense, long rowlen, bool clear);
 void release_block_heff(BlockHeff& h);
+// y = H x (FP64 vectors in the plan's layout) with an FP32 / BF16 product on
+// the twin: x moved into the twin's layout and precision (xin), the product
+// into yout (FP32), moved back into y (whose forbidden entries are cleared
+// for a dense layout)
+void lowp_product(Ctx* c, BlockHeff& h, LowpTwin& tw, d3s_prec p, const void* Lc, const void* Wc, const void* Rc,
+                  const double* x, double* y, void* xin, float* yout, bool use_graph);
+// bind an operator (FP64 L, W, R in the plan's layouts) for FP32 / BF16
+// products, and apply it
+void op_block_bind(Ctx* c, BlockHeff& h, d3s_prec p, const double* L, const double* W, const double* R);
+void op_apply_heff_blocks_bound(Ctx* c, BlockHeff& h, const double* psi, double* out, bool use_graph);
 void op_apply_heff_blocks(Ctx* c, BlockHeff& h, d3s_prec p, const void* L, const void* W, const void* R,
                           const void* psi, void* out, bool use_graph);
 // Block-sparse expansion (FP64): writes the allowed blocks of Mt = [psi | P]

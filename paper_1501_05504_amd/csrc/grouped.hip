@@ -14,9 +14,18 @@
 // each with its own L2.  Workgroup ids are therefore remapped so that runs of
 // kChunk consecutive tiles (mostly tiles of one task, which share operand
 // blocks) execute on the same XCD, the runs dealt to the XCDs round-robin for
-// balance.  Tile t then belongs to the task with the largest tile0 <= t
-// (binary search over the prefix sums).  Tasks are sorted largest-first by
-// the host so that long tiles start early.
+// balance.  The task of a tile is read from a per-tile table (one load, where
+// a search over the tasks' tile prefix sums would chain a dozen).  Tasks are
+// sorted largest-first by the host so that long tiles start early.
+//
+// Block products are small (sector dimensions of tens to hundreds), so a
+// tile's K loop is short and each K step carries little MFMA work.  With
+// the small tiles (64x64 and 32x32, whose registers allow it) the operand
+// loads of a K step are issued three steps ahead (two register buffers
+// behind the two LDS stages), so that their latency overlaps two steps of
+// MFMAs instead of one; the large tiles keep one register buffer.
+#include <type_traits>
+
 #include "mfma_tile.h"
 
 namespace d3s {
@@ -30,6 +39,7 @@ constexpr int kXcd = 8;
 struct GParams {
   const GTask* tasks;
   const GSeg* segs;
+  const int* tile_task;
   int ntasks;
   int total;                // tiles
   const void* A;
@@ -54,13 +64,7 @@ void grouped_kernel(GParams p) {
   const int xcd = (int)blockIdx.x % kXcd, slot = (int)blockIdx.x / kXcd;
   const int bid = ((slot / kChunk) * kXcd + xcd) * kChunk + slot % kChunk;
   if (bid >= p.total) return;
-  int lo = 0, hi = p.ntasks - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (p.tasks[mid].tile0 <= bid) lo = mid;
-    else hi = mid - 1;
-  }
-  const GTask t = p.tasks[lo];
+  const GTask t = p.tasks[p.tile_task[bid]];
   const int local = bid - t.tile0;
   const int nTn = (t.N + BN - 1) / BN;
   const int m0 = (local / nTn) * BM, n0 = (local % nTn) * BN;
@@ -80,35 +84,40 @@ void grouped_kernel(GParams p) {
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = AV{0, 0, 0, 0};
 
-  Stager<S, BM, NT, AKC> ga;
-  Stager<S, BN, NT, BKC> gb;
+  // register buffers: two where the registers allow it (FP32 / BF16 tiles
+  // up to 64x64, FP64 up to 32x32), else one
+  constexpr int NB = (BM * BN <= 32 * 32 || (BM * BN <= 64 * 64 && sizeof(S) < 8)) ? 2 : 1;
+  Stager<S, BM, NT, AKC> ga[NB];
+  Stager<S, BN, NT, BKC> gb[NB];
   const int send = t.seg0 + t.nseg;
   int ntiles = 0;
   for (int q = t.seg0; q < send; ++q) {
     const int K = p.segs[q].K;
     if (K > 0) ntiles += (K + BK - 1) / BK;
   }
-  int fs = t.seg0, fk = 0;
+  // the K step to load next: segment fs (copied into cs), offset ck
+  int fs = t.seg0, ck = 0;
   while (fs < send && p.segs[fs].K <= 0) ++fs;
-  auto fetch_next = [&]() {
-    const GSeg sg = p.segs[fs];
-    const S* As = Ab + sg.a_off;
-    const S* Bs = Bb + sg.b_off;
-    const int k0 = fk * BK;
-    if (Stager<S, BM, NT, AKC>::full_ok(As, sg.lda, m0, t.M, k0, sg.K) &&
-        Stager<S, BN, NT, BKC>::full_ok(Bs, sg.ldb, n0, t.N, k0, sg.K)) {
-      ga.load_full(As, sg.lda, m0, k0);
-      gb.load_full(Bs, sg.ldb, n0, k0);
+  GSeg cs = (fs < send) ? p.segs[fs] : GSeg{0, 0, 0, 0, 0};
+  // operand tiles of the next K step (in list order) into register buffer u.
+  // Every fetch issues its loads, also past the end of the list (it then
+  // reloads the last step, whose data is never used): with the same loads
+  // on every path the compiler's wait counts stay exact, and the loads of
+  // later steps stay in flight while earlier ones are consumed.
+  auto fetch_next = [&](auto ub) {
+    constexpr int u = decltype(ub)::value;
+    ga[u].load_buf(Ab + cs.a_off, cs.lda, m0, t.M, ck, cs.K);
+    gb[u].load_buf(Bb + cs.b_off, cs.ldb, n0, t.N, ck, cs.K);
+    if (ck + BK < cs.K) {
+      ck += BK;
     } else {
-      ga.load(As, sg.lda, m0, t.M, k0, sg.K);
-      gb.load(Bs, sg.ldb, n0, t.N, k0, sg.K);
-    }
-    if ((fk + 1) * BK >= sg.K) {
-      ++fs;
-      fk = 0;
-      while (fs < send && p.segs[fs].K <= 0) ++fs;
-    } else {
-      ++fk;
+      int f = fs + 1;
+      while (f < send && p.segs[f].K <= 0) ++f;
+      if (f < send) {
+        fs = f;
+        cs = p.segs[f];
+        ck = 0;
+      }
     }
   };
   typedef Grp<S> G;
@@ -130,14 +139,27 @@ void grouped_kernel(GParams p) {
 #pragma unroll
         for (int j = 0; j < TN; ++j) G::mma(acc[i][j], ra[g][i], rb[g][j], st);
   };
+  // K step u lives in LDS stage u & 1 and, before that, in register buffer
+  // u % NB.  Prologue: steps 0 and 1 into both stages (and, with two
+  // buffers, step 2 into buffer 0).
+  using B0 = std::integral_constant<int, 0>;
+  using B1 = std::integral_constant<int, 1>;
   if (ntiles > 0) {
-    fetch_next();
-    ga.store(sA[0]);
-    gb.store(sB[0]);
-    if (ntiles > 1) {
-      fetch_next();
-      ga.store(sA[1]);
-      gb.store(sB[1]);
+    if constexpr (NB == 2) {
+      fetch_next(B0());
+      fetch_next(B1());
+      ga[0].store(sA[0]);
+      gb[0].store(sB[0]);
+      ga[1].store(sA[1]);
+      gb[1].store(sB[1]);
+      fetch_next(B0());
+    } else {
+      fetch_next(B0());
+      ga[0].store(sA[0]);
+      gb[0].store(sB[0]);
+      fetch_next(B0());
+      ga[0].store(sA[1]);
+      gb[0].store(sB[1]);
     }
   }
   __syncthreads();
@@ -145,17 +167,24 @@ void grouped_kernel(GParams p) {
 #pragma unroll
     for (int g = 0; g < NG - 1; ++g) read_group(0, g);
   }
-  // As in the plain GEMM: the last register group of tile kt is read at the
-  // top of iteration kt, the groups of tile kt+1 after the barrier during the
-  // MFMAs of the next group of tile kt, and the staged tile kt+2 is stored
-  // with the last group.  After the fetch each iteration is branch-free:
-  // past the end of the list the reads and the store move data that is
-  // never used (the store's stage holds a tile that has been read in full).
+  // As in the plain GEMM: the last register group of step kt is read at the
+  // top of iteration kt, the groups of step kt+1 after the barrier during the
+  // MFMAs of the next group of step kt, and step kt+2 is stored with the
+  // last group; the loads of step kt+1+NB go out at the top (so step kt+2
+  // was loaded during this iteration with one buffer, the previous one with
+  // two).  Each iteration is branch-free: past the end of the list the
+  // loads, reads and the store move data that is never used (the store's
+  // stage holds a step that has been read in full).  The loop is unrolled
+  // by two so that stage and buffer indices are constants.
   constexpr int QM = G::STEPS * TM * TN;
   constexpr int NW = 2 * (Stager<S, BM, NT, AKC>::LPT + Stager<S, BN, NT, BKC>::LPT);
-  for (int kt = 0; kt < ntiles; ++kt) {
-    const int cur = kt & 1, nxt = cur ^ 1;
-    if (kt + 2 < ntiles) fetch_next();
+  // (with one buffer the stage indices are run-time values and the loop is
+  // not unrolled: fewer live registers for the large tiles)
+  auto step = [&](auto parity, int kt) {
+    constexpr int pc = decltype(parity)::value;
+    const int cur = (NB == 2) ? pc : (kt & 1), nxt = cur ^ 1;
+    constexpr int bload = (NB == 2) ? (pc ^ 1) : 0, bstore = (NB == 2) ? pc : 0;
+    fetch_next(std::integral_constant<int, bload>());
     read_group(cur, NG - 1);
     mma_group(0);
     interleave<QM, TM + TN, 0, 0>();
@@ -164,13 +193,22 @@ void grouped_kernel(GParams p) {
     for (int g = 1; g < NG; ++g) {
       read_group(nxt, g - 1);
       if (g == NG - 1) {
-        ga.store(sA[cur]);
-        gb.store(sB[cur]);
+        ga[bstore].store(sA[cur]);
+        gb[bstore].store(sB[cur]);
       }
       mma_group(g);
       if (g == NG - 1) interleave<QM, TM + TN, NW, 0>();
       else interleave<QM, TM + TN, 0, 0>();
     }
+  };
+  if constexpr (NB == 2) {
+    for (int kt = 0; kt < ntiles; kt += 2) {
+      step(B0(), kt);
+      if (kt + 1 >= ntiles) break;
+      step(B1(), kt + 1);
+    }
+  } else {
+    for (int kt = 0; kt < ntiles; ++kt) step(B0(), kt);
   }
 
   const AT alpha = (AT)p.alpha, beta = (AT)p.beta;
@@ -195,7 +233,7 @@ void grouped_kernel(GParams p) {
 template <typename S, int BM, int BN, int WM, int WN>
 void launch_grouped(Ctx* c, const GroupedPlan& g, const void* A, const void* B, void* C, double alpha,
                     double beta) {
-  GParams p{g.d_tasks, g.d_segs, g.ntasks, g.total_tiles, A, B, C, alpha, beta};
+  GParams p{g.d_tasks, g.d_segs, g.d_tile, g.ntasks, g.total_tiles, A, B, C, alpha, beta};
   const long span = (long)kXcd * kChunk;
   dim3 grid((unsigned)((g.total_tiles + span - 1) / span * span)), block((BM / WM) * (BN / WN) * 64);
   if (g.a_kc && g.b_kc)
@@ -228,6 +266,11 @@ void grouped_tile_dims(int cfg, int& bm, int& bn) {
 void grouped_gemm(Ctx* c, d3s_prec prec, const GroupedPlan& g, const void* A, const void* B, void* C,
                   double alpha, double beta) {
   if (g.ntasks <= 0 || g.total_tiles <= 0) return;
+  if (prec != D3S_F64) {
+    const bool ok = (prec == D3S_F32 ? g.chunked32 : g.chunked16) &&
+                    (reinterpret_cast<uintptr_t>(A) & 15) == 0 && (reinterpret_cast<uintptr_t>(B) & 15) == 0;
+    if (!ok) throw Error{D3S_EINVAL, "grouped GEMM: FP32 / BF16 blocks must be whole 16-byte chunks"};
+  }
   auto run = [&](auto tag) {
     typedef decltype(tag) S;
     switch (g.cfg) {

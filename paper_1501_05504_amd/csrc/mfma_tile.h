@@ -155,6 +155,47 @@ struct Stager {
     }
   }
 
+  // Loads of the grouped kernel, through a buffer resource whose base is the
+  // tile's first element (X at (o0, k0), always inside the block): each
+  // chunk is a 32-bit byte offset from it, and a chunk outside the block
+  // gets an offset beyond the resource's range, for which the hardware
+  // returns zeros without touching memory.  Low precision: every block is
+  // made of whole 16-byte chunks (offsets, leading dimensions and the
+  // chunked extent multiples of VE, the base 16-byte aligned; the host
+  // checks this), so a chunk is one 16-byte load.  FP64 makes no such
+  // assumption: a chunk is two 8-byte elements.  No branches, no per-lane
+  // 64-bit addresses, whole-register loads: the compiler keeps the loads of
+  // later K steps in flight across the iterations.  Offsets stay below 2^31
+  // when the host-checked bound ld * 256 * sizeof(S) < 2^31 - 2^20 holds.
+  __device__ __forceinline__ void load_buf(const S* __restrict__ X, long ld, int o0, int Odim, int k0, int K) {
+    const S* first = KC ? X + (long)o0 * ld + k0 : X + (long)k0 * ld + o0;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<S*>(first), (short)0, 0x7fffffff, 0x00020000);
+    constexpr unsigned kOut = 0x80000000u;          // beyond the range: reads as zero
+    const int ldi = (int)ld;
+#pragma unroll
+    for (int p = 0; p < LPT; ++p) {
+      const int c = threadIdx.x + p * NT;
+      int o, k;
+      if constexpr (KC) { o = c / (BK / VE); k = (c % (BK / VE)) * VE; }
+      else { k = c / (O / VE); o = (c % (O / VE)) * VE; }
+      const int go = o0 + o, gk = k0 + k;
+      const unsigned off = (unsigned)((KC ? o * ldi + k : k * ldi + o) * (int)sizeof(S));
+      if constexpr (sizeof(S) == 8) {
+        const bool v0 = go < Odim && gk < K;
+        const bool v1 = KC ? (go < Odim && gk + 1 < K) : (gk < K && go + 1 < Odim);
+        typedef unsigned u2v __attribute__((ext_vector_type(2)));
+        const u2v a = __builtin_amdgcn_raw_buffer_load_b64(rs, v0 ? off : kOut, 0, 0);
+        const u2v b = __builtin_amdgcn_raw_buffer_load_b64(rs, v1 ? off + 8u : kOut, 0, 0);
+        r[p] = make_uint4(a.x, a.y, b.x, b.y);
+      } else {
+        typedef unsigned u4v __attribute__((ext_vector_type(4)));
+        const u4v q = __builtin_amdgcn_raw_buffer_load_b128(rs, (go < Odim && gk < K) ? off : kOut, 0, 0);
+        r[p] = make_uint4(q.x, q.y, q.z, q.w);
+      }
+    }
+  }
+
   // whether a tile starting at (o0, k0) may use load_full
   __device__ __forceinline__ static bool full_ok(const S* X, long ld, int o0, int Odim, int k0, int K) {
     const bool in = (o0 + O <= Odim) && (k0 + BK <= K);

@@ -687,11 +687,7 @@ struct Matvec {
       return;
     }
     if (tw) {
-      relayout_tiles(c, RL_F64, p == D3S_F32 ? RL_F32 : RL_BF16, x, xin, tw->d_X, tw->nX);
-      op_apply_heff_blocks(c, tw->h, p, Lc, Wc, Rc, xin, yout, false);
-      // the dense layout's forbidden entries are not written by the relayout
-      if (!plan->packed) zero_bytes(c, y, sizeof(double) * (size_t)n);
-      relayout_tiles(c, RL_F32, RL_F64, yout, y, tw->d_Y, tw->nY);
+      lowp_product(c, *plan, *tw, p, Lc, Wc, Rc, x, y, xin, yout, false);
       return;
     }
     if (p == D3S_F32) cast_f64_to_f32(c, x, (float*)xin, n);
