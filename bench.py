@@ -307,7 +307,9 @@ def hubbard_sweep_bench(ctx, abi, synth, torch, dev, l, sched, U, tol, lanczos_t
             if not final and max(st.m) < m:
                 saturated = True
         wall = time.perf_counter() - t0
-        split = {k: round(sum(getattr(r, k) for r in recs), 3) for k in ("t_eig", "t_expand", "t_trunc", "t_env", "t_energy")}
+        split = {k: round(sum(getattr(r, k) for r in recs), 3)
+                 for k in ("t_eig", "t_expand", "t_trunc", "t_trunc_eig", "t_env", "t_energy")}
+        split["trunc_passes_mean"] = round(sum(r.trunc_passes for r in recs) / len(recs), 2)
         out[name] = {"seconds_to_tol": None if t_conv is None else round(t_conv, 3), "seconds": round(wall, 3),
                      "sweeps": nsweeps, "energy": energies[-1], "matvecs": mv, "f64_matvecs": mv64,
                      "low_precision_share": round(1.0 - mv64 / max(mv, 1), 4),
@@ -384,6 +386,9 @@ def cylinder_bench(ctx, abi, synth, torch, dev, sched, sweeps_last, lanczos_tol,
             rows.append({"m": sched[-1], "seconds": round(time.perf_counter() - t, 3), "energy": stats.energy,
                          "rel_energy_change": dE, "t_eig": round(sum(r.t_eig for r in recs), 3),
                          "t_trunc": round(sum(r.t_trunc for r in recs), 3),
+                         "t_trunc_eig": round(sum(r.t_trunc_eig for r in recs), 3),
+                         "trunc_passes_max": max(r.trunc_passes for r in recs),
+                         "trunc_passes_mean": round(sum(r.trunc_passes for r in recs) / len(recs), 2),
                          "matvecs": sum(r.matvecs for r in recs), "f64_matvecs": sum(r.f64_matvecs for r in recs),
                          "max_bond": max(st.m), "sectors_mid_bond": int(sym._nsec[l // 2])})
             print("bench: cylinder %s m=%d %.2f s E=%.10f dE=%s" % (name, sched[-1], rows[-1]["seconds"],

@@ -117,6 +117,15 @@ d3s_status d3s_set_autotune(d3s_ctx ctx, int enable, const char* cache_path);
  * (eigenvectors of repeated eigenvalues may differ by a rotation within
  * their eigenspace); only the speed differs.  D3S_EINVAL outside 0..3. */
 d3s_status d3s_set_eigensolver(d3s_ctx ctx, int kind, int jacobi_max_n);
+/* Concurrency of the truncations' divide-and-conquer solves (Sec. 5 step 4
+ * on a GPU): rocSOLVER's solver is bound by its per-column launch sequence,
+ * so the batched calls of one truncation (groups of sector matrices) run on
+ * up to `workers` host threads at once, each with its own stream and
+ * rocBLAS handle (default 4; 1 = one call after the other).  A call of
+ * several matrices may be halved to balance the threads.  The results are
+ * those of the one-at-a-time solves up to rounding (the grouping into calls
+ * may differ).  D3S_EINVAL outside 1..8. */
+d3s_status d3s_set_eig_workers(d3s_ctx ctx, int workers);
 /* The batched FP64 symmetric eigensolver of the truncations (a6): `batch`
  * matrices of size n, column-major, stored one after the other in A
  * (device, n*n*batch), are replaced by their eigenvectors (columns) and W
@@ -551,6 +560,9 @@ typedef struct {
   int site, dir, k, matvecs, f64_matvecs;   /* matvecs: all H_eff products; f64_matvecs: the FP64 ones */
   double e_before, lambda, e_f, alpha, discarded;
   double t_eig, t_expand, t_trunc, t_env, t_energy;  /* seconds */
+  double t_trunc_eig;        /* seconds of t_trunc in the batched eigensolves */
+  int trunc_passes;          /* Gram passes of the truncation */
+  int reserved_;
 } d3s_site_record;
 
 typedef struct {

@@ -72,7 +72,8 @@ class d3s_site_record(ctypes.Structure):
     _fields_ = [("site", c_int), ("dir", c_int), ("k", c_int), ("matvecs", c_int), ("f64_matvecs", c_int),
                 ("e_before", c_double), ("lam", c_double), ("e_f", c_double), ("alpha", c_double),
                 ("discarded", c_double), ("t_eig", c_double), ("t_expand", c_double),
-                ("t_trunc", c_double), ("t_env", c_double), ("t_energy", c_double)]
+                ("t_trunc", c_double), ("t_env", c_double), ("t_energy", c_double),
+                ("t_trunc_eig", c_double), ("trunc_passes", c_int), ("reserved_", c_int)]
 
 
 class d3s_sweep_stats(ctypes.Structure):
@@ -142,6 +143,7 @@ _plan_create = _sig("d3s_block_plan_create", c_int, [c_void_p, c_int, c_int, c_i
                                                      ctypes.POINTER(d3s_sectors), ctypes.POINTER(d3s_sectors),
                                                      c_int_p, c_int_p, c_int_p, ctypes.POINTER(c_void_p),
                                                      c_double_p, c_int_p])
+_set_eig_workers = _sig("d3s_set_eig_workers", c_int, [c_void_p, c_int])
 _plan_create_layout = _sig("d3s_block_plan_create_layout", c_int,
                            [c_void_p, c_int, c_int, c_int, c_int, ctypes.POINTER(d3s_sectors),
                             ctypes.POINTER(d3s_sectors), c_int_p, c_int_p, c_int_p, c_int,
@@ -297,6 +299,10 @@ class Context:
         """0 auto (Jacobi up to jacobi_max_n), 1 divide and conquer, 2 Jacobi,
         3 the library's LDS solver up to n = 128."""
         self._check(_set_eig(self.h, int(kind), int(jacobi_max_n)))
+
+    def set_eig_workers(self, workers):
+        """Concurrent divide-and-conquer solves in a truncation (1 = one at a time)."""
+        self._check(_set_eig_workers(self.h, int(workers)))
 
     def set_block_split(self, min_gflop):
         """Split the block sweeps' second GEMM from min_gflop GFLOP on (< 0: never)."""

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "lib", "libdmrg3s.so")
-SOURCES = ["gemm.hip", "grouped.hip", "blocks.hip", "kernels.hip", "ops.hip", "sweep.hip", "trunc.hip", "noalloc.hip", "api.hip", "autotune.hip", "mpo.cpp"]
+SOURCES = ["gemm.hip", "grouped.hip", "blocks.hip", "kernels.hip", "ops.hip", "sweep.hip", "trunc.hip", "eigpool.hip", "noalloc.hip", "api.hip", "autotune.hip", "mpo.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

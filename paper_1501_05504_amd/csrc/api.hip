@@ -102,6 +102,7 @@ void d3s_destroy(d3s_ctx ctx) {
   (void)hipSetDevice(ctx->c.device);
   (void)hipStreamSynchronize(ctx->c.stream);
   for (hipEvent_t e : ctx->c.prof_ev) (void)hipEventDestroy(e);
+  d3s::eig_pool_destroy(&ctx->c);
   d3s::ws_release_all(&ctx->c);
   if (ctx->c.solver) rocblas_destroy_handle((rocblas_handle)ctx->c.solver);
   if (ctx->c.host_red) (void)hipHostFree(ctx->c.host_red);
@@ -205,6 +206,14 @@ d3s_status d3s_set_eigensolver(d3s_ctx ctx, int kind, int jacobi_max_n) {
     D3S_REQUIRE(jacobi_max_n >= 0, "jacobi_max_n must be >= 0");
     ctx->c.eig_kind = kind;
     ctx->c.eig_jacobi_max = jacobi_max_n;
+    return D3S_OK;
+  });
+}
+
+d3s_status d3s_set_eig_workers(d3s_ctx ctx, int workers) {
+  return guarded(ctx, [&] {
+    D3S_REQUIRE(workers >= 1 && workers <= 8, "workers must be 1 to 8");
+    ctx->c.eig_workers = workers;
     return D3S_OK;
   });
 }

@@ -1403,6 +1403,8 @@ void op_sweep_blocks(Ctx* c, d3s_state* s, SymChain& sym, d3s_sweep_params* p, d
         op_expand_blocks(c, cur.h, D3S_R2L, s->renv[i], s->mpo[i], xp, p->alpha, Mt);
         D3S_HIP(hipStreamSynchronize(c->stream));
         t2 = now_s();
+        c->stat_eig_s = 0.0;
+        c->stat_passes = 0;
         const int mll = s->m[i - 1];
         t = op_truncate_blocks(c, D3S_R2L, sym.bonds[i], sym.bonds[i + 1], d, sym.phys.data(), sym.wq[i].data(), wl,
                                (long)(1 + wl) * ml, Mt, s->site[i], (int)budget_of(l, d, mlim, i), p->eps,
@@ -1412,6 +1414,8 @@ void op_sweep_blocks(Ctx* c, d3s_state* s, SymChain& sym, d3s_sweep_params* p, d
         s->m[i] = t.k;
         sym.bonds[i] = Sectors(sym.nq, (int)t.dim.size(), t.q.data(), t.dim.data());
         t3 = now_s();
+        r.t_trunc_eig = c->stat_eig_s;
+        r.trunc_passes = c->stat_passes;
         {
           PlanGuard e;
           site_plan(c, e.h, s, sym, i, false, false);
@@ -1428,6 +1432,8 @@ void op_sweep_blocks(Ctx* c, d3s_state* s, SymChain& sym, d3s_sweep_params* p, d
         op_expand_blocks(c, cur.h, D3S_L2R, s->lenv[i], s->mpo[i], xp, p->alpha, Mt);
         D3S_HIP(hipStreamSynchronize(c->stream));
         t2 = now_s();
+        c->stat_eig_s = 0.0;
+        c->stat_passes = 0;
         const int mrr = s->m[i + 2];
         t = op_truncate_blocks(c, D3S_L2R, sym.bonds[i], sym.bonds[i + 1], d, sym.phys.data(), sym.wq[i + 1].data(),
                                wr, (long)(1 + wr) * mr, Mt, s->site[i], (int)budget_of(l, d, mlim, i + 1), p->eps,
@@ -1437,6 +1443,8 @@ void op_sweep_blocks(Ctx* c, d3s_state* s, SymChain& sym, d3s_sweep_params* p, d
         s->m[i + 1] = t.k;
         sym.bonds[i + 1] = Sectors(sym.nq, (int)t.dim.size(), t.q.data(), t.dim.data());
         t3 = now_s();
+        r.t_trunc_eig = c->stat_eig_s;
+        r.trunc_passes = c->stat_passes;
         {
           PlanGuard e;
           site_plan(c, e.h, s, sym, i, false, false);

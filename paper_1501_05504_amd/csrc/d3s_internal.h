@@ -40,9 +40,11 @@ enum WsSlot {
   WS_EIGTMP, WS_UKT, WS_X, WS_MT, WS_CAST_L, WS_CAST_R, WS_CAST_X, WS_CAST_Y,
   WS_CAST_W, WS_REF, WS_PSI, WS_INFO, WS_NBR, WS_MISC, WS_SPLITK, WS_DESC, WS_BLK_X, WS_XPACK, WS_GPACK, WS_GVAL, WS_TUNE, WS_PK, WS_LZ_K, WS_GS_NORM, WS_JD_V, WS_JD_W, WS_JD_Z, WS_JD_COEF, WS_G2_PART, WS_W2, WS_RMET, WS_RZ, WS_RT, WS_RGRAM, WS_H2, WS_PSIT, WS_LP_L, WS_LP_R, WS_LP_X, WS_LP_Y,
   WS_TR_G, WS_TR_V, WS_TR_W0, WS_TR_W1, WS_TR_T2, WS_TR_T3, WS_TR_T4, WS_TR_P, WS_TR_TAB, WS_TR_AUX, WS_TR_XT,
+  WS_EIG_PAR,
   WS_NSLOTS
 };
 
+struct EigPool;   // worker threads of the concurrent eigensolves (eigpool.hip)
 struct Ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -62,6 +64,12 @@ struct Ctx {
   d3s_prec tune_prec = D3S_F64;      // precision the grouped plans being built will run in
   int eig_kind = 0;                  // batched eigensolver: 0 auto, 1 divide and conquer, 2 Jacobi, 3 LDS solver
   int eig_jacobi_max = 0;            // auto: Jacobi up to this size
+  int eig_workers = 4;               // concurrent divide-and-conquer solves in a truncation (1: one at a time)
+  EigPool* eig_pool = nullptr;       // created on first concurrent use
+  // truncation statistics, accumulated until the caller resets them: wall
+  // seconds of the batched eigensolves and the Gram passes run
+  double stat_eig_s = 0.0;
+  int stat_passes = 0;
   std::unordered_map<std::string, int> tune_cache;
   std::string tune_path;
   // per-kernel profiling of H_eff: events around GEMM-1, W-map, GEMM-2
@@ -262,6 +270,9 @@ void op_update_env(Ctx* c, d3s_dir dir, int ml, int d, int mr, int wl, int wr,
 // ---------------------------------------------------------------- truncation engine (trunc.hip)
 // Batches of the eigensolver: per matrix its padded size and the offsets of
 // its (column-major) matrix and eigenvalues; matrices of a bucket share a size.
+// one batched solve: `batch` matrices of size n stored consecutively from G
+// + goff (column-major n x n each), eigenvalues from V + voff
+struct EigCall { int n, batch; long goff, voff; };
 struct EigPlan {
   std::vector<int> npad;
   std::vector<long> goff, voff;
@@ -269,7 +280,16 @@ struct EigPlan {
   std::vector<std::vector<int>> members;
   std::vector<long> bucket_goff, bucket_voff;
   long gtot = 0, vtot = 0;
+  // the solves and, when they run concurrently, the worker of each
+  std::vector<EigCall> calls;
+  std::vector<int> worker;
+  int workers = 1;
 };
+// the calls on `workers` threads at once (divide and conquer); returns when
+// all have completed; D3S_EDEVICE on a failed or unconverged solve
+void eig_calls_parallel(Ctx* c, const std::vector<EigCall>& calls, const std::vector<int>& worker, int workers,
+                        double* G, double* V);
+void eig_pool_destroy(Ctx* c);
 EigPlan plan_eig(Ctx* c, const std::vector<int>& n);          // n[q] <= 0: matrix q not in the plan
 // normalise every matrix (largest diagonal entry 1, padded diagonal -1) and
 // solve; scale[q] multiplies matrix q's eigenvalues back

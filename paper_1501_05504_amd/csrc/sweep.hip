@@ -184,6 +184,8 @@ void op_sweep(Ctx* c, d3s_state* s, d3s_sweep_params* p, d3s_sweep_stats* st) {
       op_expand(c, D3S_R2L, ml, d, mr, wl, wr, s->renv[i], s->mpo[i], s->site[i], p->alpha, Mt);
     D3S_HIP(hipStreamSynchronize(c->stream));
     double t2 = now();
+    c->stat_eig_s = 0.0;
+    c->stat_passes = 0;
     const int mll = s->m[i - 1];
     TruncResult t = op_truncate(c, D3S_R2L, ml, d, mr, rows, Mt, s->site[i], (int)bond_budget(l, d, mlim, i),
                                 p->eps, s->site[i - 1], (long)mll * d, tmpS, tmpN, nullptr, true);
@@ -191,6 +193,8 @@ void op_sweep(Ctx* c, d3s_state* s, d3s_sweep_params* p, d3s_sweep_stats* st) {
     copy_f64(c, tmpN, s->site[i - 1], (long)mll * d * t.k);
     s->m[i] = t.k;
     double t3 = now();
+    r.t_trunc_eig = c->stat_eig_s;
+    r.trunc_passes = c->stat_passes;
     op_update_env(c, D3S_R2L, t.k, d, mr, wl, wr, s->renv[i], s->mpo[i], s->site[i], s->renv[i - 1]);
     if (residual)
       op_update_env_h2(c, D3S_R2L, t.k, d, mr, wl, wr, h2r[i], s->mpo[i], s->site[i], h2r[i - 1]);
@@ -235,6 +239,8 @@ void op_sweep(Ctx* c, d3s_state* s, d3s_sweep_params* p, d3s_sweep_stats* st) {
       op_expand(c, D3S_L2R, ml, d, mr, wl, wr, s->lenv[i], s->mpo[i], s->site[i], p->alpha, Mt);
     D3S_HIP(hipStreamSynchronize(c->stream));
     double t2 = now();
+    c->stat_eig_s = 0.0;
+    c->stat_passes = 0;
     const int mrr = s->m[i + 2];
     TruncResult t = op_truncate(c, D3S_L2R, ml, d, mr, width, Mt, s->site[i], (int)bond_budget(l, d, mlim, i + 1),
                                 p->eps, s->site[i + 1], (long)d * mrr, tmpS, tmpN, nullptr, true);
@@ -242,6 +248,8 @@ void op_sweep(Ctx* c, d3s_state* s, d3s_sweep_params* p, d3s_sweep_stats* st) {
     copy_f64(c, tmpN, s->site[i + 1], (long)t.k * d * mrr);
     s->m[i + 1] = t.k;
     double t3 = now();
+    r.t_trunc_eig = c->stat_eig_s;
+    r.trunc_passes = c->stat_passes;
     op_update_env(c, D3S_L2R, ml, d, t.k, wl, wr, s->lenv[i], s->mpo[i], s->site[i], s->lenv[i + 1]);
     if (residual)
       op_update_env_h2(c, D3S_L2R, ml, d, t.k, wl, wr, h2l[i], s->mpo[i], s->site[i], h2l[i + 1]);

@@ -33,6 +33,7 @@
 // ones (which then sit in the last n columns, supported on the first n rows,
 // to rounding).
 #include <algorithm>
+#include <chrono>
 #include <cfloat>
 #include <cmath>
 #include <map>
@@ -196,6 +197,56 @@ EigPlan plan_eig(Ctx* c, const std::vector<int>& n) {
       ep.vtot += np;
       ep.members.back().push_back(q);
     }
+    ep.calls.push_back(EigCall{np, cnt, ep.bucket_goff.back(), ep.bucket_voff.back()});
+  }
+  // Concurrent solves (divide and conquer only): each call's cost model as
+  // above; the calls are dealt to the workers largest first, each to the
+  // least loaded, and a call of several matrices is halved (its halves are
+  // two calls on consecutive matrices) while that lowers the largest load.
+  const int K = c->eig_workers;
+  bool all_dc = c->eig_kind != 2;
+  for (int b : ep.bucket_n)
+    all_dc = all_dc && !eig_small_used(c, b) && !(c->eig_kind == 0 && b <= c->eig_jacobi_max);
+  if (K >= 2 && all_dc && !ep.calls.empty()) {
+    auto cc = [](const EigCall& e) { return 2.4e-5 * e.n + 1.6e-12 * (double)e.batch * e.n * e.n * (double)e.n; };
+    auto assign = [&](std::vector<EigCall>& calls, std::vector<int>& who) {
+      std::vector<int> ord2(calls.size());
+      for (size_t i = 0; i < ord2.size(); ++i) ord2[i] = (int)i;
+      std::stable_sort(ord2.begin(), ord2.end(), [&](int a, int b) { return cc(calls[a]) > cc(calls[b]); });
+      std::vector<double> load(K, 0.0);
+      who.assign(calls.size(), 0);
+      for (int i : ord2) {
+        const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        who[i] = k;
+        load[k] += cc(calls[i]);
+      }
+      return *std::max_element(load.begin(), load.end());
+    };
+    std::vector<int> who;
+    double span = assign(ep.calls, who);
+    for (;;) {
+      double best = span;
+      std::vector<EigCall> best_calls;
+      for (size_t i = 0; i < ep.calls.size(); ++i) {
+        const EigCall e = ep.calls[i];
+        if (e.batch < 2) continue;
+        const int h = e.batch / 2;
+        std::vector<EigCall> t = ep.calls;
+        t[i] = EigCall{e.n, h, e.goff, e.voff};
+        t.push_back(EigCall{e.n, e.batch - h, e.goff + (long)h * e.n * e.n, e.voff + (long)h * e.n});
+        std::vector<int> w2;
+        const double v = assign(t, w2);
+        if (v < best - 1e-9) {
+          best = v;
+          best_calls = t;
+        }
+      }
+      if (best_calls.empty()) break;
+      ep.calls = best_calls;
+      span = best;
+    }
+    assign(ep.calls, ep.worker);
+    ep.workers = (ep.calls.size() >= 2) ? K : 1;
   }
   return ep;
 }
@@ -235,8 +286,16 @@ void eig_run(Ctx* c, const EigPlan& ep, const std::vector<int>& n, double* G, do
   const unsigned gx = (unsigned)std::min<long>((maxel + kThr - 1) / kThr, 2048);
   hipLaunchKernelGGL(gram_normalize_kernel, dim3(gx, (unsigned)mats.size()), dim3(kThr), 0, c->stream, G, d, sc);
   D3S_HIP(hipGetLastError());
-  for (size_t b = 0; b < ep.bucket_n.size(); ++b)
-    eig_batched_f64(c, ep.bucket_n[b], (int)ep.members[b].size(), G + ep.bucket_goff[b], V + ep.bucket_voff[b]);
+  D3S_HIP(hipStreamSynchronize(c->stream));
+  const auto t0 = std::chrono::steady_clock::now();
+  if (ep.workers >= 2) {
+    eig_calls_parallel(c, ep.calls, ep.worker, ep.workers, G, V);
+  } else {
+    for (size_t b = 0; b < ep.bucket_n.size(); ++b)
+      eig_batched_f64(c, ep.bucket_n[b], (int)ep.members[b].size(), G + ep.bucket_goff[b], V + ep.bucket_voff[b]);
+  }
+  // every solve path ends with a readback of its convergence flags
+  c->stat_eig_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   for (size_t i = 0; i < qs.size(); ++i) scale[qs[i]] = hs[i];
 }
 
@@ -268,6 +327,7 @@ void trunc_solve(Ctx* c, const TruncMats& tm, int kmax, double eps, TruncSel& ou
   std::vector<int> solve(Q, 1);
   double s0 = 0.0;
   for (int pass = 1;; ++pass) {
+    ++c->stat_passes;
     // ---- Gram matrices of this pass, padded batched eigensolves
     std::vector<int> nsolve(Q, 0);
     for (int q = 0; q < Q; ++q)

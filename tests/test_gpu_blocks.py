@@ -305,6 +305,45 @@ def test_block_truncate_keeps_every_value_above_eps(ctx, direction, ml, mr, seed
     assert abs(disc - disc_ref) < 1e-14 * float(np.sum(s ** 2))
 
 
+@pytest.mark.parametrize("direction", ["l2r", "r2l"])
+def test_block_truncate_concurrent_solves_equal_serial(direction):
+    """The sector eigensolves of one truncation run concurrently (four
+    worker threads and streams) or one after the other: same kept states
+    per sector, the same kept subspace and discarded weight to rounding."""
+    case = hubbard_block_case(300, 257, 41)
+    ml, mr, d = case["psi"].shape[0], case["psi"].shape[2], 4
+    Mt, psi, kept = _sector_spectrum_case(case, direction, 141)
+    n = ml * d if direction == "l2r" else d * mr
+    res = []
+    for workers in (1, 4):
+        c = abi.Context(0)
+        try:
+            c.set_eig_workers(workers)
+            plan = make_plan(c, case)
+            site = torch.empty(n * n, dtype=torch.float64, device=DEV)
+            if direction == "l2r":
+                nbr = np.ones((mr, d, 3))
+                nout = torch.empty(n * d * 3, dtype=torch.float64, device=DEV)
+                k, disc, q, dims = plan.truncate(abi.L2R, dev(Mt), dev(psi), n, 1e-14, dev(nbr), site, nout,
+                                                 renormalize=False)
+                U = site[: n * k].view(n, k).cpu().numpy()
+            else:
+                nbr = np.ones((3, d, ml))
+                nout = torch.empty(3 * d * n, dtype=torch.float64, device=DEV)
+                k, disc, q, dims = plan.truncate(abi.R2L, dev(Mt), dev(psi), n, 1e-14, dev(nbr), site, nout,
+                                                 renormalize=False)
+                U = site[: k * n].view(k, n).cpu().numpy().T
+            res.append((k, disc, [tuple(x) for x in np.asarray(q).tolist()], list(dims), U @ U.T))
+            plan.close()
+        finally:
+            c.close()
+    (k1, d1, q1, m1, P1), (k4, d4, q4, m4, P4) = res
+    assert k1 == k4 == sum(kept.values())
+    assert q1 == q4 and m1 == m4
+    assert abs(d1 - d4) < 1e-14 * float(np.sum(Mt ** 2))
+    assert np.abs(P1 - P4).max() < 1e-8
+
+
 @pytest.mark.parametrize("ml,mr,seed", [(40, 52, 21), (300, 257, 22)])
 def test_block_update_env_equals_dense_oracle(ctx, ml, mr, seed):
     """Both environment updates from the grouped launches equal the oracle's
