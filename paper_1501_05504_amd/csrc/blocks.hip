@@ -55,6 +55,30 @@ int Sectors::find(const int* charge) const {
   return it == index.end() ? -1 : it->second;
 }
 
+// Tile size (measured on MI355X with the sectors of a 4096-state cylinder
+// bond, ~45 sectors: 64x64 tiles beat 96x96 and 128x128 in FP64 and FP32,
+// their smaller register footprint keeping more waves in flight): 64x64 by
+// default, 128x128 only when the blocks nearly fill them, 32x32 when 64x64
+// tiles would be more than half empty.  BF16: the 8-wave 128x128 tile beats
+// 64x64 by 14 % at that site, where 128x128 tiles cover at most ~40 % more
+// area than 64x64 ones; at half the bond 64x64 wins.  The autotuner, when
+// on, times all six.
+int grouped_pick_cfg(const Ctx* c, const GroupedPlan& g, d3s_prec p) {
+  if (c->grouped_cfg >= 0) return c->grouped_cfg;
+  long t64 = 0, t128 = 0;
+  double a32 = 0.0, a64 = 0.0;
+  for (const GTask& t : g.tasks) {
+    t64 += (long)((t.M + 63) / 64) * ((t.N + 63) / 64);
+    t128 += (long)((t.M + 127) / 128) * ((t.N + 127) / 128);
+    a32 += 1024.0 * ((t.M + 31) / 32) * ((t.N + 31) / 32);
+    a64 += 4096.0 * ((t.M + 63) / 64) * ((t.N + 63) / 64);
+  }
+  if (p == D3S_BF16 && t128 >= 256 && 4 * t128 <= t64 + (2 * t64) / 5) return 4;
+  if (t128 >= 512 && 4 * t128 <= t64 + t64 / 4) return 0;
+  if (a64 > 2.0 * a32) return 3;
+  return 1;
+}
+
 void grouped_finalize(Ctx* c, GroupedPlan& g) {
   // largest tasks first (by flops), then tile prefix sums
   std::vector<int> order(g.tasks.size());
@@ -74,26 +98,7 @@ void grouped_finalize(Ctx* c, GroupedPlan& g) {
     g.flops += 2.0 * work(g.tasks[i]);
   }
   g.tasks.swap(sorted);
-  // tile size (measured on MI355X with the sectors of a 4096-state cylinder
-  // bond, ~45 sectors: 64x64 tiles beat 96x96 and 128x128 in FP64 and FP32,
-  // their smaller register footprint keeping more waves in flight): 64x64 by
-  // default, 128x128 only when the blocks nearly fill them, 32x32 when
-  // 64x64 tiles would be more than half empty; the autotuner times all four
-  if (c->grouped_cfg >= 0) {
-    g.cfg = c->grouped_cfg;
-  } else {
-    long t64 = 0, t128 = 0;
-    double a32 = 0.0, a64 = 0.0;
-    for (const GTask& t : g.tasks) {
-      t64 += (long)((t.M + 63) / 64) * ((t.N + 63) / 64);
-      t128 += (long)((t.M + 127) / 128) * ((t.N + 127) / 128);
-      a32 += 1024.0 * ((t.M + 31) / 32) * ((t.N + 31) / 32);
-      a64 += 4096.0 * ((t.M + 63) / 64) * ((t.N + 63) / 64);
-    }
-    if (t128 >= 512 && 4 * t128 <= t64 + t64 / 4) g.cfg = 0;
-    else if (a64 > 2.0 * a32) g.cfg = 3;
-    else g.cfg = 1;
-  }
+  g.cfg = grouped_pick_cfg(c, g, c->tune_prec);
   g.ntasks = (int)g.tasks.size();
   grouped_release(g);
   if (g.ntasks == 0) return;
@@ -576,7 +581,20 @@ Sectors padded_sectors(const Sectors& s) {
 
 LowpTwin& ensure_lowp(Ctx* c, BlockHeff& h, d3s_prec p) {
   if (h.padded) throw Error{D3S_EINVAL, "blocks: a padded plan has no twin"};
-  if (h.lp) return *h.lp;
+  if (h.lp) {
+    // built for the other low precision: its launches get that precision's
+    // tile rule (the autotuner's choices are kept)
+    if (h.lp->prec != p && !c->autotune)
+      for (GroupedPlan* g : {&h.lp->h.g1, &h.lp->h.g1t, &h.lp->h.g2}) {
+        const int cfg = grouped_pick_cfg(c, *g, p);
+        if (g->ntasks > 0 && cfg != g->cfg) {
+          g->cfg = cfg;
+          grouped_retile(c, *g);
+        }
+      }
+    h.lp->prec = p;
+    return *h.lp;
+  }
   LowpTwin* tw = new LowpTwin();
   try {
     const Sectors pl = padded_sectors(h.left), pr = padded_sectors(h.right);
@@ -591,6 +609,7 @@ LowpTwin& ensure_lowp(Ctx* c, BlockHeff& h, d3s_prec p) {
     }
     c->tune_prec = D3S_F64;
     tw->h.padded = true;
+    tw->prec = p;
     const BlockHeff& t = tw->h;
     std::vector<RlTile> vl, vr, vx, vy;
     int qq[4];

@@ -129,6 +129,9 @@ struct GroupedPlan {
   Ctx* owner = nullptr;         // context whose allocator holds the tables
 };
 void grouped_tile_dims(int cfg, int& bm, int& bn);   // block tile of a grouped configuration
+// the tile configuration of a plan's launches in precision p (the rule; or
+// the context's fixed configuration)
+int grouped_pick_cfg(const Ctx* c, const GroupedPlan& g, d3s_prec p);
 // sort tasks largest-first, pick the tile size, compute tile prefix sums and
 // upload the tables (synchronises the stream)
 void grouped_finalize(Ctx* c, GroupedPlan& g);
@@ -443,6 +446,7 @@ struct LowpTwin {
   // product's element type, W in FP32 (owned, from the plan owner's allocator)
   void *bL = nullptr, *bR = nullptr, *bW = nullptr;
   d3s_prec bprec = D3S_F64;                 // D3S_F64: nothing bound
+  d3s_prec prec = D3S_F32;                  // precision its tile sizes were chosen for
 };
 // built on the first FP32 / BF16 product; its grouped launches are tuned
 // (autotuning on) in that product's precision

@@ -239,8 +239,8 @@ void wmap_blocks_kernel(const Tin* __restrict__ in, const Tc* __restrict__ Wg, T
     sOutW[i] = ents[tk.idx0 + nin + i].wp;
   }
   __syncthreads();
-  // W rows zero-padded to MAXK, input rows past nin clamped to the last one:
-  // the loads and the inner loop carry no bounds tests
+  // W rows zero-padded to MAXK; inputs past nin are zeros (the test is
+  // uniform over the workgroup, so it costs no divergence and no loads)
   for (int i = threadIdx.x; i < nout * MAXK; i += blockDim.x) {
     const int o = i / MAXK, k = i - o * MAXK;
     sW[i] = (k < nin) ? alpha * Wg[sInW[k] + sOutW[o]] : Tc(0);
@@ -260,7 +260,7 @@ void wmap_blocks_kernel(const Tin* __restrict__ in, const Tc* __restrict__ Wg, T
     }
     Tc v[MAXK];
 #pragma unroll
-    for (int k = 0; k < MAXK; ++k) v[k] = (Tc)Cvt<Tin>::ld(src[sInOff[min(k, nin - 1)]]);
+    for (int k = 0; k < MAXK; ++k) v[k] = (k < nin) ? (Tc)Cvt<Tin>::ld(src[sInOff[k]]) : Tc(0);
     for (int o = 0; o < nout; ++o) {
       Tc acc = 0;
 #pragma unroll
@@ -317,9 +317,14 @@ void wmap_blocks_vec4_kernel(const Tin* __restrict__ in, const Tc* __restrict__ 
   Tc v[MAXK][4];
 #pragma unroll
   for (int k = 0; k < MAXK; ++k) {
-    const Vec4<Tin> q = *reinterpret_cast<const Vec4<Tin>*>(src + sInOff[min(k, nin - 1)]);
+    if (k < nin) {
+      const Vec4<Tin> q = *reinterpret_cast<const Vec4<Tin>*>(src + sInOff[k]);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) v[k][j] = (Tc)Cvt<Tin>::ld(q.v[j]);
+      for (int j = 0; j < 4; ++j) v[k][j] = (Tc)Cvt<Tin>::ld(q.v[j]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[k][j] = Tc(0);
+    }
   }
   for (int o = 0; o < nout; ++o) {
     Tc acc[4] = {0, 0, 0, 0};
