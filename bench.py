@@ -28,8 +28,8 @@ HBM_PEAK = 8.0e12
 # only for the sources they were taken on (first 16 hex digits of the
 # SHA-256 of the GEMM kernels and their host set-up); any other source
 # reports null.
-TRAFFIC = {"src_sha": "3899ab4aa3600510", "m": 2048,
-           "gemm1": 4.164e9 + 0.940e9, "gemm2": 4.633e9 + 0.134e9}
+TRAFFIC = {"src_sha": "6065cd2a47b13271", "m": 2048,
+           "gemm1": 4.165e9 + 0.940e9, "gemm2": 4.591e9 + 0.134e9}
 
 
 def gemm_source_sha():
@@ -648,7 +648,7 @@ def main():
                     help="Gaussian L and R instead of MPS-built environments (same kernels and shapes; "
                          "no eigensolver calls, for counter runs)")
     ap.add_argument("--no-blocks", action="store_true", help="skip the block-sparse H_eff, sweep and cylinder measurements")
-    ap.add_argument("--sweep-l", type=int, default=64)
+    ap.add_argument("--sweep-l", type=int, default=64, help="Hubbard chain length of the block sweeps (0 = skip)")
     ap.add_argument("--sweep-sched", type=str, default="128,256,512,1024,2048",
                     help="bond limits of the block sweep run (two sweeps each, then to convergence at the last)")
     ap.add_argument("--sweep-max", type=int, default=8, help="sweeps at the last bond limit")
@@ -787,8 +787,9 @@ def main():
         if args.site_m > 0:
             line["cylinder_site"] = cylinder_site_bench(ctx, abi, synth, torch, np, args.site_m, dev, 20)
         sched = [int(x) for x in args.sweep_sched.split(",")]
-        line["sweep"] = hubbard_sweep_bench(ctx, abi, synth, torch, dev, args.sweep_l, sched, 8.0, 1e-8, 1e-10,
-                                            args.sweep_max, args.growth_tol, args.mixed_min_gflop)
+        if args.sweep_l > 0:
+            line["sweep"] = hubbard_sweep_bench(ctx, abi, synth, torch, dev, args.sweep_l, sched, 8.0, 1e-8, 1e-10,
+                                                args.sweep_max, args.growth_tol, args.mixed_min_gflop)
         if args.dense_m > 0:
             line["dense_vs_blocks"] = dense_vs_blocks_bench(ctx, abi, synth, torch, dev, args.sweep_l, args.dense_m,
                                                             8.0)
