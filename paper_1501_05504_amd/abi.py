@@ -678,6 +678,44 @@ class State:
         return [self.site_tensor(i) for i in range(self.l)]
 
 
+def save_checkpoint(path, state, sym=None, **scalars):
+    """Checkpoint of a sweep (host side, an .npz file with arrays only): the
+    site tensors of `state` (anything with .l and .tensors()), the sectors of
+    every bond when `sym` is given (anything with .sectors(b)), and scalar
+    values by keyword (for instance alpha, energy).  A sweep resumes from it
+    through load_checkpoint: a State and a Symmetry rebuilt from the arrays,
+    environments from prepare / prepare_blocks, and the saved alpha."""
+    import numpy as np
+    arrs = {"l": np.int64(state.l)}
+    for i, t in enumerate(state.tensors()):
+        arrs["site_%d" % i] = torch.as_tensor(t).detach().to("cpu", torch.float64).numpy()
+    if sym is not None:
+        for b in range(state.l + 1):
+            q, d = sym.sectors(b)
+            arrs["secq_%d" % b] = np.asarray(q, dtype=np.int32)
+            arrs["secd_%d" % b] = np.asarray(d, dtype=np.int32)
+    for k, v in scalars.items():
+        arrs["scalar_" + k] = np.float64(v)
+    with open(path, "wb") as f:
+        np.savez(f, **arrs)
+
+
+def load_checkpoint(path):
+    """Inverse of save_checkpoint: {"tensors": [CPU FP64 tensors],
+    "sectors": [(charges, dims) per bond] or None, and the scalars}.  Reads
+    arrays only (no pickled objects)."""
+    import numpy as np
+    with np.load(path, allow_pickle=False) as z:
+        l = int(z["l"])
+        out = {"tensors": [torch.from_numpy(z["site_%d" % i].copy()) for i in range(l)],
+               "sectors": ([(z["secq_%d" % b].copy(), z["secd_%d" % b].copy()) for b in range(l + 1)]
+                           if "secq_0" in z.files else None)}
+        for k in z.files:
+            if k.startswith("scalar_"):
+                out[k[len("scalar_"):]] = float(z[k])
+    return out
+
+
 class Symmetry:
     """Charges of a symmetric chain (d3s_symmetry): physical charges, MPO
     channel charges per MPO bond and the current sectors of every MPS bond."""
