@@ -126,6 +126,17 @@ d3s_status d3s_set_eigensolver(d3s_ctx ctx, int kind, int jacobi_max_n);
  * those of the one-at-a-time solves up to rounding (the grouping into calls
  * may differ).  D3S_EINVAL outside 1..8. */
 d3s_status d3s_set_eig_workers(d3s_ctx ctx, int workers);
+/* The mixed-precision eigensolver's two phases (FP32 / BF16 products, see
+ * d3s_lanczos): Lanczos on the low-precision operator stops at relative
+ * residual `low_tol` (<= 0: 1e-6 for FP32, 3e-3 for BF16, the defaults);
+ * each FP64 refinement step then solves its correction equation with at
+ * most `inner_max` low-precision conjugate-gradient steps, until the inner
+ * residual is below `eta` times the outer one (defaults 0.1 and 20).  A
+ * smaller eta spends more low-precision products per FP64 product.  The
+ * converged eigenpair meets the same FP64 residual tolerance whatever the
+ * setting.  D3S_EINVAL unless 0 < eta < 1, 1 <= inner_max <= 1000 and
+ * low_tol < 1. */
+d3s_status d3s_set_refinement(d3s_ctx ctx, double eta, int inner_max, double low_tol);
 /* The batched FP64 symmetric eigensolver of the truncations (a6): `batch`
  * matrices of size n, column-major, stored one after the other in A
  * (device, n*n*batch), are replaced by their eigenvectors (columns) and W

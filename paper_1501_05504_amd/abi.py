@@ -144,6 +144,7 @@ _plan_create = _sig("d3s_block_plan_create", c_int, [c_void_p, c_int, c_int, c_i
                                                      c_int_p, c_int_p, c_int_p, ctypes.POINTER(c_void_p),
                                                      c_double_p, c_int_p])
 _set_eig_workers = _sig("d3s_set_eig_workers", c_int, [c_void_p, c_int])
+_set_refine = _sig("d3s_set_refinement", c_int, [c_void_p, c_double, c_int, c_double])
 _plan_create_layout = _sig("d3s_block_plan_create_layout", c_int,
                            [c_void_p, c_int, c_int, c_int, c_int, ctypes.POINTER(d3s_sectors),
                             ctypes.POINTER(d3s_sectors), c_int_p, c_int_p, c_int_p, c_int,
@@ -303,6 +304,12 @@ class Context:
     def set_eig_workers(self, workers):
         """Concurrent divide-and-conquer solves in a truncation (1 = one at a time)."""
         self._check(_set_eig_workers(self.h, int(workers)))
+
+    def set_refinement(self, eta=0.1, inner_max=20, low_tol=0.0):
+        """Mixed-precision eigensolver: inner CG target eta (relative to the
+        FP64 residual), its step cap, and the low-precision Lanczos stop
+        (<= 0: the per-precision default)."""
+        self._check(_set_refine(self.h, float(eta), int(inner_max), float(low_tol)))
 
     def set_block_split(self, min_gflop):
         """Split the block sweeps' second GEMM from min_gflop GFLOP on (< 0: never)."""

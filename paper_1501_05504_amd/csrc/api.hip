@@ -218,6 +218,18 @@ d3s_status d3s_set_eig_workers(d3s_ctx ctx, int workers) {
   });
 }
 
+d3s_status d3s_set_refinement(d3s_ctx ctx, double eta, int inner_max, double low_tol) {
+  return guarded(ctx, [&] {
+    D3S_REQUIRE(eta > 0.0 && eta < 1.0, "eta must lie in (0, 1)");
+    D3S_REQUIRE(inner_max >= 1 && inner_max <= 1000, "inner_max must be 1 to 1000");
+    D3S_REQUIRE(std::isfinite(low_tol) && low_tol < 1.0, "low_tol must be below 1");
+    ctx->c.refine_eta = eta;
+    ctx->c.refine_inner = inner_max;
+    ctx->c.refine_low_tol = low_tol;
+    return D3S_OK;
+  });
+}
+
 d3s_status d3s_set_splitk(d3s_ctx ctx, int enable) {
   return guarded(ctx, [&] {
     ctx->c.splitk_off = (enable == 0);

@@ -65,6 +65,9 @@ struct Ctx {
   int eig_kind = 0;                  // batched eigensolver: 0 auto, 1 divide and conquer, 2 Jacobi, 3 LDS solver
   int eig_jacobi_max = 0;            // auto: Jacobi up to this size
   int eig_workers = 4;               // concurrent divide-and-conquer solves in a truncation (1: one at a time)
+  double refine_eta = 0.1;           // mixed-precision refinement: inner CG target relative to the outer residual
+  int refine_inner = 20;             // ... and its step cap
+  double refine_low_tol = 0.0;       // low-precision Lanczos stop (<= 0: per-precision default)
   EigPool* eig_pool = nullptr;       // created on first concurrent use
   // truncation statistics, accumulated until the caller resets them: wall
   // seconds of the batched eigensolves and the Gram passes run

@@ -1042,7 +1042,7 @@ static LanczosResult lanczos_with(Ctx* c, Matvec& mv, d3s_prec p, double* psi, l
   // 2. FP64 iterative refinement of that Ritz vector (jd_refine) to the
   //    caller's tolerance on the exact FP64 residual.  The Ritz value is an
   //    FP64 Rayleigh quotient, whose error is quadratic in the residual.
-  const double low_tol = (p == D3S_F32) ? 1e-6 : 3e-3;
+  const double low_tol = (c->refine_low_tol > 0.0) ? c->refine_low_tol : (p == D3S_F32) ? 1e-6 : 3e-3;
   LanczosResult r1 = lanczos_core(c, mv, psi, n, std::max(tol, low_tol), kmax, max_matvecs, false);
   if (n <= 2 * kJdMax) {
     LanczosResult r2 = lanczos_core(c, mv, psi, n, tol, kmax, std::max(1, max_matvecs - r1.matvecs), true);
@@ -1050,7 +1050,8 @@ static LanczosResult lanczos_with(Ctx* c, Matvec& mv, d3s_prec p, double* psi, l
     r2.restarts += r1.restarts;
     return r2;
   }
-  LanczosResult r2 = jd_refine(c, mv, psi, n, tol, std::max(2, max_matvecs - r1.matvecs), 20, 0.1);
+  LanczosResult r2 = jd_refine(c, mv, psi, n, tol, std::max(2, max_matvecs - r1.matvecs), c->refine_inner,
+                               c->refine_eta);
   r2.matvecs += r1.matvecs;
   r2.restarts += r1.restarts;
   return r2;

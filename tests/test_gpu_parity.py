@@ -426,6 +426,30 @@ def test_lanczos_mixed_precision_refines_to_f64(ctx, prec):
     assert abs(th - e0) < 1e-10
 
 
+@pytest.mark.parametrize("setting", [(0.03, 40, 1e-2), (0.5, 3, 0.0)])
+def test_mixed_precision_refinement_settings(ctx, setting):
+    """Other refinement settings (a tighter inner solve with an earlier switch
+    from the low-precision Lanczos; a loose inner solve with few CG steps)
+    change the work, not the result: the BF16-product Ritz value still
+    matches the FP64 eigenvalue to 1e-10.  Out-of-range settings are
+    rejected."""
+    l, center = 10, 5
+    mpo = MPO.heisenberg_mpo(l)
+    M, Lenv, Renv = _mixed(synth.random_mps(l, 2, 32, seed=47), mpo, center)
+    e0 = np.linalg.eigvalsh(C.heff_matrix(Lenv, mpo[center], Renv))[0]
+    try:
+        ctx.set_refinement(*setting)
+        th, nmv, ok = ctx.lanczos(dev(Lenv), dev(mpo[center]), dev(Renv), dev(M[center]), tol=1e-12, kmax=40,
+                                  prec=abi.BF16)
+        assert ok
+        assert abs(th - e0) < 1e-10
+        for bad in [(0.0, 20, 0.0), (1.0, 20, 0.0), (0.1, 0, 0.0), (0.1, 20, 1.0)]:
+            with pytest.raises(abi.D3SError):
+                ctx.set_refinement(*bad)
+    finally:
+        ctx.set_refinement(0.1, 20, 0.0)
+
+
 def test_heff_grad_W(ctx):
     ml, d, mr, wl, wr = 37, 4, 53, 6, 6
     L, W, R, psi = _inputs(ml, d, mr, wl, wr, seed=9)
