@@ -1231,19 +1231,73 @@ TruncBlocksResult op_truncate_blocks(Ctx* c, d3s_dir dir, const Sectors& left, c
     }
   }
   run_copies(c, scatter, site_out);
-  // ---- neighbour: the dense products on the structured layout
+  // ---- neighbour (Sec. 5 step 5).  X = U^T M (L2R) or M U^T (R2L) couples a
+  // kept sector only to the old bond's sector of the same charge, so X is
+  // block diagonal and both products run sector by sector, one grouped
+  // launch each (on the structured layout the dense products would spend
+  // nearly all their flops on zero blocks).  X and the neighbour's output
+  // are cleared first: blocks no sector writes stay zero.
+  GroupedPlan px, pn;
+  auto run = [&](GroupedPlan& gp, const double* A, const double* B, double* C) {
+    if (gp.tasks.empty()) return;
+    gp.table_slot = WS_TR_TAB;
+    grouped_finalize(c, gp);
+    grouped_gemm(c, D3S_F64, gp, A, B, C, 1.0, 0.0);
+    grouped_release(gp);
+  };
   if (dir == D3S_L2R) {
     double* Xn = (double*)ws_get(c, WS_X, sizeof(double) * (size_t)k * mr);
-    GemmArgs g1{k, mr, (int)n, site_out, k, false, 0, psi, mr, false, 0, Xn, mr, 0, 1.0, 0.0, 1};
-    gemm_f64(c, g1);
-    GemmArgs g2{k, (int)nbr_other, mr, Xn, mr, true, 0, nbr, nbr_other, false, 0, nbr_out, nbr_other, 0, 1.0, 0.0, 1};
-    gemm_f64(c, g2);
+    zero_bytes(c, Xn, sizeof(double) * (size_t)k * mr);
+    zero_bytes(c, nbr_out, sizeof(double) * (size_t)k * nbr_other);
+    // X[new, b] = sum over the sector's (a, s) rows of U[(a, s), new] M[(a, s), b]
+    px.a_kc = false;
+    px.b_kc = false;
+    // nbr_out[new, :] = X[new, b-block] B[b-block, :]
+    pn.a_kc = true;
+    pn.b_kc = false;
+    for (int gi : order) {
+      const SecGroup& g = gs[gi];
+      const int j = right.find(g.q.data());
+      if (j < 0) continue;
+      const long oj = right.off[j];
+      GTask t{g.keep, right.dim[j], (int)px.segs.size(), 0, 0, (long)g.new_off * mr + oj, (long)mr};
+      for (const RowGroup& rg : g.rows) {
+        px.segs.push_back(GSeg{rg.count, rg.start * k + g.new_off, rg.stride * k, rg.start * mr + oj, rg.stride * mr});
+        ++t.nseg;
+      }
+      px.tasks.push_back(t);
+      pn.tasks.push_back(GTask{g.keep, (int)nbr_other, (int)pn.segs.size(), 1, 0, (long)g.new_off * nbr_other,
+                               nbr_other});
+      pn.segs.push_back(GSeg{right.dim[j], (long)g.new_off * mr + oj, (long)mr, oj * nbr_other, nbr_other});
+    }
+    run(px, site_out, psi, Xn);
+    run(pn, Xn, nbr, nbr_out);
   } else {
     double* Xn = (double*)ws_get(c, WS_X, sizeof(double) * (size_t)ml * k);
-    GemmArgs g1{ml, k, (int)n, psi, n, true, 0, site_out, n, true, 0, Xn, k, 0, 1.0, 0.0, 1};
-    gemm_f64(c, g1);
-    GemmArgs g2{(int)nbr_other, k, ml, nbr, ml, true, 0, Xn, k, false, 0, nbr_out, k, 0, 1.0, 0.0, 1};
-    gemm_f64(c, g2);
+    zero_bytes(c, Xn, sizeof(double) * (size_t)ml * k);
+    zero_bytes(c, nbr_out, sizeof(double) * (size_t)nbr_other * k);
+    // X[a, new] = sum over the sector's (s, b) columns of M[a, (s, b)] U[new, (s, b)]
+    px.a_kc = true;
+    px.b_kc = true;
+    // nbr_out[:, new] = A[:, a-block] X[a-block, new]
+    pn.a_kc = true;
+    pn.b_kc = false;
+    for (int gi : order) {
+      const SecGroup& g = gs[gi];
+      const int i = left.find(g.q.data());
+      if (i < 0) continue;
+      const long oi = left.off[i];
+      GTask t{left.dim[i], g.keep, (int)px.segs.size(), 0, 0, oi * k + g.new_off, (long)k};
+      for (const ColGroup& cg : g.cols) {
+        px.segs.push_back(GSeg{cg.count, oi * n + cg.start, n, (long)g.new_off * n + cg.start, n});
+        ++t.nseg;
+      }
+      px.tasks.push_back(t);
+      pn.tasks.push_back(GTask{(int)nbr_other, g.keep, (int)pn.segs.size(), 1, 0, (long)g.new_off, (long)k});
+      pn.segs.push_back(GSeg{left.dim[i], oi, (long)ml, oi * k + g.new_off, (long)k});
+    }
+    run(px, psi, site_out, Xn);
+    run(pn, nbr, Xn, nbr_out);
   }
   if (renormalize) {
     const long nn = (long)k * nbr_other;
