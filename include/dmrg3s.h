@@ -121,7 +121,7 @@ d3s_status d3s_set_eigensolver(d3s_ctx ctx, int kind, int jacobi_max_n);
  * on a GPU): rocSOLVER's solver is bound by its per-column launch sequence,
  * so the batched calls of one truncation (groups of sector matrices) run on
  * up to `workers` host threads at once, each with its own stream and
- * rocBLAS handle (default 4; 1 = one call after the other).  A call of
+ * rocBLAS handle (default 3; 1 = one call after the other).  A call of
  * several matrices may be halved to balance the threads.  The results are
  * those of the one-at-a-time solves up to rounding (the grouping into calls
  * may differ).  D3S_EINVAL outside 1..8. */
