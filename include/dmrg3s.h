@@ -119,12 +119,13 @@ d3s_status d3s_set_autotune(d3s_ctx ctx, int enable, const char* cache_path);
 d3s_status d3s_set_eigensolver(d3s_ctx ctx, int kind, int jacobi_max_n);
 /* Concurrency of the truncations' divide-and-conquer solves (Sec. 5 step 4
  * on a GPU): rocSOLVER's solver is bound by its per-column launch sequence,
- * so the batched calls of one truncation (groups of sector matrices) run on
- * up to `workers` host threads at once, each with its own stream and
- * rocBLAS handle (default 3; 1 = one call after the other).  A call of
- * several matrices may be halved to balance the threads.  The results are
- * those of the one-at-a-time solves up to rounding (the grouping into calls
- * may differ).  D3S_EINVAL outside 1..8. */
+ * so the batched calls of one truncation (groups of sector matrices) are
+ * split into `workers` shares that run at once: one on the calling thread
+ * and the context's stream, the others on host threads with their own
+ * streams and rocBLAS handles (default 3; 1 = one call after the other).  A
+ * call of several matrices may be halved to balance the shares.  The
+ * results are those of the one-at-a-time solves up to rounding (the
+ * grouping into calls may differ).  D3S_EINVAL outside 1..8. */
 d3s_status d3s_set_eig_workers(d3s_ctx ctx, int workers);
 /* The mixed-precision eigensolver's two phases (FP32 / BF16 products, see
  * d3s_lanczos): Lanczos on the low-precision operator stops at relative

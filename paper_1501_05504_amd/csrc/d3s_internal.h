@@ -64,10 +64,9 @@ struct Ctx {
   d3s_prec tune_prec = D3S_F64;      // precision the grouped plans being built will run in
   int eig_kind = 0;                  // batched eigensolver: 0 auto, 1 divide and conquer, 2 Jacobi, 3 LDS solver
   int eig_jacobi_max = 0;            // auto: Jacobi up to this size
-  // concurrent divide-and-conquer solves in a truncation (1: one at a time).
-  // Three: under HIP's default of four hardware queues per process a fourth
-  // worker stream shares a queue with the context's stream, and the
-  // truncations were slower with four than with three (measured on MI355X)
+  // concurrent shares of a truncation's divide-and-conquer solves, the
+  // calling thread's on the context's stream (1: one at a time).  Three:
+  // four were no faster and five or more slower (measured on MI355X)
   int eig_workers = 3;
   double refine_eta = 0.1;           // mixed-precision refinement: inner CG target relative to the outer residual
   int refine_inner = 20;             // ... and its step cap

@@ -7,9 +7,13 @@
 // group of sector matrices of similar size) are independent, so they run
 // side by side: a few host threads, each with its own HIP stream (default
 // priority) and its own rocBLAS handle, each issue their calls' launch
-// sequences at once.  The caller's stream work before the solves is ordered
-// before them by an event; every worker synchronises its own stream before
-// reporting, so the caller continues after all solves have completed.
+// sequences at once, and the calling thread takes one share itself on the
+// context's stream (so k concurrent shares use k streams: under HIP's
+// default of four hardware queues per process a stream beyond them shares a
+// queue and serialises behind it).  The caller's stream work before the
+// solves is ordered before the workers' by an event; every worker
+// synchronises its own stream before reporting, so the caller continues
+// after all solves have completed.
 #include <condition_variable>
 #include <functional>
 #include <mutex>
@@ -119,9 +123,54 @@ void eig_pool_destroy(Ctx* c) {
   c->eig_pool = nullptr;
 }
 
+namespace {
+
+// the calls `mine` of one share on stream s with handle h; throws on a
+// failed or unconverged solve, and drains s before returning either way
+void run_share(const std::vector<EigCall>& calls, const std::vector<int>& mine, hipStream_t s, rocblas_handle h,
+               hipEvent_t start, char* scratch, const std::vector<size_t>& eo, const std::vector<size_t>& io,
+               double* G, double* V) {
+  std::vector<std::vector<rocblas_int>> info(mine.size());
+  // whatever happens, the stream is drained before the share reports (and
+  // before `info`, which copies may target, goes away)
+  struct Drain {
+    hipStream_t s;
+    ~Drain() { (void)hipStreamSynchronize(s); }
+  } drain{s};
+  if (start) D3S_HIP(hipStreamWaitEvent(s, start, 0));
+  for (size_t j = 0; j < mine.size(); ++j) {
+    const EigCall& e = calls[mine[j]];
+    double* E = (double*)(scratch + eo[mine[j]]);
+    rocblas_int* inf = (rocblas_int*)(scratch + io[mine[j]]);
+    const rocblas_status st = rocsolver_dsyevd_strided_batched(
+        h, rocblas_evect_original, rocblas_fill_upper, e.n, G + e.goff, e.n, (rocblas_stride)e.n * e.n, V + e.voff,
+        e.n, E, e.n, inf, e.batch);
+    if (st != rocblas_status_success)
+      throw Error{D3S_EDEVICE, "rocsolver batched eigensolver failed (status " + std::to_string((int)st) + ")"};
+    info[j].resize(e.batch);
+    D3S_HIP(hipMemcpyAsync(info[j].data(), inf, sizeof(rocblas_int) * e.batch, hipMemcpyDeviceToHost, s));
+  }
+  D3S_HIP(hipStreamSynchronize(s));
+  for (const auto& v : info)
+    for (rocblas_int x : v)
+      if (x != 0)
+        throw Error{D3S_EDEVICE, "rocsolver batched eigensolver did not converge (info " + std::to_string(x) + ")"};
+}
+
+}  // namespace
+
 void eig_calls_parallel(Ctx* c, const std::vector<EigCall>& calls, const std::vector<int>& worker, int workers,
                         double* G, double* V) {
-  EigPool* P = pool_of(c, workers);
+  // share 0 runs here on the context's stream, shares 1.. on pool threads
+  EigPool* P = pool_of(c, workers - 1);
+  if (!c->solver) {
+    rocblas_handle h = nullptr;
+    if (rocblas_create_handle(&h) != rocblas_status_success) throw Error{D3S_EDEVICE, "rocblas_create_handle failed"};
+    c->solver = h;
+  }
+  rocblas_handle own = (rocblas_handle)c->solver;
+  if (rocblas_set_stream(own, c->stream) != rocblas_status_success)
+    throw Error{D3S_EDEVICE, "rocblas_set_stream failed"};
   // per call: the off-diagonal scratch of the tridiagonal form and the info flags
   std::vector<size_t> eo(calls.size()), io(calls.size());
   size_t bytes = 0;
@@ -133,6 +182,7 @@ void eig_calls_parallel(Ctx* c, const std::vector<EigCall>& calls, const std::ve
   }
   char* scratch = (char*)ws_get(c, WS_EIG_PAR, bytes);
   D3S_HIP(hipEventRecord(P->start, c->stream));
+  std::vector<int> mine0;
   {
     std::lock_guard<std::mutex> lk(P->m);
     P->pending = 0;
@@ -140,48 +190,38 @@ void eig_calls_parallel(Ctx* c, const std::vector<EigCall>& calls, const std::ve
       std::vector<int> mine;
       for (size_t i = 0; i < calls.size(); ++i)
         if (worker[i] == k) mine.push_back((int)i);
-      EigPool::Worker& W = P->w[k];
+      if (k == 0) {
+        mine0 = mine;
+        continue;
+      }
+      EigPool::Worker& W = P->w[k - 1];
       W.code = D3S_OK;
       W.msg.clear();
       if (mine.empty()) continue;
-      W.job = [=, &calls, &W]() {
-        std::vector<std::vector<rocblas_int>> info(mine.size());
-        // whatever happens, the stream is drained before the worker reports
-        // (and before `info`, which copies may target, goes away)
-        struct Drain {
-          hipStream_t s;
-          ~Drain() { (void)hipStreamSynchronize(s); }
-        } drain{W.stream};
-        D3S_HIP(hipStreamWaitEvent(W.stream, P->start, 0));
-        for (size_t j = 0; j < mine.size(); ++j) {
-          const EigCall& e = calls[mine[j]];
-          double* E = (double*)(scratch + eo[mine[j]]);
-          rocblas_int* inf = (rocblas_int*)(scratch + io[mine[j]]);
-          const rocblas_status st = rocsolver_dsyevd_strided_batched(
-              W.handle, rocblas_evect_original, rocblas_fill_upper, e.n, G + e.goff, e.n, (rocblas_stride)e.n * e.n,
-              V + e.voff, e.n, E, e.n, inf, e.batch);
-          if (st != rocblas_status_success)
-            throw Error{D3S_EDEVICE, "rocsolver batched eigensolver failed (status " + std::to_string((int)st) + ")"};
-          info[j].resize(e.batch);
-          D3S_HIP(hipMemcpyAsync(info[j].data(), inf, sizeof(rocblas_int) * e.batch, hipMemcpyDeviceToHost,
-                                 W.stream));
-        }
-        D3S_HIP(hipStreamSynchronize(W.stream));
-        for (const auto& v : info)
-          for (rocblas_int x : v)
-            if (x != 0)
-              throw Error{D3S_EDEVICE, "rocsolver batched eigensolver did not converge (info " + std::to_string(x) +
-                                           ")"};
+      W.job = [=, &calls, &W, &eo, &io]() {
+        run_share(calls, mine, W.stream, W.handle, P->start, scratch, eo, io, G, V);
       };
       W.has_job = true;
       ++P->pending;
     }
   }
   P->cv_job.notify_all();
+  d3s_status code = D3S_OK;
+  std::string msg;
+  try {
+    run_share(calls, mine0, c->stream, own, nullptr, scratch, eo, io, G, V);
+  } catch (const Error& e) {
+    code = e.code;
+    msg = e.msg;
+  } catch (...) {
+    code = D3S_EDEVICE;
+    msg = "eigensolver: unexpected exception";
+  }
   {
     std::unique_lock<std::mutex> lk(P->m);
     P->cv_done.wait(lk, [&] { return P->pending == 0; });
   }
+  if (code != D3S_OK) throw Error{code, msg};
   for (auto& W : P->w)
     if (W.code != D3S_OK) throw Error{W.code, W.msg};
 }
