@@ -155,8 +155,17 @@ void grouped_finalize(Ctx* c, GroupedPlan& g) {
 void grouped_retile(Ctx* c, GroupedPlan& g) {
   int bm, bn;
   grouped_tile_dims(g.cfg, bm, bn);
+  // tiles are dispatched in table order; a task's tiles cost about its
+  // summed K, so the tasks go longest first (the short tiles fill the tail)
+  std::vector<long> klen(g.tasks.size(), 0);
+  for (size_t k = 0; k < g.tasks.size(); ++k)
+    for (int q = 0; q < g.tasks[k].nseg; ++q) klen[k] += g.segs[(size_t)g.tasks[k].seg0 + q].K;
+  std::vector<int> ord(g.tasks.size());
+  for (size_t k = 0; k < ord.size(); ++k) ord[k] = (int)k;
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return klen[a] > klen[b]; });
   int acc = 0;
-  for (GTask& t : g.tasks) {
+  for (int k : ord) {
+    GTask& t = g.tasks[k];
     t.tile0 = acc;
     acc += ((t.M + bm - 1) / bm) * ((t.N + bn - 1) / bn);
   }
