@@ -308,7 +308,8 @@ def test_block_truncate_keeps_every_value_above_eps(ctx, direction, ml, mr, seed
 @pytest.mark.parametrize("direction", ["l2r", "r2l"])
 def test_block_truncate_concurrent_solves_equal_serial(direction):
     """The sector eigensolves of one truncation run concurrently (four
-    worker threads and streams) or one after the other: same kept states
+    shares: the calling thread on the context's stream and three worker
+    threads with their own streams) or one after the other: same kept states
     per sector, the same kept subspace and discarded weight to rounding."""
     case = hubbard_block_case(300, 257, 41)
     ml, mr, d = case["psi"].shape[0], case["psi"].shape[2], 4
