@@ -292,13 +292,22 @@ void build_wmap_r2l(const BlockHeff& h, WmapPlan& wm, long out_base, long out_ws
     }
 }
 
-void finalize_and_tune(Ctx* c, GroupedPlan& g, size_t na, size_t nb, size_t nc) {
-  grouped_finalize(c, g);
-  if (!c->autotune || g.ntasks == 0) return;
-  // time both tile sizes on zeroed operands of the right extents
+// time the tile configurations on zeroed operands of the launch's extents
+// (in c->tune_prec)
+void retune(Ctx* c, GroupedPlan& g) {
+  const size_t na = g.tune_n[0], nb = g.tune_n[1], nc = g.tune_n[2];
+  if (!c->autotune || g.ntasks == 0 || na + nb + nc == 0) return;
   double* s = (double*)ws_get(c, WS_TUNE, sizeof(double) * (na + nb + nc));
   zero_bytes(c, s, sizeof(double) * (na + nb + nc));
   tune_grouped(c, g, s, s + na, s + na + nb);
+}
+
+void finalize_and_tune(Ctx* c, GroupedPlan& g, size_t na, size_t nb, size_t nc) {
+  grouped_finalize(c, g);
+  g.tune_n[0] = na;
+  g.tune_n[1] = nb;
+  g.tune_n[2] = nc;
+  retune(c, g);
 }
 
 }  // namespace
@@ -592,15 +601,27 @@ LowpTwin& ensure_lowp(Ctx* c, BlockHeff& h, d3s_prec p) {
   if (h.padded) throw Error{D3S_EINVAL, "blocks: a padded plan has no twin"};
   if (h.lp) {
     // built for the other low precision: its launches get that precision's
-    // tile rule (the autotuner's choices are kept)
-    if (h.lp->prec != p && !c->autotune)
-      for (GroupedPlan* g : {&h.lp->h.g1, &h.lp->h.g1t, &h.lp->h.g2}) {
-        const int cfg = grouped_pick_cfg(c, *g, p);
-        if (g->ntasks > 0 && cfg != g->cfg) {
-          g->cfg = cfg;
-          grouped_retile(c, *g);
+    // tile rule, or with the autotuner on are timed again in it
+    if (h.lp->prec != p) {
+      if (!c->autotune) {
+        for (GroupedPlan* g : {&h.lp->h.g1, &h.lp->h.g1t, &h.lp->h.g2}) {
+          const int cfg = grouped_pick_cfg(c, *g, p);
+          if (g->ntasks > 0 && cfg != g->cfg) {
+            g->cfg = cfg;
+            grouped_retile(c, *g);
+          }
         }
+      } else {
+        c->tune_prec = p;
+        try {
+          for (GroupedPlan* g : {&h.lp->h.g1, &h.lp->h.g1t, &h.lp->h.g2}) retune(c, *g);
+        } catch (...) {
+          c->tune_prec = D3S_F64;
+          throw;
+        }
+        c->tune_prec = D3S_F64;
       }
+    }
     h.lp->prec = p;
     return *h.lp;
   }

@@ -133,6 +133,7 @@ struct GroupedPlan {
   double flops = 0.0;
   int table_slot = -1;          // >= 0: the device tables live in this workspace slot (not owned)
   Ctx* owner = nullptr;         // context whose allocator holds the tables
+  size_t tune_n[3] = {0, 0, 0}; // extents (in doubles) of A, B, C for timing its tile configurations
 };
 void grouped_tile_dims(int cfg, int& bm, int& bn);   // block tile of a grouped configuration
 // the tile configuration of a plan's launches in precision p (the rule; or

@@ -147,6 +147,38 @@ def test_bound_product_equals_oracle(ctx, layout, prec, ml, mr, seed):
     plan.close()
 
 
+def test_autotuned_twin_switches_precision():
+    """With the autotuner on, the padded twin built for FP32 products is
+    timed again in BF16 when BF16 products follow (its tiles are re-picked
+    for that precision); both products still meet their bounds against the
+    oracle on rounded operands, and so does FP32 again afterwards."""
+    from tests.test_gpu_parity import bf16_bound, bf16_round
+    case = packed_case(300, 257, 27)
+    c = abi.Context(0)
+    try:
+        c.set_autotune(True)
+        plan = make_plan(c, case, abi.LAYOUT_PACKED)
+        Wf = np.asarray(case["W"], dtype=np.float32).astype(np.float64)
+        f32 = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)
+        for prec in ("f32", "bf16", "f32"):
+            rnd = bf16_round if prec == "bf16" else f32
+            Lr, Rr, pr = rnd(case["L"]), rnd(case["R"]), rnd(case["psi"])
+            ref = C.apply_heff(Lr, Wf, Rr, pr)
+            plan.bind(dev(case["Lp"]), dev(case["W"]), dev(case["Rp"]), abi.F32 if prec == "f32" else abi.BF16)
+            out = torch.full((plan.npsi,), float("nan"), dtype=torch.float64, device=DEV)
+            plan.apply_bound(dev(case["psip"]), out)
+            torch.cuda.synchronize()
+            o = unpack_site(out.cpu().numpy(), case["psi"].shape, case["qL"], case["dL"], case["qR"], case["dR"],
+                            case["phys"])
+            if prec == "f32":
+                assert rel_err(o, ref) < 3e-5
+            else:
+                assert np.all(np.abs(o - ref) <= bf16_bound(Lr, Wf, Rr, pr))
+        plan.close()
+    finally:
+        c.close()
+
+
 def test_bind_replaces_the_operator(ctx):
     """A second bind replaces the first (2 L gives twice the product)."""
     case = packed_case(96, 80, 25)
