@@ -160,11 +160,17 @@ EigPlan plan_eig(Ctx* c, const std::vector<int>& n) {
     if (small(m)) return (m + 7) / 8 * 8;
     return cnt == 1 ? m : std::max(96, (m + 15) / 16 * 16);
   };
+  // With K concurrent shares (below) the launch chains of separate calls
+  // overlap, so grouping is charged 1/K of a column's serial cost: fewer,
+  // padded calls save less than they would one after the other (measured:
+  // the full serial cost grouped too much on the cylinder and the chain)
+  const int shares = (c->eig_workers >= 2 && c->eig_kind != 2) ? c->eig_workers : 1;
+  const double col = 2.4e-5 / shares;
   auto cost = [&](int i, int j) {
     const int cnt = j - i + 1;
     const double np = pad(n[ord[j]], cnt);
     if (small(n[ord[j]])) return (5e-5 + 6.5e-7 * np * np) * ((cnt + 255) / 256);
-    return 2.4e-5 * np + 1.6e-12 * (double)cnt * np * np * np;
+    return col * np + 1.6e-12 * (double)cnt * np * np * np;
   };
   const int G = (int)ord.size();
   std::vector<double> best(G + 1, 0.0);
