@@ -122,7 +122,7 @@ d3s_status d3s_set_eigensolver(d3s_ctx ctx, int kind, int jacobi_max_n);
  * so the batched calls of one truncation (groups of sector matrices) are
  * split into `workers` shares that run at once: one on the calling thread
  * and the context's stream, the others on host threads with their own
- * streams and rocBLAS handles (default 3; 1 = one call after the other).  A
+ * streams and rocBLAS handles (default 4; 1 = one call after the other).  A
  * call of several matrices may be halved to balance the shares.  The
  * results are those of the one-at-a-time solves up to rounding (the
  * grouping into calls may differ).  D3S_EINVAL outside 1..8. */

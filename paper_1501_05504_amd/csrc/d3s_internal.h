@@ -65,9 +65,10 @@ struct Ctx {
   int eig_kind = 0;                  // batched eigensolver: 0 auto, 1 divide and conquer, 2 Jacobi, 3 LDS solver
   int eig_jacobi_max = 0;            // auto: Jacobi up to this size
   // concurrent shares of a truncation's divide-and-conquer solves, the
-  // calling thread's on the context's stream (1: one at a time).  Three:
-  // four were no faster and five or more slower (measured on MI355X)
-  int eig_workers = 3;
+  // calling thread's on the context's stream (1: one at a time).  Four:
+  // with the concurrency-aware grouping four beat three on large sectors
+  // and tie on small ones; five or more were slower (measured on MI355X)
+  int eig_workers = 4;
   double refine_eta = 0.1;           // mixed-precision refinement: inner CG target relative to the outer residual
   int refine_inner = 20;             // ... and its step cap
   double refine_low_tol = 0.0;       // low-precision Lanczos stop (<= 0: per-precision default)
